@@ -1,0 +1,315 @@
+"""Plain FP64 CPU oracle of the two-grid algebraic multiscale preconditioner.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the product path never does.  It
+shares no code with the HIP library: numpy/scipy (LAPACK) in float64, written
+to be read against the paper, not to be fast.
+
+Paper: "An algebraic multiscale preconditioner for large sparse SPD matrices"
+(Zhou, Fu, Chung).  Section references below are to that paper.
+
+Readings where the paper is silent (each also listed in the design notes):
+  * overlap: the support region around a core subdomain (Section 3.1, "an
+    overlapping region constructed around Omega_i") is delta rounds of
+    adding graph neighbours; the local problems live on that region;
+  * Neumann diagonal (Section 3.2): only couplings inside the region count;
+  * partition of unity: each zero-extended eigenvector is divided by the
+    number of regions that contain the dof (the paper zero-extends only);
+  * preconditioner: additive two-level Schwarz, the paper's coarse term
+    R0^T A0^{-1} R0 (Section 3.1) plus local solves sum_i R_i^T A_i^{-1} R_i,
+    so that the operator is SPD and usable in CG;
+  * Krylov method: preconditioned CG (the paper runs GMRES) stopping on the
+    unpreconditioned 2-norm ||r|| <= rtol ||f|| from x0 = 0;
+  * normalisation/sign: psi^T S psi = 1, largest-|entry| positive (lowest
+    global index on ties).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+class OracleError(ValueError):
+    pass
+
+
+# --------------------------------------------------------------------------
+# Input checks (Section 1: A is symmetric positive definite; Section 3.1: the
+# non-overlapping partition covers every dof).
+# --------------------------------------------------------------------------
+def validate(A: sp.csr_matrix, part: np.ndarray, nparts: int) -> None:
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise OracleError("A must be square")
+    if abs(A - A.T).max() > 1e-14 * abs(A).max():
+        raise OracleError("A must be symmetric")
+    if (A.diagonal() <= 0).any():
+        raise OracleError("diagonal of A must be positive")
+    if len(part) != n or part.min() < 0 or part.max() >= nparts:
+        raise OracleError("partition out of range")
+    if (np.bincount(part, minlength=nparts) == 0).any():
+        raise OracleError("empty subdomain")
+
+
+# --------------------------------------------------------------------------
+# Subdomains (Section 3.1): cores Omega_i from the partition, then the
+# overlapping region Omega_i^delta by delta rounds of graph growth.
+# --------------------------------------------------------------------------
+def cores(part: np.ndarray, nparts: int) -> list[np.ndarray]:
+    order = np.argsort(part, kind="stable")
+    counts = np.bincount(part, minlength=nparts)
+    splits = np.cumsum(counts)[:-1]
+    return [np.sort(c) for c in np.split(order, splits)]
+
+
+def grow(A: sp.csr_matrix, dofs: np.ndarray, delta: int) -> np.ndarray:
+    """Omega^delta: add every dof coupled (nonzero off-diagonal) to the set, delta times."""
+    cur = np.asarray(dofs, dtype=np.int64)
+    for _ in range(delta):
+        rows = A[cur]
+        nb = rows.indices[rows.data != 0]
+        cur = np.union1d(cur, nb)
+    return cur
+
+
+def multiplicity(n: int, regions: list[np.ndarray]) -> np.ndarray:
+    mult = np.zeros(n, dtype=np.int64)
+    for r in regions:
+        mult[r] += 1
+    return mult
+
+
+# --------------------------------------------------------------------------
+# Local matrices (Section 3.2).
+# --------------------------------------------------------------------------
+def local_matrix(A: sp.csr_matrix, dofs: np.ndarray) -> np.ndarray:
+    """A_i = R_i A R_i^T (Boolean restriction to the region, dense)."""
+    return A[dofs][:, dofs].toarray()
+
+
+def neumann_matrix(Ai: np.ndarray) -> np.ndarray:
+    """hat A_i: keep the off-diagonals of A_i, set each diagonal entry to minus
+    the sum of the off-diagonal entries of its row, so that row sums vanish."""
+    Ah = Ai.copy()
+    np.fill_diagonal(Ah, 0.0)
+    np.fill_diagonal(Ah, -Ah.sum(axis=1))
+    return Ah
+
+
+def weighting(Ah: np.ndarray) -> np.ndarray:
+    """S_i = diag(hat A_i), returned as the vector of its diagonal."""
+    s = np.diag(Ah).copy()
+    if (s <= 0).any():
+        raise OracleError("weighting matrix S_i must have a positive diagonal")
+    return s
+
+
+def local_eigenpairs(Ah: np.ndarray, s: np.ndarray, m: int, gdofs: np.ndarray | None = None):
+    """Smallest eigenpairs of hat A psi = lambda S psi (the algebraic local
+    eigenproblem of Section 3.2), solved through the equivalent standard
+    problem S^{-1/2} hat A S^{-1/2} z = lambda z with psi = S^{-1/2} z
+    (Section 5, parameter test).
+
+    Returns (lam, psi): lam holds min(m+1, n_i) eigenvalues (the last one is
+    the first eigenvalue left out of the coarse space, used for mu_c of
+    Theorem 2); psi holds the first m_i = min(m, n_i) eigenvectors,
+    normalised psi^T S psi = 1, sign: largest |entry| positive.
+    """
+    ni = Ah.shape[0]
+    mi = min(m, ni)
+    k = min(m + 1, ni)
+    dm = 1.0 / np.sqrt(s)
+    B = dm[:, None] * Ah * dm[None, :]
+    B = 0.5 * (B + B.T)
+    lam, Z = sla.eigh(B, subset_by_index=[0, k - 1])
+    psi = dm[:, None] * Z[:, :mi]
+    if gdofs is None:
+        gdofs = np.arange(ni)
+    for c in range(mi):
+        a = np.abs(psi[:, c])
+        cand = np.flatnonzero(a == a.max())
+        j = cand[np.argmin(gdofs[cand])]
+        if psi[j, c] < 0:
+            psi[:, c] = -psi[:, c]
+    return lam, psi
+
+
+# --------------------------------------------------------------------------
+# Coarse space (Section 3.1 and 3.2): R0^T columns are the (scaled,
+# zero-extended) local eigenvectors; A0 = R0 A R0^T.
+# --------------------------------------------------------------------------
+def prolongation(n: int, regions, psis, mult, pou: str = "mult") -> sp.csr_matrix:
+    cols, rows, vals = [], [], []
+    c0 = 0
+    for dofs, psi in zip(regions, psis):
+        for k in range(psi.shape[1]):
+            v = psi[:, k].copy()
+            if pou == "mult":
+                v = v / mult[dofs]
+            rows.append(dofs)
+            cols.append(np.full(len(dofs), c0 + k))
+            vals.append(v)
+        c0 += psi.shape[1]
+    if c0 == 0:
+        return sp.csr_matrix((n, 0))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(n, c0))
+
+
+def coarse_matrix(A: sp.csr_matrix, R0T: sp.csr_matrix) -> np.ndarray:
+    """A0 = R0 A R0^T (Galerkin projection), symmetrised."""
+    A0 = (R0T.T @ (A @ R0T)).toarray()
+    return 0.5 * (A0 + A0.T)
+
+
+# --------------------------------------------------------------------------
+# The preconditioner M^{-1} r = sum_i R_i^T A_i^{-1} R_i r + R0^T A0^{-1} R0 r.
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Setup:
+    n: int
+    regions: list
+    mult: np.ndarray
+    local_chol: list
+    lam: list
+    psi: list
+    R0T: sp.csr_matrix
+    A0: np.ndarray
+    A0_chol: object
+    nev: int
+    overlap: int
+
+    @property
+    def nc(self) -> int:
+        return self.R0T.shape[1]
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        return apply(self, r)
+
+
+def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
+          local_solves=True) -> Setup:
+    A = sp.csr_matrix(A)
+    validate(A, part, nparts)
+    if nev < 0:
+        raise OracleError("nev must be >= 0")
+    n = A.shape[0]
+    regions = [grow(A, c, overlap) for c in cores(part, nparts)]
+    if local_order == "descending":
+        regions = [r[::-1].copy() for r in regions]
+    mult = multiplicity(n, regions)
+    chol, lams, psis = [], [], []
+    for dofs in regions:
+        Ai = local_matrix(A, dofs)
+        if local_solves:
+            try:
+                chol.append(sla.cho_factor(Ai, lower=True))
+            except np.linalg.LinAlgError as e:
+                raise OracleError("local matrix not SPD") from e
+        if nev > 0:
+            Ah = neumann_matrix(Ai)
+            s = weighting(Ah)
+            lam, psi = local_eigenpairs(Ah, s, nev, dofs)
+        else:
+            lam, psi = np.zeros(0), np.zeros((len(dofs), 0))
+        lams.append(lam)
+        psis.append(psi)
+    R0T = prolongation(n, regions, psis, mult, pou)
+    if R0T.shape[1] > 0:
+        A0 = coarse_matrix(A, R0T)
+        try:
+            A0c = sla.cho_factor(A0, lower=True)
+        except np.linalg.LinAlgError as e:
+            raise OracleError("coarse matrix not SPD") from e
+    else:
+        A0, A0c = np.zeros((0, 0)), None
+    return Setup(n, regions, mult, chol, lams, psis, R0T, A0, A0c, nev, overlap)
+
+
+def local_part(st: Setup, r: np.ndarray) -> np.ndarray:
+    z = np.zeros_like(r)
+    for dofs, c in zip(st.regions, st.local_chol):
+        z[dofs] += sla.cho_solve(c, r[dofs])
+    return z
+
+
+def coarse_part(st: Setup, r: np.ndarray) -> np.ndarray:
+    if st.nc == 0:
+        return np.zeros_like(r)
+    c = st.R0T.T @ r
+    return st.R0T @ sla.cho_solve(st.A0_chol, c)
+
+
+def apply(st: Setup, r: np.ndarray) -> np.ndarray:
+    """M^{-1} r: additive local solves plus the coarse correction."""
+    return local_part(st, r) + coarse_part(st, r)
+
+
+# --------------------------------------------------------------------------
+# Preconditioned conjugate gradients (Hestenes-Stiefel; Saad, Iterative
+# Methods for Sparse Linear Systems, Algorithm 9.1), x0 = 0.
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class PCGResult:
+    x: np.ndarray
+    iterations: int
+    converged: bool
+    relres_history: list
+    relres_true: float
+    alphas: list
+    betas: list
+
+
+def pcg(A, f, Minv, rtol=1e-8, maxit=1000) -> PCGResult:
+    A = sp.csr_matrix(A)
+    x = np.zeros_like(f)
+    r = f.copy()
+    nf = np.linalg.norm(f)
+    hist = [1.0 if nf > 0 else 0.0]
+    alphas, betas = [], []
+    if nf == 0.0:
+        return PCGResult(x, 0, True, hist, 0.0, alphas, betas)
+    z = Minv(r)
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    converged = False
+    while it < maxit:
+        q = A @ p
+        alpha = rz / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        alphas.append(alpha)
+        rel = np.linalg.norm(r) / nf
+        hist.append(rel)
+        if rel <= rtol:
+            converged = True
+            break
+        z = Minv(r)
+        rz_new = r @ z
+        beta = rz_new / rz
+        betas.append(beta)
+        p = z + beta * p
+        rz = rz_new
+    true = np.linalg.norm(f - A @ x) / nf
+    return PCGResult(x, it, converged, hist, true, alphas, betas)
+
+
+def lanczos_condition(alphas, betas) -> float:
+    """kappa(M^{-1}A) estimate from the CG coefficients (the Lanczos
+    tridiagonal T: diag 1/a_k + b_{k-1}/a_{k-1}, offdiag sqrt(b_k)/a_k)."""
+    k = len(alphas)
+    if k == 0:
+        return 1.0
+    d = np.empty(k)
+    e = np.empty(max(k - 1, 0))
+    for j in range(k):
+        d[j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
+        if j < k - 1:
+            e[j] = np.sqrt(betas[j]) / alphas[j]
+    ev = sla.eigh_tridiagonal(d, e, eigvals_only=True)
+    return float(ev[-1] / ev[0])

@@ -1,0 +1,311 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check uses a hand-derived
+worked example, a closed form, a brute-force computation on a tiny input, an
+identity stated in the paper, or an independent library routine.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import workloads as W
+from workloads import configs
+
+
+def _small(nx=16, nparts=4, overlap=1, nev=2, contrast=1e4, nchan=3):
+    w = configs.channels(nx=nx, nparts=nparts, overlap=overlap, nev=nev, contrast=contrast,
+                         nchan=nchan)
+    return w, w.A.to_scipy()
+
+
+# ---------------------------------------------------------------- golden ---
+@pytest.mark.parametrize("case", ["overlap0", "overlap1"])
+def test_worked_example_1d(golden, case):
+    g = golden("worked_1d_4cell.txt")
+    A = sp.csr_matrix(g["A"])
+    part = g["part"].astype(np.int32)
+    overlap = 0 if case == "overlap0" else 1
+    st = O.setup(A, part, 2, 1, overlap=overlap)
+    for r, ref in zip(st.regions, g[f"{case}.regions"]):
+        np.testing.assert_array_equal(r, ref.astype(int))
+    Ai = O.local_matrix(A, st.regions[0])
+    Ah = O.neumann_matrix(Ai)
+    np.testing.assert_allclose(Ah, g[f"{case}.neumann0"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(O.weighting(Ah), g[f"{case}.S0"], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(st.lam[0], g[f"{case}.lambda0"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(st.psi[0][:, 0], g[f"{case}.psi0"], rtol=1e-13)
+    if case == "overlap1":
+        np.testing.assert_array_equal(st.mult, g["overlap1.mult"].astype(int))
+        np.testing.assert_allclose(st.R0T.toarray(), g["overlap1.R0T"], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(st.A0, g[f"{case}.A0"], rtol=1e-13)
+    np.testing.assert_allclose(st.apply(g["f"]), g[f"{case}.Minv_f"], rtol=1e-13)
+    res = O.pcg(A, g["f"], st.apply, rtol=1e-14, maxit=10)
+    assert res.iterations <= 4
+    np.testing.assert_allclose(res.x, g["u"], rtol=1e-12)
+
+
+# ------------------------------------------------- Neumann matrix, S_i -----
+def test_neumann_rowsums_and_edge_sum_identity():
+    """Row sums of hat A_i vanish (Section 3.2) and x^T hat A_i x equals the
+    edge sum 1/2 sum_{j!=k} (-A_jk)(x_j - x_k)^2 (proof of Lemma 2)."""
+    w, A = _small(nx=20, nparts=4, overlap=2)
+    rng = np.random.default_rng(0)
+    st_regions = [O.grow(A, c, 2) for c in O.cores(w.part, w.nparts)]
+    for dofs in st_regions:
+        Ai = O.local_matrix(A, dofs)
+        Ah = O.neumann_matrix(Ai)
+        assert np.abs(Ah.sum(axis=1)).max() <= 1e-13 * np.abs(Ah).max()
+        s = O.weighting(Ah)
+        assert (s > 0).all()
+        x = rng.standard_normal(len(dofs))
+        # brute force edge loop, written from the definition
+        e = 0.0
+        for j in range(len(dofs)):
+            for k in range(len(dofs)):
+                if j != k and Ai[j, k] != 0.0:
+                    e += 0.5 * (-Ai[j, k]) * (x[j] - x[k]) ** 2
+        assert abs(x @ Ah @ x - e) <= 1e-12 * abs(e)
+
+
+# ------------------------------------------------------------ eigenpairs ---
+def test_hep_equals_ghep_bruteforce():
+    """The standard form S^{-1/2} hat A S^{-1/2} (Section 5) has the same
+    spectrum as the generalized pencil (hat A, S) solved by a full dense GHEP."""
+    w, A = _small(nx=16, nparts=4, overlap=1, nev=5)
+    for c in O.cores(w.part, w.nparts):
+        dofs = O.grow(A, c, 1)
+        Ah = O.neumann_matrix(O.local_matrix(A, dofs))
+        s = O.weighting(Ah)
+        lam, psi = O.local_eigenpairs(Ah, s, 5, dofs)
+        full = sla.eigh(Ah, np.diag(s), eigvals_only=True)
+        np.testing.assert_allclose(lam, full[:6], rtol=0, atol=1e-12)
+        # psi solves the generalized problem and is S-orthonormal
+        np.testing.assert_allclose(Ah @ psi, (s[:, None] * psi) * lam[None, :5], atol=1e-10)
+        np.testing.assert_allclose(psi.T @ (s[:, None] * psi), np.eye(5), atol=1e-12)
+
+
+def test_first_eigenpair_is_constant():
+    """Row sums of hat A vanish, so lambda_1 = 0 with psi_1 constant on a
+    connected region."""
+    w, A = _small(nx=16, nparts=4, overlap=1)
+    for c in O.cores(w.part, w.nparts):
+        dofs = O.grow(A, c, 1)
+        Ah = O.neumann_matrix(O.local_matrix(A, dofs))
+        s = O.weighting(Ah)
+        lam, psi = O.local_eigenpairs(Ah, s, 2, dofs)
+        assert abs(lam[0]) < 1e-12
+        v = psi[:, 0]
+        np.testing.assert_allclose(v, v.mean(), rtol=1e-10)
+        np.testing.assert_allclose(v @ (s * v), 1.0, rtol=1e-12)
+
+
+@pytest.mark.parametrize("n", [5, 12, 33])
+def test_path_graph_closed_form(n):
+    """Uniform chain: the pencil (Laplacian, degree) has lambda_k =
+    1 - cos(pi k/(n-1)) and psi_k(j) proportional to cos(pi k j/(n-1))."""
+    w = 3.7
+    L = np.zeros((n, n))
+    for j in range(n - 1):
+        L[j, j + 1] = L[j + 1, j] = -w
+    Ah = O.neumann_matrix(L)
+    s = O.weighting(Ah)
+    m = n - 1
+    lam, psi = O.local_eigenpairs(Ah, s, m)
+    k = np.arange(n)
+    np.testing.assert_allclose(lam, 1 - np.cos(np.pi * k / (n - 1)), atol=1e-13)
+    j = np.arange(n)
+    for kk in range(1, min(m, 6)):
+        ref = np.cos(np.pi * kk * j / (n - 1))
+        ref = ref / np.sqrt(ref @ (s * ref))
+        if ref[np.argmax(np.abs(ref))] < 0:
+            ref = -ref
+        assert min(np.abs(psi[:, kk] - ref).max(), np.abs(psi[:, kk] + ref).max()) < 1e-10
+
+
+def test_weighted_three_node_path_spectrum():
+    """Any weighted 3-node path: the normalised pencil spectrum is {0, 1, 2}
+    (bipartite graph; hand derivation)."""
+    for a, b in [(2.0, 5.0), (1e-6, 1e6), (3.0, 3.0)]:
+        L = np.array([[0, -a, 0], [-a, 0, -b], [0, -b, 0]], dtype=float)
+        Ah = O.neumann_matrix(L)
+        lam, _ = O.local_eigenpairs(Ah, O.weighting(Ah), 2)
+        np.testing.assert_allclose(lam, [0, 1, 2], atol=1e-12 * max(1, b / a))
+
+
+# ------------------------------------------------------------ theory -------
+def _nonoverlap_setup(nev, contrast=1e4):
+    w, A = _small(nx=14, nparts=4, overlap=0, nev=nev, contrast=contrast)
+    st = O.setup(A, w.part, w.nparts, nev, overlap=0, pou="none")
+    return w, A, st
+
+
+def test_lemma1_s_norm_additivity():
+    w, A, st = _nonoverlap_setup(2)
+    rng = np.random.default_rng(1)
+    n = A.shape[0]
+    Sglob = np.zeros(n)
+    total = 0.0
+    v = np.zeros(n)
+    for dofs in st.regions:
+        s = O.weighting(O.neumann_matrix(O.local_matrix(A, dofs)))
+        Sglob[dofs] = s
+        x = rng.standard_normal(len(dofs))
+        total += x @ (s * x)
+        v[dofs] += x
+    assert abs(v @ (Sglob * v) - total) <= 1e-13 * total
+
+
+def test_lemma2_energy_splitting():
+    w, A, st = _nonoverlap_setup(2)
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        x = rng.standard_normal(A.shape[0])
+        lhs = sum(x[d] @ O.neumann_matrix(O.local_matrix(A, d)) @ x[d] for d in st.regions)
+        assert lhs <= x @ (A @ x) * (1 + 1e-13)
+
+
+@pytest.mark.parametrize("nev", [1, 3])
+def test_theorem2_approximation_constant(nev):
+    """K = max_x min_{x_c in coarse space} ||x - x_c||_S^2 / ||x||_A^2 <= 1/mu_c
+    with mu_c = min_i lambda_{m_i+1}, by a dense generalized eigenproblem."""
+    w, A, st = _nonoverlap_setup(nev)
+    n = A.shape[0]
+    Sg = np.zeros(n)
+    for dofs in st.regions:
+        Sg[dofs] = O.weighting(O.neumann_matrix(O.local_matrix(A, dofs)))
+    P = st.R0T.toarray()  # no PoU scaling: Boolean zero extension
+    S = np.diag(Sg)
+    # S-orthogonal projector onto the coarse space, error operator I - Pi
+    Pi = P @ np.linalg.solve(P.T @ S @ P, P.T @ S)
+    E = np.eye(n) - Pi
+    K = sla.eigh(E.T @ S @ E, A.toarray(), eigvals_only=True)[-1]
+    mu_c = min(l[nev] for l in st.lam)
+    assert K <= (1.0 / mu_c) * (1 + 1e-9)
+
+
+# ------------------------------------------------------- coarse operator ---
+def test_coarse_operator_galerkin_identities():
+    w, A = _small(nx=16, nparts=4, overlap=1, nev=3)
+    st = O.setup(A, w.part, w.nparts, 3, overlap=1)
+    Ad = A.toarray()
+    R0T = st.R0T.toarray()
+    C = R0T @ np.linalg.solve(st.A0, R0T.T)
+    np.testing.assert_allclose(C @ Ad @ C, C, atol=1e-12 * np.abs(C).max())
+    np.testing.assert_allclose(R0T.T @ (np.eye(A.shape[0]) - Ad @ C), 0,
+                               atol=1e-12 * np.abs(R0T).max())
+
+
+def test_full_coarse_space_is_exact_inverse():
+    """overlap 0 and nev = n_i everywhere: R0^T is square and invertible, so
+    R0^T A0^{-1} R0 = A^{-1}."""
+    w, A = _small(nx=8, nparts=4, overlap=0)
+    ni = np.bincount(w.part).max()
+    st = O.setup(A, w.part, w.nparts, int(ni), overlap=0, pou="none")
+    assert st.nc == A.shape[0]
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(A.shape[0])
+    np.testing.assert_allclose(O.coarse_part(st, r), spla.spsolve(A.tocsc(), r), rtol=1e-10)
+
+
+# ------------------------------------------------------- preconditioner ---
+def test_preconditioner_is_spd():
+    w, A = _small(nx=16, nparts=4, overlap=1, nev=2)
+    st = O.setup(A, w.part, w.nparts, 2, overlap=1)
+    n = A.shape[0]
+    M = np.column_stack([st.apply(e) for e in np.eye(n)])
+    assert np.abs(M - M.T).max() <= 1e-13 * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+
+
+def test_condition_number_dense_vs_lanczos():
+    w, A = _small(nx=16, nparts=4, overlap=1, nev=2)
+    st = O.setup(A, w.part, w.nparts, 2, overlap=1)
+    n = A.shape[0]
+    M = np.column_stack([st.apply(e) for e in np.eye(n)])
+    ev = np.sort(np.linalg.eigvals(M @ A.toarray()).real)
+    kappa = ev[-1] / ev[0]
+    res = O.pcg(A, np.random.default_rng(4).standard_normal(n), st.apply, rtol=1e-14, maxit=n)
+    est = O.lanczos_condition(res.alphas, res.betas)
+    assert abs(est - kappa) <= 1e-3 * kappa
+
+
+# ------------------------------------------------------------------ PCG ----
+def test_pcg_identity_matches_scipy_cg():
+    w, A = _small(nx=12, nparts=4)
+    f = np.random.default_rng(5).standard_normal(A.shape[0])
+    ours = O.pcg(A, f, lambda r: r.copy(), rtol=1e-30, maxit=15)
+    iterates = []
+    spla.cg(A, f, x0=np.zeros_like(f), rtol=1e-30, maxiter=15, callback=lambda x: iterates.append(x.copy()))
+    assert len(iterates) >= 15
+    np.testing.assert_allclose(ours.x, iterates[14], rtol=1e-9, atol=1e-12 * np.abs(iterates[14]).max())
+
+
+def test_pcg_solution_matches_direct_solve():
+    w = W.get("channels64")
+    A = w.A.to_scipy()
+    st = O.setup(A, w.part, w.nparts, w.nev, w.overlap)
+    res = O.pcg(A, w.b, st.apply, rtol=1e-8)
+    assert res.converged and res.relres_true <= 1e-8 * 1.01
+    u = spla.spsolve(A.tocsc(), w.b)
+    assert np.linalg.norm(res.x - u) / np.linalg.norm(u) < 1e-5
+    assert res.iterations <= A.shape[0]
+
+
+def test_contrast_flatness():
+    """Iteration counts stay flat as the channel contrast grows (the trend of
+    the paper's contrast tables), while one-level Schwarz (nev = 0) degrades."""
+    its, its0 = [], []
+    for c in [0, 2, 4, 6]:
+        w = configs.channels(contrast=10.0 ** c)
+        A = w.A.to_scipy()
+        st = O.setup(A, w.part, w.nparts, 4, 1)
+        its.append(O.pcg(A, w.b, st.apply, 1e-8).iterations)
+        st0 = O.setup(A, w.part, w.nparts, 0, 1)
+        its0.append(O.pcg(A, w.b, st0.apply, 1e-8).iterations)
+    assert max(its) <= 1.5 * its[0], its
+    assert its0[-1] > its[-1], (its0, its)
+
+
+# -------------------------------------------- planted-mistake detection ----
+def test_planted_mistakes_are_caught(monkeypatch):
+    """Each plausible slip in the oracle breaks one of the pins above."""
+    g = __import__("conftest").load_golden("worked_1d_4cell.txt")
+    A = sp.csr_matrix(g["A"])
+    part = g["part"].astype(np.int32)
+
+    def minv_f(**patch):
+        for k, v in patch.items():
+            monkeypatch.setattr(O.amsp_oracle, k, v)
+        try:
+            return O.setup(A, part, 2, 1, overlap=1).apply(g["f"])
+        except O.OracleError:
+            return None  # the slip is rejected outright
+        finally:
+            monkeypatch.undo()
+
+    ref = g["overlap1.Minv_f"]
+    np.testing.assert_allclose(minv_f(), ref, rtol=1e-13)
+
+    real_neu = O.amsp_oracle.neumann_matrix
+    real_pro = O.amsp_oracle.prolongation
+    # wrong sign of the Neumann diagonal (diag = +sum of off-diagonals)
+    def flipped(Ai):
+        M = real_neu(Ai)
+        np.fill_diagonal(M, -np.diag(M))
+        return M
+    bad1 = minv_f(neumann_matrix=flipped)
+    # Dirichlet diagonal kept instead of the Neumann one
+    bad2 = minv_f(neumann_matrix=lambda Ai: Ai.copy())
+    # partition of unity dropped
+    bad3 = minv_f(prolongation=lambda n, reg, psis, mult, pou="mult": real_pro(n, reg, psis, mult, "none"))
+    # eigenvectors not scaled back by S^{-1/2}
+    real_eig = O.amsp_oracle.local_eigenpairs
+    def unscaled(Ah, s, m, gdofs=None):
+        lam, psi = real_eig(Ah, s, m, gdofs)
+        return lam, psi * np.sqrt(s)[:, None]
+    bad4 = minv_f(local_eigenpairs=unscaled)
+    for bad in (bad1, bad2, bad3, bad4):
+        assert bad is None or np.abs(bad - ref).max() > 1e-3

@@ -1,0 +1,59 @@
+"""Generator and partitioner checks (host inputs shared by oracle and HIP path)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import configs, darcy
+
+
+def _check_mmatrix(A):
+    S = A.to_scipy()
+    assert abs(S - S.T).max() == 0.0
+    off = S.copy()
+    off.setdiag(0)
+    assert off.data.max() <= 0.0
+    assert np.asarray(S.sum(axis=1)).min() >= -1e-12 * abs(S).max()
+    assert (S.diagonal() > 0).all()
+    # sorted columns
+    for i in range(0, A.n, max(1, A.n // 50)):
+        c = A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]
+        assert (np.diff(c) > 0).all()
+
+
+def test_channels64_shape_and_mmatrix():
+    w = W.get("channels64")
+    assert w.n == 4096 and w.A.nnz == 5 * 4096 - 4 * 64
+    _check_mmatrix(w.A)
+    assert set(np.unique(w.kappa)) == {1.0, 1e4}
+
+
+def test_3d_tpfa_nnz_and_anisotropy():
+    k = np.ones((6, 6, 6))
+    A = darcy.tpfa_matrix(k, 0.1 * k)
+    assert A.n == 216 and A.nnz == 7 * 216 - 6 * 36
+    _check_mmatrix(A)
+    S = A.to_scipy()
+    # x coupling h^(d-2)*harm(1,1) = 1/6; z coupling a tenth of that
+    assert np.isclose(S[0, 1], -1.0 / 6) and np.isclose(S[0, 36], -0.1 / 6)
+
+
+def test_seeds_reproduce():
+    a = configs.gauss_inclusions(nx=64, nparts=4)
+    b = configs.gauss_inclusions(nx=64, nparts=4)
+    assert np.array_equal(a.A.val, b.A.val) and np.array_equal(a.b, b.b)
+    assert a.part_sha256() == b.part_sha256()
+
+
+@pytest.mark.parametrize("nparts", [1, 3, 16, 37])
+def test_partition_covers_balanced(nparts):
+    w = configs.channels(nx=40, nparts=nparts)
+    cnt = np.bincount(w.part, minlength=nparts)
+    assert cnt.sum() == 1600 and (cnt > 0).all()
+    assert cnt.max() - cnt.min() <= 2
+
+
+def test_grf_statistics():
+    rng = np.random.default_rng(0)
+    f = darcy.gaussian_random_field((256, 256), 4.0, 0.05, rng)
+    assert abs(f.var() - 4.0) < 1.5
+    assert abs(f.mean()) < 1.5

@@ -1,0 +1,109 @@
+"""Named workloads: seeded synthetic heterogeneous Darcy problems.
+
+Each workload bundles the matrix, the right-hand side, the host partition and
+the preconditioner parameters (overlap layers, eigenvectors per subdomain).
+Seeds: workload K uses numpy default_rng seeded from SeedSequence(260604864 + K)
+with spawned sub-streams for field, source and geometry.
+
+The paper's fields exist only as figures, so these recipes stand in for them:
+  * channels64   -- 64x64, background 1 with 8 straight channels (width 2,
+                    kappa 1e4), f = 1, 16 parts, 1 overlap layer, 4 eigenvectors.
+  * gauss1024    -- 1024x1024, kappa = exp(GRF(var 4, corr 0.05)) times 1e6 in 200
+                    disks of radius 3-10 cells, f ~ N(0,1), 1024 parts, 2 overlap
+                    layers, 6 eigenvectors.
+  * layered128   -- 128^3 7-point, 32 layers of extruded exp(GRF(var 3)) with two
+                    sinuous channels (x1e6) per layer, kz = 0.1 kx, 4096 parts,
+                    1 overlap layer, 8 eigenvectors.
+  * gauss<N>     -- the gauss1024 recipe at a smaller side N (parity sizes).
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+
+import numpy as np
+
+from . import darcy
+from .partition import partition, partition_hash
+
+SEED_BASE = 260604864
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    A: darcy.CSR
+    b: np.ndarray
+    part: np.ndarray
+    nparts: int
+    overlap: int
+    nev: int
+    kappa: np.ndarray
+    grid: tuple
+
+    @property
+    def n(self) -> int:
+        return self.A.n
+
+    def part_sha256(self) -> str:
+        return partition_hash(self.part)
+
+
+def _streams(k: int, count: int = 4):
+    ss = np.random.SeedSequence(SEED_BASE + k)
+    return [np.random.default_rng(s) for s in ss.spawn(count)]
+
+
+def channels(nx: int = 64, nparts: int = 16, overlap: int = 1, nev: int = 4,
+             contrast: float = 1e4, nchan: int = 8, seed_key: int = 1) -> Workload:
+    rng_geo, _, _, _ = _streams(seed_key)
+    kappa = darcy.channel_field_2d(nx, nchan, 2, contrast, rng_geo)
+    A = darcy.tpfa_matrix(kappa)
+    b = darcy.rhs_from_source(np.ones((nx, nx)))
+    part = partition(A.row_ptr, A.col_idx, nparts)
+    return Workload(f"channels{nx}", A, b, part, nparts, overlap, nev, kappa, (nx, nx))
+
+
+def gauss_inclusions(nx: int = 1024, nparts: int = 1024, overlap: int = 2, nev: int = 6,
+                     var: float = 4.0, corr: float = 0.05, ndisks: int | None = None,
+                     factor: float = 1e6, seed_key: int = 2) -> Workload:
+    rng_field, rng_src, rng_geo, _ = _streams(seed_key)
+    logk = darcy.gaussian_random_field((nx, nx), var, corr, rng_field)
+    kappa = np.exp(logk)
+    if ndisks is None:
+        ndisks = max(1, round(200 * (nx / 1024) ** 2))
+    kappa = darcy.disk_inclusions_2d(kappa, ndisks, 3.0, 10.0, factor, rng_geo)
+    A = darcy.tpfa_matrix(kappa)
+    b = darcy.rhs_from_source(rng_src.standard_normal((nx, nx)))
+    part = partition(A.row_ptr, A.col_idx, nparts)
+    return Workload(f"gauss{nx}", A, b, part, nparts, overlap, nev, kappa, (nx, nx))
+
+
+def layered(n: int = 128, nparts: int = 4096, overlap: int = 1, nev: int = 8,
+            seed_key: int = 3) -> Workload:
+    rng_field, rng_src, _, _ = _streams(seed_key)
+    nlayers = 32 if n >= 32 else max(1, n // 4)
+    kx = darcy.layered_channel_field_3d(n, nlayers, 3.0, 0.1, 2, 3, 1e6, rng_field)
+    A = darcy.tpfa_matrix(kx, 0.1 * kx)
+    b = darcy.rhs_from_source(rng_src.standard_normal((n, n, n)))
+    part = partition(A.row_ptr, A.col_idx, nparts)
+    return Workload(f"layered{n}", A, b, part, nparts, overlap, nev, kx, (n, n, n))
+
+
+@functools.lru_cache(maxsize=8)
+def get(name: str) -> Workload:
+    """Workloads by name; cached per process."""
+    if name == "channels64":
+        return channels()
+    if name == "gauss1024":
+        return gauss_inclusions()
+    if name == "layered128":
+        return layered()
+    if name.startswith("gauss"):
+        nx = int(name[5:])
+        nparts = max(4, (nx * nx) // 1024)
+        return gauss_inclusions(nx=nx, nparts=nparts)
+    if name.startswith("channels"):
+        nx = int(name[8:])
+        return channels(nx=nx, nparts=max(4, (nx * nx) // 256))
+    raise KeyError(name)
