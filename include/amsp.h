@@ -1,0 +1,180 @@
+/*
+ * amsp.h -- C ABI of the MI355X two-grid algebraic multiscale preconditioner.
+ *
+ * Method: "An algebraic multiscale preconditioner for large sparse SPD
+ * matrices" (Zhou, Fu, Chung).  Section 3.1 defines the non-overlapping
+ * graph subdomains, the coarse space spanned by locally supported basis
+ * vectors (columns of R0^T) and the Galerkin coarse matrix A0 = R0 A R0^T;
+ * Section 3.2 defines the local matrices A_i = R_i A R_i^T, the Neumann
+ * modification hat A_i (diagonal replaced by minus the sum of the row's
+ * off-diagonals), the weighting S_i = diag(hat A_i) and the local generalized
+ * eigenproblem hat A_i psi = lambda S_i psi whose lowest modes form R0^T;
+ * Section 5 (parameter test) solves it in the standard form
+ * S^{-1/2} hat A S^{-1/2} z = lambda z.
+ *
+ * The preconditioner applied here is the additive two-level operator
+ *     M^{-1} r = sum_i R_i^T A_i^{-1} R_i r  +  R0^T A0^{-1} R0 r
+ * on overlapping regions (delta graph layers around each core), with every
+ * local eigenvector divided by the multiplicity of its dof (partition of
+ * unity).  It is SPD, so the Krylov method is preconditioned CG.
+ *
+ * Conventions shared by every entry point:
+ *   - Host inputs (CSR, partition) are borrowed for the call and copied.
+ *   - Vectors named *_dev are caller-owned device buffers (HIP device
+ *     pointers, e.g. torch tensors' data_ptr()), float64, column-major
+ *     n x nrhs.
+ *   - All device work is ordered on the stream given in amsp_options.stream
+ *     (a hipStream_t; NULL = the legacy default stream).
+ *   - Errors are status codes; nothing throws or aborts across the ABI.
+ *     amsp_last_error() gives a message (e.g. the failing subdomain).
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef AMSP_H
+#define AMSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMSP_OK = 0,
+  AMSP_ERR_ARG = -1,            /* bad argument (null pointer, nev < 0, ...)           */
+  AMSP_ERR_CSR = -2,            /* malformed CSR (row_ptr, unsorted/out-of-range cols) */
+  AMSP_ERR_NONSYM = -3,         /* values not symmetric to 1e-14 max|a|               */
+  AMSP_ERR_PARTITION = -4,      /* part[j] out of range or an empty part              */
+  AMSP_ERR_NEUMANN_DIAG = -5,   /* some S_jj <= 0 (weighting matrix not positive)      */
+  AMSP_ERR_LOCAL_NOT_SPD = -6,  /* Cholesky of a local matrix failed                   */
+  AMSP_ERR_EIG_NOCONV = -7,     /* local eigensolver hit eig_maxit (see setup info)    */
+  AMSP_ERR_COARSE_NOT_SPD = -8, /* Cholesky of A0 failed                               */
+  AMSP_ERR_PCG_NOCONV = -9,     /* PCG hit maxit; u holds the last iterate             */
+  AMSP_ERR_BREAKDOWN = -10,     /* non-finite or zero curvature in PCG                 */
+  AMSP_ERR_HIP = -11,           /* a HIP runtime call failed                           */
+  AMSP_ERR_OOM = -12            /* device or host allocation failed                    */
+} amsp_status;
+
+/* Storage precision of the local factors, the coarse basis and the coarse
+ * inverse factor used by the apply.  The outer CG, its dot products, A0 and
+ * its Cholesky factorisation are float64 in every form. */
+typedef enum {
+  AMSP_FP64 = 0,        /* everything float64                                         */
+  AMSP_MIXED_FP32 = 1,  /* local factors, basis, coarse inverse factor stored float32,  */
+                        /* applied with float32 accumulation; eigensolve sweeps float32 */
+  AMSP_MIXED_BF16 = 2   /* as MIXED_FP32 but the coarse basis stored bfloat16           */
+} amsp_precision;
+
+typedef enum {
+  AMSP_ORDER_RCM = 0,     /* reverse Cuthill-McKee local order, tile profile (default) */
+  AMSP_ORDER_NATURAL = 1  /* ascending global index, tile profile                       */
+} amsp_local_order;
+
+/* Host CSR matrix, symmetric positive definite, sorted columns, diagonal
+ * present.  row_ptr has n+1 entries; nnz = row_ptr[n] < 2^31. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const double *val;
+} amsp_csr;
+
+typedef struct {
+  int32_t overlap;          /* delta: graph layers added around each core (default 1)  */
+  amsp_precision precision; /* default AMSP_FP64                                        */
+  int32_t pou;              /* 0: divide by dof multiplicity (default); 1: none         */
+  int32_t local_order;      /* amsp_local_order                                         */
+  int32_t dense_tiles;      /* 1: store the full lower triangle of tiles (no profile)   */
+  double eig_tol;           /* residual bound ||B x - theta x|| for the kept pairs;      */
+                            /* 0 (default): 1e-10, or 1e-5 for the mixed forms           */
+  int32_t eig_maxit;        /* maximum subspace sweeps (default 80)                      */
+  double eig_shift;         /* sigma in (B + sigma I)^{-1} (default 1e-4)                */
+  int32_t chunk;            /* PCG iterations per host poll (default 8)                  */
+  int32_t flexible;         /* 1: Polak-Ribiere beta; -1 (default): on for mixed forms   */
+  int32_t keep_a0;          /* 1: keep a copy of A0 for amsp_get_coarse_matrix           */
+  void *stream;             /* hipStream_t                                               */
+} amsp_options;
+
+typedef struct {
+  int32_t iterations;       /* CG steps taken (SpMVs with the search direction)   */
+  int32_t converged;        /* 1 if the true relative residual <= rtol            */
+  double relres_recursive;  /* ||r_k|| / ||f|| from the recurrence                 */
+  double relres_true;       /* ||f - A u|| / ||f|| recomputed at the end           */
+  int32_t restarts;         /* residual replacements after a false convergence     */
+  double solve_ms;          /* wall time of the call                               */
+  int64_t bytes_per_iter;   /* algorithmic HBM bytes of one CG iteration           */
+} amsp_info;
+
+typedef struct {
+  int32_t nsub;             /* N subdomains                                         */
+  int32_t nc;               /* coarse dimension N_c = sum_i m_i                     */
+  int64_t sum_ni;           /* sum of region sizes                                  */
+  int32_t max_ni;
+  int64_t factor_tiles;     /* 64x64 tiles of one local factor set                  */
+  int32_t eig_sweeps;       /* subspace sweeps used                                 */
+  int32_t eig_unconverged;  /* subdomains not converged at eig_maxit                */
+  int32_t n_gap_flags;      /* subdomains with lambda_{m+1} - lambda_m tiny         */
+  double mu_c;              /* min_i lambda_{m_i+1}                                 */
+  double phase_ms[8];       /* plan, upload, extract, local chol, eig, basis+A0,    */
+                            /* coarse chol+inverse, total                           */
+} amsp_setup_info;
+
+typedef struct amsp_handle amsp_handle;
+
+/* Fills *opt with the defaults listed above. */
+void amsp_default_options(amsp_options *opt);
+
+/* Setup (Sections 3.1-3.2): validates A and the partition on the host,
+ * plans the overlapping regions, then on the device extracts the local
+ * matrices, factors them, solves the batched local eigenproblems, builds the
+ * PoU-scaled basis, forms A0 = R0 A R0^T and factors it.
+ *   A         host CSR (copied).
+ *   partition host int32[n], values in [0, nparts); every part non-empty.
+ *   nev       eigenvectors kept per subdomain (m_i = min(nev, n_i)); 0 gives
+ *             one-level additive Schwarz.
+ *   opt       NULL for defaults.
+ *   out       receives the handle; NULL on failure.
+ * Blocks until the setup is complete. */
+amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, int32_t nparts,
+                       int32_t nev, const amsp_options *opt, amsp_handle **out);
+
+/* z = M^{-1} r for nrhs columns (asynchronous on the handle's stream).
+ * parts: 3 = both terms, 1 = local solves only, 2 = coarse correction only. */
+amsp_status amsp_apply(amsp_handle *h, const double *r_dev, double *z_dev, int32_t nrhs);
+amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
+                             int32_t nrhs, int32_t parts);
+
+/* Preconditioned CG from u = 0 until ||f - A u|| <= rtol ||f|| (recursive
+ * residual, confirmed by the true residual; a replacement restart follows a
+ * false convergence).  Blocks; info may be NULL.  On AMSP_ERR_PCG_NOCONV u
+ * holds the last iterate and the handle stays valid. */
+amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
+                     double rtol, int32_t maxit, amsp_info *info);
+
+/* y = A x with the handle's matrix (asynchronous). */
+amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_dev);
+
+/* Introspection (host copies; each blocks on the stream). */
+amsp_status amsp_get_setup_info(const amsp_handle *h, amsp_setup_info *info);
+/* lambda_host: N*(nev+1) values; row i holds lambda_1..lambda_{m_i+1} of
+ * subdomain i (unused slots = NaN). */
+amsp_status amsp_get_eigenvalues(const amsp_handle *h, double *lambda_host);
+/* A0 as a dense row-major nc x nc float64 matrix (needs opt.keep_a0 = 1). */
+amsp_status amsp_get_coarse_matrix(const amsp_handle *h, double *a0_host);
+/* Region of subdomain i: fills dofs (n_i global indices in the handle's
+ * local order) and, if phi is not NULL, the n_i x nev row-major block of
+ * PoU-scaled basis vectors (columns >= m_i are zero).  Call with dofs = NULL
+ * to get n_i in *ni first. */
+amsp_status amsp_get_region(const amsp_handle *h, int32_t i, int32_t *ni, int32_t *dofs,
+                            double *phi);
+
+void amsp_destroy(amsp_handle *h);
+const char *amsp_status_string(amsp_status s);
+const char *amsp_last_error(const amsp_handle *h);
+/* Message of the last failed amsp_setup in this thread (no handle exists). */
+const char *amsp_setup_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMSP_H */

@@ -1,0 +1,252 @@
+"""MI355X two-grid algebraic multiscale preconditioner (HIP, gfx950).
+
+Thin ctypes binding over the C ABI in include/amsp.h: it only marshals
+arguments.  Every step of setup, apply and PCG runs in the HIP kernels of
+libamsp.so; PyTorch tensors provide device memory and the HIP stream.  There
+is no CPU fallback: importing this package fails loudly when the library is
+missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamsp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_04864_amd.build` "
+                      "(hipcc --offload-arch=gfx950)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes
+AMSP_OK = 0
+STATUS = {0: "AMSP_OK", -1: "AMSP_ERR_ARG", -2: "AMSP_ERR_CSR", -3: "AMSP_ERR_NONSYM",
+          -4: "AMSP_ERR_PARTITION", -5: "AMSP_ERR_NEUMANN_DIAG", -6: "AMSP_ERR_LOCAL_NOT_SPD",
+          -7: "AMSP_ERR_EIG_NOCONV", -8: "AMSP_ERR_COARSE_NOT_SPD", -9: "AMSP_ERR_PCG_NOCONV",
+          -10: "AMSP_ERR_BREAKDOWN", -11: "AMSP_ERR_HIP", -12: "AMSP_ERR_OOM"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+ORDER = {"rcm": 0, "natural": 1}
+
+
+class AmspError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        self.msg = msg
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("overlap", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("pou", ctypes.c_int32), ("local_order", ctypes.c_int32),
+                ("dense_tiles", ctypes.c_int32), ("eig_tol", ctypes.c_double),
+                ("eig_maxit", ctypes.c_int32), ("eig_shift", ctypes.c_double),
+                ("chunk", ctypes.c_int32), ("flexible", ctypes.c_int32),
+                ("keep_a0", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("relres_recursive", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("restarts", ctypes.c_int32), ("solve_ms", ctypes.c_double),
+                ("bytes_per_iter", ctypes.c_int64)]
+
+
+class _SetupInfo(ctypes.Structure):
+    _fields_ = [("nsub", ctypes.c_int32), ("nc", ctypes.c_int32), ("sum_ni", ctypes.c_int64),
+                ("max_ni", ctypes.c_int32), ("factor_tiles", ctypes.c_int64),
+                ("eig_sweeps", ctypes.c_int32), ("eig_unconverged", ctypes.c_int32),
+                ("n_gap_flags", ctypes.c_int32), ("mu_c", ctypes.c_double),
+                ("phase_ms", ctypes.c_double * 8)]
+
+
+_vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_lib.amsp_default_options.argtypes = [ctypes.POINTER(_Options)]
+_lib.amsp_setup.argtypes = [ctypes.POINTER(_CSR), _vp, _i32, _i32, ctypes.POINTER(_Options),
+                            ctypes.POINTER(_vp)]
+_lib.amsp_setup.restype = _i32
+_lib.amsp_apply.argtypes = [_vp, _vp, _vp, _i32]
+_lib.amsp_apply.restype = _i32
+_lib.amsp_apply_parts.argtypes = [_vp, _vp, _vp, _i32, _i32]
+_lib.amsp_apply_parts.restype = _i32
+_lib.amsp_pcg.argtypes = [_vp, _vp, _vp, _i32, _d, _i32, ctypes.POINTER(_Info)]
+_lib.amsp_pcg.restype = _i32
+_lib.amsp_spmv.argtypes = [_vp, _vp, _vp]
+_lib.amsp_spmv.restype = _i32
+_lib.amsp_get_setup_info.argtypes = [_vp, ctypes.POINTER(_SetupInfo)]
+_lib.amsp_get_setup_info.restype = _i32
+_lib.amsp_get_eigenvalues.argtypes = [_vp, _vp]
+_lib.amsp_get_eigenvalues.restype = _i32
+_lib.amsp_get_coarse_matrix.argtypes = [_vp, _vp]
+_lib.amsp_get_coarse_matrix.restype = _i32
+_lib.amsp_get_region.argtypes = [_vp, _i32, ctypes.POINTER(_i32), _vp, _vp]
+_lib.amsp_get_region.restype = _i32
+_lib.amsp_destroy.argtypes = [_vp]
+_lib.amsp_status_string.argtypes = [_i32]
+_lib.amsp_status_string.restype = ctypes.c_char_p
+_lib.amsp_last_error.argtypes = [_vp]
+_lib.amsp_last_error.restype = ctypes.c_char_p
+_lib.amsp_setup_error.argtypes = []
+_lib.amsp_setup_error.restype = ctypes.c_char_p
+
+EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts", "amsp_pcg",
+            "amsp_spmv", "amsp_get_setup_info", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
+            "amsp_get_region", "amsp_destroy", "amsp_status_string", "amsp_last_error",
+            "amsp_setup_error"]
+
+
+def default_options() -> dict:
+    o = _Options()
+    _lib.amsp_default_options(ctypes.byref(o))
+    return {name: getattr(o, name) for name, _ in _Options._fields_ if name != "stream"}
+
+
+def _torch():
+    import torch  # imported lazily so that the C-ABI checks run without a GPU
+    return torch
+
+
+def _check_dev(t, name, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.shape[0] != n:
+        raise ValueError(f"{name} must have {n} rows")
+
+
+class Preconditioner:
+    """Handle over amsp_setup / amsp_apply / amsp_pcg.
+
+    A: (row_ptr int64[n+1], col_idx int32[nnz], val float64[nnz]) host arrays
+    part: int32[n] host partition with values in [0, nparts)
+    """
+
+    def __init__(self, row_ptr, col_idx, val, part, nparts: int, nev: int, *, overlap: int = 1,
+                 precision: str = "fp64", pou: int = 0, local_order: str = "rcm",
+                 dense_tiles: bool = False, eig_tol: float = 0.0, eig_maxit: int = 80,
+                 eig_shift: float = 1e-4, chunk: int = 8, flexible: int = -1,
+                 keep_a0: bool = False, stream=None):
+        torch = _torch()
+        self._h = None
+        self._keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
+                      np.ascontiguousarray(col_idx, dtype=np.int32),
+                      np.ascontiguousarray(val, dtype=np.float64),
+                      np.ascontiguousarray(part, dtype=np.int32)]
+        rp, ci, va, pa = self._keep
+        self.n = len(rp) - 1
+        self.nparts = int(nparts)
+        self.nev = int(nev)
+        csr = _CSR(self.n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+        o = _Options()
+        _lib.amsp_default_options(ctypes.byref(o))
+        o.overlap, o.precision, o.pou = int(overlap), PRECISION[precision], int(pou)
+        o.local_order, o.dense_tiles = ORDER[local_order], int(bool(dense_tiles))
+        o.eig_tol, o.eig_maxit, o.eig_shift = float(eig_tol), int(eig_maxit), float(eig_shift)
+        o.chunk, o.flexible, o.keep_a0 = int(chunk), int(flexible), int(bool(keep_a0))
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        h = ctypes.c_void_p()
+        st = _lib.amsp_setup(ctypes.byref(csr), pa.ctypes.data, self.nparts, self.nev,
+                             ctypes.byref(o), ctypes.byref(h))
+        if st != AMSP_OK:
+            raise AmspError(st, _lib.amsp_setup_error().decode())
+        self._h = h
+        self.precision = precision
+        self.info = self.setup_info()
+
+    # -- lifetime
+    def close(self):
+        if self._h is not None:
+            _lib.amsp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st):
+        if st != AMSP_OK:
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
+
+    # -- compute
+    def apply(self, r, out=None, parts: int = 3):
+        """z = M^{-1} r (r: float64 device tensor of shape (n,) or (n, k))."""
+        torch = _torch()
+        _check_dev(r, "r", self.n)
+        z = out if out is not None else torch.empty_like(r)
+        nrhs = 1 if r.dim() == 1 else r.shape[1]
+        rr = r if r.dim() == 1 else r.t().contiguous()
+        zz = z if r.dim() == 1 else torch.empty_like(rr)
+        self._err(_lib.amsp_apply_parts(self._h, rr.data_ptr(), zz.data_ptr(), nrhs, parts))
+        if r.dim() == 2:
+            z.copy_(zz.t())
+        return z
+
+    def spmv(self, x, out=None):
+        torch = _torch()
+        _check_dev(x, "x", self.n)
+        y = out if out is not None else torch.empty_like(x)
+        self._err(_lib.amsp_spmv(self._h, x.data_ptr(), y.data_ptr()))
+        return y
+
+    def pcg(self, f, rtol: float = 1e-8, maxit: int = 1000, out=None, raise_on_noconv=True):
+        """Solve A u = f by preconditioned CG; returns (u, info dict)."""
+        torch = _torch()
+        _check_dev(f, "f", self.n)
+        u = out if out is not None else torch.empty_like(f)
+        inf = _Info()
+        st = _lib.amsp_pcg(self._h, f.data_ptr(), u.data_ptr(), 1, float(rtol), int(maxit),
+                           ctypes.byref(inf))
+        info = {name: getattr(inf, name) for name, _ in _Info._fields_}
+        info["status"] = STATUS.get(st, st)
+        if st != AMSP_OK and (raise_on_noconv or st != -9):
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
+        return u, info
+
+    # -- introspection
+    def setup_info(self) -> dict:
+        si = _SetupInfo()
+        self._err(_lib.amsp_get_setup_info(self._h, ctypes.byref(si)))
+        d = {name: getattr(si, name) for name, _ in _SetupInfo._fields_ if name != "phase_ms"}
+        d["phase_ms"] = list(si.phase_ms)
+        return d
+
+    def eigenvalues(self) -> np.ndarray:
+        out = np.empty((self.nparts, self.nev + 1), dtype=np.float64)
+        self._err(_lib.amsp_get_eigenvalues(self._h, out.ctypes.data))
+        return out
+
+    def coarse_matrix(self) -> np.ndarray:
+        nc = self.info["nc"]
+        out = np.empty((nc, nc), dtype=np.float64)
+        self._err(_lib.amsp_get_coarse_matrix(self._h, out.ctypes.data))
+        return out
+
+    def region(self, i: int, with_basis: bool = True):
+        ni = ctypes.c_int32()
+        self._err(_lib.amsp_get_region(self._h, int(i), ctypes.byref(ni), None, None))
+        dofs = np.empty(ni.value, dtype=np.int32)
+        phi = np.empty((ni.value, max(self.nev, 1)), dtype=np.float64) if with_basis else None
+        self._err(_lib.amsp_get_region(self._h, int(i), ctypes.byref(ni), dofs.ctypes.data,
+                                       phi.ctypes.data if (with_basis and self.nev > 0) else None))
+        return dofs, (phi[:, :self.nev] if with_basis else None)
+
+
+def setup(A, part, nparts, nev, **kw) -> Preconditioner:
+    """A: object with row_ptr, col_idx, val (e.g. workloads.CSR)."""
+    return Preconditioner(A.row_ptr, A.col_idx, A.val, part, nparts, nev, **kw)

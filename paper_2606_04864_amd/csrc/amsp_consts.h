@@ -1,0 +1,12 @@
+// Compile-time constants shared by host planning and the HIP kernels.
+#pragma once
+
+namespace amsp {
+
+constexpr int TS = 64;       // tile edge: 64x64 tiles, one wavefront-wide row block
+constexpr int TE = TS * TS;  // elements per tile
+constexpr int WG = 256;      // workgroup size of the batched kernels (4 wavefronts)
+constexpr int EIGP = 16;     // subspace block width of the local eigensolver
+constexpr int MAXNEV = 15;   // nev + 1 must fit in the subspace block
+
+}  // namespace amsp

@@ -1,0 +1,762 @@
+// C ABI of the two-grid algebraic multiscale preconditioner (see include/amsp.h):
+// handle lifetime, device setup orchestration, the preconditioner apply and
+// the preconditioned CG driver.  All arithmetic runs in the HIP kernels;
+// this file moves data, launches kernels and reads back status words.
+#include <hip/hip_bf16.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/amsp.h"
+#include "amsp_internal.h"
+#include "amsp_plan.h"
+
+using namespace amsp;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct DevArena {
+  std::vector<void *> ptrs;
+  size_t bytes = 0;
+  ~DevArena() { release(); }
+  void release() {
+    for (void *p : ptrs) hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  template <typename T>
+  T *alloc(size_t count) {
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    bytes += count * sizeof(T);
+    return static_cast<T *>(p);
+  }
+  void free_one(void *p) {
+    for (size_t k = 0; k < ptrs.size(); ++k)
+      if (ptrs[k] == p) {
+        hipFree(p);
+        ptrs.erase(ptrs.begin() + k);
+        return;
+      }
+  }
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct amsp_handle {
+  amsp_options opt{};
+  hipStream_t stream = nullptr;
+  int n = 0, N = 0, nev = 0, nc = 0, T0 = 0;
+  int64_t nnz = 0;
+  HostPlan hp;
+  DevArena mem;
+  // matrix
+  int *rowptr = nullptr, *col = nullptr;
+  double *val = nullptr;
+  // plan
+  Plan plan{};
+  CoarsePlan cplan{};
+  int *inv_ptr = nullptr, *inv_sd = nullptr, *inv_loc = nullptr;
+  int ntilerows = 0;
+  // local factors and basis
+  double *sdiag = nullptr;
+  double *fac64 = nullptr;
+  float *fac32 = nullptr;
+  double *phi64 = nullptr;
+  void *phi_lo = nullptr;  // float or bf16 copy used by the mixed apply
+  double *lam = nullptr;   // N*(nev+1)
+  // coarse
+  double *a0keep = nullptr;  // copy of A0 tiles before factorisation (introspection)
+  double *W0 = nullptr;
+  float *W0f = nullptr;
+  // apply scratch
+  double *xloc = nullptr, *cvec = nullptr, *t1 = nullptr, *tvec = nullptr, *trmv_part = nullptr;
+  // pcg scratch
+  double *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+  double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr, *scal = nullptr;
+  PcgState *st = nullptr;
+  amsp_setup_info sinfo{};
+  std::string err;
+};
+
+#define HIP_TRY(expr)                                                     \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) {                                               \
+      h->err = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+      return AMSP_ERR_HIP;                                                \
+    }                                                                     \
+  } while (0)
+
+#define ALLOC(dst, T, count)                                              \
+  do {                                                                    \
+    dst = h->mem.alloc<T>(count);                                         \
+    if (!dst) {                                                           \
+      h->err = "device allocation failed: " #dst;                          \
+      return AMSP_ERR_OOM;                                                \
+    }                                                                     \
+  } while (0)
+
+template <typename T>
+static T *upload(amsp_handle *h, const std::vector<T> &v, bool &ok) {
+  T *d = h->mem.alloc<T>(v.size());
+  if (!d) {
+    ok = false;
+    return nullptr;
+  }
+  if (!v.empty() &&
+      hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+    ok = false;
+    return nullptr;
+  }
+  return d;
+}
+
+extern "C" void amsp_default_options(amsp_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->overlap = 1;
+  opt->precision = AMSP_FP64;
+  opt->pou = 0;
+  opt->local_order = AMSP_ORDER_RCM;
+  opt->dense_tiles = 0;
+  opt->eig_tol = 0.0;  // 0: 1e-10 (FP64) or 1e-5 (mixed forms)
+  opt->eig_maxit = 80;
+  opt->eig_shift = 1e-4;
+  opt->chunk = 8;
+  opt->flexible = -1;  // -1: on for the mixed forms
+  opt->stream = nullptr;
+}
+
+static amsp_status sync_status(amsp_handle *h, const int *dstatus, int N, int mask, int &first_bad) {
+  std::vector<int> st(N);
+  HIP_TRY(hipMemcpyAsync(st.data(), dstatus, N * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  first_bad = -1;
+  for (int i = 0; i < N; ++i)
+    if (st[i] & mask) {
+      first_bad = i;
+      break;
+    }
+  return AMSP_OK;
+}
+
+static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
+  HostPlan &P = h->hp;
+  const bool mixed = h->opt.precision != AMSP_FP64;
+  double t0 = now_ms();
+  bool ok = true;
+  // --- upload matrix and plan
+  {
+    std::vector<int> rp32(h->n + 1);
+    for (int i = 0; i <= h->n; ++i) rp32[i] = (int)A->row_ptr[i];
+    h->rowptr = upload(h, rp32, ok);
+    h->col = h->mem.alloc<int>(h->nnz);
+    h->val = h->mem.alloc<double>(h->nnz);
+    if (!ok || !h->col || !h->val) {
+      h->err = "device allocation failed (matrix)";
+      return AMSP_ERR_OOM;
+    }
+    HIP_TRY(hipMemcpyAsync(h->col, A->col_idx, h->nnz * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->val, A->val, h->nnz * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  }
+  Plan &p = h->plan;
+  p.N = h->N;
+  p.nev = h->nev;
+  p.sd_ptr = upload(h, P.sd_ptr, ok);
+  p.sd_dofs = upload(h, P.sd_dofs, ok);
+  p.vp_ptr = upload(h, P.vp_ptr, ok);
+  p.trow_ptr = upload(h, P.trow_ptr, ok);
+  p.tfirst = upload(h, P.tfirst, ok);
+  p.toff = upload(h, P.toff, ok);
+  p.loc_rowptr = upload(h, P.loc_rowptr, ok);
+  p.loc_col = upload(h, P.loc_col, ok);
+  p.loc_src = upload(h, P.loc_src, ok);
+  p.mi = upload(h, P.mi, ok);
+  p.coff = upload(h, P.coff, ok);
+  p.mult = upload(h, P.mult, ok);
+  h->inv_ptr = upload(h, P.inv_ptr, ok);
+  h->inv_sd = upload(h, P.inv_sd, ok);
+  h->inv_loc = upload(h, P.inv_loc, ok);
+  CoarsePlan &c = h->cplan;
+  c.N = h->N;
+  c.nev = h->nev;
+  if (h->nc > 0) {
+    c.ext_ptr = upload(h, P.ext_ptr, ok);
+    c.ext_rowptr = upload(h, P.ext_rowptr, ok);
+    c.ext_src = upload(h, P.ext_src, ok);
+    c.ext_loc = upload(h, P.ext_loc, ok);
+    c.npairs = (int)P.pair_i.size();
+    c.pair_i = upload(h, P.pair_i, ok);
+    c.pair_j = upload(h, P.pair_j, ok);
+    c.pair_ptr = upload(h, P.pair_ptr, ok);
+    c.pair_l = upload(h, P.pair_l, ok);
+    c.pair_e = upload(h, P.pair_e, ok);
+  }
+  if (!ok) {
+    h->err = "device allocation or upload failed (plan)";
+    return AMSP_ERR_OOM;
+  }
+  h->ntilerows = P.trow_ptr.back();
+  const int sum_ni = P.sd_ptr.back();
+  const int sum_npad = P.vp_ptr.back();
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  double t1 = now_ms();
+  h->sinfo.phase_ms[1] = t1 - t0;
+
+  int *status;
+  ALLOC(status, int, h->N);
+  HIP_TRY(hipMemsetAsync(status, 0, h->N * sizeof(int), h->stream));
+  ALLOC(h->sdiag, double, sum_ni);
+  const size_t fac_elems = (size_t)P.ntiles * TE;
+  ALLOC(h->fac64, double, fac_elems);
+  if (h->nev > 0) {
+    launch_neumann_diag(h->stream, p, h->val, h->sdiag, status);
+    int bad;
+    amsp_status s = sync_status(h, status, h->N, 1, bad);
+    if (s != AMSP_OK) return s;
+    if (bad >= 0) {
+      h->err = "weighting matrix S_i not positive in subdomain " + std::to_string(bad);
+      return AMSP_ERR_NEUMANN_DIAG;
+    }
+  }
+  // --- local Dirichlet matrices and their factors
+  launch_extract_tiles(h->stream, p, h->ntilerows, h->val, h->sdiag, h->fac64, 0, 0.0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  double t2 = now_ms();
+  h->sinfo.phase_ms[2] = t2 - t1;
+  launch_profile_cholesky(h->stream, p, h->fac64, status, 2);
+  HIP_TRY(hipGetLastError());
+  {
+    int bad;
+    amsp_status s = sync_status(h, status, h->N, 2, bad);
+    if (s != AMSP_OK) return s;
+    if (bad >= 0) {
+      h->err = "local matrix not SPD in subdomain " + std::to_string(bad);
+      return AMSP_ERR_LOCAL_NOT_SPD;
+    }
+  }
+  double t3 = now_ms();
+  h->sinfo.phase_ms[3] = t3 - t2;
+
+  // --- local eigenproblems
+  ALLOC(h->lam, double, (size_t)h->N * (h->nev + 1));
+  launch_fill(h->stream, (size_t)h->N * (h->nev + 1), h->lam, std::nan(""));
+  if (h->nev > 0) {
+    double *facB, *X, *BQ;
+    int *conv;
+    ALLOC(facB, double, fac_elems);
+    ALLOC(X, double, (size_t)sum_npad * EIGP);
+    ALLOC(BQ, double, (size_t)sum_npad * EIGP);
+    ALLOC(conv, int, h->N);
+    HIP_TRY(hipMemsetAsync(conv, 0, h->N * sizeof(int), h->stream));
+    launch_extract_tiles(h->stream, p, h->ntilerows, h->val, h->sdiag, facB, 1, h->opt.eig_shift);
+    launch_profile_cholesky(h->stream, p, facB, status, 4);
+    float *facB32 = nullptr;
+    if (mixed) {
+      ALLOC(facB32, float, fac_elems);
+      launch_tiles_to_f32(h->stream, facB, facB32, fac_elems);
+    }
+    {
+      int bad;
+      amsp_status s = sync_status(h, status, h->N, 4, bad);
+      if (s != AMSP_OK) return s;
+      if (bad >= 0) {
+        h->err = "shifted eigen-operator not SPD in subdomain " + std::to_string(bad);
+        return AMSP_ERR_LOCAL_NOT_SPD;
+      }
+    }
+    if (mixed) {
+      h->mem.free_one(facB);
+      facB = nullptr;
+    }
+    launch_eig_init(h->stream, p, h->sdiag, X);
+    const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-5 : 1e-10);
+    std::vector<int> hconv(h->N);
+    int sweeps = 0, unconv = h->N;
+    for (int it = 1; it <= h->opt.eig_maxit; ++it) {
+      if (mixed)
+        launch_profile_solve_block<float>(h->stream, p, facB32, X, conv);
+      else
+        launch_profile_solve_block<double>(h->stream, p, facB, X, conv);
+      launch_eig_rr(h->stream, p, h->val, h->sdiag, X, X, BQ, tol, conv, h->lam);
+      sweeps = it;
+      if (it >= 4 && (it % 2 == 0 || it == h->opt.eig_maxit)) {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(hconv.data(), conv, h->N * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        unconv = 0;
+        for (int v : hconv) unconv += (v == 0);
+        if (unconv == 0) break;
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(hconv.data(), conv, h->N * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    unconv = 0;
+    for (int v : hconv) unconv += (v == 0);
+    h->sinfo.eig_sweeps = sweeps;
+    h->sinfo.eig_unconverged = unconv;
+    ALLOC(h->phi64, double, (size_t)sum_ni * h->nev);
+    launch_build_basis(h->stream, p, h->sdiag, X, h->phi64, h->opt.pou);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (facB) h->mem.free_one(facB);
+    if (facB32) h->mem.free_one(facB32);
+    h->mem.free_one(X);
+    h->mem.free_one(BQ);
+    h->mem.free_one(conv);
+    // gap flags and mu_c
+    std::vector<double> lam((size_t)h->N * (h->nev + 1));
+    HIP_TRY(hipMemcpy(lam.data(), h->lam, lam.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double mu = INFINITY;
+    int flags = 0;
+    for (int i = 0; i < h->N; ++i) {
+      const int m = P.mi[i];
+      const int ni = P.sd_ptr[i + 1] - P.sd_ptr[i];
+      if (m < ni) {
+        const double lm = lam[(size_t)i * (h->nev + 1) + m - 1], lm1 = lam[(size_t)i * (h->nev + 1) + m];
+        mu = std::min(mu, lm1);
+        if (lm1 - lm < 1e-8 * std::max(lm1, 1e-12)) ++flags;
+      }
+    }
+    h->sinfo.mu_c = mu;
+    h->sinfo.n_gap_flags = flags;
+  }
+  double t4 = now_ms();
+  h->sinfo.phase_ms[4] = t4 - t3;
+
+  // --- coarse matrix A0 = R0 A R0^T and its inverse factor
+  const int T0 = h->T0;
+  if (h->nc > 0) {
+    double *W, *A0t, *dinv;
+    int *cstat;
+    ALLOC(W, double, (size_t)P.ext_ptr.back() * h->nev);
+    ALLOC(A0t, double, (size_t)T0 * T0 * TE);
+    ALLOC(dinv, double, (size_t)T0 * TE);
+    ALLOC(cstat, int, 1);
+    HIP_TRY(hipMemsetAsync(cstat, 0, sizeof(int), h->stream));
+    HIP_TRY(hipMemsetAsync(A0t, 0, (size_t)T0 * T0 * TE * sizeof(double), h->stream));
+    launch_apply_A_to_basis(h->stream, p, c, h->val, h->phi64, W);
+    launch_pair_products(h->stream, p, c, h->phi64, W, A0t, T0);
+    launch_symmetrize_tiles(h->stream, A0t, T0, h->nc);
+    HIP_TRY(hipGetLastError());
+    if (h->opt.keep_a0) {
+      ALLOC(h->a0keep, double, (size_t)T0 * T0 * TE);
+      HIP_TRY(hipMemcpyAsync(h->a0keep, A0t, (size_t)T0 * T0 * TE * sizeof(double),
+                             hipMemcpyDeviceToDevice, h->stream));
+    }
+    double t5 = now_ms();
+    for (int k = 0; k < T0; ++k) {
+      launch_dense_potrf_diag(h->stream, A0t, T0, k, dinv, cstat);
+      launch_dense_trsm_panel(h->stream, A0t, T0, k, dinv);
+      launch_dense_syrk_update(h->stream, A0t, T0, k);
+    }
+    ALLOC(h->W0, double, (size_t)T0 * T0 * TE);
+    launch_tiles_identity(h->stream, h->W0, T0);
+    for (int k = 0; k < T0; ++k) {
+      launch_dense_inv_row(h->stream, h->W0, T0, k, dinv);
+      launch_dense_inv_update(h->stream, A0t, h->W0, T0, k);
+    }
+    HIP_TRY(hipGetLastError());
+    int cs = 0;
+    HIP_TRY(hipMemcpyAsync(&cs, cstat, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (cs) {
+      h->err = "coarse matrix A0 not SPD";
+      return AMSP_ERR_COARSE_NOT_SPD;
+    }
+    h->mem.free_one(W);
+    h->mem.free_one(A0t);
+    h->mem.free_one(dinv);
+    if (mixed) {
+      ALLOC(h->W0f, float, (size_t)T0 * T0 * TE);
+      launch_dense_tiles_to_f32(h->stream, h->W0, h->W0f, T0);
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      h->mem.free_one(h->W0);
+      h->W0 = nullptr;
+    }
+    h->sinfo.phase_ms[6] = now_ms() - t5;
+  }
+  double t6 = now_ms();
+  h->sinfo.phase_ms[5] = (t6 - t4) - h->sinfo.phase_ms[6];
+
+  // --- mixed storage of the apply operands
+  if (mixed) {
+    ALLOC(h->fac32, float, fac_elems);
+    launch_tiles_to_f32(h->stream, h->fac64, h->fac32, fac_elems);
+    if (h->nev > 0) {
+      const bool bf = h->opt.precision == AMSP_MIXED_BF16;
+      if (bf) {
+        __hip_bfloat16 *pl;
+        ALLOC(pl, __hip_bfloat16, (size_t)sum_ni * h->nev);
+        h->phi_lo = pl;
+      } else {
+        float *pl;
+        ALLOC(pl, float, (size_t)sum_ni * h->nev);
+        h->phi_lo = pl;
+      }
+      launch_basis_convert(h->stream, h->phi64, h->phi_lo, (size_t)sum_ni * h->nev, bf ? 1 : 0);
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->mem.free_one(h->fac64);
+    h->fac64 = nullptr;
+  }
+  // --- apply / PCG scratch
+  ALLOC(h->xloc, double, sum_npad);
+  const int ncp = std::max(1, T0 * TS);
+  ALLOC(h->cvec, double, ncp);
+  ALLOC(h->t1, double, ncp);
+  ALLOC(h->tvec, double, ncp);
+  HIP_TRY(hipMemsetAsync(h->cvec, 0, ncp * sizeof(double), h->stream));
+  HIP_TRY(hipMemsetAsync(h->t1, 0, ncp * sizeof(double), h->stream));
+  HIP_TRY(hipMemsetAsync(h->tvec, 0, ncp * sizeof(double), h->stream));
+  ALLOC(h->trmv_part, double, (size_t)std::max(1, T0 * T0) * TS);
+  ALLOC(h->r, double, h->n);
+  ALLOC(h->z, double, h->n);
+  ALLOC(h->p0, double, h->n);
+  ALLOC(h->p1, double, h->n);
+  ALLOC(h->q, double, h->n);
+  ALLOC(h->part_a, double, 4096);
+  ALLOC(h->part_b, double, 4096);
+  ALLOC(h->part_c, double, 4096);
+  ALLOC(h->scal, double, 8);
+  ALLOC(h->st, PcgState, 1);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->mem.free_one(status);
+  h->sinfo.phase_ms[7] = now_ms() - t0 + h->sinfo.phase_ms[0];
+  if (h->sinfo.eig_unconverged > 0) {
+    h->err = std::to_string(h->sinfo.eig_unconverged) + " subdomain eigensolves did not converge";
+  }
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, int32_t nparts,
+                                  int32_t nev, const amsp_options *opt, amsp_handle **out) {
+  if (!out) return AMSP_ERR_ARG;
+  *out = nullptr;
+  amsp_options o;
+  amsp_default_options(&o);
+  if (opt) o = *opt;
+  if (o.eig_maxit < 1) o.eig_maxit = 1;
+  if (o.chunk < 1) o.chunk = 1;
+  if (!(o.eig_shift > 0.0)) {
+    g_setup_error = "eig_shift must be positive";
+    return AMSP_ERR_ARG;
+  }
+  std::string msg;
+  int s = validate_inputs(A, partition, nparts, nev, o.overlap, msg);
+  if (s != AMSP_OK) {
+    g_setup_error = msg;
+    return (amsp_status)s;
+  }
+  amsp_handle *h = new (std::nothrow) amsp_handle();
+  if (!h) return AMSP_ERR_OOM;
+  h->opt = o;
+  if (h->opt.flexible < 0) h->opt.flexible = (o.precision != AMSP_FP64) ? 1 : 0;
+  h->stream = (hipStream_t)o.stream;
+  h->n = (int)A->n;
+  h->nnz = A->nnz;
+  h->N = nparts;
+  h->nev = nev;
+  double t0 = now_ms();
+  try {
+    s = build_plan(A, partition, nparts, nev, o, h->hp, msg);
+  } catch (const std::bad_alloc &) {
+    s = AMSP_ERR_OOM;
+    msg = "host allocation failed during planning";
+  }
+  if (s != AMSP_OK) {
+    g_setup_error = msg;
+    delete h;
+    return (amsp_status)s;
+  }
+  h->nc = h->hp.nc;
+  h->T0 = (h->nc + TS - 1) / TS;
+  h->sinfo.phase_ms[0] = now_ms() - t0;
+  h->sinfo.nsub = h->N;
+  h->sinfo.nc = h->nc;
+  h->sinfo.sum_ni = h->hp.sd_ptr.back();
+  h->sinfo.max_ni = h->hp.max_ni;
+  h->sinfo.factor_tiles = h->hp.ntiles;
+  amsp_status ds;
+  try {
+    ds = device_setup(h, A);
+  } catch (const std::bad_alloc &) {
+    ds = AMSP_ERR_OOM;
+    h->err = "host allocation failed during setup";
+  }
+  if (ds != AMSP_OK) {
+    g_setup_error = h->err;
+    delete h;
+    return ds;
+  }
+  *out = h;
+  return AMSP_OK;
+}
+
+// ------------------------------------------------------------- apply ------
+static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int parts,
+                             double *partial_rz, const int *done) {
+  const Plan &p = h->plan;
+  const int do_local = (parts & 1) ? 1 : 0;
+  const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
+  const bool mixed = h->opt.precision != AMSP_FP64;
+  const bool bf = h->opt.precision == AMSP_MIXED_BF16;
+  if (!mixed) {
+    launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->fac64, h->phi64,
+                                                 h->xloc, h->cvec, do_local, do_coarse, done);
+  } else if (!bf) {
+    launch_local_apply_t<float, float, float>(h->stream, p, h->hp.max_npad, r, h->fac32,
+                                              (const float *)h->phi_lo, h->xloc, h->cvec, do_local,
+                                              do_coarse, done);
+  } else {
+    launch_local_apply_t<float, float, __hip_bfloat16>(h->stream, p, h->hp.max_npad, r, h->fac32,
+                                                       (const __hip_bfloat16 *)h->phi_lo, h->xloc,
+                                                       h->cvec, do_local, do_coarse, done);
+  }
+  if (do_coarse) {
+    if (!mixed) {
+      launch_trmv<double>(h->stream, h->W0, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
+      launch_trmv<double>(h->stream, h->W0, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
+    } else {
+      launch_trmv<float>(h->stream, h->W0f, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
+      launch_trmv<float>(h->stream, h->W0f, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
+    }
+  }
+  if (!mixed || h->nev == 0)
+    launch_scatter_sum_t<double>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
+                                 h->phi64, h->tvec, z, partial_rz ? r : nullptr, partial_rz,
+                                 do_local, do_coarse, done);
+  else if (!bf)
+    launch_scatter_sum_t<float>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
+                                (const float *)h->phi_lo, h->tvec, z, partial_rz ? r : nullptr,
+                                partial_rz, do_local, do_coarse, done);
+  else
+    launch_scatter_sum_t<__hip_bfloat16>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p,
+                                         h->xloc, (const __hip_bfloat16 *)h->phi_lo, h->tvec, z,
+                                         partial_rz ? r : nullptr, partial_rz, do_local, do_coarse,
+                                         done);
+  HIP_TRY(hipGetLastError());
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
+                                        int32_t nrhs, int32_t parts) {
+  if (!h || !r_dev || !z_dev || nrhs < 1 || parts < 1 || parts > 3) return AMSP_ERR_ARG;
+  for (int k = 0; k < nrhs; ++k) {
+    amsp_status s = apply_one(h, r_dev + (size_t)k * h->n, z_dev + (size_t)k * h->n, parts, nullptr, nullptr);
+    if (s != AMSP_OK) return s;
+  }
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_apply(amsp_handle *h, const double *r_dev, double *z_dev, int32_t nrhs) {
+  return amsp_apply_parts(h, r_dev, z_dev, nrhs, 3);
+}
+
+extern "C" amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_dev) {
+  if (!h || !x_dev || !y_dev) return AMSP_ERR_ARG;
+  launch_spmv(h->stream, h->n, h->rowptr, h->col, h->val, x_dev, y_dev, nullptr, nullptr);
+  HIP_TRY(hipGetLastError());
+  return AMSP_OK;
+}
+
+static int64_t bytes_per_iter(const amsp_handle *h) {
+  const HostPlan &P = h->hp;
+  const bool mixed = h->opt.precision != AMSP_FP64;
+  const int64_t n = h->n, nnz = h->nnz, sni = P.sd_ptr.back(), snp = P.vp_ptr.back();
+  const int64_t fb = mixed ? 4 : 8;
+  const int64_t pb = mixed ? (h->opt.precision == AMSP_MIXED_BF16 ? 2 : 4) : 8;
+  int64_t b = 0;
+  b += nnz * 12 + (n + 1) * 4 + n * 8 * 4;          // spmv with the fused p update
+  b += n * 8 * 6;                                   // x, r update
+  b += sni * (8 + 4) + snp * 8;                     // local gather + write
+  b += 2 * P.ntiles * (int64_t)TE * fb;             // forward + backward factor sweep
+  if (h->nc > 0) {
+    b += sni * h->nev * pb * 2;                     // restrict + prolong basis reads
+    b += 2 * (int64_t)h->T0 * (h->T0 + 1) / 2 * TE * (mixed ? 4 : 8);  // coarse W0 twice
+  }
+  b += sni * (8 + 8) + n * 8 * 3;                   // scatter: inverse map, locals, z, r
+  if (h->opt.flexible) b += n * 16;
+  return b;
+}
+
+extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
+                                double rtol, int32_t maxit, amsp_info *info) {
+  if (!h || !f_dev || !u_dev || nrhs < 1 || maxit < 0 || !(rtol >= 0.0)) return AMSP_ERR_ARG;
+  const int n = h->n;
+  const int nb = reduce_blocks(n);
+  amsp_info inf{};
+  inf.bytes_per_iter = bytes_per_iter(h);
+  double t0 = now_ms();
+  amsp_status final_status = AMSP_OK;
+  int tot_it = 0;
+  double worst_true = 0.0, worst_rec = 0.0;
+  int all_conv = 1, tot_restarts = 0;
+  PcgState hs{};
+  for (int k = 0; k < nrhs; ++k) {
+    const double *f = f_dev + (size_t)k * n;
+    double *x = u_dev + (size_t)k * n;
+    launch_fill(h->stream, n, x, 0.0);
+    launch_copy_scale(h->stream, n, f, h->r, 1.0);
+    int restarts = 0;
+    bool fresh = true;
+    double relres_true = 0.0;
+    for (;;) {
+      // z = M^{-1} r with r.z partials; r.r partials; p_old = 0
+      launch_dot(h->stream, n, h->r, h->r, h->part_a, nullptr);
+      amsp_status s = apply_one(h, h->r, h->z, 3, h->part_b, nullptr);
+      if (s != AMSP_OK) return s;
+      launch_fill(h->stream, n, h->p0, 0.0);
+      launch_pcg_init(h->stream, h->st, h->part_a, nb, h->part_b, nb, fresh ? rtol : -1.0, maxit);
+      HIP_TRY(hipGetLastError());
+      const int *done = &h->st->done;
+      double *pold = h->p0, *pnew = h->p1;
+      for (;;) {
+        HIP_TRY(hipMemcpyAsync(&hs, h->st, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (hs.done) break;
+        for (int c = 0; c < h->opt.chunk; ++c) {
+          launch_spmv_pupdate_st(h->stream, n, h->rowptr, h->col, h->val, h->z, pold, pnew, h->q,
+                                 h->part_a, h->st);
+          launch_pcg_alpha(h->stream, h->st, h->part_a, nb);
+          launch_axpy_update_st(h->stream, n, x, h->r, pnew, h->q, h->st, h->part_a);
+          launch_pcg_rr(h->stream, h->st, h->part_a, nb);
+          if (h->opt.flexible) launch_dot(h->stream, n, h->r, h->z, h->part_c, done);
+          s = apply_one(h, h->r, h->z, 3, h->part_b, done);
+          if (s != AMSP_OK) return s;
+          launch_pcg_beta(h->stream, h->st, h->part_b, nb, h->part_c, h->opt.flexible);
+          std::swap(pold, pnew);
+        }
+        HIP_TRY(hipGetLastError());
+      }
+      // true residual
+      launch_spmv(h->stream, n, h->rowptr, h->col, h->val, x, h->q, nullptr, nullptr);
+      launch_residual(h->stream, n, f, h->q, h->r, h->part_a);
+      launch_sum_partials(h->stream, h->part_a, nb, h->scal);
+      double rrt = 0.0;
+      HIP_TRY(hipMemcpyAsync(&rrt, h->scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      relres_true = hs.f2 > 0 ? std::sqrt(rrt / hs.f2) : 0.0;
+      if (hs.breakdown) {
+        final_status = AMSP_ERR_BREAKDOWN;
+        break;
+      }
+      if (!(relres_true <= rtol) && hs.it < maxit && restarts < 3) {
+        // false convergence of the recursive residual: restart from r = f - A x
+        ++restarts;
+        fresh = false;
+        continue;
+      }
+      break;
+    }
+    const double rel_rec = hs.f2 > 0 ? std::sqrt(hs.rr / hs.f2) : 0.0;
+    tot_it += hs.it;
+    tot_restarts += restarts;
+    worst_true = std::max(worst_true, relres_true);
+    worst_rec = std::max(worst_rec, rel_rec);
+    const bool conv = (relres_true <= rtol) && !hs.breakdown;
+    if (!conv) all_conv = 0;
+    if (!conv && final_status == AMSP_OK) final_status = AMSP_ERR_PCG_NOCONV;
+  }
+  inf.iterations = tot_it;
+  inf.converged = all_conv;
+  inf.relres_recursive = worst_rec;
+  inf.relres_true = worst_true;
+  inf.restarts = tot_restarts;
+  inf.solve_ms = now_ms() - t0;
+  if (info) *info = inf;
+  return final_status;
+}
+
+// ------------------------------------------------------- introspection ----
+extern "C" amsp_status amsp_get_setup_info(const amsp_handle *h, amsp_setup_info *info) {
+  if (!h || !info) return AMSP_ERR_ARG;
+  *info = h->sinfo;
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_get_eigenvalues(const amsp_handle *hc, double *lambda_host) {
+  amsp_handle *h = const_cast<amsp_handle *>(hc);
+  if (!h || !lambda_host) return AMSP_ERR_ARG;
+  HIP_TRY(hipMemcpyAsync(lambda_host, h->lam, (size_t)h->N * (h->nev + 1) * sizeof(double),
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_get_coarse_matrix(const amsp_handle *hc, double *a0_host) {
+  amsp_handle *h = const_cast<amsp_handle *>(hc);
+  if (!h || !a0_host) return AMSP_ERR_ARG;
+  if (h->nc == 0) return AMSP_OK;
+  if (!h->a0keep) {
+    h->err = "A0 not kept: set amsp_options.keep_a0 = 1 before amsp_setup";
+    return AMSP_ERR_ARG;
+  }
+  const int T0 = h->T0, nc = h->nc;
+  std::vector<double> t((size_t)T0 * T0 * TE);
+  HIP_TRY(hipMemcpyAsync(t.data(), h->a0keep, t.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int R = 0; R < nc; ++R)
+    for (int C = 0; C < nc; ++C)
+      a0_host[(size_t)R * nc + C] =
+          t[((size_t)(R / TS) * T0 + C / TS) * TE + (size_t)(R % TS) * TS + (C % TS)];
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_get_region(const amsp_handle *hc, int32_t i, int32_t *ni, int32_t *dofs,
+                                       double *phi) {
+  amsp_handle *h = const_cast<amsp_handle *>(hc);
+  if (!h || !ni || i < 0 || i >= h->N) return AMSP_ERR_ARG;
+  const int r0 = h->hp.sd_ptr[i], cnt = h->hp.sd_ptr[i + 1] - r0;
+  *ni = cnt;
+  if (dofs) std::memcpy(dofs, h->hp.sd_dofs.data() + r0, cnt * sizeof(int));
+  if (phi && h->nev > 0) {
+    if (!h->phi64) return AMSP_ERR_ARG;
+    HIP_TRY(hipMemcpyAsync(phi, h->phi64 + (size_t)r0 * h->nev, (size_t)cnt * h->nev * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  return AMSP_OK;
+}
+
+extern "C" void amsp_destroy(amsp_handle *h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
+  delete h;
+}
+
+extern "C" const char *amsp_status_string(amsp_status s) {
+  switch (s) {
+    case AMSP_OK: return "AMSP_OK";
+    case AMSP_ERR_ARG: return "AMSP_ERR_ARG";
+    case AMSP_ERR_CSR: return "AMSP_ERR_CSR";
+    case AMSP_ERR_NONSYM: return "AMSP_ERR_NONSYM";
+    case AMSP_ERR_PARTITION: return "AMSP_ERR_PARTITION";
+    case AMSP_ERR_NEUMANN_DIAG: return "AMSP_ERR_NEUMANN_DIAG";
+    case AMSP_ERR_LOCAL_NOT_SPD: return "AMSP_ERR_LOCAL_NOT_SPD";
+    case AMSP_ERR_EIG_NOCONV: return "AMSP_ERR_EIG_NOCONV";
+    case AMSP_ERR_COARSE_NOT_SPD: return "AMSP_ERR_COARSE_NOT_SPD";
+    case AMSP_ERR_PCG_NOCONV: return "AMSP_ERR_PCG_NOCONV";
+    case AMSP_ERR_BREAKDOWN: return "AMSP_ERR_BREAKDOWN";
+    case AMSP_ERR_HIP: return "AMSP_ERR_HIP";
+    case AMSP_ERR_OOM: return "AMSP_ERR_OOM";
+  }
+  return "AMSP_UNKNOWN";
+}
+
+extern "C" const char *amsp_last_error(const amsp_handle *h) { return h ? h->err.c_str() : ""; }
+extern "C" const char *amsp_setup_error(void) { return g_setup_error.c_str(); }

@@ -1,0 +1,127 @@
+// Internal declarations shared by the host library and the HIP kernels.
+// Not part of the public ABI (see include/amsp.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "amsp_consts.h"
+
+namespace amsp {
+
+// Device view of the planned subdomain structure (all arrays on the device).
+struct Plan {
+  int N;                    // subdomains
+  int nev;                  // requested eigenvectors (row stride of basis arrays)
+  const int *sd_ptr;        // [N+1] offsets of each region in the concatenated local vectors
+  const int *sd_dofs;       // [sum n_i] global dof of each local index (local order)
+  const int *vp_ptr;        // [N+1] padded offsets (multiples of 64) for tile-aligned vectors
+  const int *trow_ptr;      // [N+1] offsets into the per-tile-row arrays
+  const int *tfirst;        // [sum nt_i] first tile column of each tile row
+  const long long *toff;    // [sum nt_i] pool index of the first tile of each tile row
+  const int *loc_rowptr;    // [sum n_i + 1] local CSR of A_i (rows in local order)
+  const int *loc_col;       //   local column index
+  const int *loc_src;       //   index of the value in the global CSR
+  const int *mi;            // [N] kept eigenvectors m_i
+  const int *coff;          // [N+1] coarse offsets
+  const int *mult;          // [n] dof multiplicity
+};
+
+// PCG scalar state kept on the device.
+struct PcgState {
+  double rz, rz_old, pq, rr, alpha, beta, tol2, f2;
+  int it, done, breakdown, maxit;
+};
+
+// ---------------------------------------------------------------- krylov ---
+int reduce_blocks(int n);
+void launch_spmv(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                 const double *x, double *y, double *partial, const int *done);
+void launch_spmv_pupdate_st(hipStream_t s, int n, const int *rp, const int *col,
+                            const double *val, const double *z, const double *pold, double *pnew,
+                            double *q, double *partial, const PcgState *st);
+void launch_dot(hipStream_t s, int n, const double *a, const double *b, double *partial,
+                const int *done);
+void launch_axpy_update_st(hipStream_t s, int n, double *x, double *r, const double *p,
+                           const double *q, const PcgState *st, double *partial);
+void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
+                     double *partial);
+void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha);
+void launch_fill(hipStream_t s, size_t n, double *a, double v);
+void launch_fill_int(hipStream_t s, size_t n, int *a, int v);
+void launch_sum_partials(hipStream_t s, const double *partial, int nb, double *out);
+void launch_pcg_init(hipStream_t s, PcgState *st, const double *partial_rr, int nb_rr,
+                     const double *partial_rz, int nb_rz, double rtol, int maxit);
+void launch_pcg_alpha(hipStream_t s, PcgState *st, const double *partial, int nb);
+void launch_pcg_rr(hipStream_t s, PcgState *st, const double *partial, int nb);
+void launch_pcg_beta(hipStream_t s, PcgState *st, const double *partial_rz, int nb,
+                     const double *partial_rzold, int flexible);
+
+// ----------------------------------------------------------------- local ---
+// s = diag(hat A_i) for every local row; status[i] |= 1 if some s <= 0.
+void launch_neumann_diag(hipStream_t s, const Plan &p, const double *val, double *sdiag,
+                         int *status);
+// Tile-profile storage: mode 0 -> A_i, mode 1 -> S^{-1/2} hat A_i S^{-1/2} + sigma I.
+void launch_extract_tiles(hipStream_t s, const Plan &p, int ntilerows, const double *val,
+                          const double *sdiag, double *tiles, int mode, double sigma);
+// In-place batched profile Cholesky; diagonal tiles then hold inv(L_II).
+// status[i] |= bit on a non-positive pivot.
+void launch_profile_cholesky(hipStream_t s, const Plan &p, double *tiles, int *status, int bit);
+void launch_tiles_to_f32(hipStream_t s, const double *src, float *dst, size_t count);
+// Local apply: gather r, coarse restriction into c (do_coarse), profile
+// forward/backward solve into xloc (do_local).  T factor, C compute, TB basis type.
+template <typename T, typename C, typename TB>
+void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
+                          const T *tiles, const TB *phi, double *xloc, double *cvec, int do_local,
+                          int do_coarse, const int *done);
+// In-place (L L^T)^{-1} X on row-major [rows][EIGP] padded blocks.
+template <typename T>
+void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, double *X,
+                                const int *skip);
+template <typename TB>
+void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
+                          const int *inv_loc, const Plan &p, const double *xloc, const TB *phi,
+                          const double *t, double *z, const double *r, double *partial,
+                          int do_local, int do_coarse, const int *done);
+
+// ---------------------------------------------------------------- eigen ---
+void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
+void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag, double *X,
+                   double *Y, double *BQ, double tol, int *conv, double *lam);
+void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
+                        double *phi, int pou);
+void launch_basis_convert(hipStream_t s, const double *phi, void *dst, size_t count, int bf16);
+
+// ---------------------------------------------------------------- coarse ---
+struct CoarsePlan {
+  int N;
+  int nev;
+  const int *ext_ptr;       // [N+1] offsets of the extended regions
+  const int *ext_rowptr;    // [sum |E_i| + 1] entries coupling each row to region i
+  const int *ext_src;       //   global CSR value index
+  const int *ext_loc;       //   local index in region i
+  int npairs;
+  const int *pair_i, *pair_j;
+  const int *pair_ptr;      // [npairs+1]
+  const int *pair_l;        // local index in region i
+  const int *pair_e;        // index in the extended region of j
+};
+void launch_apply_A_to_basis(hipStream_t s, const Plan &p, const CoarsePlan &c,
+                             const double *val, const double *phi, double *W);
+void launch_pair_products(hipStream_t s, const Plan &p, const CoarsePlan &c, const double *phi,
+                          const double *W, double *A0t, int T0);
+void launch_symmetrize_tiles(hipStream_t s, double *A0t, int T0, int nc);
+void launch_dense_potrf_diag(hipStream_t s, double *A0t, int T0, int k, double *dinv, int *status);
+void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const double *dinv);
+void launch_dense_syrk_update(hipStream_t s, double *A0t, int T0, int k);
+void launch_dense_inv_row(hipStream_t s, double *Wt, int T0, int k, const double *dinv);
+void launch_dense_inv_update(hipStream_t s, const double *Lt, double *Wt, int T0, int k);
+void launch_tiles_identity(hipStream_t s, double *Wt, int T0);
+void launch_dense_tiles_to_f32(hipStream_t s, const double *src, float *dst, int T0);
+// y = W x (transpose 0) or W^T x (transpose 1) over the lower tiles of W;
+// part: T0*T0*64 doubles of scratch.
+template <typename T>
+void launch_trmv(hipStream_t s, const T *Wt, int T0, const double *x, double *part, double *y,
+                 int transpose, const int *done);
+
+}  // namespace amsp

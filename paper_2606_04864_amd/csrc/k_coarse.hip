@@ -1,0 +1,346 @@
+// Coarse level: Galerkin matrix A0 = R0 A R0^T (Section 3.1), its tiled
+// dense Cholesky factorisation A0 = L0 L0^T, the inverse factor W0 = inv(L0),
+// and the coarse solve A0^{-1} c = W0^T (W0 c) as two fully parallel
+// triangular matrix-vector products.
+//
+// A0 is stored as T0 x T0 row-major 64x64 tiles (tile (I,J) at (I*T0+J)*64*64);
+// rows/columns past N_c are padding with a unit diagonal.
+#include "k_common.h"
+
+namespace amsp {
+
+// W_j = A Phi_j on the extended region of subdomain j (region grown by one
+// layer), one workgroup per subdomain.  Row stride of W and Phi: nev.
+__global__ void __launch_bounds__(WG) k_apply_A_to_basis(Plan p, CoarsePlan c,
+                                                         const double *__restrict__ val,
+                                                         const double *__restrict__ phi,
+                                                         double *__restrict__ W) {
+  const int j = blockIdx.x;
+  const int nev = p.nev, m = p.mi[j];
+  const int e0 = c.ext_ptr[j], e1 = c.ext_ptr[j + 1];
+  const int r0 = p.sd_ptr[j];
+  for (int e = e0 + threadIdx.x; e < e1; e += WG) {
+    double acc[MAXNEV];
+#pragma unroll
+    for (int k = 0; k < MAXNEV; ++k) acc[k] = 0.0;
+    for (int q = c.ext_rowptr[e]; q < c.ext_rowptr[e + 1]; ++q) {
+      const double a = val[c.ext_src[q]];
+      const double *ph = phi + (size_t)(r0 + c.ext_loc[q]) * nev;
+#pragma unroll
+      for (int k = 0; k < MAXNEV; ++k)
+        if (k < m) acc[k] = fma(a, ph[k], acc[k]);
+    }
+    for (int k = 0; k < nev; ++k) W[(size_t)e * nev + k] = (k < m) ? acc[k] : 0.0;
+  }
+}
+
+__device__ __forceinline__ size_t a0_index(int R, int C, int T0) {
+  return ((size_t)(R >> 6) * T0 + (C >> 6)) * TE + (size_t)(R & 63) * TS + (C & 63);
+}
+
+// Block (i,j) of A0: Phi_i^T W_j summed over the overlap list of the pair.
+// Thread t handles entry (a,b) = (t % (nev*nev)) and list segment t / (nev*nev);
+// segments are combined in fixed order.
+__global__ void __launch_bounds__(WG) k_pair_products(Plan p, CoarsePlan c,
+                                                      const double *__restrict__ phi,
+                                                      const double *__restrict__ W,
+                                                      double *__restrict__ A0t, int T0) {
+  const int pr = blockIdx.x;
+  const int i = c.pair_i[pr], j = c.pair_j[pr];
+  const int nev = p.nev;
+  const int mi = p.mi[i], mj = p.mi[j];
+  const int nn = nev * nev;
+  const int nseg = WG / nn;
+  __shared__ double part[WG];
+  const int t = threadIdx.x;
+  const int q0 = c.pair_ptr[pr], q1 = c.pair_ptr[pr + 1];
+  double s = 0.0;
+  const int ab = t % nn, seg = t / nn;
+  const int a = ab / nev, b = ab % nev;
+  if (seg < nseg && a < mi && b < mj) {
+    const int len = q1 - q0;
+    const int s0 = q0 + (int)(((long long)len * seg) / nseg);
+    const int s1 = q0 + (int)(((long long)len * (seg + 1)) / nseg);
+    const int ri = p.sd_ptr[i], ej = 0;
+    (void)ej;
+    for (int q = s0; q < s1; ++q) {
+      s = fma(phi[(size_t)(ri + c.pair_l[q]) * nev + a], W[(size_t)(c.ext_ptr[j] + c.pair_e[q]) * nev + b], s);
+    }
+  }
+  part[t] = s;
+  __syncthreads();
+  if (t < nn && a < mi && b < mj) {
+    double tot = 0.0;
+    for (int g = 0; g < nseg; ++g) tot += part[g * nn + t];
+    A0t[a0_index(p.coff[i] + a, p.coff[j] + b, T0)] = tot;
+  }
+}
+
+// Lower tiles <- (A0 + A0^T)/2, padding diagonal <- 1.  One thread per
+// lower-triangle element pair.
+__global__ void k_symmetrize(double *__restrict__ A0t, int T0, int nc) {
+  const size_t npad = (size_t)T0 * TS;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < npad * npad;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int R = (int)(e / npad), C = (int)(e % npad);
+    if (C > R) continue;
+    if (R >= nc || C >= nc) {
+      A0t[a0_index(R, C, T0)] = (R == C) ? 1.0 : 0.0;
+      if (R != C) A0t[a0_index(C, R, T0)] = 0.0;
+      continue;
+    }
+    const double v = 0.5 * (A0t[a0_index(R, C, T0)] + A0t[a0_index(C, R, T0)]);
+    A0t[a0_index(R, C, T0)] = v;
+    A0t[a0_index(C, R, T0)] = v;
+  }
+}
+
+// ------------------------------------------------- dense tiled Cholesky ---
+__device__ __forceinline__ double *tile_ptr(double *A, int T0, int I, int J) {
+  return A + ((size_t)I * T0 + J) * TE;
+}
+
+// Step k: factor diagonal tile, store L_kk in place and inv(L_kk) in dinv.
+__global__ void __launch_bounds__(WG) k_dense_potrf_diag(double *A0t, int T0, int k, double *dinv,
+                                                         int *status) {
+  extern __shared__ double lds[];
+  double *X = lds, *Y = lds + TS * LDT, *part = lds + 2 * TS * LDT;
+  __shared__ int fail;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  tile_to_lds(tile_ptr(A0t, T0, k, k), X);
+  __syncthreads();
+  lds_potrf(X, &fail);
+  lds_trtri(X, Y, part);
+  lds_to_tile(X, tile_ptr(A0t, T0, k, k));
+  lds_to_tile(Y, dinv + (size_t)k * TE);
+  __syncthreads();
+  if (threadIdx.x == 0 && fail) *status |= 1;
+}
+
+// L_ik = A_ik inv(L_kk)^T for i > k
+__global__ void __launch_bounds__(WG) k_dense_trsm_panel(double *A0t, int T0, int k,
+                                                         const double *dinv) {
+  extern __shared__ double lds[];
+  double *X = lds, *Y = lds + TS * LDT;
+  const int i = k + 1 + blockIdx.x;
+  double *a = tile_ptr(A0t, T0, i, k);
+  tile_to_lds(a, X);
+  tile_to_lds(dinv + (size_t)k * TE, Y);
+  __syncthreads();
+  Blk o;
+  blk_abt(o, X, Y);
+  blk_store(o, a);
+}
+
+// A_ij -= L_ik L_jk^T for k < j <= i
+__global__ void __launch_bounds__(WG) k_dense_syrk_update(double *A0t, int T0, int k) {
+  extern __shared__ double lds[];
+  double *X = lds, *Y = lds + TS * LDT;
+  // blockIdx -> (i, j) in the lower triangle of the trailing (T0-k-1)^2 block
+  const int b = blockIdx.x;
+  int ii = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((ii + 1) * (ii + 2) / 2 <= b) ++ii;
+  while (ii * (ii + 1) / 2 > b) --ii;
+  const int jj = b - ii * (ii + 1) / 2;
+  const int i = k + 1 + ii, j = k + 1 + jj;
+  tile_to_lds(tile_ptr(A0t, T0, i, k), X);
+  tile_to_lds(tile_ptr(A0t, T0, j, k), Y);
+  __syncthreads();
+  double *c = tile_ptr(A0t, T0, i, j);
+  Blk o;
+  blk_load(o, c);
+  blk_sub_abt(o, X, Y);
+  blk_store(o, c);
+}
+
+// Inverse factor by a right-looking solve of L X = I, step k:
+//   row k:   X_kj <- inv(L_kk) B_kj  (j <= k)
+//   update:  B_ij -= L_ik X_kj        (i > k, j <= k)
+__global__ void __launch_bounds__(WG) k_dense_inv_row(double *Wt, int T0, int k,
+                                                      const double *dinv) {
+  extern __shared__ double lds[];
+  double *X = lds, *Y = lds + TS * LDT;
+  const int j = blockIdx.x;  // 0..k
+  double *w = tile_ptr(Wt, T0, k, j);
+  tile_to_lds(dinv + (size_t)k * TE, X);
+  tile_to_lds(w, Y);
+  __syncthreads();
+  Blk o;
+  blk_ab(o, X, Y);
+  blk_store(o, w);
+}
+
+__global__ void __launch_bounds__(WG) k_dense_inv_update(const double *Lt, double *Wt, int T0,
+                                                         int k) {
+  extern __shared__ double lds[];
+  double *X = lds, *Y = lds + TS * LDT;
+  const int i = k + 1 + blockIdx.x / (k + 1);
+  const int j = blockIdx.x % (k + 1);
+  tile_to_lds(Lt + ((size_t)i * T0 + k) * TE, X);
+  tile_to_lds(Wt + ((size_t)k * T0 + j) * TE, Y);
+  __syncthreads();
+  double *c = tile_ptr(Wt, T0, i, j);
+  Blk o;
+  blk_load(o, c);
+  blk_sub_ab(o, X, Y);
+  blk_store(o, c);
+}
+
+__global__ void k_tiles_identity(double *Wt, int T0) {
+  const size_t tot = (size_t)T0 * T0 * TE;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t tile = e / TE;
+    const int I = (int)(tile / T0), J = (int)(tile % T0);
+    const int r = (int)((e % TE) / TS), c = (int)(e % TS);
+    Wt[e] = (I == J && r == c) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void k_tiles_to_f32_lower(const double *__restrict__ src, float *__restrict__ dst,
+                                     int T0) {
+  const size_t tot = (size_t)T0 * T0 * TE;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+// ------------------------------------------------ coarse solve (TRMV) -----
+// y = W x (transpose = 0) or y = W^T x (transpose = 1) for the lower tiles
+// of W.  Stage 1: one workgroup per lower tile writes its 64-vector product
+// into part[(out tile) * T0 + (in tile)]; stage 2 sums in tile order.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_trmv_tiles(const T *__restrict__ Wt, int T0,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ part, int transpose,
+                                                   const int *__restrict__ done) {
+  if (done && *done) return;
+  __shared__ double xs[TS];
+  __shared__ double red[4][TS];
+  const int b = blockIdx.x;
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;  // J <= I
+  const T *w = Wt + ((size_t)I * T0 + J) * TE;
+  const int t = threadIdx.x;
+  if (!transpose) {
+    if (t < TS) xs[t] = x[J * TS + t];
+    __syncthreads();
+    const int r = t >> 2, q = t & 3;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s = fma((double)w[r * TS + 16 * q + c], xs[16 * q + c], s);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (q == 0) part[((size_t)I * T0 + J) * TS + r] = s;
+  } else {
+    if (t < TS) xs[t] = x[I * TS + t];
+    __syncthreads();
+    const int c = t & 63, g = t >> 6;
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s = fma((double)w[(16 * g + r) * TS + c], xs[16 * g + r], s);
+    red[g][c] = s;
+    __syncthreads();
+    if (g == 0) part[((size_t)J * T0 + I) * TS + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  }
+}
+
+// y[O*64 + r] = sum over input tiles K (in order) of part[(O*T0 + K)*64 + r],
+// K ranging over J <= O (no transpose) or I >= O (transpose).
+__global__ void k_trmv_reduce(int T0, const double *__restrict__ part, double *__restrict__ y,
+                              int transpose, const int *__restrict__ done) {
+  if (done && *done) return;
+  const int O = blockIdx.x, r = threadIdx.x;
+  double s = 0.0;
+  if (!transpose)
+    for (int K = 0; K <= O; ++K) s += part[((size_t)O * T0 + K) * TS + r];
+  else
+    for (int K = O; K < T0; ++K) s += part[((size_t)O * T0 + K) * TS + r];
+  y[O * TS + r] = s;
+}
+
+// ------------------------------------------------------------- launchers ---
+static size_t two_tiles_lds() { return (size_t)(2 * TS * LDT + 4 * TS) * sizeof(double); }
+
+void launch_apply_A_to_basis(hipStream_t s, const Plan &p, const CoarsePlan &c,
+                             const double *val, const double *phi, double *W) {
+  hipLaunchKernelGGL(k_apply_A_to_basis, dim3(p.N), dim3(WG), 0, s, p, c, val, phi, W);
+}
+
+void launch_pair_products(hipStream_t s, const Plan &p, const CoarsePlan &c, const double *phi,
+                          const double *W, double *A0t, int T0) {
+  if (c.npairs == 0) return;
+  hipLaunchKernelGGL(k_pair_products, dim3(c.npairs), dim3(WG), 0, s, p, c, phi, W, A0t, T0);
+}
+
+void launch_symmetrize_tiles(hipStream_t s, double *A0t, int T0, int nc) {
+  size_t tot = (size_t)T0 * TS * T0 * TS;
+  size_t b = (tot + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)b), dim3(WG), 0, s, A0t, T0, nc);
+}
+
+void launch_dense_potrf_diag(hipStream_t s, double *A0t, int T0, int k, double *dinv, int *status) {
+  allow_lds(k_dense_potrf_diag, two_tiles_lds());
+  hipLaunchKernelGGL(k_dense_potrf_diag, dim3(1), dim3(WG), two_tiles_lds(), s, A0t, T0, k, dinv,
+                     status);
+}
+
+void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const double *dinv) {
+  const int nb = T0 - k - 1;
+  if (nb <= 0) return;
+  allow_lds(k_dense_trsm_panel, two_tiles_lds());
+  hipLaunchKernelGGL(k_dense_trsm_panel, dim3(nb), dim3(WG), two_tiles_lds(), s, A0t, T0, k, dinv);
+}
+
+void launch_dense_syrk_update(hipStream_t s, double *A0t, int T0, int k) {
+  const int m = T0 - k - 1;
+  if (m <= 0) return;
+  allow_lds(k_dense_syrk_update, two_tiles_lds());
+  hipLaunchKernelGGL(k_dense_syrk_update, dim3(m * (m + 1) / 2), dim3(WG), two_tiles_lds(), s, A0t,
+                     T0, k);
+}
+
+void launch_dense_inv_row(hipStream_t s, double *Wt, int T0, int k, const double *dinv) {
+  allow_lds(k_dense_inv_row, two_tiles_lds());
+  hipLaunchKernelGGL(k_dense_inv_row, dim3(k + 1), dim3(WG), two_tiles_lds(), s, Wt, T0, k, dinv);
+}
+
+void launch_dense_inv_update(hipStream_t s, const double *Lt, double *Wt, int T0, int k) {
+  const int m = T0 - k - 1;
+  if (m <= 0) return;
+  allow_lds(k_dense_inv_update, two_tiles_lds());
+  hipLaunchKernelGGL(k_dense_inv_update, dim3(m * (k + 1)), dim3(WG), two_tiles_lds(), s, Lt, Wt,
+                     T0, k);
+}
+
+void launch_tiles_identity(hipStream_t s, double *Wt, int T0) {
+  size_t tot = (size_t)T0 * T0 * TE;
+  size_t b = (tot + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  hipLaunchKernelGGL(k_tiles_identity, dim3((unsigned)b), dim3(WG), 0, s, Wt, T0);
+}
+
+void launch_dense_tiles_to_f32(hipStream_t s, const double *src, float *dst, int T0) {
+  size_t tot = (size_t)T0 * T0 * TE;
+  size_t b = (tot + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  hipLaunchKernelGGL(k_tiles_to_f32_lower, dim3((unsigned)b), dim3(WG), 0, s, src, dst, T0);
+}
+
+template <typename T>
+void launch_trmv(hipStream_t s, const T *Wt, int T0, const double *x, double *part, double *y,
+                 int transpose, const int *done) {
+  const int nb = T0 * (T0 + 1) / 2;
+  hipLaunchKernelGGL((k_trmv_tiles<T>), dim3(nb), dim3(WG), 0, s, Wt, T0, x, part, transpose, done);
+  hipLaunchKernelGGL(k_trmv_reduce, dim3(T0), dim3(TS), 0, s, T0, part, y, transpose, done);
+}
+template void launch_trmv<double>(hipStream_t, const double *, int, const double *, double *,
+                                  double *, int, const int *);
+template void launch_trmv<float>(hipStream_t, const float *, int, const double *, double *,
+                                 double *, int, const int *);
+
+}  // namespace amsp

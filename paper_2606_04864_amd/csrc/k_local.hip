@@ -1,0 +1,473 @@
+// Per-subdomain local matrices, their batched tile-profile Cholesky
+// factorisation, and the local solves of the additive Schwarz term.
+//
+// Local matrices (Section 3.2): A_i = R_i A R_i^T on the overlapping region,
+// hat A_i = A_i with the diagonal replaced by minus the sum of the row's
+// off-diagonals (couplings inside the region only), S_i = diag(hat A_i) and
+// the standard-form eigen-operator B_i = S^{-1/2} hat A_i S^{-1/2}.
+//
+// Storage: each region is ordered locally (RCM by default) and stored as
+// 64x64 row-major tiles of its lower triangle, restricted to the tile
+// profile: tile row I holds tiles J = first(I)..I.  Cholesky fill stays
+// inside the row envelope, so the profile of the factor equals that of A_i.
+// After factorisation each diagonal tile holds inv(L_II) (the local solves
+// then need only matrix-vector products) and the off-diagonal tiles hold L_IJ.
+#include "k_common.h"
+
+namespace amsp {
+
+// ------------------------------------------------------------ S_i ---------
+__global__ void __launch_bounds__(WG) k_neumann_diag(Plan p, const double *__restrict__ val,
+                                                     double *__restrict__ sdiag,
+                                                     int *__restrict__ status) {
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], r1 = p.sd_ptr[i + 1];
+  int bad = 0;
+  for (int R = r0 + threadIdx.x; R < r1; R += WG) {
+    const int l = R - r0;
+    double s = 0.0;
+    for (int e = p.loc_rowptr[R]; e < p.loc_rowptr[R + 1]; ++e)
+      if (p.loc_col[e] != l) s -= val[p.loc_src[e]];
+    sdiag[R] = s;
+    if (!(s > 0.0)) bad = 1;
+  }
+  if (bad) status[i] |= 1;
+}
+
+// ----------------------------------------------------- tile extraction ----
+// One workgroup per tile row.  Thread t fills row (t>>2) of each tile, columns
+// 16*(t&3) .. +15, by scanning that local CSR row once.
+__global__ void __launch_bounds__(WG) k_extract_tiles(Plan p, int nrows_total,
+                                                      const double *__restrict__ val,
+                                                      const double *__restrict__ sdiag,
+                                                      double *__restrict__ tiles, int mode,
+                                                      double sigma) {
+  const int g = blockIdx.x;
+  const int i = find_segment(p.trow_ptr, p.N, g);
+  const int I = g - p.trow_ptr[i];
+  const int r0 = p.sd_ptr[i];
+  const int ni = p.sd_ptr[i + 1] - r0;
+  const int fI = p.tfirst[g];
+  const long long t0 = p.toff[g];
+  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+  const int l = I * TS + r;
+  const bool real = l < ni;
+  const int e0 = real ? p.loc_rowptr[r0 + l] : 0, e1 = real ? p.loc_rowptr[r0 + l + 1] : 0;
+  const double sl = (real && mode == 1) ? sdiag[r0 + l] : 1.0;
+  for (int J = fI; J <= I; ++J) {
+    double v[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = 0.0;
+    const int cbase = J * TS + 16 * q;
+    if (real) {
+      for (int e = e0; e < e1; ++e) {
+        const int lc = p.loc_col[e];
+        const int off = lc - cbase;
+        if (off >= 0 && off < 16) {
+          double a = val[p.loc_src[e]];
+          if (mode == 1) a = (lc == l) ? 1.0 + sigma : a / sqrt(sl * sdiag[r0 + lc]);
+#pragma unroll
+          for (int c = 0; c < 16; ++c)
+            if (c == off) v[c] = a;
+        }
+      }
+    } else {
+      // padding rows: identity on the diagonal
+      const int off = l - cbase;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c == off) v[c] = 1.0;
+    }
+    double *dst = tiles + tile_elem(t0 + (J - fI)) + r * TS + 16 * q;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) dst[c] = v[c];
+  }
+}
+
+// ------------------------------------------------ batched Cholesky --------
+// One workgroup per region, left-looking over tile rows.  For tile (I,J):
+//   C = A_IJ - sum_K L_IK L_JK^T  (K over tiles present in both rows)
+//   J < I : L_IJ = C inv(L_JJ)^T
+//   J = I : L_II = chol(C); the tile then stores inv(L_II).
+__global__ void __launch_bounds__(WG) k_profile_cholesky(Plan p, double *__restrict__ tiles, int bit,
+                                                         int *__restrict__ status) {
+  extern __shared__ double lds[];
+  double *X = lds;             // 64 x LDT
+  double *Y = lds + TS * LDT;  // 64 x LDT
+  double *part = lds + 2 * TS * LDT;  // 4 x 64
+  __shared__ int fail;
+  const int i = blockIdx.x;
+  const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  for (int I = 0; I < nt; ++I) {
+    const int fI = p.tfirst[g0 + I];
+    const long long tI = p.toff[g0 + I];
+    for (int J = fI; J <= I; ++J) {
+      const int fJ = p.tfirst[g0 + J];
+      const long long tJ = p.toff[g0 + J];
+      double *cij = tiles + tile_elem(tI + (J - fI));
+      Blk c;
+      blk_load(c, cij);
+      const int k0 = fI > fJ ? fI : fJ;
+      for (int K = k0; K < J; ++K) {
+        __syncthreads();
+        tile_to_lds(tiles + tile_elem(tI + (K - fI)), X);
+        tile_to_lds(tiles + tile_elem(tJ + (K - fJ)), Y);
+        __syncthreads();
+        blk_sub_abt(c, X, Y);
+      }
+      __syncthreads();
+      if (J < I) {
+        blk_to_lds(c, X);
+        tile_to_lds(tiles + tile_elem(tJ + (J - fJ)), Y);  // inv(L_JJ)
+        __syncthreads();
+        Blk o;
+        blk_abt(o, X, Y);
+        blk_store(o, cij);
+      } else {
+        blk_to_lds(c, X);
+        __syncthreads();
+        lds_potrf(X, &fail);
+        lds_trtri(X, Y, part);
+        lds_to_tile(Y, cij);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && fail) status[i] |= bit;
+}
+
+__global__ void k_tiles_to_f32(const double *__restrict__ src, float *__restrict__ dst,
+                               size_t count) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+// ------------------------------------------------ local solves (1 rhs) ----
+// Row-mapped tile-vector product: thread t owns row t>>2 and 16 columns.
+template <typename T, typename C>
+__device__ __forceinline__ C tile_row_dot(const T *__restrict__ tile, const C *v) {
+  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+  const T *row = tile + r * TS + 16 * q;
+  const C *vv = v + 16 * q;
+  C s = 0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) s = fma((C)row[c], vv[c], s);
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  return s;  // full row sum in all 4 lanes of the row
+}
+
+// Column-mapped transposed product: thread t owns column t&63 and 16 rows;
+// partial sums over the 4 row groups are combined through LDS.
+template <typename T, typename C>
+__device__ __forceinline__ C tile_col_dot(const T *__restrict__ tile, const C *v) {
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  C s = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) s = fma((C)tile[(16 * g + r) * TS + c], v[16 * g + r], s);
+  return s;
+}
+
+// Fused additive-Schwarz local kernel for one region per workgroup:
+//   gather r on the region, coarse restriction c_i = Phi_i^T r_i (optional),
+//   forward/backward substitution with the tile-profile factor (optional),
+//   store the local correction into the padded local vector xloc.
+// T: factor storage type, C: compute type, TB: basis storage type.
+template <typename T, typename C, typename TB>
+__global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__restrict__ r,
+                                                    const T *__restrict__ tiles,
+                                                    const TB *__restrict__ phi,
+                                                    double *__restrict__ xloc,
+                                                    double *__restrict__ cvec, int do_local,
+                                                    int do_coarse, const int *__restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ char smem_raw[];
+  C *v = reinterpret_cast<C *>(smem_raw);          // whole local vector (padded)
+  C *tmp = v + (p.vp_ptr[blockIdx.x + 1] - p.vp_ptr[blockIdx.x]);  // 64
+  C *part = tmp + TS;                               // 4 x 64
+  __shared__ double red[MAXNEV + 1][WG / 64];
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
+  const int npad = nt * TS;
+  const int nev = p.nev;
+  const int m = p.mi[i];
+  double cacc[MAXNEV];
+#pragma unroll
+  for (int k = 0; k < MAXNEV; ++k) cacc[k] = 0.0;
+  for (int l = threadIdx.x; l < npad; l += WG) {
+    double rv = 0.0;
+    if (l < ni) {
+      rv = r[p.sd_dofs[r0 + l]];
+      if (do_coarse) {
+        const TB *ph = phi + (size_t)(r0 + l) * nev;
+#pragma unroll
+        for (int k = 0; k < MAXNEV; ++k)
+          if (k < m) cacc[k] = fma(to_d(ph[k]), rv, cacc[k]);
+      }
+    }
+    v[l] = (C)rv;
+  }
+  if (do_coarse) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = 0; k < m; ++k) {
+      double s = wave_sum(cacc[k]);
+      if (lane == 0) red[k][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+      double s = 0.0;
+      for (int ww = 0; ww < WG / 64; ++ww) s += red[threadIdx.x][ww];
+      cvec[p.coff[i] + threadIdx.x] = s;
+    }
+  }
+  __syncthreads();
+  if (!do_local) return;
+  const int rr = threadIdx.x >> 2, q = threadIdx.x & 3;
+  const int cc = threadIdx.x & 63, gg = threadIdx.x >> 6;
+  // forward: y_I = inv(L_II) (b_I - sum_J L_IJ y_J)
+  for (int I = 0; I < nt; ++I) {
+    const int fI = p.tfirst[g0 + I];
+    const long long tI = p.toff[g0 + I];
+    C acc = v[I * TS + rr];
+    for (int J = fI; J < I; ++J) acc -= tile_row_dot<T, C>(tiles + tile_elem(tI + (J - fI)), v + J * TS);
+    if (q == 0) tmp[rr] = acc;
+    __syncthreads();
+    C y = tile_row_dot<T, C>(tiles + tile_elem(tI + (I - fI)), tmp);
+    if (q == 0) v[I * TS + rr] = y;
+    __syncthreads();
+  }
+  // backward: x_I = inv(L_II)^T (y_I - sum_{J>I} L_JI^T x_J)
+  for (int I = nt - 1; I >= 0; --I) {
+    C s = 0;
+    for (int J = I + 1; J < nt; ++J) {
+      const int fJ = p.tfirst[g0 + J];
+      if (fJ > I) continue;
+      s += tile_col_dot<T, C>(tiles + tile_elem(p.toff[g0 + J] + (I - fJ)), v + J * TS);
+    }
+    part[gg * TS + cc] = s;
+    __syncthreads();
+    if (gg == 0) tmp[cc] = v[I * TS + cc] - ((part[cc] + part[TS + cc]) + (part[2 * TS + cc] + part[3 * TS + cc]));
+    __syncthreads();
+    const int fI = p.tfirst[g0 + I];
+    C y = tile_col_dot<T, C>(tiles + tile_elem(p.toff[g0 + I] + (I - fI)), tmp);
+    part[gg * TS + cc] = y;
+    __syncthreads();
+    if (gg == 0) v[I * TS + cc] = (part[cc] + part[TS + cc]) + (part[2 * TS + cc] + part[3 * TS + cc]);
+    __syncthreads();
+  }
+  double *dst = xloc + p.vp_ptr[i];
+  for (int l = threadIdx.x; l < npad; l += WG) dst[l] = (double)v[l];
+}
+
+// ------------------------------------------- block solve (EIGP rhs) -------
+// In-place (L L^T)^{-1} X for a row-major padded block X[rows][EIGP], one
+// workgroup per region; regions flagged in skip[] are left untouched.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_profile_solve_block(Plan p, const T *__restrict__ tiles,
+                                                            double *__restrict__ X,
+                                                            const int *__restrict__ skip) {
+  const int i = blockIdx.x;
+  if (skip && skip[i]) return;
+  extern __shared__ double lds[];
+  double *Lt = lds;                    // 64 x LDT
+  double *V = lds + TS * LDT;          // 64 x (EIGP+1) right-hand block
+  double *Acc = V + TS * (EIGP + 1);   // 64 x (EIGP+1)
+  constexpr int LV = EIGP + 1;
+  const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
+  double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
+  const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
+  // forward
+  for (int I = 0; I < nt; ++I) {
+    const int fI = p.tfirst[g0 + I];
+    const long long tI = p.toff[g0 + I];
+    double acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = Xi[(size_t)(I * TS + r) * EIGP + c0 + j];
+    for (int J = fI; J < I; ++J) {
+      __syncthreads();
+      tile_to_lds(tiles + tile_elem(tI + (J - fI)), Lt);
+      for (int e = threadIdx.x; e < TS * EIGP; e += WG)
+        V[(e / EIGP) * LV + (e % EIGP)] = Xi[(size_t)J * TS * EIGP + e];
+      __syncthreads();
+      for (int k = 0; k < TS; ++k) {
+        const double a = Lt[r * LDT + k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = fma(-a, V[k * LV + c0 + j], acc[j]);
+      }
+    }
+    __syncthreads();
+    tile_to_lds(tiles + tile_elem(tI + (I - fI)), Lt);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Acc[r * LV + c0 + j] = acc[j];
+    __syncthreads();
+    double y[4] = {0, 0, 0, 0};
+    for (int k = 0; k < TS; ++k) {
+      const double a = Lt[r * LDT + k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) y[j] = fma(a, Acc[k * LV + c0 + j], y[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Xi[(size_t)(I * TS + r) * EIGP + c0 + j] = y[j];
+  }
+  // backward
+  for (int I = nt - 1; I >= 0; --I) {
+    __syncthreads();
+    double acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = Xi[(size_t)(I * TS + r) * EIGP + c0 + j];
+    for (int J = I + 1; J < nt; ++J) {
+      const int fJ = p.tfirst[g0 + J];
+      if (fJ > I) continue;
+      __syncthreads();
+      tile_to_lds(tiles + tile_elem(p.toff[g0 + J] + (I - fJ)), Lt);
+      for (int e = threadIdx.x; e < TS * EIGP; e += WG)
+        V[(e / EIGP) * LV + (e % EIGP)] = Xi[(size_t)J * TS * EIGP + e];
+      __syncthreads();
+      // acc[r][:] -= sum_k L_JI[k][r] V[k][:]
+      for (int k = 0; k < TS; ++k) {
+        const double a = Lt[k * LDT + r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = fma(-a, V[k * LV + c0 + j], acc[j]);
+      }
+    }
+    __syncthreads();
+    const int fI = p.tfirst[g0 + I];
+    tile_to_lds(tiles + tile_elem(p.toff[g0 + I] + (I - fI)), Lt);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Acc[r * LV + c0 + j] = acc[j];
+    __syncthreads();
+    double y[4] = {0, 0, 0, 0};
+    for (int k = 0; k < TS; ++k) {
+      const double a = Lt[k * LDT + r];  // inv(L_II)^T
+#pragma unroll
+      for (int j = 0; j < 4; ++j) y[j] = fma(a, Acc[k * LV + c0 + j], y[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Xi[(size_t)(I * TS + r) * EIGP + c0 + j] = y[j];
+  }
+}
+
+// ------------------------------------------------------------ scatter -----
+// z[j] = sum over regions containing j of (local correction + Phi t) and the
+// partial r.z, in the fixed order of the inverse map (no atomics).
+template <typename TB>
+__global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict__ inv_ptr,
+                                                    const int *__restrict__ inv_sd,
+                                                    const int *__restrict__ inv_loc, Plan p,
+                                                    const double *__restrict__ xloc,
+                                                    const TB *__restrict__ phi,
+                                                    const double *__restrict__ t,
+                                                    double *__restrict__ z,
+                                                    const double *__restrict__ r,
+                                                    double *__restrict__ partial, int do_local,
+                                                    int do_coarse, const int *__restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[WG / 64];
+  const int nev = p.nev;
+  double acc = 0.0;
+  for (int j = blockIdx.x * WG + threadIdx.x; j < n; j += gridDim.x * WG) {
+    double zj = 0.0;
+    for (int e = inv_ptr[j]; e < inv_ptr[j + 1]; ++e) {
+      const int sd = inv_sd[e], l = inv_loc[e];
+      if (do_local) zj += xloc[p.vp_ptr[sd] + l];
+      if (do_coarse) {
+        const int m = p.mi[sd];
+        const TB *ph = phi + (size_t)(p.sd_ptr[sd] + l) * nev;
+        const double *tt = t + p.coff[sd];
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s = fma(to_d(ph[k]), tt[k], s);
+        zj += s;
+      }
+    }
+    z[j] = zj;
+    if (r) acc = fma(r[j], zj, acc);
+  }
+  double tot = block_sum(acc, sh);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// ------------------------------------------------------------- launchers ---
+void launch_neumann_diag(hipStream_t s, const Plan &p, const double *val, double *sdiag,
+                         int *status) {
+  hipLaunchKernelGGL(k_neumann_diag, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, status);
+}
+
+void launch_extract_tiles(hipStream_t s, const Plan &p, int ntilerows, const double *val,
+                          const double *sdiag, double *tiles, int mode, double sigma) {
+  hipLaunchKernelGGL(k_extract_tiles, dim3(ntilerows), dim3(WG), 0, s, p, ntilerows, val, sdiag,
+                     tiles, mode, sigma);
+}
+
+void launch_profile_cholesky(hipStream_t s, const Plan &p, double *tiles, int *status, int bit) {
+  size_t sm = (size_t)(2 * TS * LDT + 4 * TS) * sizeof(double);
+  allow_lds(k_profile_cholesky, sm);
+  hipLaunchKernelGGL(k_profile_cholesky, dim3(p.N), dim3(WG), sm, s, p, tiles, bit, status);
+}
+
+void launch_tiles_to_f32(hipStream_t s, const double *src, float *dst, size_t count) {
+  size_t b = (count + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  hipLaunchKernelGGL(k_tiles_to_f32, dim3((unsigned)b), dim3(WG), 0, s, src, dst, count);
+}
+
+template <typename T, typename C, typename TB>
+void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
+                          const T *tiles, const TB *phi, double *xloc, double *cvec, int do_local,
+                          int do_coarse, const int *done) {
+  size_t sm = (size_t)(max_npad + TS + 4 * TS) * sizeof(C);
+  allow_lds(k_local_apply<T, C, TB>, sm);
+  hipLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, p, r, tiles, phi, xloc,
+                     cvec, do_local, do_coarse, done);
+}
+
+template void launch_local_apply_t<double, double, double>(hipStream_t, const Plan &, int,
+                                                           const double *, const double *,
+                                                           const double *, double *, double *,
+                                                           int, int, const int *);
+template void launch_local_apply_t<float, float, float>(hipStream_t, const Plan &, int,
+                                                        const double *, const float *,
+                                                        const float *, double *, double *, int,
+                                                        int, const int *);
+template void launch_local_apply_t<float, float, __hip_bfloat16>(hipStream_t, const Plan &, int,
+                                                                 const double *, const float *,
+                                                                 const __hip_bfloat16 *, double *,
+                                                                 double *, int, int, const int *);
+
+template <typename T>
+void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, double *X,
+                                const int *skip) {
+  size_t sm = (size_t)(TS * LDT + 2 * TS * (EIGP + 1)) * sizeof(double);
+  hipLaunchKernelGGL((k_profile_solve_block<T>), dim3(p.N), dim3(WG), sm, s, p, tiles, X, skip);
+}
+template void launch_profile_solve_block<double>(hipStream_t, const Plan &, const double *,
+                                                 double *, const int *);
+template void launch_profile_solve_block<float>(hipStream_t, const Plan &, const float *, double *,
+                                                const int *);
+
+template <typename TB>
+void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
+                          const int *inv_loc, const Plan &p, const double *xloc, const TB *phi,
+                          const double *t, double *z, const double *r, double *partial,
+                          int do_local, int do_coarse, const int *done) {
+  hipLaunchKernelGGL((k_scatter_sum<TB>), dim3(reduce_blocks(n)), dim3(WG), 0, s, n, inv_ptr,
+                     inv_sd, inv_loc, p, xloc, phi, t, z, r, partial, do_local, do_coarse, done);
+}
+template void launch_scatter_sum_t<double>(hipStream_t, int, const int *, const int *, const int *,
+                                           const Plan &, const double *, const double *,
+                                           const double *, double *, const double *, double *,
+                                           int, int, const int *);
+template void launch_scatter_sum_t<float>(hipStream_t, int, const int *, const int *, const int *,
+                                          const Plan &, const double *, const float *,
+                                          const double *, double *, const double *, double *, int,
+                                          int, const int *);
+template void launch_scatter_sum_t<__hip_bfloat16>(hipStream_t, int, const int *, const int *,
+                                                   const int *, const Plan &, const double *,
+                                                   const __hip_bfloat16 *, const double *,
+                                                   double *, const double *, double *, int, int,
+                                                   const int *);
+
+}  // namespace amsp
