@@ -86,12 +86,13 @@ typedef struct {
   int32_t local_order;      /* amsp_local_order                                         */
   int32_t dense_tiles;      /* 1: store the full lower triangle of tiles (no profile)   */
   double eig_tol;           /* residual bound ||B x - theta x|| for the kept pairs;      */
-                            /* 0 (default): 1e-10, or 1e-5 for the mixed forms           */
+                            /* 0 (default): 1e-12, or 1e-5 for the mixed forms           */
   int32_t eig_maxit;        /* maximum subspace sweeps (default 80)                      */
   double eig_shift;         /* sigma in (B + sigma I)^{-1} (default 1e-4)                */
   int32_t chunk;            /* PCG iterations per host poll (default 8)                  */
   int32_t flexible;         /* 1: Polak-Ribiere beta; -1 (default): on for mixed forms   */
   int32_t keep_a0;          /* 1: keep a copy of A0 for amsp_get_coarse_matrix           */
+  int32_t timing;           /* 1: time every PCG kernel launch with HIP events           */
   void *stream;             /* hipStream_t                                               */
 } amsp_options;
 
@@ -103,6 +104,16 @@ typedef struct {
   int32_t restarts;         /* residual replacements after a false convergence     */
   double solve_ms;          /* wall time of the call                               */
   int64_t bytes_per_iter;   /* algorithmic HBM bytes of one CG iteration           */
+  /* with opt.timing: summed device time and launch count per kernel class:
+   * [0] SpMV (+ search-direction update), [1] local apply (gather, restriction,
+   * forward/backward solves), [2] coarse solve (both triangular products),
+   * [3] scatter-sum, [4] CG vector update and reductions */
+  double kernel_ms[5];
+  int32_t kernel_launches[5];
+  int64_t local_apply_bytes; /* algorithmic bytes of one local-apply launch          */
+  /* attainable-accuracy floor eps * || |A| |u| || / ||f||: no float64 vector u
+   * can be certified below it; converged means relres_true <= max(rtol, floor) */
+  double relres_floor;
 } amsp_info;
 
 typedef struct {
@@ -144,12 +155,20 @@ amsp_status amsp_apply(amsp_handle *h, const double *r_dev, double *z_dev, int32
 amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
                              int32_t nrhs, int32_t parts);
 
-/* Preconditioned CG from u = 0 until ||f - A u|| <= rtol ||f|| (recursive
- * residual, confirmed by the true residual; a replacement restart follows a
- * false convergence).  Blocks; info may be NULL.  On AMSP_ERR_PCG_NOCONV u
- * holds the last iterate and the handle stays valid. */
+/* Preconditioned CG from u = 0 until the recursive residual satisfies
+ * ||r_k|| <= rtol ||f||; the true residual f - A u is then recomputed and
+ * accepted if it is below max(rtol, floor) with floor = eps || |A||u| || / ||f||
+ * (the rounding level of any float64 residual); otherwise CG restarts from the
+ * true residual (at most 3 times).  Blocks; info may be NULL.  On
+ * AMSP_ERR_PCG_NOCONV u holds the last iterate and the handle stays valid. */
 amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                      double rtol, int32_t maxit, amsp_info *info);
+
+/* Recursive relative residuals ||r_k|| / ||f|| of the last amsp_pcg call
+ * (last right-hand side; k = 0 .. iterations).  *count receives the length;
+ * at most cap values are written to relres_host (may be NULL). */
+amsp_status amsp_get_pcg_history(const amsp_handle *h, double *relres_host, int32_t cap,
+                                 int32_t *count);
 
 /* y = A x with the handle's matrix (asynchronous). */
 amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_dev);
@@ -167,6 +186,23 @@ amsp_status amsp_get_coarse_matrix(const amsp_handle *h, double *a0_host);
  * to get n_i in *ni first. */
 amsp_status amsp_get_region(const amsp_handle *h, int32_t i, int32_t *ni, int32_t *dofs,
                             double *phi);
+
+/* Host-only planning (no device work, usable without a GPU): validates the
+ * inputs and plans the overlapping regions exactly as amsp_setup does.
+ *   region_ptr   N+1 offsets (required)
+ *   region_dofs  global dofs of every region in the local order used by the
+ *                kernels; NULL to query sizes only; cap = its capacity
+ *   ntiles       64x64 tiles of one local factor set (may be NULL)
+ *   npairs       coupled subdomain pairs of A0 (may be NULL) */
+amsp_status amsp_plan_regions(const amsp_csr *A, const int32_t *partition, int32_t nparts,
+                              int32_t nev, const amsp_options *opt, int32_t *region_ptr,
+                              int32_t *region_dofs, int64_t cap, int64_t *ntiles,
+                              int64_t *npairs);
+
+/* Device self-test of the matrix-core operand layout the kernels rely on:
+ * D (16x16) = A (16x4) B (4x16) computed by one v_mfma_f64_16x16x4f64,
+ * all three row-major host arrays.  Uses the default stream; blocks. */
+amsp_status amsp_selftest_mfma(const double *a_host, const double *b_host, double *d_host);
 
 void amsp_destroy(amsp_handle *h);
 const char *amsp_status_string(amsp_status s);

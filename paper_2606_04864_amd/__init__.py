@@ -17,8 +17,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libamsp.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_04864_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2606_04864_amd/build.py` "
                       "(hipcc --offload-arch=gfx950)")
+# PyTorch-ROCm ships its own HIP/HSA runtime with the same soname as the
+# system one.  Loading torch first makes libamsp.so bind to that runtime, so
+# the process holds a single HSA instance that sees the GPU.
+try:
+    import torch as _torch_preload  # noqa: F401
+except ImportError:  # host-only use (planning, error codes) needs no torch
+    _torch_preload = None
 _lib = ctypes.CDLL(LIB_PATH)
 
 # status codes
@@ -51,14 +58,17 @@ class _Options(ctypes.Structure):
                 ("dense_tiles", ctypes.c_int32), ("eig_tol", ctypes.c_double),
                 ("eig_maxit", ctypes.c_int32), ("eig_shift", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("flexible", ctypes.c_int32),
-                ("keep_a0", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("keep_a0", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("relres_recursive", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("restarts", ctypes.c_int32), ("solve_ms", ctypes.c_double),
-                ("bytes_per_iter", ctypes.c_int64)]
+                ("bytes_per_iter", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 5),
+                ("kernel_launches", ctypes.c_int32 * 5), ("local_apply_bytes", ctypes.c_int64),
+                ("relres_floor", ctypes.c_double)]
 
 
 class _SetupInfo(ctypes.Structure):
@@ -84,12 +94,19 @@ _lib.amsp_spmv.argtypes = [_vp, _vp, _vp]
 _lib.amsp_spmv.restype = _i32
 _lib.amsp_get_setup_info.argtypes = [_vp, ctypes.POINTER(_SetupInfo)]
 _lib.amsp_get_setup_info.restype = _i32
+_lib.amsp_get_pcg_history.argtypes = [_vp, _vp, _i32, ctypes.POINTER(_i32)]
+_lib.amsp_get_pcg_history.restype = _i32
 _lib.amsp_get_eigenvalues.argtypes = [_vp, _vp]
 _lib.amsp_get_eigenvalues.restype = _i32
 _lib.amsp_get_coarse_matrix.argtypes = [_vp, _vp]
 _lib.amsp_get_coarse_matrix.restype = _i32
 _lib.amsp_get_region.argtypes = [_vp, _i32, ctypes.POINTER(_i32), _vp, _vp]
 _lib.amsp_get_region.restype = _i32
+_lib.amsp_plan_regions.argtypes = [ctypes.POINTER(_CSR), _vp, _i32, _i32, ctypes.POINTER(_Options),
+                                   _vp, _vp, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+_lib.amsp_plan_regions.restype = _i32
+_lib.amsp_selftest_mfma.argtypes = [_vp, _vp, _vp]
+_lib.amsp_selftest_mfma.restype = _i32
 _lib.amsp_destroy.argtypes = [_vp]
 _lib.amsp_status_string.argtypes = [_i32]
 _lib.amsp_status_string.restype = ctypes.c_char_p
@@ -99,15 +116,77 @@ _lib.amsp_setup_error.argtypes = []
 _lib.amsp_setup_error.restype = ctypes.c_char_p
 
 EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts", "amsp_pcg",
-            "amsp_spmv", "amsp_get_setup_info", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
-            "amsp_get_region", "amsp_destroy", "amsp_status_string", "amsp_last_error",
-            "amsp_setup_error"]
+            "amsp_spmv", "amsp_get_setup_info", "amsp_get_pcg_history", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
+            "amsp_get_region", "amsp_plan_regions", "amsp_selftest_mfma", "amsp_destroy", "amsp_status_string",
+            "amsp_last_error", "amsp_setup_error"]
+
+
+def plan_regions(row_ptr, col_idx, val, part, nparts: int, nev: int, *, overlap: int = 1,
+                 local_order: str = "rcm", dense_tiles: bool = False):
+    """Host-only planning: returns (list of region dof arrays in local order,
+    tile count of one factor set, number of coupled subdomain pairs)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(val, dtype=np.float64)
+    pa = np.ascontiguousarray(part, dtype=np.int32)
+    csr = _CSR(len(rp) - 1, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    o = _Options()
+    _lib.amsp_default_options(ctypes.byref(o))
+    o.overlap, o.local_order, o.dense_tiles = int(overlap), ORDER[local_order], int(dense_tiles)
+    ptr = np.zeros(int(nparts) + 1, dtype=np.int32)
+    nt, npairs = _i64(), _i64()
+    st = _lib.amsp_plan_regions(ctypes.byref(csr), pa.ctypes.data, int(nparts), int(nev),
+                                ctypes.byref(o), ptr.ctypes.data, None, 0, ctypes.byref(nt),
+                                ctypes.byref(npairs))
+    if st != AMSP_OK:
+        raise AmspError(st, _lib.amsp_setup_error().decode())
+    dofs = np.empty(int(ptr[-1]), dtype=np.int32)
+    st = _lib.amsp_plan_regions(ctypes.byref(csr), pa.ctypes.data, int(nparts), int(nev),
+                                ctypes.byref(o), ptr.ctypes.data, dofs.ctypes.data, len(dofs),
+                                None, None)
+    if st != AMSP_OK:
+        raise AmspError(st, _lib.amsp_setup_error().decode())
+    return [dofs[ptr[i]:ptr[i + 1]] for i in range(int(nparts))], nt.value, npairs.value
+
+
+def setup_error_code(row_ptr, col_idx, val, part, nparts: int, nev: int, overlap: int = 1,
+                     eig_shift: float = 1e-4) -> tuple:
+    """Run amsp_setup's host-side checks on inputs that are expected to fail
+    before any device work; returns (status name, message)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(val, dtype=np.float64)
+    pa = np.ascontiguousarray(part, dtype=np.int32)
+    csr = _CSR(len(rp) - 1, int(rp[-1]), rp.ctypes.data, ci.ctypes.data, va.ctypes.data)
+    o = _Options()
+    _lib.amsp_default_options(ctypes.byref(o))
+    o.overlap, o.eig_shift = int(overlap), float(eig_shift)
+    ptr = np.zeros(max(int(nparts), 0) + 1, dtype=np.int32)
+    st = _lib.amsp_plan_regions(ctypes.byref(csr), pa.ctypes.data, int(nparts), int(nev),
+                                ctypes.byref(o), ptr.ctypes.data, None, 0, None, None)
+    return STATUS.get(st, st), _lib.amsp_setup_error().decode()
+
+
+def selftest_mfma(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """D = A B (16x4 times 4x16) by one matrix-core instruction on the device."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    d = np.empty((16, 16), dtype=np.float64)
+    st = _lib.amsp_selftest_mfma(a.ctypes.data, b.ctypes.data, d.ctypes.data)
+    if st != AMSP_OK:
+        raise AmspError(st, "selftest failed")
+    return d
 
 
 def default_options() -> dict:
     o = _Options()
     _lib.amsp_default_options(ctypes.byref(o))
     return {name: getattr(o, name) for name, _ in _Options._fields_ if name != "stream"}
+
+
+def synchronize(stream=None):
+    torch = _torch()
+    (stream or torch.cuda.current_stream()).synchronize()
 
 
 def _torch():
@@ -136,7 +215,7 @@ class Preconditioner:
                  precision: str = "fp64", pou: int = 0, local_order: str = "rcm",
                  dense_tiles: bool = False, eig_tol: float = 0.0, eig_maxit: int = 80,
                  eig_shift: float = 1e-4, chunk: int = 8, flexible: int = -1,
-                 keep_a0: bool = False, stream=None):
+                 keep_a0: bool = False, timing: bool = False, stream=None):
         torch = _torch()
         self._h = None
         self._keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
@@ -154,8 +233,12 @@ class Preconditioner:
         o.local_order, o.dense_tiles = ORDER[local_order], int(bool(dense_tiles))
         o.eig_tol, o.eig_maxit, o.eig_shift = float(eig_tol), int(eig_maxit), float(eig_shift)
         o.chunk, o.flexible, o.keep_a0 = int(chunk), int(flexible), int(bool(keep_a0))
-        if stream is None and torch.cuda.is_available():
-            stream = torch.cuda.current_stream()
+        o.timing = int(bool(timing))
+        if torch.cuda.is_available():
+            torch.cuda.init()  # the device context exists before the library's first HIP call
+            torch.cuda.synchronize()
+            if stream is None:
+                stream = torch.cuda.current_stream()
         self.stream = stream
         o.stream = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
         h = ctypes.c_void_p()
@@ -212,7 +295,10 @@ class Preconditioner:
         inf = _Info()
         st = _lib.amsp_pcg(self._h, f.data_ptr(), u.data_ptr(), 1, float(rtol), int(maxit),
                            ctypes.byref(inf))
-        info = {name: getattr(inf, name) for name, _ in _Info._fields_}
+        info = {name: getattr(inf, name) for name, _ in _Info._fields_
+                if name not in ("kernel_ms", "kernel_launches")}
+        info["kernel_ms"] = list(inf.kernel_ms)
+        info["kernel_launches"] = list(inf.kernel_launches)
         info["status"] = STATUS.get(st, st)
         if st != AMSP_OK and (raise_on_noconv or st != -9):
             raise AmspError(st, _lib.amsp_last_error(self._h).decode())
@@ -225,6 +311,14 @@ class Preconditioner:
         d = {name: getattr(si, name) for name, _ in _SetupInfo._fields_ if name != "phase_ms"}
         d["phase_ms"] = list(si.phase_ms)
         return d
+
+    def pcg_history(self) -> np.ndarray:
+        """Recursive relative residuals of the last pcg() call."""
+        cnt = ctypes.c_int32()
+        self._err(_lib.amsp_get_pcg_history(self._h, None, 0, ctypes.byref(cnt)))
+        out = np.empty(cnt.value, dtype=np.float64)
+        self._err(_lib.amsp_get_pcg_history(self._h, out.ctypes.data, len(out), ctypes.byref(cnt)))
+        return out
 
     def eigenvalues(self) -> np.ndarray:
         out = np.empty((self.nparts, self.nev + 1), dtype=np.float64)

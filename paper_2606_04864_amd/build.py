@@ -1,6 +1,6 @@
 """Build libamsp.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
 
-Usage: python -m paper_2606_04864_amd.build   (or call build()).
+Usage: python paper_2606_04864_amd/build.py   (or call build()).
 Object files go to _build/ at the repository root (git-ignored); the shared
 library lands next to this file so that the binding and the GPU machine find it.
 """

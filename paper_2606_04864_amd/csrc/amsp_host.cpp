@@ -4,6 +4,7 @@
 // this file moves data, launches kernels and reads back status words.
 #include <hip/hip_bf16.h>
 
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -87,9 +88,46 @@ struct amsp_handle {
   double *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr, *scal = nullptr;
   PcgState *st = nullptr;
+  double *hist = nullptr;  // recursive residual history of the last PCG call
+  int hist_cap = 0, hist_len = 0;
+  double hist_f2 = 0.0;
   amsp_setup_info sinfo{};
   std::string err;
+  // per-launch HIP-event timing of the PCG kernels (opt.timing)
+  std::vector<hipEvent_t> evs;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, int>> ev_rec;  // (kernel class, index of start event)
+  bool timing_active = false;
+  ~amsp_handle() {
+    for (hipEvent_t e : evs) hipEventDestroy(e);
+  }
 };
+
+static hipEvent_t next_event(amsp_handle *h) {
+  if (h->ev_used == h->evs.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->evs.push_back(e);
+  }
+  return h->evs[h->ev_used++];
+}
+
+static int tstart(amsp_handle *h) {
+  if (!h->timing_active) return -1;
+  const int idx = (int)h->ev_used;
+  hipEvent_t e = next_event(h);
+  if (!e) return -1;
+  hipEventRecord(e, h->stream);
+  return idx;
+}
+
+static void tstop(amsp_handle *h, int cls, int idx) {
+  if (idx < 0) return;
+  hipEvent_t e = next_event(h);
+  if (!e) return;
+  hipEventRecord(e, h->stream);
+  h->ev_rec.emplace_back(cls, idx);
+}
 
 #define HIP_TRY(expr)                                                     \
   do {                                                                    \
@@ -104,7 +142,8 @@ struct amsp_handle {
   do {                                                                    \
     dst = h->mem.alloc<T>(count);                                         \
     if (!dst) {                                                           \
-      h->err = "device allocation failed: " #dst;                          \
+      h->err = std::string("device allocation failed: " #dst ": ") +       \
+               hipGetErrorString(hipGetLastError());                      \
       return AMSP_ERR_OOM;                                                \
     }                                                                     \
   } while (0)
@@ -132,11 +171,13 @@ extern "C" void amsp_default_options(amsp_options *opt) {
   opt->pou = 0;
   opt->local_order = AMSP_ORDER_RCM;
   opt->dense_tiles = 0;
-  opt->eig_tol = 0.0;  // 0: 1e-10 (FP64) or 1e-5 (mixed forms)
+  opt->eig_tol = 0.0;  // 0: 1e-12 (FP64) or 1e-5 (mixed forms)
   opt->eig_maxit = 80;
   opt->eig_shift = 1e-4;
   opt->chunk = 8;
   opt->flexible = -1;  // -1: on for the mixed forms
+  opt->keep_a0 = 0;
+  opt->timing = 0;
   opt->stream = nullptr;
 }
 
@@ -166,7 +207,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     h->col = h->mem.alloc<int>(h->nnz);
     h->val = h->mem.alloc<double>(h->nnz);
     if (!ok || !h->col || !h->val) {
-      h->err = "device allocation failed (matrix)";
+      h->err = std::string("device allocation failed (matrix): ") + hipGetErrorString(hipGetLastError());
       return AMSP_ERR_OOM;
     }
     HIP_TRY(hipMemcpyAsync(h->col, A->col_idx, h->nnz * sizeof(int), hipMemcpyHostToDevice, h->stream));
@@ -256,11 +297,14 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   ALLOC(h->lam, double, (size_t)h->N * (h->nev + 1));
   launch_fill(h->stream, (size_t)h->N * (h->nev + 1), h->lam, std::nan(""));
   if (h->nev > 0) {
-    double *facB, *X, *BQ;
+    double *facB, *X, *BQ, *Hbuf, *Vbuf, *Tbuf;
     int *conv;
     ALLOC(facB, double, fac_elems);
     ALLOC(X, double, (size_t)sum_npad * EIGP);
     ALLOC(BQ, double, (size_t)sum_npad * EIGP);
+    ALLOC(Hbuf, double, (size_t)h->N * EIGP * EIGP);
+    ALLOC(Vbuf, double, (size_t)h->N * EIGP * EIGP);
+    ALLOC(Tbuf, double, (size_t)h->N * EIGP);
     ALLOC(conv, int, h->N);
     HIP_TRY(hipMemsetAsync(conv, 0, h->N * sizeof(int), h->stream));
     launch_extract_tiles(h->stream, p, h->ntilerows, h->val, h->sdiag, facB, 1, h->opt.eig_shift);
@@ -284,7 +328,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       facB = nullptr;
     }
     launch_eig_init(h->stream, p, h->sdiag, X);
-    const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-5 : 1e-10);
+    const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-5 : 1e-12);
     std::vector<int> hconv(h->N);
     int sweeps = 0, unconv = h->N;
     for (int it = 1; it <= h->opt.eig_maxit; ++it) {
@@ -292,7 +336,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
         launch_profile_solve_block<float>(h->stream, p, facB32, X, conv);
       else
         launch_profile_solve_block<double>(h->stream, p, facB, X, conv);
-      launch_eig_rr(h->stream, p, h->val, h->sdiag, X, X, BQ, tol, conv, h->lam);
+      launch_eig_rr(h->stream, p, h->val, h->sdiag, X, BQ, Hbuf, Vbuf, Tbuf, tol, conv, h->lam);
       sweeps = it;
       if (it >= 4 && (it % 2 == 0 || it == h->opt.eig_maxit)) {
         HIP_TRY(hipGetLastError());
@@ -317,6 +361,9 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     if (facB32) h->mem.free_one(facB32);
     h->mem.free_one(X);
     h->mem.free_one(BQ);
+    h->mem.free_one(Hbuf);
+    h->mem.free_one(Vbuf);
+    h->mem.free_one(Tbuf);
     h->mem.free_one(conv);
     // gap flags and mu_c
     std::vector<double> lam((size_t)h->N * (h->nev + 1));
@@ -515,6 +562,7 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
   const bool mixed = h->opt.precision != AMSP_FP64;
   const bool bf = h->opt.precision == AMSP_MIXED_BF16;
+  int tk = tstart(h);
   if (!mixed) {
     launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->fac64, h->phi64,
                                                  h->xloc, h->cvec, do_local, do_coarse, done);
@@ -527,7 +575,9 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
                                                        (const __hip_bfloat16 *)h->phi_lo, h->xloc,
                                                        h->cvec, do_local, do_coarse, done);
   }
+  tstop(h, 1, tk);
   if (do_coarse) {
+    tk = tstart(h);
     if (!mixed) {
       launch_trmv<double>(h->stream, h->W0, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
       launch_trmv<double>(h->stream, h->W0, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
@@ -535,7 +585,9 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
       launch_trmv<float>(h->stream, h->W0f, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
       launch_trmv<float>(h->stream, h->W0f, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
     }
+    tstop(h, 2, tk);
   }
+  tk = tstart(h);
   if (!mixed || h->nev == 0)
     launch_scatter_sum_t<double>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
                                  h->phi64, h->tvec, z, partial_rz ? r : nullptr, partial_rz,
@@ -549,6 +601,7 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
                                          h->xloc, (const __hip_bfloat16 *)h->phi_lo, h->tvec, z,
                                          partial_rz ? r : nullptr, partial_rz, do_local, do_coarse,
                                          done);
+  tstop(h, 3, tk);
   HIP_TRY(hipGetLastError());
   return AMSP_OK;
 }
@@ -572,6 +625,19 @@ extern "C" amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_
   launch_spmv(h->stream, h->n, h->rowptr, h->col, h->val, x_dev, y_dev, nullptr, nullptr);
   HIP_TRY(hipGetLastError());
   return AMSP_OK;
+}
+
+// Algorithmic bytes of one local-apply launch: gather of r and the region
+// index, basis read for the restriction, both factor sweeps, local output.
+static int64_t local_apply_bytes(const amsp_handle *h) {
+  const HostPlan &P = h->hp;
+  const bool mixed = h->opt.precision != AMSP_FP64;
+  const int64_t sni = P.sd_ptr.back(), snp = P.vp_ptr.back();
+  const int64_t fb = mixed ? 4 : 8;
+  const int64_t pb = mixed ? (h->opt.precision == AMSP_MIXED_BF16 ? 2 : 4) : 8;
+  int64_t b = sni * (8 + 4) + snp * 8 + 2 * P.ntiles * (int64_t)TE * fb;
+  if (h->nc > 0) b += sni * h->nev * pb + (int64_t)h->nc * 8;
+  return b;
 }
 
 static int64_t bytes_per_iter(const amsp_handle *h) {
@@ -601,10 +667,25 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   const int nb = reduce_blocks(n);
   amsp_info inf{};
   inf.bytes_per_iter = bytes_per_iter(h);
+  inf.local_apply_bytes = local_apply_bytes(h);
+  h->timing_active = h->opt.timing != 0;
+  h->ev_used = 0;
+  h->ev_rec.clear();
+  if (h->hist_cap < maxit + 2) {
+    if (h->hist) h->mem.free_one(h->hist);
+    h->hist_cap = std::max(maxit + 2, 1024);
+    ALLOC(h->hist, double, h->hist_cap);
+  }
+  {
+    PcgState init{};
+    init.hist = h->hist;
+    init.hist_cap = h->hist_cap;
+    HIP_TRY(hipMemcpyAsync(h->st, &init, sizeof(PcgState), hipMemcpyHostToDevice, h->stream));
+  }
   double t0 = now_ms();
   amsp_status final_status = AMSP_OK;
   int tot_it = 0;
-  double worst_true = 0.0, worst_rec = 0.0;
+  double worst_true = 0.0, worst_rec = 0.0, worst_floor = 0.0;
   int all_conv = 1, tot_restarts = 0;
   PcgState hs{};
   for (int k = 0; k < nrhs; ++k) {
@@ -614,7 +695,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
     launch_copy_scale(h->stream, n, f, h->r, 1.0);
     int restarts = 0;
     bool fresh = true;
-    double relres_true = 0.0;
+    double relres_true = 0.0, floor_rel = 0.0;
     for (;;) {
       // z = M^{-1} r with r.z partials; r.r partials; p_old = 0
       launch_dot(h->stream, n, h->r, h->r, h->part_a, nullptr);
@@ -625,20 +706,38 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
       HIP_TRY(hipGetLastError());
       const int *done = &h->st->done;
       double *pold = h->p0, *pnew = h->p1;
+      int next = h->opt.chunk, prev_it = 0;
+      double prev_rr = -1.0;
       for (;;) {
         HIP_TRY(hipMemcpyAsync(&hs, h->st, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
         if (hs.done) break;
-        for (int c = 0; c < h->opt.chunk; ++c) {
+        // size the next chunk from the observed residual decay so that few
+        // launches follow convergence (they would return at once anyway)
+        if (prev_rr > 0.0 && hs.it > prev_it && hs.rr < prev_rr && hs.rr > 0.0) {
+          const double rate = std::log(hs.rr / prev_rr) / (double)(hs.it - prev_it);
+          const double need = std::log(hs.tol2 / hs.rr) / rate;
+          next = (int)std::ceil(need);
+          next = std::max(1, std::min(next, h->opt.chunk));
+        }
+        prev_rr = hs.rr;
+        prev_it = hs.it;
+        for (int c = 0; c < next; ++c) {
+          int tk = tstart(h);
           launch_spmv_pupdate_st(h->stream, n, h->rowptr, h->col, h->val, h->z, pold, pnew, h->q,
                                  h->part_a, h->st);
+          tstop(h, 0, tk);
+          tk = tstart(h);
           launch_pcg_alpha(h->stream, h->st, h->part_a, nb);
           launch_axpy_update_st(h->stream, n, x, h->r, pnew, h->q, h->st, h->part_a);
           launch_pcg_rr(h->stream, h->st, h->part_a, nb);
           if (h->opt.flexible) launch_dot(h->stream, n, h->r, h->z, h->part_c, done);
+          tstop(h, 4, tk);
           s = apply_one(h, h->r, h->z, 3, h->part_b, done);
           if (s != AMSP_OK) return s;
+          tk = tstart(h);
           launch_pcg_beta(h->stream, h->st, h->part_b, nb, h->part_c, h->opt.flexible);
+          tstop(h, 4, tk);
           std::swap(pold, pnew);
         }
         HIP_TRY(hipGetLastError());
@@ -647,15 +746,18 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
       launch_spmv(h->stream, n, h->rowptr, h->col, h->val, x, h->q, nullptr, nullptr);
       launch_residual(h->stream, n, f, h->q, h->r, h->part_a);
       launch_sum_partials(h->stream, h->part_a, nb, h->scal);
-      double rrt = 0.0;
-      HIP_TRY(hipMemcpyAsync(&rrt, h->scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      launch_abs_spmv_sq(h->stream, n, h->rowptr, h->col, h->val, x, h->part_c);
+      launch_sum_partials(h->stream, h->part_c, nb, h->scal + 1);
+      double rrt[2] = {0.0, 0.0};
+      HIP_TRY(hipMemcpyAsync(rrt, h->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
       HIP_TRY(hipStreamSynchronize(h->stream));
-      relres_true = hs.f2 > 0 ? std::sqrt(rrt / hs.f2) : 0.0;
+      relres_true = hs.f2 > 0 ? std::sqrt(rrt[0] / hs.f2) : 0.0;
+      floor_rel = hs.f2 > 0 ? DBL_EPSILON * std::sqrt(rrt[1] / hs.f2) : 0.0;
       if (hs.breakdown) {
         final_status = AMSP_ERR_BREAKDOWN;
         break;
       }
-      if (!(relres_true <= rtol) && hs.it < maxit && restarts < 3) {
+      if (!(relres_true <= std::max(rtol, floor_rel)) && hs.it < maxit && restarts < 3) {
         // false convergence of the recursive residual: restart from r = f - A x
         ++restarts;
         fresh = false;
@@ -664,11 +766,14 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
       break;
     }
     const double rel_rec = hs.f2 > 0 ? std::sqrt(hs.rr / hs.f2) : 0.0;
+    h->hist_len = std::min(hs.it + 1, h->hist_cap);
+    h->hist_f2 = hs.f2;
     tot_it += hs.it;
     tot_restarts += restarts;
     worst_true = std::max(worst_true, relres_true);
     worst_rec = std::max(worst_rec, rel_rec);
-    const bool conv = (relres_true <= rtol) && !hs.breakdown;
+    worst_floor = std::max(worst_floor, floor_rel);
+    const bool conv = (relres_true <= std::max(rtol, floor_rel)) && !hs.breakdown;
     if (!conv) all_conv = 0;
     if (!conv && final_status == AMSP_OK) final_status = AMSP_ERR_PCG_NOCONV;
   }
@@ -677,7 +782,21 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   inf.relres_recursive = worst_rec;
   inf.relres_true = worst_true;
   inf.restarts = tot_restarts;
+  inf.relres_floor = worst_floor;
   inf.solve_ms = now_ms() - t0;
+  if (h->timing_active) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (auto &rc : h->ev_rec) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, h->evs[rc.second], h->evs[rc.second + 1]) == hipSuccess) {
+        inf.kernel_ms[rc.first] += ms;
+        inf.kernel_launches[rc.first] += 1;
+      }
+    }
+    h->ev_rec.clear();
+    h->ev_used = 0;
+    h->timing_active = false;
+  }
   if (info) *info = inf;
   return final_status;
 }
@@ -686,6 +805,20 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
 extern "C" amsp_status amsp_get_setup_info(const amsp_handle *h, amsp_setup_info *info) {
   if (!h || !info) return AMSP_ERR_ARG;
   *info = h->sinfo;
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_get_pcg_history(const amsp_handle *hc, double *relres_host,
+                                            int32_t cap, int32_t *count) {
+  amsp_handle *h = const_cast<amsp_handle *>(hc);
+  if (!h || !count) return AMSP_ERR_ARG;
+  *count = h->hist_len;
+  if (!relres_host || h->hist_len == 0) return AMSP_OK;
+  const int k = std::min(cap, h->hist_len);
+  std::vector<double> tmp(k);
+  HIP_TRY(hipMemcpyAsync(tmp.data(), h->hist, k * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int j = 0; j < k; ++j) relres_host[j] = h->hist_f2 > 0 ? std::sqrt(tmp[j] / h->hist_f2) : 0.0;
   return AMSP_OK;
 }
 
@@ -731,6 +864,59 @@ extern "C" amsp_status amsp_get_region(const amsp_handle *hc, int32_t i, int32_t
     HIP_TRY(hipStreamSynchronize(h->stream));
   }
   return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_plan_regions(const amsp_csr *A, const int32_t *partition,
+                                         int32_t nparts, int32_t nev, const amsp_options *opt,
+                                         int32_t *region_ptr, int32_t *region_dofs, int64_t cap,
+                                         int64_t *ntiles, int64_t *npairs) {
+  if (!region_ptr) return AMSP_ERR_ARG;
+  amsp_options o;
+  amsp_default_options(&o);
+  if (opt) o = *opt;
+  std::string msg;
+  int s = validate_inputs(A, partition, nparts, nev, o.overlap, msg);
+  if (s != AMSP_OK) {
+    g_setup_error = msg;
+    return (amsp_status)s;
+  }
+  HostPlan P;
+  try {
+    s = build_plan(A, partition, nparts, nev, o, P, msg);
+  } catch (const std::bad_alloc &) {
+    g_setup_error = "host allocation failed during planning";
+    return AMSP_ERR_OOM;
+  }
+  if (s != AMSP_OK) {
+    g_setup_error = msg;
+    return (amsp_status)s;
+  }
+  for (int i = 0; i <= nparts; ++i) region_ptr[i] = P.sd_ptr[i];
+  if (region_dofs) {
+    if (cap < (int64_t)P.sd_dofs.size()) return AMSP_ERR_ARG;
+    std::memcpy(region_dofs, P.sd_dofs.data(), P.sd_dofs.size() * sizeof(int32_t));
+  }
+  if (ntiles) *ntiles = P.ntiles;
+  if (npairs) *npairs = (int64_t)P.pair_i.size();
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_selftest_mfma(const double *a_host, const double *b_host, double *d_host) {
+  if (!a_host || !b_host || !d_host) return AMSP_ERR_ARG;
+  double *d = nullptr;
+  if (hipMalloc(&d, (64 + 64 + 256) * sizeof(double)) != hipSuccess) return AMSP_ERR_HIP;
+  amsp_status st = AMSP_OK;
+  if (hipMemcpy(d, a_host, 64 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d + 64, b_host, 64 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    st = AMSP_ERR_HIP;
+  } else {
+    launch_selftest_mfma(nullptr, d, d + 64, d + 128);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpy(d_host, d + 128, 256 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      st = AMSP_ERR_HIP;
+  }
+  hipFree(d);
+  return st;
 }
 
 extern "C" void amsp_destroy(amsp_handle *h) {

@@ -31,6 +31,8 @@ struct Plan {
 struct PcgState {
   double rz, rz_old, pq, rr, alpha, beta, tol2, f2;
   int it, done, breakdown, maxit;
+  double *hist;   // rr after each iteration (hist[it]); may be null
+  int hist_cap;
 };
 
 // ---------------------------------------------------------------- krylov ---
@@ -47,6 +49,8 @@ void launch_axpy_update_st(hipStream_t s, int n, double *x, double *r, const dou
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
                      double *partial);
 void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha);
+void launch_abs_spmv_sq(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                        const double *x, double *partial);
 void launch_fill(hipStream_t s, size_t n, double *a, double v);
 void launch_fill_int(hipStream_t s, size_t n, int *a, int v);
 void launch_sum_partials(hipStream_t s, const double *partial, int nb, double *out);
@@ -78,6 +82,7 @@ void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const doub
 template <typename T>
 void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, double *X,
                                 const int *skip);
+void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D);
 template <typename TB>
 void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
                           const int *inv_loc, const Plan &p, const double *xloc, const TB *phi,
@@ -86,8 +91,12 @@ void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *i
 
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
+// Rayleigh-Ritz step on the solve output held in X (in place): CholQR2,
+// projection H = Q^T B Q, Jacobi, X = Q V, residuals and convergence flags.
+// Hbuf, Vbuf: N*EIGP*EIGP doubles; Tbuf: N*EIGP doubles.
 void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag, double *X,
-                   double *Y, double *BQ, double tol, int *conv, double *lam);
+                   double *BQ, double *Hbuf, double *Vbuf, double *Tbuf, double tol, int *conv,
+                   double *lam);
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
                         double *phi, int pou);
 void launch_basis_convert(hipStream_t s, const double *phi, void *dst, size_t count, int bf16);

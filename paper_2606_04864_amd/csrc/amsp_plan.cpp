@@ -14,10 +14,37 @@
 #include "amsp_plan.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
+#include <thread>
 
 namespace amsp {
+
+// Run fn(i) for i in [0, count) on up to `threads` workers (dynamic schedule).
+template <typename F>
+static void parallel_for(int count, F fn) {
+  unsigned hw = std::thread::hardware_concurrency();
+#ifdef AMSP_PLAN_SERIAL
+  hw = 1;
+#endif
+  int nth = (int)std::min<unsigned>(hw ? hw : 1, 16);
+  nth = std::max(1, std::min(nth, count));
+  std::atomic<int> next(0);
+  auto work = [&]() {
+    for (;;) {
+      int i = next.fetch_add(1);
+      if (i >= count) break;
+      fn(i);
+    }
+  };
+  std::vector<std::thread> ts;
+  for (int t = 1; t < nth; ++t) ts.emplace_back(work);
+  work();
+  for (auto &t : ts) t.join();
+}
 
 int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
                     int32_t overlap, std::string &msg) {
@@ -47,49 +74,80 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     msg = "row_ptr[0] must be 0, row_ptr[n] == nnz < 2^31";
     return AMSP_ERR_CSR;
   }
-  double amax = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
+  // row structure (sequential: cheap, and the first error is well defined)
+  for (int64_t i = 0; i < n; ++i)
     if (rp[i + 1] < rp[i]) {
       msg = "row_ptr not monotone at row " + std::to_string(i);
       return AMSP_ERR_CSR;
     }
-    bool diag = false;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      const int32_t c = A->col_idx[e];
-      if (c < 0 || c >= n || (e > rp[i] && c <= A->col_idx[e - 1])) {
-        msg = "column index out of range or unsorted in row " + std::to_string(i);
-        return AMSP_ERR_CSR;
+  // per-row checks in parallel chunks; the lowest failing row is reported
+  const int nchunk = 64;
+  std::vector<int> cerr(nchunk, 0);
+  std::vector<int64_t> crow(nchunk, -1);
+  std::vector<double> cmax(nchunk, 0.0);
+  auto chunk_rows = [&](int c, int64_t &r0, int64_t &r1) {
+    r0 = n * c / nchunk;
+    r1 = n * (c + 1) / nchunk;
+  };
+  parallel_for(nchunk, [&](int c) {
+    int64_t r0, r1;
+    chunk_rows(c, r0, r1);
+    double amax = 0.0;
+    for (int64_t i = r0; i < r1; ++i) {
+      bool diag = false;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t cc = A->col_idx[e];
+        if (cc < 0 || cc >= n || (e > rp[i] && cc <= A->col_idx[e - 1]) || !std::isfinite(A->val[e])) {
+          cerr[c] = 1;
+          crow[c] = i;
+          return;
+        }
+        if (cc == i) diag = true;
+        amax = std::max(amax, std::fabs(A->val[e]));
       }
-      const double v = A->val[e];
-      if (!std::isfinite(v)) {
-        msg = "non-finite value in row " + std::to_string(i);
-        return AMSP_ERR_CSR;
+      if (!diag) {
+        cerr[c] = 2;
+        crow[c] = i;
+        return;
       }
-      if (c == i) diag = true;
-      amax = std::max(amax, std::fabs(v));
     }
-    if (!diag) {
-      msg = "missing diagonal entry in row " + std::to_string(i);
+    cmax[c] = amax;
+  });
+  for (int c = 0; c < nchunk; ++c) {
+    if (cerr[c] == 1) {
+      msg = "column index out of range, unsorted, or non-finite value in row " + std::to_string(crow[c]);
+      return AMSP_ERR_CSR;
+    }
+    if (cerr[c] == 2) {
+      msg = "missing diagonal entry in row " + std::to_string(crow[c]);
       return AMSP_ERR_CSR;
     }
   }
+  double amax = 0.0;
+  for (double v : cmax) amax = std::max(amax, v);
   const double tol = 1e-14 * amax;
-  for (int64_t i = 0; i < n; ++i) {
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      const int32_t c = A->col_idx[e];
-      if (c == i) continue;
-      const int32_t *b = A->col_idx + rp[c], *en = A->col_idx + rp[c + 1];
-      const int32_t *f = std::lower_bound(b, en, (int32_t)i);
-      if (f == en || *f != i) {
-        msg = "pattern not symmetric at (" + std::to_string(i) + "," + std::to_string(c) + ")";
-        return AMSP_ERR_NONSYM;
-      }
-      if (std::fabs(A->val[rp[c] + (f - b)] - A->val[e]) > tol) {
-        msg = "values not symmetric at (" + std::to_string(i) + "," + std::to_string(c) + ")";
-        return AMSP_ERR_NONSYM;
+  parallel_for(nchunk, [&](int c) {
+    int64_t r0, r1;
+    chunk_rows(c, r0, r1);
+    for (int64_t i = r0; i < r1; ++i) {
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t cc = A->col_idx[e];
+        if (cc == i) continue;
+        const int32_t *b = A->col_idx + rp[cc], *en = A->col_idx + rp[cc + 1];
+        const int32_t *f = std::lower_bound(b, en, (int32_t)i);
+        if (f == en || *f != i || std::fabs(A->val[rp[cc] + (f - b)] - A->val[e]) > tol) {
+          cerr[c] = 3;
+          crow[c] = i;
+          return;
+        }
       }
     }
-  }
+  });
+  for (int c = 0; c < nchunk; ++c)
+    if (cerr[c] == 3) {
+      msg = "matrix not symmetric in row " + std::to_string(crow[c]);
+      return AMSP_ERR_NONSYM;
+    }
   std::vector<int64_t> cnt(nparts, 0);
   for (int64_t j = 0; j < n; ++j) {
     if (part[j] < 0 || part[j] >= nparts) {
@@ -169,9 +227,15 @@ static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &a
       nb.clear();
       for (int e = adj_ptr[v]; e < adj_ptr[v + 1]; ++e)
         if (!vis[adj[e]]) nb.push_back(adj[e]);
-      std::sort(nb.begin(), nb.end(), [&](int a, int b) {
-        return deg[a] != deg[b] ? deg[a] < deg[b] : a < b;
-      });
+      for (size_t x = 1; x < nb.size(); ++x) {  // short lists: insertion sort by (degree, index)
+        const int w = nb[x];
+        size_t y = x;
+        while (y > 0 && (deg[nb[y - 1]] > deg[w] || (deg[nb[y - 1]] == deg[w] && nb[y - 1] > w))) {
+          nb[y] = nb[y - 1];
+          --y;
+        }
+        nb[y] = w;
+      }
       for (int w : nb)
         if (!vis[w]) {
           vis[w] = 1;
@@ -182,18 +246,145 @@ static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &a
   std::reverse(order.begin(), order.end());
 }
 
-int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
-               const amsp_options &opt, HostPlan &P, std::string &msg) {
-  const int n = (int)A->n;
+// Per-subdomain planning result (built independently, concatenated in order).
+struct SubPlan {
+  std::vector<int> dofs;                 // local order -> global dof
+  std::vector<int> rowlen, lcol, lsrc;   // local CSR (row lengths)
+  std::vector<int> tfirst;               // tile profile
+  std::vector<int> ext;                  // extended region (ascending global)
+  std::vector<int> ext_rowlen, ext_src, ext_loc;
+  std::vector<int> pair_j, pair_len, pair_l, pair_e;
+};
+
+namespace {
+struct Scratch {
+  std::vector<int> stamp, loc;
+  std::vector<int> frontier, next, adj_ptr, adj, order, mincol;
+  std::vector<std::pair<int, int>> row;
+  explicit Scratch(int n) : stamp(n, -1), loc(n, -1) {}
+};
+}  // namespace
+
+static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_ptr,
+                        const std::vector<int> &core, int nev, const amsp_options &opt,
+                        Scratch &S, SubPlan &out) {
   const int64_t *rp = A->row_ptr;
   const int32_t *ci = A->col_idx;
   const double *va = A->val;
-  const int N = nparts;
   const int delta = opt.overlap;
+  std::vector<int> region(core.begin() + core_ptr[i], core.begin() + core_ptr[i + 1]);
+  for (int g : region) S.stamp[g] = i;
+  S.frontier = region;
+  const int layers = delta + (nev > 0 ? 1 : 0);
+  size_t region_size = region.size();
+  for (int d = 0; d < layers; ++d) {
+    S.next.clear();
+    for (int g : S.frontier)
+      for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+        const int c = ci[e];
+        if (c != g && va[e] != 0.0 && S.stamp[c] != i) {
+          S.stamp[c] = i;
+          S.next.push_back(c);
+        }
+      }
+    region.insert(region.end(), S.next.begin(), S.next.end());
+    if (d == delta - 1) region_size = region.size();
+    S.frontier.swap(S.next);
+  }
+  if (nev > 0) out.ext.assign(region.begin(), region.end());
+  region.resize(region_size);
+  std::sort(region.begin(), region.end());
+  const int ni = (int)region.size();
+  std::vector<int> &loc = S.loc;
+  for (int k = 0; k < ni; ++k) loc[region[k]] = k;
+  S.adj_ptr.assign(ni + 1, 0);
+  S.adj.clear();
+  for (int k = 0; k < ni; ++k) {
+    const int g = region[k];
+    for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+      const int c = ci[e];
+      if (c != g && va[e] != 0.0 && loc[c] >= 0) S.adj.push_back(loc[c]);
+    }
+    S.adj_ptr[k + 1] = (int)S.adj.size();
+  }
+  if (opt.local_order == AMSP_ORDER_RCM) {
+    rcm_order(S.adj_ptr, S.adj, S.order);
+  } else {
+    S.order.resize(ni);
+    for (int k = 0; k < ni; ++k) S.order[k] = k;
+  }
+  out.dofs.resize(ni);
+  for (int k = 0; k < ni; ++k) {
+    const int g = region[S.order[k]];
+    out.dofs[k] = g;
+    loc[g] = k;
+  }
+  S.mincol.assign(ni, 0);
+  out.rowlen.resize(ni);
+  for (int k = 0; k < ni; ++k) {
+    const int g = out.dofs[k];
+    S.row.clear();
+    for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+      const int c = ci[e];
+      if (loc[c] >= 0) S.row.emplace_back(loc[c], (int)e);
+    }
+    std::sort(S.row.begin(), S.row.end());
+    S.mincol[k] = S.row.empty() ? k : std::min(k, S.row.front().first);
+    for (auto &pr : S.row) {
+      out.lcol.push_back(pr.first);
+      out.lsrc.push_back(pr.second);
+    }
+    out.rowlen[k] = (int)S.row.size();
+  }
+  const int nt = (ni + TS - 1) / TS;
+  out.tfirst.resize(nt);
+  for (int I = 0; I < nt; ++I) {
+    int f = I;
+    if (opt.dense_tiles) {
+      f = 0;
+    } else {
+      for (int k = I * TS; k < std::min(ni, (I + 1) * TS); ++k) f = std::min(f, S.mincol[k] / TS);
+    }
+    out.tfirst[I] = f;
+  }
+  if (nev > 0) {
+    std::sort(out.ext.begin(), out.ext.end());
+    out.ext_rowlen.resize(out.ext.size());
+    for (size_t q = 0; q < out.ext.size(); ++q) {
+      const int g = out.ext[q];
+      int cnt = 0;
+      for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+        const int c = ci[e];
+        if (loc[c] >= 0) {
+          out.ext_src.push_back((int)e);
+          out.ext_loc.push_back(loc[c]);
+          ++cnt;
+        }
+      }
+      out.ext_rowlen[q] = cnt;
+    }
+  }
+  for (int k = 0; k < ni; ++k) loc[out.dofs[k]] = -1;
+}
+
+#ifdef AMSP_PLAN_PROFILE
+#include <chrono>
+#include <cstdio>
+#define PTIME(label) do { auto t_ = std::chrono::steady_clock::now(); fprintf(stderr, "  %s %.1f ms\n", label, std::chrono::duration<double, std::milli>(t_ - tp_).count()); tp_ = t_; } while (0)
+#else
+#define PTIME(label) do { } while (0)
+#endif
+
+int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
+               const amsp_options &opt, HostPlan &P, std::string &msg) {
+#ifdef AMSP_PLAN_PROFILE
+  auto tp_ = std::chrono::steady_clock::now();
+#endif
+  const int n = (int)A->n;
+  const int N = nparts;
   P.n = n;
   P.N = N;
   P.nev = nev;
-  // cores: stable bucket by part
   std::vector<int> core_ptr(N + 1, 0), core(n);
   for (int j = 0; j < n; ++j) core_ptr[part[j] + 1]++;
   for (int i = 0; i < N; ++i) core_ptr[i + 1] += core_ptr[i];
@@ -201,167 +392,160 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
     std::vector<int> pos(core_ptr.begin(), core_ptr.end() - 1);
     for (int j = 0; j < n; ++j) core[pos[part[j]]++] = j;
   }
-  std::vector<int> stamp(n, -1), loc(n, -1);
-  P.sd_ptr.assign(1, 0);
-  P.sd_dofs.clear();
-  P.vp_ptr.assign(1, 0);
-  P.trow_ptr.assign(1, 0);
-  P.tfirst.clear();
-  P.toff.clear();
-  P.loc_rowptr.assign(1, 0);
-  P.loc_col.clear();
-  P.loc_src.clear();
-  P.mult.assign(n, 0);
+  std::vector<SubPlan> sub(N);
+  {
+    // one scratch per worker thread, handed out through a free list
+    std::mutex mu;
+    std::vector<std::unique_ptr<Scratch>> pool;
+    parallel_for(N, [&](int i) {
+      std::unique_ptr<Scratch> sc;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!pool.empty()) {
+          sc = std::move(pool.back());
+          pool.pop_back();
+        }
+      }
+      if (!sc) sc.reset(new Scratch(n));
+      plan_region(i, A, core_ptr, core, nev, opt, *sc, sub[i]);
+      std::lock_guard<std::mutex> lk(mu);
+      pool.push_back(std::move(sc));
+    });
+  }
+  PTIME("regions");
+  // concatenate in subdomain order: offsets first, then parallel copies
+  P.sd_ptr.assign(N + 1, 0);
+  P.vp_ptr.assign(N + 1, 0);
+  P.trow_ptr.assign(N + 1, 0);
   P.mi.assign(N, 0);
-  P.coff.assign(1, 0);
-  P.ext_ptr.assign(1, 0);
-  P.ext_rowptr.assign(1, 0);
-  P.ext_src.clear();
-  P.ext_loc.clear();
-  std::vector<int> ext_dofs;  // concatenated extended regions (ascending global)
-  long long tiles = 0;
+  P.coff.assign(N + 1, 0);
+  P.ext_ptr.assign(N + 1, 0);
+  std::vector<size_t> loc_off(N + 1, 0), exs_off(N + 1, 0);
+  std::vector<long long> tile_off(N + 1, 0);
+  for (int i = 0; i < N; ++i) {
+    const int ni = (int)sub[i].dofs.size();
+    const int nt = (int)sub[i].tfirst.size();
+    P.sd_ptr[i + 1] = P.sd_ptr[i] + ni;
+    P.vp_ptr[i + 1] = P.vp_ptr[i] + nt * TS;
+    P.trow_ptr[i + 1] = P.trow_ptr[i] + nt;
+    P.mi[i] = std::min(nev, ni);
+    P.coff[i + 1] = P.coff[i] + P.mi[i];
+    P.ext_ptr[i + 1] = P.ext_ptr[i] + (int)sub[i].ext.size();
+    loc_off[i + 1] = loc_off[i] + sub[i].lcol.size();
+    exs_off[i + 1] = exs_off[i] + sub[i].ext_src.size();
+    long long t = 0;
+    for (int I = 0; I < nt; ++I) t += I - sub[i].tfirst[I] + 1;
+    tile_off[i + 1] = tile_off[i] + t;
+  }
+  const int sum_ni = P.sd_ptr[N];
+  P.sd_dofs.resize(sum_ni);
+  P.loc_rowptr.assign(sum_ni + 1, 0);
+  P.loc_col.resize(loc_off[N]);
+  P.loc_src.resize(loc_off[N]);
+  P.tfirst.resize(P.trow_ptr[N]);
+  P.toff.resize(P.trow_ptr[N]);
+  P.ext_rowptr.assign(P.ext_ptr[N] + 1, 0);
+  P.ext_src.resize(exs_off[N]);
+  P.ext_loc.resize(exs_off[N]);
+  std::vector<int> ext_dofs(P.ext_ptr[N]);
+  parallel_for(N, [&](int i) {
+    SubPlan &S = sub[i];
+    const int r0 = P.sd_ptr[i], ni = (int)S.dofs.size();
+    int acc = (int)loc_off[i];
+    for (int k = 0; k < ni; ++k) {
+      P.sd_dofs[r0 + k] = S.dofs[k];
+      acc += S.rowlen[k];
+      P.loc_rowptr[r0 + k + 1] = acc;
+    }
+    std::copy(S.lcol.begin(), S.lcol.end(), P.loc_col.begin() + loc_off[i]);
+    std::copy(S.lsrc.begin(), S.lsrc.end(), P.loc_src.begin() + loc_off[i]);
+    const int g0 = P.trow_ptr[i];
+    long long t = tile_off[i];
+    for (size_t I = 0; I < S.tfirst.size(); ++I) {
+      P.tfirst[g0 + I] = S.tfirst[I];
+      P.toff[g0 + I] = t;
+      t += (long long)I - S.tfirst[I] + 1;
+    }
+    const int x0 = P.ext_ptr[i];
+    int eacc = (int)exs_off[i];
+    for (size_t q = 0; q < S.ext.size(); ++q) {
+      ext_dofs[x0 + q] = S.ext[q];
+      eacc += S.ext_rowlen[q];
+      P.ext_rowptr[x0 + q + 1] = eacc;
+    }
+    std::copy(S.ext_src.begin(), S.ext_src.end(), P.ext_src.begin() + exs_off[i]);
+    std::copy(S.ext_loc.begin(), S.ext_loc.end(), P.ext_loc.begin() + exs_off[i]);
+    std::vector<int>().swap(S.lcol);
+    std::vector<int>().swap(S.lsrc);
+    std::vector<int>().swap(S.ext_src);
+    std::vector<int>().swap(S.ext_loc);
+  });
   P.max_ni = 0;
   P.max_npad = 0;
-  std::vector<int> region, frontier, next, adj_ptr, adj, order, mincol;
   for (int i = 0; i < N; ++i) {
-    region.assign(core.begin() + core_ptr[i], core.begin() + core_ptr[i + 1]);
-    for (int g : region) stamp[g] = i;
-    frontier = region;
-    const int layers = delta + (nev > 0 ? 1 : 0);
-    size_t region_size = region.size();
-    for (int d = 0; d < layers; ++d) {
-      next.clear();
-      for (int g : frontier)
-        for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-          const int c = ci[e];
-          if (c != g && va[e] != 0.0 && stamp[c] != i) {
-            stamp[c] = i;
-            next.push_back(c);
-          }
-        }
-      region.insert(region.end(), next.begin(), next.end());
-      if (d == delta - 1) region_size = region.size();
-      frontier.swap(next);
-    }
-    if (delta == 0) region_size = core_ptr[i + 1] - core_ptr[i];
-    std::vector<int> ext(region.begin(), region.end());
-    region.resize(region_size);
-    std::sort(region.begin(), region.end());
-    const int ni = (int)region.size();
-    // local adjacency in ascending-global order
-    for (int k = 0; k < ni; ++k) loc[region[k]] = k;
-    adj_ptr.assign(ni + 1, 0);
-    adj.clear();
-    for (int k = 0; k < ni; ++k) {
-      const int g = region[k];
-      for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-        const int c = ci[e];
-        if (c != g && va[e] != 0.0 && loc[c] >= 0) adj.push_back(loc[c]);
-      }
-      adj_ptr[k + 1] = (int)adj.size();
-    }
-    if (opt.local_order == AMSP_ORDER_RCM) {
-      rcm_order(adj_ptr, adj, order);
-    } else {
-      order.resize(ni);
-      for (int k = 0; k < ni; ++k) order[k] = k;
-    }
-    // final local order: local index k -> global region[order[k]]
-    const int base = P.sd_ptr.back();
-    for (int k = 0; k < ni; ++k) {
-      const int g = region[order[k]];
-      P.sd_dofs.push_back(g);
-      loc[g] = k;
-      P.mult[g]++;
-    }
-    // local CSR in the final order
-    mincol.assign(ni, 0);
-    std::vector<std::pair<int, int>> row;
-    for (int k = 0; k < ni; ++k) {
-      const int g = P.sd_dofs[base + k];
-      row.clear();
-      for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-        const int c = ci[e];
-        if (loc[c] >= 0) row.emplace_back(loc[c], (int)e);
-      }
-      std::sort(row.begin(), row.end());
-      mincol[k] = row.empty() ? k : std::min(k, row.front().first);
-      for (auto &pr : row) {
-        P.loc_col.push_back(pr.first);
-        P.loc_src.push_back(pr.second);
-      }
-      P.loc_rowptr.push_back((int)P.loc_col.size());
-    }
-    // tile profile
-    const int nt = (ni + TS - 1) / TS;
-    for (int I = 0; I < nt; ++I) {
-      int f = I;
-      if (opt.dense_tiles) {
-        f = 0;
-      } else {
-        for (int k = I * TS; k < std::min(ni, (I + 1) * TS); ++k) f = std::min(f, mincol[k] / TS);
-      }
-      P.tfirst.push_back(f);
-      P.toff.push_back(tiles);
-      tiles += I - f + 1;
-    }
-    P.trow_ptr.push_back(P.trow_ptr.back() + nt);
-    P.sd_ptr.push_back(base + ni);
-    P.vp_ptr.push_back(P.vp_ptr.back() + nt * TS);
-    P.max_ni = std::max(P.max_ni, ni);
-    P.max_npad = std::max(P.max_npad, nt * TS);
-    const int m = std::min(nev, ni);
-    P.mi[i] = m;
-    P.coff.push_back(P.coff.back() + m);
-    // extended region (one more layer) for A Phi_i
-    if (nev > 0) {
-      std::sort(ext.begin(), ext.end());
-      for (int g : ext) {
-        ext_dofs.push_back(g);
-        for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-          const int c = ci[e];
-          if (loc[c] >= 0) {
-            P.ext_src.push_back((int)e);
-            P.ext_loc.push_back(loc[c]);
-          }
-        }
-        P.ext_rowptr.push_back((int)P.ext_src.size());
-      }
-      P.ext_ptr.push_back((int)ext_dofs.size());
-    }
-    for (int k = 0; k < ni; ++k) loc[P.sd_dofs[base + k]] = -1;
+    P.max_ni = std::max(P.max_ni, P.sd_ptr[i + 1] - P.sd_ptr[i]);
+    P.max_npad = std::max(P.max_npad, P.vp_ptr[i + 1] - P.vp_ptr[i]);
   }
-  P.ntiles = tiles;
-  P.nc = P.coff.back();
-  // inverse map: dof -> (subdomain, local index), subdomains ascending
-  P.inv_ptr.assign(n + 1, 0);
-  for (int j = 0; j < n; ++j) P.inv_ptr[j + 1] = P.inv_ptr[j] + P.mult[j];
-  const int tot = P.inv_ptr[n];
-  P.inv_sd.assign(tot, 0);
-  P.inv_loc.assign(tot, 0);
+  P.ntiles = tile_off[N];
+  P.nc = P.coff[N];
+  PTIME("concat");
+  // Multiplicities and the inverse map dof -> (subdomain, local index), with
+  // the subdomains of each dof in ascending order: contiguous subdomain
+  // chunks count their dofs, chunk offsets per dof follow by a prefix over
+  // chunks, then each chunk writes its entries in order.
   {
-    std::vector<int> pos(P.inv_ptr.begin(), P.inv_ptr.end() - 1);
-    for (int i = 0; i < N; ++i)
-      for (int k = P.sd_ptr[i]; k < P.sd_ptr[i + 1]; ++k) {
-        const int g = P.sd_dofs[k];
-        P.inv_sd[pos[g]] = i;
-        P.inv_loc[pos[g]] = k - P.sd_ptr[i];
-        pos[g]++;
+    const int nch = std::max(1, std::min(8, N));
+    std::vector<std::vector<int>> cnt(nch);
+    auto chunk_sd = [&](int c, int &i0, int &i1) {
+      i0 = (int)((long long)N * c / nch);
+      i1 = (int)((long long)N * (c + 1) / nch);
+    };
+    parallel_for(nch, [&](int c) {
+      cnt[c].assign(n, 0);
+      int i0, i1;
+      chunk_sd(c, i0, i1);
+      for (int k = P.sd_ptr[i0]; k < P.sd_ptr[i1]; ++k) cnt[c][P.sd_dofs[k]]++;
+    });
+    P.mult.assign(n, 0);
+    P.inv_ptr.assign(n + 1, 0);
+    for (int j = 0; j < n; ++j) {
+      int off = P.inv_ptr[j];
+      for (int c = 0; c < nch; ++c) {
+        const int v = cnt[c][j];
+        cnt[c][j] = off;  // becomes the chunk's write position for dof j
+        off += v;
       }
+      P.mult[j] = off - P.inv_ptr[j];
+      P.inv_ptr[j + 1] = off;
+    }
+    P.inv_sd.assign(P.inv_ptr[n], 0);
+    P.inv_loc.assign(P.inv_ptr[n], 0);
+    parallel_for(nch, [&](int c) {
+      int i0, i1;
+      chunk_sd(c, i0, i1);
+      std::vector<int> &pos = cnt[c];
+      for (int i = i0; i < i1; ++i)
+        for (int k = P.sd_ptr[i]; k < P.sd_ptr[i + 1]; ++k) {
+          const int g = P.sd_dofs[k];
+          P.inv_sd[pos[g]] = i;
+          P.inv_loc[pos[g]] = k - P.sd_ptr[i];
+          pos[g]++;
+        }
+    });
   }
   for (int j = 0; j < n; ++j)
     if (P.mult[j] == 0) {
       msg = "dof not covered by any region";
       return AMSP_ERR_PARTITION;
     }
-  // coupled subdomain pairs for A0
+  PTIME("inverse map");
+  // coupled subdomain pairs for A0, grouped by partner subdomain (ascending)
   P.pair_i.clear();
   P.pair_j.clear();
   P.pair_ptr.assign(1, 0);
   P.pair_l.clear();
   P.pair_e.clear();
   if (nev > 0 && P.nc > 0) {
-    // dof -> list of (j, e) with dof = ext_dofs[ext_ptr[j] + e]
     std::vector<int> xptr(n + 1, 0);
     for (int g : ext_dofs) xptr[g + 1]++;
     for (int j = 0; j < n; ++j) xptr[j + 1] += xptr[j];
@@ -376,32 +560,84 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
           pos[g]++;
         }
     }
-    std::vector<std::array<int, 3>> trip;
-    for (int i = 0; i < N; ++i) {
-      if (P.mi[i] == 0) continue;
-      trip.clear();
+    std::mutex mu;
+    std::vector<std::unique_ptr<std::vector<int>>> slots;
+    parallel_for(N, [&](int i) {
+      SubPlan &S = sub[i];
+      if (P.mi[i] == 0) return;
+      std::unique_ptr<std::vector<int>> sl;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!slots.empty()) {
+          sl = std::move(slots.back());
+          slots.pop_back();
+        }
+      }
+      if (!sl) sl.reset(new std::vector<int>(N, -1));
+      std::vector<int> &slot = *sl;
+      std::vector<int> js, counts;
       for (int k = P.sd_ptr[i]; k < P.sd_ptr[i + 1]; ++k) {
         const int g = P.sd_dofs[k];
-        for (int q = xptr[g]; q < xptr[g + 1]; ++q)
-          if (P.mi[xj[q]] > 0) trip.push_back({xj[q], k - P.sd_ptr[i], xe[q]});
-      }
-      std::stable_sort(trip.begin(), trip.end(),
-                       [](const std::array<int, 3> &a, const std::array<int, 3> &b) { return a[0] < b[0]; });
-      size_t s = 0;
-      while (s < trip.size()) {
-        size_t e = s;
-        while (e < trip.size() && trip[e][0] == trip[s][0]) ++e;
-        P.pair_i.push_back(i);
-        P.pair_j.push_back(trip[s][0]);
-        for (size_t u = s; u < e; ++u) {
-          P.pair_l.push_back(trip[u][1]);
-          P.pair_e.push_back(trip[u][2]);
+        for (int q = xptr[g]; q < xptr[g + 1]; ++q) {
+          const int j = xj[q];
+          if (P.mi[j] == 0) continue;
+          if (slot[j] < 0) {
+            slot[j] = (int)js.size();
+            js.push_back(j);
+            counts.push_back(0);
+          }
+          counts[slot[j]]++;
         }
-        P.pair_ptr.push_back((int)P.pair_l.size());
-        s = e;
       }
+      std::vector<int> order(js.size());
+      for (size_t u = 0; u < js.size(); ++u) order[u] = (int)u;
+      std::sort(order.begin(), order.end(), [&](int a, int b) { return js[a] < js[b]; });
+      std::vector<int> start(js.size());
+      int tot = 0;
+      for (int u : order) {
+        start[u] = tot;
+        tot += counts[u];
+        S.pair_j.push_back(js[u]);
+        S.pair_len.push_back(counts[u]);
+      }
+      S.pair_l.resize(tot);
+      S.pair_e.resize(tot);
+      for (int k = P.sd_ptr[i]; k < P.sd_ptr[i + 1]; ++k) {
+        const int g = P.sd_dofs[k];
+        for (int q = xptr[g]; q < xptr[g + 1]; ++q) {
+          const int j = xj[q];
+          if (P.mi[j] == 0) continue;
+          const int at = start[slot[j]]++;
+          S.pair_l[at] = k - P.sd_ptr[i];
+          S.pair_e[at] = xe[q];
+        }
+      }
+      for (int j : js) slot[j] = -1;
+      std::lock_guard<std::mutex> lk(mu);
+      slots.push_back(std::move(sl));
+    });
+    size_t npairs = 0, nent = 0;
+    for (int i = 0; i < N; ++i) {
+      npairs += sub[i].pair_j.size();
+      nent += sub[i].pair_l.size();
+    }
+    P.pair_i.reserve(npairs);
+    P.pair_j.reserve(npairs);
+    P.pair_ptr.reserve(npairs + 1);
+    P.pair_l.reserve(nent);
+    P.pair_e.reserve(nent);
+    for (int i = 0; i < N; ++i) {
+      SubPlan &S = sub[i];
+      for (size_t q = 0; q < S.pair_j.size(); ++q) {
+        P.pair_i.push_back(i);
+        P.pair_j.push_back(S.pair_j[q]);
+        P.pair_ptr.push_back(P.pair_ptr.back() + S.pair_len[q]);
+      }
+      P.pair_l.insert(P.pair_l.end(), S.pair_l.begin(), S.pair_l.end());
+      P.pair_e.insert(P.pair_e.end(), S.pair_e.begin(), S.pair_e.end());
     }
   }
+  PTIME("pairs");
   return AMSP_OK;
 }
 

@@ -62,6 +62,17 @@ inline void allow_lds(F *kernel, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// ---------------------------------------------------------------- MFMA ----
+// v_mfma_f64_16x16x4f64: D(16x16) = A(16x4) B(4x16) + C, wave64.
+// Lane l supplies A[l%16][l/16] and B[l/16][l%16]; D is returned in four
+// registers, D[l/16 + 4r][l%16] in register r (checked on the device by
+// amsp_selftest_mfma).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Copy a 64x64 row-major tile from global memory into padded LDS (coalesced).
 template <typename T>
 __device__ __forceinline__ void tile_to_lds(const T *__restrict__ g, double *lds) {

@@ -43,12 +43,12 @@ __global__ void __launch_bounds__(WG) k_eig_init(Plan p, const double *__restric
   }
 }
 
-// Cyclic Jacobi on the symmetric EIGP x EIGP matrix H (LDS, stride HP);
-// V accumulates the rotations.  Round-robin ordering: 8 disjoint pairs per
-// round, 15 rounds per sweep.
+// Cyclic Jacobi on the symmetric EIGP x EIGP matrix H (LDS, stride HP) by
+// one workgroup of any size; V accumulates the rotations.  Round-robin
+// ordering: EIGP/2 disjoint pairs per round, EIGP-1 rounds per sweep.
 __device__ void jacobi16(double *H, double *V, double *cs, int *flag) {
-  const int t = threadIdx.x;
-  for (int e = t; e < EIGP * EIGP; e += WG) V[(e / EIGP) * HP + e % EIGP] = (e / EIGP == e % EIGP) ? 1.0 : 0.0;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < EIGP * EIGP; e += nt) V[(e / EIGP) * HP + e % EIGP] = (e / EIGP == e % EIGP) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
     if (t == 0) {
@@ -92,8 +92,8 @@ __device__ void jacobi16(double *H, double *V, double *cs, int *flag) {
         cs[4 * t + 3] = (double)qq;
       }
       __syncthreads();
-      if (t < (EIGP / 2) * EIGP) {  // rows: H <- J^T H
-        const int pr = t / EIGP, k = t % EIGP;
+      for (int u = t; u < (EIGP / 2) * EIGP; u += nt) {  // rows: H <- J^T H
+        const int pr = u / EIGP, k = u % EIGP;
         const double c = cs[4 * pr], s = cs[4 * pr + 1];
         const int pp = (int)cs[4 * pr + 2], qq = (int)cs[4 * pr + 3];
         const double hp = H[pp * HP + k], hq = H[qq * HP + k];
@@ -101,44 +101,57 @@ __device__ void jacobi16(double *H, double *V, double *cs, int *flag) {
         H[qq * HP + k] = s * hp + c * hq;
       }
       __syncthreads();
-      if (t < (EIGP / 2) * EIGP) {  // columns: H <- H J
-        const int pr = t / EIGP, k = t % EIGP;
+      for (int u = t; u < 2 * (EIGP / 2) * EIGP; u += nt) {
+        const int half = (EIGP / 2) * EIGP;
+        const int v = u < half ? u : u - half;
+        const int pr = v / EIGP, k = v % EIGP;
         const double c = cs[4 * pr], s = cs[4 * pr + 1];
         const int pp = (int)cs[4 * pr + 2], qq = (int)cs[4 * pr + 3];
-        const double hp = H[k * HP + pp], hq = H[k * HP + qq];
-        H[k * HP + pp] = c * hp - s * hq;
-        H[k * HP + qq] = s * hp + c * hq;
-      } else if (t < EIGP * EIGP) {  // V <- V J
-        const int u = t - (EIGP / 2) * EIGP;
-        const int pr = u / EIGP, k = u % EIGP;
-        const double c = cs[4 * pr], s = cs[4 * pr + 1];
-        const int pp = (int)cs[4 * pr + 2], qq = (int)cs[4 * pr + 3];
-        const double vp = V[k * HP + pp], vq = V[k * HP + qq];
-        V[k * HP + pp] = c * vp - s * vq;
-        V[k * HP + qq] = s * vp + c * vq;
+        double *M = u < half ? H : V;  // columns of H (H <- H J), then V <- V J
+        const double hp = M[k * HP + pp], hq = M[k * HP + qq];
+        M[k * HP + pp] = c * hp - s * hq;
+        M[k * HP + qq] = s * hp + c * hq;
       }
       __syncthreads();
     }
   }
 }
 
-// G = Y^T Y style product of two row-major [n][EIGP] blocks into LDS (stride HP).
-__device__ void gram16(const double *__restrict__ A, const double *__restrict__ B, int n, double *G) {
-  const int a = threadIdx.x >> 4, b = threadIdx.x & 15;
-  double s = 0.0;
-  for (int l = 0; l < n; ++l) s = fma(A[(size_t)l * EIGP + a], B[(size_t)l * EIGP + b], s);
-  G[a * HP + b] = s;
+// G = A^T B for row-major [n][EIGP] blocks A, B into LDS (stride HP), with
+// WG threads: group g = t/EIGP sums rows g, g+EIGP, ... for row a = t%EIGP
+// of G (EIGP independent accumulators), then groups are added in order.
+// red: EIGP*EIGP*EIGP doubles of LDS.
+__device__ void gram16(const double *__restrict__ A, const double *__restrict__ B, int n, double *G,
+                       double *red) {
+  const int g = threadIdx.x / EIGP, a = threadIdx.x % EIGP;
+  double acc[EIGP];
+#pragma unroll
+  for (int b = 0; b < EIGP; ++b) acc[b] = 0.0;
+  for (int l = g; l < n; l += WG / EIGP) {
+    const double x = A[(size_t)l * EIGP + a];
+    const double *row = B + (size_t)l * EIGP;
+#pragma unroll
+    for (int b = 0; b < EIGP; ++b) acc[b] = fma(x, row[b], acc[b]);
+  }
+#pragma unroll
+  for (int b = 0; b < EIGP; ++b) red[(g * EIGP + a) * EIGP + b] = acc[b];
+  __syncthreads();
+  {
+    const int aa = threadIdx.x / EIGP, bb = threadIdx.x % EIGP;
+    double s = 0.0;
+    for (int gg = 0; gg < WG / EIGP; ++gg) s += red[(gg * EIGP + aa) * EIGP + bb];
+    G[aa * HP + bb] = s;
+  }
+  __syncthreads();
 }
 
-// In-place Y <- Y L^{-T} with G = L L^T (one CholQR pass).
-__device__ void cholqr_pass(double *__restrict__ Y, int n, double *G, double *Li) {
-  gram16(Y, Y, n, G);
-  __syncthreads();
+// In-place Y <- Y L^{-T} with G = Y^T Y = L L^T (one CholQR pass).
+__device__ void cholqr_pass(double *__restrict__ Y, int n, double *G, double *Li, double *red) {
+  gram16(Y, Y, n, G, red);
   if (threadIdx.x == 0) {
     double tr = 0.0;
     for (int a = 0; a < EIGP; ++a) tr += G[a * HP + a];
     const double floor_ = 1e-28 * (tr > 0.0 ? tr : 1.0);
-    // Cholesky G = L L^T (lower, in place)
     for (int k = 0; k < EIGP; ++k) {
       double d = G[k * HP + k];
       for (int j = 0; j < k; ++j) d -= G[k * HP + j] * G[k * HP + j];
@@ -151,7 +164,6 @@ __device__ void cholqr_pass(double *__restrict__ Y, int n, double *G, double *Li
         G[r * HP + k] = v / d;
       }
     }
-    // Li = L^{-1}
     for (int a = 0; a < EIGP; ++a)
       for (int b = 0; b < EIGP; ++b) Li[a * HP + b] = 0.0;
     for (int j = 0; j < EIGP; ++j) {
@@ -165,91 +177,114 @@ __device__ void cholqr_pass(double *__restrict__ Y, int n, double *G, double *Li
   }
   __syncthreads();
   for (int l = threadIdx.x; l < n; l += WG) {
-    double y[EIGP], o[EIGP];
+    // keep the LDS matrix in LDS: without this barrier the compiler hoists
+    // all of its entries into registers across the row loop and spills
+    __asm__ volatile("" ::: "memory");
+    double y[EIGP];
 #pragma unroll
     for (int k = 0; k < EIGP; ++k) y[k] = Y[(size_t)l * EIGP + k];
 #pragma unroll
-    for (int j = 0; j < EIGP; ++j) {
+    for (int j = EIGP - 1; j >= 0; --j) {
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k <= j; ++k) s = fma(y[k], Li[j * HP + k], s);
-      o[j] = s;
+      y[j] = s;  // y[k] for k < j is still the input row
     }
 #pragma unroll
-    for (int k = 0; k < EIGP; ++k) Y[(size_t)l * EIGP + k] = o[k];
+    for (int k = 0; k < EIGP; ++k) Y[(size_t)l * EIGP + k] = y[k];
   }
   __syncthreads();
 }
 
-// Rayleigh-Ritz step of the subspace iteration (see file header).
-__global__ void __launch_bounds__(WG) k_eig_rr(Plan p, const double *__restrict__ val,
-                                               const double *__restrict__ sdiag,
-                                               double *X, double *Y,
-                                               double *__restrict__ BQ, double tol,
-                                               int *__restrict__ conv, double *__restrict__ lam) {
+// Rayleigh-Ritz, part 1: CholQR2 orthonormalisation of the solve output Y.
+__global__ void __launch_bounds__(WG) k_eig_cholqr(Plan p, double *__restrict__ Y,
+                                                   const int *__restrict__ conv) {
   const int i = blockIdx.x;
   if (conv[i]) return;
-  __shared__ double H[EIGP * HP], V[EIGP * HP], Li[EIGP * HP];
-  __shared__ double cs[4 * EIGP / 2];
-  __shared__ double res[EIGP][WG / 64];
-  __shared__ int perm[EIGP];
-  __shared__ double theta[EIGP];
-  __shared__ int flag;
-  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
-  const int npad = p.vp_ptr[i + 1] - p.vp_ptr[i];
-  double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
+  const int ni = p.sd_ptr[i + 1] - p.sd_ptr[i];
+  if (ni <= EIGP) return;
+  __shared__ double G[EIGP * HP], Li[EIGP * HP];
+  __shared__ double red[EIGP * EIGP * EIGP];
   double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
-  double *Bi = BQ + (size_t)p.vp_ptr[i] * EIGP;
-  const int m = p.mi[i];
-  const int t = threadIdx.x;
-  const bool small = ni <= EIGP;
+  cholqr_pass(Yi, ni, G, Li, red);
+  cholqr_pass(Yi, ni, G, Li, red);
+}
 
-  if (small) {
-    // dense B_i (n_i <= EIGP) padded with a diagonal above the spectrum [0, 2]
+// Part 2: BQ = B_i Q with the sparse unit-diagonal B_i, and H = Q^T B_i Q
+// (symmetrised) into Hbuf[i][EIGP*EIGP].  Regions with n_i <= EIGP store
+// their dense B_i padded with a diagonal above the spectrum [0, 2].
+__global__ void __launch_bounds__(WG) k_eig_project(Plan p, const double *__restrict__ val,
+                                                    const double *__restrict__ sdiag,
+                                                    const double *__restrict__ Y,
+                                                    double *__restrict__ BQ,
+                                                    double *__restrict__ Hbuf,
+                                                    const int *__restrict__ conv) {
+  const int i = blockIdx.x;
+  if (conv[i]) return;
+  __shared__ double H[EIGP * HP];
+  __shared__ double red[EIGP * EIGP * EIGP];
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int t = threadIdx.x;
+  double *Hg = Hbuf + (size_t)i * EIGP * EIGP;
+  if (ni <= EIGP) {
     for (int e = t; e < EIGP * EIGP; e += WG) {
       const int a = e / EIGP, b = e % EIGP;
       H[a * HP + b] = (a == b) ? (a < ni ? 1.0 : 3.0 + a) : 0.0;
     }
     __syncthreads();
     if (t < ni) {
-      const int a = t;
-      const double sa = sdiag[r0 + a];
-      for (int e = p.loc_rowptr[r0 + a]; e < p.loc_rowptr[r0 + a + 1]; ++e) {
+      const double sa = sdiag[r0 + t];
+      for (int e = p.loc_rowptr[r0 + t]; e < p.loc_rowptr[r0 + t + 1]; ++e) {
         const int b = p.loc_col[e];
-        if (b != a) H[a * HP + b] = val[p.loc_src[e]] / sqrt(sa * sdiag[r0 + b]);
+        if (b != t) H[t * HP + b] = val[p.loc_src[e]] / sqrt(sa * sdiag[r0 + b]);
       }
     }
     __syncthreads();
-  } else {
-    cholqr_pass(Yi, ni, H, Li);
-    cholqr_pass(Yi, ni, H, Li);
-    // BQ = B_i Y (sparse, unit diagonal)
-    for (int l = t; l < ni; l += WG) {
-      double acc[EIGP];
-#pragma unroll
-      for (int k = 0; k < EIGP; ++k) acc[k] = Yi[(size_t)l * EIGP + k];
-      const double sl = sdiag[r0 + l];
-      for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
-        const int c = p.loc_col[e];
-        if (c == l) continue;
-        const double b = val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]);
-#pragma unroll
-        for (int k = 0; k < EIGP; ++k) acc[k] = fma(b, Yi[(size_t)c * EIGP + k], acc[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < EIGP; ++k) Bi[(size_t)l * EIGP + k] = acc[k];
-    }
-    __syncthreads();
-    gram16(Yi, Bi, ni, H);
-    __syncthreads();
-    {  // symmetrise
-      const int a = t >> 4, b = t & 15;
-      double hs = 0.5 * (H[a * HP + b] + H[b * HP + a]);
-      __syncthreads();
-      H[a * HP + b] = hs;
-    }
-    __syncthreads();
+    Hg[t] = H[(t / EIGP) * HP + t % EIGP];
+    return;
   }
+  const double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
+  double *Bi = BQ + (size_t)p.vp_ptr[i] * EIGP;
+  for (int l = t; l < ni; l += WG) {
+    double acc[EIGP];
+#pragma unroll
+    for (int k = 0; k < EIGP; ++k) acc[k] = Yi[(size_t)l * EIGP + k];
+    const double sl = sdiag[r0 + l];
+    for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
+      const int c = p.loc_col[e];
+      if (c == l) continue;
+      const double b = val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]);
+#pragma unroll
+      for (int k = 0; k < EIGP; ++k) acc[k] = fma(b, Yi[(size_t)c * EIGP + k], acc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < EIGP; ++k) Bi[(size_t)l * EIGP + k] = acc[k];
+  }
+  __syncthreads();
+  gram16(Yi, Bi, ni, H, red);
+  {
+    const int a = t / EIGP, b = t % EIGP;
+    Hg[t] = 0.5 * (H[a * HP + b] + H[b * HP + a]);
+  }
+}
+
+// Part 3: Jacobi eigendecomposition of H, one wavefront per region; writes the
+// eigenvector matrix with columns sorted by ascending eigenvalue into
+// Vbuf[i][EIGP*EIGP] (row-major) and the eigenvalues into Tbuf[i][EIGP].
+__global__ void __launch_bounds__(64) k_eig_jacobi(const double *__restrict__ Hbuf,
+                                                   double *__restrict__ Vbuf,
+                                                   double *__restrict__ Tbuf,
+                                                   const int *__restrict__ conv) {
+  const int i = blockIdx.x;
+  if (conv[i]) return;
+  __shared__ double H[EIGP * HP], V[EIGP * HP];
+  __shared__ double cs[4 * EIGP / 2];
+  __shared__ int perm[EIGP];
+  __shared__ double theta[EIGP];
+  __shared__ int flag;
+  const int t = threadIdx.x;
+  for (int e = t; e < EIGP * EIGP; e += 64) H[(e / EIGP) * HP + e % EIGP] = Hbuf[(size_t)i * EIGP * EIGP + e];
+  __syncthreads();
   jacobi16(H, V, cs, &flag);
   if (t == 0) {
     for (int a = 0; a < EIGP; ++a) {
@@ -270,17 +305,48 @@ __global__ void __launch_bounds__(WG) k_eig_rr(Plan p, const double *__restrict_
     }
   }
   __syncthreads();
-  const int nchk = (m + 1 < ni ? m + 1 : ni);  // pairs that must converge
+  for (int e = t; e < EIGP * EIGP; e += 64) {
+    const int k = e / EIGP, j = e % EIGP;
+    Vbuf[(size_t)i * EIGP * EIGP + e] = V[k * HP + perm[j]];
+  }
+  if (t < EIGP) Tbuf[(size_t)i * EIGP + t] = theta[t];
+}
+
+// Part 4: X = Q V, residual norms ||B x_j - theta_j x_j|| (with B Q V) for the
+// m_i + 1 lowest pairs, convergence flag and eigenvalues.
+__global__ void __launch_bounds__(WG) k_eig_update(Plan p, double *X, const double *Y,
+                                                   const double *__restrict__ BQ,
+                                                   const double *__restrict__ Vbuf,
+                                                   const double *__restrict__ Tbuf, double tol,
+                                                   int *__restrict__ conv,
+                                                   double *__restrict__ lam) {
+  const int i = blockIdx.x;
+  if (conv[i]) return;
+  __shared__ double V[EIGP * EIGP], theta[EIGP];
+  __shared__ double res[EIGP][WG / 64];
+  const int t = threadIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int npad = p.vp_ptr[i + 1] - p.vp_ptr[i];
+  const int m = p.mi[i];
+  V[t] = Vbuf[(size_t)i * EIGP * EIGP + t];
+  if (t < EIGP) theta[t] = Tbuf[(size_t)i * EIGP + t];
+  __syncthreads();
+  double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
+  const double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
+  const double *Bi = BQ + (size_t)p.vp_ptr[i] * EIGP;
+  const bool small = ni <= EIGP;
+  const int nchk = (m + 1 < ni ? m + 1 : ni);
+  double rs[EIGP];
+#pragma unroll
+  for (int j = 0; j < EIGP; ++j) rs[j] = 0.0;
   if (small) {
     for (int e = t; e < npad * EIGP; e += WG) {
       const int l = e / EIGP, j = e % EIGP;
-      Xi[e] = (l < ni) ? V[l * HP + perm[j]] : 0.0;
+      Xi[e] = (l < ni) ? V[l * EIGP + j] : 0.0;
     }
   } else {
-    double rs[EIGP];
-#pragma unroll
-    for (int j = 0; j < EIGP; ++j) rs[j] = 0.0;
     for (int l = t; l < ni; l += WG) {
+      __asm__ volatile("" ::: "memory");  // keep V in LDS (see cholqr_pass)
       double y[EIGP], b[EIGP];
 #pragma unroll
       for (int k = 0; k < EIGP; ++k) {
@@ -289,11 +355,10 @@ __global__ void __launch_bounds__(WG) k_eig_rr(Plan p, const double *__restrict_
       }
 #pragma unroll
       for (int j = 0; j < EIGP; ++j) {
-        const int pj = perm[j];
         double x = 0.0, bx = 0.0;
 #pragma unroll
         for (int k = 0; k < EIGP; ++k) {
-          const double v = V[k * HP + pj];
+          const double v = V[k * EIGP + j];
           x = fma(y[k], v, x);
           bx = fma(b[k], v, bx);
         }
@@ -302,12 +367,12 @@ __global__ void __launch_bounds__(WG) k_eig_rr(Plan p, const double *__restrict_
         rs[j] = fma(rr, rr, rs[j]);
       }
     }
-    const int lane = t & 63, w = t >> 6;
+  }
+  const int lane = t & 63, w = t >> 6;
 #pragma unroll
-    for (int j = 0; j < EIGP; ++j) {
-      double s = wave_sum(rs[j]);
-      if (lane == 0) res[j][w] = s;
-    }
+  for (int j = 0; j < EIGP; ++j) {
+    double s = wave_sum(rs[j]);
+    if (lane == 0) res[j][w] = s;
   }
   __syncthreads();
   if (t == 0) {
@@ -315,7 +380,7 @@ __global__ void __launch_bounds__(WG) k_eig_rr(Plan p, const double *__restrict_
     if (!small) {
       for (int j = 0; j < nchk; ++j) {
         double s = 0.0;
-        for (int w = 0; w < WG / 64; ++w) s += res[j][w];
+        for (int ww = 0; ww < WG / 64; ++ww) s += res[j][ww];
         s = sqrt(s);
         if (s > worst || !(s == s)) worst = (s == s) ? s : 1e300;
       }
@@ -412,8 +477,13 @@ void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *
 }
 
 void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag, double *X,
-                   double *Y, double *BQ, double tol, int *conv, double *lam) {
-  hipLaunchKernelGGL(k_eig_rr, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, X, Y, BQ, tol, conv, lam);
+                   double *BQ, double *Hbuf, double *Vbuf, double *Tbuf, double tol, int *conv,
+                   double *lam) {
+  hipLaunchKernelGGL(k_eig_cholqr, dim3(p.N), dim3(WG), 0, s, p, X, conv);
+  hipLaunchKernelGGL(k_eig_project, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, X, BQ, Hbuf, conv);
+  hipLaunchKernelGGL(k_eig_jacobi, dim3(p.N), dim3(64), 0, s, Hbuf, Vbuf, Tbuf, conv);
+  hipLaunchKernelGGL(k_eig_update, dim3(p.N), dim3(WG), 0, s, p, X, X, BQ, Vbuf, Tbuf, tol, conv,
+                     lam);
 }
 
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,

@@ -119,6 +119,24 @@ __global__ void __launch_bounds__(WG) k_residual(int n, const double *__restrict
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+// partial sums of (|A| |x|)_i^2: the scale of the rounding error of any
+// float64 residual f - A x (attainable-accuracy floor of the solve)
+__global__ void __launch_bounds__(WG) k_abs_spmv_sq(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const double *__restrict__ val,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ partial) {
+  __shared__ double sh[WG / 64];
+  double acc = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    double s = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) s = fma(fabs(val[e]), fabs(x[col[e]]), s);
+    acc = fma(s, s, acc);
+  }
+  double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
 __global__ void k_copy_scale(int n, const double *__restrict__ a, double *__restrict__ b,
                              double alpha) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -168,6 +186,7 @@ __global__ void __launch_bounds__(WG) k_pcg_init(PcgState *st, const double *prr
     st->rr = rr;
     st->rz = rz;
     st->rz_old = rz;
+    if (st->hist && st->it < st->hist_cap) st->hist[st->it] = rr;
     st->beta = 0.0;
     st->alpha = 0.0;
     int done = (rr <= st->tol2) ? 1 : 0;
@@ -206,6 +225,7 @@ __global__ void __launch_bounds__(WG) k_pcg_rr(PcgState *st, const double *parti
   if (threadIdx.x == 0) {
     st->rr = rr;
     st->it += 1;
+    if (st->hist && st->it < st->hist_cap) st->hist[st->it] = rr;
     if (!isfinite(rr)) {
       st->breakdown = 1;
       st->done = 1;
@@ -265,6 +285,12 @@ void launch_axpy_update_st(hipStream_t s, int n, double *x, double *r, const dou
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
                      double *partial) {
   hipLaunchKernelGGL(k_residual, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, f, Ax, r, partial);
+}
+
+void launch_abs_spmv_sq(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                        const double *x, double *partial) {
+  hipLaunchKernelGGL(k_abs_spmv_sq, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, rp, col, val, x,
+                     partial);
 }
 
 void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha) {

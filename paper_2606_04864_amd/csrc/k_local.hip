@@ -351,6 +351,109 @@ __global__ void __launch_bounds__(WG) k_profile_solve_block(Plan p, const T *__r
   }
 }
 
+// ------------------------------------ block solve on MFMA (EIGP rhs) ------
+// Same operation as k_profile_solve_block, one workgroup (4 wavefronts) per
+// region: wavefront w owns rows 16w..16w+15 of the 64 x EIGP block of the
+// current tile row.  A 64x64 tile times the 64x16 block is 16 MFMA steps;
+// K-slot q of step s stands for column k = 16q + s, so that each lane reads
+// 16 contiguous entries of one tile row (non-transposed products) and the
+// transposed products read 16 consecutive columns per instruction.
+template <typename T>
+__device__ __forceinline__ d4 mfma_tile_rhs(const T *__restrict__ tile, const double *rhs, int w,
+                                            int transpose, d4 acc, double sign) {
+  const int l = threadIdx.x & 63;
+  const int i = l & 15, q = l >> 4;
+  double a[16];
+  if (!transpose) {
+    const T *row = tile + (16 * w + i) * TS + 16 * q;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) a[s] = (double)row[s];
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) a[s] = (double)tile[(16 * q + s) * TS + 16 * w + i];
+  }
+#pragma unroll
+  for (int s = 0; s < 16; ++s) acc = mfma16x16x4(sign * a[s], rhs[(16 * q + s) * (EIGP + 1) + i], acc);
+  return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_profile_solve_block_mfma(Plan p, const T *__restrict__ tiles,
+                                                                 double *__restrict__ X,
+                                                                 const int *__restrict__ skip) {
+  const int i = blockIdx.x;
+  if (skip && skip[i]) return;
+  __shared__ double V[TS * (EIGP + 1)];    // right-hand block of a neighbour tile row
+  __shared__ double Acc[TS * (EIGP + 1)];  // current accumulated block
+  constexpr int LV = EIGP + 1;
+  const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
+  double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int col = l & 15, rb = 16 * w + (l >> 4);  // D register r: row rb + 4r, column col
+  auto load_block = [&](int J, double *dst) {
+    for (int e = threadIdx.x; e < TS * EIGP; e += WG) dst[(e / EIGP) * LV + (e % EIGP)] = Xi[(size_t)J * TS * EIGP + e];
+  };
+  // forward: Y_I = inv(L_II) (X_I - sum_J L_IJ Y_J)
+  for (int I = 0; I < nt; ++I) {
+    const int fI = p.tfirst[g0 + I];
+    const long long tI = p.toff[g0 + I];
+    d4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = Xi[(size_t)(I * TS + rb + 4 * r) * EIGP + col];
+    for (int J = fI; J < I; ++J) {
+      __syncthreads();
+      load_block(J, V);
+      __syncthreads();
+      acc = mfma_tile_rhs<T>(tiles + tile_elem(tI + (J - fI)), V, w, 0, acc, -1.0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Acc[(rb + 4 * r) * LV + col] = acc[r];
+    __syncthreads();
+    d4 y = {0.0, 0.0, 0.0, 0.0};
+    y = mfma_tile_rhs<T>(tiles + tile_elem(tI + (I - fI)), Acc, w, 0, y, 1.0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Xi[(size_t)(I * TS + rb + 4 * r) * EIGP + col] = y[r];
+    __syncthreads();
+  }
+  // backward: X_I = inv(L_II)^T (Y_I - sum_{J>I} L_JI^T X_J)
+  for (int I = nt - 1; I >= 0; --I) {
+    d4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = Xi[(size_t)(I * TS + rb + 4 * r) * EIGP + col];
+    for (int J = I + 1; J < nt; ++J) {
+      const int fJ = p.tfirst[g0 + J];
+      if (fJ > I) continue;
+      __syncthreads();
+      load_block(J, V);
+      __syncthreads();
+      acc = mfma_tile_rhs<T>(tiles + tile_elem(p.toff[g0 + J] + (I - fJ)), V, w, 1, acc, -1.0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Acc[(rb + 4 * r) * LV + col] = acc[r];
+    __syncthreads();
+    const int fI = p.tfirst[g0 + I];
+    d4 y = {0.0, 0.0, 0.0, 0.0};
+    y = mfma_tile_rhs<T>(tiles + tile_elem(p.toff[g0 + I] + (I - fI)), Acc, w, 1, y, 1.0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Xi[(size_t)(I * TS + rb + 4 * r) * EIGP + col] = y[r];
+    __syncthreads();
+  }
+}
+
+// Device self-test of the MFMA operand/result layout used above: D = A B
+// for A (16x4) and B (4x16) given row-major, D written row-major (16x16).
+__global__ void k_selftest_mfma(const double *A, const double *B, double *D) {
+  const int l = threadIdx.x;
+  d4 c = {0.0, 0.0, 0.0, 0.0};
+  c = mfma16x16x4(A[(l & 15) * 4 + (l >> 4)], B[(l >> 4) * 16 + (l & 15)], c);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) D[((l >> 4) + 4 * r) * 16 + (l & 15)] = c[r];
+}
+
+void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D) {
+  hipLaunchKernelGGL(k_selftest_mfma, dim3(1), dim3(64), 0, s, A, B, D);
+}
+
 // ------------------------------------------------------------ scatter -----
 // z[j] = sum over regions containing j of (local correction + Phi t) and the
 // partial r.z, in the fixed order of the inverse map (no atomics).
@@ -440,8 +543,7 @@ template void launch_local_apply_t<float, float, __hip_bfloat16>(hipStream_t, co
 template <typename T>
 void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, double *X,
                                 const int *skip) {
-  size_t sm = (size_t)(TS * LDT + 2 * TS * (EIGP + 1)) * sizeof(double);
-  hipLaunchKernelGGL((k_profile_solve_block<T>), dim3(p.N), dim3(WG), sm, s, p, tiles, X, skip);
+  hipLaunchKernelGGL((k_profile_solve_block_mfma<T>), dim3(p.N), dim3(WG), 0, s, p, tiles, X, skip);
 }
 template void launch_profile_solve_block<double>(hipStream_t, const Plan &, const double *,
                                                  double *, const int *);

@@ -1,0 +1,113 @@
+"""Parity at the benchmark's full size (gauss1024: n = 1,048,576, 1024 parts,
+2 overlap layers, 6 eigenvectors) in the configuration bench.py times.
+
+The oracle cannot run the whole problem in test time, so it checks samples it
+can compute one by one (local eigenpairs of sampled subdomains, the local
+solves hit by a vector supported on one core), and properties that hold at
+any size check the rest (A0 equals the Galerkin product of the exported
+basis, M^{-1} is symmetric and positive, PCG reaches the attainable residual).
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2606_04864_amd as P  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    w = W.get("gauss1024")
+    say("gauss1024 generated", w.n, w.nparts)
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, keep_a0=True)
+    say("setup", pc.info["phase_ms"][-1], "ms")
+    yield w, w.A.to_scipy(), pc
+    pc.close()
+
+
+def test_fullsize_eigen_samples(big):
+    w, A, pc = big
+    assert pc.info["eig_unconverged"] == 0
+    lam = pc.eigenvalues()
+    cores = O.cores(w.part, w.nparts)
+    for i in np.linspace(0, w.nparts - 1, 6).astype(int):
+        d = O.grow(A, cores[i], w.overlap)
+        Ah = O.neumann_matrix(O.local_matrix(A, d))
+        ref, _ = O.local_eigenpairs(Ah, O.weighting(Ah), w.nev, d)
+        np.testing.assert_allclose(lam[i, :len(ref)], ref, rtol=0, atol=1e-10)
+
+
+def test_fullsize_coarse_matrix_is_galerkin(big):
+    w, A, pc = big
+    rows, cols, vals = [], [], []
+    for i in range(w.nparts):
+        d, phi = pc.region(i)
+        for k in range(w.nev):
+            rows.append(d)
+            cols.append(np.full(len(d), i * w.nev + k))
+            vals.append(phi[:, k])
+    R0T = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                        shape=(w.n, w.nparts * w.nev))
+    ref = (R0T.T @ (A @ R0T)).toarray()
+    ref = 0.5 * (ref + ref.T)
+    A0 = pc.coarse_matrix()
+    assert np.abs(A0 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_fullsize_local_solves_sample(big):
+    w, A, pc = big
+    rng = np.random.default_rng(11)
+    cores = O.cores(w.part, w.nparts)
+    i = w.nparts // 3
+    r = np.zeros(w.n)
+    r[cores[i]] = rng.standard_normal(len(cores[i]))
+    z = pc.apply(torch.tensor(r, device="cuda"), parts=1)
+    torch.cuda.synchronize()
+    z = z.cpu().numpy()
+    ref = np.zeros(w.n)
+    hit = 0
+    for j in range(w.nparts):
+        d = O.grow(A, cores[j], w.overlap)
+        if not np.any(r[d]):
+            continue
+        hit += 1
+        ref[d] += sla.cho_solve(sla.cho_factor(O.local_matrix(A, d), lower=True), r[d])
+    assert hit >= 2
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_fullsize_symmetry_and_pcg(big):
+    w, A, pc = big
+    rng = np.random.default_rng(12)
+    x, y = rng.standard_normal(w.n), rng.standard_normal(w.n)
+    mx = pc.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    my = pc.apply(torch.tensor(y, device="cuda")).cpu().numpy()
+    assert abs(x @ my - y @ mx) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(my)
+    assert x @ mx > 0
+    f = torch.tensor(w.b, device="cuda")
+    u64, i64 = pc.pcg(f, 1e-8, 2000)
+    assert i64["converged"] == 1 and i64["relres_true"] <= max(1e-8, i64["relres_floor"])
+    say("fp64 pcg", i64["iterations"], i64["relres_true"], i64["relres_floor"])
+    pm = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision="fp32")
+    u32, i32 = pm.pcg(f, 1e-8, 2000)
+    assert i32["converged"] == 1 and i32["relres_true"] <= max(1e-8, i32["relres_floor"])
+    say("fp32 pcg", i32["iterations"], i32["relres_true"], i32["relres_floor"])
+    assert abs(i32["iterations"] - i64["iterations"]) <= max(3, 0.1 * i64["iterations"])
+    d = torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)
+    assert float(d) < 1e-5
+    pm.close()
