@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/amsp.h"
@@ -194,11 +195,52 @@ static amsp_status sync_status(amsp_handle *h, const int *dstatus, int N, int ma
   return AMSP_OK;
 }
 
+// Second planning phase (multiplicities, inverse map, extended regions,
+// coupled pairs) on a host thread while the device extracts, factors and
+// solves the local eigenproblems; joined before the first device use.
+struct CouplingTask {
+  std::thread th;
+  int status = AMSP_OK;
+  std::string msg;
+  bool joined = true;
+  void start(const amsp_csr *A, const amsp_options &opt, HostPlan *P) {
+    joined = false;
+    th = std::thread([this, A, opt, P]() {
+      try {
+        status = build_plan_coupling(A, opt, *P, msg);
+      } catch (const std::bad_alloc &) {
+        status = AMSP_ERR_OOM;
+        msg = "host allocation failed during planning";
+      }
+    });
+  }
+  int join() {
+    if (!joined) {
+      th.join();
+      joined = true;
+    }
+    return status;
+  }
+  ~CouplingTask() { join(); }
+};
+
+static amsp_status upload_coupling(amsp_handle *h);
+
 static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   HostPlan &P = h->hp;
   const bool mixed = h->opt.precision != AMSP_FP64;
   double t0 = now_ms();
   bool ok = true;
+  CouplingTask coupling;
+  coupling.start(A, h->opt, &P);
+  auto join_coupling = [&]() -> amsp_status {
+    const int cs = coupling.join();
+    if (cs != AMSP_OK) {
+      h->err = coupling.msg;
+      return (amsp_status)cs;
+    }
+    return upload_coupling(h);
+  };
   // --- upload matrix and plan
   {
     std::vector<int> rp32(h->n + 1);
@@ -227,25 +269,9 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   p.loc_src = upload(h, P.loc_src, ok);
   p.mi = upload(h, P.mi, ok);
   p.coff = upload(h, P.coff, ok);
-  p.mult = upload(h, P.mult, ok);
-  h->inv_ptr = upload(h, P.inv_ptr, ok);
-  h->inv_sd = upload(h, P.inv_sd, ok);
-  h->inv_loc = upload(h, P.inv_loc, ok);
   CoarsePlan &c = h->cplan;
   c.N = h->N;
   c.nev = h->nev;
-  if (h->nc > 0) {
-    c.ext_ptr = upload(h, P.ext_ptr, ok);
-    c.ext_rowptr = upload(h, P.ext_rowptr, ok);
-    c.ext_src = upload(h, P.ext_src, ok);
-    c.ext_loc = upload(h, P.ext_loc, ok);
-    c.npairs = (int)P.pair_i.size();
-    c.pair_i = upload(h, P.pair_i, ok);
-    c.pair_j = upload(h, P.pair_j, ok);
-    c.pair_ptr = upload(h, P.pair_ptr, ok);
-    c.pair_l = upload(h, P.pair_l, ok);
-    c.pair_e = upload(h, P.pair_e, ok);
-  }
   if (!ok) {
     h->err = "device allocation or upload failed (plan)";
     return AMSP_ERR_OOM;
@@ -297,14 +323,13 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   ALLOC(h->lam, double, (size_t)h->N * (h->nev + 1));
   launch_fill(h->stream, (size_t)h->N * (h->nev + 1), h->lam, std::nan(""));
   if (h->nev > 0) {
-    double *facB, *X, *BQ, *Hbuf, *Vbuf, *Tbuf;
+    double *facB, *X, *Yb, *GK, *CC;
     int *conv;
     ALLOC(facB, double, fac_elems);
     ALLOC(X, double, (size_t)sum_npad * EIGP);
-    ALLOC(BQ, double, (size_t)sum_npad * EIGP);
-    ALLOC(Hbuf, double, (size_t)h->N * EIGP * EIGP);
-    ALLOC(Vbuf, double, (size_t)h->N * EIGP * EIGP);
-    ALLOC(Tbuf, double, (size_t)h->N * EIGP);
+    ALLOC(Yb, double, (size_t)sum_npad * EIGP);
+    ALLOC(GK, double, (size_t)h->N * 2 * EIGP * EIGP);
+    ALLOC(CC, double, (size_t)h->N * (EIGP * EIGP + EIGP));
     ALLOC(conv, int, h->N);
     HIP_TRY(hipMemsetAsync(conv, 0, h->N * sizeof(int), h->stream));
     launch_extract_tiles(h->stream, p, h->ntilerows, h->val, h->sdiag, facB, 1, h->opt.eig_shift);
@@ -333,10 +358,10 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     int sweeps = 0, unconv = h->N;
     for (int it = 1; it <= h->opt.eig_maxit; ++it) {
       if (mixed)
-        launch_profile_solve_block<float>(h->stream, p, facB32, X, conv);
+        launch_profile_solve_block<float>(h->stream, p, facB32, X, Yb, conv);
       else
-        launch_profile_solve_block<double>(h->stream, p, facB, X, conv);
-      launch_eig_rr(h->stream, p, h->val, h->sdiag, X, BQ, Hbuf, Vbuf, Tbuf, tol, conv, h->lam);
+        launch_profile_solve_block<double>(h->stream, p, facB, X, Yb, conv);
+      launch_eig_rr(h->stream, p, h->val, h->sdiag, Yb, X, GK, CC, tol, conv, h->lam);
       sweeps = it;
       if (it >= 4 && (it % 2 == 0 || it == h->opt.eig_maxit)) {
         HIP_TRY(hipGetLastError());
@@ -353,6 +378,10 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     for (int v : hconv) unconv += (v == 0);
     h->sinfo.eig_sweeps = sweeps;
     h->sinfo.eig_unconverged = unconv;
+    {
+      const amsp_status js = join_coupling();
+      if (js != AMSP_OK) return js;
+    }
     ALLOC(h->phi64, double, (size_t)sum_ni * h->nev);
     launch_build_basis(h->stream, p, h->sdiag, X, h->phi64, h->opt.pou);
     HIP_TRY(hipGetLastError());
@@ -360,10 +389,9 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     if (facB) h->mem.free_one(facB);
     if (facB32) h->mem.free_one(facB32);
     h->mem.free_one(X);
-    h->mem.free_one(BQ);
-    h->mem.free_one(Hbuf);
-    h->mem.free_one(Vbuf);
-    h->mem.free_one(Tbuf);
+    h->mem.free_one(Yb);
+    h->mem.free_one(GK);
+    h->mem.free_one(CC);
     h->mem.free_one(conv);
     // gap flags and mu_c
     std::vector<double> lam((size_t)h->N * (h->nev + 1));
@@ -381,6 +409,10 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     }
     h->sinfo.mu_c = mu;
     h->sinfo.n_gap_flags = flags;
+  }
+  if (h->nev == 0) {
+    const amsp_status js = join_coupling();
+    if (js != AMSP_OK) return js;
   }
   double t4 = now_ms();
   h->sinfo.phase_ms[4] = t4 - t3;
@@ -490,6 +522,34 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   return AMSP_OK;
 }
 
+static amsp_status upload_coupling(amsp_handle *h) {
+  HostPlan &P = h->hp;
+  Plan &p = h->plan;
+  CoarsePlan &c = h->cplan;
+  bool ok = true;
+  p.mult = upload(h, P.mult, ok);
+  h->inv_ptr = upload(h, P.inv_ptr, ok);
+  h->inv_sd = upload(h, P.inv_sd, ok);
+  h->inv_loc = upload(h, P.inv_loc, ok);
+  if (h->nc > 0) {
+    c.ext_ptr = upload(h, P.ext_ptr, ok);
+    c.ext_rowptr = upload(h, P.ext_rowptr, ok);
+    c.ext_src = upload(h, P.ext_src, ok);
+    c.ext_loc = upload(h, P.ext_loc, ok);
+    c.npairs = (int)P.pair_i.size();
+    c.pair_i = upload(h, P.pair_i, ok);
+    c.pair_j = upload(h, P.pair_j, ok);
+    c.pair_ptr = upload(h, P.pair_ptr, ok);
+    c.pair_l = upload(h, P.pair_l, ok);
+    c.pair_e = upload(h, P.pair_e, ok);
+  }
+  if (!ok) {
+    h->err = "device allocation or upload failed (coupling plan)";
+    return AMSP_ERR_OOM;
+  }
+  return AMSP_OK;
+}
+
 extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, int32_t nparts,
                                   int32_t nev, const amsp_options *opt, amsp_handle **out) {
   if (!out) return AMSP_ERR_ARG;
@@ -520,7 +580,7 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
   h->nev = nev;
   double t0 = now_ms();
   try {
-    s = build_plan(A, partition, nparts, nev, o, h->hp, msg);
+    s = build_plan_local(A, partition, nparts, nev, o, h->hp, msg);
   } catch (const std::bad_alloc &) {
     s = AMSP_ERR_OOM;
     msg = "host allocation failed during planning";
@@ -656,7 +716,7 @@ static int64_t bytes_per_iter(const amsp_handle *h) {
     b += 2 * (int64_t)h->T0 * (h->T0 + 1) / 2 * TE * (mixed ? 4 : 8);  // coarse W0 twice
   }
   b += sni * (8 + 8) + n * 8 * 3;                   // scatter: inverse map, locals, z, r
-  if (h->opt.flexible) b += n * 16;
+  if (h->opt.flexible) b += n * 8;
   return b;
 }
 
@@ -729,9 +789,9 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
           tstop(h, 0, tk);
           tk = tstart(h);
           launch_pcg_alpha(h->stream, h->st, h->part_a, nb);
-          launch_axpy_update_st(h->stream, n, x, h->r, pnew, h->q, h->st, h->part_a);
+          launch_axpy_update_st(h->stream, n, x, h->r, pnew, h->q, h->st, h->part_a,
+                                h->opt.flexible ? h->z : nullptr, h->part_c);
           launch_pcg_rr(h->stream, h->st, h->part_a, nb);
-          if (h->opt.flexible) launch_dot(h->stream, n, h->r, h->z, h->part_c, done);
           tstop(h, 4, tk);
           s = apply_one(h, h->r, h->z, 3, h->part_b, done);
           if (s != AMSP_OK) return s;

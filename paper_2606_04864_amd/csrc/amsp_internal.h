@@ -45,7 +45,8 @@ void launch_spmv_pupdate_st(hipStream_t s, int n, const int *rp, const int *col,
 void launch_dot(hipStream_t s, int n, const double *a, const double *b, double *partial,
                 const int *done);
 void launch_axpy_update_st(hipStream_t s, int n, double *x, double *r, const double *p,
-                           const double *q, const PcgState *st, double *partial);
+                           const double *q, const PcgState *st, double *partial,
+                           const double *zold, double *partial_rzo);
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
                      double *partial);
 void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha);
@@ -78,10 +79,10 @@ template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
                           const T *tiles, const TB *phi, double *xloc, double *cvec, int do_local,
                           int do_coarse, const int *done);
-// In-place (L L^T)^{-1} X on row-major [rows][EIGP] padded blocks.
+// Y = (L L^T)^{-1} X on row-major [rows][EIGP] padded blocks (Y may equal X).
 template <typename T>
-void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, double *X,
-                                const int *skip);
+void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, const double *X,
+                                double *Y, const int *skip);
 void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D);
 template <typename TB>
 void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
@@ -91,11 +92,11 @@ void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *i
 
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
-// Rayleigh-Ritz step on the solve output held in X (in place): CholQR2,
-// projection H = Q^T B Q, Jacobi, X = Q V, residuals and convergence flags.
-// Hbuf, Vbuf: N*EIGP*EIGP doubles; Tbuf: N*EIGP doubles.
-void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag, double *X,
-                   double *BQ, double *Hbuf, double *Vbuf, double *Tbuf, double tol, int *conv,
+// Rayleigh-Ritz step on the solve output Y, writing the Ritz vectors into X
+// (distinct buffer), residuals, convergence flags and eigenvalues.
+// GK: N*2*EIGP*EIGP doubles; CC: N*(EIGP*EIGP+EIGP) doubles.
+void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
+                   const double *Y, double *X, double *GK, double *CC, double tol, int *conv,
                    double *lam);
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
                         double *phi, int pou);

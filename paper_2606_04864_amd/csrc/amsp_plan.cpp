@@ -265,9 +265,20 @@ struct Scratch {
 };
 }  // namespace
 
+#ifdef AMSP_PLAN_PROFILE
+#include <chrono>
+static double g_sec[8];
+#define SEC(k) do { auto t_ = std::chrono::steady_clock::now(); g_sec[k] += std::chrono::duration<double, std::milli>(t_ - ts_).count(); ts_ = t_; } while (0)
+#else
+#define SEC(k) do { } while (0)
+#endif
+
 static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_ptr,
                         const std::vector<int> &core, int nev, const amsp_options &opt,
                         Scratch &S, SubPlan &out) {
+#ifdef AMSP_PLAN_PROFILE
+  auto ts_ = std::chrono::steady_clock::now();
+#endif
   const int64_t *rp = A->row_ptr;
   const int32_t *ci = A->col_idx;
   const double *va = A->val;
@@ -275,7 +286,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   std::vector<int> region(core.begin() + core_ptr[i], core.begin() + core_ptr[i + 1]);
   for (int g : region) S.stamp[g] = i;
   S.frontier = region;
-  const int layers = delta + (nev > 0 ? 1 : 0);
+  const int layers = delta;
   size_t region_size = region.size();
   for (int d = 0; d < layers; ++d) {
     S.next.clear();
@@ -291,9 +302,9 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     if (d == delta - 1) region_size = region.size();
     S.frontier.swap(S.next);
   }
-  if (nev > 0) out.ext.assign(region.begin(), region.end());
   region.resize(region_size);
   std::sort(region.begin(), region.end());
+  SEC(0);
   const int ni = (int)region.size();
   std::vector<int> &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[region[k]] = k;
@@ -307,12 +318,14 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     }
     S.adj_ptr[k + 1] = (int)S.adj.size();
   }
+  SEC(1);
   if (opt.local_order == AMSP_ORDER_RCM) {
     rcm_order(S.adj_ptr, S.adj, S.order);
   } else {
     S.order.resize(ni);
     for (int k = 0; k < ni; ++k) S.order[k] = k;
   }
+  SEC(2);
   out.dofs.resize(ni);
   for (int k = 0; k < ni; ++k) {
     const int g = region[S.order[k]];
@@ -336,6 +349,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     }
     out.rowlen[k] = (int)S.row.size();
   }
+  SEC(3);
   const int nt = (ni + TS - 1) / TS;
   out.tfirst.resize(nt);
   for (int I = 0; I < nt; ++I) {
@@ -347,39 +361,89 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     }
     out.tfirst[I] = f;
   }
-  if (nev > 0) {
-    std::sort(out.ext.begin(), out.ext.end());
-    out.ext_rowlen.resize(out.ext.size());
-    for (size_t q = 0; q < out.ext.size(); ++q) {
-      const int g = out.ext[q];
-      int cnt = 0;
-      for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-        const int c = ci[e];
-        if (loc[c] >= 0) {
-          out.ext_src.push_back((int)e);
-          out.ext_loc.push_back(loc[c]);
-          ++cnt;
-        }
-      }
-      out.ext_rowlen[q] = cnt;
-    }
-  }
+  SEC(4);
   for (int k = 0; k < ni; ++k) loc[out.dofs[k]] = -1;
 }
 
+// Extended region of subdomain i (its region grown by one more layer) and
+// the entries of A coupling each extended row to the region (local indices).
+static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, SubPlan &out) {
+  const int64_t *rp = A->row_ptr;
+  const int32_t *ci = A->col_idx;
+  const double *va = A->val;
+  const int r0 = P.sd_ptr[i], ni = P.sd_ptr[i + 1] - r0;
+  std::vector<int> &loc = S.loc;
+  for (int k = 0; k < ni; ++k) loc[P.sd_dofs[r0 + k]] = k;
+  out.ext.assign(P.sd_dofs.begin() + r0, P.sd_dofs.begin() + r0 + ni);
+  for (int k = 0; k < ni; ++k) {
+    const int g = P.sd_dofs[r0 + k];
+    for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+      const int c = ci[e];
+      if (c != g && va[e] != 0.0 && loc[c] < 0 && S.stamp[c] != -(i + 2)) {
+        S.stamp[c] = -(i + 2);  // distinct from region-growth marks and from -1
+        out.ext.push_back(c);
+      }
+    }
+  }
+  std::sort(out.ext.begin(), out.ext.end());
+  out.ext_rowlen.resize(out.ext.size());
+  out.ext_src.clear();
+  out.ext_loc.clear();
+  out.ext_src.reserve(out.ext.size() * 4);
+  out.ext_loc.reserve(out.ext.size() * 4);
+  for (size_t q = 0; q < out.ext.size(); ++q) {
+    const int g = out.ext[q];
+    int cnt = 0;
+    for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
+      const int c = ci[e];
+      if (loc[c] >= 0) {
+        out.ext_src.push_back((int)e);
+        out.ext_loc.push_back(loc[c]);
+        ++cnt;
+      }
+    }
+    out.ext_rowlen[q] = cnt;
+  }
+  for (int k = 0; k < ni; ++k) loc[P.sd_dofs[r0 + k]] = -1;
+}
+
 #ifdef AMSP_PLAN_PROFILE
-#include <chrono>
 #include <cstdio>
 #define PTIME(label) do { auto t_ = std::chrono::steady_clock::now(); fprintf(stderr, "  %s %.1f ms\n", label, std::chrono::duration<double, std::milli>(t_ - tp_).count()); tp_ = t_; } while (0)
+#define PSTART auto tp_ = std::chrono::steady_clock::now()
 #else
 #define PTIME(label) do { } while (0)
+#define PSTART do { } while (0)
 #endif
 
-int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
-               const amsp_options &opt, HostPlan &P, std::string &msg) {
-#ifdef AMSP_PLAN_PROFILE
-  auto tp_ = std::chrono::steady_clock::now();
-#endif
+// Workers take scratch space (two n-sized index maps) from a shared pool.
+namespace {
+struct ScratchPool {
+  int n;
+  std::mutex mu;
+  std::vector<std::unique_ptr<Scratch>> pool;
+  explicit ScratchPool(int n_) : n(n_) {}
+  std::unique_ptr<Scratch> get() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!pool.empty()) {
+        auto s = std::move(pool.back());
+        pool.pop_back();
+        return s;
+      }
+    }
+    return std::unique_ptr<Scratch>(new Scratch(n));
+  }
+  void put(std::unique_ptr<Scratch> s) {
+    std::lock_guard<std::mutex> lk(mu);
+    pool.push_back(std::move(s));
+  }
+};
+}  // namespace
+
+int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
+                     const amsp_options &opt, HostPlan &P, std::string &msg) {
+  PSTART;
   const int n = (int)A->n;
   const int N = nparts;
   P.n = n;
@@ -394,33 +458,24 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
   }
   std::vector<SubPlan> sub(N);
   {
-    // one scratch per worker thread, handed out through a free list
-    std::mutex mu;
-    std::vector<std::unique_ptr<Scratch>> pool;
+    ScratchPool pool(n);
     parallel_for(N, [&](int i) {
-      std::unique_ptr<Scratch> sc;
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        if (!pool.empty()) {
-          sc = std::move(pool.back());
-          pool.pop_back();
-        }
-      }
-      if (!sc) sc.reset(new Scratch(n));
+      auto sc = pool.get();
       plan_region(i, A, core_ptr, core, nev, opt, *sc, sub[i]);
-      std::lock_guard<std::mutex> lk(mu);
-      pool.push_back(std::move(sc));
+      pool.put(std::move(sc));
     });
   }
   PTIME("regions");
-  // concatenate in subdomain order: offsets first, then parallel copies
+#ifdef AMSP_PLAN_PROFILE
+  fprintf(stderr, "   grow+sort %.1f adj %.1f rcm %.1f lcsr %.1f (thread-summed ms)\n", g_sec[0], g_sec[1], g_sec[2], g_sec[3]);
+  for (double &x : g_sec) x = 0;
+#endif
   P.sd_ptr.assign(N + 1, 0);
   P.vp_ptr.assign(N + 1, 0);
   P.trow_ptr.assign(N + 1, 0);
   P.mi.assign(N, 0);
   P.coff.assign(N + 1, 0);
-  P.ext_ptr.assign(N + 1, 0);
-  std::vector<size_t> loc_off(N + 1, 0), exs_off(N + 1, 0);
+  std::vector<size_t> loc_off(N + 1, 0);
   std::vector<long long> tile_off(N + 1, 0);
   for (int i = 0; i < N; ++i) {
     const int ni = (int)sub[i].dofs.size();
@@ -430,9 +485,7 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
     P.trow_ptr[i + 1] = P.trow_ptr[i] + nt;
     P.mi[i] = std::min(nev, ni);
     P.coff[i + 1] = P.coff[i] + P.mi[i];
-    P.ext_ptr[i + 1] = P.ext_ptr[i] + (int)sub[i].ext.size();
     loc_off[i + 1] = loc_off[i] + sub[i].lcol.size();
-    exs_off[i + 1] = exs_off[i] + sub[i].ext_src.size();
     long long t = 0;
     for (int I = 0; I < nt; ++I) t += I - sub[i].tfirst[I] + 1;
     tile_off[i + 1] = tile_off[i] + t;
@@ -444,10 +497,6 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
   P.loc_src.resize(loc_off[N]);
   P.tfirst.resize(P.trow_ptr[N]);
   P.toff.resize(P.trow_ptr[N]);
-  P.ext_rowptr.assign(P.ext_ptr[N] + 1, 0);
-  P.ext_src.resize(exs_off[N]);
-  P.ext_loc.resize(exs_off[N]);
-  std::vector<int> ext_dofs(P.ext_ptr[N]);
   parallel_for(N, [&](int i) {
     SubPlan &S = sub[i];
     const int r0 = P.sd_ptr[i], ni = (int)S.dofs.size();
@@ -466,19 +515,6 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
       P.toff[g0 + I] = t;
       t += (long long)I - S.tfirst[I] + 1;
     }
-    const int x0 = P.ext_ptr[i];
-    int eacc = (int)exs_off[i];
-    for (size_t q = 0; q < S.ext.size(); ++q) {
-      ext_dofs[x0 + q] = S.ext[q];
-      eacc += S.ext_rowlen[q];
-      P.ext_rowptr[x0 + q + 1] = eacc;
-    }
-    std::copy(S.ext_src.begin(), S.ext_src.end(), P.ext_src.begin() + exs_off[i]);
-    std::copy(S.ext_loc.begin(), S.ext_loc.end(), P.ext_loc.begin() + exs_off[i]);
-    std::vector<int>().swap(S.lcol);
-    std::vector<int>().swap(S.lsrc);
-    std::vector<int>().swap(S.ext_src);
-    std::vector<int>().swap(S.ext_loc);
   });
   P.max_ni = 0;
   P.max_npad = 0;
@@ -489,6 +525,14 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
   P.ntiles = tile_off[N];
   P.nc = P.coff[N];
   PTIME("concat");
+  (void)msg;
+  return AMSP_OK;
+}
+
+int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P, std::string &msg) {
+  PSTART;
+  (void)opt;
+  const int n = P.n, N = P.N, nev = P.nev;
   // Multiplicities and the inverse map dof -> (subdomain, local index), with
   // the subdomains of each dof in ascending order: contiguous subdomain
   // chunks count their dofs, chunk offsets per dof follow by a prefix over
@@ -539,13 +583,51 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
       return AMSP_ERR_PARTITION;
     }
   PTIME("inverse map");
-  // coupled subdomain pairs for A0, grouped by partner subdomain (ascending)
+  P.ext_ptr.assign(N + 1, 0);
+  P.ext_rowptr.assign(1, 0);
+  P.ext_src.clear();
+  P.ext_loc.clear();
   P.pair_i.clear();
   P.pair_j.clear();
   P.pair_ptr.assign(1, 0);
   P.pair_l.clear();
   P.pair_e.clear();
-  if (nev > 0 && P.nc > 0) {
+  if (nev == 0 || P.nc == 0) return AMSP_OK;
+  std::vector<SubPlan> sub(N);
+  {
+    ScratchPool pool(n);
+    parallel_for(N, [&](int i) {
+      auto sc = pool.get();
+      plan_ext(i, A, P, *sc, sub[i]);
+      pool.put(std::move(sc));
+    });
+  }
+  std::vector<size_t> exs_off(N + 1, 0);
+  for (int i = 0; i < N; ++i) {
+    P.ext_ptr[i + 1] = P.ext_ptr[i] + (int)sub[i].ext.size();
+    exs_off[i + 1] = exs_off[i] + sub[i].ext_src.size();
+  }
+  P.ext_rowptr.assign(P.ext_ptr[N] + 1, 0);
+  P.ext_src.resize(exs_off[N]);
+  P.ext_loc.resize(exs_off[N]);
+  std::vector<int> ext_dofs(P.ext_ptr[N]);
+  parallel_for(N, [&](int i) {
+    SubPlan &S = sub[i];
+    const int x0 = P.ext_ptr[i];
+    int eacc = (int)exs_off[i];
+    for (size_t q = 0; q < S.ext.size(); ++q) {
+      ext_dofs[x0 + q] = S.ext[q];
+      eacc += S.ext_rowlen[q];
+      P.ext_rowptr[x0 + q + 1] = eacc;
+    }
+    std::copy(S.ext_src.begin(), S.ext_src.end(), P.ext_src.begin() + exs_off[i]);
+    std::copy(S.ext_loc.begin(), S.ext_loc.end(), P.ext_loc.begin() + exs_off[i]);
+    std::vector<int>().swap(S.ext_src);
+    std::vector<int>().swap(S.ext_loc);
+  });
+  PTIME("ext regions");
+  // coupled subdomain pairs for A0, grouped by partner subdomain (ascending)
+  {
     std::vector<int> xptr(n + 1, 0);
     for (int g : ext_dofs) xptr[g + 1]++;
     for (int j = 0; j < n; ++j) xptr[j + 1] += xptr[j];
@@ -639,6 +721,13 @@ int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t n
   }
   PTIME("pairs");
   return AMSP_OK;
+}
+
+int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
+               const amsp_options &opt, HostPlan &P, std::string &msg) {
+  int s = build_plan_local(A, part, nparts, nev, opt, P, msg);
+  if (s != AMSP_OK) return s;
+  return build_plan_coupling(A, opt, P, msg);
 }
 
 }  // namespace amsp

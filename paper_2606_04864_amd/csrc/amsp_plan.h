@@ -24,6 +24,14 @@ struct HostPlan {
 
 int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
                     int32_t overlap, std::string &msg);
+// Regions, local orders, local CSR and tile profiles (everything the local
+// factorisations and eigensolves need).
+int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
+                     const amsp_options &opt, HostPlan &P, std::string &msg);
+// Multiplicities, inverse map, extended regions and coupled pairs (needed by
+// the basis, A0 and the apply); reads what build_plan_local produced.
+int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P, std::string &msg);
+// Both phases in order.
 int build_plan(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
                const amsp_options &opt, HostPlan &P, std::string &msg);
 

@@ -104,54 +104,43 @@ __device__ __forceinline__ double *tile_ptr(double *A, int T0, int I, int J) {
 __global__ void __launch_bounds__(WG) k_dense_potrf_diag(double *A0t, int T0, int k, double *dinv,
                                                          int *status) {
   extern __shared__ double lds[];
-  double *X = lds, *Y = lds + TS * LDT, *part = lds + 2 * TS * LDT;
+  double *X = lds, *Y = lds + TS * LDT;
   __shared__ int fail;
   if (threadIdx.x == 0) fail = 0;
-  __syncthreads();
   tile_to_lds(tile_ptr(A0t, T0, k, k), X);
   __syncthreads();
-  lds_potrf(X, &fail);
-  lds_trtri(X, Y, part);
+  lds_potrf_trtri(X, Y, &fail);
   lds_to_tile(X, tile_ptr(A0t, T0, k, k));
   lds_to_tile(Y, dinv + (size_t)k * TE);
   __syncthreads();
   if (threadIdx.x == 0 && fail) *status |= 1;
 }
 
-// L_ik = A_ik inv(L_kk)^T for i > k
+// L_ik = A_ik inv(L_kk)^T for i > k (each wavefront reads only its own rows
+// of A_ik before writing them, so the product can be formed in place)
 __global__ void __launch_bounds__(WG) k_dense_trsm_panel(double *A0t, int T0, int k,
                                                          const double *dinv) {
-  extern __shared__ double lds[];
-  double *X = lds, *Y = lds + TS * LDT;
   const int i = k + 1 + blockIdx.x;
   double *a = tile_ptr(A0t, T0, i, k);
-  tile_to_lds(a, X);
-  tile_to_lds(dinv + (size_t)k * TE, Y);
-  __syncthreads();
-  Blk o;
-  blk_abt(o, X, Y);
-  blk_store(o, a);
+  Acc4 o;
+  acc_zero(o);
+  acc_mma_abt(o, a, TS, dinv + (size_t)k * TE, TS, 1.0);
+  acc_store(o, a);
 }
 
 // A_ij -= L_ik L_jk^T for k < j <= i
 __global__ void __launch_bounds__(WG) k_dense_syrk_update(double *A0t, int T0, int k) {
-  extern __shared__ double lds[];
-  double *X = lds, *Y = lds + TS * LDT;
-  // blockIdx -> (i, j) in the lower triangle of the trailing (T0-k-1)^2 block
   const int b = blockIdx.x;
   int ii = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
   while ((ii + 1) * (ii + 2) / 2 <= b) ++ii;
   while (ii * (ii + 1) / 2 > b) --ii;
   const int jj = b - ii * (ii + 1) / 2;
   const int i = k + 1 + ii, j = k + 1 + jj;
-  tile_to_lds(tile_ptr(A0t, T0, i, k), X);
-  tile_to_lds(tile_ptr(A0t, T0, j, k), Y);
-  __syncthreads();
   double *c = tile_ptr(A0t, T0, i, j);
-  Blk o;
-  blk_load(o, c);
-  blk_sub_abt(o, X, Y);
-  blk_store(o, c);
+  Acc4 o;
+  acc_load(o, c);
+  acc_mma_abt(o, tile_ptr(A0t, T0, i, k), TS, tile_ptr(A0t, T0, j, k), TS, -1.0);
+  acc_store(o, c);
 }
 
 // Inverse factor by a right-looking solve of L X = I, step k:
@@ -160,31 +149,25 @@ __global__ void __launch_bounds__(WG) k_dense_syrk_update(double *A0t, int T0, i
 __global__ void __launch_bounds__(WG) k_dense_inv_row(double *Wt, int T0, int k,
                                                       const double *dinv) {
   extern __shared__ double lds[];
-  double *X = lds, *Y = lds + TS * LDT;
   const int j = blockIdx.x;  // 0..k
   double *w = tile_ptr(Wt, T0, k, j);
-  tile_to_lds(dinv + (size_t)k * TE, X);
-  tile_to_lds(w, Y);
+  tile_to_lds(w, lds);
   __syncthreads();
-  Blk o;
-  blk_ab(o, X, Y);
-  blk_store(o, w);
+  Acc4 o;
+  acc_zero(o);
+  acc_mma_ab(o, dinv + (size_t)k * TE, TS, lds, LDT, 1.0);
+  acc_store(o, w);
 }
 
 __global__ void __launch_bounds__(WG) k_dense_inv_update(const double *Lt, double *Wt, int T0,
                                                          int k) {
-  extern __shared__ double lds[];
-  double *X = lds, *Y = lds + TS * LDT;
   const int i = k + 1 + blockIdx.x / (k + 1);
   const int j = blockIdx.x % (k + 1);
-  tile_to_lds(Lt + ((size_t)i * T0 + k) * TE, X);
-  tile_to_lds(Wt + ((size_t)k * T0 + j) * TE, Y);
-  __syncthreads();
   double *c = tile_ptr(Wt, T0, i, j);
-  Blk o;
-  blk_load(o, c);
-  blk_sub_ab(o, X, Y);
-  blk_store(o, c);
+  Acc4 o;
+  acc_load(o, c);
+  acc_mma_ab(o, Lt + ((size_t)i * T0 + k) * TE, TS, Wt + ((size_t)k * T0 + j) * TE, TS, -1.0);
+  acc_store(o, c);
 }
 
 __global__ void k_tiles_identity(double *Wt, int T0) {
@@ -249,21 +232,27 @@ __global__ void __launch_bounds__(WG) k_trmv_tiles(const T *__restrict__ Wt, int
 }
 
 // y[O*64 + r] = sum over input tiles K (in order) of part[(O*T0 + K)*64 + r],
-// K ranging over J <= O (no transpose) or I >= O (transpose).
-__global__ void k_trmv_reduce(int T0, const double *__restrict__ part, double *__restrict__ y,
-                              int transpose, const int *__restrict__ done) {
+// K ranging over J <= O (no transpose) or I >= O (transpose).  Four threads
+// per output split the K range into fixed quarters, combined in order.
+__global__ void __launch_bounds__(WG) k_trmv_reduce(int T0, const double *__restrict__ part,
+                                                    double *__restrict__ y, int transpose,
+                                                    const int *__restrict__ done) {
   if (done && *done) return;
-  const int O = blockIdx.x, r = threadIdx.x;
+  __shared__ double red[4][TS];
+  const int O = blockIdx.x, r = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int k0 = transpose ? O : 0, k1 = transpose ? T0 : O + 1;
+  const int len = k1 - k0;
+  const int a = k0 + (len * g) / 4, b = k0 + (len * (g + 1)) / 4;
   double s = 0.0;
-  if (!transpose)
-    for (int K = 0; K <= O; ++K) s += part[((size_t)O * T0 + K) * TS + r];
-  else
-    for (int K = O; K < T0; ++K) s += part[((size_t)O * T0 + K) * TS + r];
-  y[O * TS + r] = s;
+  for (int K = a; K < b; ++K) s += part[((size_t)O * T0 + K) * TS + r];
+  red[g][r] = s;
+  __syncthreads();
+  if (g == 0) y[O * TS + r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
 }
 
 // ------------------------------------------------------------- launchers ---
-static size_t two_tiles_lds() { return (size_t)(2 * TS * LDT + 4 * TS) * sizeof(double); }
+static size_t two_tiles_lds() { return (size_t)(2 * TS * LDT) * sizeof(double); }
+static size_t one_tile_lds() { return (size_t)(TS * LDT) * sizeof(double); }
 
 void launch_apply_A_to_basis(hipStream_t s, const Plan &p, const CoarsePlan &c,
                              const double *val, const double *phi, double *W) {
@@ -292,29 +281,23 @@ void launch_dense_potrf_diag(hipStream_t s, double *A0t, int T0, int k, double *
 void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const double *dinv) {
   const int nb = T0 - k - 1;
   if (nb <= 0) return;
-  allow_lds(k_dense_trsm_panel, two_tiles_lds());
-  hipLaunchKernelGGL(k_dense_trsm_panel, dim3(nb), dim3(WG), two_tiles_lds(), s, A0t, T0, k, dinv);
+  hipLaunchKernelGGL(k_dense_trsm_panel, dim3(nb), dim3(WG), 0, s, A0t, T0, k, dinv);
 }
 
 void launch_dense_syrk_update(hipStream_t s, double *A0t, int T0, int k) {
   const int m = T0 - k - 1;
   if (m <= 0) return;
-  allow_lds(k_dense_syrk_update, two_tiles_lds());
-  hipLaunchKernelGGL(k_dense_syrk_update, dim3(m * (m + 1) / 2), dim3(WG), two_tiles_lds(), s, A0t,
-                     T0, k);
+  hipLaunchKernelGGL(k_dense_syrk_update, dim3(m * (m + 1) / 2), dim3(WG), 0, s, A0t, T0, k);
 }
 
 void launch_dense_inv_row(hipStream_t s, double *Wt, int T0, int k, const double *dinv) {
-  allow_lds(k_dense_inv_row, two_tiles_lds());
-  hipLaunchKernelGGL(k_dense_inv_row, dim3(k + 1), dim3(WG), two_tiles_lds(), s, Wt, T0, k, dinv);
+  hipLaunchKernelGGL(k_dense_inv_row, dim3(k + 1), dim3(WG), one_tile_lds(), s, Wt, T0, k, dinv);
 }
 
 void launch_dense_inv_update(hipStream_t s, const double *Lt, double *Wt, int T0, int k) {
   const int m = T0 - k - 1;
   if (m <= 0) return;
-  allow_lds(k_dense_inv_update, two_tiles_lds());
-  hipLaunchKernelGGL(k_dense_inv_update, dim3(m * (k + 1)), dim3(WG), two_tiles_lds(), s, Lt, Wt,
-                     T0, k);
+  hipLaunchKernelGGL(k_dense_inv_update, dim3(m * (k + 1)), dim3(WG), 0, s, Lt, Wt, T0, k);
 }
 
 void launch_tiles_identity(hipStream_t s, double *Wt, int T0) {
@@ -336,7 +319,7 @@ void launch_trmv(hipStream_t s, const T *Wt, int T0, const double *x, double *pa
                  int transpose, const int *done) {
   const int nb = T0 * (T0 + 1) / 2;
   hipLaunchKernelGGL((k_trmv_tiles<T>), dim3(nb), dim3(WG), 0, s, Wt, T0, x, part, transpose, done);
-  hipLaunchKernelGGL(k_trmv_reduce, dim3(T0), dim3(TS), 0, s, T0, part, y, transpose, done);
+  hipLaunchKernelGGL(k_trmv_reduce, dim3(T0), dim3(WG), 0, s, T0, part, y, transpose, done);
 }
 template void launch_trmv<double>(hipStream_t, const double *, int, const double *, double *,
                                   double *, int, const int *);

@@ -170,30 +170,117 @@ __device__ __forceinline__ void blk_ab(Blk &b, const double *X, const double *Y)
     for (int j = 0; j < 4; ++j) b.v[i][j] = -b.v[i][j];
 }
 
-// In-LDS Cholesky of the lower triangle of a 64x64 SPD tile (padded stride).
-// Non-positive pivots set *fail and are replaced by 1 so that the
-// factorisation always finishes with finite values.
-__device__ __forceinline__ void lds_potrf(double *a, int *fail) {
-  const int t = threadIdx.x;
-  for (int k = 0; k < TS; ++k) {
-    if (t == 0) {
-      double d = a[k * LDT + k];
-      if (!(d > 0.0) || !isfinite(d)) {
-        *fail = 1;
-        d = 1.0;
+// Synchronisation of the lanes of one wavefront around LDS traffic: LDS
+// operations of a wavefront complete in order; the fences keep the compiler
+// from moving loads or stores across the point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Blocked Cholesky of a 64x64 SPD tile and the inverse of its factor, in LDS.
+//   a (stride LDT): lower triangle of the tile on entry, L on exit (upper 0)
+//   w (stride LDT): inv(L) on exit (lower triangular)
+// 16x16 diagonal blocks are factored and inverted by wavefront 0 alone
+// (wave-level sync); panels, trailing updates and the off-diagonal blocks of
+// the inverse use the whole workgroup.  Non-positive pivots set *fail and are
+// replaced by 1 so that the factorisation ends with finite values.
+__device__ void lds_potrf_trtri(double *a, double *w, int *fail) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int e = t; e < TE; e += WG) w[(e >> 6) * LDT + (e & 63)] = 0.0;
+  for (int kb = 0; kb < 4; ++kb) {
+    const int k0 = 16 * kb;
+    if (wave == 0) {
+      for (int k = 0; k < 16; ++k) {
+        const int kk = k0 + k;
+        double d = a[kk * LDT + kk];
+        const bool bad = !(d > 0.0) || !isfinite(d);
+        d = bad ? 1.0 : sqrt(d);
+        wave_sync();
+        if (lane == 0) {
+          a[kk * LDT + kk] = d;
+          if (bad) *fail = 1;
+        }
+        if (lane > k && lane < 16) a[(k0 + lane) * LDT + kk] /= d;
+        wave_sync();
+        for (int e = lane; e < 256; e += 64) {
+          const int i = e >> 4, j = e & 15;
+          if (j > k && j <= i)
+            a[(k0 + i) * LDT + k0 + j] =
+                fma(-a[(k0 + i) * LDT + kk], a[(k0 + j) * LDT + kk], a[(k0 + i) * LDT + k0 + j]);
+        }
+        wave_sync();
       }
-      a[k * LDT + k] = sqrt(d);
+      // inverse of the 16x16 diagonal factor block, row by row
+      for (int i = 0; i < 16; ++i) {
+        if (lane <= i) {
+          const double lii = a[(k0 + i) * LDT + k0 + i];
+          double v;
+          if (lane == i) {
+            v = 1.0 / lii;
+          } else {
+            double s = 0.0;
+            for (int m = lane; m < i; ++m) s = fma(a[(k0 + i) * LDT + k0 + m], w[(k0 + m) * LDT + k0 + lane], s);
+            v = -s / lii;
+          }
+          w[(k0 + i) * LDT + k0 + lane] = v;
+        }
+        wave_sync();
+      }
     }
     __syncthreads();
-    if (t > k && t < TS) a[t * LDT + k] /= a[k * LDT + k];
+    // panel: L[r][c] = sum_{m <= c} A[r][m] inv(L_kk)[c][m] for rows below the block
+    const int nr = TS - k0 - 16;
+    double out[3];
+    int cnt = 0;
+    for (int e = t; e < nr * 16; e += WG) {
+      const int r = k0 + 16 + e / 16, c = e % 16;
+      double s = 0.0;
+      for (int m = 0; m <= c; ++m) s = fma(a[r * LDT + k0 + m], w[(k0 + c) * LDT + k0 + m], s);
+      out[cnt++] = s;
+    }
     __syncthreads();
-    for (int e = t; e < TE; e += WG) {
-      const int i = e >> 6, j = e & 63;
-      if (j > k && j <= i) a[i * LDT + j] = fma(-a[i * LDT + k], a[j * LDT + k], a[i * LDT + j]);
+    cnt = 0;
+    for (int e = t; e < nr * 16; e += WG) {
+      const int r = k0 + 16 + e / 16, c = e % 16;
+      a[r * LDT + k0 + c] = out[cnt++];
+    }
+    __syncthreads();
+    // trailing update of the lower triangle
+    for (int e = t; e < nr * nr; e += WG) {
+      const int r = k0 + 16 + e / nr, c = k0 + 16 + e % nr;
+      if (c <= r) {
+        double s = a[r * LDT + c];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) s = fma(-a[r * LDT + k0 + m], a[c * LDT + k0 + m], s);
+        a[r * LDT + c] = s;
+      }
     }
     __syncthreads();
   }
-  // clear the strict upper triangle
+  // off-diagonal blocks of the inverse: W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj,
+  // block rows in order; T_j is staged in the (unused) strict upper part of a
+  for (int ib = 1; ib < 4; ++ib) {
+    for (int e = t; e < ib * 256; e += WG) {
+      const int j = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      double s = 0.0;
+      for (int kb = j; kb < ib; ++kb)
+#pragma unroll 4
+        for (int m = 0; m < 16; ++m)
+          s = fma(a[(16 * ib + r) * LDT + 16 * kb + m], w[(16 * kb + m) * LDT + 16 * j + c], s);
+      a[(16 * j + r) * LDT + 16 * ib + c] = s;  // T_j (r, c) in upper block (j, ib)
+    }
+    __syncthreads();
+    for (int e = t; e < ib * 256; e += WG) {
+      const int j = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      double s = 0.0;
+      for (int m = 0; m <= r; ++m)
+        s = fma(w[(16 * ib + r) * LDT + 16 * ib + m], a[(16 * j + m) * LDT + 16 * ib + c], s);
+      w[(16 * ib + r) * LDT + 16 * j + c] = -s;
+    }
+    __syncthreads();
+  }
   for (int e = t; e < TE; e += WG) {
     const int i = e >> 6, j = e & 63;
     if (j > i) a[i * LDT + j] = 0.0;
@@ -201,32 +288,77 @@ __device__ __forceinline__ void lds_potrf(double *a, int *fail) {
   __syncthreads();
 }
 
-// x = inv(L) for lower-triangular L in LDS (both padded).  part: 4*64 doubles.
-__device__ __forceinline__ void lds_trtri(const double *L, double *x, double *part) {
-  const int t = threadIdx.x;
-  const int j = t & 63, seg = t >> 6;
-  for (int e = t; e < TE; e += WG) x[(e >> 6) * LDT + (e & 63)] = 0.0;
-  __syncthreads();
-  for (int i = 0; i < TS; ++i) {
-    // x[i][j] = -(sum_{k=j}^{i-1} L[i][k] x[k][j]) / L[i][i]  for j < i
-    double s = 0.0;
-    if (j < i) {
-      const int len = i - j;
-      const int k0 = j + (len * seg) / 4, k1 = j + (len * (seg + 1)) / 4;
-      for (int k = k0; k < k1; ++k) s = fma(L[i * LDT + k], x[k * LDT + j], s);
-    }
-    part[seg * TS + j] = s;
-    __syncthreads();
-    if (seg == 0) {
-      const double lii = L[i * LDT + i];
-      if (j < i) {
-        const double tot = (part[j] + part[TS + j]) + (part[2 * TS + j] + part[3 * TS + j]);
-        x[i * LDT + j] = -tot / lii;
-      } else if (j == i) {
-        x[i * LDT + i] = 1.0 / lii;
-      }
-    }
-    __syncthreads();
+// ------------------------------------------------ MFMA tile products ------
+// One 64x64 output tile per workgroup: wavefront w owns rows 16w..16w+15 as
+// four 16x16 MFMA blocks (acc[cb] = columns 16cb..).  K-slot q of MFMA step s
+// stands for k = 16q + s, so each lane reads 16 contiguous entries of a row.
+// Tiles are row-major 64x64 in global memory.
+struct Acc4 {
+  d4 v[4];
+};
+
+__device__ __forceinline__ void acc_load(Acc4 &c, const double *__restrict__ g) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c.v[cb][r] = g[(16 * wv + (l >> 4) + 4 * r) * TS + 16 * cb + (l & 15)];
+}
+
+__device__ __forceinline__ void acc_zero(Acc4 &c) {
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) c.v[cb] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+__device__ __forceinline__ void acc_store(const Acc4 &c, double *__restrict__ g) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) g[(16 * wv + (l >> 4) + 4 * r) * TS + 16 * cb + (l & 15)] = c.v[cb][r];
+}
+
+__device__ __forceinline__ void acc_to_lds(const Acc4 &c, double *lds) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lds[(16 * wv + (l >> 4) + 4 * r) * LDT + 16 * cb + (l & 15)] = c.v[cb][r];
+}
+
+// c += sign * X Y^T, X and Y with row stride ldx/ldy (global or LDS)
+__device__ __forceinline__ void acc_mma_abt(Acc4 &c, const double *X, int ldx, const double *Y,
+                                            int ldy, double sign) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = l & 15, q = l >> 4;
+  double xa[16];
+  const double *xr = X + (16 * wv + i) * ldx + 16 * q;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) xa[s] = sign * xr[s];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const double *yr = Y + (16 * cb + i) * ldy + 16 * q;
+    double yb[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) yb[s] = yr[s];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) c.v[cb] = mfma16x16x4(xa[s], yb[s], c.v[cb]);
+  }
+}
+
+// c += sign * X Y
+__device__ __forceinline__ void acc_mma_ab(Acc4 &c, const double *X, int ldx, const double *Y,
+                                           int ldy, double sign) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = l & 15, q = l >> 4;
+  double xa[16];
+  const double *xr = X + (16 * wv + i) * ldx + 16 * q;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) xa[s] = sign * xr[s];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) c.v[cb] = mfma16x16x4(xa[s], Y[(16 * q + s) * ldy + 16 * cb + i], c.v[cb]);
   }
 }
 

@@ -51,15 +51,17 @@ __device__ void jacobi16(double *H, double *V, double *cs, int *flag) {
   for (int e = t; e < EIGP * EIGP; e += nt) V[(e / EIGP) * HP + e % EIGP] = (e / EIGP == e % EIGP) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
-    if (t == 0) {
+    if (t < 64) {  // first wavefront: off-diagonal and total Frobenius norms
       double off = 0.0, tot = 0.0;
-      for (int a = 0; a < EIGP; ++a)
-        for (int b = 0; b < EIGP; ++b) {
-          const double h2 = H[a * HP + b] * H[a * HP + b];
-          tot += h2;
-          if (a != b) off += h2;
-        }
-      *flag = (off <= 1e-32 * tot) ? 1 : 0;
+      for (int e = t; e < EIGP * EIGP; e += 64) {
+        const int a = e / EIGP, b = e % EIGP;
+        const double h2 = H[a * HP + b] * H[a * HP + b];
+        tot += h2;
+        if (a != b) off += h2;
+      }
+      off = wave_sum(off);
+      tot = wave_sum(tot);
+      if (t == 0) *flag = (off <= 1e-32 * tot) ? 1 : 0;
     }
     __syncthreads();
     if (*flag) break;
@@ -117,173 +119,158 @@ __device__ void jacobi16(double *H, double *V, double *cs, int *flag) {
   }
 }
 
-// G = A^T B for row-major [n][EIGP] blocks A, B into LDS (stride HP), with
-// WG threads: group g = t/EIGP sums rows g, g+EIGP, ... for row a = t%EIGP
-// of G (EIGP independent accumulators), then groups are added in order.
-// red: EIGP*EIGP*EIGP doubles of LDS.
-__device__ void gram16(const double *__restrict__ A, const double *__restrict__ B, int n, double *G,
-                       double *red) {
-  const int g = threadIdx.x / EIGP, a = threadIdx.x % EIGP;
-  double acc[EIGP];
-#pragma unroll
-  for (int b = 0; b < EIGP; ++b) acc[b] = 0.0;
-  for (int l = g; l < n; l += WG / EIGP) {
-    const double x = A[(size_t)l * EIGP + a];
-    const double *row = B + (size_t)l * EIGP;
-#pragma unroll
-    for (int b = 0; b < EIGP; ++b) acc[b] = fma(x, row[b], acc[b]);
+// Rayleigh-Ritz on the span of the solve output Y (n_i x EIGP), without
+// forming an orthonormal basis: with G = Y^T Y = L L^T and K = Y^T B Y, the
+// Ritz problem is H = L^{-1} K L^{-T}, H V = V Theta, and the Ritz vectors
+// are X = Y C with C = L^{-T} V.  Two passes over Y per sweep.
+
+// B_i y for one local row l, 16 columns, from the sparse unit-diagonal B_i
+// (thread holds column a only: returns (B y)[l][a]).
+__device__ __forceinline__ double b_row_col(const Plan &p, const double *__restrict__ val,
+                                            const double *__restrict__ sdiag, const double *Y,
+                                            int r0, int l, int a) {
+  double acc = Y[(size_t)l * EIGP + a];
+  const double sl = sdiag[r0 + l];
+  for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
+    const int c = p.loc_col[e];
+    if (c == l) continue;
+    acc = fma(val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]), Y[(size_t)c * EIGP + a], acc);
   }
-#pragma unroll
-  for (int b = 0; b < EIGP; ++b) red[(g * EIGP + a) * EIGP + b] = acc[b];
-  __syncthreads();
-  {
-    const int aa = threadIdx.x / EIGP, bb = threadIdx.x % EIGP;
-    double s = 0.0;
-    for (int gg = 0; gg < WG / EIGP; ++gg) s += red[(gg * EIGP + aa) * EIGP + bb];
-    G[aa * HP + bb] = s;
-  }
-  __syncthreads();
+  return acc;
 }
 
-// In-place Y <- Y L^{-T} with G = Y^T Y = L L^T (one CholQR pass).
-__device__ void cholqr_pass(double *__restrict__ Y, int n, double *G, double *Li, double *red) {
-  gram16(Y, Y, n, G, red);
-  if (threadIdx.x == 0) {
-    double tr = 0.0;
-    for (int a = 0; a < EIGP; ++a) tr += G[a * HP + a];
-    const double floor_ = 1e-28 * (tr > 0.0 ? tr : 1.0);
-    for (int k = 0; k < EIGP; ++k) {
-      double d = G[k * HP + k];
-      for (int j = 0; j < k; ++j) d -= G[k * HP + j] * G[k * HP + j];
-      if (!(d > floor_)) d = floor_;
-      d = sqrt(d);
-      G[k * HP + k] = d;
-      for (int r = k + 1; r < EIGP; ++r) {
-        double v = G[r * HP + k];
-        for (int j = 0; j < k; ++j) v -= G[r * HP + j] * G[k * HP + j];
-        G[r * HP + k] = v / d;
-      }
-    }
-    for (int a = 0; a < EIGP; ++a)
-      for (int b = 0; b < EIGP; ++b) Li[a * HP + b] = 0.0;
-    for (int j = 0; j < EIGP; ++j) {
-      Li[j * HP + j] = 1.0 / G[j * HP + j];
-      for (int r = j + 1; r < EIGP; ++r) {
-        double s = 0.0;
-        for (int k = j; k < r; ++k) s += G[r * HP + k] * Li[k * HP + j];
-        Li[r * HP + j] = -s / G[r * HP + r];
-      }
-    }
-  }
-  __syncthreads();
-  for (int l = threadIdx.x; l < n; l += WG) {
-    // keep the LDS matrix in LDS: without this barrier the compiler hoists
-    // all of its entries into registers across the row loop and spills
-    __asm__ volatile("" ::: "memory");
-    double y[EIGP];
-#pragma unroll
-    for (int k = 0; k < EIGP; ++k) y[k] = Y[(size_t)l * EIGP + k];
-#pragma unroll
-    for (int j = EIGP - 1; j >= 0; --j) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k <= j; ++k) s = fma(y[k], Li[j * HP + k], s);
-      y[j] = s;  // y[k] for k < j is still the input row
-    }
-#pragma unroll
-    for (int k = 0; k < EIGP; ++k) Y[(size_t)l * EIGP + k] = y[k];
-  }
-  __syncthreads();
-}
-
-// Rayleigh-Ritz, part 1: CholQR2 orthonormalisation of the solve output Y.
-__global__ void __launch_bounds__(WG) k_eig_cholqr(Plan p, double *__restrict__ Y,
-                                                   const int *__restrict__ conv) {
+// Pass 1: G = Y^T Y and K = Y^T (B Y) into GK[i][2*EIGP*EIGP].  Thread
+// (group g, column a) handles rows g, g+16, ...; the 16 threads of a group
+// share one row's entries through lane shuffles.  Regions with n_i <= EIGP
+// store G = I and K = dense B_i padded with a diagonal above [0, 2].
+__global__ void __launch_bounds__(WG) k_eig_gram(Plan p, const double *__restrict__ val,
+                                                 const double *__restrict__ sdiag,
+                                                 const double *__restrict__ Y,
+                                                 double *__restrict__ GK,
+                                                 const int *__restrict__ conv) {
   const int i = blockIdx.x;
   if (conv[i]) return;
-  const int ni = p.sd_ptr[i + 1] - p.sd_ptr[i];
-  if (ni <= EIGP) return;
-  __shared__ double G[EIGP * HP], Li[EIGP * HP];
-  __shared__ double red[EIGP * EIGP * EIGP];
-  double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
-  cholqr_pass(Yi, ni, G, Li, red);
-  cholqr_pass(Yi, ni, G, Li, red);
-}
-
-// Part 2: BQ = B_i Q with the sparse unit-diagonal B_i, and H = Q^T B_i Q
-// (symmetrised) into Hbuf[i][EIGP*EIGP].  Regions with n_i <= EIGP store
-// their dense B_i padded with a diagonal above the spectrum [0, 2].
-__global__ void __launch_bounds__(WG) k_eig_project(Plan p, const double *__restrict__ val,
-                                                    const double *__restrict__ sdiag,
-                                                    const double *__restrict__ Y,
-                                                    double *__restrict__ BQ,
-                                                    double *__restrict__ Hbuf,
-                                                    const int *__restrict__ conv) {
-  const int i = blockIdx.x;
-  if (conv[i]) return;
-  __shared__ double H[EIGP * HP];
-  __shared__ double red[EIGP * EIGP * EIGP];
+  __shared__ double red[(WG / EIGP) * EIGP * EIGP];
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int t = threadIdx.x;
-  double *Hg = Hbuf + (size_t)i * EIGP * EIGP;
+  double *out = GK + (size_t)i * 2 * EIGP * EIGP;
   if (ni <= EIGP) {
-    for (int e = t; e < EIGP * EIGP; e += WG) {
-      const int a = e / EIGP, b = e % EIGP;
-      H[a * HP + b] = (a == b) ? (a < ni ? 1.0 : 3.0 + a) : 0.0;
+    const int a = t / EIGP, b = t % EIGP;
+    out[t] = (a == b) ? 1.0 : 0.0;
+    double h = (a == b) ? (a < ni ? 1.0 : 3.0 + a) : 0.0;
+    if (a < ni && b < ni && a != b) {
+      const double sa = sdiag[r0 + a];
+      for (int e = p.loc_rowptr[r0 + a]; e < p.loc_rowptr[r0 + a + 1]; ++e)
+        if (p.loc_col[e] == b) h = val[p.loc_src[e]] / sqrt(sa * sdiag[r0 + b]);
     }
-    __syncthreads();
-    if (t < ni) {
-      const double sa = sdiag[r0 + t];
-      for (int e = p.loc_rowptr[r0 + t]; e < p.loc_rowptr[r0 + t + 1]; ++e) {
-        const int b = p.loc_col[e];
-        if (b != t) H[t * HP + b] = val[p.loc_src[e]] / sqrt(sa * sdiag[r0 + b]);
-      }
-    }
-    __syncthreads();
-    Hg[t] = H[(t / EIGP) * HP + t % EIGP];
+    out[EIGP * EIGP + t] = h;
     return;
   }
   const double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
-  double *Bi = BQ + (size_t)p.vp_ptr[i] * EIGP;
-  for (int l = t; l < ni; l += WG) {
-    double acc[EIGP];
+  const int g = t / EIGP, a = t % EIGP;
+  double gacc[EIGP], kacc[EIGP];
 #pragma unroll
-    for (int k = 0; k < EIGP; ++k) acc[k] = Yi[(size_t)l * EIGP + k];
-    const double sl = sdiag[r0 + l];
-    for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
-      const int c = p.loc_col[e];
-      if (c == l) continue;
-      const double b = val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]);
+  for (int b = 0; b < EIGP; ++b) gacc[b] = kacc[b] = 0.0;
+  for (int l = g; l < ni; l += WG / EIGP) {
+    const double ya = Yi[(size_t)l * EIGP + a];
+    const double bya = b_row_col(p, val, sdiag, Yi, r0, l, a);
 #pragma unroll
-      for (int k = 0; k < EIGP; ++k) acc[k] = fma(b, Yi[(size_t)c * EIGP + k], acc[k]);
+    for (int b = 0; b < EIGP; ++b) {
+      const double yb = __shfl(ya, (threadIdx.x & 48) + b, 64);
+      const double byb = __shfl(bya, (threadIdx.x & 48) + b, 64);
+      gacc[b] = fma(ya, yb, gacc[b]);
+      kacc[b] = fma(ya, byb, kacc[b]);
     }
-#pragma unroll
-    for (int k = 0; k < EIGP; ++k) Bi[(size_t)l * EIGP + k] = acc[k];
   }
-  __syncthreads();
-  gram16(Yi, Bi, ni, H, red);
-  {
-    const int a = t / EIGP, b = t % EIGP;
-    Hg[t] = 0.5 * (H[a * HP + b] + H[b * HP + a]);
+  // fixed-order sums over the 16 row groups: G, then K
+  for (int m = 0; m < 2; ++m) {
+#pragma unroll
+    for (int b = 0; b < EIGP; ++b) red[(g * EIGP + a) * EIGP + b] = m == 0 ? gacc[b] : kacc[b];
+    __syncthreads();
+    {
+      const int aa = t / EIGP, bb = t % EIGP;
+      double s = 0.0;
+      for (int gg = 0; gg < WG / EIGP; ++gg) s += red[(gg * EIGP + aa) * EIGP + bb];
+      out[m * EIGP * EIGP + t] = s;
+    }
+    __syncthreads();
   }
 }
 
-// Part 3: Jacobi eigendecomposition of H, one wavefront per region; writes the
-// eigenvector matrix with columns sorted by ascending eigenvalue into
-// Vbuf[i][EIGP*EIGP] (row-major) and the eigenvalues into Tbuf[i][EIGP].
-__global__ void __launch_bounds__(64) k_eig_jacobi(const double *__restrict__ Hbuf,
-                                                   double *__restrict__ Vbuf,
-                                                   double *__restrict__ Tbuf,
-                                                   const int *__restrict__ conv) {
+// Pass 2 (small): L L^T = G, H = L^{-1} K L^{-T} (symmetrised), Jacobi,
+// C = L^{-T} V with columns sorted by ascending Ritz value.  One wavefront
+// per region.  CC[i] holds C (row-major EIGP x EIGP) then the Ritz values.
+__global__ void __launch_bounds__(64) k_eig_ritz(const double *__restrict__ GK,
+                                                 double *__restrict__ CC,
+                                                 const int *__restrict__ conv) {
   const int i = blockIdx.x;
   if (conv[i]) return;
-  __shared__ double H[EIGP * HP], V[EIGP * HP];
+  __shared__ double G[EIGP * HP], K[EIGP * HP], Li[EIGP * HP], H[EIGP * HP], V[EIGP * HP];
   __shared__ double cs[4 * EIGP / 2];
   __shared__ int perm[EIGP];
   __shared__ double theta[EIGP];
   __shared__ int flag;
+  __shared__ double floor_;
   const int t = threadIdx.x;
-  for (int e = t; e < EIGP * EIGP; e += 64) H[(e / EIGP) * HP + e % EIGP] = Hbuf[(size_t)i * EIGP * EIGP + e];
+  const double *in = GK + (size_t)i * 2 * EIGP * EIGP;
+  for (int e = t; e < EIGP * EIGP; e += 64) {
+    G[(e / EIGP) * HP + e % EIGP] = in[e];
+    K[(e / EIGP) * HP + e % EIGP] = in[EIGP * EIGP + e];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double tr = 0.0;
+    for (int a = 0; a < EIGP; ++a) tr += G[a * HP + a];
+    floor_ = 1e-26 * (tr > 0.0 ? tr : 1.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < EIGP; ++k) {  // Cholesky of G (lower, in place)
+    if (t == 0) {
+      double d = G[k * HP + k];
+      if (!(d > floor_)) d = floor_;
+      G[k * HP + k] = sqrt(d);
+    }
+    __syncthreads();
+    if (t > k && t < EIGP) G[t * HP + k] /= G[k * HP + k];
+    __syncthreads();
+    for (int e = t; e < EIGP * EIGP; e += 64) {
+      const int r = e / EIGP, c = e % EIGP;
+      if (c > k && c <= r) G[r * HP + c] = fma(-G[r * HP + k], G[c * HP + k], G[r * HP + c]);
+    }
+    __syncthreads();
+  }
+  if (t < EIGP) {  // Li = L^{-1}: lane j computes column j by forward substitution
+    const int j = t;
+    for (int r = 0; r < EIGP; ++r) Li[r * HP + j] = 0.0;
+    for (int r = j; r < EIGP; ++r) {
+      double s = (r == j) ? 1.0 : 0.0;
+      for (int m = j; m < r; ++m) s = fma(-G[r * HP + m], Li[m * HP + j], s);
+      Li[r * HP + j] = s / G[r * HP + r];
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < EIGP * EIGP; e += 64) {  // V <- Li K (temporary)
+    const int r = e / EIGP, c = e % EIGP;
+    double s = 0.0;
+    for (int m = 0; m <= r; ++m) s = fma(Li[r * HP + m], K[m * HP + c], s);
+    V[r * HP + c] = s;
+  }
+  __syncthreads();
+  for (int e = t; e < EIGP * EIGP; e += 64) {  // H = (Li K) Li^T
+    const int r = e / EIGP, c = e % EIGP;
+    double s = 0.0;
+    for (int m = 0; m <= c; ++m) s = fma(V[r * HP + m], Li[c * HP + m], s);
+    H[r * HP + c] = s;
+  }
+  __syncthreads();
+  for (int e = t; e < EIGP * EIGP; e += 64) {
+    const int r = e / EIGP, c = e % EIGP;
+    if (c > r) {
+      const double m = 0.5 * (H[r * HP + c] + H[c * HP + r]);
+      H[r * HP + c] = m;
+      H[c * HP + r] = m;
+    }
+  }
   __syncthreads();
   jacobi16(H, V, cs, &flag);
   if (t == 0) {
@@ -305,35 +292,40 @@ __global__ void __launch_bounds__(64) k_eig_jacobi(const double *__restrict__ Hb
     }
   }
   __syncthreads();
-  for (int e = t; e < EIGP * EIGP; e += 64) {
-    const int k = e / EIGP, j = e % EIGP;
-    Vbuf[(size_t)i * EIGP * EIGP + e] = V[k * HP + perm[j]];
+  double *out = CC + (size_t)i * (EIGP * EIGP + EIGP);
+  for (int e = t; e < EIGP * EIGP; e += 64) {  // C = Li^T V (sorted columns)
+    const int r = e / EIGP, c = e % EIGP;
+    double s = 0.0;
+    for (int m = r; m < EIGP; ++m) s = fma(Li[m * HP + r], V[m * HP + perm[c]], s);
+    out[e] = s;
   }
-  if (t < EIGP) Tbuf[(size_t)i * EIGP + t] = theta[t];
+  if (t < EIGP) out[EIGP * EIGP + t] = theta[t];
 }
 
-// Part 4: X = Q V, residual norms ||B x_j - theta_j x_j|| (with B Q V) for the
-// m_i + 1 lowest pairs, convergence flag and eigenvalues.
-__global__ void __launch_bounds__(WG) k_eig_update(Plan p, double *X, const double *Y,
-                                                   const double *__restrict__ BQ,
-                                                   const double *__restrict__ Vbuf,
-                                                   const double *__restrict__ Tbuf, double tol,
+// Pass 3: X = Y C, residuals ||B x_j - theta_j x_j|| from (B Y) C for the
+// m_i + 1 lowest pairs, convergence flags and eigenvalues.  Y and X must be
+// distinct buffers (neighbour rows of Y are read while X is written).
+__global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restrict__ val,
+                                                   const double *__restrict__ sdiag,
+                                                   const double *__restrict__ Y,
+                                                   double *__restrict__ X,
+                                                   const double *__restrict__ CC, double tol,
                                                    int *__restrict__ conv,
                                                    double *__restrict__ lam) {
   const int i = blockIdx.x;
   if (conv[i]) return;
-  __shared__ double V[EIGP * EIGP], theta[EIGP];
+  __shared__ double C[EIGP * EIGP], theta[EIGP];
   __shared__ double res[EIGP][WG / 64];
   const int t = threadIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int npad = p.vp_ptr[i + 1] - p.vp_ptr[i];
   const int m = p.mi[i];
-  V[t] = Vbuf[(size_t)i * EIGP * EIGP + t];
-  if (t < EIGP) theta[t] = Tbuf[(size_t)i * EIGP + t];
+  const double *in = CC + (size_t)i * (EIGP * EIGP + EIGP);
+  C[t] = in[t];
+  if (t < EIGP) theta[t] = in[EIGP * EIGP + t];
   __syncthreads();
   double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
   const double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
-  const double *Bi = BQ + (size_t)p.vp_ptr[i] * EIGP;
   const bool small = ni <= EIGP;
   const int nchk = (m + 1 < ni ? m + 1 : ni);
   double rs[EIGP];
@@ -342,25 +334,30 @@ __global__ void __launch_bounds__(WG) k_eig_update(Plan p, double *X, const doub
   if (small) {
     for (int e = t; e < npad * EIGP; e += WG) {
       const int l = e / EIGP, j = e % EIGP;
-      Xi[e] = (l < ni) ? V[l * EIGP + j] : 0.0;
+      Xi[e] = (l < ni) ? C[l * EIGP + j] : 0.0;
     }
   } else {
     for (int l = t; l < ni; l += WG) {
-      __asm__ volatile("" ::: "memory");  // keep V in LDS (see cholqr_pass)
-      double y[EIGP], b[EIGP];
+      __asm__ volatile("" ::: "memory");  // keep C in LDS (see cholqr_pass)
+      double y[EIGP], by[EIGP];
+      const double sl = sdiag[r0 + l];
 #pragma unroll
-      for (int k = 0; k < EIGP; ++k) {
-        y[k] = Yi[(size_t)l * EIGP + k];
-        b[k] = Bi[(size_t)l * EIGP + k];
+      for (int k = 0; k < EIGP; ++k) y[k] = by[k] = Yi[(size_t)l * EIGP + k];
+      for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
+        const int c = p.loc_col[e];
+        if (c == l) continue;
+        const double b = val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]);
+#pragma unroll
+        for (int k = 0; k < EIGP; ++k) by[k] = fma(b, Yi[(size_t)c * EIGP + k], by[k]);
       }
 #pragma unroll
       for (int j = 0; j < EIGP; ++j) {
         double x = 0.0, bx = 0.0;
 #pragma unroll
         for (int k = 0; k < EIGP; ++k) {
-          const double v = V[k * EIGP + j];
-          x = fma(y[k], v, x);
-          bx = fma(b[k], v, bx);
+          const double c = C[k * EIGP + j];
+          x = fma(y[k], c, x);
+          bx = fma(by[k], c, bx);
         }
         Xi[(size_t)l * EIGP + j] = x;
         const double rr = bx - theta[j] * x;
@@ -476,13 +473,12 @@ void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *
   hipLaunchKernelGGL(k_eig_init, dim3(p.N), dim3(WG), 0, s, p, sdiag, X);
 }
 
-void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag, double *X,
-                   double *BQ, double *Hbuf, double *Vbuf, double *Tbuf, double tol, int *conv,
+void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
+                   const double *Y, double *X, double *GK, double *CC, double tol, int *conv,
                    double *lam) {
-  hipLaunchKernelGGL(k_eig_cholqr, dim3(p.N), dim3(WG), 0, s, p, X, conv);
-  hipLaunchKernelGGL(k_eig_project, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, X, BQ, Hbuf, conv);
-  hipLaunchKernelGGL(k_eig_jacobi, dim3(p.N), dim3(64), 0, s, Hbuf, Vbuf, Tbuf, conv);
-  hipLaunchKernelGGL(k_eig_update, dim3(p.N), dim3(WG), 0, s, p, X, X, BQ, Vbuf, Tbuf, tol, conv,
+  hipLaunchKernelGGL(k_eig_gram, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, Y, GK, conv);
+  hipLaunchKernelGGL(k_eig_ritz, dim3(p.N), dim3(64), 0, s, GK, CC, conv);
+  hipLaunchKernelGGL(k_eig_finish, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, Y, X, CC, tol, conv,
                      lam);
 }
 

@@ -82,25 +82,33 @@ __global__ void __launch_bounds__(WG) k_dot(int n, const double *__restrict__ a,
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// x += alpha p; r -= alpha q; partial r.r
+// x += alpha p; r -= alpha q; partial r.r and, when zold is given, the
+// partial r_new.z_old used by the flexible (Polak-Ribiere) beta
 __global__ void __launch_bounds__(WG) k_axpy_update(int n, double *__restrict__ x,
                                                     double *__restrict__ r,
                                                     const double *__restrict__ p,
                                                     const double *__restrict__ q,
                                                     const PcgState *__restrict__ st,
-                                                    double *__restrict__ partial) {
+                                                    double *__restrict__ partial,
+                                                    const double *__restrict__ zold,
+                                                    double *__restrict__ partial_rzo) {
   if (st->done) return;
   __shared__ double sh[WG / 64];
   const double alpha = st->alpha;
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
   for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
     x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
     acc = fma(ri, ri, acc);
+    if (zold) acc2 = fma(ri, zold[i], acc2);
   }
   double tot = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+  if (zold) {
+    tot = block_sum(acc2, sh);
+    if (threadIdx.x == 0) partial_rzo[blockIdx.x] = tot;
+  }
 }
 
 // r = f - Ax, partial r.r
@@ -277,9 +285,10 @@ void launch_dot(hipStream_t s, int n, const double *a, const double *b, double *
 }
 
 void launch_axpy_update_st(hipStream_t s, int n, double *x, double *r, const double *p,
-                           const double *q, const PcgState *st, double *partial) {
+                           const double *q, const PcgState *st, double *partial,
+                           const double *zold, double *partial_rzo) {
   hipLaunchKernelGGL(k_axpy_update, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, x, r, p, q, st,
-                     partial);
+                     partial, zold, partial_rzo);
 }
 
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,

@@ -86,15 +86,14 @@ __global__ void __launch_bounds__(WG) k_extract_tiles(Plan p, int nrows_total,
 
 // ------------------------------------------------ batched Cholesky --------
 // One workgroup per region, left-looking over tile rows.  For tile (I,J):
-//   C = A_IJ - sum_K L_IK L_JK^T  (K over tiles present in both rows)
-//   J < I : L_IJ = C inv(L_JJ)^T
-//   J = I : L_II = chol(C); the tile then stores inv(L_II).
+//   C = A_IJ - sum_K L_IK L_JK^T  (K over tiles present in both rows; MFMA)
+//   J < I : L_IJ = C inv(L_JJ)^T   (MFMA)
+//   J = I : L_II = chol(C) in LDS; the tile then stores inv(L_II).
 __global__ void __launch_bounds__(WG) k_profile_cholesky(Plan p, double *__restrict__ tiles, int bit,
                                                          int *__restrict__ status) {
   extern __shared__ double lds[];
   double *X = lds;             // 64 x LDT
   double *Y = lds + TS * LDT;  // 64 x LDT
-  double *part = lds + 2 * TS * LDT;  // 4 x 64
   __shared__ int fail;
   const int i = blockIdx.x;
   const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
@@ -107,34 +106,25 @@ __global__ void __launch_bounds__(WG) k_profile_cholesky(Plan p, double *__restr
       const int fJ = p.tfirst[g0 + J];
       const long long tJ = p.toff[g0 + J];
       double *cij = tiles + tile_elem(tI + (J - fI));
-      Blk c;
-      blk_load(c, cij);
+      Acc4 c;
+      acc_load(c, cij);
       const int k0 = fI > fJ ? fI : fJ;
-      for (int K = k0; K < J; ++K) {
-        __syncthreads();
-        tile_to_lds(tiles + tile_elem(tI + (K - fI)), X);
-        tile_to_lds(tiles + tile_elem(tJ + (K - fJ)), Y);
-        __syncthreads();
-        blk_sub_abt(c, X, Y);
-      }
+      for (int K = k0; K < J; ++K)
+        acc_mma_abt(c, tiles + tile_elem(tI + (K - fI)), TS, tiles + tile_elem(tJ + (K - fJ)), TS, -1.0);
+      acc_to_lds(c, X);
       __syncthreads();
       if (J < I) {
-        blk_to_lds(c, X);
-        tile_to_lds(tiles + tile_elem(tJ + (J - fJ)), Y);  // inv(L_JJ)
-        __syncthreads();
-        Blk o;
-        blk_abt(o, X, Y);
-        blk_store(o, cij);
+        Acc4 o;
+        acc_zero(o);
+        acc_mma_abt(o, X, LDT, tiles + tile_elem(tJ + (J - fJ)), TS, 1.0);  // C inv(L_JJ)^T
+        acc_store(o, cij);
       } else {
-        blk_to_lds(c, X);
-        __syncthreads();
-        lds_potrf(X, &fail);
-        lds_trtri(X, Y, part);
+        lds_potrf_trtri(X, Y, &fail);
         lds_to_tile(Y, cij);
       }
+      __syncthreads();
     }
   }
-  __syncthreads();
   if (threadIdx.x == 0 && fail) status[i] |= bit;
 }
 
@@ -379,7 +369,7 @@ __device__ __forceinline__ d4 mfma_tile_rhs(const T *__restrict__ tile, const do
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_profile_solve_block_mfma(Plan p, const T *__restrict__ tiles,
-                                                                 double *__restrict__ X,
+                                                                 const double *Xin, double *X,
                                                                  const int *__restrict__ skip) {
   const int i = blockIdx.x;
   if (skip && skip[i]) return;
@@ -388,6 +378,7 @@ __global__ void __launch_bounds__(WG) k_profile_solve_block_mfma(Plan p, const T
   constexpr int LV = EIGP + 1;
   const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
   double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
+  const double *Xin_i = Xin + (size_t)p.vp_ptr[i] * EIGP;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = l & 15, rb = 16 * w + (l >> 4);  // D register r: row rb + 4r, column col
   auto load_block = [&](int J, double *dst) {
@@ -399,7 +390,7 @@ __global__ void __launch_bounds__(WG) k_profile_solve_block_mfma(Plan p, const T
     const long long tI = p.toff[g0 + I];
     d4 acc;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = Xi[(size_t)(I * TS + rb + 4 * r) * EIGP + col];
+    for (int r = 0; r < 4; ++r) acc[r] = Xin_i[(size_t)(I * TS + rb + 4 * r) * EIGP + col];
     for (int J = fI; J < I; ++J) {
       __syncthreads();
       load_block(J, V);
@@ -506,7 +497,7 @@ void launch_extract_tiles(hipStream_t s, const Plan &p, int ntilerows, const dou
 }
 
 void launch_profile_cholesky(hipStream_t s, const Plan &p, double *tiles, int *status, int bit) {
-  size_t sm = (size_t)(2 * TS * LDT + 4 * TS) * sizeof(double);
+  size_t sm = (size_t)(2 * TS * LDT) * sizeof(double);
   allow_lds(k_profile_cholesky, sm);
   hipLaunchKernelGGL(k_profile_cholesky, dim3(p.N), dim3(WG), sm, s, p, tiles, bit, status);
 }
@@ -541,14 +532,15 @@ template void launch_local_apply_t<float, float, __hip_bfloat16>(hipStream_t, co
                                                                  double *, int, int, const int *);
 
 template <typename T>
-void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, double *X,
-                                const int *skip) {
-  hipLaunchKernelGGL((k_profile_solve_block_mfma<T>), dim3(p.N), dim3(WG), 0, s, p, tiles, X, skip);
+void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, const double *X,
+                                double *Y, const int *skip) {
+  hipLaunchKernelGGL((k_profile_solve_block_mfma<T>), dim3(p.N), dim3(WG), 0, s, p, tiles, X, Y,
+                     skip);
 }
 template void launch_profile_solve_block<double>(hipStream_t, const Plan &, const double *,
-                                                 double *, const int *);
-template void launch_profile_solve_block<float>(hipStream_t, const Plan &, const float *, double *,
-                                                const int *);
+                                                 const double *, double *, const int *);
+template void launch_profile_solve_block<float>(hipStream_t, const Plan &, const float *,
+                                                const double *, double *, const int *);
 
 template <typename TB>
 void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
