@@ -51,6 +51,7 @@ def run_form(P, torch, w, f, prec, steps, warmup, timing):
             rec.append(dict(setup_ms=(t1 - t0) * 1e3, pcg_ms=(t2 - t1) * 1e3,
                             upload_ms=si["phase_ms"][1], plan_ms=si["phase_ms"][0],
                             phase_ms=si["phase_ms"], eig_sweeps=si["eig_sweeps"],
+                            coupling_ms=si["coupling_ms"], coupling_wait_ms=si["coupling_wait_ms"],
                             iterations=info["iterations"], relres_true=info["relres_true"],
                             kernel_ms=info["kernel_ms"], kernel_launches=info["kernel_launches"],
                             local_apply_bytes=info["local_apply_bytes"],
@@ -163,6 +164,7 @@ def main():
                     iterations=int(rec[-1]["iterations"]), relres_true=float(rec[-1]["relres_true"]),
                     eig_sweeps=int(rec[-1]["eig_sweeps"]),
                     setup_phase_ms=[round(x, 3) for x in rec[-1]["phase_ms"]],
+                    coupling_plan_ms=med("coupling_ms"), coupling_wait_ms=med("coupling_wait_ms"),
                     pcg_gbs=float(rec[-1]["bytes_per_iter"] * rec[-1]["iterations"]
                                   / (np.median([r["pcg_ms"] for r in rec]) * 1e-3) / 1e9))
 

@@ -128,6 +128,8 @@ typedef struct {
   double mu_c;              /* min_i lambda_{m_i+1}                                 */
   double phase_ms[8];       /* plan, upload, extract, local chol, eig, basis+A0,    */
                             /* coarse chol+inverse, total                           */
+  double coupling_ms;       /* host coupling-plan thread (overlaps device work)     */
+  double coupling_wait_ms;  /* time the device path waited for it                   */
 } amsp_setup_info;
 
 typedef struct amsp_handle amsp_handle;

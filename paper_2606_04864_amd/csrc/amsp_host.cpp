@@ -149,8 +149,9 @@ static void tstop(amsp_handle *h, int cls, int idx) {
     }                                                                     \
   } while (0)
 
-template <typename T>
-static T *upload(amsp_handle *h, const std::vector<T> &v, bool &ok) {
+template <typename V>
+static typename V::value_type *upload(amsp_handle *h, const V &v, bool &ok) {
+  using T = typename V::value_type;
   T *d = h->mem.alloc<T>(v.size());
   if (!d) {
     ok = false;
@@ -203,20 +204,25 @@ struct CouplingTask {
   int status = AMSP_OK;
   std::string msg;
   bool joined = true;
+  double run_ms = 0.0, wait_ms = 0.0;
   void start(const amsp_csr *A, const amsp_options &opt, HostPlan *P) {
     joined = false;
     th = std::thread([this, A, opt, P]() {
+      const double t = now_ms();
       try {
         status = build_plan_coupling(A, opt, *P, msg);
       } catch (const std::bad_alloc &) {
         status = AMSP_ERR_OOM;
         msg = "host allocation failed during planning";
       }
+      run_ms = now_ms() - t;
     });
   }
   int join() {
     if (!joined) {
+      const double t = now_ms();
       th.join();
+      wait_ms = now_ms() - t;
       joined = true;
     }
     return status;
@@ -235,6 +241,8 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   coupling.start(A, h->opt, &P);
   auto join_coupling = [&]() -> amsp_status {
     const int cs = coupling.join();
+    h->sinfo.coupling_ms = coupling.run_ms;
+    h->sinfo.coupling_wait_ms = coupling.wait_ms;
     if (cs != AMSP_OK) {
       h->err = coupling.msg;
       return (amsp_status)cs;

@@ -17,11 +17,69 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <thread>
+#include <unordered_map>
 
 namespace amsp {
+
+namespace {
+constexpr size_t kCacheMin = size_t(1) << 20;
+constexpr size_t kCacheCap = size_t(4) << 30;
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, void *> free_blocks;   // block size -> block
+  std::unordered_map<void *, size_t> live;     // block -> block size
+  size_t held = 0;
+};
+BlockCache &block_cache() {
+  static BlockCache *c = new BlockCache();  // never destroyed: blocks may be freed at exit
+  return *c;
+}
+}  // namespace
+
+void *plan_alloc(size_t bytes) {
+  if (bytes < kCacheMin) return ::operator new(bytes);
+  BlockCache &c = block_cache();
+  const size_t want = (bytes + kCacheMin - 1) & ~(kCacheMin - 1);
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.free_blocks.lower_bound(want);
+    if (it != c.free_blocks.end() && it->first <= 2 * want) {
+      void *p = it->second;
+      c.live[p] = it->first;
+      c.held -= it->first;
+      c.free_blocks.erase(it);
+      return p;
+    }
+  }
+  void *p = ::operator new(want);
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.live[p] = want;
+  return p;
+}
+
+void plan_free(void *p, size_t bytes) {
+  if (!p) return;
+  if (bytes < kCacheMin) {
+    ::operator delete(p);
+    return;
+  }
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.live.find(p);
+  const size_t sz = it->second;
+  c.live.erase(it);
+  if (c.held + sz <= kCacheCap) {
+    c.free_blocks.emplace(sz, p);
+    c.held += sz;
+  } else {
+    ::operator delete(p);
+  }
+}
 
 // Run fn(i) for i in [0, count) on up to `threads` workers (dynamic schedule).
 template <typename F>
@@ -45,6 +103,71 @@ static void parallel_for(int count, F fn) {
   work();
   for (auto &t : ts) t.join();
 }
+
+// fn(i) for i in [0, count) in 64 contiguous chunks: neighbouring subdomains
+// stay on one worker, so the index arrays they share rarely bounce between
+// cores.
+template <typename F>
+static void parallel_chunks(int count, F fn) {
+  const int nch = std::max(1, std::min(count, 64));
+  parallel_for(nch, [&](int c) {
+    const int a = (int)((long long)count * c / nch), b = (int)((long long)count * (c + 1) / nch);
+    for (int i = a; i < b; ++i) fn(i);
+  });
+}
+
+// ptr[0] = 0, ptr[j + 1] = ptr[j] + cnt[j] for j < n (chunked, in parallel).
+template <typename V1, typename V2>
+static void exclusive_scan(const V1 &cnt, V2 &ptr, int n) {
+  const int nch = 16;
+  std::vector<long long> part(nch + 1, 0);
+  auto rng = [&](int c, int &a, int &b) {
+    a = (int)((long long)n * c / nch);
+    b = (int)((long long)n * (c + 1) / nch);
+  };
+  parallel_for(nch, [&](int c) {
+    int a, b;
+    rng(c, a, b);
+    long long t = 0;
+    for (int j = a; j < b; ++j) t += cnt[j];
+    part[c + 1] = t;
+  });
+  for (int c = 0; c < nch; ++c) part[c + 1] += part[c];
+  ptr[0] = 0;
+  parallel_for(nch, [&](int c) {
+    int a, b;
+    rng(c, a, b);
+    long long t = part[c];
+    for (int j = a; j < b; ++j) {
+      t += cnt[j];
+      ptr[j + 1] = (int)t;
+    }
+  });
+}
+
+// Sort each list [ptr[j], ptr[j+1]) of (key, payload) pairs by key; keys in
+// a list are distinct, lists are short.
+template <typename V>
+static void sort_lists(const V &ptr, int n, V &key, V &pay) {
+  const int nch = 64;
+  parallel_for(nch, [&](int c) {
+    const int a = (int)((long long)n * c / nch), b = (int)((long long)n * (c + 1) / nch);
+    for (int j = a; j < b; ++j)
+      for (int x = ptr[j] + 1; x < ptr[j + 1]; ++x) {
+        const int kk = key[x], pp = pay[x];
+        int y = x;
+        while (y > ptr[j] && key[y - 1] > kk) {
+          key[y] = key[y - 1];
+          pay[y] = pay[y - 1];
+          --y;
+        }
+        key[y] = kk;
+        pay[y] = pp;
+      }
+  });
+}
+
+static inline int atomic_inc(int *x) { return __atomic_fetch_add(x, 1, __ATOMIC_RELAXED); }
 
 int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
                     int32_t overlap, std::string &msg) {
@@ -258,10 +381,14 @@ struct SubPlan {
 
 namespace {
 struct Scratch {
-  std::vector<int> stamp, loc;
+  ivec stamp, loc;  // stamp: visit marks (fresh value per use); loc: -1 between uses
+  int gen = 0;
   std::vector<int> frontier, next, adj_ptr, adj, order, mincol;
   std::vector<std::pair<int, int>> row;
-  explicit Scratch(int n) : stamp(n, -1), loc(n, -1) {}
+  explicit Scratch(int n) {
+    stamp.assign(n, -1);
+    loc.assign(n, -1);
+  }
 };
 }  // namespace
 
@@ -284,7 +411,8 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   const double *va = A->val;
   const int delta = opt.overlap;
   std::vector<int> region(core.begin() + core_ptr[i], core.begin() + core_ptr[i + 1]);
-  for (int g : region) S.stamp[g] = i;
+  const int mark = ++S.gen;
+  for (int g : region) S.stamp[g] = mark;
   S.frontier = region;
   const int layers = delta;
   size_t region_size = region.size();
@@ -293,8 +421,8 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     for (int g : S.frontier)
       for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
         const int c = ci[e];
-        if (c != g && va[e] != 0.0 && S.stamp[c] != i) {
-          S.stamp[c] = i;
+        if (c != g && va[e] != 0.0 && S.stamp[c] != mark) {
+          S.stamp[c] = mark;
           S.next.push_back(c);
         }
       }
@@ -306,7 +434,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   std::sort(region.begin(), region.end());
   SEC(0);
   const int ni = (int)region.size();
-  std::vector<int> &loc = S.loc;
+  ivec &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[region[k]] = k;
   S.adj_ptr.assign(ni + 1, 0);
   S.adj.clear();
@@ -334,20 +462,32 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   }
   S.mincol.assign(ni, 0);
   out.rowlen.resize(ni);
+  out.lcol.clear();
+  out.lsrc.clear();
+  out.lcol.reserve(S.adj.size() + ni);
+  out.lsrc.reserve(S.adj.size() + ni);
   for (int k = 0; k < ni; ++k) {
     const int g = out.dofs[k];
-    S.row.clear();
+    const size_t b = out.lcol.size();
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
       const int c = ci[e];
-      if (loc[c] >= 0) S.row.emplace_back(loc[c], (int)e);
+      if (loc[c] < 0) continue;
+      // insertion into the row's run, ascending local column (rows are short)
+      int lc = loc[c], ls = (int)e;
+      out.lcol.push_back(lc);
+      out.lsrc.push_back(ls);
+      size_t y = out.lcol.size() - 1;
+      while (y > b && out.lcol[y - 1] > lc) {
+        out.lcol[y] = out.lcol[y - 1];
+        out.lsrc[y] = out.lsrc[y - 1];
+        --y;
+      }
+      out.lcol[y] = lc;
+      out.lsrc[y] = ls;
     }
-    std::sort(S.row.begin(), S.row.end());
-    S.mincol[k] = S.row.empty() ? k : std::min(k, S.row.front().first);
-    for (auto &pr : S.row) {
-      out.lcol.push_back(pr.first);
-      out.lsrc.push_back(pr.second);
-    }
-    out.rowlen[k] = (int)S.row.size();
+    const int len = (int)(out.lcol.size() - b);
+    S.mincol[k] = len == 0 ? k : std::min(k, out.lcol[b]);
+    out.rowlen[k] = len;
   }
   SEC(3);
   const int nt = (ni + TS - 1) / TS;
@@ -372,15 +512,16 @@ static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, Su
   const int32_t *ci = A->col_idx;
   const double *va = A->val;
   const int r0 = P.sd_ptr[i], ni = P.sd_ptr[i + 1] - r0;
-  std::vector<int> &loc = S.loc;
+  ivec &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[P.sd_dofs[r0 + k]] = k;
   out.ext.assign(P.sd_dofs.begin() + r0, P.sd_dofs.begin() + r0 + ni);
+  const int mark = ++S.gen;
   for (int k = 0; k < ni; ++k) {
     const int g = P.sd_dofs[r0 + k];
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
       const int c = ci[e];
-      if (c != g && va[e] != 0.0 && loc[c] < 0 && S.stamp[c] != -(i + 2)) {
-        S.stamp[c] = -(i + 2);  // distinct from region-growth marks and from -1
+      if (c != g && va[e] != 0.0 && loc[c] < 0 && S.stamp[c] != mark) {
+        S.stamp[c] = mark;
         out.ext.push_back(c);
       }
     }
@@ -389,8 +530,8 @@ static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, Su
   out.ext_rowlen.resize(out.ext.size());
   out.ext_src.clear();
   out.ext_loc.clear();
-  out.ext_src.reserve(out.ext.size() * 4);
-  out.ext_loc.reserve(out.ext.size() * 4);
+  out.ext_src.reserve(out.ext.size() * 6);
+  out.ext_loc.reserve(out.ext.size() * 6);
   for (size_t q = 0; q < out.ext.size(); ++q) {
     const int g = out.ext[q];
     int cnt = 0;
@@ -492,7 +633,8 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
   }
   const int sum_ni = P.sd_ptr[N];
   P.sd_dofs.resize(sum_ni);
-  P.loc_rowptr.assign(sum_ni + 1, 0);
+  P.loc_rowptr.resize(sum_ni + 1);
+  P.loc_rowptr[0] = 0;
   P.loc_col.resize(loc_off[N]);
   P.loc_src.resize(loc_off[N]);
   P.tfirst.resize(P.trow_ptr[N]);
@@ -534,48 +676,30 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
   (void)opt;
   const int n = P.n, N = P.N, nev = P.nev;
   // Multiplicities and the inverse map dof -> (subdomain, local index), with
-  // the subdomains of each dof in ascending order: contiguous subdomain
-  // chunks count their dofs, chunk offsets per dof follow by a prefix over
-  // chunks, then each chunk writes its entries in order.
+  // the subdomains of each dof in ascending order: counts by atomic
+  // increments, offsets by a scan, unordered fill, then each dof's short
+  // list is ordered by subdomain.
   {
-    const int nch = std::max(1, std::min(8, N));
-    std::vector<std::vector<int>> cnt(nch);
-    auto chunk_sd = [&](int c, int &i0, int &i1) {
-      i0 = (int)((long long)N * c / nch);
-      i1 = (int)((long long)N * (c + 1) / nch);
-    };
-    parallel_for(nch, [&](int c) {
-      cnt[c].assign(n, 0);
-      int i0, i1;
-      chunk_sd(c, i0, i1);
-      for (int k = P.sd_ptr[i0]; k < P.sd_ptr[i1]; ++k) cnt[c][P.sd_dofs[k]]++;
-    });
     P.mult.assign(n, 0);
-    P.inv_ptr.assign(n + 1, 0);
-    for (int j = 0; j < n; ++j) {
-      int off = P.inv_ptr[j];
-      for (int c = 0; c < nch; ++c) {
-        const int v = cnt[c][j];
-        cnt[c][j] = off;  // becomes the chunk's write position for dof j
-        off += v;
-      }
-      P.mult[j] = off - P.inv_ptr[j];
-      P.inv_ptr[j + 1] = off;
-    }
-    P.inv_sd.assign(P.inv_ptr[n], 0);
-    P.inv_loc.assign(P.inv_ptr[n], 0);
-    parallel_for(nch, [&](int c) {
-      int i0, i1;
-      chunk_sd(c, i0, i1);
-      std::vector<int> &pos = cnt[c];
-      for (int i = i0; i < i1; ++i)
-        for (int k = P.sd_ptr[i]; k < P.sd_ptr[i + 1]; ++k) {
-          const int g = P.sd_dofs[k];
-          P.inv_sd[pos[g]] = i;
-          P.inv_loc[pos[g]] = k - P.sd_ptr[i];
-          pos[g]++;
-        }
+    parallel_chunks(N, [&](int i) {
+      for (int k = P.sd_ptr[i]; k < P.sd_ptr[i + 1]; ++k) atomic_inc(&P.mult[P.sd_dofs[k]]);
     });
+    P.inv_ptr.resize(n + 1);
+    exclusive_scan(P.mult, P.inv_ptr, n);
+    P.inv_sd.resize(P.inv_ptr[n]);
+    P.inv_loc.resize(P.inv_ptr[n]);
+    ivec fill;
+    fill.assign(n, 0);
+    parallel_chunks(N, [&](int i) {
+      const int r0 = P.sd_ptr[i];
+      for (int k = r0; k < P.sd_ptr[i + 1]; ++k) {
+        const int g = P.sd_dofs[k];
+        const int at = P.inv_ptr[g] + atomic_inc(&fill[g]);
+        P.inv_sd[at] = i;
+        P.inv_loc[at] = k - r0;
+      }
+    });
+    sort_lists(P.inv_ptr, n, P.inv_sd, P.inv_loc);
   }
   for (int j = 0; j < n; ++j)
     if (P.mult[j] == 0) {
@@ -607,10 +731,12 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
     P.ext_ptr[i + 1] = P.ext_ptr[i] + (int)sub[i].ext.size();
     exs_off[i + 1] = exs_off[i] + sub[i].ext_src.size();
   }
-  P.ext_rowptr.assign(P.ext_ptr[N] + 1, 0);
+  P.ext_rowptr.resize(P.ext_ptr[N] + 1);
+  P.ext_rowptr[0] = 0;
   P.ext_src.resize(exs_off[N]);
   P.ext_loc.resize(exs_off[N]);
-  std::vector<int> ext_dofs(P.ext_ptr[N]);
+  ivec ext_dofs;
+  ext_dofs.resize(P.ext_ptr[N]);
   parallel_for(N, [&](int i) {
     SubPlan &S = sub[i];
     const int x0 = P.ext_ptr[i];
@@ -628,20 +754,25 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
   PTIME("ext regions");
   // coupled subdomain pairs for A0, grouped by partner subdomain (ascending)
   {
-    std::vector<int> xptr(n + 1, 0);
-    for (int g : ext_dofs) xptr[g + 1]++;
-    for (int j = 0; j < n; ++j) xptr[j + 1] += xptr[j];
-    std::vector<int> xj(ext_dofs.size()), xe(ext_dofs.size());
-    {
-      std::vector<int> pos(xptr.begin(), xptr.end() - 1);
-      for (int j = 0; j < N; ++j)
-        for (int e = P.ext_ptr[j]; e < P.ext_ptr[j + 1]; ++e) {
-          const int g = ext_dofs[e];
-          xj[pos[g]] = j;
-          xe[pos[g]] = e - P.ext_ptr[j];
-          pos[g]++;
-        }
-    }
+    ivec xcnt, xptr, xj, xe;
+    xcnt.assign(n, 0);
+    parallel_chunks(N, [&](int j) {
+      for (int e = P.ext_ptr[j]; e < P.ext_ptr[j + 1]; ++e) atomic_inc(&xcnt[ext_dofs[e]]);
+    });
+    xptr.resize(n + 1);
+    exclusive_scan(xcnt, xptr, n);
+    xj.resize(ext_dofs.size());
+    xe.resize(ext_dofs.size());
+    std::fill(xcnt.begin(), xcnt.end(), 0);
+    parallel_chunks(N, [&](int j) {
+      for (int e = P.ext_ptr[j]; e < P.ext_ptr[j + 1]; ++e) {
+        const int g = ext_dofs[e];
+        const int at = xptr[g] + atomic_inc(&xcnt[g]);
+        xj[at] = j;
+        xe[at] = e - P.ext_ptr[j];
+      }
+    });
+    sort_lists(xptr, n, xj, xe);
     std::mutex mu;
     std::vector<std::unique_ptr<std::vector<int>>> slots;
     parallel_for(N, [&](int i) {
@@ -698,26 +829,29 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
       std::lock_guard<std::mutex> lk(mu);
       slots.push_back(std::move(sl));
     });
-    size_t npairs = 0, nent = 0;
+    std::vector<size_t> poff(N + 1, 0), eoff(N + 1, 0);
     for (int i = 0; i < N; ++i) {
-      npairs += sub[i].pair_j.size();
-      nent += sub[i].pair_l.size();
+      poff[i + 1] = poff[i] + sub[i].pair_j.size();
+      eoff[i + 1] = eoff[i] + sub[i].pair_l.size();
     }
-    P.pair_i.reserve(npairs);
-    P.pair_j.reserve(npairs);
-    P.pair_ptr.reserve(npairs + 1);
-    P.pair_l.reserve(nent);
-    P.pair_e.reserve(nent);
-    for (int i = 0; i < N; ++i) {
+    P.pair_i.resize(poff[N]);
+    P.pair_j.resize(poff[N]);
+    P.pair_ptr.resize(poff[N] + 1);
+    P.pair_ptr[0] = 0;
+    P.pair_l.resize(eoff[N]);
+    P.pair_e.resize(eoff[N]);
+    parallel_for(N, [&](int i) {
       SubPlan &S = sub[i];
+      size_t acc = eoff[i];
       for (size_t q = 0; q < S.pair_j.size(); ++q) {
-        P.pair_i.push_back(i);
-        P.pair_j.push_back(S.pair_j[q]);
-        P.pair_ptr.push_back(P.pair_ptr.back() + S.pair_len[q]);
+        P.pair_i[poff[i] + q] = i;
+        P.pair_j[poff[i] + q] = S.pair_j[q];
+        acc += S.pair_len[q];
+        P.pair_ptr[poff[i] + q + 1] = (int)acc;
       }
-      P.pair_l.insert(P.pair_l.end(), S.pair_l.begin(), S.pair_l.end());
-      P.pair_e.insert(P.pair_e.end(), S.pair_e.begin(), S.pair_e.end());
-    }
+      std::copy(S.pair_l.begin(), S.pair_l.end(), P.pair_l.begin() + eoff[i]);
+      std::copy(S.pair_e.begin(), S.pair_e.end(), P.pair_e.begin() + eoff[i]);
+    });
   }
   PTIME("pairs");
   return AMSP_OK;

@@ -1,7 +1,9 @@
 // Host index planner (integer work) shared by the library's setup.
 #pragma once
 #include <array>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/amsp.h"
@@ -9,17 +11,51 @@
 
 namespace amsp {
 
+// Host blocks of 1 MiB and more are recycled through a process-wide cache
+// (at most 4 GiB held), so repeated setups do not pay fresh page faults for
+// their index arrays; smaller requests go to operator new.
+void *plan_alloc(size_t bytes);
+void plan_free(void *p, size_t bytes);
+
+// Allocator whose resize() leaves new elements uninitialised (large index
+// arrays are first written by the threads that fill them), backed by the
+// recycling cache above.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U> &) {}
+  T *allocate(size_t n) { return static_cast<T *>(plan_alloc(n * sizeof(T))); }
+  void deallocate(T *p, size_t n) { plan_free(p, n * sizeof(T)); }
+  template <typename U>
+  void construct(U *p) noexcept {
+    ::new ((void *)p) U;
+  }
+  template <typename U, typename... Args>
+  void construct(U *p, Args &&...args) {
+    ::new ((void *)p) U(std::forward<Args>(args)...);
+  }
+};
+using ivec = std::vector<int, NoInitAlloc<int>>;
+
 struct HostPlan {
   int n = 0, N = 0, nev = 0, nc = 0;
   int max_ni = 0, max_npad = 0;
   long long ntiles = 0;
-  std::vector<int> sd_ptr, sd_dofs, vp_ptr, trow_ptr, tfirst;
+  std::vector<int> sd_ptr, vp_ptr, trow_ptr, tfirst;
+  ivec sd_dofs;
   std::vector<long long> toff;
-  std::vector<int> loc_rowptr, loc_col, loc_src;
-  std::vector<int> mult, mi, coff;
-  std::vector<int> inv_ptr, inv_sd, inv_loc;
-  std::vector<int> ext_ptr, ext_rowptr, ext_src, ext_loc;
-  std::vector<int> pair_i, pair_j, pair_ptr, pair_l, pair_e;
+  ivec loc_rowptr, loc_col, loc_src;
+  std::vector<int> mi, coff;
+  ivec mult, inv_ptr, inv_sd, inv_loc;
+  std::vector<int> ext_ptr;
+  ivec ext_rowptr, ext_src, ext_loc;
+  std::vector<int> pair_i, pair_j, pair_ptr;
+  ivec pair_l, pair_e;
 };
 
 int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
