@@ -126,8 +126,9 @@ typedef struct {
   int32_t eig_unconverged;  /* subdomains not converged at eig_maxit                */
   int32_t n_gap_flags;      /* subdomains with lambda_{m+1} - lambda_m tiny         */
   double mu_c;              /* min_i lambda_{m_i+1}                                 */
-  double phase_ms[8];       /* plan, upload, extract, local chol, eig, basis+A0,    */
-                            /* coarse chol+inverse, total                           */
+  double phase_ms[8];       /* plan (host planning + upload of its index arrays),   */
+                            /* input matrix host->device transfer, extract, local   */
+                            /* chol, eig, basis+A0, coarse chol+inverse, total      */
   double coupling_ms;       /* host coupling-plan thread (overlaps device work)     */
   double coupling_wait_ms;  /* time the device path waited for it                   */
 } amsp_setup_info;

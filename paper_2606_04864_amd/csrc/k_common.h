@@ -179,111 +179,90 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Blocked Cholesky of a 64x64 SPD tile and the inverse of its factor, in LDS.
+// Broadcast lane `src` (a compile-time constant in the callers' unrolled
+// loops) of a double to the whole wavefront.
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, src);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky factor of a 64x64 SPD tile and the inverse of the factor, in LDS.
 //   a (stride LDT): lower triangle of the tile on entry, L on exit (upper 0)
-//   w (stride LDT): inv(L) on exit (lower triangular)
-// 16x16 diagonal blocks are factored and inverted by wavefront 0 alone
-// (wave-level sync); panels, trailing updates and the off-diagonal blocks of
-// the inverse use the whole workgroup.  Non-positive pivots set *fail and are
-// replaced by 1 so that the factorisation ends with finite values.
+//   w (stride LDT): inv(L) on exit (upper 0)
+// Wavefront 0 does the work in registers: for the factorisation lane i holds
+// row i (right-looking; column k of L is broadcast through LDS at step k),
+// for the inverse lane j holds column j of inv(L) (forward substitution
+// against broadcast rows of L).  Other wavefronts only meet the closing
+// barrier.  A non-positive or non-finite pivot sets *fail and is replaced by
+// 1 so that the result stays finite.
+__device__ __forceinline__ int opaque_int(int v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
+}
+
 __device__ void lds_potrf_trtri(double *a, double *w, int *fail) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int e = t; e < TE; e += WG) w[(e >> 6) * LDT + (e & 63)] = 0.0;
-  for (int kb = 0; kb < 4; ++kb) {
-    const int k0 = 16 * kb;
-    if (wave == 0) {
-      for (int k = 0; k < 16; ++k) {
-        const int kk = k0 + k;
-        double d = a[kk * LDT + kk];
-        const bool bad = !(d > 0.0) || !isfinite(d);
-        d = bad ? 1.0 : sqrt(d);
-        wave_sync();
-        if (lane == 0) {
-          a[kk * LDT + kk] = d;
-          if (bad) *fail = 1;
-        }
-        if (lane > k && lane < 16) a[(k0 + lane) * LDT + kk] /= d;
-        wave_sync();
-        for (int e = lane; e < 256; e += 64) {
-          const int i = e >> 4, j = e & 15;
-          if (j > k && j <= i)
-            a[(k0 + i) * LDT + k0 + j] =
-                fma(-a[(k0 + i) * LDT + kk], a[(k0 + j) * LDT + kk], a[(k0 + i) * LDT + k0 + j]);
-        }
-        wave_sync();
-      }
-      // inverse of the 16x16 diagonal factor block, row by row
-      for (int i = 0; i < 16; ++i) {
-        if (lane <= i) {
-          const double lii = a[(k0 + i) * LDT + k0 + i];
-          double v;
-          if (lane == i) {
-            v = 1.0 / lii;
-          } else {
-            double s = 0.0;
-            for (int m = lane; m < i; ++m) s = fma(a[(k0 + i) * LDT + k0 + m], w[(k0 + m) * LDT + k0 + lane], s);
-            v = -s / lii;
-          }
-          w[(k0 + i) * LDT + k0 + lane] = v;
-        }
-        wave_sync();
-      }
-    }
-    __syncthreads();
-    // panel: L[r][c] = sum_{m <= c} A[r][m] inv(L_kk)[c][m] for rows below the block
-    const int nr = TS - k0 - 16;
-    double out[3];
-    int cnt = 0;
-    for (int e = t; e < nr * 16; e += WG) {
-      const int r = k0 + 16 + e / 16, c = e % 16;
-      double s = 0.0;
-      for (int m = 0; m <= c; ++m) s = fma(a[r * LDT + k0 + m], w[(k0 + c) * LDT + k0 + m], s);
-      out[cnt++] = s;
-    }
-    __syncthreads();
-    cnt = 0;
-    for (int e = t; e < nr * 16; e += WG) {
-      const int r = k0 + 16 + e / 16, c = e % 16;
-      a[r * LDT + k0 + c] = out[cnt++];
-    }
-    __syncthreads();
-    // trailing update of the lower triangle
-    for (int e = t; e < nr * nr; e += WG) {
-      const int r = k0 + 16 + e / nr, c = k0 + 16 + e % nr;
-      if (c <= r) {
-        double s = a[r * LDT + c];
+  if (threadIdx.x < 64) {
+    // Lane-dependent compares go through opaque_int at their point of use so
+    // that callers' loops cannot hoist 64 masks (or the constant LDS
+    // addresses, via z) out of the loop and keep them live.
+    const int z = opaque_int(0);
+    double *aa = a + z, *ww = w + z;
+    const int i = threadIdx.x;
+    double *col = aa;      // column k of L (a is free once its rows are in registers)
+    double *ls = ww;       // rows of L with stride 64 for the inverse phase
+    double *rdg = ww + TE; // 1 / L_kk  (TE + 64 <= TS * LDT)
+    double r[TS];          // row i; entries right of the diagonal are never used
 #pragma unroll
-        for (int m = 0; m < 16; ++m) s = fma(-a[r * LDT + k0 + m], a[c * LDT + k0 + m], s);
-        a[r * LDT + c] = s;
+    for (int j = 0; j < TS; ++j) r[j] = aa[i * LDT + j];
+    wave_sync();
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < TS; ++k) {
+      double d = readlane_d(r[k], k);
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = true;
+        d = 1.0;
       }
+      const double sq = sqrt(d);
+      const double inv = 1.0 / sq;
+      r[k] = (opaque_int(i) == k) ? sq : r[k] * inv;
+      rdg[k] = inv;
+      col[i] = r[k];
+      wave_sync();
+#pragma unroll
+      for (int j = k + 1; j < TS; ++j) r[j] = fma(-r[k], col[j], r[j]);
+      wave_sync();
     }
-    __syncthreads();
+    if (bad && i == 0) *fail = 1;
+#pragma unroll
+    for (int j = 0; j < TS; ++j) {
+      aa[i * LDT + j] = r[j];
+      ls[i * TS + j] = r[j];
+    }
+    wave_sync();
+    // column j = i of inv(L): x_m = (delta_mj - sum_{q<m} L_mq x_q) / L_mm
+    double x[TS];
+#pragma unroll
+    for (int m = 0; m < TS; ++m) {
+      double s0 = (opaque_int(i) == m) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+      for (int q = 0; q + 1 < m; q += 2) {
+        s0 = fma(-ls[m * TS + q], x[q], s0);
+        s1 = fma(-ls[m * TS + q + 1], x[q + 1], s1);
+      }
+      if (m & 1) s0 = fma(-ls[m * TS + m - 1], x[m - 1], s0);
+      x[m] = (s0 + s1) * rdg[m];
+    }
+    wave_sync();
+#pragma unroll
+    for (int m = 0; m < TS; ++m) ww[m * LDT + i] = x[m];  // exact zeros above the diagonal
   }
-  // off-diagonal blocks of the inverse: W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj,
-  // block rows in order; T_j is staged in the (unused) strict upper part of a
-  for (int ib = 1; ib < 4; ++ib) {
-    for (int e = t; e < ib * 256; e += WG) {
-      const int j = e >> 8, r = (e >> 4) & 15, c = e & 15;
-      double s = 0.0;
-      for (int kb = j; kb < ib; ++kb)
-#pragma unroll 4
-        for (int m = 0; m < 16; ++m)
-          s = fma(a[(16 * ib + r) * LDT + 16 * kb + m], w[(16 * kb + m) * LDT + 16 * j + c], s);
-      a[(16 * j + r) * LDT + 16 * ib + c] = s;  // T_j (r, c) in upper block (j, ib)
-    }
-    __syncthreads();
-    for (int e = t; e < ib * 256; e += WG) {
-      const int j = e >> 8, r = (e >> 4) & 15, c = e & 15;
-      double s = 0.0;
-      for (int m = 0; m <= r; ++m)
-        s = fma(w[(16 * ib + r) * LDT + 16 * ib + m], a[(16 * j + m) * LDT + 16 * ib + c], s);
-      w[(16 * ib + r) * LDT + 16 * j + c] = -s;
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < TE; e += WG) {
-    const int i = e >> 6, j = e & 63;
-    if (j > i) a[i * LDT + j] = 0.0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < TE; e += blockDim.x) {
+    const int r = e >> 6, c = e & 63;
+    if (c > r) a[r * LDT + c] = 0.0;
   }
   __syncthreads();
 }

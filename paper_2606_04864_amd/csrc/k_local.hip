@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(WG) k_extract_tiles(Plan p, int nrows_total,
 //   C = A_IJ - sum_K L_IK L_JK^T  (K over tiles present in both rows; MFMA)
 //   J < I : L_IJ = C inv(L_JJ)^T   (MFMA)
 //   J = I : L_II = chol(C) in LDS; the tile then stores inv(L_II).
-__global__ void __launch_bounds__(WG) k_profile_cholesky(Plan p, double *__restrict__ tiles, int bit,
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) k_profile_cholesky(Plan p, double *__restrict__ tiles, int bit,
                                                          int *__restrict__ status) {
   extern __shared__ double lds[];
   double *X = lds;             // 64 x LDT
