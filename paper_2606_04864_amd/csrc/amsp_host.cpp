@@ -232,6 +232,27 @@ struct CouplingTask {
 
 static amsp_status upload_coupling(amsp_handle *h);
 
+// A second stream (default priority) with two events, released on scope exit
+// after the stream has drained.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t create() {
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+    return e;
+  }
+  ~SideStream() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   HostPlan &P = h->hp;
   const bool mixed = h->opt.precision != AMSP_FP64;
@@ -452,17 +473,41 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
                              hipMemcpyDeviceToDevice, h->stream));
     }
     double t5 = now_ms();
+    // Tiled right-looking Cholesky with lookahead.  Main stream: diagonal
+    // factor, panel, then the update of the next tile column only, so the
+    // next diagonal step can start while a second stream applies the rest of
+    // the trailing update.  A third stream forms the inverse factor
+    // W0 = inv(L0) by a right-looking solve of L0 X = I; its step k needs
+    // only column k of L0, final once the panel of step k is done.
+    //   main:  potrf(k) trsm(k) [panel] ... wait [rest of k-1] next(k)
+    //   bulk:  wait [panel] rest(k) [rest]
+    //   inv:   wait [panel] inv_row(k) inv_update(k)
+    ALLOC(h->W0, double, (size_t)T0 * T0 * TE);
+    SideStream bulk, inv;
+    HIP_TRY(bulk.create());
+    HIP_TRY(inv.create());
+    hipEvent_t ev_panel = bulk.e0, ev_rest = bulk.e1, ev_inv = inv.e1;
+    HIP_TRY(hipEventRecord(ev_panel, h->stream));  // A0 formed, W0 and dinv allocated
+    HIP_TRY(hipStreamWaitEvent(inv.s, ev_panel, 0));
+    HIP_TRY(hipStreamWaitEvent(bulk.s, ev_panel, 0));
+    HIP_TRY(hipEventRecord(ev_rest, bulk.s));
+    launch_tiles_identity(inv.s, h->W0, T0);
     for (int k = 0; k < T0; ++k) {
       launch_dense_potrf_diag(h->stream, A0t, T0, k, dinv, cstat);
       launch_dense_trsm_panel(h->stream, A0t, T0, k, dinv);
-      launch_dense_syrk_update(h->stream, A0t, T0, k);
+      HIP_TRY(hipEventRecord(ev_panel, h->stream));
+      HIP_TRY(hipStreamWaitEvent(inv.s, ev_panel, 0));
+      launch_dense_inv_row(inv.s, h->W0, T0, k, dinv);
+      launch_dense_inv_update(inv.s, A0t, h->W0, T0, k);
+      HIP_TRY(hipStreamWaitEvent(h->stream, ev_rest, 0));  // rest of step k-1
+      launch_dense_syrk_next(h->stream, A0t, T0, k);
+      HIP_TRY(hipStreamWaitEvent(bulk.s, ev_panel, 0));
+      launch_dense_syrk_rest(bulk.s, A0t, T0, k);
+      HIP_TRY(hipEventRecord(ev_rest, bulk.s));
     }
-    ALLOC(h->W0, double, (size_t)T0 * T0 * TE);
-    launch_tiles_identity(h->stream, h->W0, T0);
-    for (int k = 0; k < T0; ++k) {
-      launch_dense_inv_row(h->stream, h->W0, T0, k, dinv);
-      launch_dense_inv_update(h->stream, A0t, h->W0, T0, k);
-    }
+    HIP_TRY(hipEventRecord(ev_inv, inv.s));
+    HIP_TRY(hipStreamWaitEvent(h->stream, ev_inv, 0));
+    HIP_TRY(hipStreamWaitEvent(h->stream, ev_rest, 0));
     HIP_TRY(hipGetLastError());
     int cs = 0;
     HIP_TRY(hipMemcpyAsync(&cs, cstat, sizeof(int), hipMemcpyDeviceToHost, h->stream));

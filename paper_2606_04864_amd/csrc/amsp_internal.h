@@ -123,7 +123,10 @@ void launch_pair_products(hipStream_t s, const Plan &p, const CoarsePlan &c, con
 void launch_symmetrize_tiles(hipStream_t s, double *A0t, int T0, int nc);
 void launch_dense_potrf_diag(hipStream_t s, double *A0t, int T0, int k, double *dinv, int *status);
 void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const double *dinv);
-void launch_dense_syrk_update(hipStream_t s, double *A0t, int T0, int k);
+// Trailing update of Cholesky step k split for lookahead: the next tile
+// column (j = k + 1) and the rest (j >= k + 2).
+void launch_dense_syrk_next(hipStream_t s, double *A0t, int T0, int k);
+void launch_dense_syrk_rest(hipStream_t s, double *A0t, int T0, int k);
 void launch_dense_inv_row(hipStream_t s, double *Wt, int T0, int k, const double *dinv);
 void launch_dense_inv_update(hipStream_t s, const double *Lt, double *Wt, int T0, int k);
 void launch_tiles_identity(hipStream_t s, double *Wt, int T0);

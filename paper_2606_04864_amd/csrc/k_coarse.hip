@@ -101,15 +101,16 @@ __device__ __forceinline__ double *tile_ptr(double *A, int T0, int I, int J) {
 }
 
 // Step k: factor diagonal tile, store L_kk in place and inv(L_kk) in dinv.
-__global__ void __launch_bounds__(WG) k_dense_potrf_diag(double *A0t, int T0, int k, double *dinv,
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) k_dense_potrf_diag(double *A0t, int T0, int k, double *dinv,
                                                          int *status) {
   extern __shared__ double lds[];
   double *X = lds, *Y = lds + TS * LDT;
   __shared__ int fail;
+  __builtin_amdgcn_s_setprio(3);  // critical path: issue ahead of concurrent update kernels
   if (threadIdx.x == 0) fail = 0;
   tile_to_lds(tile_ptr(A0t, T0, k, k), X);
   __syncthreads();
-  lds_potrf_trtri(X, Y, &fail);
+  lds_potrf_trtri<32>(X, Y, &fail);
   lds_to_tile(X, tile_ptr(A0t, T0, k, k));
   lds_to_tile(Y, dinv + (size_t)k * TE);
   __syncthreads();
@@ -122,20 +123,27 @@ __global__ void __launch_bounds__(WG) k_dense_trsm_panel(double *A0t, int T0, in
                                                          const double *dinv) {
   const int i = k + 1 + blockIdx.x;
   double *a = tile_ptr(A0t, T0, i, k);
+  __builtin_amdgcn_s_setprio(3);  // critical path
   Acc4 o;
   acc_zero(o);
   acc_mma_abt(o, a, TS, dinv + (size_t)k * TE, TS, 1.0);
   acc_store(o, a);
 }
 
-// A_ij -= L_ik L_jk^T for k < j <= i
-__global__ void __launch_bounds__(WG) k_dense_syrk_update(double *A0t, int T0, int k) {
+// A_ij -= L_ik L_jk^T over the tiles j0 <= j <= i (tri = 1), or over the
+// single tile column j = j0, i >= j0 (tri = 0).
+__global__ void __launch_bounds__(WG) k_dense_syrk_update(double *A0t, int T0, int k, int j0,
+                                                          int tri) {
   const int b = blockIdx.x;
-  int ii = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-  while ((ii + 1) * (ii + 2) / 2 <= b) ++ii;
-  while (ii * (ii + 1) / 2 > b) --ii;
-  const int jj = b - ii * (ii + 1) / 2;
-  const int i = k + 1 + ii, j = k + 1 + jj;
+  int ii = b, jj = 0;
+  if (!tri) __builtin_amdgcn_s_setprio(3);  // next tile column: critical path
+  if (tri) {
+    ii = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((ii + 1) * (ii + 2) / 2 <= b) ++ii;
+    while (ii * (ii + 1) / 2 > b) --ii;
+    jj = b - ii * (ii + 1) / 2;
+  }
+  const int i = j0 + ii, j = j0 + jj;
   double *c = tile_ptr(A0t, T0, i, j);
   Acc4 o;
   acc_load(o, c);
@@ -284,10 +292,17 @@ void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const do
   hipLaunchKernelGGL(k_dense_trsm_panel, dim3(nb), dim3(WG), 0, s, A0t, T0, k, dinv);
 }
 
-void launch_dense_syrk_update(hipStream_t s, double *A0t, int T0, int k) {
+void launch_dense_syrk_next(hipStream_t s, double *A0t, int T0, int k) {
   const int m = T0 - k - 1;
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_dense_syrk_update, dim3(m * (m + 1) / 2), dim3(WG), 0, s, A0t, T0, k);
+  hipLaunchKernelGGL(k_dense_syrk_update, dim3(m), dim3(WG), 0, s, A0t, T0, k, k + 1, 0);
+}
+
+void launch_dense_syrk_rest(hipStream_t s, double *A0t, int T0, int k) {
+  const int m = T0 - k - 2;
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_dense_syrk_update, dim3(m * (m + 1) / 2), dim3(WG), 0, s, A0t, T0, k, k + 2,
+                     1);
 }
 
 void launch_dense_inv_row(hipStream_t s, double *Wt, int T0, int k, const double *dinv) {

@@ -1,5 +1,6 @@
 // Device helpers shared by the HIP kernels (gfx950, wave64).
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include "amsp_internal.h"
@@ -188,78 +189,169 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Cholesky factor of a 64x64 SPD tile and the inverse of the factor, in LDS.
-//   a (stride LDT): lower triangle of the tile on entry, L on exit (upper 0)
-//   w (stride LDT): inv(L) on exit (upper 0)
-// Wavefront 0 does the work in registers: for the factorisation lane i holds
-// row i (right-looking; column k of L is broadcast through LDS at step k),
-// for the inverse lane j holds column j of inv(L) (forward substitution
-// against broadcast rows of L).  Other wavefronts only meet the closing
-// barrier.  A non-positive or non-finite pivot sets *fail and is replaced by
-// 1 so that the result stays finite.
+// 1/sqrt(d) for d > 0 to double precision: hardware estimate refined by two
+// Newton steps y <- y (3 - d y^2) / 2 (each squares the relative error).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double hd = -0.5 * d;
+  y = y * fma(hd, y * y, 1.5);
+  y = y * fma(hd, y * y, 1.5);
+  return y;
+}
+
 __device__ __forceinline__ int opaque_int(int v) {
   __asm__ volatile("" : "+v"(v));
   return v;
 }
 
-__device__ void lds_potrf_trtri(double *a, double *w, int *fail) {
+// Compile-time loop: f(std::integral_constant<int, v>) for v = B, B+S, ... < E.
+template <int B, int E, int S = 1, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + S, E, S>(f);
+  }
+}
+
+// Quad permutation of a double across lanes (DPP, no LDS traffic); CTRL is a
+// quad_perm control word: 0xB1 swaps neighbours (lane ^ 1), 0x4E swaps pairs
+// (lane ^ 2).
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky factor of a 64x64 SPD tile and the inverse of the factor, in LDS.
+//   a (stride LDT): lower triangle of the tile on entry, L on exit (upper 0)
+//   w (stride LDT): inv(L) on exit (upper 0)
+// Factorisation: wavefront 0, lane i holds row i in registers (right-looking).
+// At step k the entry L[k+1][k] that the next pivot waits for is taken from
+// lane k+1 directly; the other entries of column k are broadcast through LDS
+// (double-buffered, read in batches of CH).  A single wavefront's LDS
+// accesses complete in program order, so the steps need no barriers.
+// Inverse: all four wavefronts; each column of inv(L) is solved by four
+// adjacent lanes that split every row's dot product and combine it with quad
+// permutations; the next row of L is fetched while the current one is used.
+// A non-positive or non-finite pivot sets *fail and is replaced by 1 so that
+// the result stays finite.  Needs blockDim.x == 256.
+template <int CH>
+__device__ __forceinline__ void lds_potrf_trtri(double *a, double *w, int *fail) {
+  // The lane index and the LDS base pass once through an opaque move, so
+  // that callers' loops cannot hoist the lane-dependent masks or the
+  // constant LDS addresses below out of the loop and keep them live.
+  const int lane_id = opaque_int((int)threadIdx.x);
+  const int z = opaque_int(0);
+  double *aa = a + z, *ww = w + z;
+  double *ls = ww;        // rows of L with stride 64 for the inverse phase
+  double *rdg = ww + TE;  // 1 / L_kk  (TE + 64 <= TS * LDT)
   if (threadIdx.x < 64) {
-    // Lane-dependent compares go through opaque_int at their point of use so
-    // that callers' loops cannot hoist 64 masks (or the constant LDS
-    // addresses, via z) out of the loop and keep them live.
-    const int z = opaque_int(0);
-    double *aa = a + z, *ww = w + z;
-    const int i = threadIdx.x;
-    double *col = aa;      // column k of L (a is free once its rows are in registers)
-    double *ls = ww;       // rows of L with stride 64 for the inverse phase
-    double *rdg = ww + TE; // 1 / L_kk  (TE + 64 <= TS * LDT)
-    double r[TS];          // row i; entries right of the diagonal are never used
-#pragma unroll
-    for (int j = 0; j < TS; ++j) r[j] = aa[i * LDT + j];
+    const int i = lane_id;
+    double *col = aa;  // two column buffers (a is free once its rows are in registers)
+    double r[TS];      // row i; entries right of the diagonal are never used
+    static_for<0, TS>([&](auto jc) __attribute__((always_inline)) {
+      r[jc.value] = aa[i * LDT + jc.value];
+    });
     wave_sync();
     bool bad = false;
-#pragma unroll
-    for (int k = 0; k < TS; ++k) {
+    // column k of L for this lane's row, given the updated r[k]
+    auto pivot = [&](auto kc) __attribute__((always_inline)) {
+      constexpr int k = decltype(kc)::value;
       double d = readlane_d(r[k], k);
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = true;
-        d = 1.0;
-      }
-      const double sq = sqrt(d);
-      const double inv = 1.0 / sq;
-      r[k] = (opaque_int(i) == k) ? sq : r[k] * inv;
+      const bool bk = !(d > 0.0) || !isfinite(d);
+      bad = bad || bk;
+      d = bk ? 1.0 : d;
+      const double inv = rsqrt_nr(d);
+      r[k] = (i == k) ? d * inv : r[k] * inv;
       rdg[k] = inv;
-      col[i] = r[k];
-      wave_sync();
-#pragma unroll
-      for (int j = k + 1; j < TS; ++j) r[j] = fma(-r[k], col[j], r[j]);
-      wave_sync();
-    }
+      col[(k & 1) * TS + i] = r[k];
+    };
+    pivot(std::integral_constant<int, 0>{});
+    // Step k: the reads of column k go out first; the next pivot (which
+    // needs only column k+1, updated through a lane read) and its column
+    // write overlap their latency; then the bulk update of columns >= k+2.
+    static_for<0, TS - 1>([&](auto kc) __attribute__((always_inline)) {
+      constexpr int k = decltype(kc)::value;
+      constexpr int nb = (TS - (k + 2) + CH - 1) / CH;  // batches of columns >= k+2
+      const double *cb = col + (k & 1) * TS;
+      const double lk = r[k];
+      double cva[CH], cvb[CH];
+      auto load_batch = [&](auto bc, double(&cv)[CH]) __attribute__((always_inline)) {
+        constexpr int j0 = k + 2 + CH * decltype(bc)::value;
+        constexpr int j1 = j0 + CH < TS ? j0 + CH : TS;
+        static_for<j0, j1>([&](auto jc) __attribute__((always_inline)) {
+          cv[jc.value - j0] = cb[jc.value];
+        });
+      };
+      if constexpr (nb > 0) load_batch(std::integral_constant<int, 0>{}, cva);
+      r[k + 1] = fma(-lk, readlane_d(lk, k + 1), r[k + 1]);
+      pivot(std::integral_constant<int, k + 1>{});
+      static_for<0, nb>([&](auto bc) __attribute__((always_inline)) {
+        constexpr int bi = decltype(bc)::value;
+        double(&cur)[CH] = (bi & 1) ? cvb : cva;
+        double(&nxt)[CH] = (bi & 1) ? cva : cvb;
+        if constexpr (bi + 1 < nb) load_batch(std::integral_constant<int, bi + 1>{}, nxt);
+        constexpr int j0 = k + 2 + CH * bi;
+        constexpr int j1 = j0 + CH < TS ? j0 + CH : TS;
+        static_for<j0, j1>([&](auto jc) __attribute__((always_inline)) {
+          r[jc.value] = fma(-lk, cur[jc.value - j0], r[jc.value]);
+        });
+      });
+    });
     if (bad && i == 0) *fail = 1;
-#pragma unroll
-    for (int j = 0; j < TS; ++j) {
-      aa[i * LDT + j] = r[j];
-      ls[i * TS + j] = r[j];
-    }
     wave_sync();
-    // column j = i of inv(L): x_m = (delta_mj - sum_{q<m} L_mq x_q) / L_mm
-    double x[TS];
-#pragma unroll
-    for (int m = 0; m < TS; ++m) {
-      double s0 = (opaque_int(i) == m) ? 1.0 : 0.0, s1 = 0.0;
-#pragma unroll
-      for (int q = 0; q + 1 < m; q += 2) {
-        s0 = fma(-ls[m * TS + q], x[q], s0);
-        s1 = fma(-ls[m * TS + q + 1], x[q + 1], s1);
-      }
-      if (m & 1) s0 = fma(-ls[m * TS + m - 1], x[m - 1], s0);
-      x[m] = (s0 + s1) * rdg[m];
-    }
-    wave_sync();
-#pragma unroll
-    for (int m = 0; m < TS; ++m) ww[m * LDT + i] = x[m];  // exact zeros above the diagonal
+    static_for<0, TS>([&](auto jc) __attribute__((always_inline)) {
+      aa[i * LDT + jc.value] = r[jc.value];
+      ls[i * TS + jc.value] = r[jc.value];
+    });
   }
   __syncthreads();
+  {
+    // column j of inv(L): x_m = (delta_mj - sum_{q<m} L_mq x_q) / L_mm.
+    // Lane (j, p): p = lane & 3 owns x_q for q = 4t + p (xs[t]).
+    const int p = lane_id & 3;
+    const int j = lane_id >> 2;  // 0..63
+    double xs[TS / 4];  // zero-initialised: masked products must see finite values
+    static_for<0, TS / 4>([&](auto tc) __attribute__((always_inline)) { xs[tc.value] = 0.0; });
+    double lva[TS / 4], lvb[TS / 4];  // rows m (even / odd) of L, entries q = 4t + p
+    auto load_row = [&](auto mc, double(&lv)[TS / 4]) __attribute__((always_inline)) {
+      constexpr int m = decltype(mc)::value;
+      static_for<0, (m + 3) / 4>([&](auto tc) __attribute__((always_inline)) {
+        constexpr int t = decltype(tc)::value;
+        const int q = 4 * t + p;
+        lv[t] = (q < m) ? ls[m * TS + q] : 0.0;
+      });
+    };
+    load_row(std::integral_constant<int, 1>{}, lvb);
+    static_for<0, TS>([&](auto mc) __attribute__((always_inline)) {
+      constexpr int m = decltype(mc)::value;
+      constexpr int nt = (m + 3) / 4;
+      double(&cur)[TS / 4] = (m & 1) ? lvb : lva;
+      double(&nxt)[TS / 4] = (m & 1) ? lva : lvb;
+      if constexpr (m + 1 < TS) load_row(std::integral_constant<int, m + 1>{}, nxt);
+      double s0 = 0.0, s1 = 0.0;
+      static_for<0, nt>([&](auto tc) __attribute__((always_inline)) {
+        constexpr int t = decltype(tc)::value;
+        if constexpr ((t & 1) == 0)
+          s0 = fma(-cur[t], xs[t], s0);
+        else
+          s1 = fma(-cur[t], xs[t], s1);
+      });
+      double sum = s0 + s1;
+      sum += dpp_quad<0xB1>(sum);
+      sum += dpp_quad<0x4E>(sum);
+      const double xm = ((j == m) ? 1.0 + sum : sum) * rdg[m];
+      constexpr int tm = m / 4;
+      xs[tm] = (p == (m & 3)) ? xm : xs[tm];
+    });
+    __syncthreads();  // all reads of ls / rdg done before w is overwritten
+    static_for<0, TS / 4>([&](auto tc) __attribute__((always_inline)) {
+      constexpr int t = decltype(tc)::value;
+      ww[(4 * t + p) * LDT + j] = xs[t];  // exact zeros above the diagonal
+    });
+  }
   for (int e = threadIdx.x; e < TE; e += blockDim.x) {
     const int r = e >> 6, c = e & 63;
     if (c > r) a[r * LDT + c] = 0.0;

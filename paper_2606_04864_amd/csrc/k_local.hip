@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) k_
         acc_mma_abt(o, X, LDT, tiles + tile_elem(tJ + (J - fJ)), TS, 1.0);  // C inv(L_JJ)^T
         acc_store(o, cij);
       } else {
-        lds_potrf_trtri(X, Y, &fail);
+        lds_potrf_trtri<16>(X, Y, &fail);
         lds_to_tile(Y, cij);
       }
       __syncthreads();
