@@ -92,7 +92,10 @@ typedef struct {
   int32_t chunk;            /* PCG iterations per host poll (default 8)                  */
   int32_t flexible;         /* 1: Polak-Ribiere beta; -1 (default): on for mixed forms   */
   int32_t keep_a0;          /* 1: keep a copy of A0 for amsp_get_coarse_matrix           */
-  int32_t timing;           /* 1: time every PCG kernel launch with HIP events           */
+  int32_t timing;           /* bit c set: time launches of PCG kernel class c (the        */
+                            /* classes of amsp_info.kernel_ms) with HIP events; 0: off;  */
+                            /* 0x1F: all.  Each timed launch adds two event records.     */
+  int32_t timing_stride;    /* time every timing_stride-th launch of a class (>= 1)      */
   void *stream;             /* hipStream_t                                               */
 } amsp_options;
 
@@ -104,7 +107,8 @@ typedef struct {
   int32_t restarts;         /* residual replacements after a false convergence     */
   double solve_ms;          /* wall time of the call                               */
   int64_t bytes_per_iter;   /* algorithmic HBM bytes of one CG iteration           */
-  /* with opt.timing: summed device time and launch count per kernel class:
+  /* with opt.timing: summed device time and count of the timed launches per
+   * kernel class (average duration = kernel_ms / kernel_launches):
    * [0] SpMV (+ search-direction update), [1] local apply (gather, restriction,
    * forward/backward solves), [2] coarse solve (both triangular products),
    * [3] scatter-sum, [4] CG vector update and reductions */

@@ -52,6 +52,10 @@ class _CSR(ctypes.Structure):
                 ("val", ctypes.c_void_p)]
 
 
+# PCG kernel classes of amsp_info.kernel_ms / the timing bit mask
+KERNEL_CLASS = {"spmv": 0, "local": 1, "coarse": 2, "scatter": 3, "vector": 4}
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("pou", ctypes.c_int32), ("local_order", ctypes.c_int32),
@@ -59,7 +63,7 @@ class _Options(ctypes.Structure):
                 ("eig_maxit", ctypes.c_int32), ("eig_shift", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("flexible", ctypes.c_int32),
                 ("keep_a0", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("timing_stride", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class _Info(ctypes.Structure):
@@ -216,7 +220,7 @@ class Preconditioner:
                  precision: str = "fp64", pou: int = 0, local_order: str = "rcm",
                  dense_tiles: bool = False, eig_tol: float = 0.0, eig_maxit: int = 80,
                  eig_shift: float = 1e-4, chunk: int = 8, flexible: int = -1,
-                 keep_a0: bool = False, timing: bool = False, stream=None):
+                 keep_a0: bool = False, timing=False, timing_stride: int = 1, stream=None):
         torch = _torch()
         self._h = None
         self._keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
@@ -234,7 +238,9 @@ class Preconditioner:
         o.local_order, o.dense_tiles = ORDER[local_order], int(bool(dense_tiles))
         o.eig_tol, o.eig_maxit, o.eig_shift = float(eig_tol), int(eig_maxit), float(eig_shift)
         o.chunk, o.flexible, o.keep_a0 = int(chunk), int(flexible), int(bool(keep_a0))
-        o.timing = int(bool(timing))
+        # timing: True -> every kernel class, or an int bit mask of classes
+        o.timing = 0x1F if timing is True else int(timing)
+        o.timing_stride = max(1, int(timing_stride))
         if torch.cuda.is_available():
             torch.cuda.init()  # the device context exists before the library's first HIP call
             torch.cuda.synchronize()

@@ -8,5 +8,6 @@ constexpr int TE = TS * TS;  // elements per tile
 constexpr int WG = 256;      // workgroup size of the batched kernels (4 wavefronts)
 constexpr int EIGP = 16;     // subspace block width of the local eigensolver
 constexpr int MAXNEV = 15;   // nev + 1 must fit in the subspace block
+constexpr int MAX_PARTIALS = 1024;  // workgroups (partial sums) of a vector reduction
 
 }  // namespace amsp

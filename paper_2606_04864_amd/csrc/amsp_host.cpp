@@ -87,7 +87,10 @@ struct amsp_handle {
   double *xloc = nullptr, *cvec = nullptr, *t1 = nullptr, *tvec = nullptr, *trmv_part = nullptr;
   // pcg scratch
   double *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
-  double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr, *scal = nullptr;
+  // partial sums (MAX_PARTIALS each): a = p.q and scratch, b = r.z (scatter),
+  // c = r.z_old (flexible) and scratch, d = r.r
+  double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr, *part_d = nullptr;
+  double *scal = nullptr;
   PcgState *st = nullptr;
   double *hist = nullptr;  // recursive residual history of the last PCG call
   int hist_cap = 0, hist_len = 0;
@@ -99,6 +102,7 @@ struct amsp_handle {
   size_t ev_used = 0;
   std::vector<std::pair<int, int>> ev_rec;  // (kernel class, index of start event)
   bool timing_active = false;
+  int ev_count[5] = {0, 0, 0, 0, 0};  // launches per class seen by tstart (for the stride)
   ~amsp_handle() {
     for (hipEvent_t e : evs) hipEventDestroy(e);
   }
@@ -113,8 +117,10 @@ static hipEvent_t next_event(amsp_handle *h) {
   return h->evs[h->ev_used++];
 }
 
-static int tstart(amsp_handle *h) {
-  if (!h->timing_active) return -1;
+static int tstart(amsp_handle *h, int cls) {
+  if (!h->timing_active || !(h->opt.timing & (1 << cls))) return -1;
+  const int k = h->ev_count[cls]++;
+  if (k % std::max(1, h->opt.timing_stride) != 0) return -1;
   const int idx = (int)h->ev_used;
   hipEvent_t e = next_event(h);
   if (!e) return -1;
@@ -180,6 +186,7 @@ extern "C" void amsp_default_options(amsp_options *opt) {
   opt->flexible = -1;  // -1: on for the mixed forms
   opt->keep_a0 = 0;
   opt->timing = 0;
+  opt->timing_stride = 1;
   opt->stream = nullptr;
 }
 
@@ -567,9 +574,10 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   ALLOC(h->p0, double, h->n);
   ALLOC(h->p1, double, h->n);
   ALLOC(h->q, double, h->n);
-  ALLOC(h->part_a, double, 4096);
-  ALLOC(h->part_b, double, 4096);
-  ALLOC(h->part_c, double, 4096);
+  ALLOC(h->part_a, double, MAX_PARTIALS);
+  ALLOC(h->part_b, double, MAX_PARTIALS);
+  ALLOC(h->part_c, double, MAX_PARTIALS);
+  ALLOC(h->part_d, double, MAX_PARTIALS);
   ALLOC(h->scal, double, 8);
   ALLOC(h->st, PcgState, 1);
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -618,6 +626,7 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
   if (opt) o = *opt;
   if (o.eig_maxit < 1) o.eig_maxit = 1;
   if (o.chunk < 1) o.chunk = 1;
+  if (o.timing_stride < 1) o.timing_stride = 1;
   if (!(o.eig_shift > 0.0)) {
     g_setup_error = "eig_shift must be positive";
     return AMSP_ERR_ARG;
@@ -681,7 +690,7 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
   const bool mixed = h->opt.precision != AMSP_FP64;
   const bool bf = h->opt.precision == AMSP_MIXED_BF16;
-  int tk = tstart(h);
+  int tk = tstart(h, 1);
   if (!mixed) {
     launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->fac64, h->phi64,
                                                  h->xloc, h->cvec, do_local, do_coarse, done);
@@ -696,7 +705,7 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   }
   tstop(h, 1, tk);
   if (do_coarse) {
-    tk = tstart(h);
+    tk = tstart(h, 2);
     if (!mixed) {
       launch_trmv<double>(h->stream, h->W0, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
       launch_trmv<double>(h->stream, h->W0, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
@@ -706,7 +715,7 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
     }
     tstop(h, 2, tk);
   }
-  tk = tstart(h);
+  tk = tstart(h, 3);
   if (!mixed || h->nev == 0)
     launch_scatter_sum_t<double>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
                                  h->phi64, h->tvec, z, partial_rz ? r : nullptr, partial_rz,
@@ -790,6 +799,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   h->timing_active = h->opt.timing != 0;
   h->ev_used = 0;
   h->ev_rec.clear();
+  for (int &c : h->ev_count) c = 0;
   if (h->hist_cap < maxit + 2) {
     if (h->hist) h->mem.free_one(h->hist);
     h->hist_cap = std::max(maxit + 2, 1024);
@@ -817,16 +827,20 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
     double relres_true = 0.0, floor_rel = 0.0;
     for (;;) {
       // z = M^{-1} r with r.z partials; r.r partials; p_old = 0
-      launch_dot(h->stream, n, h->r, h->r, h->part_a, nullptr);
+      launch_dot(h->stream, n, h->r, h->r, h->part_d, nullptr);
       amsp_status s = apply_one(h, h->r, h->z, 3, h->part_b, nullptr);
       if (s != AMSP_OK) return s;
       launch_fill(h->stream, n, h->p0, 0.0);
-      launch_pcg_init(h->stream, h->st, h->part_a, nb, h->part_b, nb, fresh ? rtol : -1.0, maxit);
+      launch_pcg_init(h->stream, h->st, h->part_d, nb, h->part_b, nb, fresh ? rtol : -1.0, maxit);
       HIP_TRY(hipGetLastError());
       const int *done = &h->st->done;
       double *pold = h->p0, *pnew = h->p1;
       int next = h->opt.chunk, prev_it = 0;
       double prev_rr = -1.0;
+      // step index of the next launch (iterations completed before it) and
+      // whether it is the first step after this (re)start
+      int t = fresh ? 0 : hs.it;
+      bool first = true;
       for (;;) {
         HIP_TRY(hipMemcpyAsync(&hs, h->st, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -836,28 +850,26 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
         if (prev_rr > 0.0 && hs.it > prev_it && hs.rr < prev_rr && hs.rr > 0.0) {
           const double rate = std::log(hs.rr / prev_rr) / (double)(hs.it - prev_it);
           const double need = std::log(hs.tol2 / hs.rr) / rate;
-          next = (int)std::ceil(need);
+          next = (int)std::ceil(need) + 1;  // + 1: convergence is seen by the following step
           next = std::max(1, std::min(next, h->opt.chunk));
         }
         prev_rr = hs.rr;
         prev_it = hs.it;
         for (int c = 0; c < next; ++c) {
-          int tk = tstart(h);
-          launch_spmv_pupdate_st(h->stream, n, h->rowptr, h->col, h->val, h->z, pold, pnew, h->q,
-                                 h->part_a, h->st);
+          int tk = tstart(h, 0);
+          launch_cg_dir(h->stream, n, h->rowptr, h->col, h->val, h->z, pold, pnew, h->q, h->part_a,
+                        h->st, h->part_d, h->part_b, h->part_c, t, first ? 1 : 0,
+                        h->opt.flexible);
           tstop(h, 0, tk);
-          tk = tstart(h);
-          launch_pcg_alpha(h->stream, h->st, h->part_a, nb);
-          launch_axpy_update_st(h->stream, n, x, h->r, pnew, h->q, h->st, h->part_a,
-                                h->opt.flexible ? h->z : nullptr, h->part_c);
-          launch_pcg_rr(h->stream, h->st, h->part_a, nb);
+          tk = tstart(h, 4);
+          launch_cg_update(h->stream, n, x, h->r, pnew, h->q, h->st, h->part_a, t, h->part_d,
+                           h->opt.flexible ? h->z : nullptr, h->part_c);
           tstop(h, 4, tk);
           s = apply_one(h, h->r, h->z, 3, h->part_b, done);
           if (s != AMSP_OK) return s;
-          tk = tstart(h);
-          launch_pcg_beta(h->stream, h->st, h->part_b, nb, h->part_c, h->opt.flexible);
-          tstop(h, 4, tk);
           std::swap(pold, pnew);
+          ++t;
+          first = false;
         }
         HIP_TRY(hipGetLastError());
       }

@@ -29,7 +29,7 @@ struct Plan {
 
 // PCG scalar state kept on the device.
 struct PcgState {
-  double rz, rz_old, pq, rr, alpha, beta, tol2, f2;
+  double rz, rz_ring[2], pq, rr, alpha, beta, tol2, f2;
   int it, done, breakdown, maxit;
   double *hist;   // rr after each iteration (hist[it]); may be null
   int hist_cap;
@@ -39,14 +39,17 @@ struct PcgState {
 int reduce_blocks(int n);
 void launch_spmv(hipStream_t s, int n, const int *rp, const int *col, const double *val,
                  const double *x, double *y, double *partial, const int *done);
-void launch_spmv_pupdate_st(hipStream_t s, int n, const int *rp, const int *col,
-                            const double *val, const double *z, const double *pold, double *pnew,
-                            double *q, double *partial, const PcgState *st);
+// One CG step t in two kernels (direction + update); the scalar reductions
+// of the previous kernels are folded in (see k_krylov.hip).
+void launch_cg_dir(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                   const double *z, const double *pold, double *pnew, double *q, double *part_pq,
+                   PcgState *st, const double *part_rr, const double *part_rz,
+                   const double *part_rzo, int t, int first, int flexible);
+void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q,
+                      PcgState *st, const double *part_pq, int t, double *part_rr,
+                      const double *zold, double *part_rzo);
 void launch_dot(hipStream_t s, int n, const double *a, const double *b, double *partial,
                 const int *done);
-void launch_axpy_update_st(hipStream_t s, int n, double *x, double *r, const double *p,
-                           const double *q, const PcgState *st, double *partial,
-                           const double *zold, double *partial_rzo);
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
                      double *partial);
 void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha);
@@ -57,10 +60,6 @@ void launch_fill_int(hipStream_t s, size_t n, int *a, int v);
 void launch_sum_partials(hipStream_t s, const double *partial, int nb, double *out);
 void launch_pcg_init(hipStream_t s, PcgState *st, const double *partial_rr, int nb_rr,
                      const double *partial_rz, int nb_rz, double rtol, int maxit);
-void launch_pcg_alpha(hipStream_t s, PcgState *st, const double *partial, int nb);
-void launch_pcg_rr(hipStream_t s, PcgState *st, const double *partial, int nb);
-void launch_pcg_beta(hipStream_t s, PcgState *st, const double *partial_rz, int nb,
-                     const double *partial_rzold, int flexible);
 
 // ----------------------------------------------------------------- local ---
 // s = diag(hat A_i) for every local row; status[i] |= 1 if some s <= 0.

@@ -1,18 +1,20 @@
 // CSR SpMV and the fused CG vector updates with deterministic reductions.
 //
 // Every reduction is two-stage: each workgroup writes one partial (wavefront
-// shuffles, then a fixed-order LDS sum) and a single-workgroup kernel adds the
-// partials in index order, so results are bitwise reproducible run to run.
-// Scalars (alpha, beta, residual norms, the convergence flag) stay on the
-// device; kernels read the 'done' flag first and return at once after
-// convergence, which lets the host launch CG iterations in chunks.
+// shuffles, then a fixed-order LDS sum) and the consumer adds the partials in
+// index order, so results are bitwise reproducible run to run.  In the CG
+// iteration the consumer is the next kernel itself: each of its workgroups
+// sums the (at most 1024) partials redundantly, obtains the same scalar, and
+// workgroup 0 records it in the device state; no single-workgroup kernels
+// and no atomics.  Kernels read the 'done' flag first and return at once
+// after convergence, which lets the host launch iterations in chunks.
 #include "k_common.h"
 
 namespace amsp {
 
 int reduce_blocks(int n) {
   int b = (n + WG - 1) / WG;
-  if (b > 4096) b = 4096;
+  if (b > MAX_PARTIALS) b = MAX_PARTIALS;
   if (b < 1) b = 1;
   return b;
 }
@@ -38,38 +40,6 @@ __global__ void __launch_bounds__(WG) k_spmv(int n, const int *__restrict__ rp,
   if (partial && threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// p_new = z + beta p_old (for the rows this thread owns) and q = A p_new,
-// where the neighbours' p_new entries are recomputed from z and p_old;
-// partial p_new.q.
-__global__ void __launch_bounds__(WG) k_spmv_pupdate(int n, const int *__restrict__ rp,
-                                                     const int *__restrict__ col,
-                                                     const double *__restrict__ val,
-                                                     const double *__restrict__ z,
-                                                     const double *__restrict__ pold,
-                                                     double *__restrict__ pnew,
-                                                     double *__restrict__ q,
-                                                     double *__restrict__ partial,
-                                                     const PcgState *__restrict__ st) {
-  if (st->done) return;
-  __shared__ double sh[WG / 64];
-  const double beta = st->beta;
-  double acc = 0.0;
-  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-    double s = 0.0;
-    const int e1 = rp[i + 1];
-    for (int e = rp[i]; e < e1; ++e) {
-      const int c = col[e];
-      s = fma(val[e], fma(beta, pold[c], z[c]), s);
-    }
-    const double pi = fma(beta, pold[i], z[i]);
-    pnew[i] = pi;
-    q[i] = s;
-    acc = fma(pi, s, acc);
-  }
-  double tot = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
 __global__ void __launch_bounds__(WG) k_dot(int n, const double *__restrict__ a,
                                             const double *__restrict__ b,
                                             double *__restrict__ partial,
@@ -80,35 +50,6 @@ __global__ void __launch_bounds__(WG) k_dot(int n, const double *__restrict__ a,
   for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) acc = fma(a[i], b[i], acc);
   double tot = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
-// x += alpha p; r -= alpha q; partial r.r and, when zold is given, the
-// partial r_new.z_old used by the flexible (Polak-Ribiere) beta
-__global__ void __launch_bounds__(WG) k_axpy_update(int n, double *__restrict__ x,
-                                                    double *__restrict__ r,
-                                                    const double *__restrict__ p,
-                                                    const double *__restrict__ q,
-                                                    const PcgState *__restrict__ st,
-                                                    double *__restrict__ partial,
-                                                    const double *__restrict__ zold,
-                                                    double *__restrict__ partial_rzo) {
-  if (st->done) return;
-  __shared__ double sh[WG / 64];
-  const double alpha = st->alpha;
-  double acc = 0.0, acc2 = 0.0;
-  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-    x[i] = fma(alpha, p[i], x[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
-    r[i] = ri;
-    acc = fma(ri, ri, acc);
-    if (zold) acc2 = fma(ri, zold[i], acc2);
-  }
-  double tot = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-  if (zold) {
-    tot = block_sum(acc2, sh);
-    if (threadIdx.x == 0) partial_rzo[blockIdx.x] = tot;
-  }
 }
 
 // r = f - Ax, partial r.r
@@ -193,7 +134,7 @@ __global__ void __launch_bounds__(WG) k_pcg_init(PcgState *st, const double *prr
     }
     st->rr = rr;
     st->rz = rz;
-    st->rz_old = rz;
+    st->rz_ring[st->it & 1] = rz;
     if (st->hist && st->it < st->hist_cap) st->hist[st->it] = rr;
     st->beta = 0.0;
     st->alpha = 0.0;
@@ -210,58 +151,115 @@ __global__ void __launch_bounds__(WG) k_pcg_init(PcgState *st, const double *prr
   }
 }
 
-__global__ void __launch_bounds__(WG) k_pcg_alpha(PcgState *st, const double *partial, int nb) {
+// CG step t, direction part.  Unless this is the first step after a (re)start,
+// iteration t-1 has just finished: r.r (partials from k_cg_update), r.z
+// (partials from the preconditioner's scatter) and, for the flexible form,
+// r.z_old decide convergence and beta; then p_new = z + beta p_old and
+// q = A p_new (neighbours' p_new entries recomputed from z and p_old), with
+// partials p_new.q.  rz of step t is kept in rz_ring[t & 1] so that no
+// workgroup reads a value this kernel is writing.
+__global__ void __launch_bounds__(WG) k_cg_dir(int n, const int *__restrict__ rp,
+                                               const int *__restrict__ col,
+                                               const double *__restrict__ val,
+                                               const double *__restrict__ z,
+                                               const double *__restrict__ pold,
+                                               double *__restrict__ pnew, double *__restrict__ q,
+                                               double *__restrict__ part_pq, PcgState *st,
+                                               const double *__restrict__ part_rr,
+                                               const double *__restrict__ part_rz,
+                                               const double *__restrict__ part_rzo, int nb, int t,
+                                               int first, int flexible) {
   if (st->done) return;
   __shared__ double sh[WG / 64];
-  const double pq = sum_partials(partial, nb, sh);
-  if (threadIdx.x == 0) {
-    st->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      st->breakdown = 1;
-      st->done = 1;
-      st->alpha = 0.0;
-    } else {
-      st->alpha = st->rz / pq;
-    }
-  }
-}
-
-__global__ void __launch_bounds__(WG) k_pcg_rr(PcgState *st, const double *partial, int nb) {
-  if (st->done) return;
-  __shared__ double sh[WG / 64];
-  const double rr = sum_partials(partial, nb, sh);
-  if (threadIdx.x == 0) {
-    st->rr = rr;
-    st->it += 1;
-    if (st->hist && st->it < st->hist_cap) st->hist[st->it] = rr;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  double beta = 0.0;
+  if (!first) {
+    const double rr = sum_partials(part_rr, nb, sh);
+    const double rz = sum_partials(part_rz, nb, sh);
+    const double rzo = flexible ? sum_partials(part_rzo, nb, sh) : 0.0;
+    int stop = 0, brk = 0;
     if (!isfinite(rr)) {
-      st->breakdown = 1;
-      st->done = 1;
-    } else if (rr <= st->tol2 || st->it >= st->maxit) {
-      st->done = 1;
+      stop = brk = 1;
+    } else if (rr <= st->tol2 || t >= st->maxit) {
+      stop = 1;
+    } else if (!isfinite(rz) || !(rz > 0.0)) {
+      stop = brk = 1;
     }
+    if (!stop) beta = (flexible ? rz - rzo : rz) / st->rz_ring[(t - 1) & 1];
+    if (lead) {
+      st->rr = rr;
+      st->it = t;
+      if (st->hist && t < st->hist_cap) st->hist[t] = rr;
+      if (stop) {
+        st->breakdown |= brk;
+        st->done = 1;
+      } else {
+        st->rz_ring[t & 1] = rz;
+        st->rz = rz;
+        st->beta = beta;
+      }
+    }
+    if (stop) return;
   }
+  double acc = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    double s = 0.0;
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; ++e) {
+      const int c = col[e];
+      s = fma(val[e], fma(beta, pold[c], z[c]), s);
+    }
+    const double pi = fma(beta, pold[i], z[i]);
+    pnew[i] = pi;
+    q[i] = s;
+    acc = fma(pi, s, acc);
+  }
+  double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
 }
 
-// beta = rz_new / rz (flexible: (rz_new - r_new.z_old) / rz)
-__global__ void __launch_bounds__(WG) k_pcg_beta(PcgState *st, const double *prz, int nb,
-                                                 const double *przo, int flexible) {
+// CG step t, update part: alpha = rz_t / p.q (p.q from this step's direction
+// partials), x += alpha p, r -= alpha q, partials r.r and, when zold is
+// given, r_new.z_old for the flexible beta.
+__global__ void __launch_bounds__(WG) k_cg_update(int n, double *__restrict__ x,
+                                                  double *__restrict__ r,
+                                                  const double *__restrict__ p,
+                                                  const double *__restrict__ q, PcgState *st,
+                                                  const double *__restrict__ part_pq, int nb, int t,
+                                                  double *__restrict__ part_rr,
+                                                  const double *__restrict__ zold,
+                                                  double *__restrict__ part_rzo) {
   if (st->done) return;
   __shared__ double sh[WG / 64];
-  const double rz = sum_partials(prz, nb, sh);
-  double rzo = 0.0;
-  if (flexible) rzo = sum_partials(przo, nb, sh);
-  if (threadIdx.x == 0) {
-    double num = flexible ? (rz - rzo) : rz;
-    if (!isfinite(rz) || !(rz > 0.0)) {
+  const double pq = sum_partials(part_pq, nb, sh);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (lead) {
+      st->pq = pq;
+      st->alpha = 0.0;
       st->breakdown = 1;
       st->done = 1;
-      st->beta = 0.0;
-    } else {
-      st->beta = num / st->rz;
-      st->rz_old = st->rz;
-      st->rz = rz;
     }
+    return;
+  }
+  const double alpha = st->rz_ring[t & 1] / pq;
+  if (lead) {
+    st->pq = pq;
+    st->alpha = alpha;
+  }
+  double acc = 0.0, acc2 = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    acc = fma(ri, ri, acc);
+    if (zold) acc2 = fma(ri, zold[i], acc2);
+  }
+  double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = tot;
+  if (zold) {
+    tot = block_sum(acc2, sh);
+    if (threadIdx.x == 0) part_rzo[blockIdx.x] = tot;
   }
 }
 
@@ -272,23 +270,26 @@ void launch_spmv(hipStream_t s, int n, const int *rp, const int *col, const doub
                      partial, done);
 }
 
-void launch_spmv_pupdate_st(hipStream_t s, int n, const int *rp, const int *col, const double *val,
-                            const double *z, const double *pold, double *pnew, double *q,
-                            double *partial, const PcgState *st) {
-  hipLaunchKernelGGL(k_spmv_pupdate, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, rp, col, val, z,
-                     pold, pnew, q, partial, st);
+void launch_cg_dir(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                   const double *z, const double *pold, double *pnew, double *q, double *part_pq,
+                   PcgState *st, const double *part_rr, const double *part_rz,
+                   const double *part_rzo, int t, int first, int flexible) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(WG), 0, s, n, rp, col, val, z, pold, pnew, q, part_pq,
+                     st, part_rr, part_rz, part_rzo, nb, t, first, flexible);
+}
+
+void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q,
+                      PcgState *st, const double *part_pq, int t, double *part_rr,
+                      const double *zold, double *part_rzo) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(WG), 0, s, n, x, r, p, q, st, part_pq, nb, t,
+                     part_rr, zold, part_rzo);
 }
 
 void launch_dot(hipStream_t s, int n, const double *a, const double *b, double *partial,
                 const int *done) {
   hipLaunchKernelGGL(k_dot, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, a, b, partial, done);
-}
-
-void launch_axpy_update_st(hipStream_t s, int n, double *x, double *r, const double *p,
-                           const double *q, const PcgState *st, double *partial,
-                           const double *zold, double *partial_rzo) {
-  hipLaunchKernelGGL(k_axpy_update, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, x, r, p, q, st,
-                     partial, zold, partial_rzo);
 }
 
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
@@ -327,19 +328,6 @@ void launch_sum_partials(hipStream_t s, const double *partial, int nb, double *o
 void launch_pcg_init(hipStream_t s, PcgState *st, const double *prr, int nbrr, const double *prz,
                      int nbrz, double rtol, int maxit) {
   hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(WG), 0, s, st, prr, nbrr, prz, nbrz, rtol, maxit);
-}
-
-void launch_pcg_alpha(hipStream_t s, PcgState *st, const double *partial, int nb) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(WG), 0, s, st, partial, nb);
-}
-
-void launch_pcg_rr(hipStream_t s, PcgState *st, const double *partial, int nb) {
-  hipLaunchKernelGGL(k_pcg_rr, dim3(1), dim3(WG), 0, s, st, partial, nb);
-}
-
-void launch_pcg_beta(hipStream_t s, PcgState *st, const double *prz, int nb, const double *przo,
-                     int flexible) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(WG), 0, s, st, prz, nb, przo, flexible);
 }
 
 }  // namespace amsp
