@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -22,11 +23,15 @@ namespace {
 
 thread_local std::string g_setup_error;
 
+// Device allocations of one handle (thread-safe: the coupling-plan thread
+// allocates while the main thread runs the setup).
 struct DevArena {
+  std::mutex mu;
   std::vector<void *> ptrs;
   size_t bytes = 0;
   ~DevArena() { release(); }
   void release() {
+    std::lock_guard<std::mutex> lk(mu);
     for (void *p : ptrs) hipFree(p);
     ptrs.clear();
     bytes = 0;
@@ -36,11 +41,13 @@ struct DevArena {
     if (count == 0) count = 1;
     void *p = nullptr;
     if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
     ptrs.push_back(p);
     bytes += count * sizeof(T);
     return static_cast<T *>(p);
   }
   void free_one(void *p) {
+    std::lock_guard<std::mutex> lk(mu);
     for (size_t k = 0; k < ptrs.size(); ++k)
       if (ptrs[k] == p) {
         hipFree(p);
@@ -156,7 +163,7 @@ static void tstop(amsp_handle *h, int cls, int idx) {
   } while (0)
 
 template <typename V>
-static typename V::value_type *upload(amsp_handle *h, const V &v, bool &ok) {
+static typename V::value_type *upload_on(amsp_handle *h, hipStream_t stream, const V &v, bool &ok) {
   using T = typename V::value_type;
   T *d = h->mem.alloc<T>(v.size());
   if (!d) {
@@ -164,11 +171,16 @@ static typename V::value_type *upload(amsp_handle *h, const V &v, bool &ok) {
     return nullptr;
   }
   if (!v.empty() &&
-      hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+      hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream) != hipSuccess) {
     ok = false;
     return nullptr;
   }
   return d;
+}
+
+template <typename V>
+static typename V::value_type *upload(amsp_handle *h, const V &v, bool &ok) {
+  return upload_on(h, h->stream, v, ok);
 }
 
 extern "C" void amsp_default_options(amsp_options *opt) {
@@ -203,21 +215,44 @@ static amsp_status sync_status(amsp_handle *h, const int *dstatus, int N, int ma
   return AMSP_OK;
 }
 
+// Device copies of the coupling plan (filled by the coupling thread, copied
+// into the handle's plans at the join).
+struct CouplingDev {
+  int *mult = nullptr, *inv_ptr = nullptr, *inv_sd = nullptr, *inv_loc = nullptr;
+  int *ext_ptr = nullptr, *ext_rowptr = nullptr, *ext_src = nullptr, *ext_loc = nullptr;
+  int npairs = 0;
+  int *pair_i = nullptr, *pair_j = nullptr, *pair_ptr = nullptr, *pair_l = nullptr,
+      *pair_e = nullptr;
+};
+
+static bool upload_coupling(amsp_handle *h, hipStream_t stream, CouplingDev &d);
+
 // Second planning phase (multiplicities, inverse map, extended regions,
 // coupled pairs) on a host thread while the device extracts, factors and
-// solves the local eigenproblems; joined before the first device use.
+// solves the local eigenproblems.  The thread also uploads the result on a
+// stream of its own and waits for the copies, so the join hands over
+// resident device arrays.
 struct CouplingTask {
   std::thread th;
   int status = AMSP_OK;
   std::string msg;
   bool joined = true;
   double run_ms = 0.0, wait_ms = 0.0;
-  void start(const amsp_csr *A, const amsp_options &opt, HostPlan *P) {
+  CouplingDev dev;
+  void start(amsp_handle *h, const amsp_csr *A, HostPlan *P, hipStream_t stream, int device) {
     joined = false;
-    th = std::thread([this, A, opt, P]() {
+    const amsp_options opt = h->opt;
+    th = std::thread([this, h, A, opt, P, stream, device]() {
       const double t = now_ms();
       try {
         status = build_plan_coupling(A, opt, *P, msg);
+        if (status == AMSP_OK) {
+          if (hipSetDevice(device) != hipSuccess || !upload_coupling(h, stream, dev) ||
+              hipStreamSynchronize(stream) != hipSuccess) {
+            status = AMSP_ERR_OOM;
+            msg = "device allocation or upload failed (coupling plan)";
+          }
+        }
       } catch (const std::bad_alloc &) {
         status = AMSP_ERR_OOM;
         msg = "host allocation failed during planning";
@@ -236,8 +271,6 @@ struct CouplingTask {
   }
   ~CouplingTask() { join(); }
 };
-
-static amsp_status upload_coupling(amsp_handle *h);
 
 // A second stream (default priority) with two events, released on scope exit
 // after the stream has drained.
@@ -265,8 +298,12 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   const bool mixed = h->opt.precision != AMSP_FP64;
   double t0 = now_ms();
   bool ok = true;
+  SideStream up;  // declared before the task: outlives the thread that uses it
+  HIP_TRY(up.create());
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
   CouplingTask coupling;
-  coupling.start(A, h->opt, &P);
+  coupling.start(h, A, &P, up.s, device);
   auto join_coupling = [&]() -> amsp_status {
     const int cs = coupling.join();
     h->sinfo.coupling_ms = coupling.run_ms;
@@ -275,7 +312,24 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       h->err = coupling.msg;
       return (amsp_status)cs;
     }
-    return upload_coupling(h);
+    const CouplingDev &d = coupling.dev;
+    Plan &pl = h->plan;
+    CoarsePlan &cp = h->cplan;
+    pl.mult = d.mult;
+    h->inv_ptr = d.inv_ptr;
+    h->inv_sd = d.inv_sd;
+    h->inv_loc = d.inv_loc;
+    cp.ext_ptr = d.ext_ptr;
+    cp.ext_rowptr = d.ext_rowptr;
+    cp.ext_src = d.ext_src;
+    cp.ext_loc = d.ext_loc;
+    cp.npairs = d.npairs;
+    cp.pair_i = d.pair_i;
+    cp.pair_j = d.pair_j;
+    cp.pair_ptr = d.pair_ptr;
+    cp.pair_l = d.pair_l;
+    cp.pair_e = d.pair_e;
+    return AMSP_OK;
   };
   const double host_plan_ms = h->sinfo.phase_ms[0];
   // --- upload matrix and plan
@@ -589,32 +643,26 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   return AMSP_OK;
 }
 
-static amsp_status upload_coupling(amsp_handle *h) {
-  HostPlan &P = h->hp;
-  Plan &p = h->plan;
-  CoarsePlan &c = h->cplan;
+static bool upload_coupling(amsp_handle *h, hipStream_t stream, CouplingDev &d) {
+  const HostPlan &P = h->hp;
   bool ok = true;
-  p.mult = upload(h, P.mult, ok);
-  h->inv_ptr = upload(h, P.inv_ptr, ok);
-  h->inv_sd = upload(h, P.inv_sd, ok);
-  h->inv_loc = upload(h, P.inv_loc, ok);
+  d.mult = upload_on(h, stream, P.mult, ok);
+  d.inv_ptr = upload_on(h, stream, P.inv_ptr, ok);
+  d.inv_sd = upload_on(h, stream, P.inv_sd, ok);
+  d.inv_loc = upload_on(h, stream, P.inv_loc, ok);
   if (h->nc > 0) {
-    c.ext_ptr = upload(h, P.ext_ptr, ok);
-    c.ext_rowptr = upload(h, P.ext_rowptr, ok);
-    c.ext_src = upload(h, P.ext_src, ok);
-    c.ext_loc = upload(h, P.ext_loc, ok);
-    c.npairs = (int)P.pair_i.size();
-    c.pair_i = upload(h, P.pair_i, ok);
-    c.pair_j = upload(h, P.pair_j, ok);
-    c.pair_ptr = upload(h, P.pair_ptr, ok);
-    c.pair_l = upload(h, P.pair_l, ok);
-    c.pair_e = upload(h, P.pair_e, ok);
+    d.ext_ptr = upload_on(h, stream, P.ext_ptr, ok);
+    d.ext_rowptr = upload_on(h, stream, P.ext_rowptr, ok);
+    d.ext_src = upload_on(h, stream, P.ext_src, ok);
+    d.ext_loc = upload_on(h, stream, P.ext_loc, ok);
+    d.npairs = (int)P.pair_i.size();
+    d.pair_i = upload_on(h, stream, P.pair_i, ok);
+    d.pair_j = upload_on(h, stream, P.pair_j, ok);
+    d.pair_ptr = upload_on(h, stream, P.pair_ptr, ok);
+    d.pair_l = upload_on(h, stream, P.pair_l, ok);
+    d.pair_e = upload_on(h, stream, P.pair_e, ok);
   }
-  if (!ok) {
-    h->err = "device allocation or upload failed (coupling plan)";
-    return AMSP_ERR_OOM;
-  }
-  return AMSP_OK;
+  return ok;
 }
 
 extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, int32_t nparts,
