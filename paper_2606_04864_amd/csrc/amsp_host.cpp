@@ -419,11 +419,13 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   ALLOC(h->lam, double, (size_t)h->N * (h->nev + 1));
   launch_fill(h->stream, (size_t)h->N * (h->nev + 1), h->lam, std::nan(""));
   if (h->nev > 0) {
-    double *facB, *X, *Yb, *GK, *CC;
+    double *facB, *X, *Yb, *BY, *bval, *GK, *CC;
     int *conv;
     ALLOC(facB, double, fac_elems);
     ALLOC(X, double, (size_t)sum_npad * EIGP);
     ALLOC(Yb, double, (size_t)sum_npad * EIGP);
+    ALLOC(BY, double, (size_t)sum_npad * EIGP);
+    ALLOC(bval, double, P.loc_col.size());
     ALLOC(GK, double, (size_t)h->N * 2 * EIGP * EIGP);
     ALLOC(CC, double, (size_t)h->N * (EIGP * EIGP + EIGP));
     ALLOC(conv, int, h->N);
@@ -449,6 +451,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       facB = nullptr;
     }
     launch_eig_init(h->stream, p, h->sdiag, X);
+    launch_eig_bval(h->stream, p, h->val, h->sdiag, bval);
     const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-5 : 1e-12);
     std::vector<int> hconv(h->N);
     int sweeps = 0, unconv = h->N;
@@ -457,7 +460,8 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
         launch_profile_solve_block<float>(h->stream, p, facB32, X, Yb, conv);
       else
         launch_profile_solve_block<double>(h->stream, p, facB, X, Yb, conv);
-      launch_eig_rr(h->stream, p, h->val, h->sdiag, Yb, X, GK, CC, tol, conv, h->lam);
+      launch_eig_rr(h->stream, p, P.max_ni, h->val, h->sdiag, bval, Yb, BY, X, GK, CC, tol, conv,
+                    h->lam);
       sweeps = it;
       if (it >= 4 && (it % 2 == 0 || it == h->opt.eig_maxit)) {
         HIP_TRY(hipGetLastError());
@@ -486,6 +490,8 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     if (facB32) h->mem.free_one(facB32);
     h->mem.free_one(X);
     h->mem.free_one(Yb);
+    h->mem.free_one(BY);
+    h->mem.free_one(bval);
     h->mem.free_one(GK);
     h->mem.free_one(CC);
     h->mem.free_one(conv);

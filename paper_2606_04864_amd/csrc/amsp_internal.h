@@ -91,12 +91,15 @@ void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *i
 
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
+// Off-diagonal values of the scaled local operators B_i per local CSR entry.
+void launch_eig_bval(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
+                     double *bval);
 // Rayleigh-Ritz step on the solve output Y, writing the Ritz vectors into X
 // (distinct buffer), residuals, convergence flags and eigenvalues.
-// GK: N*2*EIGP*EIGP doubles; CC: N*(EIGP*EIGP+EIGP) doubles.
-void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
-                   const double *Y, double *X, double *GK, double *CC, double tol, int *conv,
-                   double *lam);
+// BY: scratch like Y; GK: N*2*EIGP*EIGP doubles; CC: N*(EIGP*EIGP+EIGP).
+void launch_eig_rr(hipStream_t s, const Plan &p, int max_ni, const double *val,
+                   const double *sdiag, const double *bval, const double *Y, double *BY, double *X,
+                   double *GK, double *CC, double tol, int *conv, double *lam);
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
                         double *phi, int pou);
 void launch_basis_convert(hipStream_t s, const double *phi, void *dst, size_t count, int bf16);

@@ -61,7 +61,9 @@ __device__ void jacobi16(double *H, double *V, double *cs, int *flag) {
       }
       off = wave_sum(off);
       tot = wave_sum(tot);
-      if (t == 0) *flag = (off <= 1e-32 * tot) ? 1 : 0;
+      // stop at an off-diagonal level of 1e-14 relative: rounding keeps the
+      // off-diagonal part near 1e-16 relative, so a tighter test is never met
+      if (t == 0) *flag = (off <= 1e-28 * tot) ? 1 : 0;
     }
     __syncthreads();
     if (*flag) break;
@@ -122,35 +124,61 @@ __device__ void jacobi16(double *H, double *V, double *cs, int *flag) {
 // Rayleigh-Ritz on the span of the solve output Y (n_i x EIGP), without
 // forming an orthonormal basis: with G = Y^T Y = L L^T and K = Y^T B Y, the
 // Ritz problem is H = L^{-1} K L^{-T}, H V = V Theta, and the Ritz vectors
-// are X = Y C with C = L^{-T} V.  Two passes over Y per sweep.
+// are X = Y C with C = L^{-T} V.  Per sweep: BY = B Y (flat sparse product),
+// G and K (MFMA over Y and BY), the small Ritz problems, then X = Y C and
+// the residuals (BY) C - X Theta (MFMA again).
 
-// B_i y for one local row l, 16 columns, from the sparse unit-diagonal B_i
-// (thread holds column a only: returns (B y)[l][a]).
-__device__ __forceinline__ double b_row_col(const Plan &p, const double *__restrict__ val,
-                                            const double *__restrict__ sdiag, const double *Y,
-                                            int r0, int l, int a) {
-  double acc = Y[(size_t)l * EIGP + a];
-  const double sl = sdiag[r0 + l];
-  for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
-    const int c = p.loc_col[e];
-    if (c == l) continue;
-    acc = fma(val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]), Y[(size_t)c * EIGP + a], acc);
+// Off-diagonal entries of B_i = S^{-1/2} hat A_i S^{-1/2} for every local CSR
+// entry; 0 on the diagonal (B_i has a unit diagonal).  Once per setup.
+__global__ void __launch_bounds__(WG) k_eig_bval(Plan p, const double *__restrict__ val,
+                                                 const double *__restrict__ sdiag,
+                                                 double *__restrict__ bval) {
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  for (int l = threadIdx.x; l < ni; l += WG) {
+    const double sl = sdiag[r0 + l];
+    for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
+      const int c = p.loc_col[e];
+      bval[e] = (c == l) ? 0.0 : val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]);
+    }
   }
-  return acc;
 }
 
-// Pass 1: G = Y^T Y and K = Y^T (B Y) into GK[i][2*EIGP*EIGP].  Thread
-// (group g, column a) handles rows g, g+16, ...; the 16 threads of a group
-// share one row's entries through lane shuffles.  Regions with n_i <= EIGP
-// store G = I and K = dense B_i padded with a diagonal above [0, 2].
+// BY = B Y for the real rows of every unconverged region: grid (row block,
+// region), 16 rows per workgroup, thread = (row, column); 16 consecutive
+// threads share a row and read 128 contiguous bytes of each neighbour row.
+__global__ void __launch_bounds__(WG) k_eig_spmm(Plan p, const double *__restrict__ bval,
+                                                 const double *__restrict__ Y,
+                                                 double *__restrict__ BY,
+                                                 const int *__restrict__ conv) {
+  const int i = blockIdx.y;
+  if (conv[i]) return;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int l = blockIdx.x * (WG / EIGP) + (threadIdx.x >> 4), a = threadIdx.x & 15;
+  if (l >= ni) return;
+  const size_t base = (size_t)p.vp_ptr[i] * EIGP;
+  double acc = Y[base + (size_t)l * EIGP + a];
+  const int e1 = p.loc_rowptr[r0 + l + 1];
+  for (int e = p.loc_rowptr[r0 + l]; e < e1; ++e)
+    acc = fma(bval[e], Y[base + (size_t)p.loc_col[e] * EIGP + a], acc);
+  BY[base + (size_t)l * EIGP + a] = acc;
+}
+
+// G = Y^T Y and K = Y^T (B Y) into GK[i][2*EIGP*EIGP].  One MFMA 16x16x4
+// consumes four rows: lane l supplies Y[row0 + l/16][l%16] as both operands
+// (for K, BY as the second), so each wavefront reads 512 contiguous bytes
+// per step; wavefronts take interleaved four-row blocks and their
+// accumulators are added in a fixed order.  Regions with n_i <= EIGP store
+// G = I and K = dense B_i padded with a diagonal above [0, 2].
 __global__ void __launch_bounds__(WG) k_eig_gram(Plan p, const double *__restrict__ val,
                                                  const double *__restrict__ sdiag,
                                                  const double *__restrict__ Y,
+                                                 const double *__restrict__ BY,
                                                  double *__restrict__ GK,
                                                  const int *__restrict__ conv) {
   const int i = blockIdx.x;
   if (conv[i]) return;
-  __shared__ double red[(WG / EIGP) * EIGP * EIGP];
+  __shared__ double red[WG / 64][2][EIGP * EIGP];
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int t = threadIdx.x;
   double *out = GK + (size_t)i * 2 * EIGP * EIGP;
@@ -166,34 +194,45 @@ __global__ void __launch_bounds__(WG) k_eig_gram(Plan p, const double *__restric
     out[EIGP * EIGP + t] = h;
     return;
   }
-  const double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
-  const int g = t / EIGP, a = t % EIGP;
-  double gacc[EIGP], kacc[EIGP];
-#pragma unroll
-  for (int b = 0; b < EIGP; ++b) gacc[b] = kacc[b] = 0.0;
-  for (int l = g; l < ni; l += WG / EIGP) {
-    const double ya = Yi[(size_t)l * EIGP + a];
-    const double bya = b_row_col(p, val, sdiag, Yi, r0, l, a);
-#pragma unroll
-    for (int b = 0; b < EIGP; ++b) {
-      const double yb = __shfl(ya, (threadIdx.x & 48) + b, 64);
-      const double byb = __shfl(bya, (threadIdx.x & 48) + b, 64);
-      gacc[b] = fma(ya, yb, gacc[b]);
-      kacc[b] = fma(ya, byb, kacc[b]);
-    }
+  const size_t base = (size_t)p.vp_ptr[i] * EIGP;
+  const int w = t >> 6, lane = t & 63;
+  d4 g = {0.0, 0.0, 0.0, 0.0}, k = {0.0, 0.0, 0.0, 0.0};
+  // rows rb .. rb+3 per step; ni > 16 so at least one full step per wave
+  int rb = 4 * w;
+  for (; rb + 16 < ni; rb += 32) {  // two steps per iteration (loads in flight)
+    const int ra = rb + (lane >> 4), rc = ra + 16;
+    const double ya = Y[base + (size_t)ra * EIGP + (lane & 15)];
+    const double ba = BY[base + (size_t)ra * EIGP + (lane & 15)];
+    const double yc = rc < ni ? Y[base + (size_t)rc * EIGP + (lane & 15)] : 0.0;
+    const double bc = rc < ni ? BY[base + (size_t)rc * EIGP + (lane & 15)] : 0.0;
+    g = mfma16x16x4(ya, ya, g);
+    k = mfma16x16x4(ya, ba, k);
+    g = mfma16x16x4(yc, yc, g);
+    k = mfma16x16x4(yc, bc, k);
   }
-  // fixed-order sums over the 16 row groups: G, then K
-  for (int m = 0; m < 2; ++m) {
+  for (; rb < ni; rb += 16) {
+    const int ra = rb + (lane >> 4);
+    const double ya = ra < ni ? Y[base + (size_t)ra * EIGP + (lane & 15)] : 0.0;
+    const double ba = ra < ni ? BY[base + (size_t)ra * EIGP + (lane & 15)] : 0.0;
+    g = mfma16x16x4(ya, ya, g);
+    k = mfma16x16x4(ya, ba, k);
+  }
+  // D register q holds entry (lane/16 + 4q, lane%16)
 #pragma unroll
-    for (int b = 0; b < EIGP; ++b) red[(g * EIGP + a) * EIGP + b] = m == 0 ? gacc[b] : kacc[b];
-    __syncthreads();
-    {
-      const int aa = t / EIGP, bb = t % EIGP;
-      double s = 0.0;
-      for (int gg = 0; gg < WG / EIGP; ++gg) s += red[(gg * EIGP + aa) * EIGP + bb];
-      out[m * EIGP * EIGP + t] = s;
+  for (int q = 0; q < 4; ++q) {
+    const int e = ((lane >> 4) + 4 * q) * EIGP + (lane & 15);
+    red[w][0][e] = g[q];
+    red[w][1][e] = k[q];
+  }
+  __syncthreads();
+  {
+    double sg = 0.0, sk = 0.0;
+    for (int ww = 0; ww < WG / 64; ++ww) {
+      sg += red[ww][0][t];
+      sk += red[ww][1][t];
     }
-    __syncthreads();
+    out[t] = sg;
+    out[EIGP * EIGP + t] = sk;
   }
 }
 
@@ -302,12 +341,14 @@ __global__ void __launch_bounds__(64) k_eig_ritz(const double *__restrict__ GK,
   if (t < EIGP) out[EIGP * EIGP + t] = theta[t];
 }
 
-// Pass 3: X = Y C, residuals ||B x_j - theta_j x_j|| from (B Y) C for the
-// m_i + 1 lowest pairs, convergence flags and eigenvalues.  Y and X must be
-// distinct buffers (neighbour rows of Y are read while X is written).
-__global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restrict__ val,
-                                                   const double *__restrict__ sdiag,
-                                                   const double *__restrict__ Y,
+// X = Y C and residuals ||B x_j - theta_j x_j|| = ||(BY) C - X Theta||_j for
+// the m_i + 1 lowest pairs, convergence flags and eigenvalues.  MFMA over
+// 16-row blocks with the K slots permuted (slot q of step s stands for
+// k = 4q + s), so a lane reads four contiguous entries of one row of Y and
+// of BY and holds C[4q + s][l%16] in registers.  Y and X are distinct
+// buffers; padded rows of X are zeroed (they feed the next block solve).
+__global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restrict__ Y,
+                                                   const double *__restrict__ BY,
                                                    double *__restrict__ X,
                                                    const double *__restrict__ CC, double tol,
                                                    int *__restrict__ conv,
@@ -315,7 +356,7 @@ __global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restr
   const int i = blockIdx.x;
   if (conv[i]) return;
   __shared__ double C[EIGP * EIGP], theta[EIGP];
-  __shared__ double res[EIGP][WG / 64];
+  __shared__ double res[WG / 64][EIGP];
   const int t = threadIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int npad = p.vp_ptr[i + 1] - p.vp_ptr[i];
@@ -324,60 +365,59 @@ __global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restr
   C[t] = in[t];
   if (t < EIGP) theta[t] = in[EIGP * EIGP + t];
   __syncthreads();
-  double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
-  const double *Yi = Y + (size_t)p.vp_ptr[i] * EIGP;
+  const size_t base = (size_t)p.vp_ptr[i] * EIGP;
   const bool small = ni <= EIGP;
   const int nchk = (m + 1 < ni ? m + 1 : ni);
-  double rs[EIGP];
-#pragma unroll
-  for (int j = 0; j < EIGP; ++j) rs[j] = 0.0;
+  const int w = t >> 6, lane = t & 63, q = lane >> 4, col = lane & 15;
+  double rs = 0.0;  // this lane's sum of squared residuals of column col
   if (small) {
     for (int e = t; e < npad * EIGP; e += WG) {
       const int l = e / EIGP, j = e % EIGP;
-      Xi[e] = (l < ni) ? C[l * EIGP + j] : 0.0;
+      X[base + e] = (l < ni) ? C[l * EIGP + j] : 0.0;
     }
   } else {
-    for (int l = t; l < ni; l += WG) {
-      __asm__ volatile("" ::: "memory");  // keep C in LDS (see cholqr_pass)
-      double y[EIGP], by[EIGP];
-      const double sl = sdiag[r0 + l];
+    double cb[4];
 #pragma unroll
-      for (int k = 0; k < EIGP; ++k) y[k] = by[k] = Yi[(size_t)l * EIGP + k];
-      for (int e = p.loc_rowptr[r0 + l]; e < p.loc_rowptr[r0 + l + 1]; ++e) {
-        const int c = p.loc_col[e];
-        if (c == l) continue;
-        const double b = val[p.loc_src[e]] / sqrt(sl * sdiag[r0 + c]);
+    for (int st = 0; st < 4; ++st) cb[st] = C[(4 * q + st) * EIGP + col];
+    const double th = theta[col];
+    for (int rb = 16 * w; rb < npad; rb += 64) {
+      const int ra = rb + col;  // A operand row: lane%16
+      d4 x = {0.0, 0.0, 0.0, 0.0}, bx = {0.0, 0.0, 0.0, 0.0};
+      if (rb < ni) {
+        double ya[4], ba[4];
 #pragma unroll
-        for (int k = 0; k < EIGP; ++k) by[k] = fma(b, Yi[(size_t)c * EIGP + k], by[k]);
-      }
-#pragma unroll
-      for (int j = 0; j < EIGP; ++j) {
-        double x = 0.0, bx = 0.0;
-#pragma unroll
-        for (int k = 0; k < EIGP; ++k) {
-          const double c = C[k * EIGP + j];
-          x = fma(y[k], c, x);
-          bx = fma(by[k], c, bx);
+        for (int st = 0; st < 4; ++st) {
+          ya[st] = ra < ni ? Y[base + (size_t)ra * EIGP + 4 * q + st] : 0.0;
+          ba[st] = ra < ni ? BY[base + (size_t)ra * EIGP + 4 * q + st] : 0.0;
         }
-        Xi[(size_t)l * EIGP + j] = x;
-        const double rr = bx - theta[j] * x;
-        rs[j] = fma(rr, rr, rs[j]);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          x = mfma16x16x4(ya[st], cb[st], x);
+          bx = mfma16x16x4(ba[st], cb[st], bx);
+        }
+      }
+      // D register u holds row rb + q + 4u, column col
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = rb + q + 4 * u;
+        const bool real = row < ni;
+        X[base + (size_t)row * EIGP + col] = real ? x[u] : 0.0;
+        const double rr = real ? bx[u] - th * x[u] : 0.0;
+        rs = fma(rr, rr, rs);
       }
     }
   }
-  const int lane = t & 63, w = t >> 6;
-#pragma unroll
-  for (int j = 0; j < EIGP; ++j) {
-    double s = wave_sum(rs[j]);
-    if (lane == 0) res[j][w] = s;
-  }
+  // column sums: lanes col, col+16, col+32, col+48, then wavefronts in order
+  rs += __shfl_xor(rs, 16, 64);
+  rs += __shfl_xor(rs, 32, 64);
+  if (lane < EIGP) res[w][lane] = rs;
   __syncthreads();
   if (t == 0) {
     double worst = 0.0;
     if (!small) {
       for (int j = 0; j < nchk; ++j) {
         double s = 0.0;
-        for (int ww = 0; ww < WG / 64; ++ww) s += res[j][ww];
+        for (int ww = 0; ww < WG / 64; ++ww) s += res[ww][j];
         s = sqrt(s);
         if (s > worst || !(s == s)) worst = (s == s) ? s : 1e300;
       }
@@ -473,13 +513,20 @@ void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *
   hipLaunchKernelGGL(k_eig_init, dim3(p.N), dim3(WG), 0, s, p, sdiag, X);
 }
 
-void launch_eig_rr(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
-                   const double *Y, double *X, double *GK, double *CC, double tol, int *conv,
-                   double *lam) {
-  hipLaunchKernelGGL(k_eig_gram, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, Y, GK, conv);
+void launch_eig_bval(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
+                     double *bval) {
+  hipLaunchKernelGGL(k_eig_bval, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, bval);
+}
+
+void launch_eig_rr(hipStream_t s, const Plan &p, int max_ni, const double *val,
+                   const double *sdiag, const double *bval, const double *Y, double *BY, double *X,
+                   double *GK, double *CC, double tol, int *conv, double *lam) {
+  const int rows_per_wg = WG / EIGP;
+  hipLaunchKernelGGL(k_eig_spmm, dim3((max_ni + rows_per_wg - 1) / rows_per_wg, p.N), dim3(WG), 0,
+                     s, p, bval, Y, BY, conv);
+  hipLaunchKernelGGL(k_eig_gram, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, Y, BY, GK, conv);
   hipLaunchKernelGGL(k_eig_ritz, dim3(p.N), dim3(64), 0, s, GK, CC, conv);
-  hipLaunchKernelGGL(k_eig_finish, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, Y, X, CC, tol, conv,
-                     lam);
+  hipLaunchKernelGGL(k_eig_finish, dim3(p.N), dim3(WG), 0, s, p, Y, BY, X, CC, tol, conv, lam);
 }
 
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
