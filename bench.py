@@ -130,6 +130,46 @@ def cpu_baseline(w, iterations, sample_sd=24):
             "setup_ms": setup_s * 1e3, "apply_ms": apply_s * 1e3}
 
 
+COPY_BYTES = 256 << 20
+
+
+def copy_calibration(torch):
+    """Five device-to-device copies of COPY_BYTES each (read COPY_BYTES, write
+    COPY_BYTES per launch): the reference that turns the FETCH_SIZE and
+    WRITE_SIZE counters of a profiled run into HBM bytes."""
+    src = torch.rand(COPY_BYTES // 4, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 5 copies of {COPY_BYTES} bytes")
+
+
+def traffic_from_profile():
+    """HBM bytes per local-apply launch from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "local_apply_traffic_gauss1024.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    import hashlib
+    import re
+    m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", text)
+    b = re.search(r"HBM bytes per launch: (\d+)", text)
+    if not m or not b:
+        return None
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2606_04864_amd", "csrc", name), "rb").read())
+    return int(b.group(1)) if h.hexdigest() == m.group(1) else None
+
+
+# sources that define the local-apply kernel (a change invalidates its counters)
+TRAFFIC_SOURCES = ("k_local.hip", "k_common.h", "amsp_consts.h", "amsp_internal.h")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,12 +178,18 @@ def main():
     ap.add_argument("--workload", default="gauss1024")
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies of known size (reference for the HBM "
+                         "byte counters FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the preconditioner runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import paper_2606_04864_amd as P
     import workloads as W
     t = time.perf_counter()
@@ -217,7 +263,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_local_apply (gather, restriction, profile "
                                                "forward/backward solves)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(),
                      "avg_launch_ms": round(avg_ms, 5), "launches": kl,
                      "timed_every_nth_launch": TIMING_STRIDE,
                      "bytes_per_launch": rec[-1]["local_apply_bytes"]},

@@ -135,6 +135,27 @@ static int tstart(amsp_handle *h, int cls) {
   return idx;
 }
 
+// Like tstart, but for a single kernel launched with its own start/stop
+// events (hipExtLaunchKernelGGL): returns both events unrecorded, or nulls.
+static int tpair(amsp_handle *h, int cls, hipEvent_t *e0, hipEvent_t *e1) {
+  *e0 = *e1 = nullptr;
+  if (!h->timing_active || !(h->opt.timing & (1 << cls))) return -1;
+  const int k = h->ev_count[cls]++;
+  if (k % std::max(1, h->opt.timing_stride) != 0) return -1;
+  const int idx = (int)h->ev_used;
+  *e0 = next_event(h);
+  *e1 = next_event(h);
+  if (!*e0 || !*e1) {
+    *e0 = *e1 = nullptr;
+    return -1;
+  }
+  return idx;
+}
+
+static void tpair_done(amsp_handle *h, int cls, int idx) {
+  if (idx >= 0) h->ev_rec.emplace_back(cls, idx);
+}
+
 static void tstop(amsp_handle *h, int cls, int idx) {
   if (idx < 0) return;
   hipEvent_t e = next_event(h);
@@ -744,20 +765,22 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
   const bool mixed = h->opt.precision != AMSP_FP64;
   const bool bf = h->opt.precision == AMSP_MIXED_BF16;
-  int tk = tstart(h, 1);
+  hipEvent_t e0, e1;
+  int tk = tpair(h, 1, &e0, &e1);
   if (!mixed) {
     launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->fac64, h->phi64,
-                                                 h->xloc, h->cvec, do_local, do_coarse, done);
+                                                 h->xloc, h->cvec, do_local, do_coarse, done, e0,
+                                                 e1);
   } else if (!bf) {
     launch_local_apply_t<float, float, float>(h->stream, p, h->hp.max_npad, r, h->fac32,
                                               (const float *)h->phi_lo, h->xloc, h->cvec, do_local,
-                                              do_coarse, done);
+                                              do_coarse, done, e0, e1);
   } else {
     launch_local_apply_t<float, float, __hip_bfloat16>(h->stream, p, h->hp.max_npad, r, h->fac32,
                                                        (const __hip_bfloat16 *)h->phi_lo, h->xloc,
-                                                       h->cvec, do_local, do_coarse, done);
+                                                       h->cvec, do_local, do_coarse, done, e0, e1);
   }
-  tstop(h, 1, tk);
+  tpair_done(h, 1, tk);
   if (do_coarse) {
     tk = tstart(h, 2);
     if (!mixed) {

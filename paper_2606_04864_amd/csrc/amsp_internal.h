@@ -75,9 +75,12 @@ void launch_tiles_to_f32(hipStream_t s, const double *src, float *dst, size_t co
 // Local apply: gather r, coarse restriction into c (do_coarse), profile
 // forward/backward solve into xloc (do_local).  T factor, C compute, TB basis type.
 template <typename T, typename C, typename TB>
+// ev_start / ev_stop (optional, created with timing): bound to the dispatch
+// itself (no extra packets in the stream).
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
                           const T *tiles, const TB *phi, double *xloc, double *cvec, int do_local,
-                          int do_coarse, const int *done);
+                          int do_coarse, const int *done, hipEvent_t ev_start = nullptr,
+                          hipEvent_t ev_stop = nullptr);
 // Y = (L L^T)^{-1} X on row-major [rows][EIGP] padded blocks (Y may equal X).
 template <typename T>
 void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, const double *X,

@@ -197,16 +197,13 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     msg = "row_ptr[0] must be 0, row_ptr[n] == nnz < 2^31";
     return AMSP_ERR_CSR;
   }
-  // row structure (sequential: cheap, and the first error is well defined)
-  for (int64_t i = 0; i < n; ++i)
-    if (rp[i + 1] < rp[i]) {
-      msg = "row_ptr not monotone at row " + std::to_string(i);
-      return AMSP_ERR_CSR;
-    }
-  // per-row checks in parallel chunks; the lowest failing row is reported
+  // Pass 1 over row chunks: row structure, column range and order, finite
+  // values, diagonal present, max |a|, counts of strictly upper / lower
+  // entries; each chunk records its first failing row (the lowest failing
+  // row overall is reported).
   const int nchunk = 64;
   std::vector<int> cerr(nchunk, 0);
-  std::vector<int64_t> crow(nchunk, -1);
+  std::vector<int64_t> crow(nchunk, -1), cup(nchunk, 0), clo(nchunk, 0);
   std::vector<double> cmax(nchunk, 0.0);
   auto chunk_rows = [&](int c, int64_t &r0, int64_t &r1) {
     r0 = n * c / nchunk;
@@ -216,7 +213,13 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     int64_t r0, r1;
     chunk_rows(c, r0, r1);
     double amax = 0.0;
+    int64_t up = 0, lo = 0;
     for (int64_t i = r0; i < r1; ++i) {
+      if (rp[i] < 0 || rp[i + 1] < rp[i] || rp[i + 1] > A->nnz) {
+        cerr[c] = 4;
+        crow[c] = i;
+        return;
+      }
       bool diag = false;
       for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
         const int32_t cc = A->col_idx[e];
@@ -226,6 +229,8 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
           return;
         }
         if (cc == i) diag = true;
+        up += (cc > i);
+        lo += (cc < i);
         amax = std::max(amax, std::fabs(A->val[e]));
       }
       if (!diag) {
@@ -235,8 +240,14 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
       }
     }
     cmax[c] = amax;
+    cup[c] = up;
+    clo[c] = lo;
   });
   for (int c = 0; c < nchunk; ++c) {
+    if (cerr[c] == 4) {
+      msg = "row_ptr not monotone at row " + std::to_string(crow[c]);
+      return AMSP_ERR_CSR;
+    }
     if (cerr[c] == 1) {
       msg = "column index out of range, unsorted, or non-finite value in row " + std::to_string(crow[c]);
       return AMSP_ERR_CSR;
@@ -247,7 +258,15 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     }
   }
   double amax = 0.0;
-  for (double v : cmax) amax = std::max(amax, v);
+  int64_t nup = 0, nlo = 0;
+  for (int c = 0; c < nchunk; ++c) {
+    amax = std::max(amax, cmax[c]);
+    nup += cup[c];
+    nlo += clo[c];
+  }
+  // Pass 2: every strictly upper entry (i, c) has its mirror (c, i) with the
+  // same value up to 1e-14 max|a|; with as many lower as upper entries this
+  // pairs them all, so the pattern and the values are symmetric.
   const double tol = 1e-14 * amax;
   parallel_for(nchunk, [&](int c) {
     int64_t r0, r1;
@@ -255,7 +274,7 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     for (int64_t i = r0; i < r1; ++i) {
       for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
         const int32_t cc = A->col_idx[e];
-        if (cc == i) continue;
+        if (cc <= i) continue;
         const int32_t *b = A->col_idx + rp[cc], *en = A->col_idx + rp[cc + 1];
         const int32_t *f = std::lower_bound(b, en, (int32_t)i);
         if (f == en || *f != i || std::fabs(A->val[rp[cc] + (f - b)] - A->val[e]) > tol) {
@@ -271,82 +290,115 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
       msg = "matrix not symmetric in row " + std::to_string(crow[c]);
       return AMSP_ERR_NONSYM;
     }
-  std::vector<int64_t> cnt(nparts, 0);
-  for (int64_t j = 0; j < n; ++j) {
-    if (part[j] < 0 || part[j] >= nparts) {
-      msg = "partition value out of range at dof " + std::to_string(j);
+  if (nup != nlo) {
+    msg = "matrix pattern not symmetric (upper and lower entry counts differ)";
+    return AMSP_ERR_NONSYM;
+  }
+  // partition values in range and every part non-empty (chunk counts, or
+  // one serial count when there are very many parts)
+  const int pchunks = nparts <= 4096 ? nchunk : 1;
+  auto prow = [&](int c, int64_t &r0, int64_t &r1) {
+    r0 = n * c / pchunks;
+    r1 = n * (c + 1) / pchunks;
+  };
+  std::vector<std::vector<int64_t>> pc(pchunks);
+  parallel_for(pchunks, [&](int c) {
+    int64_t r0, r1;
+    prow(c, r0, r1);
+    pc[c].assign(nparts, 0);
+    for (int64_t j = r0; j < r1; ++j) {
+      if (part[j] < 0 || part[j] >= nparts) {
+        cerr[c] = 5;
+        crow[c] = j;
+        return;
+      }
+      pc[c][part[j]]++;
+    }
+  });
+  for (int c = 0; c < pchunks; ++c)
+    if (cerr[c] == 5) {
+      msg = "partition value out of range at dof " + std::to_string(crow[c]);
       return AMSP_ERR_PARTITION;
     }
-    cnt[part[j]]++;
-  }
-  for (int32_t k = 0; k < nparts; ++k)
-    if (cnt[k] == 0) {
+  for (int32_t k = 0; k < nparts; ++k) {
+    int64_t cnt = 0;
+    for (int c = 0; c < pchunks; ++c) cnt += pc[c][k];
+    if (cnt == 0) {
       msg = "empty subdomain " + std::to_string(k);
       return AMSP_ERR_PARTITION;
     }
+  }
   return AMSP_OK;
 }
 
+// Work arrays of rcm_order, reused across calls by one worker.
+struct RcmWork {
+  std::vector<int> deg, level, q, touched, nb;
+  std::vector<char> vis;
+};
+
 // Reverse Cuthill-McKee order of a small graph given as adjacency lists
-// (local indices).  Each component starts from a pseudo-peripheral node;
-// neighbours are visited by increasing degree, ties by index.
+// (local indices).  Each component starts from a pseudo-peripheral node
+// (George-Liu search, at most four BFS passes); neighbours are visited by
+// increasing degree, ties by index.
 static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &adj,
-                      std::vector<int> &order) {
+                      std::vector<int> &order, RcmWork &W) {
   const int n = (int)adj_ptr.size() - 1;
-  std::vector<int> deg(n), level(n, -1);
-  for (int v = 0; v < n; ++v) deg[v] = adj_ptr[v + 1] - adj_ptr[v];
-  std::vector<char> vis(n, 0);
+  W.deg.resize(n);
+  W.level.assign(n, -1);
+  W.vis.assign(n, 0);
+  for (int v = 0; v < n; ++v) W.deg[v] = adj_ptr[v + 1] - adj_ptr[v];
+  const int *deg = W.deg.data();
+  int *level = W.level.data();
+  char *vis = W.vis.data();
   order.clear();
   order.reserve(n);
-  std::vector<int> q;
-  q.reserve(n);
+  W.q.resize(n);
+  // BFS within the component (unvisited nodes); returns the min-degree node
+  // of the last level and its eccentricity
   auto bfs_last_min = [&](int s, int &ecc) {
-    // BFS within the component (unvisited nodes); return min-degree node of the last level
-    q.clear();
-    q.push_back(s);
-    std::vector<int> touched{s};
+    int *q = W.q.data();
+    int head = 0, tail = 0;
+    q[tail++] = s;
     level[s] = 0;
-    size_t h = 0;
     int last = 0;
-    while (h < q.size()) {
-      int v = q[h++];
-      last = std::max(last, level[v]);
+    while (head < tail) {
+      const int v = q[head++];
+      last = level[v];
       for (int e = adj_ptr[v]; e < adj_ptr[v + 1]; ++e) {
-        int w = adj[e];
+        const int w = adj[e];
         if (!vis[w] && level[w] < 0) {
           level[w] = level[v] + 1;
-          q.push_back(w);
-          touched.push_back(w);
+          q[tail++] = w;
         }
       }
     }
     int best = -1;
-    for (int v : q)
-      if (level[v] == last && (best < 0 || deg[v] < deg[best] || (deg[v] == deg[best] && v < best)))
-        best = v;
-    for (int v : touched) level[v] = -1;
+    for (int k = tail - 1; k >= 0 && level[q[k]] == last; --k) {
+      const int v = q[k];
+      if (best < 0 || deg[v] < deg[best] || (deg[v] == deg[best] && v < best)) best = v;
+    }
+    for (int k = 0; k < tail; ++k) level[q[k]] = -1;
     ecc = last;
     return best;
   };
+  std::vector<int> &nb = W.nb;
   for (int s0 = 0; s0 < n; ++s0) {
     if (vis[s0]) continue;
-    // pseudo-peripheral node (George-Liu)
     int s = s0, ecc = -1;
-    for (int it = 0; it < 8; ++it) {
+    for (int it = 0; it < 4; ++it) {
       int e2;
-      int cand = bfs_last_min(s, e2);
+      const int cand = bfs_last_min(s, e2);
       if (e2 <= ecc) break;
       ecc = e2;
       s = cand;
     }
     // Cuthill-McKee from s
-    size_t start = order.size();
+    size_t h = order.size();
     order.push_back(s);
     vis[s] = 1;
-    size_t h = start;
-    std::vector<int> nb;
     while (h < order.size()) {
-      int v = order[h++];
+      const int v = order[h++];
       nb.clear();
       for (int e = adj_ptr[v]; e < adj_ptr[v + 1]; ++e)
         if (!vis[adj[e]]) nb.push_back(adj[e]);
@@ -383,6 +435,9 @@ namespace {
 struct Scratch {
   ivec stamp, loc;  // stamp: visit marks (fresh value per use); loc: -1 between uses
   int gen = 0;
+  RcmWork rcm;
+  std::vector<unsigned long long> bits;  // bitmap for ordering a region's dofs
+  std::vector<int> tptr, tcol, tsrc, pos;  // local CSR in ascending order, relabelling
   std::vector<int> frontier, next, adj_ptr, adj, order, mincol;
   std::vector<std::pair<int, int>> row;
   explicit Scratch(int n) {
@@ -431,52 +486,84 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     S.frontier.swap(S.next);
   }
   region.resize(region_size);
-  std::sort(region.begin(), region.end());
+  // ascending order: bitmap scan over the index range when it is compact
+  // (typical for mesh numberings), otherwise a comparison sort
+  {
+    int lo = region[0], hi = region[0];
+    for (int g : region) {
+      lo = std::min(lo, g);
+      hi = std::max(hi, g);
+    }
+    const long long range = (long long)hi - lo + 1;
+    if (range <= 64LL * (long long)region.size()) {
+      const size_t nw = (size_t)((range + 63) / 64);
+      S.bits.assign(nw, 0ULL);
+      for (int g : region) S.bits[(g - lo) >> 6] |= 1ULL << ((g - lo) & 63);
+      size_t k = 0;
+      for (size_t wi = 0; wi < nw; ++wi) {
+        unsigned long long b = S.bits[wi];
+        while (b) {
+          const int bit = __builtin_ctzll(b);
+          region[k++] = lo + (int)(wi * 64) + bit;
+          b &= b - 1;
+        }
+      }
+    } else {
+      std::sort(region.begin(), region.end());
+    }
+  }
   SEC(0);
   const int ni = (int)region.size();
   ivec &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[region[k]] = k;
+  // one pass over the region's rows of A (ascending order): the local CSR
+  // in that order (tcol/tsrc, diagonal included) and the adjacency for the
+  // ordering (off-diagonal, nonzero values)
   S.adj_ptr.assign(ni + 1, 0);
   S.adj.clear();
+  S.tptr.assign(ni + 1, 0);
+  S.tcol.clear();
+  S.tsrc.clear();
   for (int k = 0; k < ni; ++k) {
     const int g = region[k];
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
       const int c = ci[e];
-      if (c != g && va[e] != 0.0 && loc[c] >= 0) S.adj.push_back(loc[c]);
+      const int lc = loc[c];
+      if (lc < 0) continue;
+      S.tcol.push_back(lc);
+      S.tsrc.push_back((int)e);
+      if (c != g && va[e] != 0.0) S.adj.push_back(lc);
     }
     S.adj_ptr[k + 1] = (int)S.adj.size();
+    S.tptr[k + 1] = (int)S.tcol.size();
   }
   SEC(1);
   if (opt.local_order == AMSP_ORDER_RCM) {
-    rcm_order(S.adj_ptr, S.adj, S.order);
+    rcm_order(S.adj_ptr, S.adj, S.order, S.rcm);
   } else {
     S.order.resize(ni);
     for (int k = 0; k < ni; ++k) S.order[k] = k;
   }
   SEC(2);
+  // relabel to the chosen order: pos[ascending index] = local index
+  S.pos.resize(ni);
   out.dofs.resize(ni);
   for (int k = 0; k < ni; ++k) {
-    const int g = region[S.order[k]];
-    out.dofs[k] = g;
-    loc[g] = k;
+    out.dofs[k] = region[S.order[k]];
+    S.pos[S.order[k]] = k;
   }
   S.mincol.assign(ni, 0);
   out.rowlen.resize(ni);
-  out.lcol.clear();
-  out.lsrc.clear();
-  out.lcol.reserve(S.adj.size() + ni);
-  out.lsrc.reserve(S.adj.size() + ni);
+  out.lcol.resize(S.tcol.size());
+  out.lsrc.resize(S.tcol.size());
+  size_t at = 0;
   for (int k = 0; k < ni; ++k) {
-    const int g = out.dofs[k];
-    const size_t b = out.lcol.size();
-    for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
-      const int c = ci[e];
-      if (loc[c] < 0) continue;
+    const int j = S.order[k];
+    const size_t b = at;
+    for (int e = S.tptr[j]; e < S.tptr[j + 1]; ++e) {
       // insertion into the row's run, ascending local column (rows are short)
-      int lc = loc[c], ls = (int)e;
-      out.lcol.push_back(lc);
-      out.lsrc.push_back(ls);
-      size_t y = out.lcol.size() - 1;
+      const int lc = S.pos[S.tcol[e]], ls = S.tsrc[e];
+      size_t y = at++;
       while (y > b && out.lcol[y - 1] > lc) {
         out.lcol[y] = out.lcol[y - 1];
         out.lsrc[y] = out.lsrc[y - 1];
@@ -485,7 +572,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
       out.lcol[y] = lc;
       out.lsrc[y] = ls;
     }
-    const int len = (int)(out.lcol.size() - b);
+    const int len = (int)(at - b);
     S.mincol[k] = len == 0 ? k : std::min(k, out.lcol[b]);
     out.rowlen[k] = len;
   }
@@ -502,7 +589,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     out.tfirst[I] = f;
   }
   SEC(4);
-  for (int k = 0; k < ni; ++k) loc[out.dofs[k]] = -1;
+  for (int k = 0; k < ni; ++k) loc[region[k]] = -1;
 }
 
 // Extended region of subdomain i (its region grown by one more layer) and

@@ -12,6 +12,8 @@
 // inside the row envelope, so the profile of the factor equals that of A_i.
 // After factorisation each diagonal tile holds inv(L_II) (the local solves
 // then need only matrix-vector products) and the off-diagonal tiles hold L_IJ.
+#include <hip/hip_ext.h>
+
 #include "k_common.h"
 
 namespace amsp {
@@ -511,25 +513,29 @@ void launch_tiles_to_f32(hipStream_t s, const double *src, float *dst, size_t co
 template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
                           const T *tiles, const TB *phi, double *xloc, double *cvec, int do_local,
-                          int do_coarse, const int *done) {
+                          int do_coarse, const int *done, hipEvent_t ev_start, hipEvent_t ev_stop) {
   size_t sm = (size_t)(max_npad + TS + 4 * TS) * sizeof(C);
   allow_lds(k_local_apply<T, C, TB>, sm);
-  hipLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, p, r, tiles, phi, xloc,
-                     cvec, do_local, do_coarse, done);
+  if (ev_start || ev_stop)  // events bound to this dispatch: exact kernel duration
+    hipExtLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, ev_start, ev_stop,
+                          0, p, r, tiles, phi, xloc, cvec, do_local, do_coarse, done);
+  else
+    hipLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, p, r, tiles, phi,
+                       xloc, cvec, do_local, do_coarse, done);
 }
 
 template void launch_local_apply_t<double, double, double>(hipStream_t, const Plan &, int,
                                                            const double *, const double *,
                                                            const double *, double *, double *,
-                                                           int, int, const int *);
+                                                           int, int, const int *, hipEvent_t,
+                                                           hipEvent_t);
 template void launch_local_apply_t<float, float, float>(hipStream_t, const Plan &, int,
                                                         const double *, const float *,
                                                         const float *, double *, double *, int,
-                                                        int, const int *);
-template void launch_local_apply_t<float, float, __hip_bfloat16>(hipStream_t, const Plan &, int,
-                                                                 const double *, const float *,
-                                                                 const __hip_bfloat16 *, double *,
-                                                                 double *, int, int, const int *);
+                                                        int, const int *, hipEvent_t, hipEvent_t);
+template void launch_local_apply_t<float, float, __hip_bfloat16>(
+    hipStream_t, const Plan &, int, const double *, const float *, const __hip_bfloat16 *,
+    double *, double *, int, int, const int *, hipEvent_t, hipEvent_t);
 
 template <typename T>
 void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, const double *X,
