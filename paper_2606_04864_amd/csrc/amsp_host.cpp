@@ -85,6 +85,7 @@ struct amsp_handle {
   float *fac32 = nullptr;
   double *phi64 = nullptr;
   void *phi_lo = nullptr;  // float or bf16 copy used by the mixed apply
+  void *phi_nat = nullptr; // the apply's basis in ascending-index layout (scatter)
   double *lam = nullptr;   // N*(nev+1)
   // coarse
   double *a0keep = nullptr;  // copy of A0 tiles before factorisation (introspection)
@@ -107,7 +108,15 @@ struct amsp_handle {
   // per-launch HIP-event timing of the PCG kernels (opt.timing)
   std::vector<hipEvent_t> evs;
   size_t ev_used = 0;
-  std::vector<std::pair<int, int>> ev_rec;  // (kernel class, index of start event)
+  // timed launches: class, index of the start event, and the CG segment and
+  // step they belong to (steps at or after the segment's converged count
+  // return at once and are left out of the averages)
+  struct EvRec {
+    int cls, idx, seg, t;
+  };
+  std::vector<EvRec> ev_rec;
+  int cur_seg = 0, cur_t = -1;  // launch context set by the CG driver
+  std::vector<int> seg_cut;     // completed CG steps of each finished segment
   bool timing_active = false;
   int ev_count[5] = {0, 0, 0, 0, 0};  // launches per class seen by tstart (for the stride)
   ~amsp_handle() {
@@ -153,7 +162,7 @@ static int tpair(amsp_handle *h, int cls, hipEvent_t *e0, hipEvent_t *e1) {
 }
 
 static void tpair_done(amsp_handle *h, int cls, int idx) {
-  if (idx >= 0) h->ev_rec.emplace_back(cls, idx);
+  if (idx >= 0) h->ev_rec.push_back({cls, idx, h->cur_seg, h->cur_t});
 }
 
 static void tstop(amsp_handle *h, int cls, int idx) {
@@ -161,7 +170,7 @@ static void tstop(amsp_handle *h, int cls, int idx) {
   hipEvent_t e = next_event(h);
   if (!e) return;
   hipEventRecord(e, h->stream);
-  h->ev_rec.emplace_back(cls, idx);
+  h->ev_rec.push_back({cls, idx, h->cur_seg, h->cur_t});
 }
 
 #define HIP_TRY(expr)                                                     \
@@ -376,6 +385,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   p.nev = h->nev;
   p.sd_ptr = upload(h, P.sd_ptr, ok);
   p.sd_dofs = upload(h, P.sd_dofs, ok);
+  p.nat = upload(h, P.nat, ok);
   p.vp_ptr = upload(h, P.vp_ptr, ok);
   p.trow_ptr = upload(h, P.trow_ptr, ok);
   p.tfirst = upload(h, P.tfirst, ok);
@@ -640,6 +650,26 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     h->mem.free_one(h->fac64);
     h->fac64 = nullptr;
   }
+  // the scatter's copy of the apply basis, in ascending-global-index layout
+  if (h->nev > 0) {
+    const size_t cnt = (size_t)sum_ni * h->nev;
+    if (!mixed) {
+      double *pn;
+      ALLOC(pn, double, cnt);
+      launch_basis_to_natural<double>(h->stream, p, h->phi64, pn);
+      h->phi_nat = pn;
+    } else if (h->opt.precision == AMSP_MIXED_BF16) {
+      __hip_bfloat16 *pn;
+      ALLOC(pn, __hip_bfloat16, cnt);
+      launch_basis_to_natural<__hip_bfloat16>(h->stream, p, (const __hip_bfloat16 *)h->phi_lo, pn);
+      h->phi_nat = pn;
+    } else {
+      float *pn;
+      ALLOC(pn, float, cnt);
+      launch_basis_to_natural<float>(h->stream, p, (const float *)h->phi_lo, pn);
+      h->phi_nat = pn;
+    }
+  }
   // --- apply / PCG scratch
   ALLOC(h->xloc, double, sum_npad);
   const int ncp = std::max(1, T0 * TS);
@@ -795,15 +825,15 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   tk = tstart(h, 3);
   if (!mixed || h->nev == 0)
     launch_scatter_sum_t<double>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
-                                 h->phi64, h->tvec, z, partial_rz ? r : nullptr, partial_rz,
-                                 do_local, do_coarse, done);
+                                 (const double *)h->phi_nat, h->tvec, z, partial_rz ? r : nullptr,
+                                 partial_rz, do_local, do_coarse, done);
   else if (!bf)
     launch_scatter_sum_t<float>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
-                                (const float *)h->phi_lo, h->tvec, z, partial_rz ? r : nullptr,
+                                (const float *)h->phi_nat, h->tvec, z, partial_rz ? r : nullptr,
                                 partial_rz, do_local, do_coarse, done);
   else
     launch_scatter_sum_t<__hip_bfloat16>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p,
-                                         h->xloc, (const __hip_bfloat16 *)h->phi_lo, h->tvec, z,
+                                         h->xloc, (const __hip_bfloat16 *)h->phi_nat, h->tvec, z,
                                          partial_rz ? r : nullptr, partial_rz, do_local, do_coarse,
                                          done);
   tstop(h, 3, tk);
@@ -876,6 +906,9 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   h->timing_active = h->opt.timing != 0;
   h->ev_used = 0;
   h->ev_rec.clear();
+  h->cur_seg = 0;
+  h->cur_t = -1;
+  h->seg_cut.clear();
   for (int &c : h->ev_count) c = 0;
   if (h->hist_cap < maxit + 2) {
     if (h->hist) h->mem.free_one(h->hist);
@@ -904,6 +937,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
     double relres_true = 0.0, floor_rel = 0.0;
     for (;;) {
       // z = M^{-1} r with r.z partials; r.r partials; p_old = 0
+      h->cur_t = -1;
       launch_dot(h->stream, n, h->r, h->r, h->part_d, nullptr);
       amsp_status s = apply_one(h, h->r, h->z, 3, h->part_b, nullptr);
       if (s != AMSP_OK) return s;
@@ -933,6 +967,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
         prev_rr = hs.rr;
         prev_it = hs.it;
         for (int c = 0; c < next; ++c) {
+          h->cur_t = t;
           int tk = tstart(h, 0);
           launch_cg_dir(h->stream, n, h->rowptr, h->col, h->val, h->z, pold, pnew, h->q, h->part_a,
                         h->st, h->part_d, h->part_b, h->part_c, t, first ? 1 : 0,
@@ -950,6 +985,9 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
         }
         HIP_TRY(hipGetLastError());
       }
+      h->seg_cut.push_back(hs.it);  // steps >= hs.it of this segment were no-ops
+      ++h->cur_seg;
+      h->cur_t = -1;
       // true residual
       launch_spmv(h->stream, n, h->rowptr, h->col, h->val, x, h->q, nullptr, nullptr);
       launch_residual(h->stream, n, f, h->q, h->r, h->part_a);
@@ -995,10 +1033,11 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   if (h->timing_active) {
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (auto &rc : h->ev_rec) {
+      const bool worked = rc.t < 0 || rc.seg >= (int)h->seg_cut.size() || rc.t < h->seg_cut[rc.seg];
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, h->evs[rc.second], h->evs[rc.second + 1]) == hipSuccess) {
-        inf.kernel_ms[rc.first] += ms;
-        inf.kernel_launches[rc.first] += 1;
+      if (worked && hipEventElapsedTime(&ms, h->evs[rc.idx], h->evs[rc.idx + 1]) == hipSuccess) {
+        inf.kernel_ms[rc.cls] += ms;
+        inf.kernel_launches[rc.cls] += 1;
       }
     }
     h->ev_rec.clear();

@@ -15,6 +15,9 @@ struct Plan {
   int nev;                  // requested eigenvectors (row stride of basis arrays)
   const int *sd_ptr;        // [N+1] offsets of each region in the concatenated local vectors
   const int *sd_dofs;       // [sum n_i] global dof of each local index (local order)
+  const int *nat;           // [sum n_i] rank of that dof among the region's dofs by global
+                            // index: position in the ascending-index layout of the
+                            // local corrections and of the scatter's basis copy
   const int *vp_ptr;        // [N+1] padded offsets (multiples of 64) for tile-aligned vectors
   const int *trow_ptr;      // [N+1] offsets into the per-tile-row arrays
   const int *tfirst;        // [sum nt_i] first tile column of each tile row
@@ -94,6 +97,10 @@ void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *i
 
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
+// dst[(sd_ptr[i] + nat[k]) * nev + c] = src[(sd_ptr[i] + k) * nev + c]: the basis
+// in each region's ascending-global-index order (read by the scatter).
+template <typename TB>
+void launch_basis_to_natural(hipStream_t s, const Plan &p, const TB *src, TB *dst);
 // Off-diagonal values of the scaled local operators B_i per local CSR entry.
 void launch_eig_bval(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
                      double *bval);

@@ -424,6 +424,7 @@ static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &a
 // Per-subdomain planning result (built independently, concatenated in order).
 struct SubPlan {
   std::vector<int> dofs;                 // local order -> global dof
+  std::vector<int> nat;                  // local order -> rank by global index
   std::vector<int> rowlen, lcol, lsrc;   // local CSR (row lengths)
   std::vector<int> tfirst;               // tile profile
   std::vector<int> ext;                  // extended region (ascending global)
@@ -548,8 +549,10 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   // relabel to the chosen order: pos[ascending index] = local index
   S.pos.resize(ni);
   out.dofs.resize(ni);
+  out.nat.resize(ni);
   for (int k = 0; k < ni; ++k) {
     out.dofs[k] = region[S.order[k]];
+    out.nat[k] = S.order[k];  // region is ascending, so its index is the rank
     S.pos[S.order[k]] = k;
   }
   S.mincol.assign(ni, 0);
@@ -720,6 +723,7 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
   }
   const int sum_ni = P.sd_ptr[N];
   P.sd_dofs.resize(sum_ni);
+  P.nat.resize(sum_ni);
   P.loc_rowptr.resize(sum_ni + 1);
   P.loc_rowptr[0] = 0;
   P.loc_col.resize(loc_off[N]);
@@ -732,6 +736,7 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
     int acc = (int)loc_off[i];
     for (int k = 0; k < ni; ++k) {
       P.sd_dofs[r0 + k] = S.dofs[k];
+      P.nat[r0 + k] = S.nat[k];
       acc += S.rowlen[k];
       P.loc_rowptr[r0 + k + 1] = acc;
     }
@@ -783,7 +788,7 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
         const int g = P.sd_dofs[k];
         const int at = P.inv_ptr[g] + atomic_inc(&fill[g]);
         P.inv_sd[at] = i;
-        P.inv_loc[at] = k - r0;
+        P.inv_loc[at] = P.nat[k];  // position in the region's ascending-index layout
       }
     });
     sort_lists(P.inv_ptr, n, P.inv_sd, P.inv_loc);

@@ -48,6 +48,7 @@ struct HostPlan {
   long long ntiles = 0;
   std::vector<int> sd_ptr, vp_ptr, trow_ptr, tfirst;
   ivec sd_dofs;
+  ivec nat;  // [sum n_i] rank of each local dof among its region's dofs by global index
   std::vector<long long> toff;
   ivec loc_rowptr, loc_col, loc_src;
   std::vector<int> mi, coff;

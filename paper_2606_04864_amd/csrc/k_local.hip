@@ -251,8 +251,10 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
     if (gg == 0) v[I * TS + cc] = (part[cc] + part[TS + cc]) + (part[2 * TS + cc] + part[3 * TS + cc]);
     __syncthreads();
   }
+  // local correction in the region's ascending-global-index layout, so that
+  // the scatter reads contiguous runs
   double *dst = xloc + p.vp_ptr[i];
-  for (int l = threadIdx.x; l < npad; l += WG) dst[l] = (double)v[l];
+  for (int l = threadIdx.x; l < ni; l += WG) dst[p.nat[r0 + l]] = (double)v[l];
 }
 
 // ------------------------------------------- block solve (EIGP rhs) -------
@@ -449,13 +451,16 @@ void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, doubl
 
 // ------------------------------------------------------------ scatter -----
 // z[j] = sum over regions containing j of (local correction + Phi t) and the
-// partial r.z, in the fixed order of the inverse map (no atomics).
+// partial r.z, in the fixed order of the inverse map (no atomics).  The local
+// corrections and the basis copy are in each region's ascending-global-index
+// layout and inv_loc holds that position, so consecutive dofs of a region
+// read consecutive entries.
 template <typename TB>
 __global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict__ inv_ptr,
                                                     const int *__restrict__ inv_sd,
                                                     const int *__restrict__ inv_loc, Plan p,
                                                     const double *__restrict__ xloc,
-                                                    const TB *__restrict__ phi,
+                                                    const TB *__restrict__ phi,  // natural layout
                                                     const double *__restrict__ t,
                                                     double *__restrict__ z,
                                                     const double *__restrict__ r,
@@ -463,30 +468,76 @@ __global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict
                                                     int do_coarse, const int *__restrict__ done) {
   if (done && *done) return;
   __shared__ double sh[WG / 64];
+  constexpr int U = 4;  // independent dofs per thread and trip (overlapping load chains)
   const int nev = p.nev;
+  const int stride = gridDim.x * WG;
   double acc = 0.0;
-  for (int j = blockIdx.x * WG + threadIdx.x; j < n; j += gridDim.x * WG) {
-    double zj = 0.0;
-    for (int e = inv_ptr[j]; e < inv_ptr[j + 1]; ++e) {
-      const int sd = inv_sd[e], l = inv_loc[e];
-      if (do_local) zj += xloc[p.vp_ptr[sd] + l];
-      if (do_coarse) {
-        const int m = p.mi[sd];
-        const TB *ph = phi + (size_t)(p.sd_ptr[sd] + l) * nev;
-        const double *tt = t + p.coff[sd];
-        double s = 0.0;
-        for (int k = 0; k < m; ++k) s = fma(to_d(ph[k]), tt[k], s);
-        zj += s;
+  for (int j0 = blockIdx.x * WG + threadIdx.x; j0 < n; j0 += U * stride) {
+    int e[U], e1[U];
+    double zj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * stride;
+      e[u] = j < n ? inv_ptr[j] : 0;
+      e1[u] = j < n ? inv_ptr[j + 1] : 0;
+      zj[u] = 0.0;
+    }
+    for (;;) {
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (e[u] >= e1[u]) continue;
+        any = true;
+        const int sd = inv_sd[e[u]], l = inv_loc[e[u]];
+        ++e[u];
+        double v = 0.0;
+        if (do_local) v = xloc[p.vp_ptr[sd] + l];
+        if (do_coarse) {
+          const int m = p.mi[sd];
+          const TB *ph = phi + (size_t)(p.sd_ptr[sd] + l) * nev;
+          const double *tt = t + p.coff[sd];
+#pragma unroll
+          for (int k = 0; k < MAXNEV; ++k)  // predicated: all loads issue together
+            if (k < m) v = fma(to_d(ph[k]), tt[k], v);
+        }
+        zj[u] += v;
+      }
+      if (!any) break;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * stride;
+      if (j < n) {
+        z[j] = zj[u];
+        if (r) acc = fma(r[j], zj[u], acc);
       }
     }
-    z[j] = zj;
-    if (r) acc = fma(r[j], zj, acc);
   }
   double tot = block_sum(acc, sh);
   if (partial && threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
+template <typename TB>
+__global__ void __launch_bounds__(WG) k_basis_to_natural(Plan p, const TB *__restrict__ src,
+                                                         TB *__restrict__ dst) {
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, nev = p.nev;
+  for (int e = threadIdx.x; e < ni * nev; e += WG) {
+    const int l = e / nev, c = e % nev;
+    dst[(size_t)(r0 + p.nat[r0 + l]) * nev + c] = src[(size_t)(r0 + l) * nev + c];
+  }
+}
+
 // ------------------------------------------------------------- launchers ---
+template <typename TB>
+void launch_basis_to_natural(hipStream_t s, const Plan &p, const TB *src, TB *dst) {
+  hipLaunchKernelGGL((k_basis_to_natural<TB>), dim3(p.N), dim3(WG), 0, s, p, src, dst);
+}
+template void launch_basis_to_natural<double>(hipStream_t, const Plan &, const double *, double *);
+template void launch_basis_to_natural<float>(hipStream_t, const Plan &, const float *, float *);
+template void launch_basis_to_natural<__hip_bfloat16>(hipStream_t, const Plan &,
+                                                      const __hip_bfloat16 *, __hip_bfloat16 *);
+
 void launch_neumann_diag(hipStream_t s, const Plan &p, const double *val, double *sdiag,
                          int *status) {
   hipLaunchKernelGGL(k_neumann_diag, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, status);
