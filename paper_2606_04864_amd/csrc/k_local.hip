@@ -152,6 +152,60 @@ __device__ __forceinline__ C tile_row_dot(const T *__restrict__ tile, const C *v
   return s;  // full row sum in all 4 lanes of the row
 }
 
+// The 16 entries of one tile row that a thread holds in the row mapping
+// (row t>>2, columns 16(t&3) ..), loaded ahead of their use.
+template <typename T>
+struct RowFrag {
+  T a[16];
+};
+
+template <typename T>
+__device__ __forceinline__ void row_frag_load(RowFrag<T> &f, const T *__restrict__ tile) {
+  const T *row = tile + (threadIdx.x >> 2) * TS + 16 * (threadIdx.x & 3);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) f.a[c] = row[c];
+}
+
+template <typename T, typename C>
+__device__ __forceinline__ C row_frag_dot(const RowFrag<T> &f, const C *v) {
+  const C *vv = v + 16 * (threadIdx.x & 3);
+  C s = 0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) s = fma((C)f.a[c], vv[c], s);
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  return s;  // full row sum in all 4 lanes of the row
+}
+
+// The 16 entries a thread holds in the column-ownership mapping: wavefront w
+// owns columns 16w .. 16w+15; lane l covers column 16w + (l & 15) and rows
+// 16(l >> 4) .. +15, so a column's 64 rows sit in four lanes 16 apart.
+template <typename T>
+struct ColFrag {
+  T a[16];
+};
+
+template <typename T>
+__device__ __forceinline__ void col_frag_load(ColFrag<T> &f, const T *__restrict__ tile) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T *src = tile + (16 * (l >> 4)) * TS + 16 * w + (l & 15);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) f.a[r] = src[r * TS];
+}
+
+// sum_r tile[r][col] x[r] for this lane's column, complete in all four lanes
+// of the column (x: the 64-vector the tile multiplies, in LDS)
+template <typename T, typename C>
+__device__ __forceinline__ C col_frag_dot(const ColFrag<T> &f, const C *x) {
+  const C *xx = x + 16 * ((threadIdx.x & 63) >> 4);
+  C s = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) s = fma((C)f.a[r], xx[r], s);
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  return s;
+}
+
 // Column-mapped transposed product: thread t owns column t&63 and 16 rows;
 // partial sums over the 4 row groups are combined through LDS.
 template <typename T, typename C>
@@ -220,35 +274,90 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
   if (!do_local) return;
   const int rr = threadIdx.x >> 2, q = threadIdx.x & 3;
   const int cc = threadIdx.x & 63, gg = threadIdx.x >> 6;
+  // Both sweeps stream the region's tiles: the forward sweep in storage
+  // order (each row's off-diagonal tiles, then its diagonal), the backward
+  // sweep in reverse.  D + 1 register slots hold the next tiles; the slot
+  // loop is unrolled so each slot is refilled in place right after its tile
+  // is used (no register copies, which would wait for the loads in flight).
+  constexpr int D = sizeof(T) == 4 ? 3 : 1;  // keeps 4 workgroups per CU resident
+  const long long t0 = p.toff[g0];
+  const int ntl = (int)(p.toff[g0 + nt - 1] + (nt - 1 - p.tfirst[g0 + nt - 1]) + 1 - t0);
+  const T *pool = tiles + tile_elem(t0);
   // forward: y_I = inv(L_II) (b_I - sum_J L_IJ y_J)
-  for (int I = 0; I < nt; ++I) {
-    const int fI = p.tfirst[g0 + I];
-    const long long tI = p.toff[g0 + I];
-    C acc = v[I * TS + rr];
-    for (int J = fI; J < I; ++J) acc -= tile_row_dot<T, C>(tiles + tile_elem(tI + (J - fI)), v + J * TS);
-    if (q == 0) tmp[rr] = acc;
-    __syncthreads();
-    C y = tile_row_dot<T, C>(tiles + tile_elem(tI + (I - fI)), tmp);
-    if (q == 0) v[I * TS + rr] = y;
-    __syncthreads();
-  }
-  // backward: x_I = inv(L_II)^T (y_I - sum_{J>I} L_JI^T x_J)
-  for (int I = nt - 1; I >= 0; --I) {
-    C s = 0;
-    for (int J = I + 1; J < nt; ++J) {
-      const int fJ = p.tfirst[g0 + J];
-      if (fJ > I) continue;
-      s += tile_col_dot<T, C>(tiles + tile_elem(p.toff[g0 + J] + (I - fJ)), v + J * TS);
+  {
+    RowFrag<T> f[D + 1];
+#pragma unroll
+    for (int d = 0; d <= D; ++d)
+      if (d < ntl) row_frag_load(f[d], pool + tile_elem(d));
+    int I = 0, J = p.tfirst[g0];
+    C acc = v[rr];
+    for (int k0 = 0; k0 < ntl; k0 += D + 1) {
+#pragma unroll
+      for (int sl = 0; sl <= D; ++sl) {
+        const int k = k0 + sl;
+        if (k < ntl) {
+          if (J < I) {
+            acc -= row_frag_dot<T, C>(f[sl], v + J * TS);
+            ++J;
+          } else {
+            if (q == 0) tmp[rr] = acc;
+            __syncthreads();
+            const C y = row_frag_dot<T, C>(f[sl], tmp);
+            if (q == 0) v[I * TS + rr] = y;
+            __syncthreads();
+            ++I;
+            if (I < nt) {
+              J = p.tfirst[g0 + I];
+              acc = v[I * TS + rr];
+            }
+          }
+          if (k + D + 1 < ntl) row_frag_load(f[sl], pool + tile_elem(k + D + 1));
+        }
+      }
     }
-    part[gg * TS + cc] = s;
-    __syncthreads();
-    if (gg == 0) tmp[cc] = v[I * TS + cc] - ((part[cc] + part[TS + cc]) + (part[2 * TS + cc] + part[3 * TS + cc]));
-    __syncthreads();
-    const int fI = p.tfirst[g0 + I];
-    C y = tile_col_dot<T, C>(tiles + tile_elem(p.toff[g0 + I] + (I - fI)), tmp);
-    part[gg * TS + cc] = y;
-    __syncthreads();
-    if (gg == 0) v[I * TS + cc] = (part[cc] + part[TS + cc]) + (part[2 * TS + cc] + part[3 * TS + cc]);
+  }
+  // backward, right-looking: for I = nt-1 .. 0, x_I = inv(L_II)^T y_I, then
+  // y_J -= L_IJ^T x_I for the off-diagonal tiles J of row I (storage order
+  // reversed: the diagonal first, then J descending).  Wavefront w owns
+  // columns 16w .. 16w+15 of every product, so each y_J entry has a single
+  // writer and a row needs two barriers.
+  {
+    ColFrag<T> f[D + 1];
+#pragma unroll
+    for (int d = 0; d <= D; ++d)
+      if (d < ntl) col_frag_load(f[d], pool + tile_elem(ntl - 1 - d));
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = 16 * w + (l & 15);
+    const bool head = (l >> 4) == 0;  // one lane of the four that share a column
+    int I = nt - 1, J = nt - 1, fI = p.tfirst[g0 + nt - 1];
+    for (int k0 = 0; k0 < ntl; k0 += D + 1) {
+#pragma unroll
+      for (int sl = 0; sl <= D; ++sl) {
+        const int k = k0 + sl;
+        if (k < ntl) {
+          if (J == I) {
+            __syncthreads();  // y_I complete (updates from rows > I)
+            const C x = col_frag_dot<T, C>(f[sl], v + I * TS);
+            if (head) tmp[col] = x;
+            __syncthreads();  // x_I visible in tmp; all reads of y_I done
+            if (head) v[I * TS + col] = x;
+          } else {
+            const C s2 = col_frag_dot<T, C>(f[sl], tmp);
+            if (head) v[J * TS + col] -= s2;
+          }
+          if (J > fI) {
+            --J;
+          } else {
+            --I;
+            if (I >= 0) {
+              J = I;
+              fI = p.tfirst[g0 + I];
+            }
+          }
+          if (k + D + 1 < ntl) col_frag_load(f[sl], pool + tile_elem(ntl - 1 - (k + D + 1)));
+        }
+      }
+    }
     __syncthreads();
   }
   // local correction in the region's ascending-global-index layout, so that
