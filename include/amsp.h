@@ -125,7 +125,8 @@ typedef struct {
   int32_t nc;               /* coarse dimension N_c = sum_i m_i                     */
   int64_t sum_ni;           /* sum of region sizes                                  */
   int32_t max_ni;
-  int64_t factor_tiles;     /* 64x64 tiles of one local factor set                  */
+  int64_t factor_tiles;     /* 64x64 profile tiles of one local factor set (the     */
+                            /* diagonal ones stored as packed lower triangles)     */
   int32_t eig_sweeps;       /* subspace sweeps used                                 */
   int32_t eig_unconverged;  /* subdomains not converged at eig_maxit                */
   int32_t n_gap_flags;      /* subdomains with lambda_{m+1} - lambda_m tiny         */

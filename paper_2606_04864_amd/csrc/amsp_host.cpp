@@ -81,8 +81,11 @@ struct amsp_handle {
   int ntilerows = 0;
   // local factors and basis
   double *sdiag = nullptr;
-  double *fac64 = nullptr;
-  float *fac32 = nullptr;
+  double *fac64 = nullptr;  // tile pool of the local factors (setup only)
+  // the apply's local factors: packed inverse diagonal tiles and the envelope
+  // (row and column forms), in the apply's precision
+  double *dg64 = nullptr, *erow64 = nullptr, *ecol64 = nullptr;
+  float *dg32 = nullptr, *erow32 = nullptr, *ecol32 = nullptr;
   double *phi64 = nullptr;
   void *phi_lo = nullptr;  // float or bf16 copy used by the mixed apply
   void *phi_nat = nullptr; // the apply's basis in ascending-index layout (scatter)
@@ -323,6 +326,12 @@ struct SideStream {
   }
 };
 
+// Entries of one local factor set: the off-diagonal tiles, then one packed
+// lower-triangular diagonal tile (DE entries) per tile row.
+static size_t factor_elems(const HostPlan &P) {
+  return (size_t)P.noff * TE + (size_t)P.trow_ptr.back() * DE;
+}
+
 static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   HostPlan &P = h->hp;
   const bool mixed = h->opt.precision != AMSP_FP64;
@@ -390,6 +399,10 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   p.trow_ptr = upload(h, P.trow_ptr, ok);
   p.tfirst = upload(h, P.tfirst, ok);
   p.toff = upload(h, P.toff, ok);
+  p.noff = P.noff;
+  p.eptr = upload(h, P.eptr, ok);
+  p.uptr = upload(h, P.uptr, ok);
+  p.ebase = upload(h, P.ebase, ok);
   p.loc_rowptr = upload(h, P.loc_rowptr, ok);
   p.loc_col = upload(h, P.loc_col, ok);
   p.loc_src = upload(h, P.loc_src, ok);
@@ -414,7 +427,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   ALLOC(status, int, h->N);
   HIP_TRY(hipMemsetAsync(status, 0, h->N * sizeof(int), h->stream));
   ALLOC(h->sdiag, double, sum_ni);
-  const size_t fac_elems = (size_t)P.ntiles * TE;
+  const size_t fac_elems = factor_elems(P);
   ALLOC(h->fac64, double, fac_elems);
   if (h->nev > 0) {
     launch_neumann_diag(h->stream, p, h->val, h->sdiag, status);
@@ -629,10 +642,30 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   double t6 = now_ms();
   h->sinfo.phase_ms[5] = (t6 - t4) - h->sinfo.phase_ms[6];
 
-  // --- mixed storage of the apply operands
+  // --- the apply's local factors: packed diagonal tiles + envelope
+  {
+    const size_t ndiag = (size_t)h->ntilerows * DE, nenv = (size_t)P.nenv;
+    const double *dsrc = h->fac64 + (size_t)P.noff * TE;
+    if (mixed) {
+      ALLOC(h->dg32, float, ndiag);
+      ALLOC(h->erow32, float, nenv);
+      ALLOC(h->ecol32, float, nenv);
+      launch_tiles_to_f32(h->stream, dsrc, h->dg32, ndiag);
+      launch_env_from_tiles<float>(h->stream, p, h->ntilerows, h->fac64, h->erow32, h->ecol32);
+    } else {
+      ALLOC(h->dg64, double, ndiag);
+      ALLOC(h->erow64, double, nenv);
+      ALLOC(h->ecol64, double, nenv);
+      HIP_TRY(hipMemcpyAsync(h->dg64, dsrc, ndiag * sizeof(double), hipMemcpyDeviceToDevice,
+                             h->stream));
+      launch_env_from_tiles<double>(h->stream, p, h->ntilerows, h->fac64, h->erow64, h->ecol64);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->mem.free_one(h->fac64);
+    h->fac64 = nullptr;
+  }
   if (mixed) {
-    ALLOC(h->fac32, float, fac_elems);
-    launch_tiles_to_f32(h->stream, h->fac64, h->fac32, fac_elems);
     if (h->nev > 0) {
       const bool bf = h->opt.precision == AMSP_MIXED_BF16;
       if (bf) {
@@ -647,8 +680,6 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       launch_basis_convert(h->stream, h->phi64, h->phi_lo, (size_t)sum_ni * h->nev, bf ? 1 : 0);
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
-    h->mem.free_one(h->fac64);
-    h->fac64 = nullptr;
   }
   // the scatter's copy of the apply basis, in ascending-global-index layout
   if (h->nev > 0) {
@@ -763,6 +794,15 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
     delete h;
     return (amsp_status)s;
   }
+  // the local apply keeps a region's vector and envelope segment starts in
+  // LDS (160 KB per workgroup, less the kernel's 512 B of static LDS)
+  if (local_apply_lds_bytes(h->hp.max_npad, o.precision == AMSP_FP64 ? 8 : 4) >
+      160 * 1024 - 512) {
+    g_setup_error = "largest region (" + std::to_string(h->hp.max_npad) +
+                    " padded rows) exceeds the local apply's LDS capacity";
+    delete h;
+    return AMSP_ERR_ARG;
+  }
   h->nc = h->hp.nc;
   h->T0 = (h->nc + TS - 1) / TS;
   h->sinfo.phase_ms[0] = now_ms() - t0;
@@ -798,17 +838,17 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   hipEvent_t e0, e1;
   int tk = tpair(h, 1, &e0, &e1);
   if (!mixed) {
-    launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->fac64, h->phi64,
-                                                 h->xloc, h->cvec, do_local, do_coarse, done, e0,
-                                                 e1);
+    launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->dg64,
+                                                 h->erow64, h->ecol64, h->phi64, h->xloc, h->cvec,
+                                                 do_local, do_coarse, done, e0, e1);
   } else if (!bf) {
-    launch_local_apply_t<float, float, float>(h->stream, p, h->hp.max_npad, r, h->fac32,
-                                              (const float *)h->phi_lo, h->xloc, h->cvec, do_local,
-                                              do_coarse, done, e0, e1);
+    launch_local_apply_t<float, float, float>(h->stream, p, h->hp.max_npad, r, h->dg32,
+                                              h->erow32, h->ecol32, (const float *)h->phi_lo,
+                                              h->xloc, h->cvec, do_local, do_coarse, done, e0, e1);
   } else {
-    launch_local_apply_t<float, float, __hip_bfloat16>(h->stream, p, h->hp.max_npad, r, h->fac32,
-                                                       (const __hip_bfloat16 *)h->phi_lo, h->xloc,
-                                                       h->cvec, do_local, do_coarse, done, e0, e1);
+    launch_local_apply_t<float, float, __hip_bfloat16>(
+        h->stream, p, h->hp.max_npad, r, h->dg32, h->erow32, h->ecol32,
+        (const __hip_bfloat16 *)h->phi_lo, h->xloc, h->cvec, do_local, do_coarse, done, e0, e1);
   }
   tpair_done(h, 1, tk);
   if (do_coarse) {
@@ -862,15 +902,22 @@ extern "C" amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_
   return AMSP_OK;
 }
 
+// Entries of the apply's local factors: one packed diagonal tile per tile
+// row and the envelope (each sweep reads the diagonal tiles and one form).
+static int64_t apply_factor_elems(const HostPlan &P) {
+  return (int64_t)P.trow_ptr.back() * DE + P.nenv;
+}
+
 // Algorithmic bytes of one local-apply launch: gather of r and the region
-// index, basis read for the restriction, both factor sweeps, local output.
+// index, basis read for the restriction, envelope segment starts, both factor
+// sweeps, local output.
 static int64_t local_apply_bytes(const amsp_handle *h) {
   const HostPlan &P = h->hp;
   const bool mixed = h->opt.precision != AMSP_FP64;
   const int64_t sni = P.sd_ptr.back(), snp = P.vp_ptr.back();
   const int64_t fb = mixed ? 4 : 8;
   const int64_t pb = mixed ? (h->opt.precision == AMSP_MIXED_BF16 ? 2 : 4) : 8;
-  int64_t b = sni * (8 + 4) + snp * 8 + 2 * P.ntiles * (int64_t)TE * fb;
+  int64_t b = sni * (8 + 4) + sni * 8 + 2 * (snp + h->N) * 4 + 2 * apply_factor_elems(P) * fb;
   if (h->nc > 0) b += sni * h->nev * pb + (int64_t)h->nc * 8;
   return b;
 }
@@ -884,8 +931,8 @@ static int64_t bytes_per_iter(const amsp_handle *h) {
   int64_t b = 0;
   b += nnz * 12 + (n + 1) * 4 + n * 8 * 4;          // spmv with the fused p update
   b += n * 8 * 6;                                   // x, r update
-  b += sni * (8 + 4) + snp * 8;                     // local gather + write
-  b += 2 * P.ntiles * (int64_t)TE * fb;             // forward + backward factor sweep
+  b += sni * (8 + 4) + sni * 8 + 2 * (snp + h->N) * 4;  // local gather, write, segments
+  b += 2 * apply_factor_elems(P) * fb;                 // forward + backward factor sweep
   if (h->nc > 0) {
     b += sni * h->nev * pb * 2;                     // restrict + prolong basis reads
     b += 2 * (int64_t)h->T0 * (h->T0 + 1) / 2 * TE * (mixed ? 4 : 8);  // coarse W0 twice

@@ -21,7 +21,13 @@ struct Plan {
   const int *vp_ptr;        // [N+1] padded offsets (multiples of 64) for tile-aligned vectors
   const int *trow_ptr;      // [N+1] offsets into the per-tile-row arrays
   const int *tfirst;        // [sum nt_i] first tile column of each tile row
-  const long long *toff;    // [sum nt_i] pool index of the first tile of each tile row
+  const long long *toff;    // [sum nt_i] pool index of the first off-diagonal tile of each
+                            // tile row (tiles J = first(I) .. I-1 follow in order)
+  long long noff;           // off-diagonal tiles in the pool; the packed diagonal tiles
+                            // follow at entry noff*TE, DE entries per tile row
+  const int *eptr;          // [sum npad_i + N] envelope of the factor below the diagonal
+  const int *uptr;          //   tiles, per region npad_i + 1 segment starts relative to
+  const long long *ebase;   //   ebase[i]: row form (eptr) and column form (uptr)
   const int *loc_rowptr;    // [sum n_i + 1] local CSR of A_i (rows in local order)
   const int *loc_col;       //   local column index
   const int *loc_src;       //   index of the value in the global CSR
@@ -75,14 +81,24 @@ void launch_extract_tiles(hipStream_t s, const Plan &p, int ntilerows, const dou
 // status[i] |= bit on a non-positive pivot.
 void launch_profile_cholesky(hipStream_t s, const Plan &p, double *tiles, int *status, int bit);
 void launch_tiles_to_f32(hipStream_t s, const double *src, float *dst, size_t count);
-// Local apply: gather r, coarse restriction into c (do_coarse), profile
-// forward/backward solve into xloc (do_local).  T factor, C compute, TB basis type.
+// Envelope copy (row and column forms, type T) of the off-diagonal part of a
+// factored tile pool.
+template <typename T>
+void launch_env_from_tiles(hipStream_t s, const Plan &p, int ntilerows, const double *tiles,
+                           T *erow, T *ecol);
+// Dynamic LDS of the local apply for regions of up to max_npad padded rows
+// and compute type of csize bytes.
+size_t local_apply_lds_bytes(int max_npad, size_t csize);
+// Local apply: gather r, coarse restriction into c (do_coarse), envelope
+// forward/backward solve into xloc (do_local).  diag: the packed inverse
+// diagonal tiles (DE entries per tile row), erow/ecol: the envelope.
+// T factor, C compute, TB basis type.  ev_start / ev_stop (optional, created
+// with timing): bound to the dispatch itself (no extra packets in the stream).
 template <typename T, typename C, typename TB>
-// ev_start / ev_stop (optional, created with timing): bound to the dispatch
-// itself (no extra packets in the stream).
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
-                          const T *tiles, const TB *phi, double *xloc, double *cvec, int do_local,
-                          int do_coarse, const int *done, hipEvent_t ev_start = nullptr,
+                          const T *diag, const T *erow, const T *ecol, const TB *phi,
+                          double *xloc, double *cvec, int do_local, int do_coarse,
+                          const int *done, hipEvent_t ev_start = nullptr,
                           hipEvent_t ev_stop = nullptr);
 // Y = (L L^T)^{-1} X on row-major [rows][EIGP] padded blocks (Y may equal X).
 template <typename T>

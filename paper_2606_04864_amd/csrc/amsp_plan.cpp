@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -427,6 +428,8 @@ struct SubPlan {
   std::vector<int> nat;                  // local order -> rank by global index
   std::vector<int> rowlen, lcol, lsrc;   // local CSR (row lengths)
   std::vector<int> tfirst;               // tile profile
+  std::vector<int> eptr, uptr;           // envelope segment starts (npad + 1 each)
+  bool env_overflow = false;             // envelope beyond 32-bit segment offsets
   std::vector<int> ext;                  // extended region (ascending global)
   std::vector<int> ext_rowlen, ext_src, ext_loc;
   std::vector<int> pair_j, pair_len, pair_l, pair_e;
@@ -439,7 +442,7 @@ struct Scratch {
   RcmWork rcm;
   std::vector<unsigned long long> bits;  // bitmap for ordering a region's dofs
   std::vector<int> tptr, tcol, tsrc, pos;  // local CSR in ascending order, relabelling
-  std::vector<int> frontier, next, adj_ptr, adj, order, mincol;
+  std::vector<int> frontier, next, adj_ptr, adj, order, mincol, fenv;
   std::vector<std::pair<int, int>> row;
   explicit Scratch(int n) {
     stamp.assign(n, -1);
@@ -591,6 +594,35 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     }
     out.tfirst[I] = f;
   }
+  // Envelope of the factor below the diagonal tiles.  Cholesky fill stays
+  // right of each row's first entry; fenv[r] = min over rows s >= r of that
+  // first column (padding rows: s itself) is nondecreasing, so that
+  //   row form:    row r of block I keeps columns fenv[r] .. 64I - 1,
+  //   column form: column c of block J keeps rows 64(J+1) .. last(c), with
+  //                last(c) = max{ r : fenv[r] <= c },
+  // both contiguous and holding the same entries.
+  const int npad = nt * TS;
+  S.fenv.resize(npad);
+  int m = npad;
+  for (int r = npad - 1; r >= 0; --r) {
+    const int f = r >= ni ? r : (opt.dense_tiles ? 0 : S.mincol[r]);
+    m = std::min(m, f);
+    S.fenv[r] = m;
+  }
+  out.eptr.resize(npad + 1);
+  out.uptr.resize(npad + 1);
+  out.eptr[0] = out.uptr[0] = 0;
+  long long er = 0, eu = 0;
+  int last = 0;  // max r with fenv[r] <= c (fenv[0] = 0 <= c always)
+  for (int r = 0; r < npad; ++r) {
+    er += std::max(0, (r / TS) * TS - S.fenv[r]);
+    const int c = r;
+    while (last + 1 < npad && S.fenv[last + 1] <= c) ++last;
+    eu += std::max(0, last - (c / TS + 1) * TS + 1);
+    out.eptr[r + 1] = (int)std::min<long long>(er, INT_MAX);
+    out.uptr[r + 1] = (int)std::min<long long>(eu, INT_MAX);
+  }
+  out.env_overflow = er >= INT_MAX;
   SEC(4);
   for (int k = 0; k < ni; ++k) loc[region[k]] = -1;
 }
@@ -697,6 +729,11 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
     });
   }
   PTIME("regions");
+  for (int i = 0; i < N; ++i)
+    if (sub[i].env_overflow) {
+      msg = "region " + std::to_string(i) + " too large: its factor envelope exceeds 2^31 entries";
+      return AMSP_ERR_ARG;
+    }
 #ifdef AMSP_PLAN_PROFILE
   fprintf(stderr, "   grow+sort %.1f adj %.1f rcm %.1f lcsr %.1f (thread-summed ms)\n", g_sec[0], g_sec[1], g_sec[2], g_sec[3]);
   for (double &x : g_sec) x = 0;
@@ -730,6 +767,10 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
   P.loc_src.resize(loc_off[N]);
   P.tfirst.resize(P.trow_ptr[N]);
   P.toff.resize(P.trow_ptr[N]);
+  P.ebase.assign(N + 1, 0);
+  for (int i = 0; i < N; ++i) P.ebase[i + 1] = P.ebase[i] + sub[i].eptr.back();
+  P.eptr.resize((size_t)P.vp_ptr[N] + N);
+  P.uptr.resize((size_t)P.vp_ptr[N] + N);
   parallel_for(N, [&](int i) {
     SubPlan &S = sub[i];
     const int r0 = P.sd_ptr[i], ni = (int)S.dofs.size();
@@ -743,12 +784,14 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
     std::copy(S.lcol.begin(), S.lcol.end(), P.loc_col.begin() + loc_off[i]);
     std::copy(S.lsrc.begin(), S.lsrc.end(), P.loc_src.begin() + loc_off[i]);
     const int g0 = P.trow_ptr[i];
-    long long t = tile_off[i];
+    long long t = tile_off[i] - g0;  // off-diagonal tiles of the regions before i
     for (size_t I = 0; I < S.tfirst.size(); ++I) {
       P.tfirst[g0 + I] = S.tfirst[I];
       P.toff[g0 + I] = t;
-      t += (long long)I - S.tfirst[I] + 1;
+      t += (long long)I - S.tfirst[I];
     }
+    std::copy(S.eptr.begin(), S.eptr.end(), P.eptr.begin() + P.vp_ptr[i] + i);
+    std::copy(S.uptr.begin(), S.uptr.end(), P.uptr.begin() + P.vp_ptr[i] + i);
   });
   P.max_ni = 0;
   P.max_npad = 0;
@@ -757,6 +800,8 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
     P.max_npad = std::max(P.max_npad, P.vp_ptr[i + 1] - P.vp_ptr[i]);
   }
   P.ntiles = tile_off[N];
+  P.noff = tile_off[N] - P.trow_ptr[N];
+  P.nenv = P.ebase[N];
   P.nc = P.coff[N];
   PTIME("concat");
   (void)msg;

@@ -45,11 +45,18 @@ using ivec = std::vector<int, NoInitAlloc<int>>;
 struct HostPlan {
   int n = 0, N = 0, nev = 0, nc = 0;
   int max_ni = 0, max_npad = 0;
-  long long ntiles = 0;
+  long long ntiles = 0;  // all profile tiles (off-diagonal + one diagonal per tile row)
+  long long noff = 0;    // off-diagonal tiles
   std::vector<int> sd_ptr, vp_ptr, trow_ptr, tfirst;
   ivec sd_dofs;
   ivec nat;  // [sum n_i] rank of each local dof among its region's dofs by global index
-  std::vector<long long> toff;
+  std::vector<long long> toff;  // first off-diagonal tile of each tile row
+  // envelope storage of the factor below the diagonal tiles: per region,
+  // npad_i + 1 segment starts of the row form (eptr) and of the column form
+  // (uptr), relative to the region's base ebase[i]; nenv entries in all
+  ivec eptr, uptr;
+  std::vector<long long> ebase;
+  long long nenv = 0;
   ivec loc_rowptr, loc_col, loc_src;
   std::vector<int> mi, coff;
   ivec mult, inv_ptr, inv_sd, inv_loc;

@@ -54,6 +54,59 @@ __device__ __forceinline__ int find_segment(const int *ptr, int n, int x) {
 
 __device__ __forceinline__ size_t tile_elem(long long tile) { return (size_t)tile * (size_t)TE; }
 
+// Packed diagonal tiles.  The factor pool holds the off-diagonal 64x64 tiles
+// (row-major, TE entries each) followed by one lower-triangular diagonal tile
+// per tile row.  Row R of a packed tile keeps columns 0..R, zero-padded to a
+// multiple of 4 entries, and starts at dpos_row(R), a multiple of 4: rows are
+// 16-byte aligned in fp32 and fp64, so they load in 4-entry vectors.
+__host__ __device__ constexpr int dpos_row(int R) {
+  return 4 * ((R >> 2) + 1) * (2 * (R >> 2) + (R & 3));
+}
+static_assert(dpos_row(TS) == DE, "packed diagonal tile size");
+static_assert((DE * 4) % 16 == 0 && (TE * 4) % 16 == 0, "16-byte aligned tiles");
+
+// first entry of the packed diagonal tile of global tile row g
+__device__ __forceinline__ size_t diag_elem(const Plan &p, int g) {
+  return (size_t)p.noff * TE + (size_t)g * DE;
+}
+
+// Entries c0 .. c0+15 (c0 a multiple of 16) of row R of a packed diagonal
+// tile; entries above the diagonal are zero.  Each 4-entry group that starts
+// right of the diagonal is not read.
+template <typename T>
+__device__ __forceinline__ void packed_row16(T (&a)[16], const T *__restrict__ dtile, int R,
+                                             int c0) {
+  const T *row = dtile + dpos_row(R) + c0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (c0 + 4 * u <= R) {
+      if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(row + 4 * u);
+        a[4 * u] = v.x;
+        a[4 * u + 1] = v.y;
+        a[4 * u + 2] = v.z;
+        a[4 * u + 3] = v.w;
+      } else {
+        const double2 v0 = *reinterpret_cast<const double2 *>(row + 4 * u);
+        const double2 v1 = *reinterpret_cast<const double2 *>(row + 4 * u + 2);
+        a[4 * u] = v0.x;
+        a[4 * u + 1] = v0.y;
+        a[4 * u + 2] = v1.x;
+        a[4 * u + 3] = v1.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[4 * u + j] = T(0);
+    }
+  }
+}
+
+// Entry (R, C) of a packed diagonal tile (zero above the diagonal).
+template <typename T>
+__device__ __forceinline__ T packed_at(const T *__restrict__ dtile, int R, int C) {
+  return C <= R ? dtile[dpos_row(R) + C] : T(0);
+}
+
 // gfx950 gives a workgroup up to 160 KB of LDS; raise the dynamic-LDS limit
 // of a kernel once before its first launch with more than 64 KB.
 template <typename F>
@@ -84,91 +137,16 @@ __device__ __forceinline__ void lds_to_tile(const double *lds, double *__restric
   for (int e = threadIdx.x; e < TE; e += WG) g[e] = lds[(e >> 6) * LDT + (e & 63)];
 }
 
-// Register block of a tile owned by one thread: rows (t>>4)+16*i, cols (t&15)+16*j.
-struct Blk {
-  double v[4][4];
-};
-
-__device__ __forceinline__ void blk_load(Blk &b, const double *__restrict__ g) {
-  const int r0 = threadIdx.x >> 4, c0 = threadIdx.x & 15;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b.v[i][j] = g[(r0 + 16 * i) * TS + c0 + 16 * j];
+// Packed diagonal tile <-> full tile in padded LDS (upper triangle zero).
+__device__ __forceinline__ void packed_to_lds(const double *__restrict__ g, double *lds) {
+  for (int e = threadIdx.x; e < TE; e += WG) lds[(e >> 6) * LDT + (e & 63)] = packed_at(g, e >> 6, e & 63);
 }
 
-__device__ __forceinline__ void blk_store(const Blk &b, double *__restrict__ g) {
-  const int r0 = threadIdx.x >> 4, c0 = threadIdx.x & 15;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) g[(r0 + 16 * i) * TS + c0 + 16 * j] = b.v[i][j];
-}
-
-__device__ __forceinline__ void blk_to_lds(const Blk &b, double *lds) {
-  const int r0 = threadIdx.x >> 4, c0 = threadIdx.x & 15;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) lds[(r0 + 16 * i) * LDT + c0 + 16 * j] = b.v[i][j];
-}
-
-// b -= X * Y^T  (X, Y 64x64 in padded LDS)
-__device__ __forceinline__ void blk_sub_abt(Blk &b, const double *X, const double *Y) {
-  const int r0 = threadIdx.x >> 4, c0 = threadIdx.x & 15;
-  for (int k = 0; k < TS; ++k) {
-    double x[4], y[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = X[(r0 + 16 * i) * LDT + k];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) y[j] = Y[(c0 + 16 * j) * LDT + k];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b.v[i][j] = fma(-x[i], y[j], b.v[i][j]);
+__device__ __forceinline__ void lds_to_packed(const double *lds, double *__restrict__ g) {
+  for (int e = threadIdx.x; e < TE; e += WG) {
+    const int r = e >> 6, c = e & 63;
+    if (c < 4 * ((r >> 2) + 1)) g[dpos_row(r) + c] = c <= r ? lds[r * LDT + c] : 0.0;
   }
-}
-
-// b -= X * Y  (X, Y 64x64 in padded LDS)
-__device__ __forceinline__ void blk_sub_ab(Blk &b, const double *X, const double *Y) {
-  const int r0 = threadIdx.x >> 4, c0 = threadIdx.x & 15;
-  for (int k = 0; k < TS; ++k) {
-    double x[4], y[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x[i] = X[(r0 + 16 * i) * LDT + k];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) y[j] = Y[k * LDT + c0 + 16 * j];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b.v[i][j] = fma(-x[i], y[j], b.v[i][j]);
-  }
-}
-
-// out = X * Y^T (fresh block)
-__device__ __forceinline__ void blk_abt(Blk &b, const double *X, const double *Y) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b.v[i][j] = 0.0;
-  blk_sub_abt(b, X, Y);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b.v[i][j] = -b.v[i][j];
-}
-
-// out = X * Y (fresh block)
-__device__ __forceinline__ void blk_ab(Blk &b, const double *X, const double *Y) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b.v[i][j] = 0.0;
-  blk_sub_ab(b, X, Y);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b.v[i][j] = -b.v[i][j];
 }
 
 // Synchronisation of the lanes of one wavefront around LDS traffic: LDS
@@ -374,6 +352,16 @@ __device__ __forceinline__ void acc_load(Acc4 &c, const double *__restrict__ g) 
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) c.v[cb][r] = g[(16 * wv + (l >> 4) + 4 * r) * TS + 16 * cb + (l & 15)];
+}
+
+// acc_load of a packed diagonal tile (zero above the diagonal)
+__device__ __forceinline__ void acc_load_packed(Acc4 &c, const double *__restrict__ g) {
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      c.v[cb][r] = packed_at(g, 16 * wv + (l >> 4) + 4 * r, 16 * cb + (l & 15));
 }
 
 __device__ __forceinline__ void acc_zero(Acc4 &c) {

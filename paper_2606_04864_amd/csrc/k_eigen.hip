@@ -5,10 +5,11 @@
 // standard form B_i z = lambda z with B_i = S^{-1/2} hat A_i S^{-1/2} and
 // psi = S^{-1/2} z (Section 5, parameter test).  Method: block shift-invert
 // subspace iteration (Bathe-Wilson) with EIGP columns: Y = (B_i + sigma I)^{-1} X
-// (tile-profile Cholesky solves, k_profile_solve_block), then a Rayleigh-Ritz
-// step here: CholQR2 orthonormalisation of Y, H = Y^T B_i Y with the sparse
-// B_i, cyclic Jacobi on the EIGP x EIGP matrix H, X = Y V sorted ascending,
-// and residuals ||B_i x - theta x|| for the m_i + 1 lowest pairs.  Regions
+// (tile-profile Cholesky solves, k_profile_solve_block_mfma), then a Rayleigh-Ritz
+// step here through the Gram matrices: G = Y^T Y = L L^T, K = Y^T B_i Y with
+// the sparse B_i, H = inv(L) K inv(L)^T, cyclic Jacobi on the EIGP x EIGP
+// matrix H, X = Y inv(L)^T V sorted ascending, and residuals
+// ||B_i x - theta x|| for the m_i + 1 lowest pairs.  Regions
 // with n_i <= EIGP are solved directly by Jacobi on the dense B_i.
 #include "k_common.h"
 

@@ -7,11 +7,13 @@
 // the standard-form eigen-operator B_i = S^{-1/2} hat A_i S^{-1/2}.
 //
 // Storage: each region is ordered locally (RCM by default) and stored as
-// 64x64 row-major tiles of its lower triangle, restricted to the tile
-// profile: tile row I holds tiles J = first(I)..I.  Cholesky fill stays
-// inside the row envelope, so the profile of the factor equals that of A_i.
-// After factorisation each diagonal tile holds inv(L_II) (the local solves
-// then need only matrix-vector products) and the off-diagonal tiles hold L_IJ.
+// 64x64 tiles of its lower triangle, restricted to the tile profile: tile row
+// I holds tiles J = first(I)..I.  Cholesky fill stays inside the row
+// envelope, so the profile of the factor equals that of A_i.  Off-diagonal
+// tiles are row-major; diagonal tiles keep only their lower triangle, packed
+// (see dpos_row), in a second pool behind the first.  After factorisation
+// each diagonal tile holds inv(L_II) (the local solves then need only
+// matrix-vector products) and the off-diagonal tiles hold L_IJ.
 #include <hip/hip_ext.h>
 
 #include "k_common.h"
@@ -80,9 +82,16 @@ __global__ void __launch_bounds__(WG) k_extract_tiles(Plan p, int nrows_total,
       for (int c = 0; c < 16; ++c)
         if (c == off) v[c] = 1.0;
     }
-    double *dst = tiles + tile_elem(t0 + (J - fI)) + r * TS + 16 * q;
+    if (J < I) {
+      double *dst = tiles + tile_elem(t0 + (J - fI)) + r * TS + 16 * q;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) dst[c] = v[c];
+      for (int c = 0; c < 16; ++c) dst[c] = v[c];
+    } else {  // packed lower triangle, zero padding right of the diagonal
+      double *dst = tiles + diag_elem(p, g) + dpos_row(r) + 16 * q;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (16 * q + (c & ~3) <= r) dst[c] = (16 * q + c <= r) ? v[c] : 0.0;
+    }
   }
 }
 
@@ -107,9 +116,14 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) k_
     for (int J = fI; J <= I; ++J) {
       const int fJ = p.tfirst[g0 + J];
       const long long tJ = p.toff[g0 + J];
-      double *cij = tiles + tile_elem(tI + (J - fI));
+      double *cij = J < I ? tiles + tile_elem(tI + (J - fI)) : tiles + diag_elem(p, g0 + I);
       Acc4 c;
-      acc_load(c, cij);
+      if (J < I) {
+        acc_load(c, cij);
+        packed_to_lds(tiles + diag_elem(p, g0 + J), Y);  // inv(L_JJ)
+      } else {
+        acc_load_packed(c, cij);  // lower triangle is all the factorisation reads
+      }
       const int k0 = fI > fJ ? fI : fJ;
       for (int K = k0; K < J; ++K)
         acc_mma_abt(c, tiles + tile_elem(tI + (K - fI)), TS, tiles + tile_elem(tJ + (K - fJ)), TS, -1.0);
@@ -118,11 +132,11 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) k_
       if (J < I) {
         Acc4 o;
         acc_zero(o);
-        acc_mma_abt(o, X, LDT, tiles + tile_elem(tJ + (J - fJ)), TS, 1.0);  // C inv(L_JJ)^T
+        acc_mma_abt(o, X, LDT, Y, LDT, 1.0);  // C inv(L_JJ)^T
         acc_store(o, cij);
       } else {
         lds_potrf_trtri<16>(X, Y, &fail);
-        lds_to_tile(Y, cij);
+        lds_to_packed(Y, cij);
       }
       __syncthreads();
     }
@@ -137,37 +151,67 @@ __global__ void k_tiles_to_f32(const double *__restrict__ src, float *__restrict
     dst[e] = (float)src[e];
 }
 
-// ------------------------------------------------ local solves (1 rhs) ----
-// Row-mapped tile-vector product: thread t owns row t>>2 and 16 columns.
-template <typename T, typename C>
-__device__ __forceinline__ C tile_row_dot(const T *__restrict__ tile, const C *v) {
+// ------------------------------------------------ envelope copy ----------
+// The local solves of the apply read the factor's off-diagonal part in
+// envelope form instead of tiles: below the diagonal tiles, row r of block I
+// (rows 64I .. 64I+63) is nonzero at most in columns fenv[r] .. 64I-1, with
+// fenv nondecreasing (see the planner), so both
+//   row form    (forward sweep):  row r, columns 64I - len_r .. 64I - 1
+//   column form (backward sweep): column c of block J, rows 64(J+1) .. +len_c - 1
+// are contiguous segments; eptr / uptr hold their starts.  One workgroup per
+// tile row g; entries outside the tile profile are zero.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_env_from_tiles(Plan p, const double *__restrict__ tiles,
+                                                       T *__restrict__ erow, T *__restrict__ ecol) {
+  const int g = blockIdx.x;
+  const int i = find_segment(p.trow_ptr, p.N, g);
+  const int g0 = p.trow_ptr[i], I = g - g0;
+  const int *ep = p.eptr + p.vp_ptr[i] + i;
+  const int *up = p.uptr + p.vp_ptr[i] + i;
+  const long long eb = p.ebase[i];
   const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
-  const T *row = tile + r * TS + 16 * q;
-  const C *vv = v + 16 * q;
-  C s = 0;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) s = fma((C)row[c], vv[c], s);
-  s += __shfl_xor(s, 1, 64);
-  s += __shfl_xor(s, 2, 64);
-  return s;  // full row sum in all 4 lanes of the row
+  const int l = I * TS + r;
+  {
+    const int e0 = ep[l], len = ep[l + 1] - e0, c0 = I * TS - len;
+    const int fI = p.tfirst[g];
+    for (int k = q; k < len; k += 4) {
+      const int c = c0 + k, J = c / TS;
+      const double v =
+          J >= fI ? tiles[tile_elem(p.toff[g] + (J - fI)) + r * TS + (c - J * TS)] : 0.0;
+      erow[eb + e0 + k] = (T)v;
+    }
+  }
+  {
+    const int e0 = up[l], len = up[l + 1] - e0, r1 = (I + 1) * TS;
+    for (int k = q; k < len; k += 4) {
+      const int rw = r1 + k, Ir = rw / TS, gr = g0 + Ir;
+      const int fr = p.tfirst[gr];
+      const double v =
+          I >= fr ? tiles[tile_elem(p.toff[gr] + (I - fr)) + (rw - Ir * TS) * TS + r] : 0.0;
+      ecol[eb + e0 + k] = (T)v;
+    }
+  }
 }
 
-// The 16 entries of one tile row that a thread holds in the row mapping
-// (row t>>2, columns 16(t&3) ..), loaded ahead of their use.
+// ------------------------------------------------ local solves (1 rhs) ----
+// What one thread holds of a streamed piece of the factor: 16 entries, and
+// for an envelope chunk the vector index paired with a[0] (entry s pairs with
+// cb + 4s) and the bound kv (entries with 4s >= kv lie past the segment and
+// are zero).
 template <typename T>
-struct RowFrag {
+struct Frag {
   T a[16];
+  int cb, kv;
 };
 
+// Row mapping of a packed diagonal tile: row t>>2, columns 16(t&3) .. +15.
 template <typename T>
-__device__ __forceinline__ void row_frag_load(RowFrag<T> &f, const T *__restrict__ tile) {
-  const T *row = tile + (threadIdx.x >> 2) * TS + 16 * (threadIdx.x & 3);
-#pragma unroll
-  for (int c = 0; c < 16; ++c) f.a[c] = row[c];
+__device__ __forceinline__ void row_frag_load_diag(Frag<T> &f, const T *__restrict__ dtile) {
+  packed_row16(f.a, dtile, threadIdx.x >> 2, 16 * (threadIdx.x & 3));
 }
 
 template <typename T, typename C>
-__device__ __forceinline__ C row_frag_dot(const RowFrag<T> &f, const C *v) {
+__device__ __forceinline__ C row_frag_dot(const Frag<T> &f, const C *v) {
   const C *vv = v + 16 * (threadIdx.x & 3);
   C s = 0;
 #pragma unroll
@@ -177,26 +221,21 @@ __device__ __forceinline__ C row_frag_dot(const RowFrag<T> &f, const C *v) {
   return s;  // full row sum in all 4 lanes of the row
 }
 
-// The 16 entries a thread holds in the column-ownership mapping: wavefront w
-// owns columns 16w .. 16w+15; lane l covers column 16w + (l & 15) and rows
-// 16(l >> 4) .. +15, so a column's 64 rows sit in four lanes 16 apart.
+// Column mapping of a packed diagonal tile: wavefront w owns columns
+// 16w .. 16w+15; lane l covers column 16w + (l & 15) and rows 16(l >> 4) ..
+// +15, so a column's 64 rows sit in four lanes 16 apart.
 template <typename T>
-struct ColFrag {
-  T a[16];
-};
-
-template <typename T>
-__device__ __forceinline__ void col_frag_load(ColFrag<T> &f, const T *__restrict__ tile) {
+__device__ __forceinline__ void col_frag_load_diag(Frag<T> &f, const T *__restrict__ dtile) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const T *src = tile + (16 * (l >> 4)) * TS + 16 * w + (l & 15);
+  const int col = 16 * w + (l & 15), r0 = 16 * (l >> 4);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) f.a[r] = src[r * TS];
+  for (int r = 0; r < 16; ++r) f.a[r] = packed_at(dtile, r0 + r, col);
 }
 
 // sum_r tile[r][col] x[r] for this lane's column, complete in all four lanes
 // of the column (x: the 64-vector the tile multiplies, in LDS)
 template <typename T, typename C>
-__device__ __forceinline__ C col_frag_dot(const ColFrag<T> &f, const C *x) {
+__device__ __forceinline__ C col_frag_dot(const Frag<T> &f, const C *x) {
   const C *xx = x + 16 * ((threadIdx.x & 63) >> 4);
   C s = 0;
 #pragma unroll
@@ -206,39 +245,57 @@ __device__ __forceinline__ C col_frag_dot(const ColFrag<T> &f, const C *x) {
   return s;
 }
 
-// Column-mapped transposed product: thread t owns column t&63 and 16 rows;
-// partial sums over the 4 row groups are combined through LDS.
-template <typename T, typename C>
-__device__ __forceinline__ C tile_col_dot(const T *__restrict__ tile, const C *v) {
-  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-  C s = 0;
+// Chunk j of this thread's envelope segment (seg: its first entry, len: its
+// length, v0: the vector index of entry 0): entries k = 64j + (t&3) + 4s.
+template <typename T>
+__device__ __forceinline__ void env_chunk_load(Frag<T> &f, const T *__restrict__ seg, int len,
+                                               int v0, int j) {
+  const int kb = TS * j + (threadIdx.x & 3);
+  f.cb = v0 + kb;
+  f.kv = len - kb;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) s = fma((C)tile[(16 * g + r) * TS + c], v[16 * g + r], s);
-  return s;
+  for (int s = 0; s < 16; ++s) f.a[s] = 4 * s < f.kv ? seg[kb + 4 * s] : T(0);
+}
+
+// acc -= sum over the chunk's entries of a[s] x[cb + 4s] (partial: this
+// thread's share of the segment)
+template <typename T, typename C>
+__device__ __forceinline__ C env_chunk_dot(const Frag<T> &f, const C *x, C acc) {
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    if (4 * s < f.kv) acc = fma(-(C)f.a[s], x[f.cb + 4 * s], acc);
+  return acc;
+}
+
+size_t local_apply_lds_bytes(int max_npad, size_t csize) {
+  return (size_t)(max_npad + TS) * csize + 2 * (size_t)(max_npad + 1) * sizeof(int);
 }
 
 // Fused additive-Schwarz local kernel for one region per workgroup:
 //   gather r on the region, coarse restriction c_i = Phi_i^T r_i (optional),
-//   forward/backward substitution with the tile-profile factor (optional),
+//   forward/backward substitution with the factor (optional),
 //   store the local correction into the padded local vector xloc.
 // T: factor storage type, C: compute type, TB: basis storage type.
 template <typename T, typename C, typename TB>
 __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__restrict__ r,
-                                                    const T *__restrict__ tiles,
+                                                    const T *__restrict__ diag,
+                                                    const T *__restrict__ erow,
+                                                    const T *__restrict__ ecol,
                                                     const TB *__restrict__ phi,
                                                     double *__restrict__ xloc,
                                                     double *__restrict__ cvec, int do_local,
                                                     int do_coarse, const int *__restrict__ done) {
   if (done && *done) return;
   extern __shared__ char smem_raw[];
-  C *v = reinterpret_cast<C *>(smem_raw);          // whole local vector (padded)
-  C *tmp = v + (p.vp_ptr[blockIdx.x + 1] - p.vp_ptr[blockIdx.x]);  // 64
-  C *part = tmp + TS;                               // 4 x 64
-  __shared__ double red[MAXNEV + 1][WG / 64];
   const int i = blockIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
   const int npad = nt * TS;
+  C *v = reinterpret_cast<C *>(smem_raw);  // whole local vector (padded)
+  C *tmp = v + npad;                         // 64
+  int *er = reinterpret_cast<int *>(tmp + TS);  // npad + 1 row-form segment starts
+  int *eu = er + npad + 1;                       // npad + 1 column-form segment starts
+  __shared__ double red[MAXNEV + 1][WG / 64];
   const int nev = p.nev;
   const int m = p.mi[i];
   double cacc[MAXNEV];
@@ -257,6 +314,13 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
     }
     v[l] = (C)rv;
   }
+  if (do_local) {
+    const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
+    for (int l = threadIdx.x; l <= npad; l += WG) {
+      er[l] = ep[l];
+      eu[l] = up[l];
+    }
+  }
   if (do_coarse) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int k = 0; k < m; ++k) {
@@ -273,92 +337,120 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
   __syncthreads();
   if (!do_local) return;
   const int rr = threadIdx.x >> 2, q = threadIdx.x & 3;
-  const int cc = threadIdx.x & 63, gg = threadIdx.x >> 6;
-  // Both sweeps stream the region's tiles: the forward sweep in storage
-  // order (each row's off-diagonal tiles, then its diagonal), the backward
-  // sweep in reverse.  D + 1 register slots hold the next tiles; the slot
-  // loop is unrolled so each slot is refilled in place right after its tile
-  // is used (no register copies, which would wait for the loads in flight).
+  const T *dpool = diag + (size_t)g0 * DE;
+  const T *erow_i = erow + p.ebase[i];
+  const T *ecol_i = ecol + p.ebase[i];
+  // Each sweep streams, per block of 64 rows, the block's envelope chunks
+  // (64 entries of every row segment each) and then its diagonal tile.  A
+  // load cursor walks that sequence D + 1 pieces ahead of the consuming one;
+  // D + 1 register slots hold the pieces in flight, and the slot loop is
+  // unrolled so each slot is refilled in place right after its piece is used
+  // (no register copies, which would wait for the loads in flight).  Segment
+  // lengths are monotone inside a block (fenv nondecreasing), so the block's
+  // chunk count comes from its first row (row form) or last column (column
+  // form).
   constexpr int D = sizeof(T) == 4 ? 3 : 1;  // keeps 4 workgroups per CU resident
-  const long long t0 = p.toff[g0];
-  const int ntl = (int)(p.toff[g0 + nt - 1] + (nt - 1 - p.tfirst[g0 + nt - 1]) + 1 - t0);
-  const T *pool = tiles + tile_elem(t0);
-  // forward: y_I = inv(L_II) (b_I - sum_J L_IJ y_J)
+  auto nch_row = [&](int I) { return (er[I * TS + 1] - er[I * TS] + TS - 1) / TS; };
+  auto nch_col = [&](int I) { return (eu[I * TS + TS] - eu[I * TS + TS - 1] + TS - 1) / TS; };
+  // forward: y_I = inv(L_II) (b_I - sum_{c < 64I} L[., c] y_c)
   {
-    RowFrag<T> f[D + 1];
+    Frag<T> f[D + 1];
+    int lI = 0, lj = 0, lnch = nch_row(0);  // load cursor: block lI, chunk lj
+    auto load_next = [&](Frag<T> &fr) {
+      if (lj < lnch) {
+        const int row = lI * TS + rr;
+        const int e0 = er[row], len = er[row + 1] - e0;
+        env_chunk_load(fr, erow_i + e0, len, lI * TS - len, lj);
+        ++lj;
+      } else {
+        row_frag_load_diag(fr, dpool + (size_t)lI * DE);
+        ++lI;
+        lj = 0;
+        if (lI < nt) lnch = nch_row(lI);
+      }
+    };
 #pragma unroll
     for (int d = 0; d <= D; ++d)
-      if (d < ntl) row_frag_load(f[d], pool + tile_elem(d));
-    int I = 0, J = p.tfirst[g0];
-    C acc = v[rr];
-    for (int k0 = 0; k0 < ntl; k0 += D + 1) {
+      if (lI < nt) load_next(f[d]);
+    int I = 0, j = 0, nch = nch_row(0);
+    C acc = 0;
+    for (;;) {
 #pragma unroll
       for (int sl = 0; sl <= D; ++sl) {
-        const int k = k0 + sl;
-        if (k < ntl) {
-          if (J < I) {
-            acc -= row_frag_dot<T, C>(f[sl], v + J * TS);
-            ++J;
+        if (I < nt) {
+          if (j < nch) {
+            acc = env_chunk_dot<T, C>(f[sl], v, acc);
+            ++j;
           } else {
-            if (q == 0) tmp[rr] = acc;
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            if (q == 0) tmp[rr] = v[I * TS + rr] + acc;
             __syncthreads();
             const C y = row_frag_dot<T, C>(f[sl], tmp);
             if (q == 0) v[I * TS + rr] = y;
             __syncthreads();
             ++I;
-            if (I < nt) {
-              J = p.tfirst[g0 + I];
-              acc = v[I * TS + rr];
-            }
+            j = 0;
+            acc = 0;
+            if (I < nt) nch = nch_row(I);
           }
-          if (k + D + 1 < ntl) row_frag_load(f[sl], pool + tile_elem(k + D + 1));
+          if (lI < nt) load_next(f[sl]);
         }
       }
+      if (I >= nt) break;
     }
   }
-  // backward, right-looking: for I = nt-1 .. 0, x_I = inv(L_II)^T y_I, then
-  // y_J -= L_IJ^T x_I for the off-diagonal tiles J of row I (storage order
-  // reversed: the diagonal first, then J descending).  Wavefront w owns
-  // columns 16w .. 16w+15 of every product, so each y_J entry has a single
-  // writer and a row needs two barriers.
+  // backward: x_J = inv(L_JJ)^T (y_J - sum_{r >= 64(J+1)} L[r, .]^T x_r),
+  // J = nt-1 .. 0, with the column form (row c of L^T).
   {
-    ColFrag<T> f[D + 1];
+    Frag<T> f[D + 1];
+    int lI = nt - 1, lj = 0, lnch = nch_col(nt - 1);
+    auto load_next = [&](Frag<T> &fr) {
+      if (lj < lnch) {
+        const int c = lI * TS + rr;
+        const int e0 = eu[c], len = eu[c + 1] - e0;
+        env_chunk_load(fr, ecol_i + e0, len, (lI + 1) * TS, lj);
+        ++lj;
+      } else {
+        col_frag_load_diag(fr, dpool + (size_t)lI * DE);
+        --lI;
+        lj = 0;
+        if (lI >= 0) lnch = nch_col(lI);
+      }
+    };
 #pragma unroll
     for (int d = 0; d <= D; ++d)
-      if (d < ntl) col_frag_load(f[d], pool + tile_elem(ntl - 1 - d));
+      if (lI >= 0) load_next(f[d]);
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int col = 16 * w + (l & 15);
     const bool head = (l >> 4) == 0;  // one lane of the four that share a column
-    int I = nt - 1, J = nt - 1, fI = p.tfirst[g0 + nt - 1];
-    for (int k0 = 0; k0 < ntl; k0 += D + 1) {
+    int I = nt - 1, j = 0, nch = nch_col(nt - 1);
+    C acc = 0;
+    for (;;) {
 #pragma unroll
       for (int sl = 0; sl <= D; ++sl) {
-        const int k = k0 + sl;
-        if (k < ntl) {
-          if (J == I) {
-            __syncthreads();  // y_I complete (updates from rows > I)
-            const C x = col_frag_dot<T, C>(f[sl], v + I * TS);
-            if (head) tmp[col] = x;
-            __syncthreads();  // x_I visible in tmp; all reads of y_I done
+        if (I >= 0) {
+          if (j < nch) {
+            acc = env_chunk_dot<T, C>(f[sl], v, acc);
+            ++j;
+          } else {
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            if (q == 0) tmp[rr] = v[I * TS + rr] + acc;
+            __syncthreads();  // tmp complete
+            const C x = col_frag_dot<T, C>(f[sl], tmp);
             if (head) v[I * TS + col] = x;
-          } else {
-            const C s2 = col_frag_dot<T, C>(f[sl], tmp);
-            if (head) v[J * TS + col] -= s2;
-          }
-          if (J > fI) {
-            --J;
-          } else {
+            __syncthreads();  // x_I visible; all reads of tmp done
             --I;
-            if (I >= 0) {
-              J = I;
-              fI = p.tfirst[g0 + I];
-            }
+            j = 0;
+            acc = 0;
+            if (I >= 0) nch = nch_col(I);
           }
-          if (k + D + 1 < ntl) col_frag_load(f[sl], pool + tile_elem(ntl - 1 - (k + D + 1)));
+          if (lI >= 0) load_next(f[sl]);
         }
       }
+      if (I < 0) break;
     }
-    __syncthreads();
   }
   // local correction in the region's ascending-global-index layout, so that
   // the scatter reads contiguous runs
@@ -366,117 +458,40 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
   for (int l = threadIdx.x; l < ni; l += WG) dst[p.nat[r0 + l]] = (double)v[l];
 }
 
-// ------------------------------------------- block solve (EIGP rhs) -------
-// In-place (L L^T)^{-1} X for a row-major padded block X[rows][EIGP], one
-// workgroup per region; regions flagged in skip[] are left untouched.
-template <typename T>
-__global__ void __launch_bounds__(WG) k_profile_solve_block(Plan p, const T *__restrict__ tiles,
-                                                            double *__restrict__ X,
-                                                            const int *__restrict__ skip) {
-  const int i = blockIdx.x;
-  if (skip && skip[i]) return;
-  extern __shared__ double lds[];
-  double *Lt = lds;                    // 64 x LDT
-  double *V = lds + TS * LDT;          // 64 x (EIGP+1) right-hand block
-  double *Acc = V + TS * (EIGP + 1);   // 64 x (EIGP+1)
-  constexpr int LV = EIGP + 1;
-  const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
-  double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
-  const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 4;
-  // forward
-  for (int I = 0; I < nt; ++I) {
-    const int fI = p.tfirst[g0 + I];
-    const long long tI = p.toff[g0 + I];
-    double acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = Xi[(size_t)(I * TS + r) * EIGP + c0 + j];
-    for (int J = fI; J < I; ++J) {
-      __syncthreads();
-      tile_to_lds(tiles + tile_elem(tI + (J - fI)), Lt);
-      for (int e = threadIdx.x; e < TS * EIGP; e += WG)
-        V[(e / EIGP) * LV + (e % EIGP)] = Xi[(size_t)J * TS * EIGP + e];
-      __syncthreads();
-      for (int k = 0; k < TS; ++k) {
-        const double a = Lt[r * LDT + k];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = fma(-a, V[k * LV + c0 + j], acc[j]);
-      }
-    }
-    __syncthreads();
-    tile_to_lds(tiles + tile_elem(tI + (I - fI)), Lt);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Acc[r * LV + c0 + j] = acc[j];
-    __syncthreads();
-    double y[4] = {0, 0, 0, 0};
-    for (int k = 0; k < TS; ++k) {
-      const double a = Lt[r * LDT + k];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = fma(a, Acc[k * LV + c0 + j], y[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Xi[(size_t)(I * TS + r) * EIGP + c0 + j] = y[j];
-  }
-  // backward
-  for (int I = nt - 1; I >= 0; --I) {
-    __syncthreads();
-    double acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = Xi[(size_t)(I * TS + r) * EIGP + c0 + j];
-    for (int J = I + 1; J < nt; ++J) {
-      const int fJ = p.tfirst[g0 + J];
-      if (fJ > I) continue;
-      __syncthreads();
-      tile_to_lds(tiles + tile_elem(p.toff[g0 + J] + (I - fJ)), Lt);
-      for (int e = threadIdx.x; e < TS * EIGP; e += WG)
-        V[(e / EIGP) * LV + (e % EIGP)] = Xi[(size_t)J * TS * EIGP + e];
-      __syncthreads();
-      // acc[r][:] -= sum_k L_JI[k][r] V[k][:]
-      for (int k = 0; k < TS; ++k) {
-        const double a = Lt[k * LDT + r];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = fma(-a, V[k * LV + c0 + j], acc[j]);
-      }
-    }
-    __syncthreads();
-    const int fI = p.tfirst[g0 + I];
-    tile_to_lds(tiles + tile_elem(p.toff[g0 + I] + (I - fI)), Lt);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Acc[r * LV + c0 + j] = acc[j];
-    __syncthreads();
-    double y[4] = {0, 0, 0, 0};
-    for (int k = 0; k < TS; ++k) {
-      const double a = Lt[k * LDT + r];  // inv(L_II)^T
-#pragma unroll
-      for (int j = 0; j < 4; ++j) y[j] = fma(a, Acc[k * LV + c0 + j], y[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Xi[(size_t)(I * TS + r) * EIGP + c0 + j] = y[j];
-  }
-}
-
 // ------------------------------------ block solve on MFMA (EIGP rhs) ------
-// Same operation as k_profile_solve_block, one workgroup (4 wavefronts) per
-// region: wavefront w owns rows 16w..16w+15 of the 64 x EIGP block of the
+// In-place (L L^T)^{-1} X for a row-major padded block X[rows][EIGP] (the
+// subspace block of the local eigensolver), one workgroup (4 wavefronts) per
+// region; regions flagged in skip[] are left untouched.  Wavefront w owns
+// rows 16w..16w+15 of the 64 x EIGP block of the
 // current tile row.  A 64x64 tile times the 64x16 block is 16 MFMA steps;
 // K-slot q of step s stands for column k = 16q + s, so that each lane reads
 // 16 contiguous entries of one tile row (non-transposed products) and the
 // transposed products read 16 consecutive columns per instruction.
+// packed: the tile is a packed diagonal tile (zero above the diagonal).
 template <typename T>
 __device__ __forceinline__ d4 mfma_tile_rhs(const T *__restrict__ tile, const double *rhs, int w,
-                                            int transpose, d4 acc, double sign) {
+                                            int transpose, int packed, d4 acc, double sign) {
   const int l = threadIdx.x & 63;
   const int i = l & 15, q = l >> 4;
-  double a[16];
+  T t[16];
   if (!transpose) {
-    const T *row = tile + (16 * w + i) * TS + 16 * q;
+    if (packed) {
+      packed_row16(t, tile, 16 * w + i, 16 * q);
+    } else {
+      const T *row = tile + (16 * w + i) * TS + 16 * q;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) a[s] = (double)row[s];
+      for (int s = 0; s < 16; ++s) t[s] = row[s];
+    }
+  } else if (packed) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) t[s] = packed_at(tile, 16 * q + s, 16 * w + i);
   } else {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) a[s] = (double)tile[(16 * q + s) * TS + 16 * w + i];
+    for (int s = 0; s < 16; ++s) t[s] = tile[(16 * q + s) * TS + 16 * w + i];
   }
 #pragma unroll
-  for (int s = 0; s < 16; ++s) acc = mfma16x16x4(sign * a[s], rhs[(16 * q + s) * (EIGP + 1) + i], acc);
+  for (int s = 0; s < 16; ++s)
+    acc = mfma16x16x4(sign * (double)t[s], rhs[(16 * q + s) * (EIGP + 1) + i], acc);
   return acc;
 }
 
@@ -508,13 +523,13 @@ __global__ void __launch_bounds__(WG) k_profile_solve_block_mfma(Plan p, const T
       __syncthreads();
       load_block(J, V);
       __syncthreads();
-      acc = mfma_tile_rhs<T>(tiles + tile_elem(tI + (J - fI)), V, w, 0, acc, -1.0);
+      acc = mfma_tile_rhs<T>(tiles + tile_elem(tI + (J - fI)), V, w, 0, 0, acc, -1.0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) Acc[(rb + 4 * r) * LV + col] = acc[r];
     __syncthreads();
     d4 y = {0.0, 0.0, 0.0, 0.0};
-    y = mfma_tile_rhs<T>(tiles + tile_elem(tI + (I - fI)), Acc, w, 0, y, 1.0);
+    y = mfma_tile_rhs<T>(tiles + diag_elem(p, g0 + I), Acc, w, 0, 1, y, 1.0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) Xi[(size_t)(I * TS + rb + 4 * r) * EIGP + col] = y[r];
     __syncthreads();
@@ -530,14 +545,13 @@ __global__ void __launch_bounds__(WG) k_profile_solve_block_mfma(Plan p, const T
       __syncthreads();
       load_block(J, V);
       __syncthreads();
-      acc = mfma_tile_rhs<T>(tiles + tile_elem(p.toff[g0 + J] + (I - fJ)), V, w, 1, acc, -1.0);
+      acc = mfma_tile_rhs<T>(tiles + tile_elem(p.toff[g0 + J] + (I - fJ)), V, w, 1, 0, acc, -1.0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) Acc[(rb + 4 * r) * LV + col] = acc[r];
     __syncthreads();
-    const int fI = p.tfirst[g0 + I];
     d4 y = {0.0, 0.0, 0.0, 0.0};
-    y = mfma_tile_rhs<T>(tiles + tile_elem(p.toff[g0 + I] + (I - fI)), Acc, w, 1, y, 1.0);
+    y = mfma_tile_rhs<T>(tiles + diag_elem(p, g0 + I), Acc, w, 1, 1, y, 1.0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) Xi[(size_t)(I * TS + rb + 4 * r) * EIGP + col] = y[r];
     __syncthreads();
@@ -670,32 +684,40 @@ void launch_tiles_to_f32(hipStream_t s, const double *src, float *dst, size_t co
   hipLaunchKernelGGL(k_tiles_to_f32, dim3((unsigned)b), dim3(WG), 0, s, src, dst, count);
 }
 
+template <typename T>
+void launch_env_from_tiles(hipStream_t s, const Plan &p, int ntilerows, const double *tiles,
+                           T *erow, T *ecol) {
+  hipLaunchKernelGGL((k_env_from_tiles<T>), dim3(ntilerows), dim3(WG), 0, s, p, tiles, erow, ecol);
+}
+template void launch_env_from_tiles<double>(hipStream_t, const Plan &, int, const double *,
+                                            double *, double *);
+template void launch_env_from_tiles<float>(hipStream_t, const Plan &, int, const double *,
+                                           float *, float *);
+
 template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
-                          const T *tiles, const TB *phi, double *xloc, double *cvec, int do_local,
-                          int do_coarse, const int *done, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  size_t sm = (size_t)(max_npad + TS + 4 * TS) * sizeof(C);
+                          const T *diag, const T *erow, const T *ecol, const TB *phi,
+                          double *xloc, double *cvec, int do_local, int do_coarse,
+                          const int *done, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const size_t sm = local_apply_lds_bytes(max_npad, sizeof(C));
   allow_lds(k_local_apply<T, C, TB>, sm);
   if (ev_start || ev_stop)  // events bound to this dispatch: exact kernel duration
     hipExtLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, ev_start, ev_stop,
-                          0, p, r, tiles, phi, xloc, cvec, do_local, do_coarse, done);
+                          0, p, r, diag, erow, ecol, phi, xloc, cvec, do_local, do_coarse, done);
   else
-    hipLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, p, r, tiles, phi,
-                       xloc, cvec, do_local, do_coarse, done);
+    hipLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, p, r, diag, erow,
+                       ecol, phi, xloc, cvec, do_local, do_coarse, done);
 }
 
-template void launch_local_apply_t<double, double, double>(hipStream_t, const Plan &, int,
-                                                           const double *, const double *,
-                                                           const double *, double *, double *,
-                                                           int, int, const int *, hipEvent_t,
-                                                           hipEvent_t);
-template void launch_local_apply_t<float, float, float>(hipStream_t, const Plan &, int,
-                                                        const double *, const float *,
-                                                        const float *, double *, double *, int,
-                                                        int, const int *, hipEvent_t, hipEvent_t);
-template void launch_local_apply_t<float, float, __hip_bfloat16>(
-    hipStream_t, const Plan &, int, const double *, const float *, const __hip_bfloat16 *,
-    double *, double *, int, int, const int *, hipEvent_t, hipEvent_t);
+#define AMSP_LOCAL_APPLY_INST(T, C, TB)                                                        \
+  template void launch_local_apply_t<T, C, TB>(hipStream_t, const Plan &, int, const double *, \
+                                               const T *, const T *, const T *, const TB *,    \
+                                               double *, double *, int, int, const int *,      \
+                                               hipEvent_t, hipEvent_t);
+AMSP_LOCAL_APPLY_INST(double, double, double)
+AMSP_LOCAL_APPLY_INST(float, float, float)
+AMSP_LOCAL_APPLY_INST(float, float, __hip_bfloat16)
+#undef AMSP_LOCAL_APPLY_INST
 
 template <typename T>
 void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, const double *X,
