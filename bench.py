@@ -167,7 +167,7 @@ def traffic_from_profile():
 
 
 # sources that define the local-apply kernel (a change invalidates its counters)
-TRAFFIC_SOURCES = ("k_local.hip", "k_common.h", "amsp_consts.h", "amsp_internal.h")
+TRAFFIC_SOURCES = ("k_apply.hip", "k_common.h", "amsp_consts.h", "amsp_internal.h")
 
 
 def main():
@@ -260,7 +260,7 @@ def main():
         "mixed_vs_fp64_speedup": (round(fp64_t / sums[head]["time_to_solution_ms"], 3)
                                   if fp64_t and head != "fp64" else None),
         "mixed_vs_fp64_u_relerr": agree,
-        "roofline": {"bound": "hbm", "kernel": "k_local_apply (gather, restriction, profile "
+        "roofline": {"bound": "hbm", "kernel": "k_local_apply (gather, restriction, envelope "
                                                "forward/backward solves)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(),

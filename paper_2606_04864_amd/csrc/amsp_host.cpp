@@ -476,10 +476,25 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     HIP_TRY(hipMemsetAsync(conv, 0, h->N * sizeof(int), h->stream));
     launch_extract_tiles(h->stream, p, h->ntilerows, h->val, h->sdiag, facB, 1, h->opt.eig_shift);
     launch_profile_cholesky(h->stream, p, facB, status, 4);
-    float *facB32 = nullptr;
+    // the sweeps' factor: packed inverse diagonal tiles + envelope, in the
+    // sweep precision (f32 in the mixed forms)
+    const size_t ndiag = (size_t)h->ntilerows * DE, nenv = (size_t)P.nenv;
+    const double *dsrcB = facB + (size_t)P.noff * TE;
+    float *dgB32 = nullptr, *erB32 = nullptr, *ecB32 = nullptr;
+    double *dgB64 = nullptr, *erB64 = nullptr, *ecB64 = nullptr;
     if (mixed) {
-      ALLOC(facB32, float, fac_elems);
-      launch_tiles_to_f32(h->stream, facB, facB32, fac_elems);
+      ALLOC(dgB32, float, ndiag);
+      ALLOC(erB32, float, nenv);
+      ALLOC(ecB32, float, nenv);
+      launch_tiles_to_f32(h->stream, dsrcB, dgB32, ndiag);
+      launch_env_from_tiles<float>(h->stream, p, h->ntilerows, facB, erB32, ecB32);
+    } else {
+      ALLOC(dgB64, double, ndiag);
+      ALLOC(erB64, double, nenv);
+      ALLOC(ecB64, double, nenv);
+      HIP_TRY(hipMemcpyAsync(dgB64, dsrcB, ndiag * sizeof(double), hipMemcpyDeviceToDevice,
+                             h->stream));
+      launch_env_from_tiles<double>(h->stream, p, h->ntilerows, facB, erB64, ecB64);
     }
     {
       int bad;
@@ -490,10 +505,8 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
         return AMSP_ERR_LOCAL_NOT_SPD;
       }
     }
-    if (mixed) {
-      h->mem.free_one(facB);
-      facB = nullptr;
-    }
+    h->mem.free_one(facB);
+    facB = nullptr;
     launch_eig_init(h->stream, p, h->sdiag, X);
     launch_eig_bval(h->stream, p, h->val, h->sdiag, bval);
     const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-5 : 1e-12);
@@ -501,9 +514,9 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     int sweeps = 0, unconv = h->N;
     for (int it = 1; it <= h->opt.eig_maxit; ++it) {
       if (mixed)
-        launch_profile_solve_block<float>(h->stream, p, facB32, X, Yb, conv);
+        launch_env_solve_block<float>(h->stream, p, dgB32, erB32, ecB32, X, Yb, conv);
       else
-        launch_profile_solve_block<double>(h->stream, p, facB, X, Yb, conv);
+        launch_env_solve_block<double>(h->stream, p, dgB64, erB64, ecB64, X, Yb, conv);
       launch_eig_rr(h->stream, p, P.max_ni, h->val, h->sdiag, bval, Yb, BY, X, GK, CC, tol, conv,
                     h->lam);
       sweeps = it;
@@ -530,8 +543,9 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     launch_build_basis(h->stream, p, h->sdiag, X, h->phi64, h->opt.pou);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(h->stream));
-    if (facB) h->mem.free_one(facB);
-    if (facB32) h->mem.free_one(facB32);
+    for (void *b : {(void *)dgB32, (void *)erB32, (void *)ecB32, (void *)dgB64, (void *)erB64,
+                    (void *)ecB64})
+      if (b) h->mem.free_one(b);
     h->mem.free_one(X);
     h->mem.free_one(Yb);
     h->mem.free_one(BY);

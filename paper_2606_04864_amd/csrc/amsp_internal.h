@@ -100,10 +100,6 @@ void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const doub
                           double *xloc, double *cvec, int do_local, int do_coarse,
                           const int *done, hipEvent_t ev_start = nullptr,
                           hipEvent_t ev_stop = nullptr);
-// Y = (L L^T)^{-1} X on row-major [rows][EIGP] padded blocks (Y may equal X).
-template <typename T>
-void launch_profile_solve_block(hipStream_t s, const Plan &p, const T *tiles, const double *X,
-                                double *Y, const int *skip);
 void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D);
 template <typename TB>
 void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
@@ -120,6 +116,11 @@ void launch_basis_to_natural(hipStream_t s, const Plan &p, const TB *src, TB *ds
 // Off-diagonal values of the scaled local operators B_i per local CSR entry.
 void launch_eig_bval(hipStream_t s, const Plan &p, const double *val, const double *sdiag,
                      double *bval);
+// Y = (L L^T)^{-1} X on row-major [rows][EIGP] padded blocks, L given as
+// packed inverse diagonal tiles + envelope (as for the local apply).
+template <typename T>
+void launch_env_solve_block(hipStream_t s, const Plan &p, const T *diag, const T *erow,
+                            const T *ecol, const double *X, double *Y, const int *skip);
 // Rayleigh-Ritz step on the solve output Y, writing the Ritz vectors into X
 // (distinct buffer), residuals, convergence flags and eigenvalues.
 // BY: scratch like Y; GK: N*2*EIGP*EIGP doubles; CC: N*(EIGP*EIGP+EIGP).

@@ -5,7 +5,7 @@
 // standard form B_i z = lambda z with B_i = S^{-1/2} hat A_i S^{-1/2} and
 // psi = S^{-1/2} z (Section 5, parameter test).  Method: block shift-invert
 // subspace iteration (Bathe-Wilson) with EIGP columns: Y = (B_i + sigma I)^{-1} X
-// (tile-profile Cholesky solves, k_profile_solve_block_mfma), then a Rayleigh-Ritz
+// (Cholesky solves, k_env_solve_block), then a Rayleigh-Ritz
 // step here through the Gram matrices: G = Y^T Y = L L^T, K = Y^T B_i Y with
 // the sparse B_i, H = inv(L) K inv(L)^T, cyclic Jacobi on the EIGP x EIGP
 // matrix H, X = Y inv(L)^T V sorted ascending, and residuals
@@ -510,6 +510,182 @@ __global__ void k_basis_convert(const double *__restrict__ src, void *__restrict
 }
 
 // ------------------------------------------------------------- launchers ---
+// ------------------------------------------- block solve (EIGP rhs) -------
+// Y = (L L^T)^{-1} X for the row-major padded blocks X[rows][EIGP] of every
+// region, one workgroup per region (regions flagged in skip[] are left
+// untouched), with L in the local apply's layout: packed inverse diagonal
+// tiles and the envelope below them (row form forward, column form
+// backward).  Per 64-row block the envelope part is a dot product of each
+// row's segment with finished rows; the diagonal part multiplies the
+// 64 x EIGP block by inv(L_II) (or its transpose) on the matrix cores:
+// wavefront w owns rows 16w..16w+15, and K-slot q of MFMA step s stands for
+// column k = 16q + s.  A block's segments are contiguous, so the workgroup
+// stages them in LDS with one coalesced load (EVC entries at a time).  The
+// last RING finished rows stay in LDS (row g in slot g mod RING), so a block
+// whose segments reach back (forward) or ahead (backward) at most RING rows
+// reads them there; longer segments read the finished rows from global
+// memory.  Each block's loads are issued together at its start, its segment
+// bounds one block earlier.
+template <typename T>
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4)))
+k_env_solve_block(Plan p, const T *__restrict__ diag, const T *__restrict__ erow,
+                  const T *__restrict__ ecol, const double *Xin, double *X,
+                  const int *__restrict__ skip) {
+  const int i = blockIdx.x;
+  if (skip && skip[i]) return;
+  constexpr int LV = EIGP + 1;   // padded LDS row
+  constexpr int RING = 2 * TS;   // finished rows kept in LDS
+  constexpr int EVC = 4 * WG;    // envelope entries staged per pass (4 per thread)
+  __shared__ double Rg[RING * LV];
+  __shared__ double Acc[TS * LV];
+  __shared__ T Ev[EVC];
+  const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
+  const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
+  const T *erow_i = erow + p.ebase[i], *ecol_i = ecol + p.ebase[i];
+  const T *dpool = diag + (size_t)g0 * DE;
+  double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
+  const double *Xin_i = Xin + (size_t)p.vp_ptr[i] * EIGP;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int mi = l & 15, mq = l >> 4;        // MFMA operand lane roles
+  const int rb = 16 * w + (l >> 4);          // D register r: row rb + 4r, column mi
+  const int rr = tid >> 2, q = tid & 3;      // envelope: row rr, columns 4q..4q+3
+  // Segment bounds of one block: this thread's row (e0, len), the block's
+  // entries [base, base + total) and its longest segment ltop.
+  struct Seg {
+    int e0, len, base, total, ltop;
+  };
+  auto seg_row = [&](int r0) {  // row form: the longest segment is the first row's
+    Seg g;
+    g.e0 = ep[r0 + rr];
+    g.len = ep[r0 + rr + 1] - g.e0;
+    g.base = ep[r0];
+    g.total = ep[r0 + TS] - g.base;
+    g.ltop = ep[r0 + 1] - g.base;
+    return g;
+  };
+  auto seg_col = [&](int r0) {  // column form: the longest segment is the last column's
+    Seg g;
+    g.e0 = up[r0 + rr];
+    g.len = up[r0 + rr + 1] - g.e0;
+    g.base = up[r0];
+    g.total = up[r0 + TS] - g.base;
+    g.ltop = up[r0 + TS] - up[r0 + TS - 1];
+    return g;
+  };
+  // entries [c0, c0 + EVC) of the block's segments, this thread's share
+  auto ev_load = [&](const T *src, const Seg &g, int c0, T (&ev)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = c0 + tid + WG * u;
+      ev[u] = k < g.total ? src[g.base + k] : T(0);
+    }
+  };
+  // acc[j] -= sum_k seg[k] * (finished row v0 + k)[4q + j]
+  auto env_part = [&](const T *src, const Seg &g, int v0, const T (&ev0)[4], double (&acc)[4]) {
+    const bool in_ring = g.ltop <= RING;
+    const int off = g.e0 - g.base;  // this row's first entry within the block's entries
+    for (int c0 = 0; c0 < g.total; c0 += EVC) {
+      T ev[4];
+      if (c0 == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ev[u] = ev0[u];
+      } else {
+        ev_load(src, g, c0, ev);
+      }
+      __syncthreads();  // earlier readers of Ev are done
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Ev[tid + WG * u] = ev[u];
+      __syncthreads();
+      const int kb = max(0, c0 - off), ke = min(g.len, c0 + EVC - off);
+      for (int k = kb; k < ke; ++k) {
+        const double a = (double)Ev[off + k - c0];
+        const int row = v0 + k;
+        const double *wr = in_ring ? Rg + (row & (RING - 1)) * LV + 4 * q
+                                   : Xi + (size_t)row * EIGP + 4 * q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = fma(-a, wr[j], acc[j]);
+      }
+    }
+  };
+  // y (rows rb + 4r, column mi of the block at row r0) into the ring and X
+  auto store_block = [&](int r0, const d4 &y) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + rb + 4 * r;
+      Rg[(row & (RING - 1)) * LV + mi] = y[r];
+      Xi[(size_t)row * EIGP + mi] = y[r];
+    }
+  };
+  // forward: Y_I = inv(L_II) (X_I - L[I rows, c < 64I] Y)
+  {
+    Seg gn = seg_row(0);
+    for (int I = 0; I < nt; ++I) {
+      const int r0 = I * TS;
+      const Seg g = gn;
+      T dA[16];
+      packed_row16(dA, dpool + (size_t)I * DE, 16 * w + mi, 16 * mq);
+      T ev0[4];
+      ev_load(erow_i, g, 0, ev0);
+      double xin[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xin[j] = Xin_i[(size_t)(r0 + rr) * EIGP + 4 * q + j];
+      if (I + 1 < nt) gn = seg_row(r0 + TS);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      env_part(erow_i, g, r0 - g.len, ev0, acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Acc[rr * LV + 4 * q + j] = xin[j] + acc[j];
+      __syncthreads();  // Acc complete; all ring reads of this block done
+      d4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 16; ++s) y = mfma16x16x4((double)dA[s], Acc[(16 * mq + s) * LV + mi], y);
+      store_block(r0, y);
+      __syncthreads();  // Y_I visible in the ring and X; Acc free
+    }
+  }
+  // backward: X_J = inv(L_JJ)^T (Y_J - L[r >= 64(J+1), J cols]^T X)
+  {
+    Seg gn = seg_col((nt - 1) * TS);
+    for (int J = nt - 1; J >= 0; --J) {
+      const int r0 = J * TS, r1 = r0 + TS;
+      const Seg g = gn;
+      T dA[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        dA[s] = packed_at(dpool + (size_t)J * DE, 16 * mq + s, 16 * w + mi);
+      T ev0[4];
+      ev_load(ecol_i, g, 0, ev0);
+      double yin[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yin[j] = Xi[(size_t)(r0 + rr) * EIGP + 4 * q + j];
+      if (J > 0) gn = seg_col(r0 - TS);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      env_part(ecol_i, g, r1, ev0, acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Acc[rr * LV + 4 * q + j] = yin[j] + acc[j];
+      __syncthreads();
+      d4 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 16; ++s) y = mfma16x16x4((double)dA[s], Acc[(16 * mq + s) * LV + mi], y);
+      store_block(r0, y);
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+void launch_env_solve_block(hipStream_t s, const Plan &p, const T *diag, const T *erow,
+                            const T *ecol, const double *X, double *Y, const int *skip) {
+  hipLaunchKernelGGL((k_env_solve_block<T>), dim3(p.N), dim3(WG), 0, s, p, diag, erow, ecol, X, Y,
+                     skip);
+}
+template void launch_env_solve_block<double>(hipStream_t, const Plan &, const double *,
+                                             const double *, const double *, const double *,
+                                             double *, const int *);
+template void launch_env_solve_block<float>(hipStream_t, const Plan &, const float *,
+                                            const float *, const float *, const double *, double *,
+                                            const int *);
+
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X) {
   hipLaunchKernelGGL(k_eig_init, dim3(p.N), dim3(WG), 0, s, p, sdiag, X);
 }
