@@ -74,6 +74,10 @@ struct amsp_handle {
   // matrix
   int *rowptr = nullptr, *col = nullptr;
   double *val = nullptr;
+  // sliced copy for the CG matrix product (64-row slices, column-major)
+  long long *sptr = nullptr;
+  int *scol = nullptr;
+  double *sval = nullptr;
   // plan
   Plan plan{};
   CoarsePlan cplan{};
@@ -388,6 +392,25 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     HIP_TRY(hipMemcpyAsync(h->val, A->val, h->nnz * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     tb = now_ms();
+    // sliced copy for the CG matrix product
+    const int ns = (h->n + 63) / 64;
+    std::vector<long long> sp(ns + 1);
+    sp[0] = 0;
+    for (int sl = 0; sl < ns; ++sl) {
+      int w = 0;
+      for (int i = 64 * sl; i < std::min(h->n, 64 * sl + 64); ++i)
+        w = std::max(w, (int)(A->row_ptr[i + 1] - A->row_ptr[i]));
+      sp[sl + 1] = sp[sl] + 64LL * w;
+    }
+    h->sptr = upload(h, sp, ok);
+    h->scol = h->mem.alloc<int>(std::max<long long>(1, sp[ns]));
+    h->sval = h->mem.alloc<double>(std::max<long long>(1, sp[ns]));
+    if (!ok || !h->scol || !h->sval) {
+      h->err = "device allocation failed (sliced matrix)";
+      return AMSP_ERR_OOM;
+    }
+    launch_csr_to_sell(h->stream, h->n, h->rowptr, h->col, h->val, h->sptr, h->scol, h->sval);
+    HIP_TRY(hipGetLastError());
   }
   Plan &p = h->plan;
   p.N = h->N;
@@ -1030,7 +1053,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
         for (int c = 0; c < next; ++c) {
           h->cur_t = t;
           int tk = tstart(h, 0);
-          launch_cg_dir(h->stream, n, h->rowptr, h->col, h->val, h->z, pold, pnew, h->q, h->part_a,
+          launch_cg_dir(h->stream, n, h->sptr, h->scol, h->sval, h->z, pold, pnew, h->q, h->part_a,
                         h->st, h->part_d, h->part_b, h->part_c, t, first ? 1 : 0,
                         h->opt.flexible);
           tstop(h, 0, tk);

@@ -50,10 +50,15 @@ void launch_spmv(hipStream_t s, int n, const int *rp, const int *col, const doub
                  const double *x, double *y, double *partial, const int *done);
 // One CG step t in two kernels (direction + update); the scalar reductions
 // of the previous kernels are folded in (see k_krylov.hip).
-void launch_cg_dir(hipStream_t s, int n, const int *rp, const int *col, const double *val,
-                   const double *z, const double *pold, double *pnew, double *q, double *part_pq,
-                   PcgState *st, const double *part_rr, const double *part_rz,
+// The direction kernel's matrix product reads the sliced copy of A (64-row
+// slices, column-major inside a slice; see launch_csr_to_sell).
+void launch_cg_dir(hipStream_t s, int n, const long long *sptr, const int *scol,
+                   const double *sval, const double *z, const double *pold, double *pnew, double *q,
+                   double *part_pq, PcgState *st, const double *part_rr, const double *part_rz,
                    const double *part_rzo, int t, int first, int flexible);
+// Sliced copy of A: sptr[s] = first entry of slice s (ceil(n/64) + 1 entries).
+void launch_csr_to_sell(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                        const long long *sptr, int *scol, double *sval);
 void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q,
                       PcgState *st, const double *part_pq, int t, double *part_rr,
                       const double *zold, double *part_rzo);

@@ -158,9 +158,9 @@ __global__ void __launch_bounds__(WG) k_pcg_init(PcgState *st, const double *prr
 // q = A p_new (neighbours' p_new entries recomputed from z and p_old), with
 // partials p_new.q.  rz of step t is kept in rz_ring[t & 1] so that no
 // workgroup reads a value this kernel is writing.
-__global__ void __launch_bounds__(WG) k_cg_dir(int n, const int *__restrict__ rp,
-                                               const int *__restrict__ col,
-                                               const double *__restrict__ val,
+__global__ void __launch_bounds__(WG) k_cg_dir(int n, const long long *__restrict__ sptr,
+                                               const int *__restrict__ scol,
+                                               const double *__restrict__ sval,
                                                const double *__restrict__ z,
                                                const double *__restrict__ pold,
                                                double *__restrict__ pnew, double *__restrict__ q,
@@ -201,21 +201,84 @@ __global__ void __launch_bounds__(WG) k_cg_dir(int n, const int *__restrict__ rp
     }
     if (stop) return;
   }
+  // q = A p with p = z + beta p_old formed on the fly, on the sliced layout:
+  // U rows per thread (one 64-row slice per wavefront each), the first JU
+  // entries of every row loaded together.
+  constexpr int U = 2, JU = 8;
+  const int lane = threadIdx.x & 63;
+  const int stride = gridDim.x * WG;
   double acc = 0.0;
-  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-    double s = 0.0;
-    const int e1 = rp[i + 1];
-    for (int e = rp[i]; e < e1; ++e) {
-      const int c = col[e];
-      s = fma(val[e], fma(beta, pold[c], z[c]), s);
+  for (int i0 = blockIdx.x * WG + threadIdx.x; i0 < n; i0 += U * stride) {
+    long long base[U];
+    int wd[U];
+    double sacc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * stride;
+      const int sl = i >> 6;
+      base[u] = i < n ? sptr[sl] : 0;
+      wd[u] = i < n ? (int)((sptr[sl + 1] - base[u]) >> 6) : 0;
+      sacc[u] = 0.0;
     }
-    const double pi = fma(beta, pold[i], z[i]);
-    pnew[i] = pi;
-    q[i] = s;
-    acc = fma(pi, s, acc);
+    int cj[U][JU];
+    double vj[U][JU];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < JU; ++j) {
+        const bool in = j < wd[u];
+        const long long e = base[u] + (long long)j * 64 + lane;
+        cj[u][j] = in ? scol[e] : 0;
+        vj[u][j] = in ? sval[e] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < JU; ++j)
+        if (j < wd[u]) {
+          const int c = cj[u][j];
+          sacc[u] = fma(vj[u][j], fma(beta, pold[c], z[c]), sacc[u]);
+        }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      for (int j = JU; j < wd[u]; ++j) {  // rows longer than JU entries
+        const long long e = base[u] + (long long)j * 64 + lane;
+        const int c = scol[e];
+        sacc[u] = fma(sval[e], fma(beta, pold[c], z[c]), sacc[u]);
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * stride;
+      if (i < n) {
+        const double pi = fma(beta, pold[i], z[i]);
+        pnew[i] = pi;
+        q[i] = sacc[u];
+        acc = fma(pi, sacc[u], acc);
+      }
+    }
   }
   double tot = block_sum(acc, sh);
   if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
+}
+
+// Sliced copy of the CSR matrix for the CG matrix product: 64-row slices,
+// slice s holding (sptr[s+1] - sptr[s]) / 64 entries per row, column-major
+// inside the slice (entry j of row 64s + l at sptr[s] + 64j + l), short rows
+// padded with zero values pointing at their own row.
+__global__ void k_csr_to_sell(int n, const int *__restrict__ rp, const int *__restrict__ col,
+                              const double *__restrict__ val, const long long *__restrict__ sptr,
+                              int *__restrict__ scol, double *__restrict__ sval) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int sl = i >> 6, lane = i & 63;
+    const long long base = sptr[sl];
+    const int w = (int)((sptr[sl + 1] - base) >> 6);
+    const int e0 = rp[i], len = rp[i + 1] - e0;
+    for (int j = 0; j < w; ++j) {
+      const long long e = base + (long long)j * 64 + lane;
+      scol[e] = j < len ? col[e0 + j] : i;
+      sval[e] = j < len ? val[e0 + j] : 0.0;
+    }
+  }
 }
 
 // CG step t, update part: alpha = rz_t / p.q (p.q from this step's direction
@@ -270,13 +333,22 @@ void launch_spmv(hipStream_t s, int n, const int *rp, const int *col, const doub
                      partial, done);
 }
 
-void launch_cg_dir(hipStream_t s, int n, const int *rp, const int *col, const double *val,
-                   const double *z, const double *pold, double *pnew, double *q, double *part_pq,
-                   PcgState *st, const double *part_rr, const double *part_rz,
+void launch_cg_dir(hipStream_t s, int n, const long long *sptr, const int *scol,
+                   const double *sval, const double *z, const double *pold, double *pnew, double *q,
+                   double *part_pq, PcgState *st, const double *part_rr, const double *part_rz,
                    const double *part_rzo, int t, int first, int flexible) {
   const int nb = reduce_blocks(n);
-  hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(WG), 0, s, n, rp, col, val, z, pold, pnew, q, part_pq,
-                     st, part_rr, part_rz, part_rzo, nb, t, first, flexible);
+  hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(WG), 0, s, n, sptr, scol, sval, z, pold, pnew, q,
+                     part_pq, st, part_rr, part_rz, part_rzo, nb, t, first, flexible);
+}
+
+void launch_csr_to_sell(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                        const long long *sptr, int *scol, double *sval) {
+  size_t b = ((size_t)n + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_csr_to_sell, dim3((unsigned)b), dim3(WG), 0, s, n, rp, col, val, sptr, scol,
+                     sval);
 }
 
 void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *p, const double *q,
