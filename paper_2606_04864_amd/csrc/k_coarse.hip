@@ -144,10 +144,14 @@ __global__ void __launch_bounds__(WG) k_dense_syrk_update(double *A0t, int T0, i
     jj = b - ii * (ii + 1) / 2;
   }
   const int i = j0 + ii, j = j0 + jj;
+  // every wavefront multiplies by the whole L_jk: stage it once in LDS
+  __shared__ double Ly[TS * LDT];
+  tile_to_lds(tile_ptr(A0t, T0, j, k), Ly);
   double *c = tile_ptr(A0t, T0, i, j);
   Acc4 o;
   acc_load(o, c);
-  acc_mma_abt(o, tile_ptr(A0t, T0, i, k), TS, tile_ptr(A0t, T0, j, k), TS, -1.0);
+  __syncthreads();
+  acc_mma_abt(o, tile_ptr(A0t, T0, i, k), TS, Ly, LDT, -1.0);
   acc_store(o, c);
 }
 
@@ -171,10 +175,14 @@ __global__ void __launch_bounds__(WG) k_dense_inv_update(const double *Lt, doubl
                                                          int k) {
   const int i = k + 1 + blockIdx.x / (k + 1);
   const int j = blockIdx.x % (k + 1);
+  // every wavefront multiplies by the whole X_kj: stage it once in LDS
+  __shared__ double Xk[TS * LDT];
+  tile_to_lds(Wt + ((size_t)k * T0 + j) * TE, Xk);
   double *c = tile_ptr(Wt, T0, i, j);
   Acc4 o;
   acc_load(o, c);
-  acc_mma_ab(o, Lt + ((size_t)i * T0 + k) * TE, TS, Wt + ((size_t)k * T0 + j) * TE, TS, -1.0);
+  __syncthreads();
+  acc_mma_ab(o, Lt + ((size_t)i * T0 + k) * TE, TS, Xk, LDT, -1.0);
   acc_store(o, c);
 }
 
