@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 
 #include <cfloat>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -88,8 +89,9 @@ struct amsp_handle {
   double *fac64 = nullptr;  // tile pool of the local factors (setup only)
   // the apply's local factors: packed inverse diagonal tiles and the envelope
   // (row and column forms), in the apply's precision
-  double *dg64 = nullptr, *erow64 = nullptr, *ecol64 = nullptr;
-  float *dg32 = nullptr, *erow32 = nullptr, *ecol32 = nullptr;
+  double *dg64 = nullptr, *erow64 = nullptr, *ecol64 = nullptr;  // FP64 form
+  float *fst32 = nullptr, *bst32 = nullptr;  // mixed forms: per-sweep streams
+  long long nst_f = 0, nst_b = 0;            // stream lengths (entries)
   double *phi64 = nullptr;
   void *phi_lo = nullptr;  // float or bf16 copy used by the mixed apply
   void *phi_nat = nullptr; // the apply's basis in ascending-index layout (scatter)
@@ -426,6 +428,38 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   p.eptr = upload(h, P.eptr, ok);
   p.uptr = upload(h, P.uptr, ok);
   p.ebase = upload(h, P.ebase, ok);
+  {
+    // per-sweep streams of the mixed form's factor: start of every 64-row
+    // block inside its region's stream, and of every region's stream
+    const int ntr = P.trow_ptr.back();
+    std::vector<int> sfb(ntr), sbb(ntr);
+    std::vector<long long> sfr(h->N + 1, 0), sbr(h->N + 1, 0);
+    for (int i = 0; i < h->N; ++i) {
+      const int g0 = P.trow_ptr[i], nt = P.trow_ptr[i + 1] - g0;
+      const int *ep = P.eptr.data() + P.vp_ptr[i] + i, *up = P.uptr.data() + P.vp_ptr[i] + i;
+      long long of = 0, ob = 0;
+      for (int I = 0; I < nt; ++I) {
+        sfb[g0 + I] = (int)of;
+        of += ((ep[I * TS + TS] - ep[I * TS] + 3) & ~3) + DE;
+      }
+      for (int J = nt - 1; J >= 0; --J) {
+        sbb[g0 + J] = (int)ob;
+        ob += ((up[J * TS + TS] - up[J * TS] + 3) & ~3) + DE;
+      }
+      if (of > INT_MAX || ob > INT_MAX) {
+        h->err = "region " + std::to_string(i) + " too large for the local apply's stream";
+        return AMSP_ERR_ARG;
+      }
+      sfr[i + 1] = sfr[i] + of;
+      sbr[i + 1] = sbr[i] + ob;
+    }
+    p.sfb = upload(h, sfb, ok);
+    p.sbb = upload(h, sbb, ok);
+    p.sfr = upload(h, sfr, ok);
+    p.sbr = upload(h, sbr, ok);
+    h->nst_f = sfr[h->N];
+    h->nst_b = sbr[h->N];
+  }
   p.loc_rowptr = upload(h, P.loc_rowptr, ok);
   p.loc_col = upload(h, P.loc_col, ok);
   p.loc_src = upload(h, P.loc_src, ok);
@@ -684,11 +718,9 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     const size_t ndiag = (size_t)h->ntilerows * DE, nenv = (size_t)P.nenv;
     const double *dsrc = h->fac64 + (size_t)P.noff * TE;
     if (mixed) {
-      ALLOC(h->dg32, float, ndiag);
-      ALLOC(h->erow32, float, nenv);
-      ALLOC(h->ecol32, float, nenv);
-      launch_tiles_to_f32(h->stream, dsrc, h->dg32, ndiag);
-      launch_env_from_tiles<float>(h->stream, p, h->ntilerows, h->fac64, h->erow32, h->ecol32);
+      ALLOC(h->fst32, float, (size_t)h->nst_f + STREAM_TAIL);
+      ALLOC(h->bst32, float, (size_t)h->nst_b + STREAM_TAIL);
+      launch_stream_from_tiles(h->stream, p, h->ntilerows, h->fac64, h->fst32, h->bst32);
     } else {
       ALLOC(h->dg64, double, ndiag);
       ALLOC(h->erow64, double, nenv);
@@ -833,7 +865,8 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
   }
   // the local apply keeps a region's vector and envelope segment starts in
   // LDS (160 KB per workgroup, less the kernel's 512 B of static LDS)
-  if (local_apply_lds_bytes(h->hp.max_npad, o.precision == AMSP_FP64 ? 8 : 4) >
+  if ((o.precision == AMSP_FP64 ? local_apply_lds_bytes(h->hp.max_npad, 8)
+                                 : local_apply_stream_lds_bytes(h->hp.max_npad)) >
       160 * 1024 - 512) {
     g_setup_error = "largest region (" + std::to_string(h->hp.max_npad) +
                     " padded rows) exceeds the local apply's LDS capacity";
@@ -879,13 +912,14 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
                                                  h->erow64, h->ecol64, h->phi64, h->xloc, h->cvec,
                                                  do_local, do_coarse, done, e0, e1);
   } else if (!bf) {
-    launch_local_apply_t<float, float, float>(h->stream, p, h->hp.max_npad, r, h->dg32,
-                                              h->erow32, h->ecol32, (const float *)h->phi_lo,
-                                              h->xloc, h->cvec, do_local, do_coarse, done, e0, e1);
+    launch_local_apply_stream<float>(h->stream, p, h->hp.max_npad, r, h->fst32, h->bst32,
+                                     (const float *)h->phi_lo, h->xloc, h->cvec, do_local,
+                                     do_coarse, done, e0, e1);
   } else {
-    launch_local_apply_t<float, float, __hip_bfloat16>(
-        h->stream, p, h->hp.max_npad, r, h->dg32, h->erow32, h->ecol32,
-        (const __hip_bfloat16 *)h->phi_lo, h->xloc, h->cvec, do_local, do_coarse, done, e0, e1);
+    launch_local_apply_stream<__hip_bfloat16>(h->stream, p, h->hp.max_npad, r, h->fst32,
+                                              h->bst32, (const __hip_bfloat16 *)h->phi_lo,
+                                              h->xloc, h->cvec, do_local, do_coarse, done, e0,
+                                              e1);
   }
   tpair_done(h, 1, tk);
   if (do_coarse) {
@@ -954,7 +988,10 @@ static int64_t local_apply_bytes(const amsp_handle *h) {
   const int64_t sni = P.sd_ptr.back(), snp = P.vp_ptr.back();
   const int64_t fb = mixed ? 4 : 8;
   const int64_t pb = mixed ? (h->opt.precision == AMSP_MIXED_BF16 ? 2 : 4) : 8;
-  int64_t b = sni * (8 + 4) + sni * 8 + 2 * (snp + h->N) * 4 + 2 * apply_factor_elems(P) * fb;
+  // the mixed forms stream the factor (diagonal tiles, envelope and block
+  // padding) once per sweep; the FP64 form reads diagonal tiles and envelope
+  const int64_t fac = mixed ? (int64_t)(h->nst_f + h->nst_b) * fb : 2 * apply_factor_elems(P) * fb;
+  int64_t b = sni * (8 + 4) + sni * 8 + 2 * (snp + h->N) * 4 + fac;
   if (h->nc > 0) b += sni * h->nev * pb + (int64_t)h->nc * 8;
   return b;
 }
@@ -969,7 +1006,8 @@ static int64_t bytes_per_iter(const amsp_handle *h) {
   b += nnz * 12 + (n + 1) * 4 + n * 8 * 4;          // spmv with the fused p update
   b += n * 8 * 6;                                   // x, r update
   b += sni * (8 + 4) + sni * 8 + 2 * (snp + h->N) * 4;  // local gather, write, segments
-  b += 2 * apply_factor_elems(P) * fb;                 // forward + backward factor sweep
+  b += mixed ? (int64_t)(h->nst_f + h->nst_b) * fb      // forward + backward factor sweep
+             : 2 * apply_factor_elems(P) * fb;
   if (h->nc > 0) {
     b += sni * h->nev * pb * 2;                     // restrict + prolong basis reads
     b += 2 * (int64_t)h->T0 * (h->T0 + 1) / 2 * TE * (mixed ? 4 : 8);  // coarse W0 twice

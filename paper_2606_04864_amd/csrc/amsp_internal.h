@@ -28,6 +28,9 @@ struct Plan {
   const int *eptr;          // [sum npad_i + N] envelope of the factor below the diagonal
   const int *uptr;          //   tiles, per region npad_i + 1 segment starts relative to
   const long long *ebase;   //   ebase[i]: row form (eptr) and column form (uptr)
+  const int *sfb, *sbb;     // [sum nt_i] start of each 64-row block in its region's forward
+  const long long *sfr;     //   / backward stream; [N+1] region starts of the forward
+  const long long *sbr;     //   / backward streams (see launch_local_apply_stream)
   const int *loc_rowptr;    // [sum n_i + 1] local CSR of A_i (rows in local order)
   const int *loc_col;       //   local column index
   const int *loc_src;       //   index of the value in the global CSR
@@ -94,6 +97,22 @@ void launch_env_from_tiles(hipStream_t s, const Plan &p, int ntilerows, const do
 // Dynamic LDS of the local apply for regions of up to max_npad padded rows
 // and compute type of csize bytes.
 size_t local_apply_lds_bytes(int max_npad, size_t csize);
+// Per-sweep streams of an f32 factor: for every region, its 64-row blocks in
+// sweep order (forward: ascending, envelope row form; backward: descending,
+// column form), each block's envelope segments zero-padded to a multiple of
+// 4 entries and followed by the block's packed inverse diagonal tile.  The
+// arrays carry STREAM_TAIL extra entries (read, never used).
+constexpr int STREAM_TAIL = 4 * WG;
+void launch_stream_from_tiles(hipStream_t s, const Plan &p, int ntilerows, const double *tiles,
+                              float *fst, float *bst);
+size_t local_apply_stream_lds_bytes(int max_npad);
+// The mixed-form local apply on the streams (same operation as
+// launch_local_apply_t with float factors).
+template <typename TB>
+void launch_local_apply_stream(hipStream_t s, const Plan &p, int max_npad, const double *r,
+                               const float *fst, const float *bst, const TB *phi, double *xloc,
+                               double *cvec, int do_local, int do_coarse, const int *done,
+                               hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // Local apply: gather r, coarse restriction into c (do_coarse), envelope
 // forward/backward solve into xloc (do_local).  diag: the packed inverse
 // diagonal tiles (DE entries per tile row), erow/ecol: the envelope.

@@ -274,6 +274,223 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
   for (int l = threadIdx.x; l < ni; l += WG) dst[p.nat[r0 + l]] = (double)v[l];
 }
 
+// ------------------------------------ local solves on the f32 streams -----
+// The mixed-form local apply reads each sweep's data as one contiguous
+// stream per region (envelope segments then packed diagonal tile, block by
+// block in sweep order).  The workgroup loads it in 4 KB units (16 bytes per
+// thread, every byte used), NS units in flight per thread, and each arriving
+// unit is copied into an LDS ring of RU units; the row and column products
+// read the ring.  Envelope entries are used as soon as their unit has
+// arrived; a block's diagonal step runs once its whole tile is in the ring.
+// The ring is large enough that a unit is overwritten only after every read
+// of it has finished.  Reads during unit step u touch envelope entries of
+// units >= u and at most the diagonal tile of a block ending after unit
+// u - 1, which starts no earlier than unit u - 3 (DE = 2.125 units).  A
+// thread still reading step u can meet another thread writing step u + 1 (one
+// barrier apart), and that write replaces unit u + 1 - RU = u - 5.
+namespace stream {
+typedef float f4 __attribute__((ext_vector_type(4)));  // one thread's 16 bytes of a unit
+constexpr int UE = 4 * WG;   // floats per unit
+constexpr int RU = 6;        // units in the LDS ring
+constexpr int RSZ = RU * UE;
+constexpr int NS = 4;        // units in flight per thread
+}  // namespace stream
+
+size_t local_apply_stream_lds_bytes(int max_npad) {
+  // v (npad) + tmp (64) + ring + one form's segment starts (npad + 1)
+  return (size_t)(max_npad + TS + stream::RSZ) * sizeof(float) + (size_t)(max_npad + 1) * sizeof(int);
+}
+
+// One sweep.  FWD: blocks I = 0 .. nt-1, row form, y_I = inv(L_II)(b_I - env);
+// otherwise blocks nt-1 .. 0, column form, x_I = inv(L_II)^T (y_I - env).
+// es: the form's segment starts of this region in LDS; boff: block starts.
+template <bool FWD>
+__device__ __forceinline__ void stream_sweep(int nt, const int *es, const int *__restrict__ boff,
+                                             const float *__restrict__ S, int L,
+                                             const float *__restrict__ tail, float *v, float *tmp,
+                                             float *ring) {
+  using namespace stream;
+  const int t = threadIdx.x, rr = t >> 2, q = t & 3;
+  const int nunits = (L + UE - 1) / UE;
+  // Every step loads and stores unconditionally (units past the stream read
+  // the shared tail), so that the compiler can count the loads in flight and
+  // wait for the oldest one only.
+  const long long tail_off = tail - S;  // one offset select, one load per unit
+  auto unit_src = [&](int u) {
+    const long long off = u < nunits ? (long long)u * UE : tail_off;
+    return reinterpret_cast<const f4 *>(S + off) + t;
+  };
+  f4 f[NS];
+  // issue in slot order (the loop below waits for slot sl with the NS - 1
+  // younger loads still in flight; the scheduler must not reorder these)
+  static_for<0, NS>([&](auto slc) __attribute__((always_inline)) {
+    f[decltype(slc)::value] = *unit_src(decltype(slc)::value);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  // current block: index b in sweep order, its tile row I, stream start bs,
+  // envelope size T and this thread's segment [bs + e0, bs + e0 + len)
+  int b = 0, I = FWD ? 0 : nt - 1;
+  int bs = boff[I], T = es[I * TS + TS] - es[I * TS];
+  int e0 = es[I * TS + rr] - es[I * TS], len = es[I * TS + rr + 1] - es[I * TS + rr];
+  int cons = bs;  // stream position up to which this block's envelope has been used
+  float acc = 0.f;
+  bool fin = nt == 0;
+  for (int k0 = 0; k0 < nunits; k0 += NS) {
+    // slots are unrolled at compile time (f[] must not be indexed at run time)
+    static_for<0, NS>([&](auto slc) __attribute__((always_inline)) {
+      constexpr int sl = decltype(slc)::value;
+      const int u = k0 + sl;
+      {
+        reinterpret_cast<f4 *>(ring + (u % RU) * UE)[t] = f[sl];
+        f[sl] = *unit_src(u + NS);
+        __syncthreads();  // unit u in the ring
+        const int avail = min(L, (u + 1) * UE);
+        while (!fin) {
+          const int dI = bs + ((T + 3) & ~3), eI = dI + DE;
+          const int hi = min(avail, dI);
+          if (hi > cons) {  // envelope entries that arrived: [cons, hi)
+            const int s0 = bs + e0;
+            const int kl = max(cons - s0, 0), kh = min(hi - s0, len);
+            const int v0 = FWD ? I * TS - len : I * TS + TS;
+            int k = kl + ((q - kl) & 3);
+            int ri = (s0 + k) % RSZ;  // ring index of entry k, advanced with a wrap
+            for (; k < kh; k += 4) {
+              acc = fmaf(-ring[ri], v[v0 + k], acc);
+              ri += 4;
+              ri = ri >= RSZ ? ri - RSZ : ri;
+            }
+            cons = hi;
+          }
+          if (avail < eI) break;
+          // diagonal step of block I
+          acc += __shfl_xor(acc, 1, 64);
+          acc += __shfl_xor(acc, 2, 64);
+          if (q == 0) tmp[rr] = v[I * TS + rr] + acc;
+          __syncthreads();  // tmp complete
+          const int dr = dI % RSZ;  // ring index of the diagonal tile
+          if (FWD) {
+            // y[rr] = sum_c inv(L_II)[rr][c] tmp[c]: row rr, columns 16q .. 16q+15
+            int ri = dr + dpos_row(rr) + 16 * q;
+            ri = ri >= RSZ ? ri - RSZ : ri;
+            float y = 0.f;
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) {
+              const int rc = ri + 4 * c4 >= RSZ ? ri + 4 * c4 - RSZ : ri + 4 * c4;
+              if (16 * q + 4 * c4 <= rr) {
+                const f4 a = *reinterpret_cast<const f4 *>(ring + rc);
+                const float *tt = tmp + 16 * q + 4 * c4;
+                y = fmaf(a[0], tt[0], y);
+                y = fmaf(a[1], tt[1], y);
+                y = fmaf(a[2], tt[2], y);
+                y = fmaf(a[3], tt[3], y);
+              }
+            }
+            y += __shfl_xor(y, 1, 64);
+            y += __shfl_xor(y, 2, 64);
+            if (q == 0) v[I * TS + rr] = y;
+          } else {
+            // x[col] = sum_r inv(L_II)[r][col] tmp[r]: column 16w + (l & 15),
+            // rows 16 (l >> 4) .. +15
+            const int l = t & 63, w = t >> 6;
+            const int col = 16 * w + (l & 15), rw0 = 16 * (l >> 4);
+            int ri = dr + dpos_row(rw0) + col;  // entry (rw0, col); rows step by
+            ri = ri >= RSZ ? ri - RSZ : ri;     // their padded lengths
+            float x = 0.f;
+#pragma unroll
+            for (int rq = 0; rq < 16; ++rq) {
+              const int row = rw0 + rq;
+              if (col <= row) x = fmaf(ring[ri], tmp[row], x);
+              ri += 4 * ((row >> 2) + 1);
+              ri = ri >= RSZ ? ri - RSZ : ri;
+            }
+            x += __shfl_xor(x, 16, 64);
+            x += __shfl_xor(x, 32, 64);
+            if ((l >> 4) == 0) v[I * TS + col] = x;
+          }
+          __syncthreads();  // block I final in v; tmp free
+          acc = 0.f;
+          if (++b == nt) {
+            fin = true;
+            break;
+          }
+          I = FWD ? b : nt - 1 - b;
+          bs = eI;
+          T = es[I * TS + TS] - es[I * TS];
+          e0 = es[I * TS + rr] - es[I * TS];
+          len = es[I * TS + rr + 1] - es[I * TS + rr];
+          cons = bs;
+        }
+      }
+    });
+  }
+}
+
+template <typename TB>
+__global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double *__restrict__ r,
+                                                           const float *__restrict__ fst,
+                                                           const float *__restrict__ bst,
+                                                           const TB *__restrict__ phi,
+                                                           double *__restrict__ xloc,
+                                                           double *__restrict__ cvec, int do_local,
+                                                           int do_coarse,
+                                                           const int *__restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ char smem_raw[];
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
+  const int npad = nt * TS;
+  float *v = reinterpret_cast<float *>(smem_raw);  // whole local vector (padded)
+  float *tmp = v + npad;                             // 64
+  float *ring = tmp + TS;                            // stream::RSZ
+  int *es = reinterpret_cast<int *>(ring + stream::RSZ);  // npad + 1 segment starts
+  __shared__ double red[MAXNEV + 1][WG / 64];
+  const int nev = p.nev;
+  const int m = p.mi[i];
+  double cacc[MAXNEV];
+#pragma unroll
+  for (int k = 0; k < MAXNEV; ++k) cacc[k] = 0.0;
+  for (int l = threadIdx.x; l < npad; l += WG) {
+    double rv = 0.0;
+    if (l < ni) {
+      rv = r[p.sd_dofs[r0 + l]];
+      if (do_coarse) {
+        const TB *ph = phi + (size_t)(r0 + l) * nev;
+#pragma unroll
+        for (int k = 0; k < MAXNEV; ++k)
+          if (k < m) cacc[k] = fma(to_d(ph[k]), rv, cacc[k]);
+      }
+    }
+    v[l] = (float)rv;
+  }
+  const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
+  if (do_local)
+    for (int l = threadIdx.x; l <= npad; l += WG) es[l] = ep[l];
+  if (do_coarse) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = 0; k < m; ++k) {
+      double s = wave_sum(cacc[k]);
+      if (lane == 0) red[k][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+      double s = 0.0;
+      for (int ww = 0; ww < WG / 64; ++ww) s += red[threadIdx.x][ww];
+      cvec[p.coff[i] + threadIdx.x] = s;
+    }
+  }
+  __syncthreads();
+  if (!do_local) return;
+  const int Lf = (int)(p.sfr[i + 1] - p.sfr[i]), Lb = (int)(p.sbr[i + 1] - p.sbr[i]);
+  stream_sweep<true>(nt, es, p.sfb + g0, fst + p.sfr[i], Lf, fst + p.sfr[p.N], v, tmp, ring);
+  for (int l = threadIdx.x; l <= npad; l += WG) es[l] = up[l];
+  __syncthreads();
+  stream_sweep<false>(nt, es, p.sbb + g0, bst + p.sbr[i], Lb, bst + p.sbr[p.N], v, tmp, ring);
+  // local correction in the region's ascending-global-index layout
+  double *dst = xloc + p.vp_ptr[i];
+  for (int l = threadIdx.x; l < ni; l += WG) dst[p.nat[r0 + l]] = (double)v[l];
+}
+
 // ------------------------------------------------------------- launchers ---
 template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
@@ -296,8 +513,30 @@ void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const doub
                                                double *, double *, int, int, const int *,      \
                                                hipEvent_t, hipEvent_t);
 AMSP_LOCAL_APPLY_INST(double, double, double)
-AMSP_LOCAL_APPLY_INST(float, float, float)
-AMSP_LOCAL_APPLY_INST(float, float, __hip_bfloat16)
 #undef AMSP_LOCAL_APPLY_INST
+
+template <typename TB>
+void launch_local_apply_stream(hipStream_t s, const Plan &p, int max_npad, const double *r,
+                               const float *fst, const float *bst, const TB *phi, double *xloc,
+                               double *cvec, int do_local, int do_coarse, const int *done,
+                               hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const size_t sm = local_apply_stream_lds_bytes(max_npad);
+  allow_lds(k_local_apply_stream<TB>, sm);
+  if (ev_start || ev_stop)  // events bound to this dispatch: exact kernel duration
+    hipExtLaunchKernelGGL((k_local_apply_stream<TB>), dim3(p.N), dim3(WG), sm, s, ev_start,
+                          ev_stop, 0, p, r, fst, bst, phi, xloc, cvec, do_local, do_coarse, done);
+  else
+    hipLaunchKernelGGL((k_local_apply_stream<TB>), dim3(p.N), dim3(WG), sm, s, p, r, fst, bst, phi,
+                       xloc, cvec, do_local, do_coarse, done);
+}
+template void launch_local_apply_stream<float>(hipStream_t, const Plan &, int, const double *,
+                                               const float *, const float *, const float *,
+                                               double *, double *, int, int, const int *,
+                                               hipEvent_t, hipEvent_t);
+template void launch_local_apply_stream<__hip_bfloat16>(hipStream_t, const Plan &, int,
+                                                        const double *, const float *,
+                                                        const float *, const __hip_bfloat16 *,
+                                                        double *, double *, int, int, const int *,
+                                                        hipEvent_t, hipEvent_t);
 
 }  // namespace amsp

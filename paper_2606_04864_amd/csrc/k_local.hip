@@ -192,6 +192,58 @@ __global__ void __launch_bounds__(WG) k_env_from_tiles(Plan p, const double *__r
   }
 }
 
+// Per-sweep streams of the f32 factor (layout in amsp_internal.h), one
+// workgroup per tile row g: the forward block of g (row-form segments,
+// padding, diagonal) and its backward block (column-form segments, padding,
+// diagonal).
+__global__ void __launch_bounds__(WG) k_stream_from_tiles(Plan p, const double *__restrict__ tiles,
+                                                          float *__restrict__ fst,
+                                                          float *__restrict__ bst) {
+  const int g = blockIdx.x;
+  const int i = find_segment(p.trow_ptr, p.N, g);
+  const int g0 = p.trow_ptr[i], I = g - g0;
+  const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
+  const int r0 = I * TS;
+  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+  const int l = r0 + r;
+  const double *dg = tiles + diag_elem(p, g);
+  // forward block
+  {
+    float *blk = fst + p.sfr[i] + p.sfb[g];
+    const int base = ep[r0], T = ep[r0 + TS] - base, Tp = (T + 3) & ~3;
+    const int e0 = ep[l] - base, len = ep[l + 1] - ep[l], c0 = r0 - len;
+    const int fI = p.tfirst[g];
+    for (int k = q; k < len; k += 4) {
+      const int c = c0 + k, J = c / TS;
+      const double v =
+          J >= fI ? tiles[tile_elem(p.toff[g] + (J - fI)) + r * TS + (c - J * TS)] : 0.0;
+      blk[e0 + k] = (float)v;
+    }
+    if ((int)threadIdx.x < Tp - T) blk[T + threadIdx.x] = 0.f;
+    for (int e = threadIdx.x; e < DE; e += WG) blk[Tp + e] = (float)dg[e];
+  }
+  // backward block
+  {
+    float *blk = bst + p.sbr[i] + p.sbb[g];
+    const int base = up[r0], T = up[r0 + TS] - base, Tp = (T + 3) & ~3;
+    const int e0 = up[l] - base, len = up[l + 1] - up[l], r1 = r0 + TS;
+    for (int k = q; k < len; k += 4) {
+      const int rw = r1 + k, Ir = rw / TS, gr = g0 + Ir;
+      const int fr = p.tfirst[gr];
+      const double v =
+          I >= fr ? tiles[tile_elem(p.toff[gr] + (I - fr)) + (rw - Ir * TS) * TS + r] : 0.0;
+      blk[e0 + k] = (float)v;
+    }
+    if ((int)threadIdx.x < Tp - T) blk[T + threadIdx.x] = 0.f;
+    for (int e = threadIdx.x; e < DE; e += WG) blk[Tp + e] = (float)dg[e];
+  }
+}
+
+void launch_stream_from_tiles(hipStream_t s, const Plan &p, int ntilerows, const double *tiles,
+                              float *fst, float *bst) {
+  hipLaunchKernelGGL(k_stream_from_tiles, dim3(ntilerows), dim3(WG), 0, s, p, tiles, fst, bst);
+}
+
 // Device self-test of the MFMA operand/result layout the kernels rely on: D = A B
 // for A (16x4) and B (4x16) given row-major, D written row-major (16x16).
 __global__ void k_selftest_mfma(const double *A, const double *B, double *D) {
