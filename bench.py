@@ -55,6 +55,7 @@ def run_form(P, torch, w, f, prec, steps, warmup, timing):
                             input_upload_ms=si["phase_ms"][1], plan_ms=si["phase_ms"][0],
                             phase_ms=si["phase_ms"], eig_sweeps=si["eig_sweeps"],
                             coupling_ms=si["coupling_ms"], coupling_wait_ms=si["coupling_wait_ms"],
+                            plan_host_ms=si["plan_host_ms"], plan_upload_ms=si["plan_upload_ms"],
                             iterations=info["iterations"], relres_true=info["relres_true"],
                             kernel_ms=info["kernel_ms"], kernel_launches=info["kernel_launches"],
                             local_apply_bytes=info["local_apply_bytes"],
@@ -217,6 +218,7 @@ def main():
                     eig_sweeps=int(rec[-1]["eig_sweeps"]),
                     setup_phase_ms=[round(x, 3) for x in rec[-1]["phase_ms"]],
                     coupling_plan_ms=med("coupling_ms"), coupling_wait_ms=med("coupling_wait_ms"),
+                    plan_host_ms=med("plan_host_ms"), plan_upload_ms=med("plan_upload_ms"),
                     pcg_gbs=float(rec[-1]["bytes_per_iter"] * rec[-1]["iterations"]
                                   / (np.median([r["pcg_ms"] for r in rec]) * 1e-3) / 1e9))
 

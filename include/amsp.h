@@ -136,6 +136,8 @@ typedef struct {
                             /* chol, eig, basis+A0, coarse chol+inverse, total      */
   double coupling_ms;       /* host coupling-plan thread (overlaps device work)     */
   double coupling_wait_ms;  /* time the device path waited for it                   */
+  double plan_host_ms;      /* part of phase_ms[0]: the host planning itself        */
+  double plan_upload_ms;    /* part of phase_ms[0]: device copies of the plan       */
 } amsp_setup_info;
 
 typedef struct amsp_handle amsp_handle;

@@ -81,7 +81,8 @@ class _SetupInfo(ctypes.Structure):
                 ("eig_sweeps", ctypes.c_int32), ("eig_unconverged", ctypes.c_int32),
                 ("n_gap_flags", ctypes.c_int32), ("mu_c", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 8), ("coupling_ms", ctypes.c_double),
-                ("coupling_wait_ms", ctypes.c_double)]
+                ("coupling_wait_ms", ctypes.c_double), ("plan_host_ms", ctypes.c_double),
+                ("plan_upload_ms", ctypes.c_double)]
 
 
 _vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double

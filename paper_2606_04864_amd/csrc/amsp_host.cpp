@@ -479,6 +479,8 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   double t1 = now_ms();
   h->sinfo.phase_ms[1] = tb - ta;                   // input matrix transfer only
   h->sinfo.phase_ms[0] += (ta - t0) + (t1 - tb);  // planning includes its index uploads
+  h->sinfo.plan_host_ms = host_plan_ms;
+  h->sinfo.plan_upload_ms = (ta - t0) + (t1 - tb);
 
   int *status;
   ALLOC(status, int, h->N);

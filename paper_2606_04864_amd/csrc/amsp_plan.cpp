@@ -13,9 +13,12 @@
 //     supports couple through A, used to form A0 = R0 A R0^T.
 #include "amsp_plan.h"
 
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <condition_variable>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -23,6 +26,8 @@
 #include <mutex>
 #include <new>
 #include <thread>
+
+#include <unistd.h>
 #include <unordered_map>
 
 namespace amsp {
@@ -30,15 +35,38 @@ namespace amsp {
 namespace {
 constexpr size_t kCacheMin = size_t(1) << 20;
 constexpr size_t kCacheCap = size_t(4) << 30;
+// Blocks of the cache are page-locked when a device is present, so that the
+// plan's uploads are direct transfers; without a device (host-only
+// planning) they are ordinary memory.
+struct Block {
+  size_t size;
+  bool pinned;
+};
 struct BlockCache {
   std::mutex mu;
-  std::multimap<size_t, void *> free_blocks;   // block size -> block
-  std::unordered_map<void *, size_t> live;     // block -> block size
+  std::multimap<size_t, std::pair<void *, bool>> free_blocks;  // size -> (block, pinned)
+  std::unordered_map<void *, Block> live;
   size_t held = 0;
 };
 BlockCache &block_cache() {
   static BlockCache *c = new BlockCache();  // never destroyed: blocks may be freed at exit
   return *c;
+}
+void *block_new(size_t bytes, bool &pinned) {
+  void *p = nullptr;
+  if (hipHostMalloc(&p, bytes, hipHostMallocPortable) == hipSuccess && p) {
+    pinned = true;
+    return p;
+  }
+  (void)hipGetLastError();  // clear the failed call's error
+  pinned = false;
+  return ::operator new(bytes);
+}
+void block_delete(void *p, bool pinned) {
+  if (pinned)
+    (void)hipHostFree(p);
+  else
+    ::operator delete(p);
 }
 }  // namespace
 
@@ -50,16 +78,17 @@ void *plan_alloc(size_t bytes) {
     std::lock_guard<std::mutex> lk(c.mu);
     auto it = c.free_blocks.lower_bound(want);
     if (it != c.free_blocks.end() && it->first <= 2 * want) {
-      void *p = it->second;
-      c.live[p] = it->first;
+      void *p = it->second.first;
+      c.live[p] = Block{it->first, it->second.second};
       c.held -= it->first;
       c.free_blocks.erase(it);
       return p;
     }
   }
-  void *p = ::operator new(want);
+  bool pinned;
+  void *p = block_new(want, pinned);
   std::lock_guard<std::mutex> lk(c.mu);
-  c.live[p] = want;
+  c.live[p] = Block{want, pinned};
   return p;
 }
 
@@ -72,25 +101,106 @@ void plan_free(void *p, size_t bytes) {
   BlockCache &c = block_cache();
   std::lock_guard<std::mutex> lk(c.mu);
   auto it = c.live.find(p);
-  const size_t sz = it->second;
+  const Block blk = it->second;
   c.live.erase(it);
-  if (c.held + sz <= kCacheCap) {
-    c.free_blocks.emplace(sz, p);
-    c.held += sz;
+  if (c.held + blk.size <= kCacheCap) {
+    c.free_blocks.emplace(blk.size, std::make_pair(p, blk.pinned));
+    c.held += blk.size;
   } else {
-    ::operator delete(p);
+    block_delete(p, blk.pinned);
   }
 }
 
-// Run fn(i) for i in [0, count) on up to `threads` workers (dynamic schedule).
+namespace {
+// Persistent workers for the planner's parallel loops: starting and joining
+// fresh threads costs ~0.5 ms per loop, and planning runs a few dozen loops.
+// One loop runs on the pool at a time; a caller that finds it busy (the
+// coupling thread and the main thread may plan concurrently) starts its own
+// threads.  After a fork the child builds a new pool (the parent's workers
+// do not exist there).
+class PlanPool {
+ public:
+  static PlanPool *get(int nworkers) {
+    static std::mutex m;
+    static PlanPool *pool = nullptr;
+    std::lock_guard<std::mutex> lk(m);
+    if (!pool || pool->pid_ != getpid()) pool = new PlanPool(nworkers);  // never freed
+    return pool;
+  }
+  // fn(i) for i in [0, n) on the caller and up to nth - 1 workers; false
+  // when another loop occupies the pool
+  template <typename F>
+  bool run(int n, int nth, F &fn) {
+    std::unique_lock<std::mutex> busy(busy_, std::try_to_lock);
+    if (!busy.owns_lock()) return false;
+    const int want = std::min(nth - 1, nworkers_);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      call_ = [](void *c, int i) { (*static_cast<F *>(c))(i); };
+      ctx_ = &fn;
+      count_ = n;
+      want_ = want;
+      finished_ = 0;
+      next_.store(0);
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (;;) {
+      const int i = next_.fetch_add(1);
+      if (i >= n) break;
+      fn(i);
+    }
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_done_.wait(lk, [&] { return finished_ == want_; });
+    return true;
+  }
+
+ private:
+  explicit PlanPool(int nworkers) : nworkers_(nworkers), pid_(getpid()) {
+    for (int w = 0; w < nworkers; ++w) std::thread([this, w] { loop(w); }).detach();
+  }
+  void loop(int w) {
+    unsigned long long seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return gen_ != seen; });
+      seen = gen_;
+      if (w >= want_) continue;  // not asked to join this loop
+      void (*call)(void *, int) = call_;
+      void *ctx = ctx_;
+      const int n = count_;
+      lk.unlock();
+      for (;;) {
+        const int i = next_.fetch_add(1);
+        if (i >= n) break;
+        call(ctx, i);
+      }
+      lk.lock();
+      if (++finished_ == want_) cv_done_.notify_one();
+    }
+  }
+  const int nworkers_;
+  const pid_t pid_;
+  std::mutex busy_, mu_;
+  std::condition_variable cv_, cv_done_;
+  unsigned long long gen_ = 0;
+  void (*call_)(void *, int) = nullptr;
+  void *ctx_ = nullptr;
+  int count_ = 0, want_ = 0, finished_ = 0;
+  std::atomic<int> next_{0};
+};
+}  // namespace
+
+// Run fn(i) for i in [0, count) on up to 16 threads (dynamic schedule).
 template <typename F>
 static void parallel_for(int count, F fn) {
   unsigned hw = std::thread::hardware_concurrency();
 #ifdef AMSP_PLAN_SERIAL
   hw = 1;
 #endif
-  int nth = (int)std::min<unsigned>(hw ? hw : 1, 16);
-  nth = std::max(1, std::min(nth, count));
+  const int maxth = (int)std::min<unsigned>(hw ? hw : 1, 16);
+  const int nth = std::max(1, std::min(maxth, count));
+  if (nth > 1 && PlanPool::get(maxth - 1)->run(count, nth, fn)) return;
   std::atomic<int> next(0);
   auto work = [&]() {
     for (;;) {
