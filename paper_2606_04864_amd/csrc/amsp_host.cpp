@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -26,33 +27,89 @@ thread_local std::string g_setup_error;
 
 // Device allocations of one handle (thread-safe: the coupling-plan thread
 // allocates while the main thread runs the setup).
-struct DevArena {
+// Device blocks of 1 MiB and more are recycled across handles in this
+// process (up to kDevCacheCap): large hipMalloc / hipFree calls cost up to a
+// few milliseconds each, and a setup makes dozens of them.  A block enters
+// the cache only after a device-wide synchronisation (as hipFree would do),
+// so that no queued work can still touch it when it is handed out again.
+constexpr size_t kDevCacheMin = size_t(1) << 20;
+constexpr size_t kDevCacheCap = size_t(8) << 30;
+struct DevCache {
   std::mutex mu;
-  std::vector<void *> ptrs;
+  std::multimap<std::pair<int, size_t>, void *> free_blocks;  // (device, size) -> block
+  size_t held = 0;
+  static DevCache &get() {
+    static DevCache *c = new DevCache();  // never destroyed: handles may outlive statics
+    return *c;
+  }
+  // a cached block of at least `size` bytes (at most a quarter more), with
+  // its real size in *got; null when there is none
+  void *take(int dev, size_t size, size_t *got) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = free_blocks.lower_bound({dev, size});
+    if (it == free_blocks.end() || it->first.first != dev || it->first.second > size + size / 4)
+      return nullptr;
+    void *p = it->second;
+    *got = it->first.second;
+    held -= *got;
+    free_blocks.erase(it);
+    return p;
+  }
+  bool put(int dev, size_t size, void *p) {  // false: over the cap, caller frees
+    std::lock_guard<std::mutex> lk(mu);
+    if (held + size > kDevCacheCap) return false;
+    free_blocks.emplace(std::make_pair(dev, size), p);
+    held += size;
+    return true;
+  }
+};
+
+struct DevArena {
+  struct Blk {
+    void *p;
+    size_t size;  // allocated size (a cached block may be larger than asked)
+    int dev;
+  };
+  std::mutex mu;
+  std::vector<Blk> blks;
   size_t bytes = 0;
   ~DevArena() { release(); }
+  static void give_back(const Blk &b) {
+    if (b.size < kDevCacheMin || !DevCache::get().put(b.dev, b.size, b.p)) (void)hipFree(b.p);
+  }
   void release() {
     std::lock_guard<std::mutex> lk(mu);
-    for (void *p : ptrs) hipFree(p);
-    ptrs.clear();
+    if (!blks.empty()) (void)hipDeviceSynchronize();
+    for (const Blk &b : blks) give_back(b);
+    blks.clear();
     bytes = 0;
   }
   template <typename T>
   T *alloc(size_t count) {
     if (count == 0) count = 1;
+    size_t size = count * sizeof(T);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
     void *p = nullptr;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+    size_t got = size;
+    if (size >= kDevCacheMin) {
+      size = (size + kDevCacheMin - 1) & ~(kDevCacheMin - 1);
+      got = size;
+      p = DevCache::get().take(dev, size, &got);
+    }
+    if (!p && hipMalloc(&p, size) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(mu);
-    ptrs.push_back(p);
+    blks.push_back({p, got, dev});
     bytes += count * sizeof(T);
     return static_cast<T *>(p);
   }
   void free_one(void *p) {
     std::lock_guard<std::mutex> lk(mu);
-    for (size_t k = 0; k < ptrs.size(); ++k)
-      if (ptrs[k] == p) {
-        hipFree(p);
-        ptrs.erase(ptrs.begin() + k);
+    for (size_t k = 0; k < blks.size(); ++k)
+      if (blks[k].p == p) {
+        (void)hipDeviceSynchronize();
+        give_back(blks[k]);
+        blks.erase(blks.begin() + k);
         return;
       }
   }
