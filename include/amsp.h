@@ -183,6 +183,22 @@ amsp_status amsp_get_pcg_history(const amsp_handle *h, double *relres_host, int3
 /* y = A x with the handle's matrix (asynchronous). */
 amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_dev);
 
+/* Adjoint of the solve u = A^{-1} f, for the gradient of a scalar loss J(u)
+ * with respect to the stored values of A.  Not part of the paper's method:
+ * it differentiates the solve the preconditioner serves.  The caller first
+ * solves the adjoint system A lambda = dJ/du with amsp_pcg on the same handle
+ * (A is symmetric); then dJ/df = lambda and, for every stored entry k of the
+ * handle's CSR (row i, column j, in the order of the CSR given to
+ * amsp_setup),
+ *     grad_val[k] = -lambda[i] * u[j].
+ * Each entry is treated as an independent value, so a symmetric perturbation
+ * of the pair (i,j),(j,i) changes J by the sum of the two entries.
+ *   lambda_dev, u_dev  device vectors of length n (read)
+ *   grad_dev           device vector of length nnz (written)
+ * Asynchronous on the handle's stream; AMSP_ERR_ARG on a null pointer. */
+amsp_status amsp_grad_values(amsp_handle *h, const double *lambda_dev, const double *u_dev,
+                             double *grad_dev);
+
 /* Introspection (host copies; each blocks on the stream). */
 amsp_status amsp_get_setup_info(const amsp_handle *h, amsp_setup_info *info);
 /* lambda_host: N*(nev+1) values; row i holds lambda_1..lambda_{m_i+1} of

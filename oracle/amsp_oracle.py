@@ -30,6 +30,7 @@ import dataclasses
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 class OracleError(ValueError):
@@ -313,3 +314,20 @@ def lanczos_condition(alphas, betas) -> float:
             e[j] = np.sqrt(betas[j]) / alphas[j]
     ev = sla.eigh_tridiagonal(d, e, eigvals_only=True)
     return float(ev[-1] / ev[0])
+
+
+# --------------------------------------------------------------------------
+# Adjoint of the solve.  Not part of the paper's method: it differentiates
+# the solve u = A^{-1} f that the preconditioner serves, for a scalar loss
+# J(u).  From A u = f, a change dA gives A du = -dA u, so
+#   dJ = g . du = -(A^{-T} g) . (dA u),   g = dJ/du.
+# With lam = A^{-T} g:  dJ/df = lam  and  dJ/dA_ij = -lam_i u_j  for every
+# stored entry (i, j), each entry taken as an independent value.  Both
+# solves are sparse direct (SuperLU); the transpose is kept explicit.
+def adjoint_gradients(A, f, dJdu):
+    """Returns (u, lam, grad_vals) with grad_vals in the CSR entry order of A."""
+    A = sp.csr_matrix(A)
+    u = spla.spsolve(A.tocsc(), f)
+    lam = spla.spsolve(A.T.tocsc(), dJdu)
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    return u, lam, -lam[rows] * u[A.indices]

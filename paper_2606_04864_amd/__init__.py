@@ -98,6 +98,8 @@ _lib.amsp_pcg.argtypes = [_vp, _vp, _vp, _i32, _d, _i32, ctypes.POINTER(_Info)]
 _lib.amsp_pcg.restype = _i32
 _lib.amsp_spmv.argtypes = [_vp, _vp, _vp]
 _lib.amsp_spmv.restype = _i32
+_lib.amsp_grad_values.argtypes = [_vp, _vp, _vp, _vp]
+_lib.amsp_grad_values.restype = _i32
 _lib.amsp_get_setup_info.argtypes = [_vp, ctypes.POINTER(_SetupInfo)]
 _lib.amsp_get_setup_info.restype = _i32
 _lib.amsp_get_pcg_history.argtypes = [_vp, _vp, _i32, ctypes.POINTER(_i32)]
@@ -122,7 +124,7 @@ _lib.amsp_setup_error.argtypes = []
 _lib.amsp_setup_error.restype = ctypes.c_char_p
 
 EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts", "amsp_pcg",
-            "amsp_spmv", "amsp_get_setup_info", "amsp_get_pcg_history", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
+            "amsp_spmv", "amsp_grad_values", "amsp_get_setup_info", "amsp_get_pcg_history", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
             "amsp_get_region", "amsp_plan_regions", "amsp_selftest_mfma", "amsp_destroy", "amsp_status_string",
             "amsp_last_error", "amsp_setup_error"]
 
@@ -312,6 +314,17 @@ class Preconditioner:
             raise AmspError(st, _lib.amsp_last_error(self._h).decode())
         return u, info
 
+    def grad_values(self, lam, u, out=None):
+        """grad[k] = -lam[row k] * u[col k] over the stored entries of A (the
+        adjoint of the solve u = A^{-1} f, given lam = A^{-1} dJ/du)."""
+        torch = _torch()
+        _check_dev(lam, "lam", self.n)
+        _check_dev(u, "u", self.n)
+        nnz = len(self._keep[1])
+        g = out if out is not None else torch.empty(nnz, dtype=torch.float64, device=u.device)
+        self._err(_lib.amsp_grad_values(self._h, lam.data_ptr(), u.data_ptr(), g.data_ptr()))
+        return g
+
     # -- introspection
     def setup_info(self) -> dict:
         si = _SetupInfo()
@@ -352,3 +365,55 @@ class Preconditioner:
 def setup(A, part, nparts, nev, **kw) -> Preconditioner:
     """A: object with row_ptr, col_idx, val (e.g. workloads.CSR)."""
     return Preconditioner(A.row_ptr, A.col_idx, A.val, part, nparts, nev, **kw)
+
+
+def _solve_fn():
+    """The torch.autograd.Function behind solve() (built on first use, so that
+    importing this module does not need torch)."""
+    global _SOLVE_FN
+    if _SOLVE_FN is not None:
+        return _SOLVE_FN
+    torch = _torch()
+
+    class _Solve(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, vals, f, row_ptr, col_idx, part, nparts, nev, rtol, maxit, kw):
+            pc = Preconditioner(row_ptr, col_idx, vals.detach().cpu().numpy(), part, nparts, nev,
+                                **kw)
+            u, info = pc.pcg(f.detach().contiguous(), rtol, maxit)
+            ctx.pc, ctx.rtol, ctx.maxit, ctx.info = pc, rtol, maxit, info
+            ctx.save_for_backward(u)
+            return u
+
+        @staticmethod
+        def backward(ctx, gu):
+            (u,) = ctx.saved_tensors
+            pc = ctx.pc
+            # adjoint system A lam = dJ/du (A symmetric: the same handle)
+            lam, _ = pc.pcg(gu.contiguous(), ctx.rtol, ctx.maxit)
+            gvals = pc.grad_values(lam, u) if ctx.needs_input_grad[0] else None
+            pc.close()
+            ctx.pc = None
+            return (gvals, lam if ctx.needs_input_grad[1] else None, None, None, None, None,
+                    None, None, None, None)
+
+    _SOLVE_FN = _Solve
+    return _Solve
+
+
+_SOLVE_FN = None
+
+
+def solve(vals, f, row_ptr, col_idx, part, nparts: int, nev: int, rtol: float = 1e-10,
+          maxit: int = 2000, **kw):
+    """u = A^{-1} f, differentiable in the stored values of A and in f.
+
+    vals: float64 tensor (nnz,) of A's values in the CSR order of
+    (row_ptr, col_idx); A must stay symmetric positive definite.  f: float64
+    device tensor (n,).  The forward pass sets up the preconditioner for these
+    values and runs PCG to rtol; the backward pass solves the adjoint system
+    A lam = dJ/du with the same handle and returns dJ/df = lam and
+    dJ/dvals[k] = -lam[row k] u[col k] (each stored entry independent).
+    Remaining keywords go to Preconditioner (overlap, precision, ...)."""
+    return _solve_fn().apply(vals, f, row_ptr, col_idx, part, nparts, nev, float(rtol),
+                             int(maxit), kw)

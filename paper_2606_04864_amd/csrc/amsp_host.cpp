@@ -1032,6 +1032,14 @@ extern "C" amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_
   return AMSP_OK;
 }
 
+extern "C" amsp_status amsp_grad_values(amsp_handle *h, const double *lambda_dev,
+                                        const double *u_dev, double *grad_dev) {
+  if (!h || !lambda_dev || !u_dev || !grad_dev) return AMSP_ERR_ARG;
+  launch_grad_values(h->stream, h->n, h->rowptr, h->col, lambda_dev, u_dev, grad_dev);
+  HIP_TRY(hipGetLastError());
+  return AMSP_OK;
+}
+
 // Entries of the apply's local factors: one packed diagonal tile per tile
 // row and the envelope (each sweep reads the diagonal tiles and one form).
 static int64_t apply_factor_elems(const HostPlan &P) {

@@ -67,6 +67,9 @@ void launch_cg_update(hipStream_t s, int n, double *x, double *r, const double *
                       const double *zold, double *part_rzo);
 void launch_dot(hipStream_t s, int n, const double *a, const double *b, double *partial,
                 const int *done);
+// grad[k] = -lambda[row k] * u[col k] for the CSR entries k
+void launch_grad_values(hipStream_t s, int n, const int *rp, const int *col, const double *lambda,
+                        const double *u, double *grad);
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
                      double *partial);
 void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha);

@@ -326,6 +326,27 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, double *__restrict__ x,
   }
 }
 
+// grad[k] = -lambda[row k] * u[col k] over the CSR entries (adjoint of the
+// solve; one thread per row).
+__global__ void __launch_bounds__(WG) k_grad_values(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const double *__restrict__ lambda,
+                                                    const double *__restrict__ u,
+                                                    double *__restrict__ grad) {
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    const double li = lambda[i];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) grad[e] = -li * u[col[e]];
+  }
+}
+
+void launch_grad_values(hipStream_t s, int n, const int *rp, const int *col, const double *lambda,
+                        const double *u, double *grad) {
+  size_t b = ((size_t)n + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_grad_values, dim3((unsigned)b), dim3(WG), 0, s, n, rp, col, lambda, u, grad);
+}
+
 // ------------------------------------------------------------- launchers ---
 void launch_spmv(hipStream_t s, int n, const int *rp, const int *col, const double *val,
                  const double *x, double *y, double *partial, const int *done) {

@@ -1,0 +1,104 @@
+"""Adjoint of the solve through the C ABI: the gradient of a scalar loss
+J(u) = 0.5 ||u - u_obs||^2 of u = A^{-1} f with respect to the stored values of
+A and to f (paper_2606_04864_amd.solve, amsp_grad_values).  Not part of the
+paper's method; it differentiates the solve the preconditioner serves.
+
+Checked against the oracle's gradient from direct sparse solves, and against
+central differences of the GPU solve itself.  The solves run to a relative
+residual of 1e-12; the bars (max-abs error over max-abs value): u and the
+gradients 1e-8 (FP64 form) and 1e-7 (mixed form, whose preconditioner differs
+but whose CG runs in FP64); central differences 1e-5 plus 1e-7 of the largest
+gradient (solve tolerance over the step).
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2606_04864_amd as P  # noqa: E402
+
+RTOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _problem():
+    w = W.get("channels64")
+    A = sp.csr_matrix((w.A.val, w.A.col_idx, w.A.row_ptr), shape=(w.n, w.n))
+    rng = np.random.default_rng(2606)
+    f = rng.standard_normal(w.n)
+    uobs = rng.standard_normal(w.n)
+    return w, A, f, uobs
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _gpu_grads(w, f, uobs, precision):
+    vals = torch.tensor(w.A.val, dtype=torch.float64, device="cuda", requires_grad=True)
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda", requires_grad=True)
+    u = P.solve(vals, ft, w.A.row_ptr, w.A.col_idx, w.part, w.nparts, w.nev, rtol=RTOL,
+                overlap=w.overlap, precision=precision)
+    J = 0.5 * ((u - torch.tensor(uobs, device="cuda")) ** 2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    return (u.detach().cpu().numpy(), vals.grad.cpu().numpy(), ft.grad.cpu().numpy(),
+            float(J.detach()))
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-8), ("fp32", 1e-7)])
+def test_solve_gradient_matches_oracle(precision, bar):
+    w, A, f, uobs = _problem()
+    say(f"adjoint vs oracle: channels64, precision={precision}")
+    u, gv, gf, _ = _gpu_grads(w, f, uobs, precision)
+    uo = O.adjoint_gradients(A, f, np.zeros(w.n))[0]
+    _, lam, go = O.adjoint_gradients(A, f, uo - uobs)
+    eu, ev, ef = _rel(u, uo), _rel(gv, go), _rel(gf, lam)
+    say(f"  u {eu:.2e}  dJ/dvals {ev:.2e}  dJ/df {ef:.2e}")
+    assert eu <= bar and ev <= bar and ef <= bar
+
+
+def test_solve_gradient_central_differences():
+    w, A, f, uobs = _problem()
+    say("adjoint vs central differences of the GPU solve: channels64, fp64")
+    _, gv, _, _ = _gpu_grads(w, f, uobs, "fp64")
+    rows = np.repeat(np.arange(w.n), np.diff(w.A.row_ptr))
+    off = np.nonzero(rows != w.A.col_idx)[0]
+    dia = np.nonzero(rows == w.A.col_idx)[0]
+    rng = np.random.default_rng(7)
+    gmax = np.abs(gv).max()
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    ut = torch.tensor(uobs, dtype=torch.float64, device="cuda")
+
+    def loss(vals):
+        u = P.solve(torch.tensor(vals, dtype=torch.float64, device="cuda"), ft, w.A.row_ptr,
+                    w.A.col_idx, w.part, w.nparts, w.nev, rtol=RTOL, overlap=w.overlap)
+        return float(0.5 * ((u - ut) ** 2).sum())
+
+    # symmetric pairs (the solver needs symmetric A): the change of J is the
+    # sum of the pair's gradients; diagonal entries alone
+    big = off[np.argsort(-np.abs(gv[off]))[:2]]
+    for k in list(big) + list(rng.choice(dia, 2, replace=False)):
+        i, j = rows[k], w.A.col_idx[k]
+        ks = [k] if i == j else [k, int(np.nonzero((rows == j) & (w.A.col_idx == i))[0][0])]
+        h = 1e-4 * abs(w.A.val[k])
+        vp, vm = w.A.val.copy(), w.A.val.copy()
+        vp[ks] += h
+        vm[ks] -= h
+        fd = (loss(vp) - loss(vm)) / (2 * h)
+        an = float(gv[ks].sum())
+        say(f"  entry {k} ({i},{j}): fd {fd:.8e} adjoint {an:.8e}")
+        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * gmax

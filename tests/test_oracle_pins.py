@@ -309,3 +309,63 @@ def test_planted_mistakes_are_caught(monkeypatch):
     bad4 = minv_f(local_eigenpairs=unscaled)
     for bad in (bad1, bad2, bad3, bad4):
         assert bad is None or np.abs(bad - ref).max() > 1e-3
+
+
+# ---------------------------------------------------------------- adjoint ---
+def _loss(A, f, uobs):
+    u = spla.spsolve(sp.csc_matrix(A), f)
+    return 0.5 * float(np.sum((u - uobs) ** 2))
+
+
+def test_adjoint_diagonal_closed_form():
+    # A = diag(d): u = f/d and dJ/dd_i = -(u_i - uobs_i) u_i / d_i exactly
+    rng = np.random.default_rng(11)
+    d = rng.uniform(1.0, 3.0, 9)
+    f, uobs = rng.standard_normal(9), rng.standard_normal(9)
+    A = sp.diags(d).tocsr()
+    u, lam, g = O.adjoint_gradients(A, f, f / d - uobs)
+    np.testing.assert_allclose(u, f / d, rtol=1e-15)
+    np.testing.assert_allclose(g, -(f / d - uobs) * (f / d) / d, rtol=1e-13)
+    np.testing.assert_allclose(lam, (f / d - uobs) / d, rtol=1e-13)
+
+
+def test_adjoint_matches_central_differences():
+    # single stored entries (the perturbed matrix is unsymmetric, so a
+    # transposed index lam_j u_i would fail) and entries of f, on a
+    # high-contrast two-point-flux matrix; central differences with a step of
+    # 1e-4 of the entry (truncation ~1e-8 relative), tolerance relative to the
+    # entry plus a floor from the largest gradient (solve rounding)
+    w, A = _small(nx=12, nparts=4, overlap=1, nev=2)
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(A.shape[0])
+    uobs = rng.standard_normal(A.shape[0])
+    u = spla.spsolve(A.tocsc(), f)
+    _, lam, g = O.adjoint_gradients(A, f, u - uobs)
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    off = np.nonzero(rows != A.indices)[0]
+    dia = np.nonzero(rows == A.indices)[0]
+    # the largest off-diagonal gradients, where a wrong index shows most
+    big = off[np.argsort(-np.abs(g[off]))[:8]]
+    picks = list(big) + list(rng.choice(off, 8, replace=False)) + list(rng.choice(dia, 6, replace=False))
+    gmax = np.abs(g).max()
+    for k in picks:
+        h = 1e-4 * abs(A.data[k])
+        Ap, Am = A.copy(), A.copy()
+        Ap.data[k] += h
+        Am.data[k] -= h
+        fd = (_loss(Ap, f, uobs) - _loss(Am, f, uobs)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-5 * abs(g[k]) + 1e-9 * gmax, (k, fd, g[k])
+    # a transposed gradient would differ from the true one on these entries
+    cols = A.indices
+    wrong = -lam[cols] * u[rows]
+    assert np.abs(wrong[big] - g[big]).max() > 1e-3 * gmax
+    # dJ/df = lam
+    lmax = np.abs(lam).max()
+    for i in rng.choice(A.shape[0], 6, replace=False):
+        e = np.zeros(A.shape[0])
+        e[i] = 1.0
+        h = 1e-4 * max(abs(f[i]), 1.0)
+        fd = (_loss(A, f + h * e, uobs) - _loss(A, f - h * e, uobs)) / (2 * h)
+        assert abs(fd - lam[i]) <= 1e-5 * abs(lam[i]) + 1e-9 * lmax
