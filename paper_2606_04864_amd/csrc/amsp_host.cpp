@@ -140,6 +140,7 @@ struct amsp_handle {
   Plan plan{};
   CoarsePlan cplan{};
   int *inv_ptr = nullptr, *inv_sd = nullptr, *inv_loc = nullptr;
+  int *inv_x = nullptr, *inv_p = nullptr, *inv_c = nullptr;  // direct scatter operand indices
   int ntilerows = 0;
   // local factors and basis
   double *sdiag = nullptr;
@@ -809,6 +810,15 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
   }
+  // direct operand indices of the inverse map for the scatter
+  {
+    const int ne = sum_ni;
+    ALLOC(h->inv_x, int, ne);
+    ALLOC(h->inv_p, int, ne);
+    ALLOC(h->inv_c, int, ne);
+    launch_inverse_direct(h->stream, ne, h->inv_sd, h->inv_loc, p, h->inv_x, h->inv_p, h->inv_c);
+    HIP_TRY(hipGetLastError());
+  }
   // the scatter's copy of the apply basis, in ascending-global-index layout
   if (h->nev > 0) {
     const size_t cnt = (size_t)sum_ni * h->nev;
@@ -994,18 +1004,18 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   }
   tk = tstart(h, 3);
   if (!mixed || h->nev == 0)
-    launch_scatter_sum_t<double>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
-                                 (const double *)h->phi_nat, h->tvec, z, partial_rz ? r : nullptr,
-                                 partial_rz, do_local, do_coarse, done);
+    launch_scatter_sum_t<double>(h->stream, h->n, h->nev, h->inv_ptr, h->inv_x, h->inv_p, h->inv_c,
+                                 h->xloc, (const double *)h->phi_nat, h->tvec, z,
+                                 partial_rz ? r : nullptr, partial_rz, do_local, do_coarse, done);
   else if (!bf)
-    launch_scatter_sum_t<float>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p, h->xloc,
-                                (const float *)h->phi_nat, h->tvec, z, partial_rz ? r : nullptr,
-                                partial_rz, do_local, do_coarse, done);
+    launch_scatter_sum_t<float>(h->stream, h->n, h->nev, h->inv_ptr, h->inv_x, h->inv_p, h->inv_c,
+                                h->xloc, (const float *)h->phi_nat, h->tvec, z,
+                                partial_rz ? r : nullptr, partial_rz, do_local, do_coarse, done);
   else
-    launch_scatter_sum_t<__hip_bfloat16>(h->stream, h->n, h->inv_ptr, h->inv_sd, h->inv_loc, p,
-                                         h->xloc, (const __hip_bfloat16 *)h->phi_nat, h->tvec, z,
-                                         partial_rz ? r : nullptr, partial_rz, do_local, do_coarse,
-                                         done);
+    launch_scatter_sum_t<__hip_bfloat16>(h->stream, h->n, h->nev, h->inv_ptr, h->inv_x, h->inv_p,
+                                         h->inv_c, h->xloc, (const __hip_bfloat16 *)h->phi_nat,
+                                         h->tvec, z, partial_rz ? r : nullptr, partial_rz,
+                                         do_local, do_coarse, done);
   tstop(h, 3, tk);
   HIP_TRY(hipGetLastError());
   return AMSP_OK;

@@ -128,9 +128,12 @@ void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const doub
                           const int *done, hipEvent_t ev_start = nullptr,
                           hipEvent_t ev_stop = nullptr);
 void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D);
+// Direct operand indices of the inverse map (see k_inverse_direct).
+void launch_inverse_direct(hipStream_t s, int ne, const int *inv_sd, const int *inv_loc,
+                           const Plan &p, int *ix, int *ip, int *ic);
 template <typename TB>
-void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
-                          const int *inv_loc, const Plan &p, const double *xloc, const TB *phi,
+void launch_scatter_sum_t(hipStream_t s, int n, int nev, const int *inv_ptr, const int *ix,
+                          const int *ip, const int *ic, const double *xloc, const TB *phi,
                           const double *t, double *z, const double *r, double *partial,
                           int do_local, int do_coarse, const int *done);
 

@@ -259,15 +259,31 @@ void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, doubl
 }
 
 // ------------------------------------------------------------ scatter -----
+// Direct indices of the inverse map, formed once at setup so that the scatter
+// reads each entry's operands without going through its region's offsets:
+//   ix = vp_ptr[sd] + l     (local correction),
+//   ip = sd_ptr[sd] + l     (basis row, ascending-index layout),
+//   ic = coff[sd] * 16 + m_sd  (coarse offset and count; m <= MAXNEV < 16).
+__global__ void k_inverse_direct(int ne, const int *__restrict__ inv_sd,
+                                 const int *__restrict__ inv_loc, Plan p, int *__restrict__ ix,
+                                 int *__restrict__ ip, int *__restrict__ ic) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
+    const int sd = inv_sd[e], l = inv_loc[e];
+    ix[e] = p.vp_ptr[sd] + l;
+    ip[e] = p.sd_ptr[sd] + l;
+    ic[e] = p.coff[sd] * 16 + p.mi[sd];
+  }
+}
+
 // z[j] = sum over regions containing j of (local correction + Phi t) and the
 // partial r.z, in the fixed order of the inverse map (no atomics).  The local
 // corrections and the basis copy are in each region's ascending-global-index
-// layout and inv_loc holds that position, so consecutive dofs of a region
-// read consecutive entries.
+// layout, so consecutive dofs of a region read consecutive entries.
 template <typename TB>
-__global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict__ inv_ptr,
-                                                    const int *__restrict__ inv_sd,
-                                                    const int *__restrict__ inv_loc, Plan p,
+__global__ void __launch_bounds__(WG) k_scatter_sum(int n, int nev, const int *__restrict__ inv_ptr,
+                                                    const int *__restrict__ ix,
+                                                    const int *__restrict__ ip,
+                                                    const int *__restrict__ ic,
                                                     const double *__restrict__ xloc,
                                                     const TB *__restrict__ phi,  // natural layout
                                                     const double *__restrict__ t,
@@ -278,7 +294,6 @@ __global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict
   if (done && *done) return;
   __shared__ double sh[WG / 64];
   constexpr int U = 4;  // independent dofs per thread and trip (overlapping load chains)
-  const int nev = p.nev;
   const int stride = gridDim.x * WG;
   double acc = 0.0;
   for (int j0 = blockIdx.x * WG + threadIdx.x; j0 < n; j0 += U * stride) {
@@ -297,17 +312,16 @@ __global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict
       for (int u = 0; u < U; ++u) {
         if (e[u] >= e1[u]) continue;
         any = true;
-        const int sd = inv_sd[e[u]], l = inv_loc[e[u]];
-        ++e[u];
+        const int k = e[u]++;
         double v = 0.0;
-        if (do_local) v = xloc[p.vp_ptr[sd] + l];
+        if (do_local) v = xloc[ix[k]];
         if (do_coarse) {
-          const int m = p.mi[sd];
-          const TB *ph = phi + (size_t)(p.sd_ptr[sd] + l) * nev;
-          const double *tt = t + p.coff[sd];
+          const int c = ic[k], m = c & 15;
+          const TB *ph = phi + (size_t)ip[k] * nev;
+          const double *tt = t + (c >> 4);
 #pragma unroll
-          for (int k = 0; k < MAXNEV; ++k)  // predicated: all loads issue together
-            if (k < m) v = fma(to_d(ph[k]), tt[k], v);
+          for (int q = 0; q < MAXNEV; ++q)  // predicated: all loads issue together
+            if (q < m) v = fma(to_d(ph[q]), tt[q], v);
         }
         zj[u] += v;
       }
@@ -381,26 +395,31 @@ template void launch_env_from_tiles<float>(hipStream_t, const Plan &, int, const
                                            float *, float *);
 
 
+void launch_inverse_direct(hipStream_t s, int ne, const int *inv_sd, const int *inv_loc,
+                           const Plan &p, int *ix, int *ip, int *ic) {
+  size_t b = ((size_t)ne + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_inverse_direct, dim3((unsigned)b), dim3(WG), 0, s, ne, inv_sd, inv_loc, p, ix,
+                     ip, ic);
+}
+
 template <typename TB>
-void launch_scatter_sum_t(hipStream_t s, int n, const int *inv_ptr, const int *inv_sd,
-                          const int *inv_loc, const Plan &p, const double *xloc, const TB *phi,
+void launch_scatter_sum_t(hipStream_t s, int n, int nev, const int *inv_ptr, const int *ix,
+                          const int *ip, const int *ic, const double *xloc, const TB *phi,
                           const double *t, double *z, const double *r, double *partial,
                           int do_local, int do_coarse, const int *done) {
-  hipLaunchKernelGGL((k_scatter_sum<TB>), dim3(reduce_blocks(n)), dim3(WG), 0, s, n, inv_ptr,
-                     inv_sd, inv_loc, p, xloc, phi, t, z, r, partial, do_local, do_coarse, done);
+  hipLaunchKernelGGL((k_scatter_sum<TB>), dim3(reduce_blocks(n)), dim3(WG), 0, s, n, nev, inv_ptr,
+                     ix, ip, ic, xloc, phi, t, z, r, partial, do_local, do_coarse, done);
 }
-template void launch_scatter_sum_t<double>(hipStream_t, int, const int *, const int *, const int *,
-                                           const Plan &, const double *, const double *,
-                                           const double *, double *, const double *, double *,
-                                           int, int, const int *);
-template void launch_scatter_sum_t<float>(hipStream_t, int, const int *, const int *, const int *,
-                                          const Plan &, const double *, const float *,
-                                          const double *, double *, const double *, double *, int,
-                                          int, const int *);
-template void launch_scatter_sum_t<__hip_bfloat16>(hipStream_t, int, const int *, const int *,
-                                                   const int *, const Plan &, const double *,
-                                                   const __hip_bfloat16 *, const double *,
-                                                   double *, const double *, double *, int, int,
-                                                   const int *);
+#define AMSP_SCATTER_INST(TB)                                                                   \
+  template void launch_scatter_sum_t<TB>(hipStream_t, int, int, const int *, const int *,      \
+                                         const int *, const int *, const double *, const TB *, \
+                                         const double *, double *, const double *, double *,   \
+                                         int, int, const int *);
+AMSP_SCATTER_INST(double)
+AMSP_SCATTER_INST(float)
+AMSP_SCATTER_INST(__hip_bfloat16)
+#undef AMSP_SCATTER_INST
 
 }  // namespace amsp
