@@ -12,7 +12,10 @@ already resident in HBM: the host-to-device transfer of the input CSR inside
 setup is excluded (and reported); host planning and the upload of its index
 arrays are included.
 
-Prints one JSON line (rank 0, N = 1 only).
+Prints one JSON line (rank 0, N = 1 only).  Besides the contract fields it
+carries `roofline` (the dominant PCG kernel), `spmv` (amsp_spmv alone, warm and
+with the MALL flushed between calls, outside the timed steps) and
+`cpu_baseline` (the oracle on a bounded sample, on the host cores).
 """
 from __future__ import annotations
 
@@ -132,6 +135,39 @@ def cpu_baseline(w, iterations, sample_sd=24):
 
 
 COPY_BYTES = 256 << 20
+
+
+def spmv_measure(P, torch, w, reps=30):
+    """amsp_spmv alone on the workload's matrix (the sliced copy the CG
+    kernels read), median of `reps` calls after 5 untimed ones: warm (the
+    previous call's data may sit in the 256 MB MALL) and flushed (a read-only
+    pass over 512 MiB between calls).  Algorithmic bytes: 12 per stored entry
+    plus x read and y written once."""
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision="fp32")
+    x = torch.randn(w.n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    flush = torch.ones(512 * 2**20 // 8, dtype=torch.float64, device="cuda")
+    alg = w.A.nnz * 12 + w.n * 16
+    out = {"bytes": int(alg)}
+    for mode in ("warm", "flushed"):
+        ts = []
+        for k in range(reps + 5):
+            if mode == "flushed":
+                flush.sum()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pc.spmv(x, out=y)
+            e1.record()
+            torch.cuda.synchronize()
+            if k >= 5:
+                ts.append(e0.elapsed_time(e1))
+        med = float(np.median(ts))
+        gbs = alg / (med * 1e-3) / 1e9
+        out[mode] = {"us": round(med * 1e3, 2), "gbs": round(gbs, 1),
+                     "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    pc.close()
+    return out
 
 
 def copy_calibration(torch):
@@ -270,6 +306,8 @@ def main():
                      "timed_every_nth_launch": TIMING_STRIDE,
                      "bytes_per_launch": rec[-1]["local_apply_bytes"]},
     }
+    log("spmv alone ...")
+    line["spmv"] = spmv_measure(P, torch, w)
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(w, sums[head]["iterations"])

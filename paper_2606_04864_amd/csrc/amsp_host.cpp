@@ -1037,7 +1037,7 @@ extern "C" amsp_status amsp_apply(amsp_handle *h, const double *r_dev, double *z
 
 extern "C" amsp_status amsp_spmv(amsp_handle *h, const double *x_dev, double *y_dev) {
   if (!h || !x_dev || !y_dev) return AMSP_ERR_ARG;
-  launch_spmv(h->stream, h->n, h->rowptr, h->col, h->val, x_dev, y_dev, nullptr, nullptr);
+  launch_spmv_sell(h->stream, h->n, h->sptr, h->scol, h->sval, x_dev, y_dev);
   HIP_TRY(hipGetLastError());
   return AMSP_OK;
 }

@@ -59,6 +59,9 @@ void launch_cg_dir(hipStream_t s, int n, const long long *sptr, const int *scol,
                    const double *sval, const double *z, const double *pold, double *pnew, double *q,
                    double *part_pq, PcgState *st, const double *part_rr, const double *part_rz,
                    const double *part_rzo, int t, int first, int flexible);
+// y = A x on the sliced copy (amsp_spmv).
+void launch_spmv_sell(hipStream_t s, int n, const long long *sptr, const int *scol,
+                      const double *sval, const double *x, double *y);
 // Sliced copy of A: sptr[s] = first entry of slice s (ceil(n/64) + 1 entries).
 void launch_csr_to_sell(hipStream_t s, int n, const int *rp, const int *col, const double *val,
                         const long long *sptr, int *scol, double *sval);

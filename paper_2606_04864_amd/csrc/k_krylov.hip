@@ -326,6 +326,47 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, double *__restrict__ x,
   }
 }
 
+// y = A x on the sliced copy of A (64-row slices, column-major inside a
+// slice): one row per thread, a wavefront per slice, so every entry load is
+// one coalesced access; the first JU entries of a row load together.
+__global__ void __launch_bounds__(WG) k_spmv_sell(int n, const long long *__restrict__ sptr,
+                                                  const int *__restrict__ scol,
+                                                  const double *__restrict__ sval,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ y) {
+  constexpr int JU = 8;
+  const int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  const int sl = i >> 6, lane = i & 63;
+  const long long base = sptr[sl];
+  const int wd = (int)((sptr[sl + 1] - base) >> 6);
+  int c[JU];
+  double v[JU];
+#pragma unroll
+  for (int j = 0; j < JU; ++j) {
+    const bool in = j < wd;
+    const long long e = base + (long long)j * 64 + lane;
+    c[j] = in ? scol[e] : i;
+    v[j] = in ? sval[e] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < JU; ++j)
+    if (j < wd) s = fma(v[j], x[c[j]], s);
+  for (int j = JU; j < wd; ++j) {  // rows longer than JU entries
+    const long long e = base + (long long)j * 64 + lane;
+    s = fma(sval[e], x[scol[e]], s);
+  }
+  y[i] = s;
+}
+
+void launch_spmv_sell(hipStream_t s, int n, const long long *sptr, const int *scol,
+                      const double *sval, const double *x, double *y) {
+  const unsigned b = (unsigned)(((long long)n + WG - 1) / WG);
+  if (b == 0) return;
+  hipLaunchKernelGGL(k_spmv_sell, dim3(b), dim3(WG), 0, s, n, sptr, scol, sval, x, y);
+}
+
 // grad[k] = -lambda[row k] * u[col k] over the CSR entries (adjoint of the
 // solve; one thread per row).
 __global__ void __launch_bounds__(WG) k_grad_values(int n, const int *__restrict__ rp,
