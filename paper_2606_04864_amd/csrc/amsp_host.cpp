@@ -140,7 +140,7 @@ struct amsp_handle {
   Plan plan{};
   CoarsePlan cplan{};
   int *inv_ptr = nullptr, *inv_sd = nullptr, *inv_loc = nullptr;
-  int *inv_x = nullptr, *inv_p = nullptr, *inv_c = nullptr;  // direct scatter operand indices
+  int *inv_x = nullptr;  // scatter: index of each copy in the local outputs
   int ntilerows = 0;
   // local factors and basis
   double *sdiag = nullptr;
@@ -814,9 +814,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   {
     const int ne = sum_ni;
     ALLOC(h->inv_x, int, ne);
-    ALLOC(h->inv_p, int, ne);
-    ALLOC(h->inv_c, int, ne);
-    launch_inverse_direct(h->stream, ne, h->inv_sd, h->inv_loc, p, h->inv_x, h->inv_p, h->inv_c);
+    launch_inverse_direct(h->stream, ne, h->inv_sd, h->inv_loc, p, h->inv_x);
     HIP_TRY(hipGetLastError());
   }
   // the scatter's copy of the apply basis, in ascending-global-index layout
@@ -1003,19 +1001,20 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
     tstop(h, 2, tk);
   }
   tk = tstart(h, 3);
+  const int mni = h->hp.max_ni;
   if (!mixed || h->nev == 0)
-    launch_scatter_sum_t<double>(h->stream, h->n, h->nev, h->inv_ptr, h->inv_x, h->inv_p, h->inv_c,
-                                 h->xloc, (const double *)h->phi_nat, h->tvec, z,
+    launch_scatter_sum_t<double>(h->stream, p, mni, h->n, h->inv_ptr, h->inv_x, h->xloc,
+                                 (const double *)h->phi_nat, h->tvec, z,
                                  partial_rz ? r : nullptr, partial_rz, do_local, do_coarse, done);
   else if (!bf)
-    launch_scatter_sum_t<float>(h->stream, h->n, h->nev, h->inv_ptr, h->inv_x, h->inv_p, h->inv_c,
-                                h->xloc, (const float *)h->phi_nat, h->tvec, z,
-                                partial_rz ? r : nullptr, partial_rz, do_local, do_coarse, done);
+    launch_scatter_sum_t<float>(h->stream, p, mni, h->n, h->inv_ptr, h->inv_x, h->xloc,
+                                (const float *)h->phi_nat, h->tvec, z, partial_rz ? r : nullptr,
+                                partial_rz, do_local, do_coarse, done);
   else
-    launch_scatter_sum_t<__hip_bfloat16>(h->stream, h->n, h->nev, h->inv_ptr, h->inv_x, h->inv_p,
-                                         h->inv_c, h->xloc, (const __hip_bfloat16 *)h->phi_nat,
-                                         h->tvec, z, partial_rz ? r : nullptr, partial_rz,
-                                         do_local, do_coarse, done);
+    launch_scatter_sum_t<__hip_bfloat16>(h->stream, p, mni, h->n, h->inv_ptr, h->inv_x, h->xloc,
+                                         (const __hip_bfloat16 *)h->phi_nat, h->tvec, z,
+                                         partial_rz ? r : nullptr, partial_rz, do_local, do_coarse,
+                                         done);
   tstop(h, 3, tk);
   HIP_TRY(hipGetLastError());
   return AMSP_OK;

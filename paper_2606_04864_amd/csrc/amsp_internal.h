@@ -133,12 +133,15 @@ void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const doub
 void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D);
 // Direct operand indices of the inverse map (see k_inverse_direct).
 void launch_inverse_direct(hipStream_t s, int ne, const int *inv_sd, const int *inv_loc,
-                           const Plan &p, int *ix, int *ip, int *ic);
+                           const Plan &p, int *ix);
+// z = sum_i R_i^T (x_i + D_i psi_i t_i): with the coarse part, first adds the
+// prolongation into the local outputs xloc (overwrites them without the local
+// part), then sums every dof's copies; partial r.z per workgroup when r != 0.
 template <typename TB>
-void launch_scatter_sum_t(hipStream_t s, int n, int nev, const int *inv_ptr, const int *ix,
-                          const int *ip, const int *ic, const double *xloc, const TB *phi,
-                          const double *t, double *z, const double *r, double *partial,
-                          int do_local, int do_coarse, const int *done);
+void launch_scatter_sum_t(hipStream_t s, const Plan &p, int max_ni, int n, const int *inv_ptr,
+                          const int *ix, double *xloc, const TB *phi, const double *t, double *z,
+                          const double *r, double *partial, int do_local, int do_coarse,
+                          const int *done);
 
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);

@@ -278,22 +278,26 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
 // The mixed-form local apply reads each sweep's data as one contiguous
 // stream per region (envelope segments then packed diagonal tile, block by
 // block in sweep order).  The workgroup loads it in 4 KB units (16 bytes per
-// thread, every byte used), NS units in flight per thread, and each arriving
-// unit is copied into an LDS ring of RU units; the row and column products
-// read the ring.  Envelope entries are used as soon as their unit has
-// arrived; a block's diagonal step runs once its whole tile is in the ring.
+// thread, every byte used), in batches of NS units: while one batch is used
+// the next is in flight.  An arriving batch is copied into an LDS ring of RU
+// units behind one barrier, and the row and column products read the ring.
+// Envelope entries are used as soon as their unit has arrived; a block's
+// diagonal step runs once its whole tile is in the ring.
 // The ring is large enough that a unit is overwritten only after every read
-// of it has finished.  Reads during unit step u touch envelope entries of
-// units >= u and at most the diagonal tile of a block ending after unit
-// u - 1, which starts no earlier than unit u - 3 (DE = 2.125 units).  A
-// thread still reading step u can meet another thread writing step u + 1 (one
-// barrier apart), and that write replaces unit u + 1 - RU = u - 5.
+// of it has finished.  While batch j (units k .. k + NS - 1) is used, reads
+// touch envelope entries of batch j and diagonal tiles that end in batch j,
+// which start no earlier than unit k - 3 (DE = 2.125 units).  Writing batch
+// j + 1 replaces units k + NS - RU .. k + 2 NS - 1 - RU, i.e. batch j - 1 when
+// RU = 2 NS.  Every diagonal step ends with a barrier, so the writer of batch
+// j + 1 can overlap only envelope reads of batch j; and the diagonal tiles
+// read in batch j + 1 start no earlier than unit k + NS - 3 >= k for NS >= 3.
 namespace stream {
 typedef float f4 __attribute__((ext_vector_type(4)));  // one thread's 16 bytes of a unit
 constexpr int UE = 4 * WG;   // floats per unit
-constexpr int RU = 6;        // units in the LDS ring
+constexpr int NS = 3;        // units per batch (and in flight per thread)
+constexpr int RU = 2 * NS;   // units in the LDS ring
 constexpr int RSZ = RU * UE;
-constexpr int NS = 4;        // units in flight per thread
+static_assert(NS >= 3, "a diagonal tile may start three units before the batch it ends in");
 }  // namespace stream
 
 size_t local_apply_stream_lds_bytes(int max_npad) {
@@ -321,7 +325,7 @@ __device__ __forceinline__ void stream_sweep(int nt, const int *es, const int *_
     return reinterpret_cast<const f4 *>(S + off) + t;
   };
   f4 f[NS];
-  // issue in slot order (the loop below waits for slot sl with the NS - 1
+  // issue in slot order (the copy below waits for slot sl with the NS - 1
   // younger loads still in flight; the scheduler must not reorder these)
   static_for<0, NS>([&](auto slc) __attribute__((always_inline)) {
     f[decltype(slc)::value] = *unit_src(decltype(slc)::value);
@@ -340,88 +344,95 @@ __device__ __forceinline__ void stream_sweep(int nt, const int *es, const int *_
     static_for<0, NS>([&](auto slc) __attribute__((always_inline)) {
       constexpr int sl = decltype(slc)::value;
       const int u = k0 + sl;
-      {
-        reinterpret_cast<f4 *>(ring + (u % RU) * UE)[t] = f[sl];
-        f[sl] = *unit_src(u + NS);
-        __syncthreads();  // unit u in the ring
-        const int avail = min(L, (u + 1) * UE);
-        while (!fin) {
-          const int dI = bs + ((T + 3) & ~3), eI = dI + DE;
-          const int hi = min(avail, dI);
-          if (hi > cons) {  // envelope entries that arrived: [cons, hi)
-            const int s0 = bs + e0;
-            const int kl = max(cons - s0, 0), kh = min(hi - s0, len);
-            const int v0 = FWD ? I * TS - len : I * TS + TS;
-            int k = kl + ((q - kl) & 3);
-            int ri = (s0 + k) % RSZ;  // ring index of entry k, advanced with a wrap
-            for (; k < kh; k += 4) {
-              acc = fmaf(-ring[ri], v[v0 + k], acc);
-              ri += 4;
-              ri = ri >= RSZ ? ri - RSZ : ri;
-            }
-            cons = hi;
-          }
-          if (avail < eI) break;
-          // diagonal step of block I
-          acc += __shfl_xor(acc, 1, 64);
-          acc += __shfl_xor(acc, 2, 64);
-          if (q == 0) tmp[rr] = v[I * TS + rr] + acc;
-          __syncthreads();  // tmp complete
-          const int dr = dI % RSZ;  // ring index of the diagonal tile
-          if (FWD) {
-            // y[rr] = sum_c inv(L_II)[rr][c] tmp[c]: row rr, columns 16q .. 16q+15
-            int ri = dr + dpos_row(rr) + 16 * q;
-            ri = ri >= RSZ ? ri - RSZ : ri;
-            float y = 0.f;
-#pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4) {
-              const int rc = ri + 4 * c4 >= RSZ ? ri + 4 * c4 - RSZ : ri + 4 * c4;
-              if (16 * q + 4 * c4 <= rr) {
-                const f4 a = *reinterpret_cast<const f4 *>(ring + rc);
-                const float *tt = tmp + 16 * q + 4 * c4;
-                y = fmaf(a[0], tt[0], y);
-                y = fmaf(a[1], tt[1], y);
-                y = fmaf(a[2], tt[2], y);
-                y = fmaf(a[3], tt[3], y);
-              }
-            }
-            y += __shfl_xor(y, 1, 64);
-            y += __shfl_xor(y, 2, 64);
-            if (q == 0) v[I * TS + rr] = y;
-          } else {
-            // x[col] = sum_r inv(L_II)[r][col] tmp[r]: column 16w + (l & 15),
-            // rows 16 (l >> 4) .. +15
-            const int l = t & 63, w = t >> 6;
-            const int col = 16 * w + (l & 15), rw0 = 16 * (l >> 4);
-            int ri = dr + dpos_row(rw0) + col;  // entry (rw0, col); rows step by
-            ri = ri >= RSZ ? ri - RSZ : ri;     // their padded lengths
-            float x = 0.f;
-#pragma unroll
-            for (int rq = 0; rq < 16; ++rq) {
-              const int row = rw0 + rq;
-              if (col <= row) x = fmaf(ring[ri], tmp[row], x);
-              ri += 4 * ((row >> 2) + 1);
-              ri = ri >= RSZ ? ri - RSZ : ri;
-            }
-            x += __shfl_xor(x, 16, 64);
-            x += __shfl_xor(x, 32, 64);
-            if ((l >> 4) == 0) v[I * TS + col] = x;
-          }
-          __syncthreads();  // block I final in v; tmp free
-          acc = 0.f;
-          if (++b == nt) {
-            fin = true;
-            break;
-          }
-          I = FWD ? b : nt - 1 - b;
-          bs = eI;
-          T = es[I * TS + TS] - es[I * TS];
-          e0 = es[I * TS + rr] - es[I * TS];
-          len = es[I * TS + rr + 1] - es[I * TS + rr];
-          cons = bs;
-        }
-      }
+      reinterpret_cast<f4 *>(ring + (u % RU) * UE)[t] = f[sl];
+      f[sl] = *unit_src(u + NS);
     });
+    __syncthreads();  // batch in the ring
+    const int avail = min(L, (k0 + NS) * UE);
+    while (!fin) {
+      const int dI = bs + ((T + 3) & ~3), eI = dI + DE;
+      const int hi = min(avail, dI);
+      if (hi > cons) {  // envelope entries that arrived: [cons, hi)
+        const int s0 = bs + e0;
+        const int kl = max(cons - s0, 0), kh = min(hi - s0, len);
+        const int v0 = FWD ? I * TS - len : I * TS + TS;
+        int k = kl + ((q - kl) & 3);
+        int ri = (s0 + k) % RSZ;  // ring index of entry k, advanced with a wrap
+        for (; k < kh; k += 4) {
+          acc = fmaf(-ring[ri], v[v0 + k], acc);
+          ri += 4;
+          ri = ri >= RSZ ? ri - RSZ : ri;
+        }
+        cons = hi;
+      }
+      if (avail < eI) break;
+      // diagonal step of block I; the next block's segment bounds are read
+      // now, off the path that follows the barriers
+      const int In = FWD ? b + 1 : nt - 2 - b;
+      int Tn = 0, e0n = 0, lenn = 0;
+      if (b + 1 < nt) {
+        const int sI = es[In * TS];
+        Tn = es[In * TS + TS] - sI;
+        e0n = es[In * TS + rr] - sI;
+        lenn = es[In * TS + rr + 1] - es[In * TS + rr];
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (q == 0) tmp[rr] = v[I * TS + rr] + acc;
+      __syncthreads();  // tmp complete
+      const int dr = dI % RSZ;  // ring index of the diagonal tile
+      if (FWD) {
+        // y[rr] = sum_c inv(L_II)[rr][c] tmp[c]: row rr, columns 16q .. 16q+15
+        int ri = dr + dpos_row(rr) + 16 * q;
+        ri = ri >= RSZ ? ri - RSZ : ri;
+        float y = 0.f;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+          const int rc = ri + 4 * c4 >= RSZ ? ri + 4 * c4 - RSZ : ri + 4 * c4;
+          if (16 * q + 4 * c4 <= rr) {
+            const f4 a = *reinterpret_cast<const f4 *>(ring + rc);
+            const float *tt = tmp + 16 * q + 4 * c4;
+            y = fmaf(a[0], tt[0], y);
+            y = fmaf(a[1], tt[1], y);
+            y = fmaf(a[2], tt[2], y);
+            y = fmaf(a[3], tt[3], y);
+          }
+        }
+        y += __shfl_xor(y, 1, 64);
+        y += __shfl_xor(y, 2, 64);
+        if (q == 0) v[I * TS + rr] = y;
+      } else {
+        // x[col] = sum_r inv(L_II)[r][col] tmp[r]: column 16w + (l & 15),
+        // rows 16 (l >> 4) .. +15
+        const int l = t & 63, w = t >> 6;
+        const int col = 16 * w + (l & 15), rw0 = 16 * (l >> 4);
+        int ri = dr + dpos_row(rw0) + col;  // entry (rw0, col); rows step by
+        ri = ri >= RSZ ? ri - RSZ : ri;     // their padded lengths
+        float x = 0.f;
+#pragma unroll
+        for (int rq = 0; rq < 16; ++rq) {
+          const int row = rw0 + rq;
+          if (col <= row) x = fmaf(ring[ri], tmp[row], x);
+          ri += 4 * ((row >> 2) + 1);
+          ri = ri >= RSZ ? ri - RSZ : ri;
+        }
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 32, 64);
+        if ((l >> 4) == 0) v[I * TS + col] = x;
+      }
+      __syncthreads();  // block I final in v; tmp free
+      acc = 0.f;
+      if (++b == nt) {
+        fin = true;
+        break;
+      }
+      I = In;
+      bs = eI;
+      T = Tn;
+      e0 = e0n;
+      len = lenn;
+      cons = bs;
+    }
   }
 }
 
@@ -450,20 +461,50 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
   double cacc[MAXNEV];
 #pragma unroll
   for (int k = 0; k < MAXNEV; ++k) cacc[k] = 0.0;
-  for (int l = threadIdx.x; l < npad; l += WG) {
-    double rv = 0.0;
-    if (l < ni) {
-      rv = r[p.sd_dofs[r0 + l]];
-      if (do_coarse) {
-        const TB *ph = phi + (size_t)(r0 + l) * nev;
+  // gather and restriction, GU rows per thread per pass with all index
+  // loads, then all value loads, issued before use (rows l, l + WG, ... are
+  // accumulated in that order)
+  constexpr int GU = 4;
+  for (int l0 = threadIdx.x; l0 < npad; l0 += GU * WG) {
+    int dof[GU];
+    double rv[GU];
 #pragma unroll
-        for (int k = 0; k < MAXNEV; ++k)
-          if (k < m) cacc[k] = fma(to_d(ph[k]), rv, cacc[k]);
+    for (int u = 0; u < GU; ++u) {
+      const int l = l0 + u * WG;
+      dof[u] = l < ni ? p.sd_dofs[r0 + l] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) rv[u] = dof[u] >= 0 ? r[dof[u]] : 0.0;
+    if (do_coarse) {
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const int l = l0 + u * WG;
+        if (l < ni) {
+          const TB *ph = phi + (size_t)(r0 + l) * nev;
+#pragma unroll
+          for (int k = 0; k < MAXNEV; ++k)
+            if (k < m) cacc[k] = fma(to_d(ph[k]), rv[u], cacc[k]);
+        }
       }
     }
-    v[l] = (float)rv;
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int l = l0 + u * WG;
+      if (l < npad) v[l] = (float)rv[u];
+    }
   }
   const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
+  // the backward sweep's segment starts are loaded now and kept in registers
+  // (regions up to UPR * WG - 1 padded rows), so that no global load sits
+  // between the two sweeps
+  constexpr int UPR = 8;
+  const bool up_regs = do_local && npad < UPR * WG;
+  int upv[UPR];
+#pragma unroll
+  for (int u = 0; u < UPR; ++u) {
+    const int l = threadIdx.x + u * WG;
+    upv[u] = (up_regs && l <= npad) ? up[l] : 0;
+  }
   if (do_local)
     for (int l = threadIdx.x; l <= npad; l += WG) es[l] = ep[l];
   if (do_coarse) {
@@ -483,7 +524,15 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
   if (!do_local) return;
   const int Lf = (int)(p.sfr[i + 1] - p.sfr[i]), Lb = (int)(p.sbr[i + 1] - p.sbr[i]);
   stream_sweep<true>(nt, es, p.sfb + g0, fst + p.sfr[i], Lf, fst + p.sfr[p.N], v, tmp, ring);
-  for (int l = threadIdx.x; l <= npad; l += WG) es[l] = up[l];
+  if (up_regs) {
+#pragma unroll
+    for (int u = 0; u < UPR; ++u) {
+      const int l = threadIdx.x + u * WG;
+      if (l <= npad) es[l] = upv[u];
+    }
+  } else {
+    for (int l = threadIdx.x; l <= npad; l += WG) es[l] = up[l];
+  }
   __syncthreads();
   stream_sweep<false>(nt, es, p.sbb + g0, bst + p.sbr[i], Lb, bst + p.sbr[p.N], v, tmp, ring);
   // local correction in the region's ascending-global-index layout

@@ -248,22 +248,30 @@ __global__ void __launch_bounds__(WG) k_trmv_tiles(const T *__restrict__ Wt, int
 }
 
 // y[O*64 + r] = sum over input tiles K (in order) of part[(O*T0 + K)*64 + r],
-// K ranging over J <= O (no transpose) or I >= O (transpose).  Four threads
-// per output split the K range into fixed quarters, combined in order.
-__global__ void __launch_bounds__(WG) k_trmv_reduce(int T0, const double *__restrict__ part,
-                                                    double *__restrict__ y, int transpose,
-                                                    const int *__restrict__ done) {
+// K ranging over J <= O (no transpose) or I >= O (transpose).  RG groups of
+// 64 threads per output tile split the K range into fixed consecutive
+// pieces (a few loads each, issued together), combined in group order.
+constexpr int RG = 16;
+__global__ void __launch_bounds__(RG * TS) k_trmv_reduce(int T0, const double *__restrict__ part,
+                                                         double *__restrict__ y, int transpose,
+                                                         const int *__restrict__ done) {
   if (done && *done) return;
-  __shared__ double red[4][TS];
+  __shared__ double red[RG][TS];
   const int O = blockIdx.x, r = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int k0 = transpose ? O : 0, k1 = transpose ? T0 : O + 1;
   const int len = k1 - k0;
-  const int a = k0 + (len * g) / 4, b = k0 + (len * (g + 1)) / 4;
+  const int a = k0 + (len * g) / RG, b = k0 + (len * (g + 1)) / RG;
   double s = 0.0;
+#pragma unroll 4
   for (int K = a; K < b; ++K) s += part[((size_t)O * T0 + K) * TS + r];
   red[g][r] = s;
   __syncthreads();
-  if (g == 0) y[O * TS + r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+  if (g == 0) {
+    double tot = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < RG; ++gg) tot += red[gg][r];
+    y[O * TS + r] = tot;
+  }
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -342,7 +350,7 @@ void launch_trmv(hipStream_t s, const T *Wt, int T0, const double *x, double *pa
                  int transpose, const int *done) {
   const int nb = T0 * (T0 + 1) / 2;
   hipLaunchKernelGGL((k_trmv_tiles<T>), dim3(nb), dim3(WG), 0, s, Wt, T0, x, part, transpose, done);
-  hipLaunchKernelGGL(k_trmv_reduce, dim3(T0), dim3(WG), 0, s, T0, part, y, transpose, done);
+  hipLaunchKernelGGL(k_trmv_reduce, dim3(T0), dim3(RG * TS), 0, s, T0, part, y, transpose, done);
 }
 template void launch_trmv<double>(hipStream_t, const double *, int, const double *, double *,
                                   double *, int, const int *);

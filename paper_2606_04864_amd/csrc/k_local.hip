@@ -265,74 +265,77 @@ void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, doubl
 //   ip = sd_ptr[sd] + l     (basis row, ascending-index layout),
 //   ic = coff[sd] * 16 + m_sd  (coarse offset and count; m <= MAXNEV < 16).
 __global__ void k_inverse_direct(int ne, const int *__restrict__ inv_sd,
-                                 const int *__restrict__ inv_loc, Plan p, int *__restrict__ ix,
-                                 int *__restrict__ ip, int *__restrict__ ic) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x) {
-    const int sd = inv_sd[e], l = inv_loc[e];
-    ix[e] = p.vp_ptr[sd] + l;
-    ip[e] = p.sd_ptr[sd] + l;
-    ic[e] = p.coff[sd] * 16 + p.mi[sd];
-  }
+                                 const int *__restrict__ inv_loc, Plan p, int *__restrict__ ix) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += gridDim.x * blockDim.x)
+    ix[e] = p.vp_ptr[inv_sd[e]] + inv_loc[e];
 }
 
-// z[j] = sum over regions containing j of (local correction + Phi t) and the
-// partial r.z, in the fixed order of the inverse map (no atomics).  The local
-// corrections and the basis copy are in each region's ascending-global-index
-// layout, so consecutive dofs of a region read consecutive entries.
+// Coarse prolongation per region, into the local output: w_i = x_i + Phi_i t_i
+// (or Phi_i t_i alone without the local part), in the region's
+// ascending-global-index layout, with Phi_i = D_i psi (the basis copy in that
+// layout).  Grid (row block, region); one row per thread.
 template <typename TB>
-__global__ void __launch_bounds__(WG) k_scatter_sum(int n, int nev, const int *__restrict__ inv_ptr,
+__global__ void __launch_bounds__(WG) k_prolong_local(Plan p, const TB *__restrict__ phi,
+                                                      const double *__restrict__ t,
+                                                      double *__restrict__ xloc, int do_local,
+                                                      const int *__restrict__ done) {
+  if (done && *done) return;
+  const int i = blockIdx.y;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int pos = blockIdx.x * WG + threadIdx.x;
+  if (pos >= ni) return;
+  const int m = p.mi[i], nev = p.nev;
+  const double *tt = t + p.coff[i];
+  const TB *ph = phi + (size_t)(r0 + pos) * nev;
+  double *dst = xloc + p.vp_ptr[i] + pos;
+  double v = do_local ? *dst : 0.0;
+#pragma unroll
+  for (int q = 0; q < MAXNEV; ++q)  // predicated: all loads issue together
+    if (q < m) v = fma(to_d(ph[q]), tt[q], v);
+  *dst = v;
+}
+
+// z[j] = sum over the copies of dof j (regions containing j, in the fixed
+// order of the inverse map; no atomics) of the region outputs, and the
+// partial r.z.  A thread takes SU consecutive dofs, whose copies are one
+// contiguous run of the map: the first SC copies are loaded together (index,
+// then value), any further ones one by one.
+constexpr int SU = 4, SC = 8;
+__global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict__ inv_ptr,
                                                     const int *__restrict__ ix,
-                                                    const int *__restrict__ ip,
-                                                    const int *__restrict__ ic,
                                                     const double *__restrict__ xloc,
-                                                    const TB *__restrict__ phi,  // natural layout
-                                                    const double *__restrict__ t,
                                                     double *__restrict__ z,
                                                     const double *__restrict__ r,
-                                                    double *__restrict__ partial, int do_local,
-                                                    int do_coarse, const int *__restrict__ done) {
+                                                    double *__restrict__ partial,
+                                                    const int *__restrict__ done) {
   if (done && *done) return;
   __shared__ double sh[WG / 64];
-  constexpr int U = 4;  // independent dofs per thread and trip (overlapping load chains)
   const int stride = gridDim.x * WG;
   double acc = 0.0;
-  for (int j0 = blockIdx.x * WG + threadIdx.x; j0 < n; j0 += U * stride) {
-    int e[U], e1[U];
-    double zj[U];
+  for (int g = blockIdx.x * WG + threadIdx.x; g < (n + SU - 1) / SU; g += stride) {
+    const int j0 = g * SU;
+    int e[SU + 1];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = j0 + u * stride;
-      e[u] = j < n ? inv_ptr[j] : 0;
-      e1[u] = j < n ? inv_ptr[j + 1] : 0;
-      zj[u] = 0.0;
+    for (int u = 0; u <= SU; ++u) e[u] = inv_ptr[min(j0 + u, n)];
+    double x[SC];
+#pragma unroll
+    for (int c = 0; c < SC; ++c) {
+      const int k = e[0] + c;
+      x[c] = k < e[SU] ? xloc[ix[k]] : 0.0;
     }
-    for (;;) {
-      bool any = false;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (e[u] >= e1[u]) continue;
-        any = true;
-        const int k = e[u]++;
-        double v = 0.0;
-        if (do_local) v = xloc[ix[k]];
-        if (do_coarse) {
-          const int c = ic[k], m = c & 15;
-          const TB *ph = phi + (size_t)ip[k] * nev;
-          const double *tt = t + (c >> 4);
+    for (int u = 0; u < SU; ++u) {
+      double zj = 0.0;
 #pragma unroll
-          for (int q = 0; q < MAXNEV; ++q)  // predicated: all loads issue together
-            if (q < m) v = fma(to_d(ph[q]), tt[q], v);
-        }
-        zj[u] += v;
+      for (int c = 0; c < SC; ++c) {
+        const int k = e[0] + c;
+        if (k >= e[u] && k < e[u + 1]) zj += x[c];
       }
-      if (!any) break;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = j0 + u * stride;
+      for (int k = max(e[u], e[0] + SC); k < e[u + 1]; ++k) zj += xloc[ix[k]];
+      const int j = j0 + u;
       if (j < n) {
-        z[j] = zj[u];
-        if (r) acc = fma(r[j], zj[u], acc);
+        z[j] = zj;
+        if (r) acc = fma(r[j], zj, acc);
       }
     }
   }
@@ -396,27 +399,31 @@ template void launch_env_from_tiles<float>(hipStream_t, const Plan &, int, const
 
 
 void launch_inverse_direct(hipStream_t s, int ne, const int *inv_sd, const int *inv_loc,
-                           const Plan &p, int *ix, int *ip, int *ic) {
+                           const Plan &p, int *ix) {
   size_t b = ((size_t)ne + WG - 1) / WG;
   if (b > 65535) b = 65535;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(k_inverse_direct, dim3((unsigned)b), dim3(WG), 0, s, ne, inv_sd, inv_loc, p, ix,
-                     ip, ic);
+  hipLaunchKernelGGL(k_inverse_direct, dim3((unsigned)b), dim3(WG), 0, s, ne, inv_sd, inv_loc, p, ix);
 }
 
 template <typename TB>
-void launch_scatter_sum_t(hipStream_t s, int n, int nev, const int *inv_ptr, const int *ix,
-                          const int *ip, const int *ic, const double *xloc, const TB *phi,
-                          const double *t, double *z, const double *r, double *partial,
-                          int do_local, int do_coarse, const int *done) {
-  hipLaunchKernelGGL((k_scatter_sum<TB>), dim3(reduce_blocks(n)), dim3(WG), 0, s, n, nev, inv_ptr,
-                     ix, ip, ic, xloc, phi, t, z, r, partial, do_local, do_coarse, done);
+void launch_scatter_sum_t(hipStream_t s, const Plan &p, int max_ni, int n, const int *inv_ptr,
+                          const int *ix, double *xloc, const TB *phi, const double *t, double *z,
+                          const double *r, double *partial, int do_local, int do_coarse,
+                          const int *done) {
+  if (do_coarse && max_ni > 0)
+    hipLaunchKernelGGL((k_prolong_local<TB>), dim3((max_ni + WG - 1) / WG, p.N), dim3(WG), 0, s, p,
+                       phi, t, xloc, do_local, done);
+  // one partial per workgroup of the usual reduction grid, which the
+  // consumers of r.z expect (the surplus workgroups add zeros)
+  hipLaunchKernelGGL(k_scatter_sum, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, inv_ptr, ix, xloc, z,
+                     r, partial, done);
 }
 #define AMSP_SCATTER_INST(TB)                                                                   \
-  template void launch_scatter_sum_t<TB>(hipStream_t, int, int, const int *, const int *,      \
-                                         const int *, const int *, const double *, const TB *, \
-                                         const double *, double *, const double *, double *,   \
-                                         int, int, const int *);
+  template void launch_scatter_sum_t<TB>(hipStream_t, const Plan &, int, int, const int *,     \
+                                         const int *, double *, const TB *, const double *,    \
+                                         double *, const double *, double *, int, int,         \
+                                         const int *);
 AMSP_SCATTER_INST(double)
 AMSP_SCATTER_INST(float)
 AMSP_SCATTER_INST(__hip_bfloat16)
