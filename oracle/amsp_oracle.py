@@ -18,8 +18,10 @@ Readings where the paper is silent (each also listed in the design notes):
   * preconditioner: additive two-level Schwarz, the paper's coarse term
     R0^T A0^{-1} R0 (Section 3.1) plus local solves sum_i R_i^T A_i^{-1} R_i,
     so that the operator is SPD and usable in CG;
-  * Krylov method: preconditioned CG (the paper runs GMRES) stopping on the
-    unpreconditioned 2-norm ||r|| <= rtol ||f|| from x0 = 0;
+  * Krylov method: preconditioned CG stopping on the unpreconditioned 2-norm
+    ||r|| <= rtol ||f|| from x0 = 0; and the paper's own GMRES (Section 5),
+    right-preconditioned in flexible form so that it minimises and reports
+    the same residual, restarted every 30 steps unless told otherwise;
   * normalisation/sign: psi^T S psi = 1, largest-|entry| positive (lowest
     global index on ties).
 """
@@ -314,6 +316,88 @@ def lanczos_condition(alphas, betas) -> float:
             e[j] = np.sqrt(betas[j]) / alphas[j]
     ev = sla.eigh_tridiagonal(d, e, eigvals_only=True)
     return float(ev[-1] / ev[0])
+
+
+# --------------------------------------------------------------------------
+# Preconditioned GMRES, the Krylov method of the paper's experiments
+# (Section 5: GMRES with the two-level preconditioner, stopped once the
+# relative residual has dropped by 1e-6).  Readings: right preconditioning
+# in its flexible form (Saad, Iterative Methods for Sparse Linear Systems,
+# Section 9.4.1: the preconditioned vectors z_j = M^{-1} v_j are kept and
+# x = x0 + Z y), so the minimised and reported quantity is the true residual
+# ||f - A x||_2 relative to ||f|| (x0 = 0); restart length m (30 by default,
+# as the paper does not state one); Arnoldi by modified Gram-Schmidt; the
+# small least-squares problem by Givens rotations.
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class GMRESResult:
+    x: np.ndarray
+    iterations: int
+    converged: bool
+    relres_history: list   # |g_{j+1}| / ||f|| after each inner step (entry 0: 1)
+    relres_true: float
+    restarts: int
+
+
+def gmres(A, f, Minv, restart=30, rtol=1e-6, maxit=1000) -> GMRESResult:
+    A = sp.csr_matrix(A)
+    n = f.shape[0]
+    x = np.zeros_like(f)
+    nf = np.linalg.norm(f)
+    hist = [1.0 if nf > 0 else 0.0]
+    if nf == 0.0:
+        return GMRESResult(x, 0, True, hist, 0.0, 0)
+    r = f.copy()
+    beta = nf
+    it = 0
+    cycles = 0
+    converged = False
+    while it < maxit:
+        m = restart
+        V = np.zeros((n, m + 1))
+        Z = np.zeros((n, m))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        V[:, 0] = r / beta
+        g[0] = beta
+        k = 0
+        for j in range(m):
+            Z[:, j] = Minv(V[:, j])
+            w = A @ Z[:, j]
+            for i in range(j + 1):  # modified Gram-Schmidt
+                H[i, j] = V[:, i] @ w
+                w = w - H[i, j] * V[:, i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0.0:
+                V[:, j + 1] = w / H[j + 1, j]
+            for i in range(j):  # earlier rotations on the new column
+                a, b = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a + sn[i] * b
+                H[i + 1, j] = -sn[i] * a + cs[i] * b
+            a, b = H[j, j], H[j + 1, j]
+            rho = np.hypot(a, b)
+            cs[j], sn[j] = (a / rho, b / rho) if rho > 0.0 else (1.0, 0.0)
+            H[j, j] = rho
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            k = j + 1
+            hist.append(abs(g[j + 1]) / nf)
+            if abs(g[j + 1]) <= rtol * nf or it >= maxit or H[k - 1, k - 1] == 0.0:
+                break
+        y = sla.solve_triangular(H[:k, :k], g[:k], lower=False)
+        x = x + Z[:, :k] @ y
+        r = f - A @ x
+        beta = np.linalg.norm(r)
+        cycles += 1
+        if beta <= rtol * nf:
+            converged = True
+            break
+    true = np.linalg.norm(f - A @ x) / nf
+    return GMRESResult(x, it, converged, hist, true, cycles - 1)
 
 
 # --------------------------------------------------------------------------

@@ -369,3 +369,77 @@ def test_adjoint_matches_central_differences():
         h = 1e-4 * max(abs(f[i]), 1.0)
         fd = (_loss(A, f + h * e, uobs) - _loss(A, f - h * e, uobs)) / (2 * h)
         assert abs(fd - lam[i]) <= 1e-5 * abs(lam[i]) + 1e-9 * lmax
+
+
+# ---------------------------------------------------------------- GMRES ----
+def _nonsym(n=40, seed=11):
+    """A small well-conditioned nonsymmetric matrix (GMRES does not need symmetry)."""
+    rng = np.random.default_rng(seed)
+    return sp.csr_matrix(np.eye(n) * 4.0 + rng.standard_normal((n, n)) / np.sqrt(n))
+
+
+def test_gmres_identity_reaches_direct_solution():
+    """Unrestarted, unpreconditioned GMRES solves an n x n system in at most n
+    steps (the Krylov space is then all of R^n)."""
+    for A in (_nonsym(), _small(nx=6, nparts=2)[1]):
+        n = A.shape[0]
+        f = np.random.default_rng(12).standard_normal(n)
+        res = O.gmres(A, f, lambda v: v.copy(), restart=n, rtol=1e-10, maxit=n)
+        assert res.converged and res.iterations <= n
+        u = np.linalg.solve(A.toarray(), f)
+        np.testing.assert_allclose(res.x, u, rtol=0, atol=1e-7 * np.abs(u).max())
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_gmres_iterate_is_the_krylov_least_squares_minimiser(k):
+    """After k steps, x_k minimises ||f - A x|| over x in M^{-1} K_k(A M^{-1}, f):
+    brute force with the explicit Krylov matrix, Householder QR and lstsq."""
+    w, A = _small(nx=12, nparts=4, nev=2)
+    st = O.setup(A, w.part, w.nparts, w.nev, w.overlap)
+    f = np.random.default_rng(13).standard_normal(A.shape[0])
+    res = O.gmres(A, f, st.apply, restart=50, rtol=0.0, maxit=k)
+    assert res.iterations == k
+    K = np.empty((A.shape[0], k))
+    v = f.copy()
+    for j in range(k):
+        K[:, j] = v
+        v = A @ st.apply(v)
+    Q, _ = np.linalg.qr(K)
+    S = np.column_stack([st.apply(Q[:, j]) for j in range(k)])
+    y, *_ = np.linalg.lstsq(A @ S, f, rcond=None)
+    xs = S @ y
+    np.testing.assert_allclose(res.x, xs, rtol=0, atol=1e-9 * np.abs(xs).max())
+    rel = np.linalg.norm(f - A @ xs) / np.linalg.norm(f)
+    assert abs(res.relres_history[-1] - rel) <= 1e-9 * rel + 1e-15
+
+
+def test_gmres_residual_never_above_pcg():
+    """With the same SPD preconditioner and x0 = 0, PCG's k-th iterate lies in
+    the space GMRES minimises over, so GMRES's residual is never larger."""
+    w = W.get("channels64")
+    A = w.A.to_scipy()
+    st = O.setup(A, w.part, w.nparts, w.nev, w.overlap)
+    cg = O.pcg(A, w.b, st.apply, rtol=1e-10)
+    gm = O.gmres(A, w.b, st.apply, restart=400, rtol=1e-10, maxit=cg.iterations)
+    k = min(len(cg.relres_history), len(gm.relres_history))
+    h_cg = np.array(cg.relres_history[:k])
+    h_gm = np.array(gm.relres_history[:k])
+    assert np.all(h_gm <= h_cg * (1 + 1e-8) + 1e-14), np.max(h_gm / h_cg)
+    assert gm.iterations <= cg.iterations
+
+
+def test_gmres_restarted_history_and_true_residual():
+    """Restarted GMRES: the residual never grows (each cycle starts from the
+    current iterate), the estimate equals the true residual at every restart,
+    and the result meets the tolerance."""
+    w = W.get("channels64")
+    A = w.A.to_scipy()
+    st = O.setup(A, w.part, w.nparts, w.nev, w.overlap)
+    res = O.gmres(A, w.b, st.apply, restart=10, rtol=1e-6)
+    h = np.array(res.relres_history)
+    assert res.converged and res.restarts >= 1
+    assert np.all(np.diff(h) <= 1e-12), np.diff(h).max()
+    assert res.relres_true <= 1e-6 and abs(res.relres_true - h[-1]) <= 1e-8 * h[-1]
+    u = spla.spsolve(A.tocsc(), w.b)
+    assert np.linalg.norm(A @ res.x - w.b) <= 1e-6 * np.linalg.norm(w.b)
+    assert np.linalg.norm(res.x - u) / np.linalg.norm(u) < 1e-3
