@@ -174,9 +174,30 @@ amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
 amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                      double rtol, int32_t maxit, amsp_info *info);
 
-/* Recursive relative residuals ||r_k|| / ||f|| of the last amsp_pcg call
- * (last right-hand side; k = 0 .. iterations).  *count receives the length;
- * at most cap values are written to relres_host (may be NULL). */
+/* Restarted GMRES with the preconditioner, the Krylov method of the paper's
+ * experiments (Section 5: GMRES preconditioned by the two-level method, run
+ * until the relative residual has dropped by a factor 1e-6).  Right
+ * preconditioning in flexible form: z_j = M^{-1} v_j are kept and
+ * u = Z y, so the residual GMRES minimises is the true one, f - A u, as for
+ * amsp_pcg.  From u = 0; every restart-th step (1 .. AMSP_GMRES_MAX_RESTART)
+ * the iterate is formed, f - A u recomputed and the next cycle starts from it.
+ * Stops when ||f - A u|| <= max(rtol, floor) ||f|| at the end of a cycle (the
+ * cycle ends once its residual estimate reaches rtol), or after maxit steps
+ * (AMSP_ERR_PCG_NOCONV; u holds the last iterate).  Arnoldi by classical
+ * Gram-Schmidt applied twice, fixed-order reductions; the small least-squares
+ * problem by Givens rotations on the host.  Workspace (allocated by the call,
+ * kept in the handle's cache): (2 restart + 1) n doubles.  info: iterations =
+ * GMRES steps (preconditioner applications), restarts = cycles after the
+ * first, relres_recursive = last residual estimate; the history getter below
+ * returns the estimates after every step.  Blocks; info may be NULL. */
+#define AMSP_GMRES_MAX_RESTART 64
+amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
+                       int32_t restart, double rtol, int32_t maxit, amsp_info *info);
+
+/* Relative residuals ||r_k|| / ||f|| of the last amsp_pcg (recursive
+ * residuals) or amsp_gmres (residual estimates) call (last right-hand side;
+ * k = 0 .. iterations).  *count receives the length; at most cap values are
+ * written to relres_host (may be NULL). */
 amsp_status amsp_get_pcg_history(const amsp_handle *h, double *relres_host, int32_t cap,
                                  int32_t *count);
 

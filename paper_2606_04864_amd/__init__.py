@@ -96,6 +96,8 @@ _lib.amsp_apply_parts.argtypes = [_vp, _vp, _vp, _i32, _i32]
 _lib.amsp_apply_parts.restype = _i32
 _lib.amsp_pcg.argtypes = [_vp, _vp, _vp, _i32, _d, _i32, ctypes.POINTER(_Info)]
 _lib.amsp_pcg.restype = _i32
+_lib.amsp_gmres.argtypes = [_vp, _vp, _vp, _i32, _i32, _d, _i32, ctypes.POINTER(_Info)]
+_lib.amsp_gmres.restype = _i32
 _lib.amsp_spmv.argtypes = [_vp, _vp, _vp]
 _lib.amsp_spmv.restype = _i32
 _lib.amsp_grad_values.argtypes = [_vp, _vp, _vp, _vp]
@@ -124,6 +126,7 @@ _lib.amsp_setup_error.argtypes = []
 _lib.amsp_setup_error.restype = ctypes.c_char_p
 
 EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts", "amsp_pcg",
+            "amsp_gmres",
             "amsp_spmv", "amsp_grad_values", "amsp_get_setup_info", "amsp_get_pcg_history", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
             "amsp_get_region", "amsp_plan_regions", "amsp_selftest_mfma", "amsp_destroy", "amsp_status_string",
             "amsp_last_error", "amsp_setup_error"]
@@ -314,6 +317,24 @@ class Preconditioner:
             raise AmspError(st, _lib.amsp_last_error(self._h).decode())
         return u, info
 
+    def gmres(self, f, rtol: float = 1e-6, restart: int = 30, maxit: int = 1000, out=None,
+              raise_on_noconv=True):
+        """Solve A u = f by restarted GMRES with the preconditioner (flexible
+        right preconditioning); returns (u, info dict).  Defaults: the
+        paper's 1e-6 reduction of the residual, restart every 30 steps."""
+        torch = _torch()
+        _check_dev(f, "f", self.n)
+        u = out if out is not None else torch.empty_like(f)
+        inf = _Info()
+        st = _lib.amsp_gmres(self._h, f.data_ptr(), u.data_ptr(), 1, int(restart), float(rtol),
+                             int(maxit), ctypes.byref(inf))
+        info = {name: getattr(inf, name) for name, _ in _Info._fields_
+                if name not in ("kernel_ms", "kernel_launches")}
+        info["status"] = STATUS.get(st, st)
+        if st != AMSP_OK and (raise_on_noconv or st != -9):
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
+        return u, info
+
     def grad_values(self, lam, u, out=None):
         """grad[k] = -lam[row k] * u[col k] over the stored entries of A (the
         adjoint of the solve u = A^{-1} f, given lam = A^{-1} dJ/du)."""
@@ -334,7 +355,8 @@ class Preconditioner:
         return d
 
     def pcg_history(self) -> np.ndarray:
-        """Recursive relative residuals of the last pcg() call."""
+        """Relative residuals of the last pcg() (recursive) or gmres()
+        (estimates) call, one per step from step 0."""
         cnt = ctypes.c_int32()
         self._err(_lib.amsp_get_pcg_history(self._h, None, 0, ctypes.byref(cnt)))
         out = np.empty(cnt.value, dtype=np.float64)

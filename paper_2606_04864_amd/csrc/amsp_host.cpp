@@ -1246,6 +1246,178 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   return final_status;
 }
 
+// ---------------------------------------------------------------- GMRES ----
+// Restarted GMRES with flexible right preconditioning (Saad, Iterative
+// Methods for Sparse Linear Systems, Section 9.4.1): Arnoldi on A M^{-1}
+// with the preconditioned vectors kept, Gram-Schmidt twice per step on the
+// device, Givens rotations and the triangular solve on the host.
+extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
+                                  int32_t restart, double rtol, int32_t maxit, amsp_info *info) {
+  if (!h || !f_dev || !u_dev || nrhs < 1 || restart < 1 || restart > AMSP_GMRES_MAX_RESTART ||
+      maxit < 0 || !(rtol >= 0.0))
+    return AMSP_ERR_ARG;
+  const int n = h->n, m = restart, nb = reduce_blocks(n);
+  const size_t ld = (size_t)n;
+  hipStream_t s = h->stream;
+  amsp_info inf{};
+  inf.bytes_per_iter = bytes_per_iter(h);
+  inf.local_apply_bytes = local_apply_bytes(h);
+  h->timing_active = false;
+  const double t0 = now_ms();
+  if (h->hist_cap < maxit + 2) {
+    if (h->hist) h->mem.free_one(h->hist);
+    h->hist_cap = std::max(maxit + 2, 1024);
+    ALLOC(h->hist, double, h->hist_cap);
+  }
+  // scalars on the device: [0, 64) first Gram-Schmidt coefficients, [64, 128)
+  // second ones, [128] squared norm, [192, 256) the cycle's y
+  double *V = nullptr, *Z = nullptr, *part = nullptr, *sc = nullptr;
+  ALLOC(V, double, ld * (m + 1));
+  ALLOC(Z, double, ld * m);
+  ALLOC(part, double, (size_t)nb * (m + 2));
+  ALLOC(sc, double, 256);
+  double *w = h->q, *pn = part + (size_t)nb * (m + 1);
+  auto release = [&]() {
+    h->mem.free_one(V);
+    h->mem.free_one(Z);
+    h->mem.free_one(part);
+    h->mem.free_one(sc);
+  };
+  auto sq_to_host = [&](double &out) -> hipError_t {  // sc[128] -> host
+    hipError_t e = hipMemcpyAsync(&out, sc + 128, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  };
+  amsp_status final_status = AMSP_OK;
+  int tot_it = 0, tot_restarts = 0, all_conv = 1;
+  double worst_true = 0.0, worst_est = 0.0, worst_floor = 0.0;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), coef(129);
+  std::vector<double> g2;
+  for (int rhs = 0; rhs < nrhs; ++rhs) {
+    const double *f = f_dev + (size_t)rhs * n;
+    double *x = u_dev + (size_t)rhs * n;
+    launch_fill(s, n, x, 0.0);
+    launch_copy_scale(s, n, f, h->r, 1.0);
+    launch_dot(s, n, f, f, pn, nullptr);
+    launch_sum_partials(s, pn, nb, sc + 128);
+    double f2 = 0.0;
+    HIP_TRY(sq_to_host(f2));
+    const double nf = std::sqrt(f2);
+    if (!std::isfinite(nf)) {
+      release();
+      h->err = "right-hand side not finite";
+      return AMSP_ERR_BREAKDOWN;
+    }
+    g2.assign(1, f2);
+    double beta = nf, est = nf > 0.0 ? 1.0 : 0.0, relres_true = est, floor_rel = 0.0;
+    int it = 0, cycles = 0;
+    bool conv = nf == 0.0;
+    while (!conv && it < maxit) {
+      launch_gs_normalize(s, n, h->r, sc + 128, V);  // v_0 = r / beta
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int k = 0;
+      for (int j = 0; j < m; ++j) {
+        double *vj = V + (size_t)j * ld, *zj = Z + (size_t)j * ld;
+        amsp_status st = apply_one(h, vj, zj, 3, nullptr, nullptr);
+        if (st != AMSP_OK) {
+          release();
+          return st;
+        }
+        launch_spmv_sell(s, n, h->sptr, h->scol, h->sval, zj, w);
+        launch_gs_dots(s, n, V, ld, j + 1, w, part, sc);
+        launch_gs_update(s, n, V, ld, j + 1, sc, w, nullptr);
+        launch_gs_dots(s, n, V, ld, j + 1, w, part, sc + 64);
+        launch_gs_update(s, n, V, ld, j + 1, sc + 64, w, pn);
+        launch_sum_partials(s, pn, nb, sc + 128);
+        launch_gs_normalize(s, n, w, sc + 128, V + (size_t)(j + 1) * ld);
+        HIP_TRY(hipMemcpyAsync(coef.data(), sc, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double *hj = H.data() + (size_t)j * (m + 1);  // column j of H
+        for (int i = 0; i <= j; ++i) hj[i] = coef[i] + coef[64 + i];
+        const double hnext = std::sqrt(coef[128]);
+        hj[j + 1] = hnext;
+        for (int i = 0; i < j; ++i) {  // earlier rotations
+          const double a = hj[i], b = hj[i + 1];
+          hj[i] = cs[i] * a + sn[i] * b;
+          hj[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double a = hj[j], b = hj[j + 1], rho = std::hypot(a, b);
+        cs[j] = rho > 0.0 ? a / rho : 1.0;
+        sn[j] = rho > 0.0 ? b / rho : 0.0;
+        hj[j] = rho;
+        hj[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++it;
+        k = j + 1;
+        g2.push_back(g[j + 1] * g[j + 1]);
+        est = nf > 0.0 ? std::fabs(g[j + 1]) / nf : 0.0;
+        if (std::fabs(g[j + 1]) <= rtol * nf || it >= maxit || !(hnext > 0.0) || !(rho > 0.0)) break;
+      }
+      // y = R^{-1} g (R: the rotated upper triangle of H), x += Z y
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * (m + 1) + i] * y[c];
+        const double d = H[(size_t)i * (m + 1) + i];
+        y[i] = d != 0.0 ? t / d : 0.0;
+      }
+      HIP_TRY(hipMemcpyAsync(sc + 192, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_basis_combine(s, n, Z, ld, k, sc + 192, x);
+      // true residual; it seeds the next cycle
+      launch_spmv_sell(s, n, h->sptr, h->scol, h->sval, x, w);
+      launch_residual(s, n, f, w, h->r, pn);
+      launch_sum_partials(s, pn, nb, sc + 128);
+      double r2 = 0.0;
+      HIP_TRY(sq_to_host(r2));
+      beta = std::sqrt(r2);
+      relres_true = beta / nf;
+      ++cycles;
+      if (!std::isfinite(beta)) {
+        release();
+        h->err = "GMRES breakdown: residual not finite";
+        return AMSP_ERR_BREAKDOWN;
+      }
+      if (relres_true <= rtol) {
+        conv = true;
+      } else if (est <= rtol) {
+        // the estimate met rtol but the recomputed residual did not: accept
+        // if it is at the rounding floor, otherwise the next cycle continues
+        launch_abs_spmv_sq(s, n, h->rowptr, h->col, h->val, x, pn);
+        launch_sum_partials(s, pn, nb, sc + 128);
+        double a2 = 0.0;
+        HIP_TRY(sq_to_host(a2));
+        floor_rel = DBL_EPSILON * std::sqrt(a2) / nf;
+        conv = relres_true <= floor_rel;
+      }
+      if (!(beta > 0.0)) conv = true;  // exact solution
+    }
+    h->hist_len = std::min((int)g2.size(), h->hist_cap);
+    h->hist_f2 = f2;
+    HIP_TRY(hipMemcpyAsync(h->hist, g2.data(), h->hist_len * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    tot_it += it;
+    tot_restarts += std::max(cycles - 1, 0);
+    worst_true = std::max(worst_true, relres_true);
+    worst_est = std::max(worst_est, est);
+    worst_floor = std::max(worst_floor, floor_rel);
+    if (!conv) {
+      all_conv = 0;
+      if (final_status == AMSP_OK) final_status = AMSP_ERR_PCG_NOCONV;
+    }
+  }
+  release();
+  inf.iterations = tot_it;
+  inf.converged = all_conv;
+  inf.relres_recursive = worst_est;
+  inf.relres_true = worst_true;
+  inf.restarts = tot_restarts;
+  inf.relres_floor = worst_floor;
+  inf.solve_ms = now_ms() - t0;
+  if (info) *info = inf;
+  return final_status;
+}
+
 // ------------------------------------------------------- introspection ----
 extern "C" amsp_status amsp_get_setup_info(const amsp_handle *h, amsp_setup_info *info) {
   if (!h || !info) return AMSP_ERR_ARG;

@@ -76,6 +76,18 @@ void launch_grad_values(hipStream_t s, int n, const int *rp, const int *col, con
 void launch_residual(hipStream_t s, int n, const double *f, const double *Ax, double *r,
                      double *partial);
 void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha);
+// GMRES (restarted, flexible right preconditioning) building blocks.  The
+// basis columns are V + k * ldv.  out[k] = V_k . w for k < k1 (part holds
+// k1 * reduce_blocks(n) partials); w -= V h with optional w.w partials;
+// v = w / sqrt(*nrm2); x += Z y.
+void launch_gs_dots(hipStream_t s, int n, const double *V, size_t ldv, int k1, const double *w,
+                    double *part, double *out);
+void launch_gs_update(hipStream_t s, int n, const double *V, size_t ldv, int k1, const double *h,
+                      double *w, double *part);
+void launch_gs_normalize(hipStream_t s, int n, const double *w, const double *nrm2, double *v);
+void launch_basis_combine(hipStream_t s, int n, const double *Z, size_t ldz, int k, const double *y,
+                          double *x);
+
 void launch_abs_spmv_sq(hipStream_t s, int n, const int *rp, const int *col, const double *val,
                         const double *x, double *partial);
 void launch_fill(hipStream_t s, size_t n, double *a, double v);

@@ -437,6 +437,105 @@ void launch_abs_spmv_sq(hipStream_t s, int n, const int *rp, const int *col, con
                      partial);
 }
 
+// ------------------------------------------------------ GMRES (Arnoldi) ---
+// Classical Gram-Schmidt passes over the basis V (column k at V + k * ldv),
+// used twice per step.  Dots: workgroup (b, c) adds rows b, b + nb, ... of
+// columns 8c .. 8c+7 into part[k * nb + b]; the reduce kernel then sums each
+// column's nb partials in a fixed order.
+constexpr int GSC = 8;
+__global__ void __launch_bounds__(WG) k_gs_dots(int n, const double *__restrict__ V, size_t ldv,
+                                                int k1, const double *__restrict__ w,
+                                                double *__restrict__ part) {
+  __shared__ double sh[WG / 64];
+  const int nb = gridDim.x, c0 = blockIdx.y * GSC;
+  double acc[GSC];
+#pragma unroll
+  for (int c = 0; c < GSC; ++c) acc[c] = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += nb * WG) {
+    const double wi = w[i];
+#pragma unroll
+    for (int c = 0; c < GSC; ++c)
+      if (c0 + c < k1) acc[c] = fma(V[(size_t)(c0 + c) * ldv + i], wi, acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < GSC; ++c) {
+    if (c0 + c >= k1) break;  // uniform
+    const double t = block_sum(acc[c], sh);
+    if (threadIdx.x == 0) part[(size_t)(c0 + c) * nb + blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(WG) k_gs_reduce(int nb, const double *__restrict__ part,
+                                                  double *__restrict__ out) {
+  __shared__ double sh[WG / 64];
+  const double t = sum_partials(part + (size_t)blockIdx.x * nb, nb, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// w -= V h (columns 0 .. k1-1, in that order); with part != 0 also the
+// partial sums of the updated w.w.
+__global__ void __launch_bounds__(WG) k_gs_update(int n, const double *__restrict__ V, size_t ldv,
+                                                  int k1, const double *__restrict__ h,
+                                                  double *__restrict__ w,
+                                                  double *__restrict__ part) {
+  __shared__ double sh[WG / 64];
+  double acc = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    double wi = w[i];
+    for (int k = 0; k < k1; ++k) wi = fma(-V[(size_t)k * ldv + i], h[k], wi);
+    w[i] = wi;
+    acc = fma(wi, wi, acc);
+  }
+  if (part) {
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
+}
+
+// v = w / sqrt(*nrm2) (zero when the norm is zero: the Krylov space is exhausted)
+__global__ void __launch_bounds__(WG) k_gs_normalize(int n, const double *__restrict__ w,
+                                                     const double *__restrict__ nrm2,
+                                                     double *__restrict__ v) {
+  const double nr = sqrt(*nrm2);
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG)
+    v[i] = nr > 0.0 ? w[i] / nr : 0.0;
+}
+
+// x += Z y (columns 0 .. k-1, in that order)
+__global__ void __launch_bounds__(WG) k_basis_combine(int n, const double *__restrict__ Z,
+                                                      size_t ldz, int k,
+                                                      const double *__restrict__ y,
+                                                      double *__restrict__ x) {
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s = fma(Z[(size_t)j * ldz + i], y[j], s);
+    x[i] += s;
+  }
+}
+
+void launch_gs_dots(hipStream_t s, int n, const double *V, size_t ldv, int k1, const double *w,
+                    double *part, double *out) {
+  const int nb = reduce_blocks(n);
+  hipLaunchKernelGGL(k_gs_dots, dim3(nb, (k1 + GSC - 1) / GSC), dim3(WG), 0, s, n, V, ldv, k1, w,
+                     part);
+  hipLaunchKernelGGL(k_gs_reduce, dim3(k1), dim3(WG), 0, s, nb, part, out);
+}
+
+void launch_gs_update(hipStream_t s, int n, const double *V, size_t ldv, int k1, const double *h,
+                      double *w, double *part) {
+  hipLaunchKernelGGL(k_gs_update, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, V, ldv, k1, h, w, part);
+}
+
+void launch_gs_normalize(hipStream_t s, int n, const double *w, const double *nrm2, double *v) {
+  hipLaunchKernelGGL(k_gs_normalize, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, w, nrm2, v);
+}
+
+void launch_basis_combine(hipStream_t s, int n, const double *Z, size_t ldz, int k, const double *y,
+                          double *x) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_basis_combine, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, Z, ldz, k, y, x);
+}
+
 void launch_copy_scale(hipStream_t s, int n, const double *a, double *b, double alpha) {
   hipLaunchKernelGGL(k_copy_scale, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, a, b, alpha);
 }

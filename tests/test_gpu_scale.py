@@ -111,3 +111,22 @@ def test_fullsize_symmetry_and_pcg(big):
     d = torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)
     assert float(d) < 1e-5
     pm.close()
+
+
+def test_fullsize_gmres_paper_stopping_rule(big):
+    """GMRES with the preconditioner to the paper's 1e-6 reduction: the
+    host recomputes the residual of the returned u; GMRES minimises the
+    residual over a space that contains PCG's iterates, so its step count
+    without a restart cannot exceed PCG's."""
+    w, A, pc = big
+    say("gauss1024 gmres")
+    f = torch.tensor(w.b, device="cuda")
+    u, info = pc.gmres(f, rtol=1e-6, restart=64, maxit=500)
+    torch.cuda.synchronize()
+    uh = u.cpu().numpy()
+    rel = np.linalg.norm(w.b - A @ uh) / np.linalg.norm(w.b)
+    assert info["converged"] == 1 and rel <= 1e-6 * 1.001, (info, rel)
+    assert abs(rel - info["relres_true"]) <= 1e-3 * rel
+    _, cg = pc.pcg(f, 1e-6, 500)
+    if info["restarts"] == 0:
+        assert info["iterations"] <= cg["iterations"], (info["iterations"], cg["iterations"])
