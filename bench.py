@@ -14,8 +14,10 @@ arrays are included.
 
 Prints one JSON line (rank 0, N = 1 only).  Besides the contract fields it
 carries `roofline` (the dominant PCG kernel), `spmv` (amsp_spmv alone, warm and
-with the MALL flushed between calls, outside the timed steps) and
-`cpu_baseline` (the oracle on a bounded sample, on the host cores).
+with the MALL flushed between calls, outside the timed steps), `rtol_1e-6`
+(the paper's own solver setting: GMRES(30) with the preconditioner to a 1e-6
+reduction, and PCG to the same, outside the timed steps) and `cpu_baseline`
+(the oracle on a bounded sample, on the host cores).
 """
 from __future__ import annotations
 
@@ -207,6 +209,34 @@ def traffic_from_profile():
 TRAFFIC_SOURCES = ("k_apply.hip", "k_common.h", "amsp_consts.h", "amsp_internal.h")
 
 
+def gmres_measure(P, torch, w, f, forms, sums):
+    """The paper's own solver configuration (Section 5): GMRES with the
+    preconditioner, restarted every 30 steps, until the residual has dropped
+    by 1e-6; PCG to the same 1e-6 on the same handle for comparison.  One
+    untimed solve first; solve times by host clock around synchronised calls.
+    time_to_solution_ms adds the form's median setup with inputs resident."""
+    out = {}
+    for prec in forms:
+        pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec)
+        rec = {}
+        for name, call in (("gmres", lambda: pc.gmres(f, rtol=1e-6, restart=30, maxit=2000)),
+                           ("pcg", lambda: pc.pcg(f, 1e-6, 2000))):
+            call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = call()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            rec[name] = {"iterations": int(info["iterations"]), "restarts": int(info["restarts"]),
+                         "solve_ms": round(ms, 3), "relres_true": float(f"{info['relres_true']:.4g}"),
+                         "time_to_solution_ms": round(sums[prec]["setup_ms"]
+                                                      - sums[prec]["input_upload_ms"] + ms, 3)}
+        pc.close()
+        out[prec] = rec
+        log(f"[{prec}] rtol 1e-6: gmres {rec['gmres']}, pcg {rec['pcg']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +338,8 @@ def main():
     }
     log("spmv alone ...")
     line["spmv"] = spmv_measure(P, torch, w)
+    log("paper's stopping rule (GMRES(30) and PCG to 1e-6) ...")
+    line["rtol_1e-6"] = gmres_measure(P, torch, w, f, forms, sums)
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(w, sums[head]["iterations"])
