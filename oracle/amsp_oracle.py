@@ -184,6 +184,7 @@ class Setup:
     A0_chol: object
     nev: int
     overlap: int
+    A0_pinv: np.ndarray | None = None  # singular problems: the pseudo-inverse of A0
 
     @property
     def nc(self) -> int:
@@ -194,7 +195,11 @@ class Setup:
 
 
 def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
-          local_solves=True) -> Setup:
+          local_solves=True, singular=False) -> Setup:
+    """singular=True: A is positive semidefinite with a null space (the
+    paper's homogeneous Neumann problem, Section 5); the coarse term then
+    uses the pseudo-inverse of A0, as the two-level operator of Section 3.1
+    is written."""
     A = sp.csr_matrix(A)
     validate(A, part, nparts)
     if nev < 0:
@@ -221,15 +226,28 @@ def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
         lams.append(lam)
         psis.append(psi)
     R0T = prolongation(n, regions, psis, mult, pou)
+    A0p = None
     if R0T.shape[1] > 0:
         A0 = coarse_matrix(A, R0T)
-        try:
-            A0c = sla.cho_factor(A0, lower=True)
-        except np.linalg.LinAlgError as e:
-            raise OracleError("coarse matrix not SPD") from e
+        if singular:
+            A0c, A0p = None, pseudo_inverse(A0)
+        else:
+            try:
+                A0c = sla.cho_factor(A0, lower=True)
+            except np.linalg.LinAlgError as e:
+                raise OracleError("coarse matrix not SPD") from e
     else:
         A0, A0c = np.zeros((0, 0)), None
-    return Setup(n, regions, mult, chol, lams, psis, R0T, A0, A0c, nev, overlap)
+    return Setup(n, regions, mult, chol, lams, psis, R0T, A0, A0c, nev, overlap, A0p)
+
+
+def pseudo_inverse(M: np.ndarray, rtol: float = 1e-10) -> np.ndarray:
+    """Moore-Penrose inverse of a symmetric positive semidefinite matrix from
+    its eigendecomposition: eigenvalues below rtol * the largest count as
+    zero."""
+    w, Q = np.linalg.eigh(M)
+    keep = w > rtol * w.max()
+    return (Q[:, keep] / w[keep]) @ Q[:, keep].T
 
 
 def local_part(st: Setup, r: np.ndarray) -> np.ndarray:
@@ -243,6 +261,8 @@ def coarse_part(st: Setup, r: np.ndarray) -> np.ndarray:
     if st.nc == 0:
         return np.zeros_like(r)
     c = st.R0T.T @ r
+    if st.A0_pinv is not None:
+        return st.R0T @ (st.A0_pinv @ c)
     return st.R0T @ sla.cho_solve(st.A0_chol, c)
 
 

@@ -443,3 +443,67 @@ def test_gmres_restarted_history_and_true_residual():
     u = spla.spsolve(A.tocsc(), w.b)
     assert np.linalg.norm(A @ res.x - w.b) <= 1e-6 * np.linalg.norm(w.b)
     assert np.linalg.norm(res.x - u) / np.linalg.norm(u) < 1e-3
+
+
+# ------------------------------------------------ Neumann-singular problem ----
+def _neumann_setup():
+    w = W.get("neumann64")
+    A = w.A.to_scipy()
+    return w, A, O.setup(A, w.part, w.nparts, w.nev, w.overlap, singular=True)
+
+
+def test_neumann_matrix_null_space():
+    """Without Dirichlet faces every row sums to zero (the constant vector is
+    in the null space) and the source is consistent."""
+    w, A, _ = _neumann_setup()
+    assert np.abs(A @ np.ones(w.n)).max() <= 1e-10 * np.abs(A.diagonal()).max()
+    assert abs(w.b.sum()) <= 1e-12 * np.abs(w.b).sum()
+
+
+def test_neumann_coarse_null_space_is_the_constant():
+    """A0 = R0 A R0^T is singular exactly along the c with R0^T c = 1: every
+    region's first mode is constant and the partition of unity sums to one."""
+    w, A, st = _neumann_setup()
+    ev, Q = np.linalg.eigh(st.A0)
+    assert ev[0] <= 1e-12 * ev[-1] and ev[1] > 1e-6 * ev[-1], ev[:3]
+    v = st.R0T @ Q[:, 0]
+    np.testing.assert_allclose(v, v.mean(), rtol=0, atol=1e-8 * np.abs(v).max())
+
+
+def test_pseudo_inverse_penrose_conditions():
+    """The four Penrose conditions, and agreement with the library's pinv."""
+    _, _, st = _neumann_setup()
+    M, X = st.A0, st.A0_pinv
+    s = np.abs(M).max()
+    assert np.abs(M @ X @ M - M).max() <= 1e-9 * s
+    assert np.abs(X @ M @ X - X).max() <= 1e-9 * np.abs(X).max()
+    assert np.abs(M @ X - (M @ X).T).max() <= 1e-9
+    assert np.abs(X @ M - (X @ M).T).max() <= 1e-9
+    ref = np.linalg.pinv(M, rcond=1e-10, hermitian=True)
+    assert np.abs(X - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def test_neumann_preconditioner_spd_on_the_range():
+    """On vectors orthogonal to the null space the preconditioner with the
+    pseudo-inverse is symmetric and positive."""
+    w, A, st = _neumann_setup()
+    rng = np.random.default_rng(21)
+    for _ in range(3):
+        x, y = rng.standard_normal(w.n), rng.standard_normal(w.n)
+        x -= x.mean()
+        y -= y.mean()
+        mx, my = st.apply(x), st.apply(y)
+        assert abs(x @ my - y @ mx) <= 1e-10 * np.linalg.norm(x) * np.linalg.norm(my)
+        assert x @ mx > 0
+
+
+def test_neumann_pcg_matches_grounded_direct_solve():
+    """PCG on the consistent singular system reaches rtol; modulo the null
+    space its solution is the direct solution with one dof grounded."""
+    w, A, st = _neumann_setup()
+    res = O.pcg(A, w.b, st.apply, rtol=1e-10)
+    assert res.converged and res.relres_true <= 1e-9
+    Ag = A[1:, 1:].tocsc()
+    ug = np.concatenate([[0.0], spla.spsolve(Ag, w.b[1:])])
+    a, b = res.x - res.x.mean(), ug - ug.mean()
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-6

@@ -90,6 +90,22 @@ def layered(n: int = 128, nparts: int = 4096, overlap: int = 1, nev: int = 8,
     return Workload(f"layered{n}", A, b, part, nparts, overlap, nev, kx, (n, n, n))
 
 
+def neumann(nx: int = 64, nparts: int = 16, overlap: int = 1, nev: int = 4,
+            contrast: float = 1e4, nchan: int = 8, seed_key: int = 5) -> Workload:
+    """The paper's boundary condition (Section 5: homogeneous Neumann): the
+    channel field of `channels` without Dirichlet faces, so A is singular
+    with the constant vector as its null space, and a source with zero mean
+    (f ~ N(0, 1) minus its mean) so that A u = f is consistent."""
+    rng_geo, rng_src, _, _ = _streams(seed_key)
+    kappa = darcy.channel_field_2d(nx, nchan, 2, contrast, rng_geo)
+    A = darcy.tpfa_matrix(kappa, neumann=True)
+    src = rng_src.standard_normal((nx, nx))
+    b = darcy.rhs_from_source(src - src.mean())
+    b -= b.mean()
+    part = partition(A.row_ptr, A.col_idx, nparts)
+    return Workload(f"neumann{nx}", A, b, part, nparts, overlap, nev, kappa, (nx, nx))
+
+
 @functools.lru_cache(maxsize=8)
 def get(name: str) -> Workload:
     """Workloads by name; cached per process."""
@@ -103,6 +119,9 @@ def get(name: str) -> Workload:
         nx = int(name[5:])
         nparts = max(4, (nx * nx) // 1024)
         return gauss_inclusions(nx=nx, nparts=nparts)
+    if name.startswith("neumann"):
+        nx = int(name[7:])
+        return neumann(nx=nx, nparts=max(4, (nx * nx) // 256))
     if name.startswith("channels"):
         nx = int(name[8:])
         return channels(nx=nx, nparts=max(4, (nx * nx) // 256))

@@ -54,11 +54,13 @@ def _harm(a, b):
     return 2.0 * a * b / (a + b)
 
 
-def tpfa_matrix(kx: np.ndarray, kz: np.ndarray | None = None) -> CSR:
+def tpfa_matrix(kx: np.ndarray, kz: np.ndarray | None = None, neumann: bool = False) -> CSR:
     """Assemble the TPFA matrix for a 2D (nx, ny) or 3D (nx, ny, nz) field.
 
     kx is indexed [ix, iy] or [ix, iy, iz]; kx is used for x and y faces and
-    kz (default kx) for z faces.
+    kz (default kx) for z faces.  neumann=True drops the Dirichlet boundary
+    faces (homogeneous Neumann problem: every row sums to zero and the
+    constant vector spans the null space).
     """
     d = kx.ndim
     shape = kx.shape
@@ -87,7 +89,7 @@ def tpfa_matrix(kx: np.ndarray, kz: np.ndarray | None = None) -> CSR:
         np.add.at(diag, lo, t)
         np.add.at(diag, hi, t)
         # Dirichlet faces on both ends of this axis
-        for end in (0, shape[ax_field] - 1):
+        for end in ((0, shape[ax_field] - 1) if not neumann else ()):
             b = np.take(idx, [end], axis=arr_axis).ravel()
             np.add.at(diag, b, scale * 2.0 * kk[b])
     rows.append(np.arange(n))
