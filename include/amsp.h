@@ -97,6 +97,14 @@ typedef struct {
                             /* 0x1F: all.  Each timed launch adds two event records.     */
   int32_t timing_stride;    /* time every timing_stride-th launch of a class (>= 1)      */
   void *stream;             /* hipStream_t                                               */
+  int32_t singular;         /* 1: A is singular with the constant vector as its null     */
+                            /* space (homogeneous Neumann problem, Section 5).  The      */
+                            /* coarse term is then the pseudo-inverse of A0 (Section     */
+                            /* 3.1) on residuals orthogonal to the constants, applied as */
+                            /* (A0 + alpha u u^T)^{-1} with u = R0 1, alpha = tr A0/u.u; */
+                            /* it differs from A0^+ only by a constant vector, which A   */
+                            /* annihilates.  f must then sum to zero; the solvers return */
+                            /* a solution determined up to a constant.  Default 0.       */
 } amsp_options;
 
 typedef struct {

@@ -63,7 +63,8 @@ class _Options(ctypes.Structure):
                 ("eig_maxit", ctypes.c_int32), ("eig_shift", ctypes.c_double),
                 ("chunk", ctypes.c_int32), ("flexible", ctypes.c_int32),
                 ("keep_a0", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("timing_stride", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("timing_stride", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("singular", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -226,7 +227,8 @@ class Preconditioner:
                  precision: str = "fp64", pou: int = 0, local_order: str = "rcm",
                  dense_tiles: bool = False, eig_tol: float = 0.0, eig_maxit: int = 80,
                  eig_shift: float = 1e-4, chunk: int = 8, flexible: int = -1,
-                 keep_a0: bool = False, timing=False, timing_stride: int = 1, stream=None):
+                 keep_a0: bool = False, timing=False, timing_stride: int = 1, stream=None,
+                 singular: bool = False):
         torch = _torch()
         self._h = None
         self._keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
@@ -247,6 +249,7 @@ class Preconditioner:
         # timing: True -> every kernel class, or an int bit mask of classes
         o.timing = 0x1F if timing is True else int(timing)
         o.timing_stride = max(1, int(timing_stride))
+        o.singular = int(bool(singular))
         if torch.cuda.is_available():
             torch.cuda.init()  # the device context exists before the library's first HIP call
             torch.cuda.synchronize()

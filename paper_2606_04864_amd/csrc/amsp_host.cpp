@@ -297,6 +297,7 @@ extern "C" void amsp_default_options(amsp_options *opt) {
   opt->timing = 0;
   opt->timing_stride = 1;
   opt->stream = nullptr;
+  opt->singular = 0;
 }
 
 static amsp_status sync_status(amsp_handle *h, const int *dstatus, int N, int mask, int &first_bad) {
@@ -713,6 +714,15 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       ALLOC(h->a0keep, double, (size_t)T0 * T0 * TE);
       HIP_TRY(hipMemcpyAsync(h->a0keep, A0t, (size_t)T0 * T0 * TE * sizeof(double),
                              hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (h->opt.singular) {  // pseudo-inverse on the consistent residuals
+      double *u1, *alpha;
+      ALLOC(u1, double, h->nc);
+      ALLOC(alpha, double, 1);
+      launch_singular_regularize(h->stream, p, h->phi64, A0t, T0, h->nc, u1, alpha);
+      HIP_TRY(hipGetLastError());
+      h->mem.free_one(u1);  // waits for the stream
+      h->mem.free_one(alpha);
     }
     double t5 = now_ms();
     // Tiled right-looking Cholesky with lookahead.  Main stream: diagonal

@@ -198,6 +198,10 @@ void launch_apply_A_to_basis(hipStream_t s, const Plan &p, const CoarsePlan &c,
 void launch_pair_products(hipStream_t s, const Plan &p, const CoarsePlan &c, const double *phi,
                           const double *W, double *A0t, int T0);
 void launch_symmetrize_tiles(hipStream_t s, double *A0t, int T0, int nc);
+// Singular problems (null space = constants): u = R0 1 (u holds nc doubles),
+// alpha = trace(A0) / u.u, A0 += alpha u u^T.
+void launch_singular_regularize(hipStream_t s, const Plan &p, const double *phi, double *A0t,
+                                int T0, int nc, double *u, double *alpha);
 void launch_dense_potrf_diag(hipStream_t s, double *A0t, int T0, int k, double *dinv, int *status);
 void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const double *dinv);
 // Trailing update of Cholesky step k split for lookahead: the next tile

@@ -95,6 +95,53 @@ __global__ void k_symmetrize(double *__restrict__ A0t, int T0, int nc) {
   }
 }
 
+// ------------------------------------- singular problems: A0 + alpha u u^T ---
+// When A's null space is the constant vector (homogeneous Neumann problem),
+// A0 = R0 A R0^T is singular along the c with R0^T c = 1.  The coarse term is
+// applied with (A0 + alpha u u^T)^{-1}, u = R0 1: for any b = R0 r with
+// 1.r = 0 this is A0^+ b plus a multiple of c, whose prolongation is a
+// constant vector that A annihilates.
+// u[coff_i + k] = sum over the region's rows of phi_i[:, k] (R0 1).
+__global__ void __launch_bounds__(WG) k_basis_colsum(Plan p, const double *__restrict__ phi,
+                                                     double *__restrict__ u) {
+  __shared__ double sh[WG / 64];
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, m = p.mi[i], nev = p.nev;
+  for (int k = 0; k < m; ++k) {  // uniform
+    double acc = 0.0;
+    for (int l = threadIdx.x; l < ni; l += WG) acc += phi[(size_t)(r0 + l) * nev + k];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) u[p.coff[i] + k] = t;
+  }
+}
+
+// alpha = trace(A0) / u.u (so that alpha u u^T is on A0's scale); one workgroup
+__global__ void __launch_bounds__(WG) k_rank1_scale(const double *__restrict__ A0t, int T0, int nc,
+                                                    const double *__restrict__ u,
+                                                    double *__restrict__ alpha) {
+  __shared__ double sh[WG / 64];
+  double tr = 0.0, uu = 0.0;
+  for (int k = threadIdx.x; k < nc; k += WG) {
+    tr += A0t[a0_index(k, k, T0)];
+    uu = fma(u[k], u[k], uu);
+  }
+  tr = block_sum(tr, sh);
+  uu = block_sum(uu, sh);
+  if (threadIdx.x == 0) *alpha = uu > 0.0 ? tr / uu : 0.0;
+}
+
+// A0 += alpha u u^T on every stored tile (entries of the padding untouched)
+__global__ void k_rank1_update(double *__restrict__ A0t, int T0, int nc,
+                               const double *__restrict__ u, const double *__restrict__ alpha) {
+  const size_t npad = (size_t)T0 * TS;
+  const double a = *alpha;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < npad * npad;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int R = (int)(e / npad), C = (int)(e % npad);
+    if (R < nc && C < nc) A0t[a0_index(R, C, T0)] += a * u[R] * u[C];
+  }
+}
+
 // ------------------------------------------------- dense tiled Cholesky ---
 __device__ __forceinline__ double *tile_ptr(double *A, int T0, int I, int J) {
   return A + ((size_t)I * T0 + J) * TE;
@@ -287,6 +334,16 @@ void launch_pair_products(hipStream_t s, const Plan &p, const CoarsePlan &c, con
                           const double *W, double *A0t, int T0) {
   if (c.npairs == 0) return;
   hipLaunchKernelGGL(k_pair_products, dim3(c.npairs), dim3(WG), 0, s, p, c, phi, W, A0t, T0);
+}
+
+void launch_singular_regularize(hipStream_t s, const Plan &p, const double *phi, double *A0t,
+                                int T0, int nc, double *u, double *alpha) {
+  hipLaunchKernelGGL(k_basis_colsum, dim3(p.N), dim3(WG), 0, s, p, phi, u);
+  hipLaunchKernelGGL(k_rank1_scale, dim3(1), dim3(WG), 0, s, A0t, T0, nc, u, alpha);
+  size_t tot = (size_t)T0 * TS * T0 * TS;
+  size_t b = (tot + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  hipLaunchKernelGGL(k_rank1_update, dim3((unsigned)b), dim3(WG), 0, s, A0t, T0, nc, u, alpha);
 }
 
 void launch_symmetrize_tiles(hipStream_t s, double *A0t, int T0, int nc) {
