@@ -185,21 +185,30 @@ class Setup:
     nev: int
     overlap: int
     A0_pinv: np.ndarray | None = None  # singular problems: the pseudo-inverse of A0
+    A: sp.csr_matrix | None = None      # kept for the multiplicative cycle
+    cycle: str = "additive"
+    omega: float = 1.0                  # smoother weight of the multiplicative cycle
 
     @property
     def nc(self) -> int:
         return self.R0T.shape[1]
 
     def apply(self, r: np.ndarray) -> np.ndarray:
-        return apply(self, r)
+        return apply(self, r) if self.cycle == "additive" else apply_multiplicative(self, r)
 
 
 def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
-          local_solves=True, singular=False) -> Setup:
+          local_solves=True, singular=False, cycle="additive", omega=None) -> Setup:
     """singular=True: A is positive semidefinite with a null space (the
     paper's homogeneous Neumann problem, Section 5); the coarse term then
     uses the pseudo-inverse of A0, as the two-level operator of Section 3.1
-    is written."""
+    is written.
+
+    cycle="multiplicative": the symmetric two-grid cycle of the paper's
+    two-grid algorithm and Section 4 (pre-smoothing, coarse correction,
+    post-smoothing) with the damped additive Schwarz smoother
+    omega * sum_i R_i^T A_i^{-1} R_i; omega defaults to 1 / (the largest
+    number of regions containing one dof)."""
     A = sp.csr_matrix(A)
     validate(A, part, nparts)
     if nev < 0:
@@ -238,7 +247,10 @@ def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
                 raise OracleError("coarse matrix not SPD") from e
     else:
         A0, A0c = np.zeros((0, 0)), None
-    return Setup(n, regions, mult, chol, lams, psis, R0T, A0, A0c, nev, overlap, A0p)
+    if cycle not in ("additive", "multiplicative"):
+        raise OracleError("cycle must be additive or multiplicative")
+    om = float(omega) if omega is not None else 1.0 / float(mult.max())
+    return Setup(n, regions, mult, chol, lams, psis, R0T, A0, A0c, nev, overlap, A0p, A, cycle, om)
 
 
 def pseudo_inverse(M: np.ndarray, rtol: float = 1e-10) -> np.ndarray:
@@ -269,6 +281,16 @@ def coarse_part(st: Setup, r: np.ndarray) -> np.ndarray:
 def apply(st: Setup, r: np.ndarray) -> np.ndarray:
     """M^{-1} r: additive local solves plus the coarse correction."""
     return local_part(st, r) + coarse_part(st, r)
+
+
+def apply_multiplicative(st: Setup, r: np.ndarray) -> np.ndarray:
+    """One symmetric two-grid cycle from x = 0 for A x = r: x1 = S r,
+    x2 = x1 + C (r - A x1), x3 = x2 + S (r - A x2), with the smoother
+    S = omega * (local solves) and C = R0^T A0^{-1} R0."""
+    A = st.A
+    x = st.omega * local_part(st, r)
+    x = x + coarse_part(st, r - A @ x)
+    return x + st.omega * local_part(st, r - A @ x)
 
 
 # --------------------------------------------------------------------------
