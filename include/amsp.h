@@ -105,6 +105,14 @@ typedef struct {
                             /* it differs from A0^+ only by a constant vector, which A   */
                             /* annihilates.  f must then sum to zero; the solvers return */
                             /* a solution determined up to a constant.  Default 0.       */
+  int32_t cycle;            /* 0: additive two-level operator (default);                 */
+                            /* 1: symmetric multiplicative two-grid cycle (the paper's   */
+                            /* two-grid algorithm analysed in Section 4): x1 = W r,      */
+                            /* x2 = x1 + C (r - A x1), z = x2 + W (r - A x2), with the   */
+                            /* smoother W = w sum_i R_i^T A_i^{-1} R_i and C the coarse  */
+                            /* term; twice the local solves and two more SpMVs per apply */
+  double smoother_weight;   /* w of cycle 1; 0 (default): 1 / (largest number of regions */
+                            /* containing one dof), which keeps the cycle SPD            */
 } amsp_options;
 
 typedef struct {

@@ -64,7 +64,8 @@ class _Options(ctypes.Structure):
                 ("chunk", ctypes.c_int32), ("flexible", ctypes.c_int32),
                 ("keep_a0", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("timing_stride", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("singular", ctypes.c_int32)]
+                ("singular", ctypes.c_int32), ("cycle", ctypes.c_int32),
+                ("smoother_weight", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -228,7 +229,7 @@ class Preconditioner:
                  dense_tiles: bool = False, eig_tol: float = 0.0, eig_maxit: int = 80,
                  eig_shift: float = 1e-4, chunk: int = 8, flexible: int = -1,
                  keep_a0: bool = False, timing=False, timing_stride: int = 1, stream=None,
-                 singular: bool = False):
+                 singular: bool = False, cycle: str = "additive", smoother_weight: float = 0.0):
         torch = _torch()
         self._h = None
         self._keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
@@ -250,6 +251,8 @@ class Preconditioner:
         o.timing = 0x1F if timing is True else int(timing)
         o.timing_stride = max(1, int(timing_stride))
         o.singular = int(bool(singular))
+        o.cycle = {"additive": 0, "multiplicative": 1}[cycle]
+        o.smoother_weight = float(smoother_weight)
         if torch.cuda.is_available():
             torch.cuda.init()  # the device context exists before the library's first HIP call
             torch.cuda.synchronize()

@@ -156,6 +156,10 @@ struct amsp_handle {
   double *lam = nullptr;   // N*(nev+1)
   // coarse
   double *a0keep = nullptr;  // copy of A0 tiles before factorisation (introspection)
+  // multiplicative cycle: work vectors and the smoother weight
+  double *mq = nullptr, *mt = nullptr, *mc = nullptr;
+  double omega = 1.0;
+  int max_mult = 1;
   double *W0 = nullptr;
   float *W0f = nullptr;
   // apply scratch
@@ -321,6 +325,7 @@ struct CouplingDev {
   int npairs = 0;
   int *pair_i = nullptr, *pair_j = nullptr, *pair_ptr = nullptr, *pair_l = nullptr,
       *pair_e = nullptr;
+  int max_mult = 1;  // largest number of regions containing one dof
 };
 
 static bool upload_coupling(amsp_handle *h, hipStream_t stream, CouplingDev &d);
@@ -420,6 +425,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     Plan &pl = h->plan;
     CoarsePlan &cp = h->cplan;
     pl.mult = d.mult;
+    h->max_mult = d.max_mult;
     h->inv_ptr = d.inv_ptr;
     h->inv_sd = d.inv_sd;
     h->inv_loc = d.inv_loc;
@@ -858,6 +864,12 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   HIP_TRY(hipMemsetAsync(h->tvec, 0, ncp * sizeof(double), h->stream));
   ALLOC(h->trmv_part, double, (size_t)std::max(1, T0 * T0) * TS);
   ALLOC(h->r, double, h->n);
+  if (h->opt.cycle == 1) {
+    ALLOC(h->mq, double, h->n);
+    ALLOC(h->mt, double, h->n);
+    ALLOC(h->mc, double, h->n);
+    h->omega = h->opt.smoother_weight > 0.0 ? h->opt.smoother_weight : 1.0 / h->max_mult;
+  }
   ALLOC(h->z, double, h->n);
   ALLOC(h->p0, double, h->n);
   ALLOC(h->p1, double, h->n);
@@ -881,6 +893,7 @@ static bool upload_coupling(amsp_handle *h, hipStream_t stream, CouplingDev &d) 
   const HostPlan &P = h->hp;
   bool ok = true;
   d.mult = upload_on(h, stream, P.mult, ok);
+  for (int v : P.mult) d.max_mult = std::max(d.max_mult, v);
   d.inv_ptr = upload_on(h, stream, P.inv_ptr, ok);
   d.inv_sd = upload_on(h, stream, P.inv_sd, ok);
   d.inv_loc = upload_on(h, stream, P.inv_loc, ok);
@@ -911,6 +924,10 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
   if (o.timing_stride < 1) o.timing_stride = 1;
   if (!(o.eig_shift > 0.0)) {
     g_setup_error = "eig_shift must be positive";
+    return AMSP_ERR_ARG;
+  }
+  if (o.cycle < 0 || o.cycle > 1 || !(o.smoother_weight >= 0.0) || !std::isfinite(o.smoother_weight)) {
+    g_setup_error = "cycle must be 0 or 1 and smoother_weight finite and >= 0";
     return AMSP_ERR_ARG;
   }
   std::string msg;
@@ -982,6 +999,12 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
   const bool mixed = h->opt.precision != AMSP_FP64;
   const bool bf = h->opt.precision == AMSP_MIXED_BF16;
+  if (!do_local && !do_coarse) {  // coarse part asked for, but no coarse space
+    launch_fill(h->stream, h->n, z, 0.0);
+    if (partial_rz) launch_fill(h->stream, reduce_blocks(h->n), partial_rz, 0.0);
+    HIP_TRY(hipGetLastError());
+    return AMSP_OK;
+  }
   hipEvent_t e0, e1;
   int tk = tpair(h, 1, &e0, &e1);
   if (!mixed) {
@@ -1030,11 +1053,37 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   return AMSP_OK;
 }
 
+// z = M^{-1} r with the handle's cycle: the additive operator, or one
+// symmetric two-grid cycle x1 = w S r, x2 = x1 + C (r - A x1),
+// z = x2 + w S (r - A x2) from the same local-solve and coarse kernels.
+static amsp_status apply_prec(amsp_handle *h, const double *r, double *z, double *partial_rz,
+                              const int *done) {
+  if (h->opt.cycle != 1) return apply_one(h, r, z, 3, partial_rz, done);
+  const int n = h->n;
+  hipStream_t s = h->stream;
+  amsp_status st = apply_one(h, r, z, 1, nullptr, done);
+  if (st != AMSP_OK) return st;
+  launch_scale_done(s, n, h->omega, z, done);
+  launch_spmv_sell(s, n, h->sptr, h->scol, h->sval, z, h->mq, done);
+  launch_sub_done(s, n, r, h->mq, h->mt, done);
+  if ((st = apply_one(h, h->mt, h->mc, 2, nullptr, done)) != AMSP_OK) return st;
+  launch_axpy_dot(s, n, 1.0, h->mc, z, nullptr, nullptr, done);
+  launch_spmv_sell(s, n, h->sptr, h->scol, h->sval, z, h->mq, done);
+  launch_sub_done(s, n, r, h->mq, h->mt, done);
+  if ((st = apply_one(h, h->mt, h->mc, 1, nullptr, done)) != AMSP_OK) return st;
+  launch_axpy_dot(s, n, h->omega, h->mc, z, partial_rz ? r : nullptr, partial_rz, done);
+  HIP_TRY(hipGetLastError());
+  return AMSP_OK;
+}
+
 extern "C" amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
                                         int32_t nrhs, int32_t parts) {
   if (!h || !r_dev || !z_dev || nrhs < 1 || parts < 1 || parts > 3) return AMSP_ERR_ARG;
   for (int k = 0; k < nrhs; ++k) {
-    amsp_status s = apply_one(h, r_dev + (size_t)k * h->n, z_dev + (size_t)k * h->n, parts, nullptr, nullptr);
+    const double *rk = r_dev + (size_t)k * h->n;
+    double *zk = z_dev + (size_t)k * h->n;
+    amsp_status s = parts == 3 ? apply_prec(h, rk, zk, nullptr, nullptr)
+                               : apply_one(h, rk, zk, parts, nullptr, nullptr);
     if (s != AMSP_OK) return s;
   }
   return AMSP_OK;
@@ -1147,7 +1196,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
       // z = M^{-1} r with r.z partials; r.r partials; p_old = 0
       h->cur_t = -1;
       launch_dot(h->stream, n, h->r, h->r, h->part_d, nullptr);
-      amsp_status s = apply_one(h, h->r, h->z, 3, h->part_b, nullptr);
+      amsp_status s = apply_prec(h, h->r, h->z, h->part_b, nullptr);
       if (s != AMSP_OK) return s;
       launch_fill(h->stream, n, h->p0, 0.0);
       launch_pcg_init(h->stream, h->st, h->part_d, nb, h->part_b, nb, fresh ? rtol : -1.0, maxit);
@@ -1185,7 +1234,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
           launch_cg_update(h->stream, n, x, h->r, pnew, h->q, h->st, h->part_a, t, h->part_d,
                            h->opt.flexible ? h->z : nullptr, h->part_c);
           tstop(h, 4, tk);
-          s = apply_one(h, h->r, h->z, 3, h->part_b, done);
+          s = apply_prec(h, h->r, h->z, h->part_b, done);
           if (s != AMSP_OK) return s;
           std::swap(pold, pnew);
           ++t;
@@ -1329,7 +1378,7 @@ extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u
       int k = 0;
       for (int j = 0; j < m; ++j) {
         double *vj = V + (size_t)j * ld, *zj = Z + (size_t)j * ld;
-        amsp_status st = apply_one(h, vj, zj, 3, nullptr, nullptr);
+        amsp_status st = apply_prec(h, vj, zj, nullptr, nullptr);
         if (st != AMSP_OK) {
           release();
           return st;

@@ -61,7 +61,14 @@ void launch_cg_dir(hipStream_t s, int n, const long long *sptr, const int *scol,
                    const double *part_rzo, int t, int first, int flexible);
 // y = A x on the sliced copy (amsp_spmv).
 void launch_spmv_sell(hipStream_t s, int n, const long long *sptr, const int *scol,
-                      const double *sval, const double *x, double *y);
+                      const double *sval, const double *x, double *y, const int *done = nullptr);
+// Multiplicative cycle steps (all return at once when *done is set):
+// x *= a; t = r - q; y += a x with optional partial sums of r.y.
+void launch_scale_done(hipStream_t s, int n, double a, double *x, const int *done);
+void launch_sub_done(hipStream_t s, int n, const double *r, const double *q, double *t,
+                     const int *done);
+void launch_axpy_dot(hipStream_t s, int n, double a, const double *x, double *y, const double *r,
+                     double *partial, const int *done);
 // Sliced copy of A: sptr[s] = first entry of slice s (ceil(n/64) + 1 entries).
 void launch_csr_to_sell(hipStream_t s, int n, const int *rp, const int *col, const double *val,
                         const long long *sptr, int *scol, double *sval);

@@ -333,7 +333,9 @@ __global__ void __launch_bounds__(WG) k_spmv_sell(int n, const long long *__rest
                                                   const int *__restrict__ scol,
                                                   const double *__restrict__ sval,
                                                   const double *__restrict__ x,
-                                                  double *__restrict__ y) {
+                                                  double *__restrict__ y,
+                                                  const int *__restrict__ done) {
+  if (done && *done) return;
   constexpr int JU = 8;
   const int i = blockIdx.x * WG + threadIdx.x;
   if (i >= n) return;
@@ -361,10 +363,61 @@ __global__ void __launch_bounds__(WG) k_spmv_sell(int n, const long long *__rest
 }
 
 void launch_spmv_sell(hipStream_t s, int n, const long long *sptr, const int *scol,
-                      const double *sval, const double *x, double *y) {
+                      const double *sval, const double *x, double *y, const int *done) {
   const unsigned b = (unsigned)(((long long)n + WG - 1) / WG);
   if (b == 0) return;
-  hipLaunchKernelGGL(k_spmv_sell, dim3(b), dim3(WG), 0, s, n, sptr, scol, sval, x, y);
+  hipLaunchKernelGGL(k_spmv_sell, dim3(b), dim3(WG), 0, s, n, sptr, scol, sval, x, y, done);
+}
+
+// ------------------------------------------ multiplicative two-grid cycle ---
+// Vector steps of z = x2 + w S (r - A x2), x2 = x1 + C (r - A x1), x1 = w S r;
+// every kernel returns at once after convergence (done flag), like the rest
+// of the CG step.
+__global__ void __launch_bounds__(WG) k_scale_done(int n, double a, double *__restrict__ x,
+                                                   const int *__restrict__ done) {
+  if (done && *done) return;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) x[i] *= a;
+}
+
+__global__ void __launch_bounds__(WG) k_sub_done(int n, const double *__restrict__ r,
+                                                 const double *__restrict__ q,
+                                                 double *__restrict__ t,
+                                                 const int *__restrict__ done) {
+  if (done && *done) return;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) t[i] = r[i] - q[i];
+}
+
+// y += a x; with partial != 0 also the partial sums of r.y
+__global__ void __launch_bounds__(WG) k_axpy_dot(int n, double a, const double *__restrict__ x,
+                                                 double *__restrict__ y,
+                                                 const double *__restrict__ r,
+                                                 double *__restrict__ partial,
+                                                 const int *__restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[WG / 64];
+  double acc = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    const double yi = fma(a, x[i], y[i]);
+    y[i] = yi;
+    if (r) acc = fma(r[i], yi, acc);
+  }
+  if (partial) {
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  }
+}
+
+void launch_scale_done(hipStream_t s, int n, double a, double *x, const int *done) {
+  hipLaunchKernelGGL(k_scale_done, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, a, x, done);
+}
+void launch_sub_done(hipStream_t s, int n, const double *r, const double *q, double *t,
+                     const int *done) {
+  hipLaunchKernelGGL(k_sub_done, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, r, q, t, done);
+}
+void launch_axpy_dot(hipStream_t s, int n, double a, const double *x, double *y, const double *r,
+                     double *partial, const int *done) {
+  hipLaunchKernelGGL(k_axpy_dot, dim3(reduce_blocks(n)), dim3(WG), 0, s, n, a, x, y, r, partial,
+                     done);
 }
 
 // grad[k] = -lambda[row k] * u[col k] over the CSR entries (adjoint of the
