@@ -16,8 +16,10 @@ Prints one JSON line (rank 0, N = 1 only).  Besides the contract fields it
 carries `roofline` (the dominant PCG kernel), `spmv` (amsp_spmv alone, warm and
 with the MALL flushed between calls, outside the timed steps), `rtol_1e-6`
 (the paper's own solver setting: GMRES(30) with the preconditioner to a 1e-6
-reduction, and PCG to the same, outside the timed steps) and `cpu_baseline`
-(the oracle on a bounded sample, on the host cores).
+reduction, and PCG to the same, outside the timed steps),
+`multiplicative_cycle` (the symmetric two-grid cycle as the preconditioner,
+setup + PCG to 1e-8, outside the timed steps) and `cpu_baseline` (the oracle
+on a bounded sample, on the host cores).
 """
 from __future__ import annotations
 
@@ -209,6 +211,34 @@ def traffic_from_profile():
 TRAFFIC_SOURCES = ("k_apply.hip", "k_common.h", "amsp_consts.h", "amsp_internal.h")
 
 
+def cycle_measure(P, torch, w, f, forms):
+    """The multiplicative two-grid cycle (twice the local solves, two more
+    SpMVs per application) against the additive operator: setup and PCG to
+    1e-8, one untimed run then one timed, host clock around synchronised
+    calls."""
+    out = {}
+    for prec in forms:
+        rec = {}
+        for k in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec,
+                         cycle="multiplicative")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = pc.pcg(f, 1e-8, 2000)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            upload = pc.info["phase_ms"][1]
+            pc.close()
+            rec = {"iterations": int(info["iterations"]), "pcg_ms": round((t2 - t1) * 1e3, 3),
+                   "time_to_solution_ms": round((t2 - t0) * 1e3 - upload, 3),
+                   "relres_true": float(f"{info['relres_true']:.4g}")}
+        out[prec] = rec
+        log(f"[{prec}] multiplicative cycle: {rec}")
+    return out
+
+
 def gmres_measure(P, torch, w, f, forms, sums):
     """The paper's own solver configuration (Section 5): GMRES with the
     preconditioner, restarted every 30 steps, until the residual has dropped
@@ -340,6 +370,8 @@ def main():
     line["spmv"] = spmv_measure(P, torch, w)
     log("paper's stopping rule (GMRES(30) and PCG to 1e-6) ...")
     line["rtol_1e-6"] = gmres_measure(P, torch, w, f, forms, sums)
+    log("multiplicative two-grid cycle ...")
+    line["multiplicative_cycle"] = cycle_measure(P, torch, w, f, forms)
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(w, sums[head]["iterations"])
