@@ -176,7 +176,15 @@ amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, int32_t npar
                        int32_t nev, const amsp_options *opt, amsp_handle **out);
 
 /* z = M^{-1} r for nrhs columns (asynchronous on the handle's stream).
- * parts: 3 = both terms, 1 = local solves only, 2 = coarse correction only. */
+ * parts: 3 = both terms, 1 = local solves only, 2 = coarse correction only.
+ * Columns are n apart (column-major).  Two or more columns are taken up to 16
+ * at a time with one pass over the local factor: triangular solves with a
+ * block of right-hand sides, whose diagonal products run on the matrix cores
+ * (the mixed forms then use their f32-stored factor with float64 arithmetic,
+ * so a column can differ from its single-column result at float32 rounding).
+ * The first such call allocates the block workspace, 3 x 128 bytes per padded
+ * local row, kept until amsp_destroy.  With cycle = 1, parts = 3 applies the
+ * cycle column by column. */
 amsp_status amsp_apply(amsp_handle *h, const double *r_dev, double *z_dev, int32_t nrhs);
 amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
                              int32_t nrhs, int32_t parts);

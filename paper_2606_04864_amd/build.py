@@ -25,7 +25,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 
-SOURCES = ["k_krylov.hip", "k_local.hip", "k_apply.hip", "k_eigen.hip", "k_coarse.hip", "amsp_plan.cpp",
+SOURCES = ["k_krylov.hip", "k_local.hip", "k_apply.hip", "k_eigen.hip", "k_coarse.hip", "k_multi.hip",
+           "amsp_plan.cpp",
            "amsp_host.cpp"]
 
 

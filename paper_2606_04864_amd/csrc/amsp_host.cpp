@@ -160,6 +160,11 @@ struct amsp_handle {
   double *mq = nullptr, *mt = nullptr, *mc = nullptr;
   double omega = 1.0;
   int max_mult = 1;
+  // several right-hand sides per pass (allocated on first use): gathered and
+  // solved blocks, region outputs, coarse vectors, and for the mixed forms
+  // the f32 factor in the block solve's layout
+  double *bX = nullptr, *bY = nullptr, *bXN = nullptr, *bC = nullptr, *bT = nullptr;
+  float *dg32 = nullptr, *er32 = nullptr, *ec32 = nullptr;
   double *W0 = nullptr;
   float *W0f = nullptr;
   // apply scratch
@@ -1053,6 +1058,75 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
   return AMSP_OK;
 }
 
+// z_k = M^{-1} r_k (parts as in apply_one) for nr <= EIGP columns, n apart,
+// with one pass over the local factor: the block solve with the Dirichlet
+// factor (f32-stored in the mixed forms, f64 arithmetic), the restriction of
+// all columns, one coarse solve per column, the prolongation and the scatter.
+static amsp_status apply_block(amsp_handle *h, const double *r, double *z, int nr, int parts) {
+  const Plan &p = h->plan;
+  const int n = h->n;
+  hipStream_t s = h->stream;
+  const bool mixed = h->opt.precision != AMSP_FP64;
+  const bool bf = h->opt.precision == AMSP_MIXED_BF16;
+  const int do_local = (parts & 1) ? 1 : 0;
+  const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
+  const size_t rows = (size_t)h->hp.vp_ptr.back();
+  const size_t ncp = (size_t)std::max(1, h->T0 * TS);
+  if (!h->bX) {
+    ALLOC(h->bX, double, rows * EIGP);
+    ALLOC(h->bY, double, rows * EIGP);
+    ALLOC(h->bXN, double, rows * EIGP);
+    ALLOC(h->bC, double, ncp * EIGP);
+    ALLOC(h->bT, double, ncp * EIGP);
+    launch_fill(s, ncp * EIGP, h->bC, 0.0);  // coarse padding stays zero
+  }
+  if (mixed && do_local && !h->dg32) {
+    const size_t nenv = (size_t)h->hp.nenv;
+    ALLOC(h->dg32, float, (size_t)h->ntilerows * DE);
+    ALLOC(h->er32, float, std::max<size_t>(nenv, 1));
+    ALLOC(h->ec32, float, std::max<size_t>(nenv, 1));
+    launch_streams_to_env(s, p, h->ntilerows, h->fst32, h->bst32, h->dg32, h->er32, h->ec32);
+  }
+  launch_gather_multi(s, p, n, nr, r, h->bX);
+  if (do_local) {
+    if (mixed)
+      launch_env_solve_block<float>(s, p, h->dg32, h->er32, h->ec32, h->bX, h->bY, nullptr);
+    else
+      launch_env_solve_block<double>(s, p, h->dg64, h->erow64, h->ecol64, h->bX, h->bY, nullptr);
+  }
+  const void *phi = mixed ? h->phi_lo : (const void *)h->phi64;
+  if (do_coarse) {
+    if (!mixed)
+      launch_restrict_multi<double>(s, p, nr, ncp, (const double *)phi, h->bX, h->bC);
+    else if (!bf)
+      launch_restrict_multi<float>(s, p, nr, ncp, (const float *)phi, h->bX, h->bC);
+    else
+      launch_restrict_multi<__hip_bfloat16>(s, p, nr, ncp, (const __hip_bfloat16 *)phi, h->bX, h->bC);
+    for (int k = 0; k < nr; ++k) {
+      double *ck = h->bC + (size_t)k * ncp, *tk = h->bT + (size_t)k * ncp;
+      if (!mixed) {
+        launch_trmv<double>(s, h->W0, h->T0, ck, h->trmv_part, h->t1, 0, nullptr);
+        launch_trmv<double>(s, h->W0, h->T0, h->t1, h->trmv_part, tk, 1, nullptr);
+      } else {
+        launch_trmv<float>(s, h->W0f, h->T0, ck, h->trmv_part, h->t1, 0, nullptr);
+        launch_trmv<float>(s, h->W0f, h->T0, h->t1, h->trmv_part, tk, 1, nullptr);
+      }
+    }
+  }
+  const double *tcoarse = do_coarse ? h->bT : nullptr;
+  const double *ylocal = do_local ? h->bY : nullptr;
+  if (!mixed)
+    launch_prolong_multi<double>(s, p, nr, ncp, (const double *)phi, tcoarse, ylocal, h->bXN);
+  else if (!bf)
+    launch_prolong_multi<float>(s, p, nr, ncp, (const float *)phi, tcoarse, ylocal, h->bXN);
+  else
+    launch_prolong_multi<__hip_bfloat16>(s, p, nr, ncp, (const __hip_bfloat16 *)phi, tcoarse,
+                                         ylocal, h->bXN);
+  launch_scatter_multi(s, n, nr, h->inv_ptr, h->inv_x, h->bXN, z);
+  HIP_TRY(hipGetLastError());
+  return AMSP_OK;
+}
+
 // z = M^{-1} r with the handle's cycle: the additive operator, or one
 // symmetric two-grid cycle x1 = w S r, x2 = x1 + C (r - A x1),
 // z = x2 + w S (r - A x2) from the same local-solve and coarse kernels.
@@ -1082,6 +1156,15 @@ extern "C" amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, dou
   for (int k = 0; k < nrhs; ++k) {
     const double *rk = r_dev + (size_t)k * h->n;
     double *zk = z_dev + (size_t)k * h->n;
+    // two or more columns: EIGP at a time through the block solve (the
+    // multiplicative cycle keeps the column-by-column path)
+    if (nrhs - k >= 2 && !(h->opt.cycle == 1 && parts == 3)) {
+      const int nr = std::min(EIGP, nrhs - k);
+      amsp_status s = apply_block(h, rk, zk, nr, parts);
+      if (s != AMSP_OK) return s;
+      k += nr - 1;
+      continue;
+    }
     amsp_status s = parts == 3 ? apply_prec(h, rk, zk, nullptr, nullptr)
                                : apply_one(h, rk, zk, parts, nullptr, nullptr);
     if (s != AMSP_OK) return s;

@@ -162,6 +162,25 @@ void launch_scatter_sum_t(hipStream_t s, const Plan &p, int max_ni, int n, const
                           const double *r, double *partial, int do_local, int do_coarse,
                           const int *done);
 
+// ------------------------------------------------------- several columns ---
+// Up to EIGP right-hand sides per pass (k_multi.hip): gather into X (per
+// region npad_i rows of EIGP doubles, local order), restriction of every
+// column into c (columns ncp apart), prolongation + local solution into XN
+// (ascending-global-index layout), scatter into z (columns n apart).
+void launch_gather_multi(hipStream_t s, const Plan &p, int n, int nr, const double *r, double *X);
+template <typename TB>
+void launch_restrict_multi(hipStream_t s, const Plan &p, int nr, size_t ncp, const TB *phi,
+                           const double *X, double *c);
+template <typename TB>
+void launch_prolong_multi(hipStream_t s, const Plan &p, int nr, size_t ncp, const TB *phi,
+                          const double *t, const double *Y, double *XN);
+void launch_scatter_multi(hipStream_t s, int n, int nr, const int *inv_ptr, const int *ix,
+                          const double *XN, double *z);
+// f32 factor of the mixed forms from its streams back into packed diagonal
+// tiles + envelope (the layout of launch_env_solve_block)
+void launch_streams_to_env(hipStream_t s, const Plan &p, int ntilerows, const float *fst,
+                           const float *bst, float *dg, float *er, float *ec);
+
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
 // dst[(sd_ptr[i] + nat[k]) * nev + c] = src[(sd_ptr[i] + k) * nev + c]: the basis

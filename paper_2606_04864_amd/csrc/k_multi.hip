@@ -1,0 +1,161 @@
+// Several right-hand sides at once: z_k = M^{-1} r_k for up to EIGP columns
+// with one pass over the local factors.  With many columns the local solves
+// become triangular solves with a block of right-hand sides, whose diagonal
+// products run on the matrix cores: the same block solve the eigensolver
+// uses (k_env_solve_block), here with the Dirichlet factor of the apply.
+//
+// Layouts: the columns of r and z are n apart (column-major n x nr); the
+// gathered block X and the solved block Y hold, per region, npad_i rows of
+// EIGP doubles in the local (RCM) order at row vp_ptr[i]; XN holds the
+// region outputs (local solve plus coarse prolongation) in the region's
+// ascending-global-index layout, the layout the scatter reads.  Columns nr ..
+// EIGP-1 and padding rows are zero.
+#include "k_common.h"
+
+namespace amsp {
+
+// X[vp_i + l][k] = r_k[dof(l)] for real rows and k < nr, zero otherwise.
+__global__ void __launch_bounds__(WG) k_gather_multi(Plan p, int n, int nr,
+                                                     const double *__restrict__ r,
+                                                     double *__restrict__ X) {
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int v0 = p.vp_ptr[i], npad = p.vp_ptr[i + 1] - v0;
+  for (int e = threadIdx.x; e < npad * EIGP; e += WG) {
+    const int l = e / EIGP, k = e % EIGP;
+    X[(size_t)v0 * EIGP + e] =
+        (l < ni && k < nr) ? r[(size_t)k * n + p.sd_dofs[r0 + l]] : 0.0;
+  }
+}
+
+// Restriction of every column: c_k[coff_i + q] = sum_l phi_i[l][q] X[l][k],
+// one thread per (q, k) of the region, rows in order.  The coarse vectors
+// are ncp apart (their padding stays zero).
+template <typename TB>
+__global__ void __launch_bounds__(WG) k_restrict_multi(Plan p, int nr, size_t ncp,
+                                                       const TB *__restrict__ phi,
+                                                       const double *__restrict__ X,
+                                                       double *__restrict__ c) {
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, m = p.mi[i], nev = p.nev;
+  const int q = threadIdx.x / EIGP, k = threadIdx.x % EIGP;
+  if (q >= m || k >= nr) return;
+  const double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
+  const TB *ph = phi + (size_t)r0 * nev;
+  double acc = 0.0;
+  for (int l = 0; l < ni; ++l) acc = fma(to_d(ph[(size_t)l * nev + q]), Xi[(size_t)l * EIGP + k], acc);
+  c[(size_t)k * ncp + p.coff[i] + q] = acc;
+}
+
+// XN[vp_i + nat(l)][k] = Y[vp_i + l][k] + sum_q phi_i[l][q] t_k[coff_i + q]
+// (without the coarse part when t is null; without the local part when Y is).
+template <typename TB>
+__global__ void __launch_bounds__(WG) k_prolong_multi(Plan p, int nr, size_t ncp,
+                                                      const TB *__restrict__ phi,
+                                                      const double *__restrict__ t,
+                                                      const double *__restrict__ Y,
+                                                      double *__restrict__ XN) {
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, m = p.mi[i], nev = p.nev;
+  const size_t v0 = p.vp_ptr[i];
+  const int co = p.coff[i];
+  for (int e = threadIdx.x; e < ni * EIGP; e += WG) {
+    const int l = e / EIGP, k = e % EIGP;
+    double v = 0.0;
+    if (k < nr) {
+      if (Y) v = Y[(v0 + l) * EIGP + k];
+      if (t) {
+        const TB *ph = phi + (size_t)(r0 + l) * nev;
+#pragma unroll
+        for (int q = 0; q < MAXNEV; ++q)
+          if (q < m) v = fma(to_d(ph[q]), t[(size_t)k * ncp + co + q], v);
+      }
+    }
+    XN[(v0 + p.nat[r0 + l]) * EIGP + k] = v;
+  }
+}
+
+// z_k[j] = sum over the copies of dof j (fixed map order) of XN[copy][k];
+// thread per (dof, column), EIGP consecutive threads share a dof.
+__global__ void __launch_bounds__(WG) k_scatter_multi(int n, int nr, const int *__restrict__ inv_ptr,
+                                                      const int *__restrict__ ix,
+                                                      const double *__restrict__ XN,
+                                                      double *__restrict__ z) {
+  const long long g = (long long)blockIdx.x * WG + threadIdx.x;
+  const int j = (int)(g / EIGP), k = (int)(g % EIGP);
+  if (j >= n || k >= nr) return;
+  double s = 0.0;
+  for (int e = inv_ptr[j]; e < inv_ptr[j + 1]; ++e) s += XN[(size_t)ix[e] * EIGP + k];
+  z[(size_t)k * n + j] = s;
+}
+
+// The mixed forms keep their f32 factor only as the two per-sweep streams;
+// the block solve reads packed diagonal tiles and the envelope (row and
+// column forms).  One workgroup per tile row g copies them back out: the
+// forward block of g is [row-form segments | padding | diagonal tile], the
+// backward block [column-form segments | padding | diagonal tile].
+__global__ void __launch_bounds__(WG) k_streams_to_env(Plan p, const float *__restrict__ fst,
+                                                       const float *__restrict__ bst,
+                                                       float *__restrict__ dg,
+                                                       float *__restrict__ er,
+                                                       float *__restrict__ ec) {
+  const int g = blockIdx.x;
+  const int i = find_segment(p.trow_ptr, p.N, g);
+  const int I = g - p.trow_ptr[i], r0 = I * TS;
+  const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
+  const long long eb = p.ebase[i];
+  {
+    const float *blk = fst + p.sfr[i] + p.sfb[g];
+    const int base = ep[r0], T = ep[r0 + TS] - base, Tp = (T + 3) & ~3;
+    for (int k = threadIdx.x; k < T; k += WG) er[eb + base + k] = blk[k];
+    for (int e = threadIdx.x; e < DE; e += WG) dg[(size_t)g * DE + e] = blk[Tp + e];
+  }
+  {
+    const float *blk = bst + p.sbr[i] + p.sbb[g];
+    const int base = up[r0], T = up[r0 + TS] - base;
+    for (int k = threadIdx.x; k < T; k += WG) ec[eb + base + k] = blk[k];
+  }
+}
+
+// ------------------------------------------------------------- launchers ---
+void launch_streams_to_env(hipStream_t s, const Plan &p, int ntilerows, const float *fst,
+                           const float *bst, float *dg, float *er, float *ec) {
+  if (ntilerows <= 0) return;
+  hipLaunchKernelGGL(k_streams_to_env, dim3(ntilerows), dim3(WG), 0, s, p, fst, bst, dg, er, ec);
+}
+
+void launch_gather_multi(hipStream_t s, const Plan &p, int n, int nr, const double *r, double *X) {
+  hipLaunchKernelGGL(k_gather_multi, dim3(p.N), dim3(WG), 0, s, p, n, nr, r, X);
+}
+
+template <typename TB>
+void launch_restrict_multi(hipStream_t s, const Plan &p, int nr, size_t ncp, const TB *phi,
+                           const double *X, double *c) {
+  hipLaunchKernelGGL((k_restrict_multi<TB>), dim3(p.N), dim3(WG), 0, s, p, nr, ncp, phi, X, c);
+}
+
+template <typename TB>
+void launch_prolong_multi(hipStream_t s, const Plan &p, int nr, size_t ncp, const TB *phi,
+                          const double *t, const double *Y, double *XN) {
+  hipLaunchKernelGGL((k_prolong_multi<TB>), dim3(p.N), dim3(WG), 0, s, p, nr, ncp, phi, t, Y, XN);
+}
+
+void launch_scatter_multi(hipStream_t s, int n, int nr, const int *inv_ptr, const int *ix,
+                          const double *XN, double *z) {
+  const long long tot = (long long)n * EIGP;
+  const unsigned b = (unsigned)((tot + WG - 1) / WG);
+  if (b == 0) return;
+  hipLaunchKernelGGL(k_scatter_multi, dim3(b), dim3(WG), 0, s, n, nr, inv_ptr, ix, XN, z);
+}
+
+#define AMSP_MULTI_INST(TB)                                                                  \
+  template void launch_restrict_multi<TB>(hipStream_t, const Plan &, int, size_t, const TB *, \
+                                          const double *, double *);                          \
+  template void launch_prolong_multi<TB>(hipStream_t, const Plan &, int, size_t, const TB *,  \
+                                         const double *, const double *, double *);
+AMSP_MULTI_INST(double)
+AMSP_MULTI_INST(float)
+AMSP_MULTI_INST(__hip_bfloat16)
+#undef AMSP_MULTI_INST
+
+}  // namespace amsp
