@@ -197,6 +197,13 @@ amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
  * AMSP_ERR_PCG_NOCONV u holds the last iterate and the handle stays valid. */
 amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                      double rtol, int32_t maxit, amsp_info *info);
+/* With nrhs >= 2 (columns n apart) and the additive operator, up to 16
+ * columns run together: one CG recurrence per column, with the stopping rule
+ * above applied per column, sharing every SpMV (matrix entries read once) and
+ * every preconditioner application (the block path of amsp_apply).  The
+ * workspace (4 n doubles per column) is allocated per call from the handle's
+ * cache.  info sums the columns' iterations and reports the worst residuals;
+ * a last single column takes the one-column path. */
 
 /* Restarted GMRES with the preconditioner, the Krylov method of the paper's
  * experiments (Section 5: GMRES preconditioned by the two-level method, run

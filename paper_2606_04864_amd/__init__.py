@@ -307,13 +307,21 @@ class Preconditioner:
         return y
 
     def pcg(self, f, rtol: float = 1e-8, maxit: int = 1000, out=None, raise_on_noconv=True):
-        """Solve A u = f by preconditioned CG; returns (u, info dict)."""
+        """Solve A u = f by preconditioned CG; returns (u, info dict).  f of
+        shape (n, k) solves k systems together (one recurrence per column)."""
         torch = _torch()
         _check_dev(f, "f", self.n)
         u = out if out is not None else torch.empty_like(f)
         inf = _Info()
-        st = _lib.amsp_pcg(self._h, f.data_ptr(), u.data_ptr(), 1, float(rtol), int(maxit),
-                           ctypes.byref(inf))
+        if f.dim() == 2:
+            ff = f.t().contiguous()
+            uu = torch.empty_like(ff)
+            st = _lib.amsp_pcg(self._h, ff.data_ptr(), uu.data_ptr(), f.shape[1], float(rtol),
+                               int(maxit), ctypes.byref(inf))
+            u.copy_(uu.t())
+        else:
+            st = _lib.amsp_pcg(self._h, f.data_ptr(), u.data_ptr(), 1, float(rtol), int(maxit),
+                               ctypes.byref(inf))
         info = {name: getattr(inf, name) for name, _ in _Info._fields_
                 if name not in ("kernel_ms", "kernel_launches")}
         info["kernel_ms"] = list(inf.kernel_ms)

@@ -1235,6 +1235,143 @@ static int64_t bytes_per_iter(const amsp_handle *h) {
   return b;
 }
 
+// PCG on nr <= EIGP columns at once: one CG recurrence per column (the same
+// steps and stopping rule as amsp_pcg), all sharing each SpMV (entries read
+// once) and each preconditioner application (the block path of amsp_apply).
+// Scalars go through the host twice per step.  Converged columns keep
+// alpha = beta = 0.  Adds to the totals in *inf; the history of the last
+// column is kept for amsp_get_pcg_history.
+static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int nr, double rtol,
+                               int maxit, amsp_info &inf) {
+  const int n = h->n;
+  const size_t ld = (size_t)n, tot = ld * nr;
+  hipStream_t s = h->stream;
+  double *R = nullptr, *Z = nullptr, *Pd = nullptr, *Q = nullptr, *part = nullptr, *sc = nullptr;
+  ALLOC(R, double, tot);
+  ALLOC(Z, double, tot);
+  ALLOC(Pd, double, tot);
+  ALLOC(Q, double, tot);
+  ALLOC(part, double, (size_t)256 * EIGP);
+  ALLOC(sc, double, 4 * EIGP);  // [0,16) alpha/beta, [16,32) dots, [32,48) rr
+  auto release = [&]() {
+    for (double *b : {R, Z, Pd, Q, part, sc}) h->mem.free_one(b);
+  };
+  auto to_host = [&](const double *src, double *dst) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dst, src, nr * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  };
+  std::vector<double> f2(nr), rr(nr), rz(nr), dot(nr), coef(nr);
+  std::vector<int> active(nr), its(nr, 0);
+  std::vector<double> hist;
+  launch_fill(s, tot, U, 0.0);
+  HIP_TRY(hipMemcpyAsync(R, F, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_col_dots(s, n, ld, nr, F, F, part, sc + 16);
+  HIP_TRY(to_host(sc + 16, f2.data()));
+  for (int k = 0; k < nr; ++k) {
+    if (!std::isfinite(f2[k])) {
+      release();
+      h->err = "right-hand side not finite";
+      return AMSP_ERR_BREAKDOWN;
+    }
+    rr[k] = f2[k];
+    active[k] = f2[k] > 0.0;
+  }
+  hist.push_back(f2[nr - 1]);
+  amsp_status st = apply_block(h, R, Z, nr, 3);
+  if (st != AMSP_OK) return st;
+  launch_col_dots(s, n, ld, nr, R, Z, part, sc + 16);
+  HIP_TRY(to_host(sc + 16, rz.data()));
+  HIP_TRY(hipMemcpyAsync(Pd, Z, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+  bool breakdown = false;
+  int it = 0;
+  auto any_active = [&]() {
+    for (int v : active)
+      if (v) return true;
+    return false;
+  };
+  while (any_active() && it < maxit) {
+    launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, Pd, Q);
+    launch_col_dots(s, n, ld, nr, Pd, Q, part, sc + 16);
+    HIP_TRY(to_host(sc + 16, dot.data()));
+    for (int k = 0; k < nr; ++k) {
+      coef[k] = 0.0;
+      if (!active[k]) continue;
+      if (!(dot[k] > 0.0) || !std::isfinite(rz[k] / dot[k])) {
+        breakdown = true;
+        active[k] = 0;
+        continue;
+      }
+      coef[k] = rz[k] / dot[k];
+    }
+    HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_col_update(s, n, ld, nr, sc, Pd, Q, U, R, part, sc + 32);
+    ++it;
+    if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) return st;
+    launch_col_dots(s, n, ld, nr, R, Z, part, sc + 16);
+    HIP_TRY(to_host(sc + 32, rr.data()));
+    HIP_TRY(to_host(sc + 16, dot.data()));
+    hist.push_back(rr[nr - 1]);
+    for (int k = 0; k < nr; ++k) {
+      coef[k] = 0.0;
+      if (!active[k]) continue;
+      its[k] = it;
+      if (!std::isfinite(rr[k])) {
+        breakdown = true;
+        active[k] = 0;
+        continue;
+      }
+      if (rr[k] <= rtol * rtol * f2[k]) {
+        active[k] = 0;
+        continue;
+      }
+      coef[k] = dot[k] / rz[k];
+      rz[k] = dot[k];
+    }
+    HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_col_direction(s, n, ld, nr, sc, Z, Pd);
+  }
+  // true residuals f - A u and the attainable floors, per column
+  launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, U, Q);
+  const int nb = reduce_blocks(n);
+  for (int k = 0; k < nr; ++k) {
+    const double fk = std::sqrt(f2[k]);
+    double rt = 0.0, fl = 0.0;
+    if (fk > 0.0) {
+      launch_residual(s, n, F + k * ld, Q + k * ld, R + k * ld, part);
+      launch_sum_partials(s, part, nb, sc + 48 - 1);
+      double r2 = 0.0;
+      HIP_TRY(hipMemcpyAsync(&r2, sc + 47, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      rt = std::sqrt(r2) / fk;
+      if (rt > rtol) {
+        launch_abs_spmv_sq(s, n, h->rowptr, h->col, h->val, U + k * ld, part);
+        launch_sum_partials(s, part, nb, sc + 47);
+        double a2 = 0.0;
+        HIP_TRY(hipMemcpyAsync(&a2, sc + 47, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        fl = DBL_EPSILON * std::sqrt(a2) / fk;
+      }
+    }
+    const bool conv = rt <= std::max(rtol, fl) && std::isfinite(rt);
+    if (!conv) inf.converged = 0;
+    inf.iterations += its[k];
+    inf.relres_true = std::max(inf.relres_true, rt);
+    inf.relres_recursive = std::max(inf.relres_recursive, f2[k] > 0 ? std::sqrt(rr[k] / f2[k]) : 0.0);
+    inf.relres_floor = std::max(inf.relres_floor, fl);
+  }
+  h->hist_len = std::min((int)hist.size(), h->hist_cap);
+  h->hist_f2 = f2[nr - 1];
+  HIP_TRY(hipMemcpyAsync(h->hist, hist.data(), h->hist_len * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  release();
+  if (breakdown) {
+    h->err = "CG breakdown in a column (p.Ap <= 0 or a non-finite value)";
+    return AMSP_ERR_BREAKDOWN;
+  }
+  return AMSP_OK;
+}
+
 extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                                 double rtol, int32_t maxit, amsp_info *info) {
   if (!h || !f_dev || !u_dev || nrhs < 1 || maxit < 0 || !(rtol >= 0.0)) return AMSP_ERR_ARG;
@@ -1243,6 +1380,36 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   amsp_info inf{};
   inf.bytes_per_iter = bytes_per_iter(h);
   inf.local_apply_bytes = local_apply_bytes(h);
+  if (nrhs >= 2 && h->opt.cycle == 0) {  // columns share operator applications
+    if (h->hist_cap < maxit + 2) {
+      if (h->hist) h->mem.free_one(h->hist);
+      h->hist_cap = std::max(maxit + 2, 1024);
+      ALLOC(h->hist, double, h->hist_cap);
+    }
+    const double t0 = now_ms();
+    inf.converged = 1;
+    for (int k0 = 0; k0 < nrhs; k0 += EIGP) {
+      const int nr = std::min(EIGP, nrhs - k0);
+      amsp_status st = nr >= 2 ? pcg_columns(h, f_dev + (size_t)k0 * n, u_dev + (size_t)k0 * n, nr,
+                                             rtol, maxit, inf)
+                               : AMSP_OK;
+      if (nr == 1) {  // a last single column: the one-column path
+        amsp_info one{};
+        st = amsp_pcg(h, f_dev + (size_t)k0 * n, u_dev + (size_t)k0 * n, 1, rtol, maxit, &one);
+        if (st != AMSP_OK && st != AMSP_ERR_PCG_NOCONV) return st;
+        inf.iterations += one.iterations;
+        inf.relres_true = std::max(inf.relres_true, one.relres_true);
+        inf.relres_recursive = std::max(inf.relres_recursive, one.relres_recursive);
+        inf.relres_floor = std::max(inf.relres_floor, one.relres_floor);
+        if (!one.converged) inf.converged = 0;
+        st = AMSP_OK;
+      }
+      if (st != AMSP_OK) return st;
+    }
+    inf.solve_ms = now_ms() - t0;
+    if (info) *info = inf;
+    return inf.converged ? AMSP_OK : AMSP_ERR_PCG_NOCONV;
+  }
   h->timing_active = h->opt.timing != 0;
   h->ev_used = 0;
   h->ev_rec.clear();

@@ -176,6 +176,19 @@ void launch_prolong_multi(hipStream_t s, const Plan &p, int nr, size_t ncp, cons
                           const double *t, const double *Y, double *XN);
 void launch_scatter_multi(hipStream_t s, int n, int nr, const int *inv_ptr, const int *ix,
                           const double *XN, double *z);
+// CG on nr columns ld apart, one recurrence per column: Y = A X (entries
+// read once for all columns); out[k] = A_k . B_k (part: 256 * nr doubles);
+// x_k += alpha_k p_k, r_k -= alpha_k q_k with rr[k] = r_k . r_k; p_k = z_k +
+// beta_k p_k.  alpha, beta, out and rr are device arrays of nr doubles.
+void launch_spmm_sell(hipStream_t s, int n, const long long *sptr, const int *scol,
+                      const double *sval, size_t ld, int nr, const double *X, double *Y);
+void launch_col_dots(hipStream_t s, int n, size_t ld, int nr, const double *A, const double *B,
+                     double *part, double *out);
+void launch_col_update(hipStream_t s, int n, size_t ld, int nr, const double *alpha,
+                       const double *P, const double *Q, double *X, double *R, double *part,
+                       double *rr);
+void launch_col_direction(hipStream_t s, int n, size_t ld, int nr, const double *beta,
+                          const double *Z, double *P);
 // f32 factor of the mixed forms from its streams back into packed diagonal
 // tiles + envelope (the layout of launch_env_solve_block)
 void launch_streams_to_env(hipStream_t s, const Plan &p, int ntilerows, const float *fst,

@@ -117,6 +117,109 @@ __global__ void __launch_bounds__(WG) k_streams_to_env(Plan p, const float *__re
   }
 }
 
+// ------------------------------------------ CG on several columns at once ---
+// Independent CG recurrences, one per column, that share every operator
+// application.  Columns are ld apart; per-column scalars come from device
+// arrays (alpha, beta); converged columns carry alpha = beta = 0.
+
+// Y_k = A X_k for k < nr on the sliced copy of A: a row's entries are
+// loaded once and used for every column.
+__global__ void __launch_bounds__(WG) k_spmm_sell(int n, const long long *__restrict__ sptr,
+                                                  const int *__restrict__ scol,
+                                                  const double *__restrict__ sval, size_t ld,
+                                                  int nr, const double *__restrict__ X,
+                                                  double *__restrict__ Y) {
+  constexpr int JU = 8;
+  const int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  const int sl = i >> 6, lane = i & 63;
+  const long long base = sptr[sl];
+  const int wd = (int)((sptr[sl + 1] - base) >> 6);
+  int c[JU];
+  double v[JU];
+#pragma unroll
+  for (int j = 0; j < JU; ++j) {
+    const bool in = j < wd;
+    const long long e = base + (long long)j * 64 + lane;
+    c[j] = in ? scol[e] : i;
+    v[j] = in ? sval[e] : 0.0;
+  }
+  for (int k = 0; k < nr; ++k) {
+    const double *x = X + (size_t)k * ld;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < JU; ++j)
+      if (j < wd) s = fma(v[j], x[c[j]], s);
+    for (int j = JU; j < wd; ++j) {
+      const long long e = base + (long long)j * 64 + lane;
+      s = fma(sval[e], x[scol[e]], s);
+    }
+    Y[(size_t)k * ld + i] = s;
+  }
+}
+
+// part[k * gridDim.x + b] = sum over rows of block-stride b of A_k . B_k
+__global__ void __launch_bounds__(WG) k_col_dots(int n, size_t ld, int nr,
+                                                 const double *__restrict__ A,
+                                                 const double *__restrict__ B,
+                                                 double *__restrict__ part) {
+  __shared__ double sh[WG / 64];
+  const int k = blockIdx.y;
+  if (k >= nr) return;  // uniform over the workgroup
+  const double *a = A + (size_t)k * ld, *b = B + (size_t)k * ld;
+  double acc = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) acc = fma(a[i], b[i], acc);
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(size_t)k * gridDim.x + blockIdx.x] = t;
+}
+
+// x_k += alpha_k p_k, r_k -= alpha_k q_k, partial sums of r_k . r_k
+__global__ void __launch_bounds__(WG) k_col_update(int n, size_t ld, int nr,
+                                                   const double *__restrict__ alpha,
+                                                   const double *__restrict__ P,
+                                                   const double *__restrict__ Q,
+                                                   double *__restrict__ X,
+                                                   double *__restrict__ R,
+                                                   double *__restrict__ part) {
+  __shared__ double sh[WG / 64];
+  const int k = blockIdx.y;
+  if (k >= nr) return;
+  const double a = alpha[k];
+  const size_t o = (size_t)k * ld;
+  double acc = 0.0;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+    X[o + i] = fma(a, P[o + i], X[o + i]);
+    const double ri = fma(-a, Q[o + i], R[o + i]);
+    R[o + i] = ri;
+    acc = fma(ri, ri, acc);
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(size_t)k * gridDim.x + blockIdx.x] = t;
+}
+
+// p_k = z_k + beta_k p_k
+__global__ void __launch_bounds__(WG) k_col_direction(int n, size_t ld, int nr,
+                                                      const double *__restrict__ beta,
+                                                      const double *__restrict__ Z,
+                                                      double *__restrict__ P) {
+  const int k = blockIdx.y;
+  if (k >= nr) return;
+  const double b = beta[k];
+  const size_t o = (size_t)k * ld;
+  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG)
+    P[o + i] = fma(b, P[o + i], Z[o + i]);
+}
+
+// out[k] = sum of part[k * nb .. k * nb + nb) in a fixed order
+__global__ void __launch_bounds__(WG) k_col_reduce(int nb, const double *__restrict__ part,
+                                                   double *__restrict__ out) {
+  __shared__ double sh[WG / 64];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += WG) acc += part[(size_t)blockIdx.x * nb + b];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
 // ------------------------------------------------------------- launchers ---
 void launch_streams_to_env(hipStream_t s, const Plan &p, int ntilerows, const float *fst,
                            const float *bst, float *dg, float *er, float *ec) {
@@ -146,6 +249,39 @@ void launch_scatter_multi(hipStream_t s, int n, int nr, const int *inv_ptr, cons
   const unsigned b = (unsigned)((tot + WG - 1) / WG);
   if (b == 0) return;
   hipLaunchKernelGGL(k_scatter_multi, dim3(b), dim3(WG), 0, s, n, nr, inv_ptr, ix, XN, z);
+}
+
+static int col_blocks(int n) {
+  int b = (n + WG - 1) / WG;
+  return b > 256 ? 256 : (b < 1 ? 1 : b);
+}
+
+void launch_spmm_sell(hipStream_t s, int n, const long long *sptr, const int *scol,
+                      const double *sval, size_t ld, int nr, const double *X, double *Y) {
+  const unsigned b = (unsigned)(((long long)n + WG - 1) / WG);
+  if (b == 0 || nr <= 0) return;
+  hipLaunchKernelGGL(k_spmm_sell, dim3(b), dim3(WG), 0, s, n, sptr, scol, sval, ld, nr, X, Y);
+}
+
+void launch_col_dots(hipStream_t s, int n, size_t ld, int nr, const double *A, const double *B,
+                     double *part, double *out) {
+  const int nb = col_blocks(n);
+  hipLaunchKernelGGL(k_col_dots, dim3(nb, nr), dim3(WG), 0, s, n, ld, nr, A, B, part);
+  hipLaunchKernelGGL(k_col_reduce, dim3(nr), dim3(WG), 0, s, nb, part, out);
+}
+
+void launch_col_update(hipStream_t s, int n, size_t ld, int nr, const double *alpha,
+                       const double *P, const double *Q, double *X, double *R, double *part,
+                       double *rr) {
+  const int nb = col_blocks(n);
+  hipLaunchKernelGGL(k_col_update, dim3(nb, nr), dim3(WG), 0, s, n, ld, nr, alpha, P, Q, X, R,
+                     part);
+  hipLaunchKernelGGL(k_col_reduce, dim3(nr), dim3(WG), 0, s, nb, part, rr);
+}
+
+void launch_col_direction(hipStream_t s, int n, size_t ld, int nr, const double *beta,
+                          const double *Z, double *P) {
+  hipLaunchKernelGGL(k_col_direction, dim3(col_blocks(n), nr), dim3(WG), 0, s, n, ld, nr, beta, Z, P);
 }
 
 #define AMSP_MULTI_INST(TB)                                                                  \

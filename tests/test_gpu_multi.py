@@ -84,3 +84,56 @@ def test_multi_apply_mixed(prec):
         e_single, e_block = relerr(single, ref), relerr(Z[:, j], ref)
         assert e_block <= max(10 * e_single, 1e-6), (j, e_block, e_single)
     pc.close()
+
+
+@pytest.mark.parametrize("name,k", [("channels64", 4), ("gauss128", 3)])
+def test_block_pcg_parity(name, k):
+    """Columns solved together: each reaches rtol with the oracle's solution
+    (bar of the one-column PCG parity), and the summed iteration count is
+    the oracle's up to one step per column."""
+    w, A, st, alt = case(name)
+    say("block pcg", name, k)
+    rng = np.random.default_rng(53)
+    F = np.column_stack([w.b] + [rng.standard_normal(w.n) for _ in range(k - 1)])
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap)
+    U, info = pc.pcg(torch.tensor(F, device="cuda"), 1e-8, 1000)
+    U = host(U)
+    assert info["converged"] == 1
+    its = 0
+    for j in range(k):
+        ref = O.pcg(A, F[:, j], st.apply, 1e-8)
+        its += ref.iterations
+        floor = relerr(O.pcg(A, F[:, j], alt.apply, 1e-8).x, ref.x)
+        err = relerr(U[:, j], ref.x)
+        assert err <= max(1e-9, 10 * floor, 100 * info["relres_floor"]), (j, err, floor)
+        rel = np.linalg.norm(F[:, j] - A @ U[:, j]) / np.linalg.norm(F[:, j])
+        assert rel <= 1.01 * max(1e-8, info["relres_floor"]), (j, rel)
+    assert abs(info["iterations"] - its) <= k, (info["iterations"], its)
+    pc.close()
+
+
+def test_block_pcg_mixed_and_edges():
+    w, A, _, _ = case("gauss128")
+    say("block pcg mixed")
+    rng = np.random.default_rng(54)
+    F = np.column_stack([w.b, rng.standard_normal(w.n), np.zeros(w.n), rng.standard_normal(w.n)])
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision="fp32")
+    Ft = torch.tensor(F, device="cuda")
+    U, info = pc.pcg(Ft, 1e-8, 2000)
+    U = host(U)
+    assert info["converged"] == 1
+    assert np.all(U[:, 2] == 0)
+    single = 0
+    for j in (0, 1, 3):
+        rel = np.linalg.norm(F[:, j] - A @ U[:, j]) / np.linalg.norm(F[:, j])
+        assert rel <= 1.01 * max(1e-8, info["relres_floor"]), (j, rel)
+        single += pc.pcg(Ft[:, j].contiguous(), 1e-8, 2000)[1]["iterations"]
+    assert info["iterations"] <= 1.2 * single + 6, (info["iterations"], single)
+    bad = F.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(P.AmspError) as e:
+        pc.pcg(torch.tensor(bad, device="cuda"), 1e-8, 100)
+    assert e.value.name == "AMSP_ERR_BREAKDOWN"
+    u, info = pc.pcg(Ft[:, 0].contiguous(), 1e-8, 2000)  # the handle still solves
+    assert info["converged"] == 1
+    pc.close()
