@@ -18,8 +18,10 @@ with the MALL flushed between calls, outside the timed steps), `rtol_1e-6`
 (the paper's own solver setting: GMRES(30) with the preconditioner to a 1e-6
 reduction, and PCG to the same, outside the timed steps),
 `multiplicative_cycle` (the symmetric two-grid cycle as the preconditioner,
-setup + PCG to 1e-8, outside the timed steps) and `cpu_baseline` (the oracle
-on a bounded sample, on the host cores).
+setup + PCG to 1e-8, outside the timed steps), `multi_rhs` (16 columns per
+apply and 8 CG recurrences sharing each operator application, against one
+column at a time, outside the timed steps) and `cpu_baseline` (the oracle on
+a bounded sample, on the host cores).
 """
 from __future__ import annotations
 
@@ -239,6 +241,58 @@ def cycle_measure(P, torch, w, f, forms):
     return out
 
 
+def multi_rhs_measure(P, torch, w, f, forms, ncols=8):
+    """Several right-hand sides (the batched reading: 8 columns): the block
+    apply of 16 columns against 16 one-column applies (median of 5 after one
+    untimed), and PCG to 1e-8 on 8 columns together against the same 8 one
+    after another; the first column is the workload's f, the others seeded
+    N(0, 1).  Host clock around synchronised calls."""
+    out = {}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2606)
+    F = torch.randn((ncols, w.n), dtype=torch.float64, device="cuda", generator=g)
+    F[0] = f
+    R16 = torch.randn((16, w.n), dtype=torch.float64, device="cuda", generator=g)
+    cols = [R16[j].contiguous() for j in range(16)]
+    fcols = [F[j].contiguous() for j in range(ncols)]
+
+    def clock(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts))
+
+    for prec in forms:
+        pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec)
+        block_ms = clock(lambda: pc.apply_columns(R16))
+        single_ms = clock(lambda: [pc.apply(c) for c in cols])
+        info = {}
+
+        def block_pcg():
+            info["b"] = pc.pcg_columns(F, 1e-8, 2000)[1]
+
+        def seq_pcg():
+            info["s"] = sum(pc.pcg(c, 1e-8, 2000)[1]["iterations"] for c in fcols)
+
+        bp = clock(block_pcg, reps=1)
+        sp = clock(seq_pcg, reps=1)
+        pc.close()
+        out[prec] = {"apply_16_columns_ms": round(block_ms, 3),
+                     "apply_16_single_ms": round(single_ms, 3),
+                     "pcg_columns": ncols, "block_pcg_ms": round(bp, 3),
+                     "sequential_pcg_ms": round(sp, 3),
+                     "block_pcg_iterations": int(info["b"]["iterations"]),
+                     "sequential_pcg_iterations": int(info["s"]),
+                     "block_relres_true_max": float(f"{info['b']['relres_true']:.4g}")}
+        log(f"[{prec}] several right-hand sides: {out[prec]}")
+    return out
+
+
 def gmres_measure(P, torch, w, f, forms, sums):
     """The paper's own solver configuration (Section 5): GMRES with the
     preconditioner, restarted every 30 steps, until the residual has dropped
@@ -372,6 +426,8 @@ def main():
     line["rtol_1e-6"] = gmres_measure(P, torch, w, f, forms, sums)
     log("multiplicative two-grid cycle ...")
     line["multiplicative_cycle"] = cycle_measure(P, torch, w, f, forms)
+    log("several right-hand sides ...")
+    line["multi_rhs"] = multi_rhs_measure(P, torch, w, f, forms)
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(w, sums[head]["iterations"])

@@ -299,6 +299,36 @@ class Preconditioner:
             z.copy_(zz.t())
         return z
 
+    def apply_columns(self, rt, out=None, parts: int = 3):
+        """z_j = M^{-1} r_j for the rows r_j of a (k, n) float64 device tensor
+        (the C ABI's layout: right-hand sides n apart, so no transposed copy)."""
+        torch = _torch()
+        if rt.dim() != 2 or rt.shape[1] != self.n:
+            raise ValueError(f"rt must have shape (k, {self.n})")
+        _check_dev(rt, "rt")
+        z = out if out is not None else torch.empty_like(rt)
+        self._err(_lib.amsp_apply_parts(self._h, rt.data_ptr(), z.data_ptr(), rt.shape[0], parts))
+        return z
+
+    def pcg_columns(self, ft, rtol: float = 1e-8, maxit: int = 1000, out=None,
+                    raise_on_noconv=True):
+        """PCG on the rows of a (k, n) float64 device tensor together (one CG
+        recurrence per right-hand side); returns (u of shape (k, n), info)."""
+        torch = _torch()
+        if ft.dim() != 2 or ft.shape[1] != self.n:
+            raise ValueError(f"ft must have shape (k, {self.n})")
+        _check_dev(ft, "ft")
+        u = out if out is not None else torch.empty_like(ft)
+        inf = _Info()
+        st = _lib.amsp_pcg(self._h, ft.data_ptr(), u.data_ptr(), ft.shape[0], float(rtol),
+                           int(maxit), ctypes.byref(inf))
+        info = {name: getattr(inf, name) for name, _ in _Info._fields_
+                if name not in ("kernel_ms", "kernel_launches")}
+        info["status"] = STATUS.get(st, st)
+        if st != AMSP_OK and (raise_on_noconv or st != -9):
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
+        return u, info
+
     def spmv(self, x, out=None):
         torch = _torch()
         _check_dev(x, "x", self.n)

@@ -163,7 +163,8 @@ struct amsp_handle {
   // several right-hand sides per pass (allocated on first use): gathered and
   // solved blocks, region outputs, coarse vectors, and for the mixed forms
   // the f32 factor in the block solve's layout
-  double *bX = nullptr, *bY = nullptr, *bXN = nullptr, *bC = nullptr, *bT = nullptr;
+  double *bX = nullptr, *bY = nullptr, *bXN = nullptr, *bC = nullptr, *bT = nullptr,
+         *bC2 = nullptr, *bPart = nullptr;
   float *dg32 = nullptr, *er32 = nullptr, *ec32 = nullptr;
   double *W0 = nullptr;
   float *W0f = nullptr;
@@ -1078,6 +1079,8 @@ static amsp_status apply_block(amsp_handle *h, const double *r, double *z, int n
     ALLOC(h->bXN, double, rows * EIGP);
     ALLOC(h->bC, double, ncp * EIGP);
     ALLOC(h->bT, double, ncp * EIGP);
+    ALLOC(h->bC2, double, ncp * EIGP);
+    ALLOC(h->bPart, double, std::max<size_t>((size_t)h->T0 * h->T0, 1) * TS * EIGP);
     launch_fill(s, ncp * EIGP, h->bC, 0.0);  // coarse padding stays zero
   }
   if (mixed && do_local && !h->dg32) {
@@ -1102,15 +1105,13 @@ static amsp_status apply_block(amsp_handle *h, const double *r, double *z, int n
       launch_restrict_multi<float>(s, p, nr, ncp, (const float *)phi, h->bX, h->bC);
     else
       launch_restrict_multi<__hip_bfloat16>(s, p, nr, ncp, (const __hip_bfloat16 *)phi, h->bX, h->bC);
-    for (int k = 0; k < nr; ++k) {
-      double *ck = h->bC + (size_t)k * ncp, *tk = h->bT + (size_t)k * ncp;
-      if (!mixed) {
-        launch_trmv<double>(s, h->W0, h->T0, ck, h->trmv_part, h->t1, 0, nullptr);
-        launch_trmv<double>(s, h->W0, h->T0, h->t1, h->trmv_part, tk, 1, nullptr);
-      } else {
-        launch_trmv<float>(s, h->W0f, h->T0, ck, h->trmv_part, h->t1, 0, nullptr);
-        launch_trmv<float>(s, h->W0f, h->T0, h->t1, h->trmv_part, tk, 1, nullptr);
-      }
+    // t_k = W0^T (W0 c_k) for all columns, W0's tiles read once per product
+    if (!mixed) {
+      launch_trmm<double>(s, h->W0, h->T0, h->bC, ncp, nr, h->bPart, h->bC2, 0);
+      launch_trmm<double>(s, h->W0, h->T0, h->bC2, ncp, nr, h->bPart, h->bT, 1);
+    } else {
+      launch_trmm<float>(s, h->W0f, h->T0, h->bC, ncp, nr, h->bPart, h->bC2, 0);
+      launch_trmm<float>(s, h->W0f, h->T0, h->bC2, ncp, nr, h->bPart, h->bT, 1);
     }
   }
   const double *tcoarse = do_coarse ? h->bT : nullptr;
@@ -1278,11 +1279,6 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
     active[k] = f2[k] > 0.0;
   }
   hist.push_back(f2[nr - 1]);
-  amsp_status st = apply_block(h, R, Z, nr, 3);
-  if (st != AMSP_OK) return st;
-  launch_col_dots(s, n, ld, nr, R, Z, part, sc + 16);
-  HIP_TRY(to_host(sc + 16, rz.data()));
-  HIP_TRY(hipMemcpyAsync(Pd, Z, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
   bool breakdown = false;
   int it = 0;
   auto any_active = [&]() {
@@ -1290,75 +1286,94 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
       if (v) return true;
     return false;
   };
-  while (any_active() && it < maxit) {
-    launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, Pd, Q);
-    launch_col_dots(s, n, ld, nr, Pd, Q, part, sc + 16);
-    HIP_TRY(to_host(sc + 16, dot.data()));
-    for (int k = 0; k < nr; ++k) {
-      coef[k] = 0.0;
-      if (!active[k]) continue;
-      if (!(dot[k] > 0.0) || !std::isfinite(rz[k] / dot[k])) {
-        breakdown = true;
-        active[k] = 0;
-        continue;
-      }
-      coef[k] = rz[k] / dot[k];
-    }
-    HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_col_update(s, n, ld, nr, sc, Pd, Q, U, R, part, sc + 32);
-    ++it;
+  std::vector<double> rt(nr, 0.0), fl(nr, 0.0), rec(nr, 0.0);
+  const int nb = reduce_blocks(n);
+  amsp_status st = AMSP_OK;
+  // as in amsp_pcg: stop on the recursive residuals, recompute f - A u, and
+  // restart the columns whose true residual is above max(rtol, floor) from
+  // it (at most 3 times)
+  for (int restarts = 0;; ++restarts) {
     if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) return st;
     launch_col_dots(s, n, ld, nr, R, Z, part, sc + 16);
-    HIP_TRY(to_host(sc + 32, rr.data()));
-    HIP_TRY(to_host(sc + 16, dot.data()));
-    hist.push_back(rr[nr - 1]);
-    for (int k = 0; k < nr; ++k) {
-      coef[k] = 0.0;
-      if (!active[k]) continue;
-      its[k] = it;
-      if (!std::isfinite(rr[k])) {
-        breakdown = true;
-        active[k] = 0;
-        continue;
+    HIP_TRY(to_host(sc + 16, rz.data()));
+    HIP_TRY(hipMemcpyAsync(Pd, Z, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+    while (any_active() && it < maxit) {
+      launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, Pd, Q);
+      launch_col_dots(s, n, ld, nr, Pd, Q, part, sc + 16);
+      HIP_TRY(to_host(sc + 16, dot.data()));
+      for (int k = 0; k < nr; ++k) {
+        coef[k] = 0.0;
+        if (!active[k]) continue;
+        if (!(dot[k] > 0.0) || !std::isfinite(rz[k] / dot[k])) {
+          breakdown = true;
+          active[k] = 0;
+          continue;
+        }
+        coef[k] = rz[k] / dot[k];
       }
-      if (rr[k] <= rtol * rtol * f2[k]) {
-        active[k] = 0;
-        continue;
+      HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_col_update(s, n, ld, nr, sc, Pd, Q, U, R, part, sc + 32);
+      ++it;
+      if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) return st;
+      launch_col_dots(s, n, ld, nr, R, Z, part, sc + 16);
+      HIP_TRY(to_host(sc + 32, rr.data()));
+      HIP_TRY(to_host(sc + 16, dot.data()));
+      hist.push_back(rr[nr - 1]);
+      for (int k = 0; k < nr; ++k) {
+        coef[k] = 0.0;
+        if (!active[k]) continue;
+        ++its[k];
+        if (!std::isfinite(rr[k])) {
+          breakdown = true;
+          active[k] = 0;
+          continue;
+        }
+        if (rr[k] <= rtol * rtol * f2[k]) {
+          active[k] = 0;
+          continue;
+        }
+        coef[k] = dot[k] / rz[k];
+        rz[k] = dot[k];
       }
-      coef[k] = dot[k] / rz[k];
-      rz[k] = dot[k];
+      HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_col_direction(s, n, ld, nr, sc, Z, Pd);
     }
-    HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_col_direction(s, n, ld, nr, sc, Z, Pd);
-  }
-  // true residuals f - A u and the attainable floors, per column
-  launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, U, Q);
-  const int nb = reduce_blocks(n);
-  for (int k = 0; k < nr; ++k) {
-    const double fk = std::sqrt(f2[k]);
-    double rt = 0.0, fl = 0.0;
-    if (fk > 0.0) {
+    for (int k = 0; k < nr; ++k) rec[k] = f2[k] > 0.0 ? std::sqrt(rr[k] / f2[k]) : 0.0;
+    // true residuals (left in R) and, where needed, the attainable floors
+    launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, U, Q);
+    bool again = false;
+    for (int k = 0; k < nr; ++k) {
+      const double fk = std::sqrt(f2[k]);
+      rt[k] = 0.0;
+      if (!(fk > 0.0)) continue;
       launch_residual(s, n, F + k * ld, Q + k * ld, R + k * ld, part);
-      launch_sum_partials(s, part, nb, sc + 48 - 1);
+      launch_sum_partials(s, part, nb, sc + 47);
       double r2 = 0.0;
       HIP_TRY(hipMemcpyAsync(&r2, sc + 47, sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      rt = std::sqrt(r2) / fk;
-      if (rt > rtol) {
+      rt[k] = std::sqrt(r2) / fk;
+      if (rt[k] > rtol && fl[k] == 0.0) {
         launch_abs_spmv_sq(s, n, h->rowptr, h->col, h->val, U + k * ld, part);
         launch_sum_partials(s, part, nb, sc + 47);
         double a2 = 0.0;
         HIP_TRY(hipMemcpyAsync(&a2, sc + 47, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        fl = DBL_EPSILON * std::sqrt(a2) / fk;
+        fl[k] = DBL_EPSILON * std::sqrt(a2) / fk;
       }
+      rr[k] = r2;
+      const bool ok = rt[k] <= std::max(rtol, fl[k]);
+      active[k] = !ok && std::isfinite(rt[k]) && restarts < 3 && it < maxit && !breakdown;
+      again = again || active[k];
     }
-    const bool conv = rt <= std::max(rtol, fl) && std::isfinite(rt);
+    if (!again) break;
+  }
+  for (int k = 0; k < nr; ++k) {
+    const bool conv = rt[k] <= std::max(rtol, fl[k]) && std::isfinite(rt[k]);
     if (!conv) inf.converged = 0;
     inf.iterations += its[k];
-    inf.relres_true = std::max(inf.relres_true, rt);
-    inf.relres_recursive = std::max(inf.relres_recursive, f2[k] > 0 ? std::sqrt(rr[k] / f2[k]) : 0.0);
-    inf.relres_floor = std::max(inf.relres_floor, fl);
+    inf.relres_true = std::max(inf.relres_true, rt[k]);
+    inf.relres_recursive = std::max(inf.relres_recursive, rec[k]);
+    inf.relres_floor = std::max(inf.relres_floor, fl[k]);
   }
   h->hist_len = std::min((int)hist.size(), h->hist_cap);
   h->hist_f2 = f2[nr - 1];

@@ -176,6 +176,11 @@ void launch_prolong_multi(hipStream_t s, const Plan &p, int nr, size_t ncp, cons
                           const double *t, const double *Y, double *XN);
 void launch_scatter_multi(hipStream_t s, int n, int nr, const int *inv_ptr, const int *ix,
                           const double *XN, double *z);
+// y_k = W0 x_k (transpose 0) or W0^T x_k (1) for k < nr, vectors ncp apart,
+// reading W0's tiles once; part holds T0 * T0 * 64 * EIGP doubles.
+template <typename T>
+void launch_trmm(hipStream_t s, const T *Wt, int T0, const double *x, size_t ncp, int nr,
+                 double *part, double *y, int transpose);
 // CG on nr columns ld apart, one recurrence per column: Y = A X (entries
 // read once for all columns); out[k] = A_k . B_k (part: 256 * nr doubles);
 // x_k += alpha_k p_k, r_k -= alpha_k q_k with rr[k] = r_k . r_k; p_k = z_k +

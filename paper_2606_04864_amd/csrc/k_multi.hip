@@ -14,79 +14,188 @@
 
 namespace amsp {
 
-// X[vp_i + l][k] = r_k[dof(l)] for real rows and k < nr, zero otherwise.
+// X[vp_i + l][k] = r_k[dof(l)] for real rows and k < nr, zero otherwise;
+// thread per row (its EIGP entries are one contiguous 128-byte row of X).
 __global__ void __launch_bounds__(WG) k_gather_multi(Plan p, int n, int nr,
                                                      const double *__restrict__ r,
                                                      double *__restrict__ X) {
   const int i = blockIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int v0 = p.vp_ptr[i], npad = p.vp_ptr[i + 1] - v0;
-  for (int e = threadIdx.x; e < npad * EIGP; e += WG) {
-    const int l = e / EIGP, k = e % EIGP;
-    X[(size_t)v0 * EIGP + e] =
-        (l < ni && k < nr) ? r[(size_t)k * n + p.sd_dofs[r0 + l]] : 0.0;
+  for (int l = threadIdx.x; l < npad; l += WG) {
+    const int dof = l < ni ? p.sd_dofs[r0 + l] : -1;
+    double v[EIGP];
+#pragma unroll
+    for (int k = 0; k < EIGP; ++k) v[k] = (dof >= 0 && k < nr) ? r[(size_t)k * n + dof] : 0.0;
+    double2 *dst = reinterpret_cast<double2 *>(X + (size_t)(v0 + l) * EIGP);
+#pragma unroll
+    for (int k = 0; k < EIGP / 2; ++k) dst[k] = make_double2(v[2 * k], v[2 * k + 1]);
   }
 }
 
-// Restriction of every column: c_k[coff_i + q] = sum_l phi_i[l][q] X[l][k],
-// one thread per (q, k) of the region, rows in order.  The coarse vectors
-// are ncp apart (their padding stays zero).
+// Restriction of every column: c_k[coff_i + q] = sum_l phi_i[l][q] X[l][k].
+// Thread (row group g, column k) adds rows g, g + 16, ... for all q; the 16
+// group sums are then added in group order.  The coarse vectors are ncp
+// apart (their padding stays zero).
 template <typename TB>
 __global__ void __launch_bounds__(WG) k_restrict_multi(Plan p, int nr, size_t ncp,
                                                        const TB *__restrict__ phi,
                                                        const double *__restrict__ X,
                                                        double *__restrict__ c) {
+  constexpr int RGS = WG / EIGP;  // row groups
+  __shared__ double sh[RGS][MAXNEV][EIGP];
   const int i = blockIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, m = p.mi[i], nev = p.nev;
-  const int q = threadIdx.x / EIGP, k = threadIdx.x % EIGP;
-  if (q >= m || k >= nr) return;
+  const int k = threadIdx.x % EIGP, g = threadIdx.x / EIGP;
   const double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
-  const TB *ph = phi + (size_t)r0 * nev;
-  double acc = 0.0;
-  for (int l = 0; l < ni; ++l) acc = fma(to_d(ph[(size_t)l * nev + q]), Xi[(size_t)l * EIGP + k], acc);
-  c[(size_t)k * ncp + p.coff[i] + q] = acc;
+  double acc[MAXNEV];
+#pragma unroll
+  for (int q = 0; q < MAXNEV; ++q) acc[q] = 0.0;
+  for (int l = g; l < ni; l += RGS) {
+    const double x = Xi[(size_t)l * EIGP + k];
+    const TB *ph = phi + (size_t)(r0 + l) * nev;
+#pragma unroll
+    for (int q = 0; q < MAXNEV; ++q)
+      if (q < m) acc[q] = fma(to_d(ph[q]), x, acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < MAXNEV; ++q)
+    if (q < m) sh[g][q][k] = acc[q];
+  __syncthreads();
+  if ((int)threadIdx.x < m * EIGP) {
+    const int q = threadIdx.x / EIGP, kk = threadIdx.x % EIGP;
+    double s = 0.0;
+    for (int gg = 0; gg < RGS; ++gg) s += sh[gg][q][kk];
+    if (kk < nr) c[(size_t)kk * ncp + p.coff[i] + q] = s;
+  }
 }
 
 // XN[vp_i + nat(l)][k] = Y[vp_i + l][k] + sum_q phi_i[l][q] t_k[coff_i + q]
 // (without the coarse part when t is null; without the local part when Y is).
+// The region's coarse values are staged in LDS; thread per row.
 template <typename TB>
 __global__ void __launch_bounds__(WG) k_prolong_multi(Plan p, int nr, size_t ncp,
                                                       const TB *__restrict__ phi,
                                                       const double *__restrict__ t,
                                                       const double *__restrict__ Y,
                                                       double *__restrict__ XN) {
+  __shared__ double tl[MAXNEV][EIGP];
   const int i = blockIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, m = p.mi[i], nev = p.nev;
   const size_t v0 = p.vp_ptr[i];
   const int co = p.coff[i];
-  for (int e = threadIdx.x; e < ni * EIGP; e += WG) {
-    const int l = e / EIGP, k = e % EIGP;
-    double v = 0.0;
-    if (k < nr) {
-      if (Y) v = Y[(v0 + l) * EIGP + k];
-      if (t) {
-        const TB *ph = phi + (size_t)(r0 + l) * nev;
+  if (t && (int)threadIdx.x < MAXNEV * EIGP) {
+    const int q = threadIdx.x / EIGP, k = threadIdx.x % EIGP;
+    tl[q][k] = (q < m && k < nr) ? t[(size_t)k * ncp + co + q] : 0.0;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < ni; l += WG) {
+    double v[EIGP];
+    if (Y) {
+      const double2 *src = reinterpret_cast<const double2 *>(Y + (v0 + l) * EIGP);
 #pragma unroll
-        for (int q = 0; q < MAXNEV; ++q)
-          if (q < m) v = fma(to_d(ph[q]), t[(size_t)k * ncp + co + q], v);
+      for (int k = 0; k < EIGP / 2; ++k) {
+        const double2 y = src[k];
+        v[2 * k] = y.x;
+        v[2 * k + 1] = y.y;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < EIGP; ++k) v[k] = 0.0;
+    }
+    if (t) {
+      const TB *ph = phi + (size_t)(r0 + l) * nev;
+#pragma unroll
+      for (int q = 0; q < MAXNEV; ++q) {
+        if (q < m) {
+          const double a = to_d(ph[q]);
+#pragma unroll
+          for (int k = 0; k < EIGP; ++k) v[k] = fma(a, tl[q][k], v[k]);
+        }
       }
     }
-    XN[(v0 + p.nat[r0 + l]) * EIGP + k] = v;
+#pragma unroll
+    for (int k = 0; k < EIGP; ++k)
+      if (k >= nr) v[k] = 0.0;
+    double2 *dst = reinterpret_cast<double2 *>(XN + (v0 + p.nat[r0 + l]) * EIGP);
+#pragma unroll
+    for (int k = 0; k < EIGP / 2; ++k) dst[k] = make_double2(v[2 * k], v[2 * k + 1]);
   }
 }
 
 // z_k[j] = sum over the copies of dof j (fixed map order) of XN[copy][k];
-// thread per (dof, column), EIGP consecutive threads share a dof.
+// thread per dof, the copies' rows read whole, each column written coalesced.
 __global__ void __launch_bounds__(WG) k_scatter_multi(int n, int nr, const int *__restrict__ inv_ptr,
                                                       const int *__restrict__ ix,
                                                       const double *__restrict__ XN,
                                                       double *__restrict__ z) {
-  const long long g = (long long)blockIdx.x * WG + threadIdx.x;
-  const int j = (int)(g / EIGP), k = (int)(g % EIGP);
-  if (j >= n || k >= nr) return;
+  const int j = blockIdx.x * WG + threadIdx.x;
+  if (j >= n) return;
+  double s[EIGP];
+#pragma unroll
+  for (int k = 0; k < EIGP; ++k) s[k] = 0.0;
+  for (int e = inv_ptr[j]; e < inv_ptr[j + 1]; ++e) {
+    const double2 *row = reinterpret_cast<const double2 *>(XN + (size_t)ix[e] * EIGP);
+#pragma unroll
+    for (int k = 0; k < EIGP / 2; ++k) {
+      const double2 x = row[k];
+      s[2 * k] += x.x;
+      s[2 * k + 1] += x.y;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < EIGP; ++k)
+    if (k < nr) z[(size_t)k * n + j] = s[k];
+}
+
+// Coarse solve of every column: the product with the tiles of W0 (or W0^T)
+// for all columns at once, so W0 is read once.  Workgroup per lower tile
+// (I, J); the input block (64 rows x EIGP columns of tile K = J, or I
+// transposed) is staged in LDS; part[(O * T0 + K)][row][k] holds the tile's
+// contribution to output tile O (I, or J transposed).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_trmm_tiles(const T *__restrict__ Wt, int T0,
+                                                   const double *__restrict__ x, size_t ncp, int nr,
+                                                   double *__restrict__ part, int transpose) {
+  __shared__ double xs[TS][EIGP];
+  const int b = blockIdx.x;
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;  // J <= I
+  const T *w = Wt + ((size_t)I * T0 + J) * TE;
+  const int K = transpose ? I : J, O = transpose ? J : I;
+  for (int e = threadIdx.x; e < TS * EIGP; e += WG) {
+    const int rr = e / EIGP, k = e % EIGP;
+    xs[rr][k] = k < nr ? x[(size_t)k * ncp + K * TS + rr] : 0.0;
+  }
+  __syncthreads();
+  const int o = threadIdx.x % TS, kq = threadIdx.x / TS;  // output row o, columns 4kq..4kq+3
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int c = 0; c < TS; ++c) {
+    const double wv = transpose ? (double)w[c * TS + o] : (double)w[o * TS + c];
+    a0 = fma(wv, xs[c][4 * kq], a0);
+    a1 = fma(wv, xs[c][4 * kq + 1], a1);
+    a2 = fma(wv, xs[c][4 * kq + 2], a2);
+    a3 = fma(wv, xs[c][4 * kq + 3], a3);
+  }
+  double *dst = part + (((size_t)O * T0 + K) * TS + o) * EIGP + 4 * kq;
+  dst[0] = a0;
+  dst[1] = a1;
+  dst[2] = a2;
+  dst[3] = a3;
+}
+
+// y_k[O*64 + r] = sum over input tiles K (in order) of part[(O*T0 + K)][r][k]
+__global__ void __launch_bounds__(TS * EIGP) k_trmm_reduce(int T0, const double *__restrict__ part,
+                                                           double *__restrict__ y, size_t ncp,
+                                                           int nr, int transpose) {
+  const int O = blockIdx.x, r = threadIdx.x / EIGP, k = threadIdx.x % EIGP;
+  const int k0 = transpose ? O : 0, k1 = transpose ? T0 : O + 1;
   double s = 0.0;
-  for (int e = inv_ptr[j]; e < inv_ptr[j + 1]; ++e) s += XN[(size_t)ix[e] * EIGP + k];
-  z[(size_t)k * n + j] = s;
+#pragma unroll 4
+  for (int K = k0; K < k1; ++K) s += part[(((size_t)O * T0 + K) * TS + r) * EIGP + k];
+  if (k < nr) y[(size_t)k * ncp + O * TS + r] = s;
 }
 
 // The mixed forms keep their f32 factor only as the two per-sweep streams;
@@ -245,11 +354,25 @@ void launch_prolong_multi(hipStream_t s, const Plan &p, int nr, size_t ncp, cons
 
 void launch_scatter_multi(hipStream_t s, int n, int nr, const int *inv_ptr, const int *ix,
                           const double *XN, double *z) {
-  const long long tot = (long long)n * EIGP;
-  const unsigned b = (unsigned)((tot + WG - 1) / WG);
+  const unsigned b = (unsigned)(((long long)n + WG - 1) / WG);
   if (b == 0) return;
   hipLaunchKernelGGL(k_scatter_multi, dim3(b), dim3(WG), 0, s, n, nr, inv_ptr, ix, XN, z);
 }
+
+template <typename T>
+void launch_trmm(hipStream_t s, const T *Wt, int T0, const double *x, size_t ncp, int nr,
+                 double *part, double *y, int transpose) {
+  const int nb = T0 * (T0 + 1) / 2;
+  if (nb == 0) return;
+  hipLaunchKernelGGL((k_trmm_tiles<T>), dim3(nb), dim3(WG), 0, s, Wt, T0, x, ncp, nr, part,
+                     transpose);
+  hipLaunchKernelGGL(k_trmm_reduce, dim3(T0), dim3(TS * EIGP), 0, s, T0, part, y, ncp, nr,
+                     transpose);
+}
+template void launch_trmm<double>(hipStream_t, const double *, int, const double *, size_t, int,
+                                  double *, double *, int);
+template void launch_trmm<float>(hipStream_t, const float *, int, const double *, size_t, int,
+                                 double *, double *, int);
 
 static int col_blocks(int n) {
   int b = (n + WG - 1) / WG;
