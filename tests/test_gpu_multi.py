@@ -137,3 +137,20 @@ def test_block_pcg_mixed_and_edges():
     u, info = pc.pcg(Ft[:, 0].contiguous(), 1e-8, 2000)  # the handle still solves
     assert info["converged"] == 1
     pc.close()
+
+
+def test_column_layout_bindings_match():
+    """apply_columns / pcg_columns take the right-hand sides as rows of a
+    (k, n) tensor (the C layout); the results equal the (n, k) calls exactly."""
+    w, A, _, _ = case("channels64")
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap)
+    R = torch.tensor(np.random.default_rng(55).standard_normal((w.n, 5)), device="cuda")
+    Zc = host(pc.apply_columns(R.t().contiguous()))
+    Zr = host(pc.apply(R))
+    assert np.array_equal(Zc, Zr.T)
+    Uc, ic = pc.pcg_columns(R.t().contiguous(), 1e-8, 500)
+    Ur, ir = pc.pcg(R, 1e-8, 500)
+    assert np.array_equal(host(Uc), host(Ur).T) and ic["iterations"] == ir["iterations"]
+    with pytest.raises(ValueError):
+        pc.apply_columns(R)
+    pc.close()
