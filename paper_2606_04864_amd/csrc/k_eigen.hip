@@ -159,8 +159,24 @@ __global__ void __launch_bounds__(WG) k_eig_spmm(Plan p, const double *__restric
   if (l >= ni) return;
   const size_t base = (size_t)p.vp_ptr[i] * EIGP;
   double acc = Y[base + (size_t)l * EIGP + a];
-  const int e1 = p.loc_rowptr[r0 + l + 1];
-  for (int e = p.loc_rowptr[r0 + l]; e < e1; ++e)
+  const int e0 = p.loc_rowptr[r0 + l], e1 = p.loc_rowptr[r0 + l + 1];
+  // the first SU entries: all index and value loads, then all row loads,
+  // then the products in entry order; longer rows continue one by one
+  constexpr int SU = 8;
+  int c[SU];
+  double b[SU], y[SU];
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const bool in = e0 + u < e1;
+    c[u] = in ? p.loc_col[e0 + u] : l;
+    b[u] = in ? bval[e0 + u] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < SU; ++u) y[u] = Y[base + (size_t)c[u] * EIGP + a];
+#pragma unroll
+  for (int u = 0; u < SU; ++u)
+    if (e0 + u < e1) acc = fma(b[u], y[u], acc);
+  for (int e = e0 + SU; e < e1; ++e)
     acc = fma(bval[e], Y[base + (size_t)p.loc_col[e] * EIGP + a], acc);
   BY[base + (size_t)l * EIGP + a] = acc;
 }
