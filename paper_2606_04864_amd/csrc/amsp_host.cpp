@@ -166,6 +166,7 @@ struct amsp_handle {
   double *bX = nullptr, *bY = nullptr, *bXN = nullptr, *bC = nullptr, *bT = nullptr,
          *bC2 = nullptr, *bPart = nullptr;
   float *dg32 = nullptr, *er32 = nullptr, *ec32 = nullptr;
+  int *loc_scratch = nullptr;  // local CSR build, large regions only
   double *W0 = nullptr;
   float *W0f = nullptr;
   // apply scratch
@@ -532,8 +533,18 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     h->nst_b = sbr[h->N];
   }
   p.loc_rowptr = upload(h, P.loc_rowptr, ok);
-  p.loc_col = upload(h, P.loc_col, ok);
-  p.loc_src = upload(h, P.loc_src, ok);
+  {  // the entries of the local CSR are built here from A's device CSR
+    int *lc = nullptr, *ls = nullptr, *gs = nullptr;
+    ALLOC(lc, int, std::max<long long>(P.nloc, 1));
+    ALLOC(ls, int, std::max<long long>(P.nloc, 1));
+    if (local_csr_lds_bytes(P.max_ni) > LOCAL_CSR_LDS_MAX)
+      ALLOC(gs, int, std::max<size_t>((size_t)2 * P.sd_ptr.back(), 1));
+    p.loc_col = lc;
+    p.loc_src = ls;
+    h->loc_scratch = gs;
+    launch_local_csr(h->stream, p, P.max_ni, h->rowptr, h->col, lc, ls, gs);
+    HIP_TRY(hipGetLastError());
+  }
   p.mi = upload(h, P.mi, ok);
   p.coff = upload(h, P.coff, ok);
   CoarsePlan &c = h->cplan;
@@ -599,7 +610,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     ALLOC(X, double, (size_t)sum_npad * EIGP);
     ALLOC(Yb, double, (size_t)sum_npad * EIGP);
     ALLOC(BY, double, (size_t)sum_npad * EIGP);
-    ALLOC(bval, double, P.loc_col.size());
+    ALLOC(bval, double, std::max<long long>(P.nloc, 1));
     ALLOC(GK, double, (size_t)h->N * 2 * EIGP * EIGP);
     ALLOC(CC, double, (size_t)h->N * (EIGP * EIGP + EIGP));
     ALLOC(conv, int, h->N);

@@ -199,6 +199,14 @@ void launch_col_direction(hipStream_t s, int n, size_t ld, int nr, const double 
 void launch_streams_to_env(hipStream_t s, const Plan &p, int ntilerows, const float *fst,
                            const float *bst, float *dg, float *er, float *ec);
 
+// Local CSR entries (loc_col, loc_src) of every region from the plan's row
+// pointers, dofs and ranks, and A's device CSR.  gscratch (2 * sum n_i ints)
+// is used only when 2 * max_ni ints exceed LOCAL_CSR_LDS_MAX bytes of LDS.
+constexpr size_t LOCAL_CSR_LDS_MAX = 128 * 1024;
+size_t local_csr_lds_bytes(int max_ni);
+void launch_local_csr(hipStream_t s, const Plan &p, int max_ni, const int *rowptr, const int *col,
+                      int *loc_col, int *loc_src, int *gscratch);
+
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
 // dst[(sd_ptr[i] + nat[k]) * nev + c] = src[(sd_ptr[i] + k) * nev + c]: the basis

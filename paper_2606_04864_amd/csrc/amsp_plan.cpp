@@ -536,7 +536,8 @@ static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &a
 struct SubPlan {
   std::vector<int> dofs;                 // local order -> global dof
   std::vector<int> nat;                  // local order -> rank by global index
-  std::vector<int> rowlen, lcol, lsrc;   // local CSR (row lengths)
+  std::vector<int> rowlen;               // local CSR row lengths (entries: on the device)
+  size_t nloc = 0;                       // local CSR entries
   std::vector<int> tfirst;               // tile profile
   std::vector<int> eptr, uptr;           // envelope segment starts (npad + 1 each)
   bool env_overflow = false;             // envelope beyond 32-bit segment offsets
@@ -551,7 +552,7 @@ struct Scratch {
   int gen = 0;
   RcmWork rcm;
   std::vector<unsigned long long> bits;  // bitmap for ordering a region's dofs
-  std::vector<int> tptr, tcol, tsrc, pos;  // local CSR in ascending order, relabelling
+  std::vector<int> tptr, tcol, pos;  // local CSR columns in ascending order, relabelling
   std::vector<int> frontier, next, adj_ptr, adj, order, mincol, fenv;
   std::vector<std::pair<int, int>> row;
   explicit Scratch(int n) {
@@ -631,13 +632,12 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   ivec &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[region[k]] = k;
   // one pass over the region's rows of A (ascending order): the local CSR
-  // in that order (tcol/tsrc, diagonal included) and the adjacency for the
+  // columns in that order (tcol, diagonal included) and the adjacency for the
   // ordering (off-diagonal, nonzero values)
   S.adj_ptr.assign(ni + 1, 0);
   S.adj.clear();
   S.tptr.assign(ni + 1, 0);
   S.tcol.clear();
-  S.tsrc.clear();
   for (int k = 0; k < ni; ++k) {
     const int g = region[k];
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
@@ -645,7 +645,6 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
       const int lc = loc[c];
       if (lc < 0) continue;
       S.tcol.push_back(lc);
-      S.tsrc.push_back((int)e);
       if (c != g && va[e] != 0.0) S.adj.push_back(lc);
     }
     S.adj_ptr[k + 1] = (int)S.adj.size();
@@ -668,30 +667,19 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     out.nat[k] = S.order[k];  // region is ascending, so its index is the rank
     S.pos[S.order[k]] = k;
   }
+  // row lengths and each row's first local column in the chosen order (the
+  // entries themselves, sorted by local column, are built on the device
+  // from the same rule: the row's matrix entries whose column is in the region)
   S.mincol.assign(ni, 0);
   out.rowlen.resize(ni);
-  out.lcol.resize(S.tcol.size());
-  out.lsrc.resize(S.tcol.size());
-  size_t at = 0;
   for (int k = 0; k < ni; ++k) {
     const int j = S.order[k];
-    const size_t b = at;
-    for (int e = S.tptr[j]; e < S.tptr[j + 1]; ++e) {
-      // insertion into the row's run, ascending local column (rows are short)
-      const int lc = S.pos[S.tcol[e]], ls = S.tsrc[e];
-      size_t y = at++;
-      while (y > b && out.lcol[y - 1] > lc) {
-        out.lcol[y] = out.lcol[y - 1];
-        out.lsrc[y] = out.lsrc[y - 1];
-        --y;
-      }
-      out.lcol[y] = lc;
-      out.lsrc[y] = ls;
-    }
-    const int len = (int)(at - b);
-    S.mincol[k] = len == 0 ? k : std::min(k, out.lcol[b]);
-    out.rowlen[k] = len;
+    int mc = k;
+    for (int e = S.tptr[j]; e < S.tptr[j + 1]; ++e) mc = std::min(mc, S.pos[S.tcol[e]]);
+    S.mincol[k] = mc;
+    out.rowlen[k] = S.tptr[j + 1] - S.tptr[j];
   }
+  out.nloc = S.tcol.size();
   SEC(3);
   const int nt = (ni + TS - 1) / TS;
   out.tfirst.resize(nt);
@@ -863,7 +851,7 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
     P.trow_ptr[i + 1] = P.trow_ptr[i] + nt;
     P.mi[i] = std::min(nev, ni);
     P.coff[i + 1] = P.coff[i] + P.mi[i];
-    loc_off[i + 1] = loc_off[i] + sub[i].lcol.size();
+    loc_off[i + 1] = loc_off[i] + sub[i].nloc;
     long long t = 0;
     for (int I = 0; I < nt; ++I) t += I - sub[i].tfirst[I] + 1;
     tile_off[i + 1] = tile_off[i] + t;
@@ -873,8 +861,7 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
   P.nat.resize(sum_ni);
   P.loc_rowptr.resize(sum_ni + 1);
   P.loc_rowptr[0] = 0;
-  P.loc_col.resize(loc_off[N]);
-  P.loc_src.resize(loc_off[N]);
+  P.nloc = (long long)loc_off[N];
   P.tfirst.resize(P.trow_ptr[N]);
   P.toff.resize(P.trow_ptr[N]);
   P.ebase.assign(N + 1, 0);
@@ -891,8 +878,6 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
       acc += S.rowlen[k];
       P.loc_rowptr[r0 + k + 1] = acc;
     }
-    std::copy(S.lcol.begin(), S.lcol.end(), P.loc_col.begin() + loc_off[i]);
-    std::copy(S.lsrc.begin(), S.lsrc.end(), P.loc_src.begin() + loc_off[i]);
     const int g0 = P.trow_ptr[i];
     long long t = tile_off[i] - g0;  // off-diagonal tiles of the regions before i
     for (size_t I = 0; I < S.tfirst.size(); ++I) {

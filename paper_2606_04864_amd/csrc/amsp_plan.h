@@ -57,7 +57,11 @@ struct HostPlan {
   ivec eptr, uptr;
   std::vector<long long> ebase;
   long long nenv = 0;
-  ivec loc_rowptr, loc_col, loc_src;
+  // local CSR of every region (rows in local order, columns ascending): the
+  // row pointers here; the nloc column indices and source entries are built on
+  // the device (launch_local_csr)
+  ivec loc_rowptr;
+  long long nloc = 0;
   std::vector<int> mi, coff;
   ivec mult, inv_ptr, inv_sd, inv_loc;
   std::vector<int> ext_ptr;

@@ -19,6 +19,70 @@
 
 namespace amsp {
 
+// ----------------------------------------------------- local CSR ---------
+// The local CSR of every region, rows in local order, columns ascending:
+// the entries of A's row dof(l) whose column is in the region, with their
+// local index and the position of the value in A's CSR.  One workgroup per
+// region; the region's dofs sorted by global index (and the local index of
+// each) are staged in LDS (or in global scratch when the largest region does
+// not fit), looked up by binary search; each row is written in place by
+// insertion (rows are short).  Row pointers come from the host plan.
+__global__ void __launch_bounds__(WG) k_local_csr(Plan p, const int *__restrict__ rowptr,
+                                                  const int *__restrict__ col,
+                                                  int *__restrict__ loc_col,
+                                                  int *__restrict__ loc_src, int *gscratch,
+                                                  int use_lds) {
+  extern __shared__ int lds_i[];
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  int *sorted = use_lds ? lds_i : gscratch + 2 * (size_t)r0;
+  int *r2l = sorted + ni;
+  for (int l = threadIdx.x; l < ni; l += WG) {
+    const int rk = p.nat[r0 + l];
+    sorted[rk] = p.sd_dofs[r0 + l];
+    r2l[rk] = l;
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < ni; l += WG) {
+    const int g = p.sd_dofs[r0 + l];
+    const int o0 = p.loc_rowptr[r0 + l];
+    int cnt = 0;
+    for (int e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+      const int c = col[e];
+      int lo = 0, hi = ni;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sorted[mid] < c)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo == ni || sorted[lo] != c) continue;
+      const int lc = r2l[lo];
+      int y = o0 + cnt++;
+      while (y > o0 && loc_col[y - 1] > lc) {
+        loc_col[y] = loc_col[y - 1];
+        loc_src[y] = loc_src[y - 1];
+        --y;
+      }
+      loc_col[y] = lc;
+      loc_src[y] = e;
+    }
+  }
+}
+
+size_t local_csr_lds_bytes(int max_ni) { return (size_t)2 * max_ni * sizeof(int); }
+
+void launch_local_csr(hipStream_t s, const Plan &p, int max_ni, const int *rowptr, const int *col,
+                      int *loc_col, int *loc_src, int *gscratch) {
+  if (p.N == 0) return;
+  const size_t sm = local_csr_lds_bytes(max_ni);
+  const int use_lds = sm <= LOCAL_CSR_LDS_MAX ? 1 : 0;
+  if (use_lds) allow_lds(k_local_csr, sm);
+  hipLaunchKernelGGL(k_local_csr, dim3(p.N), dim3(WG), use_lds ? sm : 0, s, p, rowptr, col, loc_col,
+                     loc_src, gscratch, use_lds);
+}
+
 // ------------------------------------------------------------ S_i ---------
 __global__ void __launch_bounds__(WG) k_neumann_diag(Plan p, const double *__restrict__ val,
                                                      double *__restrict__ sdiag,
