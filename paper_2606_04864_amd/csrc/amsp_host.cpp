@@ -659,7 +659,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       else
         launch_env_solve_block<double>(h->stream, p, dgB64, erB64, ecB64, X, Yb, conv);
       launch_eig_rr(h->stream, p, P.max_ni, h->val, h->sdiag, bval, Yb, BY, X, GK, CC, tol, conv,
-                    h->lam);
+                    h->lam, !mixed);
       sweeps = it;
       if (it >= 4 && (it % 2 == 0 || it == h->opt.eig_maxit)) {
         HIP_TRY(hipGetLastError());

@@ -226,7 +226,8 @@ void launch_env_solve_block(hipStream_t s, const Plan &p, const T *diag, const T
 // BY: scratch like Y; GK: N*2*EIGP*EIGP doubles; CC: N*(EIGP*EIGP+EIGP).
 void launch_eig_rr(hipStream_t s, const Plan &p, int max_ni, const double *val,
                    const double *sdiag, const double *bval, const double *Y, double *BY, double *X,
-                   double *GK, double *CC, double tol, int *conv, double *lam);
+                   double *GK, double *CC, double tol, int *conv, double *lam,
+                   bool test_next);
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
                         double *phi, int pou);
 void launch_basis_convert(hipStream_t s, const double *phi, void *dst, size_t count, int bf16);

@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restr
                                                    double *__restrict__ X,
                                                    const double *__restrict__ CC, double tol,
                                                    int *__restrict__ conv,
-                                                   double *__restrict__ lam) {
+                                                   double *__restrict__ lam, int ntest_extra) {
   const int i = blockIdx.x;
   if (conv[i]) return;
   __shared__ double C[EIGP * EIGP], theta[EIGP];
@@ -385,6 +385,7 @@ __global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restr
   const size_t base = (size_t)p.vp_ptr[i] * EIGP;
   const bool small = ni <= EIGP;
   const int nchk = (m + 1 < ni ? m + 1 : ni);
+  const int ntest = m + ntest_extra;  // pairs whose residuals decide convergence
   const int w = t >> 6, lane = t & 63, q = lane >> 4, col = lane & 15;
   double rs = 0.0;  // this lane's sum of squared residuals of column col
   if (small) {
@@ -432,7 +433,7 @@ __global__ void __launch_bounds__(WG) k_eig_finish(Plan p, const double *__restr
   if (t == 0) {
     double worst = 0.0;
     if (!small) {
-      for (int j = 0; j < nchk; ++j) {
+      for (int j = 0; j < min(ntest, nchk); ++j) {
         double s = 0.0;
         for (int ww = 0; ww < WG / 64; ++ww) s += res[ww][j];
         s = sqrt(s);
@@ -713,7 +714,7 @@ void launch_eig_bval(hipStream_t s, const Plan &p, const double *val, const doub
 
 void launch_eig_rr(hipStream_t s, const Plan &p, int max_ni, const double *val,
                    const double *sdiag, const double *bval, const double *Y, double *BY, double *X,
-                   double *GK, double *CC, double tol, int *conv, double *lam) {
+                   double *GK, double *CC, double tol, int *conv, double *lam, bool test_next) {
   const int rows_per_wg = WG / EIGP;
   hipLaunchKernelGGL(k_eig_spmm, dim3((max_ni + rows_per_wg - 1) / rows_per_wg, p.N), dim3(WG), 0,
                      s, p, bval, Y, BY, conv);
@@ -723,7 +724,8 @@ void launch_eig_rr(hipStream_t s, const Plan &p, int max_ni, const double *val,
   // tests (on the vectors themselves), so this only saves Jacobi sweeps
   const double rel = fmax(1e-14, 1e-2 * tol);
   hipLaunchKernelGGL(k_eig_ritz, dim3(p.N), dim3(64), 0, s, rel * rel, GK, CC, conv);
-  hipLaunchKernelGGL(k_eig_finish, dim3(p.N), dim3(WG), 0, s, p, Y, BY, X, CC, tol, conv, lam);
+  hipLaunchKernelGGL(k_eig_finish, dim3(p.N), dim3(WG), 0, s, p, Y, BY, X, CC, tol, conv, lam,
+                     test_next ? 1 : 0);
 }
 
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
