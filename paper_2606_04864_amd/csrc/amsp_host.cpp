@@ -167,6 +167,7 @@ struct amsp_handle {
          *bC2 = nullptr, *bPart = nullptr;
   float *dg32 = nullptr, *er32 = nullptr, *ec32 = nullptr;
   int *loc_scratch = nullptr;  // local CSR build, large regions only
+  int *inv_work = nullptr, *max_mult_dev = nullptr;  // inverse map build
   double *W0 = nullptr;
   float *W0f = nullptr;
   // apply scratch
@@ -327,12 +328,10 @@ static amsp_status sync_status(amsp_handle *h, const int *dstatus, int N, int ma
 // Device copies of the coupling plan (filled by the coupling thread, copied
 // into the handle's plans at the join).
 struct CouplingDev {
-  int *mult = nullptr, *inv_ptr = nullptr, *inv_sd = nullptr, *inv_loc = nullptr;
   int *ext_ptr = nullptr, *ext_rowptr = nullptr, *ext_src = nullptr, *ext_loc = nullptr;
   int npairs = 0;
   int *pair_i = nullptr, *pair_j = nullptr, *pair_ptr = nullptr, *pair_l = nullptr,
       *pair_e = nullptr;
-  int max_mult = 1;  // largest number of regions containing one dof
 };
 
 static bool upload_coupling(amsp_handle *h, hipStream_t stream, CouplingDev &d);
@@ -431,11 +430,6 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     const CouplingDev &d = coupling.dev;
     Plan &pl = h->plan;
     CoarsePlan &cp = h->cplan;
-    pl.mult = d.mult;
-    h->max_mult = d.max_mult;
-    h->inv_ptr = d.inv_ptr;
-    h->inv_sd = d.inv_sd;
-    h->inv_loc = d.inv_loc;
     cp.ext_ptr = d.ext_ptr;
     cp.ext_rowptr = d.ext_rowptr;
     cp.ext_src = d.ext_src;
@@ -544,6 +538,22 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     h->loc_scratch = gs;
     launch_local_csr(h->stream, p, P.max_ni, h->rowptr, h->col, lc, ls, gs);
     HIP_TRY(hipGetLastError());
+  }
+  {  // multiplicities and the inverse map, from the regions on the device
+    const int n = h->n, ne = P.sd_ptr.back();
+    int *mult = nullptr, *iptr = nullptr, *isd = nullptr, *iloc = nullptr;
+    ALLOC(mult, int, std::max(n, 1));
+    ALLOC(iptr, int, n + 1);
+    ALLOC(isd, int, std::max(ne, 1));
+    ALLOC(iloc, int, std::max(ne, 1));
+    ALLOC(h->inv_work, int, (size_t)n + (n + 4 * WG - 1) / (4 * WG) + 1);
+    ALLOC(h->max_mult_dev, int, 1);
+    launch_inverse_map(h->stream, p, n, mult, iptr, isd, iloc, h->inv_work, h->max_mult_dev);
+    HIP_TRY(hipGetLastError());
+    p.mult = mult;
+    h->inv_ptr = iptr;
+    h->inv_sd = isd;
+    h->inv_loc = iloc;
   }
   p.mi = upload(h, P.mi, ok);
   p.coff = upload(h, P.coff, ok);
@@ -885,6 +895,10 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     ALLOC(h->mq, double, h->n);
     ALLOC(h->mt, double, h->n);
     ALLOC(h->mc, double, h->n);
+    HIP_TRY(hipMemcpyAsync(&h->max_mult, h->max_mult_dev, sizeof(int), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->max_mult = std::max(h->max_mult, 1);
     h->omega = h->opt.smoother_weight > 0.0 ? h->opt.smoother_weight : 1.0 / h->max_mult;
   }
   ALLOC(h->z, double, h->n);
@@ -909,11 +923,6 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
 static bool upload_coupling(amsp_handle *h, hipStream_t stream, CouplingDev &d) {
   const HostPlan &P = h->hp;
   bool ok = true;
-  d.mult = upload_on(h, stream, P.mult, ok);
-  for (int v : P.mult) d.max_mult = std::max(d.max_mult, v);
-  d.inv_ptr = upload_on(h, stream, P.inv_ptr, ok);
-  d.inv_sd = upload_on(h, stream, P.inv_sd, ok);
-  d.inv_loc = upload_on(h, stream, P.inv_loc, ok);
   if (h->nc > 0) {
     d.ext_ptr = upload_on(h, stream, P.ext_ptr, ok);
     d.ext_rowptr = upload_on(h, stream, P.ext_rowptr, ok);

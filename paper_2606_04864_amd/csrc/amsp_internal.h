@@ -199,6 +199,11 @@ void launch_col_direction(hipStream_t s, int n, size_t ld, int nr, const double 
 void launch_streams_to_env(hipStream_t s, const Plan &p, int ntilerows, const float *fst,
                            const float *bst, float *dg, float *er, float *ec);
 
+// mult[j] (regions containing dof j), inv_ptr (n + 1) and the per-dof lists
+// (subdomain, ascending-index position) ordered by subdomain; work holds
+// n + ceil(n / 1024) ints; *max_mult receives the largest multiplicity.
+void launch_inverse_map(hipStream_t s, const Plan &p, int n, int *mult, int *inv_ptr,
+                        int *inv_sd, int *inv_loc, int *work, int *max_mult);
 // Local CSR entries (loc_col, loc_src) of every region from the plan's row
 // pointers, dofs and ranks, and A's device CSR.  gscratch (2 * sum n_i ints)
 // is used only when 2 * max_ni ints exceed LOCAL_CSR_LDS_MAX bytes of LDS.

@@ -907,38 +907,9 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
   PSTART;
   (void)opt;
   const int n = P.n, N = P.N, nev = P.nev;
-  // Multiplicities and the inverse map dof -> (subdomain, local index), with
-  // the subdomains of each dof in ascending order: counts by atomic
-  // increments, offsets by a scan, unordered fill, then each dof's short
-  // list is ordered by subdomain.
-  {
-    P.mult.assign(n, 0);
-    parallel_chunks(N, [&](int i) {
-      for (int k = P.sd_ptr[i]; k < P.sd_ptr[i + 1]; ++k) atomic_inc(&P.mult[P.sd_dofs[k]]);
-    });
-    P.inv_ptr.resize(n + 1);
-    exclusive_scan(P.mult, P.inv_ptr, n);
-    P.inv_sd.resize(P.inv_ptr[n]);
-    P.inv_loc.resize(P.inv_ptr[n]);
-    ivec fill;
-    fill.assign(n, 0);
-    parallel_chunks(N, [&](int i) {
-      const int r0 = P.sd_ptr[i];
-      for (int k = r0; k < P.sd_ptr[i + 1]; ++k) {
-        const int g = P.sd_dofs[k];
-        const int at = P.inv_ptr[g] + atomic_inc(&fill[g]);
-        P.inv_sd[at] = i;
-        P.inv_loc[at] = P.nat[k];  // position in the region's ascending-index layout
-      }
-    });
-    sort_lists(P.inv_ptr, n, P.inv_sd, P.inv_loc);
-  }
-  for (int j = 0; j < n; ++j)
-    if (P.mult[j] == 0) {
-      msg = "dof not covered by any region";
-      return AMSP_ERR_PARTITION;
-    }
-  PTIME("inverse map");
+  // The multiplicities and the inverse map dof -> (subdomain, local index)
+  // are built on the device from the uploaded regions (launch_inverse_map).
+  // Every dof lies in the core of its own part, so each has at least one copy.
   P.ext_ptr.assign(N + 1, 0);
   P.ext_rowptr.assign(1, 0);
   P.ext_src.clear();

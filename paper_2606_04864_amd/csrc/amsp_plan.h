@@ -63,7 +63,6 @@ struct HostPlan {
   ivec loc_rowptr;
   long long nloc = 0;
   std::vector<int> mi, coff;
-  ivec mult, inv_ptr, inv_sd, inv_loc;
   std::vector<int> ext_ptr;
   ivec ext_rowptr, ext_src, ext_loc;
   std::vector<int> pair_i, pair_j, pair_ptr;

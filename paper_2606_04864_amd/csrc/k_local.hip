@@ -19,6 +19,131 @@
 
 namespace amsp {
 
+// ------------------------------------------------------- inverse map -----
+// mult[j] = number of regions containing dof j, inv_ptr = exclusive scan of
+// mult, and each dof's list (subdomain, position in the region's
+// ascending-global-index layout) ordered by subdomain: counts and fill by
+// atomic increments, then every short list sorted in place, so the result
+// does not depend on the order of the increments.
+// mult = fill = 0, *max_mult = 0
+__global__ void k_fill_int_dev(int n, int *__restrict__ mult, int *__restrict__ fill,
+                               int *__restrict__ max_mult) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    mult[j] = 0;
+    fill[j] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *max_mult = 0;
+}
+
+__global__ void __launch_bounds__(WG) k_count_mult(Plan p, int *__restrict__ mult) {
+  const int i = blockIdx.x;
+  for (int k = p.sd_ptr[i] + threadIdx.x; k < p.sd_ptr[i + 1]; k += WG)
+    atomicAdd(&mult[p.sd_dofs[k]], 1);
+}
+
+// exclusive scan in three passes: block totals (SCB entries per block), a
+// scan of the totals by one workgroup, then each block's entries
+constexpr int SCB = 4 * WG;
+__global__ void __launch_bounds__(WG) k_scan_totals(int n, const int *__restrict__ in,
+                                                    int *__restrict__ tot) {
+  __shared__ int sh[WG / 64];
+  const int b0 = blockIdx.x * SCB;
+  int acc = 0;
+  for (int u = 0; u < 4; ++u) {
+    const int j = b0 + u * WG + threadIdx.x;
+    if (j < n) acc += in[j];
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < WG / 64; ++w) t += sh[w];
+    tot[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(WG) k_scan_offsets(int nb, int *__restrict__ tot) {
+  __shared__ int sh[WG];
+  int carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += WG) {
+    const int j = c0 + threadIdx.x;
+    const int v = j < nb ? tot[j] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < WG; o <<= 1) {  // inclusive scan (Hillis-Steele)
+      const int a = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (j < nb) tot[j] = carry + sh[threadIdx.x] - v;  // exclusive
+    carry += sh[WG - 1];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(WG) k_scan_apply(int n, const int *__restrict__ in,
+                                                   const int *__restrict__ off,
+                                                   int *__restrict__ out) {
+  __shared__ int wt[WG / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int j0 = blockIdx.x * SCB + 4 * t;  // this thread's four consecutive entries
+  int v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = j0 + u < n ? in[j0 + u] : 0;
+  const int s4 = v[0] + v[1] + v[2] + v[3];
+  int x = s4;  // inclusive scan over the wavefront
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wt[w] = x;
+  __syncthreads();
+  int e = off[blockIdx.x] + x - s4;
+  for (int ww = 0; ww < w; ++ww) e += wt[ww];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (j0 + u < n) out[j0 + u] = e;
+    e += v[u];
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == WG - 1) out[n] = e;  // the total (entries past n are 0)
+}
+
+__global__ void __launch_bounds__(WG) k_fill_inverse(Plan p, const int *__restrict__ inv_ptr,
+                                                     int *__restrict__ fill, int *__restrict__ inv_sd,
+                                                     int *__restrict__ inv_loc) {
+  const int i = blockIdx.x;
+  for (int k = p.sd_ptr[i] + threadIdx.x; k < p.sd_ptr[i + 1]; k += WG) {
+    const int g = p.sd_dofs[k];
+    const int at = inv_ptr[g] + atomicAdd(&fill[g], 1);
+    inv_sd[at] = i;
+    inv_loc[at] = p.nat[k];
+  }
+}
+
+__global__ void __launch_bounds__(WG) k_sort_inverse(int n, const int *__restrict__ inv_ptr,
+                                                     int *__restrict__ inv_sd,
+                                                     int *__restrict__ inv_loc,
+                                                     int *__restrict__ max_mult) {
+  const int j = blockIdx.x * WG + threadIdx.x;
+  if (j >= n) return;
+  const int a = inv_ptr[j], b = inv_ptr[j + 1];
+  for (int e = a + 1; e < b; ++e) {
+    const int sd = inv_sd[e], lc = inv_loc[e];
+    int y = e;
+    while (y > a && inv_sd[y - 1] > sd) {
+      inv_sd[y] = inv_sd[y - 1];
+      inv_loc[y] = inv_loc[y - 1];
+      --y;
+    }
+    inv_sd[y] = sd;
+    inv_loc[y] = lc;
+  }
+  atomicMax(max_mult, b - a);
+}
+
 // ----------------------------------------------------- local CSR ---------
 // The local CSR of every region, rows in local order, columns ascending:
 // the entries of A's row dof(l) whose column is in the region, with their
@@ -69,6 +194,23 @@ __global__ void __launch_bounds__(WG) k_local_csr(Plan p, const int *__restrict_
       loc_src[y] = e;
     }
   }
+}
+
+void launch_inverse_map(hipStream_t s, const Plan &p, int n, int *mult, int *inv_ptr,
+                        int *inv_sd, int *inv_loc, int *work, int *max_mult) {
+  if (n <= 0 || p.N == 0) return;
+  const int nb = (n + SCB - 1) / SCB;
+  int *fill = work, *tot = work + n;  // work: n + nb ints
+  const int zb = (n + WG - 1) / WG;
+  hipLaunchKernelGGL(k_fill_int_dev, dim3(zb < 16384 ? zb : 16384), dim3(WG), 0, s, n, mult, fill,
+                     max_mult);
+  hipLaunchKernelGGL(k_count_mult, dim3(p.N), dim3(WG), 0, s, p, mult);
+  hipLaunchKernelGGL(k_scan_totals, dim3(nb), dim3(WG), 0, s, n, mult, tot);
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(WG), 0, s, nb, tot);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(WG), 0, s, n, mult, tot, inv_ptr);
+  hipLaunchKernelGGL(k_fill_inverse, dim3(p.N), dim3(WG), 0, s, p, inv_ptr, fill, inv_sd, inv_loc);
+  hipLaunchKernelGGL(k_sort_inverse, dim3((n + WG - 1) / WG), dim3(WG), 0, s, n, inv_ptr, inv_sd,
+                     inv_loc, max_mult);
 }
 
 size_t local_csr_lds_bytes(int max_ni) { return (size_t)2 * max_ni * sizeof(int); }
