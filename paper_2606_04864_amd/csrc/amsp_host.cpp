@@ -179,6 +179,8 @@ struct amsp_handle {
   double *part_a = nullptr, *part_b = nullptr, *part_c = nullptr, *part_d = nullptr;
   double *scal = nullptr;
   PcgState *st = nullptr;
+  PcgState *st_host = nullptr;               // two pinned slots for state copies
+  hipEvent_t st_ev[2] = {nullptr, nullptr};  // completion of each slot's copy
   double *hist = nullptr;  // recursive residual history of the last PCG call
   int hist_cap = 0, hist_len = 0;
   double hist_f2 = 0.0;
@@ -200,6 +202,9 @@ struct amsp_handle {
   int ev_count[5] = {0, 0, 0, 0, 0};  // launches per class seen by tstart (for the stride)
   ~amsp_handle() {
     for (hipEvent_t e : evs) hipEventDestroy(e);
+    for (hipEvent_t e : st_ev)
+      if (e) hipEventDestroy(e);
+    if (st_host) hipHostFree(st_host);
   }
 };
 
@@ -1463,6 +1468,11 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
     init.hist_cap = h->hist_cap;
     HIP_TRY(hipMemcpyAsync(h->st, &init, sizeof(PcgState), hipMemcpyHostToDevice, h->stream));
   }
+  if (!h->st_host) {
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h->st_host), 2 * sizeof(PcgState),
+                          hipHostMallocDefault));
+    for (hipEvent_t &e : h->st_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   double t0 = now_ms();
   amsp_status final_status = AMSP_OK;
   int tot_it = 0;
@@ -1488,26 +1498,30 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
       HIP_TRY(hipGetLastError());
       const int *done = &h->st->done;
       double *pold = h->p0, *pnew = h->p1;
-      int next = h->opt.chunk, prev_it = 0;
+      int prev_it = 0;
       double prev_rr = -1.0;
       // step index of the next launch (iterations completed before it) and
       // whether it is the first step after this (re)start
       int t = fresh ? 0 : hs.it;
       bool first = true;
-      for (;;) {
-        HIP_TRY(hipMemcpyAsync(&hs, h->st, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        if (hs.done) break;
-        // size the next chunk from the observed residual decay so that few
-        // launches follow convergence (they would return at once anyway)
+      HIP_TRY(hipMemcpyAsync(&hs, h->st, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      // Chunks of steps run back to back.  Behind each chunk the state is
+      // copied to a pinned slot; the host reads a chunk's copy while the
+      // next chunk runs, so the device does not wait for the host between
+      // chunks.  Chunk sizes follow the observed residual decay (minus the
+      // steps still in flight), so that few steps are enqueued after
+      // convergence; those return at once.
+      int pend = -1, pend_steps = 0;  // slot of the copy in flight, steps of its chunk
+      while (!hs.done) {
+        int next = h->opt.chunk;
         if (prev_rr > 0.0 && hs.it > prev_it && hs.rr < prev_rr && hs.rr > 0.0) {
           const double rate = std::log(hs.rr / prev_rr) / (double)(hs.it - prev_it);
           const double need = std::log(hs.tol2 / hs.rr) / rate;
-          next = (int)std::ceil(need) + 1;  // + 1: convergence is seen by the following step
-          next = std::max(1, std::min(next, h->opt.chunk));
+          // + 1: convergence is seen by the following step
+          next = (int)std::ceil(need) + 1 - pend_steps;
+          next = std::max(pend >= 0 ? 0 : 1, std::min(next, h->opt.chunk));
         }
-        prev_rr = hs.rr;
-        prev_it = hs.it;
         for (int c = 0; c < next; ++c) {
           h->cur_t = t;
           int tk = tstart(h, 0);
@@ -1526,7 +1540,24 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
           first = false;
         }
         HIP_TRY(hipGetLastError());
+        int slot = -1;
+        if (next > 0) {
+          slot = pend == 0 ? 1 : 0;
+          HIP_TRY(hipMemcpyAsync(&h->st_host[slot], h->st, sizeof(PcgState),
+                                 hipMemcpyDeviceToHost, h->stream));
+          HIP_TRY(hipEventRecord(h->st_ev[slot], h->stream));
+        }
+        if (pend >= 0) {  // the previous chunk's state, read while this chunk runs
+          HIP_TRY(hipEventSynchronize(h->st_ev[pend]));
+          prev_rr = hs.rr;
+          prev_it = hs.it;
+          hs = h->st_host[pend];
+        }
+        pend = slot;
+        pend_steps = slot >= 0 ? next : 0;
       }
+      // steps enqueued after convergence were no-ops: hs is the final state
+      HIP_TRY(hipStreamSynchronize(h->stream));
       h->seg_cut.push_back(hs.it);  // steps >= hs.it of this segment were no-ops
       ++h->cur_seg;
       h->cur_t = -1;
