@@ -181,6 +181,8 @@ struct amsp_handle {
   PcgState *st = nullptr;
   PcgState *st_host = nullptr;               // two pinned slots for state copies
   hipEvent_t st_ev[2] = {nullptr, nullptr};  // completion of each slot's copy
+  double *gm_host = nullptr;                 // GMRES: two pinned slots of 129 coefficients
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};
   double *hist = nullptr;  // recursive residual history of the last PCG call
   int hist_cap = 0, hist_len = 0;
   double hist_f2 = 0.0;
@@ -204,7 +206,10 @@ struct amsp_handle {
     for (hipEvent_t e : evs) hipEventDestroy(e);
     for (hipEvent_t e : st_ev)
       if (e) hipEventDestroy(e);
+    for (hipEvent_t e : gm_ev)
+      if (e) hipEventDestroy(e);
     if (st_host) hipHostFree(st_host);
+    if (gm_host) hipHostFree(gm_host);
   }
 };
 
@@ -1666,8 +1671,33 @@ extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u
   amsp_status final_status = AMSP_OK;
   int tot_it = 0, tot_restarts = 0, all_conv = 1;
   double worst_true = 0.0, worst_est = 0.0, worst_floor = 0.0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), coef(129);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   std::vector<double> g2;
+  if (!h->gm_host) {
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h->gm_host), 2 * 129 * sizeof(double),
+                          hipHostMallocDefault));
+    for (hipEvent_t &e : h->gm_ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // One Arnoldi step on the device: z_j = M^-1 v_j, w = A z_j, two rounds of
+  // classical Gram-Schmidt against v_0..v_j, v_{j+1} = w / |w|; its 129
+  // coefficients are copied behind it to pinned slot j % 2.
+  auto arnoldi_step = [&](int j) -> amsp_status {
+    double *vj = V + (size_t)j * ld, *zj = Z + (size_t)j * ld;
+    amsp_status st = apply_prec(h, vj, zj, nullptr, nullptr);
+    if (st != AMSP_OK) return st;
+    launch_spmv_sell(s, n, h->sptr, h->scol, h->sval, zj, w);
+    launch_gs_dots(s, n, V, ld, j + 1, w, part, sc);
+    launch_gs_update(s, n, V, ld, j + 1, sc, w, nullptr);
+    launch_gs_dots(s, n, V, ld, j + 1, w, part, sc + 64);
+    launch_gs_update(s, n, V, ld, j + 1, sc + 64, w, pn);
+    launch_sum_partials(s, pn, nb, sc + 128);
+    launch_gs_normalize(s, n, w, sc + 128, V + (size_t)(j + 1) * ld);
+    HIP_TRY(hipMemcpyAsync(h->gm_host + (j & 1) * 129, sc, 129 * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(h->gm_ev[j & 1], s));
+    HIP_TRY(hipGetLastError());
+    return AMSP_OK;
+  };
   for (int rhs = 0; rhs < nrhs; ++rhs) {
     const double *f = f_dev + (size_t)rhs * n;
     double *x = u_dev + (size_t)rhs * n;
@@ -1692,22 +1722,32 @@ extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int k = 0;
+      // Step j + 1 is enqueued before the host reads step j's coefficients,
+      // so the device runs on while the host applies the rotations, unless
+      // the estimate's recent decay says that step j converges (a step
+      // enqueued after the last one is harmless: its results are not used).
+      double est_prev = -1.0;
+      bool queued = false;  // step j already enqueued
       for (int j = 0; j < m; ++j) {
-        double *vj = V + (size_t)j * ld, *zj = Z + (size_t)j * ld;
-        amsp_status st = apply_prec(h, vj, zj, nullptr, nullptr);
-        if (st != AMSP_OK) {
-          release();
-          return st;
+        if (!queued) {
+          const amsp_status st = arnoldi_step(j);
+          if (st != AMSP_OK) {
+            release();
+            return st;
+          }
         }
-        launch_spmv_sell(s, n, h->sptr, h->scol, h->sval, zj, w);
-        launch_gs_dots(s, n, V, ld, j + 1, w, part, sc);
-        launch_gs_update(s, n, V, ld, j + 1, sc, w, nullptr);
-        launch_gs_dots(s, n, V, ld, j + 1, w, part, sc + 64);
-        launch_gs_update(s, n, V, ld, j + 1, sc + 64, w, pn);
-        launch_sum_partials(s, pn, nb, sc + 128);
-        launch_gs_normalize(s, n, w, sc + 128, V + (size_t)(j + 1) * ld);
-        HIP_TRY(hipMemcpyAsync(coef.data(), sc, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        double pred = est;  // estimate expected after step j
+        if (est_prev > 0.0 && est < est_prev) pred = est * (est / est_prev);
+        queued = j + 1 < m && it + 1 < maxit && pred > rtol;
+        if (queued) {
+          const amsp_status st = arnoldi_step(j + 1);
+          if (st != AMSP_OK) {
+            release();
+            return st;
+          }
+        }
+        HIP_TRY(hipEventSynchronize(h->gm_ev[j & 1]));
+        const double *coef = h->gm_host + (j & 1) * 129;
         double *hj = H.data() + (size_t)j * (m + 1);  // column j of H
         for (int i = 0; i <= j; ++i) hj[i] = coef[i] + coef[64 + i];
         const double hnext = std::sqrt(coef[128]);
@@ -1727,6 +1767,7 @@ extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u
         ++it;
         k = j + 1;
         g2.push_back(g[j + 1] * g[j + 1]);
+        est_prev = est;
         est = nf > 0.0 ? std::fabs(g[j + 1]) / nf : 0.0;
         if (std::fabs(g[j + 1]) <= rtol * nf || it >= maxit || !(hnext > 0.0) || !(rho > 0.0)) break;
       }
