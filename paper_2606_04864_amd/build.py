@@ -2,7 +2,7 @@
 
 Usage: python paper_2606_04864_amd/build.py   (or call build()).
 Object files go to _build/ at the repository root (git-ignored); the shared
-library lands next to this file so that the binding and the GPU machine find it.
+library lands next to this file, where the Python binding loads it.
 """
 from __future__ import annotations
 
