@@ -673,6 +673,26 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-5 : 1e-12);
     std::vector<int> hconv(h->N);
     int sweeps = 0, unconv = h->N;
+    // Convergence is checked every second sweep from the fourth.  Each
+    // check's flags are copied to pinned memory behind its sweep and read
+    // two sweeps later, so the device does not wait for the host; every
+    // kernel of a sweep skips converged regions, so the sweeps run past the
+    // point where all have converged change nothing.
+    int *conv_host = nullptr;
+    hipEvent_t conv_ev = nullptr;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&conv_host), h->N * sizeof(int),
+                          hipHostMallocDefault));
+    struct PinnedFlags {
+      int *p;
+      hipEvent_t e;
+      ~PinnedFlags() {
+        if (e) (void)hipEventDestroy(e);
+        if (p) (void)hipHostFree(p);
+      }
+    } conv_guard{conv_host, nullptr};
+    HIP_TRY(hipEventCreateWithFlags(&conv_ev, hipEventDisableTiming));
+    conv_guard.e = conv_ev;
+    int pending = 0;  // sweep whose flags are in flight to conv_host (0: none)
     for (int it = 1; it <= h->opt.eig_maxit; ++it) {
       if (mixed)
         launch_env_solve_block<float>(h->stream, p, dgB32, erB32, ecB32, X, Yb, conv);
@@ -683,11 +703,19 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       sweeps = it;
       if (it >= 4 && (it % 2 == 0 || it == h->opt.eig_maxit)) {
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(hconv.data(), conv, h->N * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        unconv = 0;
-        for (int v : hconv) unconv += (v == 0);
-        if (unconv == 0) break;
+        if (pending > 0) {
+          HIP_TRY(hipEventSynchronize(conv_ev));
+          unconv = 0;
+          for (int i = 0; i < h->N; ++i) unconv += (conv_host[i] == 0);
+          if (unconv == 0) {
+            sweeps = pending;
+            break;
+          }
+        }
+        HIP_TRY(hipMemcpyAsync(conv_host, conv, h->N * sizeof(int), hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipEventRecord(conv_ev, h->stream));
+        pending = it;
       }
     }
     HIP_TRY(hipMemcpyAsync(hconv.data(), conv, h->N * sizeof(int), hipMemcpyDeviceToHost, h->stream));
