@@ -423,6 +423,9 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   const bool mixed = h->opt.precision != AMSP_FP64;
   double t0 = now_ms();
   bool ok = true;
+  // device blocks whose last reader is still queued: returned to the
+  // arena after the final synchronisation instead of after a wait of their own
+  std::vector<void *> deferred;
   SideStream up;  // declared before the task: outlives the thread that uses it
   HIP_TRY(up.create());
   int device = 0;
@@ -845,8 +848,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     if (mixed) {
       ALLOC(h->W0f, float, (size_t)T0 * T0 * TE);
       launch_dense_tiles_to_f32(h->stream, h->W0, h->W0f, T0);
-      HIP_TRY(hipStreamSynchronize(h->stream));
-      h->mem.free_one(h->W0);
+      deferred.push_back(h->W0);
       h->W0 = nullptr;
     }
     h->sinfo.phase_ms[6] = now_ms() - t5;
@@ -871,8 +873,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       launch_env_from_tiles<double>(h->stream, p, h->ntilerows, h->fac64, h->erow64, h->ecol64);
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->mem.free_one(h->fac64);
+    deferred.push_back(h->fac64);
     h->fac64 = nullptr;
   }
   if (mixed) {
@@ -889,7 +890,6 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       }
       launch_basis_convert(h->stream, h->phi64, h->phi_lo, (size_t)sum_ni * h->nev, bf ? 1 : 0);
     }
-    HIP_TRY(hipStreamSynchronize(h->stream));
   }
   // direct operand indices of the inverse map for the scatter
   {
@@ -951,6 +951,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   ALLOC(h->st, PcgState, 1);
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->mem.free_one(status);
+  for (void *b : deferred) h->mem.free_one(b);
   h->sinfo.phase_ms[7] = now_ms() - t0 + host_plan_ms;
   if (h->sinfo.eig_unconverged > 0) {
     h->err = std::to_string(h->sinfo.eig_unconverged) + " subdomain eigensolves did not converge";
