@@ -194,7 +194,9 @@ amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
  * accepted if it is below max(rtol, floor) with floor = eps || |A||u| || / ||f||
  * (the rounding level of any float64 residual); otherwise CG restarts from the
  * true residual (at most 3 times).  Blocks; info may be NULL.  On
- * AMSP_ERR_PCG_NOCONV u holds the last iterate and the handle stays valid. */
+ * AMSP_ERR_PCG_NOCONV u holds the last iterate and the handle stays valid.
+ * The first call allocates two pinned host slots for the solver state (a few
+ * hundred bytes), kept until amsp_destroy. */
 amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                      double rtol, int32_t maxit, amsp_info *info);
 /* With nrhs >= 2 (columns n apart) and the additive operator, up to 16
@@ -220,7 +222,9 @@ amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t
  * kept in the handle's cache): (2 restart + 1) n doubles.  info: iterations =
  * GMRES steps (preconditioner applications), restarts = cycles after the
  * first, relres_recursive = last residual estimate; the history getter below
- * returns the estimates after every step.  Blocks; info may be NULL. */
+ * returns the estimates after every step.  Blocks; info may be NULL.  The
+ * first call allocates two pinned host slots of 129 doubles for the step
+ * coefficients, kept until amsp_destroy. */
 #define AMSP_GMRES_MAX_RESTART 64
 amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                        int32_t restart, double rtol, int32_t maxit, amsp_info *info);
