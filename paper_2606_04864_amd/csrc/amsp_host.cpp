@@ -1321,7 +1321,7 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
   };
-  std::vector<double> f2(nr), rr(nr), rz(nr), dot(nr), coef(nr);
+  std::vector<double> f2(nr), rr(nr);
   std::vector<int> active(nr), its(nr, 0);
   std::vector<double> hist;
   launch_fill(s, tot, U, 0.0);
@@ -1351,51 +1351,86 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
   // as in amsp_pcg: stop on the recursive residuals, recompute f - A u, and
   // restart the columns whose true residual is above max(rtol, floor) from
   // it (at most 3 times)
+  // The per-column scalars stay on the device (ColCgState).  Behind every
+  // step the state is copied to a pinned slot, and the host reads step t's
+  // copy while step t + 1 runs; once no column is active the step already
+  // enqueued changes nothing (all its coefficients are zero).
+  ColCgState *cs = nullptr, *cs_host = nullptr;
+  ALLOC(cs, ColCgState, 1);
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&cs_host), 2 * sizeof(ColCgState),
+                        hipHostMallocDefault));
+  hipEvent_t cev[2] = {nullptr, nullptr};
+  struct Guard {
+    ColCgState *p;
+    hipEvent_t *e;
+    ~Guard() {
+      for (int k = 0; k < 2; ++k)
+        if (e[k]) (void)hipEventDestroy(e[k]);
+      if (p) (void)hipHostFree(p);
+    }
+  } guard{cs_host, cev};
+  for (hipEvent_t &e : cev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  {
+    ColCgState init{};
+    for (int k = 0; k < nr; ++k) {
+      init.f2[k] = f2[k];
+      init.rr[k] = rr[k];
+    }
+    HIP_TRY(hipMemcpyAsync(cs, &init, sizeof(ColCgState), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  const double rtol2 = rtol * rtol;
   for (int restarts = 0;; ++restarts) {
     if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) return st;
     launch_col_dots(s, n, ld, nr, R, Z, part, sc + 16);
-    HIP_TRY(to_host(sc + 16, rz.data()));
+    HIP_TRY(hipMemcpyAsync(cs->rz, sc + 16, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    {
+      int act[EIGP] = {0};
+      for (int k = 0; k < nr; ++k) act[k] = active[k];
+      HIP_TRY(hipMemcpyAsync(cs->active, act, sizeof(act), hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipMemcpyAsync(Pd, Z, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
-    while (any_active() && it < maxit) {
+    int pend = -1;  // slot of the state copy in flight
+    bool live = any_active();
+    while (live && it < maxit) {
       launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, Pd, Q);
       launch_col_dots(s, n, ld, nr, Pd, Q, part, sc + 16);
-      HIP_TRY(to_host(sc + 16, dot.data()));
-      for (int k = 0; k < nr; ++k) {
-        coef[k] = 0.0;
-        if (!active[k]) continue;
-        if (!(dot[k] > 0.0) || !std::isfinite(rz[k] / dot[k])) {
-          breakdown = true;
-          active[k] = 0;
-          continue;
-        }
-        coef[k] = rz[k] / dot[k];
-      }
-      HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_col_alpha(s, nr, cs, sc + 16, sc);
       launch_col_update(s, n, ld, nr, sc, Pd, Q, U, R, part, sc + 32);
-      ++it;
       if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) return st;
       launch_col_dots(s, n, ld, nr, R, Z, part, sc + 16);
-      HIP_TRY(to_host(sc + 32, rr.data()));
-      HIP_TRY(to_host(sc + 16, dot.data()));
-      hist.push_back(rr[nr - 1]);
-      for (int k = 0; k < nr; ++k) {
-        coef[k] = 0.0;
-        if (!active[k]) continue;
-        ++its[k];
-        if (!std::isfinite(rr[k])) {
-          breakdown = true;
-          active[k] = 0;
-          continue;
-        }
-        if (rr[k] <= rtol * rtol * f2[k]) {
-          active[k] = 0;
-          continue;
-        }
-        coef[k] = dot[k] / rz[k];
-        rz[k] = dot[k];
-      }
-      HIP_TRY(hipMemcpyAsync(sc, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_col_beta(s, nr, cs, sc + 32, sc + 16, rtol2, sc);
       launch_col_direction(s, n, ld, nr, sc, Z, Pd);
+      const int slot = pend == 0 ? 1 : 0;
+      HIP_TRY(hipMemcpyAsync(cs_host + slot, cs, sizeof(ColCgState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(cev[slot], s));
+      HIP_TRY(hipGetLastError());
+      ++it;
+      if (pend >= 0) {  // the previous step's state, read while this step runs
+        HIP_TRY(hipEventSynchronize(cev[pend]));
+        hist.push_back(cs_host[pend].rr[nr - 1]);
+        if (cs_host[pend].nact == 0) {
+          --it;  // this step found no active column
+          pend = -1;
+          break;
+        }
+      }
+      pend = slot;
+    }
+    if (pend >= 0) {  // the last step's state
+      HIP_TRY(hipEventSynchronize(cev[pend]));
+      hist.push_back(cs_host[pend].rr[nr - 1]);
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    {
+      ColCgState fin{};
+      HIP_TRY(hipMemcpy(&fin, cs, sizeof(ColCgState), hipMemcpyDeviceToHost));
+      for (int k = 0; k < nr; ++k) {
+        rr[k] = fin.rr[k];
+        its[k] = fin.its[k];
+        active[k] = fin.active[k];
+      }
+      breakdown = breakdown || fin.breakdown != 0;
     }
     for (int k = 0; k < nr; ++k) rec[k] = f2[k] > 0.0 ? std::sqrt(rr[k] / f2[k]) : 0.0;
     // true residuals (left in R) and, where needed, the attainable floors
@@ -1439,6 +1474,7 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
   HIP_TRY(hipMemcpyAsync(h->hist, hist.data(), h->hist_len * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   release();
+  h->mem.free_one(cs);
   if (breakdown) {
     h->err = "CG breakdown in a column (p.Ap <= 0 or a non-finite value)";
     return AMSP_ERR_BREAKDOWN;

@@ -194,6 +194,21 @@ void launch_col_update(hipStream_t s, int n, size_t ld, int nr, const double *al
                        double *rr);
 void launch_col_direction(hipStream_t s, int n, size_t ld, int nr, const double *beta,
                           const double *Z, double *P);
+// Scalars of the per-column CG recurrences, kept on the device (nr <= EIGP).
+struct ColCgState {
+  double rz[EIGP], f2[EIGP], rr[EIGP];  // r.z, f.f and r.r (after the last update) per column
+  int active[EIGP], its[EIGP];
+  int breakdown, nact;  // a column broke down; columns still active
+};
+// alpha_k = (r.z)_k / (p.Ap)_k for active columns (0 otherwise); a column with
+// p.Ap <= 0 or a non-finite ratio stops and sets breakdown.
+void launch_col_alpha(hipStream_t s, int nr, ColCgState *cs, const double *pq, double *alpha);
+// After the update: an active column with r.r <= rtol2 f.f stops (a
+// non-finite r.r stops it with breakdown); the others take beta_k =
+// (r.z)'_k / (r.z)_k and keep (r.z)'.  Copies rr into the state, counts the
+// active columns.
+void launch_col_beta(hipStream_t s, int nr, ColCgState *cs, const double *rr, const double *rz,
+                     double rtol2, double *beta);
 // f32 factor of the mixed forms from its streams back into packed diagonal
 // tiles + envelope (the layout of launch_env_solve_block)
 void launch_streams_to_env(hipStream_t s, const Plan &p, int ntilerows, const float *fst,

@@ -402,6 +402,61 @@ void launch_col_update(hipStream_t s, int n, size_t ld, int nr, const double *al
   hipLaunchKernelGGL(k_col_reduce, dim3(nr), dim3(WG), 0, s, nb, part, rr);
 }
 
+__global__ void __launch_bounds__(64) k_col_alpha(int nr, ColCgState *cs,
+                                                  const double *__restrict__ pq,
+                                                  double *__restrict__ alpha) {
+  const int k = threadIdx.x;
+  if (k >= nr) return;
+  double c = 0.0;
+  if (cs->active[k]) {
+    const double q = cs->rz[k] / pq[k];
+    if (!(pq[k] > 0.0) || !isfinite(q)) {
+      cs->breakdown = 1;
+      cs->active[k] = 0;
+    } else {
+      c = q;
+    }
+  }
+  alpha[k] = c;
+}
+
+__global__ void __launch_bounds__(64) k_col_beta(int nr, ColCgState *cs,
+                                                 const double *__restrict__ rr,
+                                                 const double *__restrict__ rz, double rtol2,
+                                                 double *__restrict__ beta) {
+  const int k = threadIdx.x;
+  int act = 0;
+  if (k < nr) {
+    double c = 0.0;
+    cs->rr[k] = rr[k];
+    if (cs->active[k]) {
+      cs->its[k] += 1;
+      if (!isfinite(rr[k])) {
+        cs->breakdown = 1;
+        cs->active[k] = 0;
+      } else if (rr[k] <= rtol2 * cs->f2[k]) {
+        cs->active[k] = 0;
+      } else {
+        c = rz[k] / cs->rz[k];
+        cs->rz[k] = rz[k];
+      }
+    }
+    beta[k] = c;
+    act = cs->active[k];
+  }
+  const unsigned long long m = __ballot(act != 0);
+  if (k == 0) cs->nact = __popcll(m);
+}
+
+void launch_col_alpha(hipStream_t s, int nr, ColCgState *cs, const double *pq, double *alpha) {
+  hipLaunchKernelGGL(k_col_alpha, dim3(1), dim3(64), 0, s, nr, cs, pq, alpha);
+}
+
+void launch_col_beta(hipStream_t s, int nr, ColCgState *cs, const double *rr, const double *rz,
+                     double rtol2, double *beta) {
+  hipLaunchKernelGGL(k_col_beta, dim3(1), dim3(64), 0, s, nr, cs, rr, rz, rtol2, beta);
+}
+
 void launch_col_direction(hipStream_t s, int n, size_t ld, int nr, const double *beta,
                           const double *Z, double *P) {
   hipLaunchKernelGGL(k_col_direction, dim3(col_blocks(n), nr), dim3(WG), 0, s, n, ld, nr, beta, Z, P);
