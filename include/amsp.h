@@ -287,6 +287,14 @@ amsp_status amsp_plan_regions(const amsp_csr *A, const int32_t *partition, int32
 amsp_status amsp_selftest_mfma(const double *a_host, const double *b_host, double *d_host);
 
 void amsp_destroy(amsp_handle *h);
+/* Returns the process-wide caches to the system: device blocks kept for
+ * later setups (freed with hipFree on their own device) and page-locked
+ * planner blocks; stops and joins the planner's worker threads.  Blocks
+ * still owned by live handles are untouched.  Later calls re-create the
+ * caches on demand.  Must not run concurrently with any other call.  The
+ * library also does this from an exit handler that runs before the HIP
+ * runtime's own teardown. */
+void amsp_release_caches(void);
 const char *amsp_status_string(amsp_status s);
 const char *amsp_last_error(const amsp_handle *h);
 /* Message of the last failed amsp_setup in this thread (no handle exists). */

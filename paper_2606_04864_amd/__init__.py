@@ -120,6 +120,8 @@ _lib.amsp_plan_regions.restype = _i32
 _lib.amsp_selftest_mfma.argtypes = [_vp, _vp, _vp]
 _lib.amsp_selftest_mfma.restype = _i32
 _lib.amsp_destroy.argtypes = [_vp]
+_lib.amsp_release_caches.argtypes = []
+_lib.amsp_release_caches.restype = None
 _lib.amsp_status_string.argtypes = [_i32]
 _lib.amsp_status_string.restype = ctypes.c_char_p
 _lib.amsp_last_error.argtypes = [_vp]
@@ -130,7 +132,8 @@ _lib.amsp_setup_error.restype = ctypes.c_char_p
 EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts", "amsp_pcg",
             "amsp_gmres",
             "amsp_spmv", "amsp_grad_values", "amsp_get_setup_info", "amsp_get_pcg_history", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
-            "amsp_get_region", "amsp_plan_regions", "amsp_selftest_mfma", "amsp_destroy", "amsp_status_string",
+            "amsp_get_region", "amsp_plan_regions", "amsp_selftest_mfma", "amsp_destroy",
+            "amsp_release_caches", "amsp_status_string",
             "amsp_last_error", "amsp_setup_error"]
 
 

@@ -8,6 +8,7 @@
 #include <climits>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <map>
@@ -34,12 +35,20 @@ thread_local std::string g_setup_error;
 // so that no queued work can still touch it when it is handed out again.
 constexpr size_t kDevCacheMin = size_t(1) << 20;
 constexpr size_t kDevCacheCap = size_t(8) << 30;
+void release_dev_cache();
 struct DevCache {
   std::mutex mu;
   std::multimap<std::pair<int, size_t>, void *> free_blocks;  // (device, size) -> block
   size_t held = 0;
   static DevCache &get() {
-    static DevCache *c = new DevCache();  // never destroyed: handles may outlive statics
+    // never destroyed (handles may outlive statics); the free blocks are
+    // released at exit, before the HIP runtime tears down (handlers run in
+    // reverse order of registration, and this one is registered after the
+    // runtime's first use)
+    static DevCache *c = [] {
+      std::atexit(release_dev_cache);
+      return new DevCache();
+    }();
     return *c;
   }
   // a cached block of at least `size` bytes (at most a quarter more), with
@@ -62,7 +71,23 @@ struct DevCache {
     held += size;
     return true;
   }
+  // hipFree every cached block on its own device (none is in use: a block
+  // enters the cache only after a device-wide synchronisation)
+  void release() {
+    std::lock_guard<std::mutex> lk(mu);
+    if (free_blocks.empty()) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : free_blocks) {
+      (void)hipSetDevice(kv.first.first);
+      (void)hipFree(kv.second);
+    }
+    (void)hipSetDevice(cur);
+    free_blocks.clear();
+    held = 0;
+  }
 };
+void release_dev_cache() { DevCache::get().release(); }
 
 struct DevArena {
   struct Blk {
@@ -733,6 +758,11 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     }
     ALLOC(h->phi64, double, (size_t)sum_ni * h->nev);
     launch_build_basis(h->stream, p, h->sdiag, X, h->phi64, h->opt.pou);
+    // mixed forms: A0 is formed from the basis as stored (rounded), so the
+    // coarse term stays the Galerkin projection of the basis it applies
+    if (mixed)
+      launch_basis_round(h->stream, h->phi64, (size_t)sum_ni * h->nev,
+                         h->opt.precision == AMSP_MIXED_BF16 ? 1 : 0);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (void *b : {(void *)dgB32, (void *)erB32, (void *)ecB32, (void *)dgB64, (void *)erB64,
@@ -2015,6 +2045,11 @@ extern "C" amsp_status amsp_selftest_mfma(const double *a_host, const double *b_
   }
   hipFree(d);
   return st;
+}
+
+extern "C" void amsp_release_caches(void) {
+  release_dev_cache();
+  plan_release_caches();
 }
 
 extern "C" void amsp_destroy(amsp_handle *h) {

@@ -251,6 +251,8 @@ void launch_eig_rr(hipStream_t s, const Plan &p, int max_ni, const double *val,
 void launch_build_basis(hipStream_t s, const Plan &p, const double *sdiag, const double *X,
                         double *phi, int pou);
 void launch_basis_convert(hipStream_t s, const double *phi, void *dst, size_t count, int bf16);
+// phi[e] := phi[e] rounded to float32 (bf16 = 0) or bfloat16 (bf16 = 1), in place
+void launch_basis_round(hipStream_t s, double *phi, size_t count, int bf16);
 
 // ---------------------------------------------------------------- coarse ---
 struct CoarsePlan {

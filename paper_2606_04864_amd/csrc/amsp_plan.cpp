@@ -20,12 +20,14 @@
 #include <climits>
 #include <condition_variable>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
+#include <vector>
 
 #include <unistd.h>
 #include <unordered_map>
@@ -48,8 +50,11 @@ struct BlockCache {
   std::unordered_map<void *, Block> live;
   size_t held = 0;
 };
+void register_exit_release();
 BlockCache &block_cache() {
-  static BlockCache *c = new BlockCache();  // never destroyed: blocks may be freed at exit
+  // never destroyed: blocks may be returned after static destructors ran; the
+  // free blocks are released by plan_release_caches (exit handler)
+  static BlockCache *c = new BlockCache();
   return *c;
 }
 void *block_new(size_t bytes, bool &pinned) {
@@ -72,6 +77,7 @@ void block_delete(void *p, bool pinned) {
 
 void *plan_alloc(size_t bytes) {
   if (bytes < kCacheMin) return ::operator new(bytes);
+  register_exit_release();
   BlockCache &c = block_cache();
   const size_t want = (bytes + kCacheMin - 1) & ~(kCacheMin - 1);
   {
@@ -118,14 +124,33 @@ namespace {
 // coupling thread and the main thread may plan concurrently) starts its own
 // threads.  After a fork the child builds a new pool (the parent's workers
 // do not exist there).
+std::mutex g_pool_mu;
+class PlanPool;
+PlanPool *g_pool = nullptr;
+
 class PlanPool {
  public:
   static PlanPool *get(int nworkers) {
-    static std::mutex m;
-    static PlanPool *pool = nullptr;
-    std::lock_guard<std::mutex> lk(m);
-    if (!pool || pool->pid_ != getpid()) pool = new PlanPool(nworkers);  // never freed
-    return pool;
+    register_exit_release();
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    // a forked child cannot use (or join) its parent's workers: it leaves
+    // that pool alone and builds its own
+    if (!g_pool || g_pool->pid_ != getpid()) g_pool = new PlanPool(nworkers);
+    return g_pool;
+  }
+  // Stops and joins the workers (no loop may be running) and frees the pool.
+  static void shutdown() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    PlanPool *pool = g_pool;
+    if (!pool || pool->pid_ != getpid()) return;
+    g_pool = nullptr;
+    {
+      std::lock_guard<std::mutex> l2(pool->mu_);
+      pool->stop_ = true;
+    }
+    pool->cv_.notify_all();
+    for (std::thread &t : pool->threads_) t.join();
+    delete pool;
   }
   // fn(i) for i in [0, n) on the caller and up to nth - 1 workers; false
   // when another loop occupies the pool
@@ -157,13 +182,14 @@ class PlanPool {
 
  private:
   explicit PlanPool(int nworkers) : nworkers_(nworkers), pid_(getpid()) {
-    for (int w = 0; w < nworkers; ++w) std::thread([this, w] { loop(w); }).detach();
+    for (int w = 0; w < nworkers; ++w) threads_.emplace_back([this, w] { loop(w); });
   }
   void loop(int w) {
     unsigned long long seen = 0;
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
-      cv_.wait(lk, [&] { return gen_ != seen; });
+      cv_.wait(lk, [&] { return gen_ != seen || stop_; });
+      if (stop_) return;
       seen = gen_;
       if (w >= want_) continue;  // not asked to join this loop
       void (*call)(void *, int) = call_;
@@ -187,9 +213,34 @@ class PlanPool {
   void (*call_)(void *, int) = nullptr;
   void *ctx_ = nullptr;
   int count_ = 0, want_ = 0, finished_ = 0;
+  bool stop_ = false;
   std::atomic<int> next_{0};
+  std::vector<std::thread> threads_;
 };
+
+// At process exit the planner's workers are joined and its cached host
+// blocks released before the HIP runtime tears itself down: the handler is
+// registered after a first runtime call, and exit handlers run in reverse
+// order of registration.
+void register_exit_release() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int ndev = 0;
+    (void)hipGetDeviceCount(&ndev);  // the runtime's own exit work is registered by now
+    (void)hipGetLastError();
+    std::atexit([] { plan_release_caches(); });
+  });
+}
 }  // namespace
+
+void plan_release_caches() {
+  PlanPool::shutdown();
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto &kv : c.free_blocks) block_delete(kv.second.first, kv.second.second);
+  c.free_blocks.clear();
+  c.held = 0;
+}
 
 // Run fn(i) for i in [0, count) on up to 16 threads (dynamic schedule).
 template <typename F>

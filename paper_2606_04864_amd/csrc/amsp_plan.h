@@ -16,6 +16,10 @@ namespace amsp {
 // their index arrays; smaller requests go to operator new.
 void *plan_alloc(size_t bytes);
 void plan_free(void *p, size_t bytes);
+// Joins the planner's worker threads and releases the free blocks of the
+// cache (blocks still in use stay valid and return to the cache later).
+// Also run by an exit handler.  Not to be called while a plan is being built.
+void plan_release_caches();
 
 // Allocator whose resize() leaves new elements uninitialised (large index
 // arrays are first written by the threads that fill them), backed by the

@@ -526,6 +526,17 @@ __global__ void k_basis_convert(const double *__restrict__ src, void *__restrict
   }
 }
 
+// The mixed forms store the basis in float32 or bfloat16; rounding the FP64
+// basis in place first makes A0 = R0 A R0^T the Galerkin matrix of the basis
+// the apply actually uses, with the products still accumulated in FP64.
+__global__ void k_basis_round(double *__restrict__ phi, size_t count, int bf16) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const float f = (float)phi[e];
+    phi[e] = bf16 ? (double)__bfloat162float(__float2bfloat16(f)) : (double)f;
+  }
+}
+
 // ------------------------------------------------------------- launchers ---
 // ------------------------------------------- block solve (EIGP rhs) -------
 // Y = (L L^T)^{-1} X for the row-major padded blocks X[rows][EIGP] of every
@@ -738,6 +749,13 @@ void launch_basis_convert(hipStream_t s, const double *phi, void *dst, size_t co
   size_t b = (count + WG - 1) / WG;
   if (b > 65535) b = 65535;
   hipLaunchKernelGGL(k_basis_convert, dim3((unsigned)b), dim3(WG), 0, s, phi, dst, count, bf16);
+}
+
+void launch_basis_round(hipStream_t s, double *phi, size_t count, int bf16) {
+  if (count == 0) return;
+  size_t b = (count + WG - 1) / WG;
+  if (b > 65535) b = 65535;
+  hipLaunchKernelGGL(k_basis_round, dim3((unsigned)b), dim3(WG), 0, s, phi, count, bf16);
 }
 
 }  // namespace amsp

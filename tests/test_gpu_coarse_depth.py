@@ -1,0 +1,163 @@
+"""The coarse level at a depth of many tiles, against the FP64 oracle.
+
+The dense coarse factorisation runs over T0 = ceil(N_c / 64) tile columns with
+lookahead on three streams, and the coarse solve applies A0^{-1} = W0^T W0 by
+two tiled triangular products whose partial sums are reduced per tile row.
+An error in any of these at a tile index the small parity cases never reach
+(they have T0 <= 2) would still leave W0^T W0 symmetric positive definite,
+so convergence alone cannot detect it.  Here gauss256 with 256 parts, 2
+overlap layers and 6 eigenvectors gives N_c = 1536, T0 = 24.
+
+Bars (FP64 form): local eigenvalues 1e-10 absolute, A0 spectrum 1e-10
+relative, the coarse term and the whole M^{-1} v within max(1e-10, 10 F),
+globally and per core subdomain in the max norm, with F the oracle's floor
+under a reversed local ordering.  Mixed forms: the exported A0 is the
+Galerkin product of the exported (rounded) basis to 1e-12, and PCG reaches
+max(1e-8, attainable floor); errors against the oracle are reported.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2606_04864_amd as P  # noqa: E402
+
+_C = {}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def case():
+    if "w" not in _C:
+        w = configs.gauss_inclusions(nx=256, nparts=256, overlap=2, nev=6)
+        A = w.A.to_scipy()
+        st = O.setup(A, w.part, w.nparts, w.nev, w.overlap)
+        alt = O.setup(A, w.part, w.nparts, w.nev, w.overlap, local_order="descending")
+        _C["w"] = (w, A, st, alt)
+    return _C["w"]
+
+
+def dev(x):
+    return torch.tensor(np.asarray(x, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def core_errors(z, ref, part, nparts):
+    order = np.argsort(part, kind="stable")
+    cuts = np.searchsorted(part[order], np.arange(nparts + 1))
+    d, a = np.abs(z - ref)[order], np.abs(ref)[order]
+    return np.array([d[cuts[i]:cuts[i + 1]].max() / max(a[cuts[i]:cuts[i + 1]].max(), 1e-300)
+                     for i in range(nparts)])
+
+
+def exported_R0T(pc, w):
+    """R0^T assembled from the handle's exported regions and stored basis."""
+    rows, cols, vals = [], [], []
+    c0 = 0
+    for i in range(w.nparts):
+        d, phi = pc.region(i)
+        m = min(w.nev, len(d))
+        for k in range(m):
+            rows.append(d)
+            cols.append(np.full(len(d), c0 + k))
+            vals.append(phi[:, k])
+        c0 += m
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(w.n, c0))
+
+
+def test_fp64_coarse_level_at_depth():
+    w, A, st, alt = case()
+    assert st.nc >= 16 * 64, st.nc
+    say(f"coarse depth: nc {st.nc}, T0 {(st.nc + 63) // 64}")
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, keep_a0=True)
+    assert pc.info["eig_unconverged"] == 0 and pc.info["nc"] == st.nc
+    lam = pc.eigenvalues()
+    lerr = max(np.abs(lam[i, :len(st.lam[i])] - st.lam[i]).max() for i in range(w.nparts))
+    say(f"  eigenvalues max abs err {lerr:.2e}")
+    assert lerr <= 1e-10
+    A0 = pc.coarse_matrix()
+    e_gpu, e_ref = np.linalg.eigvalsh(A0), np.linalg.eigvalsh(st.A0)
+    a0err = np.abs(e_gpu - e_ref).max() / np.abs(e_ref).max()
+    say(f"  A0 spectrum relerr {a0err:.2e}")
+    assert a0err <= 1e-10
+    r = np.random.default_rng(61).standard_normal(w.n)
+    for parts, f in [(2, O.coarse_part), (3, O.apply)]:
+        ref, other = f(st, r), f(alt, r)
+        F = relerr(other, ref)
+        z = host(pc.apply(dev(r), parts=parts))
+        err = relerr(z, ref)
+        say(f"  parts={parts}: err {err:.2e} bar {max(1e-10, 10 * F):.2e}")
+        assert err <= max(1e-10, 10 * F)
+        e = core_errors(z, ref, w.part, w.nparts)
+        bar = np.maximum(1e-10, 10 * core_errors(other, ref, w.part, w.nparts))
+        k = int(np.argmax(e / bar))
+        say(f"  parts={parts}: worst core {k}: err {e[k]:.2e} bar {bar[k]:.2e}")
+        assert np.all(e <= bar)
+    pc.close()
+
+
+def test_fp64_pcg_at_depth():
+    w, A, st, alt = case()
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap)
+    u, info = pc.pcg(dev(w.b), 1e-8, 1000)
+    ref = O.pcg(A, w.b, st.apply, 1e-8)
+    F = relerr(O.pcg(A, w.b, alt.apply, 1e-8).x, ref.x)
+    err = relerr(host(u), ref.x)
+    say(f"depth pcg: its {info['iterations']} (oracle {ref.iterations}), u err {err:.2e} "
+        f"bar {max(1e-10, 10 * F):.2e}")
+    assert info["converged"] == 1
+    h = np.array(ref.relres_history)
+    assert abs(info["iterations"] - ref.iterations) <= 1 + int(np.sum((h > 1e-8) & (h < 3e-8)))
+    assert err <= max(1e-10, 10 * F)
+    pc.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_coarse_is_galerkin_of_stored_basis(prec):
+    w, A, st, _ = case()
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec, keep_a0=True)
+    R0T = exported_R0T(pc, w)
+    # the exported basis is exactly representable in the storage precision
+    lo = np.float32 if prec == "fp32" else None
+    if lo is not None:
+        assert np.array_equal(R0T.data, R0T.data.astype(lo).astype(np.float64))
+    else:
+        bits = R0T.data.astype(np.float32).view(np.uint32)
+        assert np.all(bits & 0xFFFF == 0)
+    A0 = pc.coarse_matrix()
+    G = (R0T.T @ (A @ R0T)).toarray()
+    G = 0.5 * (G + G.T)
+    gerr = np.abs(A0 - G).max() / np.abs(G).max()
+    say(f"{prec}: exported A0 vs R0 A R0^T of the stored basis: {gerr:.2e}")
+    assert gerr <= 1e-12
+    r = np.random.default_rng(62).standard_normal(w.n)
+    ce = relerr(host(pc.apply(dev(r), parts=2)), O.coarse_part(st, r))
+    u, info = pc.pcg(dev(w.b), 1e-8, 2000)
+    ref = O.pcg(A, w.b, st.apply, 1e-8)
+    ue = relerr(host(u), ref.x)
+    say(f"{prec}: coarse term err {ce:.2e}; PCG its {info['iterations']} (FP64 oracle "
+        f"{ref.iterations}), true relres {info['relres_true']:.2e}, u err {ue:.2e}")
+    assert info["converged"] == 1 and info["relres_true"] <= max(1e-8, info["relres_floor"])
+    assert ue <= 1e-6
+    pc.close()

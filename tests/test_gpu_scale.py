@@ -79,7 +79,7 @@ def test_fullsize_local_solves_sample(big):
     z = pc.apply(torch.tensor(r, device="cuda"), parts=1)
     torch.cuda.synchronize()
     z = z.cpu().numpy()
-    ref = np.zeros(w.n)
+    ref, alt = np.zeros(w.n), np.zeros(w.n)
     hit = 0
     for j in range(w.nparts):
         d = O.grow(A, cores[j], w.overlap)
@@ -87,8 +87,13 @@ def test_fullsize_local_solves_sample(big):
             continue
         hit += 1
         ref[d] += sla.cho_solve(sla.cho_factor(O.local_matrix(A, d), lower=True), r[d])
+        e = d[::-1]  # the oracle's floor: the same solves in reversed local order
+        alt[e] += sla.cho_solve(sla.cho_factor(O.local_matrix(A, e), lower=True), r[e])
     assert hit >= 2
-    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+    F = np.linalg.norm(alt - ref) / np.linalg.norm(ref)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say(f"fullsize local solves ({hit} regions): err {err:.2e} bar {max(1e-10, 10 * F):.2e}")
+    assert err <= max(1e-10, 10 * F)
 
 
 def test_fullsize_symmetry_and_pcg(big):
