@@ -54,6 +54,25 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+def build_plan_check(out: str | None = None) -> str:
+    """The host-only planner check program (csrc/plan_check.cpp) with
+    AddressSanitizer and UndefinedBehaviorSanitizer: g++ on host code only,
+    linked against the HIP runtime for its host API (page-locked blocks)."""
+    out = out or os.path.join(BUILD, "plan_check")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    rocm = os.path.dirname(os.path.dirname(HIPCC))
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-D__HIP_PLATFORM_AMD__",
+           "-I" + os.path.join(rocm, "include"), "-I" + CSRC,
+           os.path.join(CSRC, "amsp_plan.cpp"), os.path.join(CSRC, "plan_check.cpp"),
+           "-o", out, "-L" + os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("plan_check build failed:\n" + r.stderr[-6000:])
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
