@@ -189,6 +189,25 @@ amsp_status amsp_apply(amsp_handle *h, const double *r_dev, double *z_dev, int32
 amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
                              int32_t nrhs, int32_t parts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): z = M^{-1} r for
+ * nrhs columns (n apart) through the block path of amsp_apply (up to 16
+ * columns per pass, also for a single column), with its workspace -- the
+ * gathered, solved and output blocks, the coarse vectors and the coarse
+ * products' partial sums, 8 * (3 rows * 16 + 3 ncp * 16 + T0^2 * 1024) bytes
+ * with rows the padded local rows and ncp = 64 T0 -- taken from a 64 MiB
+ * array the library holds on each device until the process ends.  Calls no
+ * allocating routine.  parts as for amsp_apply_parts (the additive operator
+ * only).  Errors: AMSP_ERR_ARG when the workspace exceeds 64 MiB, when
+ * cycle = 1 and parts = 3, or for a mixed form whose float32 block-solve
+ * factor copy does not exist yet (the first amsp_apply with nrhs >= 2 builds
+ * it).  Asynchronous on the handle's stream.  Every call on one device shares
+ * that device's array: calls that overlap in time on one device (two
+ * streams, two threads, two handles) race and must be serialised by the
+ * caller.  Results equal amsp_apply's block path. */
+amsp_status amsp_apply_noalloc(amsp_handle *h, const double *r_dev, double *z_dev, int32_t nrhs,
+                               int32_t parts);
+
 /* Preconditioned CG from u = 0 until the recursive residual satisfies
  * ||r_k|| <= rtol ||f||; the true residual f - A u is then recomputed and
  * accepted if it is below max(rtol, floor) with floor = eps || |A||u| || / ||f||

@@ -96,6 +96,8 @@ _lib.amsp_apply.argtypes = [_vp, _vp, _vp, _i32]
 _lib.amsp_apply.restype = _i32
 _lib.amsp_apply_parts.argtypes = [_vp, _vp, _vp, _i32, _i32]
 _lib.amsp_apply_parts.restype = _i32
+_lib.amsp_apply_noalloc.argtypes = [_vp, _vp, _vp, _i32, _i32]
+_lib.amsp_apply_noalloc.restype = _i32
 _lib.amsp_pcg.argtypes = [_vp, _vp, _vp, _i32, _d, _i32, ctypes.POINTER(_Info)]
 _lib.amsp_pcg.restype = _i32
 _lib.amsp_gmres.argtypes = [_vp, _vp, _vp, _i32, _i32, _d, _i32, ctypes.POINTER(_Info)]
@@ -129,7 +131,8 @@ _lib.amsp_last_error.restype = ctypes.c_char_p
 _lib.amsp_setup_error.argtypes = []
 _lib.amsp_setup_error.restype = ctypes.c_char_p
 
-EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts", "amsp_pcg",
+EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts",
+            "amsp_apply_noalloc", "amsp_pcg",
             "amsp_gmres",
             "amsp_spmv", "amsp_grad_values", "amsp_get_setup_info", "amsp_get_pcg_history", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
             "amsp_get_region", "amsp_plan_regions", "amsp_selftest_mfma", "amsp_destroy",
@@ -338,6 +341,21 @@ class Preconditioner:
         y = out if out is not None else torch.empty_like(x)
         self._err(_lib.amsp_spmv(self._h, x.data_ptr(), y.data_ptr()))
         return y
+
+    def apply_noalloc(self, r, out=None, parts: int = 3):
+        """z = M^{-1} r through amsp_apply_noalloc (no device allocation; the
+        workspace is the library's per-device scratch array).  r: float64
+        device tensor of shape (n,) or (n, k)."""
+        torch = _torch()
+        _check_dev(r, "r", self.n)
+        z = out if out is not None else torch.empty_like(r)
+        nrhs = 1 if r.dim() == 1 else r.shape[1]
+        rr = r if r.dim() == 1 else r.t().contiguous()
+        zz = z if r.dim() == 1 else torch.empty_like(rr)
+        self._err(_lib.amsp_apply_noalloc(self._h, rr.data_ptr(), zz.data_ptr(), nrhs, parts))
+        if r.dim() == 2:
+            z.copy_(zz.t())
+        return z
 
     def pcg(self, f, rtol: float = 1e-8, maxit: int = 1000, out=None, raise_on_noconv=True):
         """Solve A u = f by preconditioned CG; returns (u, info dict).  f of

@@ -150,6 +150,7 @@ double now_ms() {
 struct amsp_handle {
   amsp_options opt{};
   hipStream_t stream = nullptr;
+  int device = 0;  // the device current at setup (holds every buffer)
   int n = 0, N = 0, nev = 0, nc = 0, T0 = 0;
   int64_t nnz = 0;
   HostPlan hp;
@@ -1007,6 +1008,37 @@ static bool upload_coupling(amsp_handle *h, hipStream_t stream, CouplingDev &d) 
   return ok;
 }
 
+// ----------------------------------------- allocation-free block apply ----
+// Workspace of amsp_apply_noalloc: one array per device, held until the
+// process ends and shared by every handle on that device.  Host code never
+// uses the array's name as an address: the device address of each device's
+// copy is taken once (hipGetSymbolAddress, with that device current) by the
+// first amsp_setup on the device, and only that address reaches kernels.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+// Takes the device address of this device's scratch array (once per device);
+// the current device is `device`.
+static amsp_status scratch_init(int device, std::string &msg) {
+  if (device < 0 || device >= kMaxDevices) {
+    msg = "device index beyond the library's limit of " + std::to_string(kMaxDevices);
+    return AMSP_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return AMSP_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return AMSP_ERR_HIP;
+  }
+  g_scratch_dev[device] = ptr;
+  return AMSP_OK;
+}
+
 extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, int32_t nparts,
                                   int32_t nev, const amsp_options *opt, amsp_handle **out) {
   if (!out) return AMSP_ERR_ARG;
@@ -1036,6 +1068,11 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
   h->opt = o;
   if (h->opt.flexible < 0) h->opt.flexible = (o.precision != AMSP_FP64) ? 1 : 0;
   h->stream = (hipStream_t)o.stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    g_setup_error = "hipGetDevice failed";
+    delete h;
+    return AMSP_ERR_HIP;
+  }
   h->n = (int)A->n;
   h->nnz = A->nnz;
   h->N = nparts;
@@ -1070,7 +1107,12 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
   h->sinfo.sum_ni = h->hp.sd_ptr.back();
   h->sinfo.max_ni = h->hp.max_ni;
   h->sinfo.factor_tiles = h->hp.ntiles;
-  amsp_status ds;
+  amsp_status ds = scratch_init(h->device, h->err);
+  if (ds != AMSP_OK) {
+    g_setup_error = h->err;
+    delete h;
+    return ds;
+  }
   try {
     ds = device_setup(h, A);
   } catch (const std::bad_alloc &) {
@@ -1152,14 +1194,41 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
 // with one pass over the local factor: the block solve with the Dirichlet
 // factor (f32-stored in the mixed forms, f64 arithmetic), the restriction of
 // all columns, one coarse solve per column, the prolongation and the scatter.
+// Workspace of the block apply: gathered, solved and output blocks (rows x
+// EIGP each), the coarse vectors (ncp x EIGP each) and the coarse products'
+// partial sums (T0^2 x TS x EIGP).
+struct BlockWs {
+  double *X, *Y, *XN, *C, *T, *C2, *Part;
+  bool clear_c;  // the coarse input's padding must be zeroed by this call
+};
+
+static size_t block_ws_doubles(const amsp_handle *h) {
+  const size_t rows = (size_t)h->hp.vp_ptr.back();
+  const size_t ncp = (size_t)std::max(1, h->T0 * TS);
+  return 3 * rows * EIGP + 3 * ncp * EIGP +
+         std::max<size_t>((size_t)h->T0 * h->T0, 1) * TS * EIGP;
+}
+
+// Carves the workspace out of one buffer of block_ws_doubles(h) doubles.
+static BlockWs block_ws_from(const amsp_handle *h, double *base) {
+  const size_t rows = (size_t)h->hp.vp_ptr.back();
+  const size_t ncp = (size_t)std::max(1, h->T0 * TS);
+  BlockWs w;
+  w.X = base;
+  w.Y = w.X + rows * EIGP;
+  w.XN = w.Y + rows * EIGP;
+  w.C = w.XN + rows * EIGP;
+  w.T = w.C + ncp * EIGP;
+  w.C2 = w.T + ncp * EIGP;
+  w.Part = w.C2 + ncp * EIGP;
+  w.clear_c = true;
+  return w;
+}
+
+static amsp_status apply_block_ws(amsp_handle *h, const double *r, double *z, int nr, int parts,
+                                  const BlockWs &ws);
+
 static amsp_status apply_block(amsp_handle *h, const double *r, double *z, int nr, int parts) {
-  const Plan &p = h->plan;
-  const int n = h->n;
-  hipStream_t s = h->stream;
-  const bool mixed = h->opt.precision != AMSP_FP64;
-  const bool bf = h->opt.precision == AMSP_MIXED_BF16;
-  const int do_local = (parts & 1) ? 1 : 0;
-  const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
   const size_t rows = (size_t)h->hp.vp_ptr.back();
   const size_t ncp = (size_t)std::max(1, h->T0 * TS);
   if (!h->bX) {
@@ -1170,8 +1239,25 @@ static amsp_status apply_block(amsp_handle *h, const double *r, double *z, int n
     ALLOC(h->bT, double, ncp * EIGP);
     ALLOC(h->bC2, double, ncp * EIGP);
     ALLOC(h->bPart, double, std::max<size_t>((size_t)h->T0 * h->T0, 1) * TS * EIGP);
-    launch_fill(s, ncp * EIGP, h->bC, 0.0);  // coarse padding stays zero
+    launch_fill(h->stream, ncp * EIGP, h->bC, 0.0);  // coarse padding stays zero
   }
+  const BlockWs ws{h->bX, h->bY, h->bXN, h->bC, h->bT, h->bC2, h->bPart, false};
+  return apply_block_ws(h, r, z, nr, parts, ws);
+}
+
+static amsp_status apply_block_ws(amsp_handle *h, const double *r, double *z, int nr, int parts,
+                                  const BlockWs &ws) {
+  const Plan &p = h->plan;
+  const int n = h->n;
+  hipStream_t s = h->stream;
+  const bool mixed = h->opt.precision != AMSP_FP64;
+  const bool bf = h->opt.precision == AMSP_MIXED_BF16;
+  const int do_local = (parts & 1) ? 1 : 0;
+  const int do_coarse = ((parts & 2) && h->nc > 0) ? 1 : 0;
+  const size_t ncp = (size_t)std::max(1, h->T0 * TS);
+  double *const bX = ws.X, *const bY = ws.Y, *const bXN = ws.XN, *const bC = ws.C,
+               *const bT = ws.T, *const bC2 = ws.C2, *const bPart = ws.Part;
+  if (do_coarse && ws.clear_c) launch_fill(s, ncp * nr, bC, 0.0);  // padding rows read as zero
   if (mixed && do_local && !h->dg32) {
     const size_t nenv = (size_t)h->hp.nenv;
     ALLOC(h->dg32, float, (size_t)h->ntilerows * DE);
@@ -1179,40 +1265,40 @@ static amsp_status apply_block(amsp_handle *h, const double *r, double *z, int n
     ALLOC(h->ec32, float, std::max<size_t>(nenv, 1));
     launch_streams_to_env(s, p, h->ntilerows, h->fst32, h->bst32, h->dg32, h->er32, h->ec32);
   }
-  launch_gather_multi(s, p, n, nr, r, h->bX);
+  launch_gather_multi(s, p, n, nr, r, bX);
   if (do_local) {
     if (mixed)
-      launch_env_solve_block<float>(s, p, h->dg32, h->er32, h->ec32, h->bX, h->bY, nullptr);
+      launch_env_solve_block<float>(s, p, h->dg32, h->er32, h->ec32, bX, bY, nullptr);
     else
-      launch_env_solve_block<double>(s, p, h->dg64, h->erow64, h->ecol64, h->bX, h->bY, nullptr);
+      launch_env_solve_block<double>(s, p, h->dg64, h->erow64, h->ecol64, bX, bY, nullptr);
   }
   const void *phi = mixed ? h->phi_lo : (const void *)h->phi64;
   if (do_coarse) {
     if (!mixed)
-      launch_restrict_multi<double>(s, p, nr, ncp, (const double *)phi, h->bX, h->bC);
+      launch_restrict_multi<double>(s, p, nr, ncp, (const double *)phi, bX, bC);
     else if (!bf)
-      launch_restrict_multi<float>(s, p, nr, ncp, (const float *)phi, h->bX, h->bC);
+      launch_restrict_multi<float>(s, p, nr, ncp, (const float *)phi, bX, bC);
     else
-      launch_restrict_multi<__hip_bfloat16>(s, p, nr, ncp, (const __hip_bfloat16 *)phi, h->bX, h->bC);
+      launch_restrict_multi<__hip_bfloat16>(s, p, nr, ncp, (const __hip_bfloat16 *)phi, bX, bC);
     // t_k = W0^T (W0 c_k) for all columns, W0's tiles read once per product
     if (!mixed) {
-      launch_trmm<double>(s, h->W0, h->T0, h->bC, ncp, nr, h->bPart, h->bC2, 0);
-      launch_trmm<double>(s, h->W0, h->T0, h->bC2, ncp, nr, h->bPart, h->bT, 1);
+      launch_trmm<double>(s, h->W0, h->T0, bC, ncp, nr, bPart, bC2, 0);
+      launch_trmm<double>(s, h->W0, h->T0, bC2, ncp, nr, bPart, bT, 1);
     } else {
-      launch_trmm<float>(s, h->W0f, h->T0, h->bC, ncp, nr, h->bPart, h->bC2, 0);
-      launch_trmm<float>(s, h->W0f, h->T0, h->bC2, ncp, nr, h->bPart, h->bT, 1);
+      launch_trmm<float>(s, h->W0f, h->T0, bC, ncp, nr, bPart, bC2, 0);
+      launch_trmm<float>(s, h->W0f, h->T0, bC2, ncp, nr, bPart, bT, 1);
     }
   }
-  const double *tcoarse = do_coarse ? h->bT : nullptr;
-  const double *ylocal = do_local ? h->bY : nullptr;
+  const double *tcoarse = do_coarse ? bT : nullptr;
+  const double *ylocal = do_local ? bY : nullptr;
   if (!mixed)
-    launch_prolong_multi<double>(s, p, nr, ncp, (const double *)phi, tcoarse, ylocal, h->bXN);
+    launch_prolong_multi<double>(s, p, nr, ncp, (const double *)phi, tcoarse, ylocal, bXN);
   else if (!bf)
-    launch_prolong_multi<float>(s, p, nr, ncp, (const float *)phi, tcoarse, ylocal, h->bXN);
+    launch_prolong_multi<float>(s, p, nr, ncp, (const float *)phi, tcoarse, ylocal, bXN);
   else
     launch_prolong_multi<__hip_bfloat16>(s, p, nr, ncp, (const __hip_bfloat16 *)phi, tcoarse,
-                                         ylocal, h->bXN);
-  launch_scatter_multi(s, n, nr, h->inv_ptr, h->inv_x, h->bXN, z);
+                                         ylocal, bXN);
+  launch_scatter_multi(s, n, nr, h->inv_ptr, h->inv_x, bXN, z);
   HIP_TRY(hipGetLastError());
   return AMSP_OK;
 }
@@ -1258,6 +1344,43 @@ extern "C" amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, dou
     amsp_status s = parts == 3 ? apply_prec(h, rk, zk, nullptr, nullptr)
                                : apply_one(h, rk, zk, parts, nullptr, nullptr);
     if (s != AMSP_OK) return s;
+  }
+  return AMSP_OK;
+}
+
+extern "C" amsp_status amsp_apply_noalloc(amsp_handle *h, const double *r_dev, double *z_dev,
+                                         int32_t nrhs, int32_t parts) {
+  if (!h || !r_dev || !z_dev || nrhs < 1 || parts < 1 || parts > 3) return AMSP_ERR_ARG;
+  if (h->opt.cycle == 1 && parts == 3) {
+    h->err = "amsp_apply_noalloc: the multiplicative cycle is not available here";
+    return AMSP_ERR_ARG;
+  }
+  if (h->opt.precision != AMSP_FP64 && (parts & 1) && !h->dg32) {
+    h->err = "amsp_apply_noalloc: the mixed forms' block solve reads a float32 copy of the local "
+             "factor that the first amsp_apply with nrhs >= 2 builds; call that once first";
+    return AMSP_ERR_ARG;
+  }
+  const size_t need = block_ws_doubles(h) * sizeof(double);
+  if (need > kNoallocScratchBytes) {
+    h->err = "amsp_apply_noalloc: workspace of " + std::to_string(need) + " bytes exceeds the " +
+             std::to_string(kNoallocScratchBytes) + "-byte scratch array";
+    return AMSP_ERR_ARG;
+  }
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = (h->device >= 0 && h->device < kMaxDevices) ? g_scratch_dev[h->device] : nullptr;
+  }
+  if (!base) {
+    h->err = "amsp_apply_noalloc: no scratch address for the handle's device";
+    return AMSP_ERR_HIP;
+  }
+  const BlockWs ws = block_ws_from(h, static_cast<double *>(base));
+  for (int k = 0; k < nrhs; k += EIGP) {
+    const int nr = std::min(EIGP, nrhs - k);
+    amsp_status st = apply_block_ws(h, r_dev + (size_t)k * h->n, z_dev + (size_t)k * h->n, nr,
+                                    parts, ws);
+    if (st != AMSP_OK) return st;
   }
   return AMSP_OK;
 }
