@@ -113,6 +113,22 @@ typedef struct {
                             /* term; twice the local solves and two more SpMVs per apply */
   double smoother_weight;   /* w of cycle 1; 0 (default): 1 / (largest number of regions */
                             /* containing one dof), which keeps the cycle SPD            */
+  int32_t coarse_basis;     /* mixed forms only: 0 (default): A0 = R0 A R0^T is formed   */
+                            /* from the basis as stored (rounded to float32/bfloat16,    */
+                            /* products in float64), the Galerkin matrix of the basis    */
+                            /* the apply uses; 1: from the float64 basis before          */
+                            /* rounding (the apply then uses an approximation of that    */
+                            /* projection).  Measured with a bfloat16 basis on the 1M    */
+                            /* high-contrast benchmark matrix: 0 reaches the rounding    */
+                            /* floor's level in 805 steps, 1 stalls near 2e-3.           */
+  int32_t coarse_solver;    /* factorisation of A0: 0 (default): automatic, the sparse   */
+                            /* one when N_c > 8192; 1: dense tiled Cholesky and its      */
+                            /* inverse factor W0 (two parallel triangular products per   */
+                            /* solve); 2: sparse multifrontal Cholesky over a nested-    */
+                            /* dissection order of the subdomains (the paper's sparse    */
+                            /* direct coarse solver, Section 5), one launch per level    */
+                            /* and direction per solve.  Problems with singular = 1 use  */
+                            /* the dense factorisation.                                   */
 } amsp_options;
 
 typedef struct {
@@ -134,6 +150,10 @@ typedef struct {
   /* attainable-accuracy floor eps * || |A| |u| || / ||f||: no float64 vector u
    * can be certified below it; converged means relres_true <= max(rtol, floor) */
   double relres_floor;
+  /* steps of the first CG segment: the step at which the recursive residual
+   * first reached rtol, before any restart from the true residual (one
+   * right-hand side; with several, their sum) */
+  int32_t first_segment;
 } amsp_info;
 
 typedef struct {
@@ -154,6 +174,12 @@ typedef struct {
   double coupling_wait_ms;  /* time the device path waited for it                   */
   double plan_host_ms;      /* part of phase_ms[0]: the host planning itself        */
   double plan_upload_ms;    /* part of phase_ms[0]: device copies of the plan       */
+  int32_t coarse_solver;    /* 1: dense, 2: sparse multifrontal (as used)           */
+  int32_t coarse_fronts;    /* sparse: fronts (supernodes) and levels of the tree   */
+  int32_t coarse_levels;
+  double coarse_gflop;      /* sparse: tile-product flops of factor + inverse parts */
+  double coarse_factor_mb;  /* solve's factor bytes (dense W0 lower tiles, or the   */
+                            /* sparse fronts' X), in MB, in the apply's precision   */
 } amsp_setup_info;
 
 typedef struct amsp_handle amsp_handle;

@@ -7,5 +7,5 @@ from .amsp_oracle import (  # noqa: F401
     OracleError, validate, cores, grow, multiplicity, local_matrix, neumann_matrix,
     weighting, local_eigenpairs, prolongation, coarse_matrix, Setup, setup, apply,
     local_part, coarse_part, pcg, PCGResult, lanczos_condition, adjoint_gradients,
-    gmres, GMRESResult, pseudo_inverse, apply_multiplicative,
+    gmres, GMRESResult, pseudo_inverse, apply_multiplicative, theta_gradient,
 )

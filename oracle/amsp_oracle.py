@@ -198,7 +198,8 @@ class Setup:
 
 
 def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
-          local_solves=True, singular=False, cycle="additive", omega=None) -> Setup:
+          local_solves=True, singular=False, cycle="additive", omega=None,
+          progress=None) -> Setup:
     """singular=True: A is positive semidefinite with a null space (the
     paper's homogeneous Neumann problem, Section 5); the coarse term then
     uses the pseudo-inverse of A0, as the two-level operator of Section 3.1
@@ -208,7 +209,10 @@ def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
     two-grid algorithm and Section 4 (pre-smoothing, coarse correction,
     post-smoothing) with the damped additive Schwarz smoother
     omega * sum_i R_i^T A_i^{-1} R_i; omega defaults to 1 / (the largest
-    number of regions containing one dof)."""
+    number of regions containing one dof).
+
+    progress: optional callable(i, N) called after subdomain i's local work
+    (reporting only; it does not change any result)."""
     A = sp.csr_matrix(A)
     validate(A, part, nparts)
     if nev < 0:
@@ -234,6 +238,8 @@ def setup(A, part, nparts, nev, overlap=1, pou="mult", local_order="ascending",
             lam, psi = np.zeros(0), np.zeros((len(dofs), 0))
         lams.append(lam)
         psis.append(psi)
+        if progress is not None:
+            progress(len(psis) - 1, len(regions))
     R0T = prolongation(n, regions, psis, mult, pou)
     A0p = None
     if R0T.shape[1] > 0:
@@ -457,3 +463,57 @@ def adjoint_gradients(A, f, dJdu):
     lam = spla.spsolve(A.T.tocsc(), dJdu)
     rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
     return u, lam, -lam[rows] * u[A.indices]
+
+
+# --------------------------------------------------------------------------
+# Gradient with respect to the log-permeability theta = log kappa of a
+# two-point-flux Darcy matrix on an nx x ny (x nz) cell grid with h = 1/nx,
+# the same kappa on every face direction, homogeneous Dirichlet faces.
+# Not part of the paper's method: it chains the adjoint of the solve (above)
+# through the matrix assembly.  For the interior face f between cells P and
+# Q, T_f = s 2 kP kQ / (kP + kQ) with s = h^(d-2) enters A as A_PQ = A_QP =
+# -T_f and adds T_f to A_PP and A_QQ; a Dirichlet face of P adds s 2 kP to
+# A_PP.  Hence
+#   dJ/dT_f = g_PP + g_QQ - g_PQ - g_QP,
+#   dT_f/dkP = s 2 kQ^2 / (kP + kQ)^2,   d(s 2 kP)/dkP = 2 s,
+#   dkP/dthetaP = kP,
+# with g = dJ/dvals from adjoint_gradients.  Cells are numbered
+# j = ix + nx (iy + ny iz); faces are read off the grid, not off A.
+def theta_gradient(A, f, u_obs, kappa):
+    """dJ/dtheta for J = 0.5 ||A(theta)^{-1} f - u_obs||^2 (kappa indexed
+    [ix, iy] or [ix, iy, iz]).  Returns (u, J, grad_theta indexed like kappa)."""
+    A = sp.csr_matrix(A)
+    u = adjoint_gradients(A, f, np.zeros(A.shape[0]))[0]
+    u, lam, g = adjoint_gradients(A, f, u - u_obs)
+    J = 0.5 * float((u - u_obs) @ (u - u_obs))
+    shape = kappa.shape
+    d = len(shape)
+    h = 1.0 / shape[0]
+    s = h ** (d - 2)
+    n = int(np.prod(shape))
+    k = np.ascontiguousarray(kappa.T).ravel()  # cell j = ix + nx (iy + ny iz)
+    cell = np.arange(n).reshape(shape[::-1]).T  # cell[ix, iy(, iz)]
+
+    def entry(i, j):  # positions of the stored entries (i, j) in A's CSR order
+        pos = np.empty(len(i), dtype=np.int64)
+        for t, (a, b) in enumerate(zip(i, j)):
+            lo, hi = A.indptr[a], A.indptr[a + 1]
+            pos[t] = lo + np.searchsorted(A.indices[lo:hi], b)
+        return pos
+
+    diag = entry(np.arange(n), np.arange(n))
+    grad_k = np.zeros(n)
+    for a in range(d):
+        # interior faces between consecutive cells along axis a
+        P = np.take(cell, np.arange(shape[a] - 1), axis=a).ravel()
+        Q = np.take(cell, np.arange(1, shape[a]), axis=a).ravel()
+        kP, kQ = k[P], k[Q]
+        dJdT = g[diag[P]] + g[diag[Q]] - g[entry(P, Q)] - g[entry(Q, P)]
+        np.add.at(grad_k, P, dJdT * s * 2.0 * kQ * kQ / (kP + kQ) ** 2)
+        np.add.at(grad_k, Q, dJdT * s * 2.0 * kP * kP / (kP + kQ) ** 2)
+        # Dirichlet faces at both ends of axis a
+        for end in (0, shape[a] - 1):
+            B = np.take(cell, [end], axis=a).ravel()
+            np.add.at(grad_k, B, g[diag[B]] * 2.0 * s)
+    grad_theta = grad_k * k
+    return u, J, grad_theta.reshape(shape[::-1]).T

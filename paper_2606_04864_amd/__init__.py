@@ -65,7 +65,8 @@ class _Options(ctypes.Structure):
                 ("keep_a0", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("timing_stride", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("singular", ctypes.c_int32), ("cycle", ctypes.c_int32),
-                ("smoother_weight", ctypes.c_double)]
+                ("smoother_weight", ctypes.c_double), ("coarse_basis", ctypes.c_int32),
+                ("coarse_solver", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -74,7 +75,7 @@ class _Info(ctypes.Structure):
                 ("restarts", ctypes.c_int32), ("solve_ms", ctypes.c_double),
                 ("bytes_per_iter", ctypes.c_int64), ("kernel_ms", ctypes.c_double * 5),
                 ("kernel_launches", ctypes.c_int32 * 5), ("local_apply_bytes", ctypes.c_int64),
-                ("relres_floor", ctypes.c_double)]
+                ("relres_floor", ctypes.c_double), ("first_segment", ctypes.c_int32)]
 
 
 class _SetupInfo(ctypes.Structure):
@@ -84,7 +85,9 @@ class _SetupInfo(ctypes.Structure):
                 ("n_gap_flags", ctypes.c_int32), ("mu_c", ctypes.c_double),
                 ("phase_ms", ctypes.c_double * 8), ("coupling_ms", ctypes.c_double),
                 ("coupling_wait_ms", ctypes.c_double), ("plan_host_ms", ctypes.c_double),
-                ("plan_upload_ms", ctypes.c_double)]
+                ("plan_upload_ms", ctypes.c_double), ("coarse_solver", ctypes.c_int32),
+                ("coarse_fronts", ctypes.c_int32), ("coarse_levels", ctypes.c_int32),
+                ("coarse_gflop", ctypes.c_double), ("coarse_factor_mb", ctypes.c_double)]
 
 
 _vp, _i32, _i64, _d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -235,7 +238,8 @@ class Preconditioner:
                  dense_tiles: bool = False, eig_tol: float = 0.0, eig_maxit: int = 80,
                  eig_shift: float = 1e-4, chunk: int = 8, flexible: int = -1,
                  keep_a0: bool = False, timing=False, timing_stride: int = 1, stream=None,
-                 singular: bool = False, cycle: str = "additive", smoother_weight: float = 0.0):
+                 singular: bool = False, cycle: str = "additive", smoother_weight: float = 0.0,
+                 coarse_basis: str = "stored", coarse_solver: str = "auto"):
         torch = _torch()
         self._h = None
         self._keep = [np.ascontiguousarray(row_ptr, dtype=np.int64),
@@ -259,6 +263,8 @@ class Preconditioner:
         o.singular = int(bool(singular))
         o.cycle = {"additive": 0, "multiplicative": 1}[cycle]
         o.smoother_weight = float(smoother_weight)
+        o.coarse_basis = {"stored": 0, "fp64": 1}[coarse_basis]
+        o.coarse_solver = {"auto": 0, "dense": 1, "sparse": 2}[coarse_solver]
         if torch.cuda.is_available():
             torch.cuda.init()  # the device context exists before the library's first HIP call
             torch.cuda.synchronize()

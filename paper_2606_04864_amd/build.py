@@ -26,6 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + CSRC,
           "-Wno-unused-command-line-argument"]
 
 SOURCES = ["k_krylov.hip", "k_local.hip", "k_apply.hip", "k_eigen.hip", "k_coarse.hip", "k_multi.hip",
+           "k_tree.hip", "amsp_tree.cpp",
            "amsp_plan.cpp",
            "amsp_host.cpp"]
 
@@ -64,7 +65,8 @@ def build_plan_check(out: str | None = None) -> str:
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
            "-fsanitize=address,undefined", "-D__HIP_PLATFORM_AMD__",
            "-I" + os.path.join(rocm, "include"), "-I" + CSRC,
-           os.path.join(CSRC, "amsp_plan.cpp"), os.path.join(CSRC, "plan_check.cpp"),
+           os.path.join(CSRC, "amsp_plan.cpp"), os.path.join(CSRC, "amsp_tree.cpp"),
+           os.path.join(CSRC, "tree_check.cpp"), os.path.join(CSRC, "plan_check.cpp"),
            "-o", out, "-L" + os.path.join(rocm, "lib"), "-lamdhip64",
            "-Wl,-rpath," + os.path.join(rocm, "lib"), "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -19,6 +19,7 @@
 #include "../../include/amsp.h"
 #include "amsp_internal.h"
 #include "amsp_plan.h"
+#include "amsp_tree.h"
 
 using namespace amsp;
 
@@ -196,6 +197,14 @@ struct amsp_handle {
   int *inv_work = nullptr, *max_mult_dev = nullptr;  // inverse map build
   double *W0 = nullptr;
   float *W0f = nullptr;
+  // sparse coarse factorisation (coarse_solver 2): plan, its device tables,
+  // the fronts' X in the apply's precision, own-row and update vectors
+  bool tree = false;
+  TreePlan tp;
+  TreeDev td{};
+  double *X64 = nullptr;
+  float *X32 = nullptr;
+  double *ty = nullptr, *tv = nullptr;
   // apply scratch
   double *xloc = nullptr, *cvec = nullptr, *t1 = nullptr, *tvec = nullptr, *trmv_part = nullptr;
   // pcg scratch
@@ -442,6 +451,138 @@ struct SideStream {
 // lower-triangular diagonal tile (DE entries) per tile row.
 static size_t factor_elems(const HostPlan &P) {
   return (size_t)P.noff * TE + (size_t)P.trow_ptr.back() * DE;
+}
+
+// Sparse coarse factorisation (see amsp_tree.h): symbolic plan on the host
+// from the coupled pairs, then on the device the pair blocks of A0, their
+// assembly into the fronts, and level by level the children's Schur
+// complements, the tile Cholesky of the own columns and the fronts' X.  With
+// keep_a0 the dense A0 is also formed (introspection only).
+static amsp_status tree_coarse_setup(amsp_handle *h, const HostPlan &P) {
+  const bool mixed = h->opt.precision != AMSP_FP64;
+  const double t5 = now_ms();
+  TreePlan &tp = h->tp;
+  {
+    std::string msg;
+    if (!build_tree_plan(h->N, P.mi, P.coff, P.pair_i, P.pair_j, tp, msg)) {
+      h->err = msg;
+      return AMSP_ERR_ARG;
+    }
+  }
+  bool ok = true;
+  TreeDev &t = h->td;
+  t.nfront = tp.nfront;
+  t.K = upload(h, tp.K, ok);
+  t.T = upload(h, tp.T, ok);
+  t.kdof = upload(h, tp.kdof, ok);
+  t.udof = upload(h, tp.udof, ok);
+  t.dbase = upload(h, tp.dbase, ok);
+  t.rbase = upload(h, tp.rbase, ok);
+  t.vbase = upload(h, tp.vbase, ok);
+  t.parent = upload(h, tp.parent, ok);
+  t.fbase = upload(h, tp.fbase, ok);
+  t.xbase = upload(h, tp.xbase, ok);
+  t.row_coarse = upload(h, tp.row_coarse, ok);
+  t.gptr = upload(h, tp.gptr, ok);
+  t.gsrc = upload(h, tp.gsrc, ok);
+  t.ea_row = upload(h, tp.ea_row, ok);
+  t.ch_front = upload(h, tp.ch_front, ok);
+  t.as_pair = upload(h, tp.as_pair, ok);
+  t.as_rev = upload(h, tp.as_rev, ok);
+  t.as_front = upload(h, tp.as_front, ok);
+  t.as_ri = upload(h, tp.as_ri, ok);
+  t.as_rj = upload(h, tp.as_rj, ok);
+  t.pair_i = h->cplan.pair_i;
+  t.pair_j = h->cplan.pair_j;
+  if (!ok) {
+    h->err = "device allocation or upload failed (coarse tree)";
+    return AMSP_ERR_OOM;
+  }
+  const Plan &p = h->plan;
+  const CoarsePlan &c = h->cplan;
+  const int nn = h->nev * h->nev;
+  double *W, *pb, *F, *dinv;
+  int *cstat;
+  ALLOC(W, double, (size_t)P.ext_ptr.back() * h->nev);
+  ALLOC(pb, double, std::max<size_t>((size_t)c.npairs * nn, 1));
+  ALLOC(F, double, (size_t)tp.ftiles * TE);
+  ALLOC(h->X64, double, (size_t)tp.xtiles * TE);
+  ALLOC(dinv, double, (size_t)std::max(tp.dtiles, 1) * TE);
+  ALLOC(cstat, int, 1);
+  ALLOC(h->ty, double, std::max(h->nc, 1));
+  ALLOC(h->tv, double, std::max(tp.nvec, 1));
+  HIP_TRY(hipMemsetAsync(cstat, 0, sizeof(int), h->stream));
+  launch_fill(h->stream, (size_t)tp.ftiles * TE, F, 0.0);
+  launch_fill(h->stream, (size_t)tp.xtiles * TE, h->X64, 0.0);
+  launch_tree_init(h->stream, t, tp.nfront, tp.max_T, F, h->X64);
+  launch_apply_A_to_basis(h->stream, p, c, h->val, h->phi64, W);
+  launch_pair_blocks(h->stream, p, c, h->phi64, W, pb);
+  launch_tree_assemble(h->stream, p, t, (int)tp.as_pair.size(), pb, F);
+  HIP_TRY(hipGetLastError());
+  if (h->opt.keep_a0) {  // the dense A0 for amsp_get_coarse_matrix
+    const int T0 = h->T0;
+    double *A0t;
+    ALLOC(A0t, double, (size_t)T0 * T0 * TE);
+    launch_fill(h->stream, (size_t)T0 * T0 * TE, A0t, 0.0);
+    launch_pair_products(h->stream, p, c, h->phi64, W, A0t, T0);
+    launch_symmetrize_tiles(h->stream, A0t, T0, h->nc);
+    h->a0keep = A0t;
+  }
+  const int MS = std::max(tp.max_slots, 1);
+  for (int lv = 0; lv < tp.nlevel; ++lv) {
+    const int f0 = tp.lvl_ptr[lv], f1 = tp.lvl_ptr[lv + 1];
+    for (int cs = 0; cs < tp.max_slots; ++cs) {
+      const int a = tp.ch_ptr[(size_t)lv * MS + cs], b = tp.ch_ptr[(size_t)lv * MS + cs + 1];
+      int maxU = 0;
+      for (int q = a; q < b; ++q) {
+        const int ch = tp.ch_front[q], U = tp.T[ch] - tp.K[ch];
+        maxU = std::max(maxU, U * (U + 1) / 2);
+      }
+      launch_tree_extend_add(h->stream, t, t.ch_front + a, b - a, maxU, F);
+    }
+    for (int k = 0; k < tp.lvl_maxK[lv]; ++k)
+      launch_tree_factor_step(h->stream, t, f0, f1, tp.lvl_maxT[lv], k, F, dinv, cstat);
+    for (int k = 0; k < tp.lvl_maxK[lv]; ++k)
+      launch_tree_inverse_step(h->stream, t, f0, f1, tp.lvl_maxT[lv], k, F, dinv, h->X64);
+    HIP_TRY(hipGetLastError());
+  }
+  int cs = 0;
+  HIP_TRY(hipMemcpyAsync(&cs, cstat, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (cs) {
+    h->err = "coarse matrix A0 not SPD";
+    return AMSP_ERR_COARSE_NOT_SPD;
+  }
+  h->mem.free_one(W);
+  h->mem.free_one(pb);
+  h->mem.free_one(F);
+  h->mem.free_one(dinv);
+  h->mem.free_one(cstat);
+  if (mixed) {
+    ALLOC(h->X32, float, (size_t)tp.xtiles * TE);
+    launch_tree_x_to_f32(h->stream, h->X64, h->X32, tp.xtiles);
+    HIP_TRY(hipGetLastError());
+    h->mem.free_one(h->X64);  // waits for the stream
+    h->X64 = nullptr;
+  }
+  h->sinfo.coarse_fronts = tp.nfront;
+  h->sinfo.coarse_levels = tp.nlevel;
+  h->sinfo.coarse_gflop = tp.flops * 1e-9;
+  h->sinfo.coarse_factor_mb = (double)tp.xtiles * TE * (mixed ? 4 : 8) * 1e-6;
+  h->sinfo.phase_ms[6] = now_ms() - t5;
+  return AMSP_OK;
+}
+
+// The coarse solve x = A0^{-1} c through the handle's factorisation.
+static void coarse_solve_tree(amsp_handle *h, hipStream_t s, const double *c, double *x,
+                              const int *done) {
+  const TreePlan &tp = h->tp;
+  if (h->X32)
+    launch_tree_solve<float>(s, h->td, tp.lvl_ptr, tp.lvl_maxT, tp.lvl_maxK, tp.max_K, tp.max_T,
+                             h->X32, c, h->ty, h->tv, x, done);
+  else
+    launch_tree_solve<double>(s, h->td, tp.lvl_ptr, tp.lvl_maxT, tp.lvl_maxK, tp.max_K, tp.max_T,
+                              h->X64, c, h->ty, h->tv, x, done);
 }
 
 static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
@@ -761,7 +902,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     launch_build_basis(h->stream, p, h->sdiag, X, h->phi64, h->opt.pou);
     // mixed forms: A0 is formed from the basis as stored (rounded), so the
     // coarse term stays the Galerkin projection of the basis it applies
-    if (mixed)
+    if (mixed && h->opt.coarse_basis == 0)
       launch_basis_round(h->stream, h->phi64, (size_t)sum_ni * h->nev,
                          h->opt.precision == AMSP_MIXED_BF16 ? 1 : 0);
     HIP_TRY(hipGetLastError());
@@ -802,7 +943,10 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
 
   // --- coarse matrix A0 = R0 A R0^T and its inverse factor
   const int T0 = h->T0;
-  if (h->nc > 0) {
+  if (h->nc > 0 && h->tree) {
+    const amsp_status ts = tree_coarse_setup(h, P);
+    if (ts != AMSP_OK) return ts;
+  } else if (h->nc > 0) {
     double *W, *A0t, *dinv;
     int *cstat;
     ALLOC(W, double, (size_t)P.ext_ptr.back() * h->nev);
@@ -883,6 +1027,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       h->W0 = nullptr;
     }
     h->sinfo.phase_ms[6] = now_ms() - t5;
+    h->sinfo.coarse_factor_mb = (double)T0 * (T0 + 1) / 2 * TE * (mixed ? 4 : 8) * 1e-6;
   }
   double t6 = now_ms();
   h->sinfo.phase_ms[5] = (t6 - t4) - h->sinfo.phase_ms[6];
@@ -958,7 +1103,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   HIP_TRY(hipMemsetAsync(h->cvec, 0, ncp * sizeof(double), h->stream));
   HIP_TRY(hipMemsetAsync(h->t1, 0, ncp * sizeof(double), h->stream));
   HIP_TRY(hipMemsetAsync(h->tvec, 0, ncp * sizeof(double), h->stream));
-  ALLOC(h->trmv_part, double, (size_t)std::max(1, T0 * T0) * TS);
+  ALLOC(h->trmv_part, double, h->tree ? 1 : (size_t)std::max(1, T0 * T0) * TS);
   ALLOC(h->r, double, h->n);
   if (h->opt.cycle == 1) {
     ALLOC(h->mq, double, h->n);
@@ -1053,6 +1198,14 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
     g_setup_error = "eig_shift must be positive";
     return AMSP_ERR_ARG;
   }
+  if (o.coarse_solver < 0 || o.coarse_solver > 2) {
+    g_setup_error = "coarse_solver must be 0, 1 or 2";
+    return AMSP_ERR_ARG;
+  }
+  if (o.coarse_basis < 0 || o.coarse_basis > 1) {
+    g_setup_error = "coarse_basis must be 0 or 1";
+    return AMSP_ERR_ARG;
+  }
   if (o.cycle < 0 || o.cycle > 1 || !(o.smoother_weight >= 0.0) || !std::isfinite(o.smoother_weight)) {
     g_setup_error = "cycle must be 0 or 1 and smoother_weight finite and >= 0";
     return AMSP_ERR_ARG;
@@ -1101,6 +1254,8 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
   }
   h->nc = h->hp.nc;
   h->T0 = (h->nc + TS - 1) / TS;
+  h->tree = !o.singular && (o.coarse_solver == 2 || (o.coarse_solver == 0 && h->nc > 8192));
+  h->sinfo.coarse_solver = h->tree ? 2 : 1;
   h->sinfo.phase_ms[0] = now_ms() - t0;
   h->sinfo.nsub = h->N;
   h->sinfo.nc = h->nc;
@@ -1159,7 +1314,11 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
                                               e1);
   }
   tpair_done(h, 1, tk);
-  if (do_coarse) {
+  if (do_coarse && h->tree) {
+    tk = tstart(h, 2);
+    coarse_solve_tree(h, h->stream, h->cvec, h->tvec, done);
+    tstop(h, 2, tk);
+  } else if (do_coarse) {
     tk = tstart(h, 2);
     if (!mixed) {
       launch_trmv<double>(h->stream, h->W0, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
@@ -1206,7 +1365,7 @@ static size_t block_ws_doubles(const amsp_handle *h) {
   const size_t rows = (size_t)h->hp.vp_ptr.back();
   const size_t ncp = (size_t)std::max(1, h->T0 * TS);
   return 3 * rows * EIGP + 3 * ncp * EIGP +
-         std::max<size_t>((size_t)h->T0 * h->T0, 1) * TS * EIGP;
+         (h->tree ? 1 : std::max<size_t>((size_t)h->T0 * h->T0, 1) * TS * EIGP);
 }
 
 // Carves the workspace out of one buffer of block_ws_doubles(h) doubles.
@@ -1238,7 +1397,8 @@ static amsp_status apply_block(amsp_handle *h, const double *r, double *z, int n
     ALLOC(h->bC, double, ncp * EIGP);
     ALLOC(h->bT, double, ncp * EIGP);
     ALLOC(h->bC2, double, ncp * EIGP);
-    ALLOC(h->bPart, double, std::max<size_t>((size_t)h->T0 * h->T0, 1) * TS * EIGP);
+    ALLOC(h->bPart, double,
+          h->tree ? 1 : std::max<size_t>((size_t)h->T0 * h->T0, 1) * TS * EIGP);
     launch_fill(h->stream, ncp * EIGP, h->bC, 0.0);  // coarse padding stays zero
   }
   const BlockWs ws{h->bX, h->bY, h->bXN, h->bC, h->bT, h->bC2, h->bPart, false};
@@ -1281,7 +1441,9 @@ static amsp_status apply_block_ws(amsp_handle *h, const double *r, double *z, in
     else
       launch_restrict_multi<__hip_bfloat16>(s, p, nr, ncp, (const __hip_bfloat16 *)phi, bX, bC);
     // t_k = W0^T (W0 c_k) for all columns, W0's tiles read once per product
-    if (!mixed) {
+    if (h->tree) {
+      for (int k = 0; k < nr; ++k) coarse_solve_tree(h, s, bC + k * ncp, bT + k * ncp, nullptr);
+    } else if (!mixed) {
       launch_trmm<double>(s, h->W0, h->T0, bC, ncp, nr, bPart, bC2, 0);
       launch_trmm<double>(s, h->W0, h->T0, bC2, ncp, nr, bPart, bT, 1);
     } else {
@@ -1441,7 +1603,8 @@ static int64_t bytes_per_iter(const amsp_handle *h) {
              : 2 * apply_factor_elems(P) * fb;
   if (h->nc > 0) {
     b += sni * h->nev * pb * 2;                     // restrict + prolong basis reads
-    b += 2 * (int64_t)h->T0 * (h->T0 + 1) / 2 * TE * (mixed ? 4 : 8);  // coarse W0 twice
+    b += h->tree ? 2 * (int64_t)h->tp.xtiles * TE * (mixed ? 4 : 8)        // fronts' X twice
+                 : 2 * (int64_t)h->T0 * (h->T0 + 1) / 2 * TE * (mixed ? 4 : 8);  // W0 twice
   }
   b += sni * (8 + 8) + n * 8 * 3;                   // scatter: inverse map, locals, z, r
   if (h->opt.flexible) b += n * 8;
@@ -1618,6 +1781,7 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
     const bool conv = rt[k] <= std::max(rtol, fl[k]) && std::isfinite(rt[k]);
     if (!conv) inf.converged = 0;
     inf.iterations += its[k];
+    inf.first_segment += its[k];  // the block path does not split its segments
     inf.relres_true = std::max(inf.relres_true, rt[k]);
     inf.relres_recursive = std::max(inf.relres_recursive, rec[k]);
     inf.relres_floor = std::max(inf.relres_floor, fl[k]);
@@ -1661,6 +1825,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
         st = amsp_pcg(h, f_dev + (size_t)k0 * n, u_dev + (size_t)k0 * n, 1, rtol, maxit, &one);
         if (st != AMSP_OK && st != AMSP_ERR_PCG_NOCONV) return st;
         inf.iterations += one.iterations;
+        inf.first_segment += one.first_segment;
         inf.relres_true = std::max(inf.relres_true, one.relres_true);
         inf.relres_recursive = std::max(inf.relres_recursive, one.relres_recursive);
         inf.relres_floor = std::max(inf.relres_floor, one.relres_floor);
@@ -1698,7 +1863,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   }
   double t0 = now_ms();
   amsp_status final_status = AMSP_OK;
-  int tot_it = 0;
+  int tot_it = 0, tot_first = 0;
   double worst_true = 0.0, worst_rec = 0.0, worst_floor = 0.0;
   int all_conv = 1, tot_restarts = 0;
   PcgState hs{};
@@ -1808,6 +1973,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
       break;
     }
     const double rel_rec = hs.f2 > 0 ? std::sqrt(hs.rr / hs.f2) : 0.0;
+    tot_first += h->seg_cut.empty() ? hs.it : h->seg_cut.front();
     h->hist_len = std::min(hs.it + 1, h->hist_cap);
     h->hist_f2 = hs.f2;
     tot_it += hs.it;
@@ -1820,6 +1986,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
     if (!conv && final_status == AMSP_OK) final_status = AMSP_ERR_PCG_NOCONV;
   }
   inf.iterations = tot_it;
+  inf.first_segment = tot_first;
   inf.converged = all_conv;
   inf.relres_recursive = worst_rec;
   inf.relres_true = worst_true;
@@ -2042,6 +2209,7 @@ extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u
   }
   release();
   inf.iterations = tot_it;
+  inf.first_segment = tot_it;  // GMRES: every step counts (no CG segments)
   inf.converged = all_conv;
   inf.relres_recursive = worst_est;
   inf.relres_true = worst_true;

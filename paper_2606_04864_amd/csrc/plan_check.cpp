@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "amsp_plan.h"
+#include "tree_check.h"
 
 using namespace amsp;
 
@@ -119,6 +120,16 @@ void plan_case(const Grid &g, int nev, int overlap, int order, int dense, const 
   expect(cores_in, std::string(name) + ": cores inside regions");
   std::printf("ok %s: N %d, sum n_i %d, tiles %lld, pairs %zu\n", name, N, P.sd_ptr[N],
               P.ntiles, P.pair_i.size());
+  if (nev > 0) {  // the sparse coarse factorisation on this plan's coupling
+    TreePlan tp;
+    s = build_tree_plan(N, P.mi, P.coff, P.pair_i, P.pair_j, tp, msg) ? 0 : 1;
+    expect(s == 0, std::string(name) + ": tree plan " + msg);
+    const double err = tree_emulate(N, nev, P.mi, P.coff, P.pair_i, P.pair_j, 7u, msg);
+    expect(err >= 0 && err < 1e-11, std::string(name) + ": tree solve " + msg + " err " +
+                                        std::to_string(err));
+    std::printf("ok %s: coarse tree %d fronts, %d levels, max front %d tiles, solve err %.2e\n",
+                name, tp.nfront, tp.nlevel, tp.max_T, err);
+  }
 }
 
 void reject_case(Grid g, int what, int want, const char *name) {
@@ -147,6 +158,9 @@ int main() {
       plan_case(g3, 8, 1, order, dense, "3d delta1");
     }
   plan_case(g2, 0, 0, 0, 0, "2d no overlap, nev 0");
+  // deeper coarse trees: 256 parts in 2D, 216 in 3D
+  plan_case(make_grid(128, 128, 1, 16, 16, 1), 4, 1, 0, 0, "2d 256 parts");
+  plan_case(make_grid(24, 24, 24, 6, 6, 6), 4, 1, 0, 0, "3d 216 parts");
   plan_case(one, 3, 1, 0, 0, "one part");
   reject_case(g2, 0, AMSP_ERR_CSR, "unsorted columns");
   reject_case(g2, 1, AMSP_ERR_NONSYM, "asymmetric");

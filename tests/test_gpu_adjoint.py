@@ -4,7 +4,12 @@ A and to f (paper_2606_04864_amd.solve, amsp_grad_values).  Not part of the
 paper's method; it differentiates the solve the preconditioner serves.
 
 Checked against the oracle's gradient from direct sparse solves, and against
-central differences of the GPU solve itself.  The solves run to a relative
+central differences of the GPU solve itself.  On the adjoint configuration
+(adjoint256) the gradient with respect to theta = log kappa chains the solve's
+adjoint through the torch two-point-flux assembly (workloads.tpfa_torch):
+against the oracle's theta_gradient at 1e-8 and against central differences
+on 50 random unit directions (h = 1e-5, those solves to 1e-13) at 1e-6 of
+||dJ/dtheta||, for the FP64 and the mixed form.  The solves run to a relative
 residual of 1e-12; the bars (max-abs error over max-abs value): u and the
 gradients 1e-8 (FP64 form) and 1e-7 (mixed form, whose preconditioner differs
 but whose CG runs in FP64); central differences 1e-5 plus 1e-7 of the largest
@@ -102,3 +107,72 @@ def test_solve_gradient_central_differences():
         an = float(gv[ks].sum())
         say(f"  entry {k} ({i},{j}): fd {fd:.8e} adjoint {an:.8e}")
         assert abs(fd - an) <= 1e-5 * abs(an) + 1e-7 * gmax
+
+
+# --------------------------------------------------------------------------
+# The adjoint configuration: 256 x 256, theta = log kappa (GRF, variance 4),
+# J = 0.5 ||u(theta) - u_obs||^2; dJ/dtheta by the adjoint solve chained
+# through the torch two-point-flux assembly (the forward model), against the
+# oracle's gradient (sparse direct solves + the closed-form derivatives of
+# the assembly) and against central differences on 50 random unit
+# directions (h = 1e-5, solves to 1e-12).
+_ADJ = {}
+
+
+def _adjoint_case():
+    if "w" not in _ADJ:
+        from workloads.tpfa_torch import TpfaAssembly
+        w = W.get("adjoint256")
+        A = w.A.to_scipy()
+        _, J, g = O.theta_gradient(A, w.b, w.u_obs, w.kappa)
+        _ADJ["w"] = (w, TpfaAssembly(w.grid, w.A.row_ptr, w.A.col_idx), J, g)
+    return _ADJ["w"]
+
+
+def _theta_loss(w, asm, theta, precision, ft, ut, rtol=RTOL):
+    vals = asm.values(theta)
+    u = P.solve(vals, ft, w.A.row_ptr, w.A.col_idx, w.part, w.nparts, w.nev, rtol=rtol,
+                overlap=w.overlap, precision=precision)
+    return 0.5 * ((u - ut) ** 2).sum()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_theta_gradient_matches_oracle(precision):
+    w, asm, Jo, go = _adjoint_case()
+    say(f"dJ/dtheta vs oracle: adjoint256, precision={precision}")
+    ft = torch.tensor(w.b, device="cuda")
+    ut = torch.tensor(w.u_obs, device="cuda")
+    theta = torch.tensor(w.theta, device="cuda", requires_grad=True)
+    J = _theta_loss(w, asm, theta, precision, ft, ut)
+    J.backward()
+    g = theta.grad.detach().cpu().numpy()
+    eJ, eg = abs(float(J.detach()) - Jo) / Jo, _rel(g, go)
+    say(f"  J {float(J.detach()):.10e} (oracle {Jo:.10e}, rel {eJ:.2e}); dJ/dtheta {eg:.2e}")
+    assert eJ <= 1e-8 and eg <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_theta_gradient_central_differences_50_directions(precision):
+    w, asm, Jo, go = _adjoint_case()
+    say(f"dJ/dtheta vs central differences, 50 directions: adjoint256, precision={precision}")
+    ft = torch.tensor(w.b, device="cuda")
+    ut = torch.tensor(w.u_obs, device="cuda")
+    th0 = torch.tensor(w.theta, device="cuda", requires_grad=True)
+    _theta_loss(w, asm, th0, precision, ft, ut).backward()
+    g = th0.grad.detach()
+    gn = float(torch.linalg.norm(g))
+    rng = np.random.default_rng(2605)
+    h = 1e-5
+    worst = 0.0
+    # the difference quotient divides the solves' error by h: they run to 1e-13
+    for k in range(50):
+        d = torch.tensor(rng.standard_normal(w.grid), device="cuda")
+        d /= torch.linalg.norm(d)
+        with torch.no_grad():
+            jp = float(_theta_loss(w, asm, th0 + h * d, precision, ft, ut, rtol=1e-13))
+            jm = float(_theta_loss(w, asm, th0 - h * d, precision, ft, ut, rtol=1e-13))
+        fd = (jp - jm) / (2 * h)
+        an = float((g * d).sum())
+        worst = max(worst, abs(fd - an) / gn)
+        assert abs(fd - an) <= 1e-6 * gn, (k, fd, an, gn)
+    say(f"  worst |fd - g.d| / ||g|| over 50 directions: {worst:.2e}")

@@ -161,3 +161,68 @@ def test_mixed_coarse_is_galerkin_of_stored_basis(prec):
     assert info["converged"] == 1 and info["relres_true"] <= max(1e-8, info["relres_floor"])
     assert ue <= 1e-6
     pc.close()
+
+
+# ---------------------------------------------------------------------------
+# The sparse coarse factorisation (coarse_solver="sparse": multifrontal
+# Cholesky over a nested-dissection tree of the subdomains) on the same
+# 24-tile case: the same bars against the oracle as the dense one.
+def test_sparse_coarse_matches_oracle():
+    w, A, st, alt = case()
+    pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, coarse_solver="sparse",
+                 keep_a0=True)
+    si = pc.info
+    say(f"sparse coarse: {si['coarse_fronts']} fronts, {si['coarse_levels']} levels, "
+        f"{si['coarse_gflop']:.2f} GFLOP, X {si['coarse_factor_mb']:.1f} MB, "
+        f"coarse phase {si['phase_ms'][6]:.2f} ms")
+    assert si["coarse_solver"] == 2 and si["coarse_levels"] >= 3
+    r = np.random.default_rng(63).standard_normal(w.n)
+    for parts, f in [(2, O.coarse_part), (3, O.apply)]:
+        ref, other = f(st, r), f(alt, r)
+        F = relerr(other, ref)
+        z = host(pc.apply(dev(r), parts=parts))
+        err = relerr(z, ref)
+        say(f"  sparse parts={parts}: err {err:.2e} bar {max(1e-10, 10 * F):.2e}")
+        assert err <= max(1e-10, 10 * F)
+        e = core_errors(z, ref, w.part, w.nparts)
+        bar = np.maximum(1e-10, 10 * core_errors(other, ref, w.part, w.nparts))
+        assert np.all(e <= bar)
+    # several columns at once go through the same sparse solve per column
+    R = np.random.default_rng(64).standard_normal((w.n, 3))
+    Z = host(pc.apply(torch.tensor(R, device="cuda"), parts=2))
+    for j in range(3):
+        ref = O.coarse_part(st, R[:, j])
+        assert relerr(Z[:, j], ref) <= max(1e-10, 10 * relerr(O.coarse_part(alt, R[:, j]), ref))
+    u, info = pc.pcg(dev(w.b), 1e-8, 1000)
+    ref = O.pcg(A, w.b, st.apply, 1e-8)
+    Fu = relerr(O.pcg(A, w.b, alt.apply, 1e-8).x, ref.x)
+    uerr = relerr(host(u), ref.x)
+    say(f"  sparse pcg: its {info['iterations']} (oracle {ref.iterations}), u err {uerr:.2e}")
+    assert info["converged"] == 1 and uerr <= max(1e-10, 10 * Fu)
+    pc.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_sparse_coarse_mixed_matches_dense(prec):
+    """The mixed forms with the sparse coarse factorisation: the coarse term
+    agrees with the dense factorisation's (both from the same rounded basis
+    and FP64 A0; they differ by float32 storage of two different inverse
+    factors), and PCG reaches the attainable residual."""
+    w, A, st, _ = case()
+    ps = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec,
+                 coarse_solver="sparse")
+    pd = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec,
+                 coarse_solver="dense")
+    r = dev(np.random.default_rng(65).standard_normal(w.n))
+    d = relerr(host(ps.apply(r, parts=2)), host(pd.apply(r, parts=2)))
+    u, info = ps.pcg(dev(w.b), 1e-8, 2000)
+    ud, infod = pd.pcg(dev(w.b), 1e-8, 2000)
+    say(f"{prec} sparse vs dense coarse term {d:.2e}; PCG its {info['iterations']} "
+        f"(dense {infod['iterations']})")
+    assert d <= 1e-4
+    assert info["converged"] == 1 and info["relres_true"] <= max(1e-8, info["relres_floor"])
+    # bfloat16 bases make the iteration count erratic: the sparse factor must
+    # not need more steps than the dense one (up to 5 percent)
+    assert info["iterations"] <= 2 + 1.05 * infod["iterations"]
+    ps.close()
+    pd.close()

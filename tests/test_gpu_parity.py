@@ -229,8 +229,9 @@ def test_pcg_parity(name):
     uh = host(u)
     F = relerr(res_alt.x, res.x)
     err = relerr(uh, res.x)
-    say(f"  u err {err:.2e} bar {max(1e-10, 10 * F):.2e} (its {info['iterations']} vs "
-        f"{res.iterations})")
+    say(f"  u err {err:.2e} bar {max(1e-10, 10 * F):.2e} (its {info['iterations']}, first "
+        f"segment {info['first_segment']}, restarts {info['restarts']}; oracle {res.iterations})")
+    assert abs(info["first_segment"] - res.iterations) <= slack
     assert err <= max(1e-10, 10 * F), (err, F)
     check_cores(uh, res.x, w, core_errors(res_alt.x, res.x, w.part, w.nparts), "u")
     pc.close()

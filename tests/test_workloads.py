@@ -57,3 +57,26 @@ def test_grf_statistics():
     f = darcy.gaussian_random_field((256, 256), 4.0, 0.05, rng)
     assert abs(f.var() - 4.0) < 1.5
     assert abs(f.mean()) < 1.5
+
+
+def test_torch_assembly_equals_generator():
+    """workloads.tpfa_torch (the differentiable forward model) gives the
+    generator's CSR values in the same order, 2D and 3D."""
+    torch = pytest.importorskip("torch")
+    from workloads.tpfa_torch import TpfaAssembly
+    rng = np.random.default_rng(3)
+    for shape in [(9, 7), (5, 4, 3)]:
+        th = 2.0 * rng.standard_normal(shape)
+        M = darcy.tpfa_matrix(np.exp(th))
+        v = TpfaAssembly(shape, M.row_ptr, M.col_idx).values(torch.tensor(th)).numpy()
+        assert np.abs(v - M.val).max() <= 1e-15 * np.abs(M.val).max()
+
+
+def test_adjoint_workload():
+    w = configs.adjoint(nx=32, nparts=4)
+    assert w.theta.shape == (32, 32) and np.allclose(np.exp(w.theta), w.kappa)
+    A = w.A.to_scipy()
+    # u_obs solves the perturbed problem, not this one
+    r = np.linalg.norm(A @ w.u_obs - w.b) / np.linalg.norm(w.b)
+    assert r > 1e-3
+    assert abs(w.theta.var() - 4.0) < 2.0

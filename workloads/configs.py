@@ -15,6 +15,9 @@ The paper's fields exist only as figures, so these recipes stand in for them:
                     sinuous channels (x1e6) per layer, kz = 0.1 kx, 4096 parts,
                     1 overlap layer, 8 eigenvectors.
   * gauss<N>     -- the gauss1024 recipe at a smaller side N (parity sizes).
+  * adjoint256   -- 256x256, theta = log kappa = GRF(var 4, corr 0.05), f = 1, u_obs
+                    from theta + GRF(var 0.25, corr 0.1), 64 parts, 2 overlap layers,
+                    6 eigenvectors (the loss J = 0.5 ||u - u_obs||^2).
 """
 from __future__ import annotations
 
@@ -106,6 +109,36 @@ def neumann(nx: int = 64, nparts: int = 16, overlap: int = 1, nev: int = 4,
     return Workload(f"neumann{nx}", A, b, part, nparts, overlap, nev, kappa, (nx, nx))
 
 
+@dataclasses.dataclass
+class AdjointWorkload(Workload):
+    """The adjoint configuration: theta = log kappa and the observation."""
+    theta: np.ndarray = None
+    u_obs: np.ndarray = None
+
+
+def adjoint(nx: int = 256, nparts: int = 64, overlap: int = 2, nev: int = 6,
+            seed_key: int = 5) -> AdjointWorkload:
+    """The adjoint configuration: theta = log kappa = GRF(var 4, corr 0.05)
+    on nx x nx cells, f = 1, J = 0.5 ||u(theta) - u_obs||^2 with u_obs the
+    solution for theta_obs = theta + GRF(var 0.25, corr 0.1).  Seeds: the
+    third and fourth sub-streams of SeedSequence(260604864 + 5) (the first
+    two serve `neumann`).  u_obs is a sparse direct solve (SuperLU): an input,
+    not a result of the preconditioner."""
+    import scipy.sparse.linalg as spla
+    streams = _streams(seed_key)
+    rng_theta, rng_obs = streams[2], streams[3]
+    theta = darcy.gaussian_random_field((nx, nx), 4.0, 0.05, rng_theta)
+    theta_obs = theta + darcy.gaussian_random_field((nx, nx), 0.25, 0.1, rng_obs)
+    kappa = np.exp(theta)
+    A = darcy.tpfa_matrix(kappa)
+    b = darcy.rhs_from_source(np.ones((nx, nx)))
+    A_obs = darcy.tpfa_matrix(np.exp(theta_obs)).to_scipy().tocsc()
+    u_obs = spla.spsolve(A_obs, b)
+    part = partition(A.row_ptr, A.col_idx, nparts)
+    return AdjointWorkload(f"adjoint{nx}", A, b, part, nparts, overlap, nev, kappa, (nx, nx),
+                           theta=theta, u_obs=u_obs)
+
+
 @functools.lru_cache(maxsize=8)
 def get(name: str) -> Workload:
     """Workloads by name; cached per process."""
@@ -119,6 +152,9 @@ def get(name: str) -> Workload:
         nx = int(name[5:])
         nparts = max(4, (nx * nx) // 1024)
         return gauss_inclusions(nx=nx, nparts=nparts)
+    if name.startswith("adjoint"):
+        nx = int(name[7:])
+        return adjoint(nx=nx, nparts=max(4, (nx * nx) // 1024))
     if name.startswith("neumann"):
         nx = int(name[7:])
         return neumann(nx=nx, nparts=max(4, (nx * nx) // 256))
