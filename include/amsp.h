@@ -252,6 +252,30 @@ amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t
  * cache.  info sums the columns' iterations and reports the worst residuals;
  * a last single column takes the one-column path. */
 
+/* Independent problems solved together (the batched form): the handle's
+ * matrix is block-diagonal, block s being problem s on rows
+ * [prob_ptr[s], prob_ptr[s+1]) (set up as one matrix with one partition,
+ * the parts of each problem disjoint: every kernel of the setup and of each
+ * step then covers all problems at once).  One CG recurrence per (problem,
+ * column) pair, nrhs columns (1 .. 16, n apart, column-major): each shares
+ * every matrix product and preconditioner application (the block path of
+ * amsp_apply) but takes its scalars from its own problem's rows, so it
+ * follows the iterates of that problem solved alone up to rounding.  The
+ * stopping rule of amsp_pcg (true residual, attainable floor, at most 3
+ * restarts) applies per recurrence, with ||f|| that problem's column norm.
+ *   prob_ptr    host int64[nprob + 1]: 0 = prob_ptr[0] < ... < prob_ptr[nprob] = n
+ *   iterations  host int32[nprob * nrhs] (problem-major) or NULL: steps taken
+ *   relres      host double[nprob * nrhs] or NULL: true relative residuals
+ * info sums the steps and reports the worst residuals.  Errors: AMSP_ERR_ARG
+ * for a bad prob_ptr, nrhs outside 1..16, cycle = 1, or a stored entry of A
+ * that couples two problems (checked on the device); AMSP_ERR_PCG_NOCONV if
+ * some recurrence did not converge (u holds the last iterates).  Workspace:
+ * 4 n nrhs doubles and small tables from the handle's cache.  Blocks. */
+amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int64_t *prob_ptr,
+                             const double *f_dev, double *u_dev, int32_t nrhs, double rtol,
+                             int32_t maxit, amsp_info *info, int32_t *iterations,
+                             double *relres);
+
 /* Restarted GMRES with the preconditioner, the Krylov method of the paper's
  * experiments (Section 5: GMRES preconditioned by the two-level method, run
  * until the relative residual has dropped by a factor 1e-6).  Right

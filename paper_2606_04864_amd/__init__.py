@@ -103,6 +103,9 @@ _lib.amsp_apply_noalloc.argtypes = [_vp, _vp, _vp, _i32, _i32]
 _lib.amsp_apply_noalloc.restype = _i32
 _lib.amsp_pcg.argtypes = [_vp, _vp, _vp, _i32, _d, _i32, ctypes.POINTER(_Info)]
 _lib.amsp_pcg.restype = _i32
+_lib.amsp_pcg_batched.argtypes = [_vp, _i32, _vp, _vp, _vp, _i32, _d, _i32, ctypes.POINTER(_Info),
+                                  _vp, _vp]
+_lib.amsp_pcg_batched.restype = _i32
 _lib.amsp_gmres.argtypes = [_vp, _vp, _vp, _i32, _i32, _d, _i32, ctypes.POINTER(_Info)]
 _lib.amsp_gmres.restype = _i32
 _lib.amsp_spmv.argtypes = [_vp, _vp, _vp]
@@ -135,7 +138,7 @@ _lib.amsp_setup_error.argtypes = []
 _lib.amsp_setup_error.restype = ctypes.c_char_p
 
 EXPORTED = ["amsp_default_options", "amsp_setup", "amsp_apply", "amsp_apply_parts",
-            "amsp_apply_noalloc", "amsp_pcg",
+            "amsp_apply_noalloc", "amsp_pcg", "amsp_pcg_batched",
             "amsp_gmres",
             "amsp_spmv", "amsp_grad_values", "amsp_get_setup_info", "amsp_get_pcg_history", "amsp_get_eigenvalues", "amsp_get_coarse_matrix",
             "amsp_get_region", "amsp_plan_regions", "amsp_selftest_mfma", "amsp_destroy",
@@ -387,6 +390,33 @@ class Preconditioner:
         if st != AMSP_OK and (raise_on_noconv or st != -9):
             raise AmspError(st, _lib.amsp_last_error(self._h).decode())
         return u, info
+
+    def pcg_batched(self, F, prob_ptr, rtol: float = 1e-8, maxit: int = 1000,
+                    raise_on_noconv=True):
+        """Independent problems together: A is block-diagonal with blocks on
+        rows [prob_ptr[s], prob_ptr[s+1]); F (n, k) float64 device tensor,
+        k <= 16.  One CG recurrence per (problem, column).  Returns (U, info,
+        iterations (nprob, k), true relative residuals (nprob, k))."""
+        torch = _torch()
+        _check_dev(F, "F", self.n)
+        k = 1 if F.dim() == 1 else F.shape[1]
+        pp = np.ascontiguousarray(prob_ptr, dtype=np.int64)
+        nprob = len(pp) - 1
+        Ft = F.reshape(self.n, k).t().contiguous()
+        Ut = torch.empty_like(Ft)
+        its = np.zeros((nprob, k), dtype=np.int32)
+        rel = np.zeros((nprob, k), dtype=np.float64)
+        inf = _Info()
+        st = _lib.amsp_pcg_batched(self._h, nprob, pp.ctypes.data, Ft.data_ptr(), Ut.data_ptr(), k,
+                                   float(rtol), int(maxit), ctypes.byref(inf), its.ctypes.data,
+                                   rel.ctypes.data)
+        info = {name: getattr(inf, name) for name, _ in _Info._fields_
+                if name not in ("kernel_ms", "kernel_launches")}
+        info["status"] = STATUS.get(st, st)
+        if st != AMSP_OK and (raise_on_noconv or st != -9):
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
+        U = Ut.t().reshape(F.shape) if F.dim() == 2 else Ut.reshape(-1)
+        return U, info, its, rel
 
     def gmres(self, f, rtol: float = 1e-6, restart: int = 30, maxit: int = 1000, out=None,
               raise_on_noconv=True):

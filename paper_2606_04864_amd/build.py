@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I" + CSRC,
           "-Wno-unused-command-line-argument"]
 
 SOURCES = ["k_krylov.hip", "k_local.hip", "k_apply.hip", "k_eigen.hip", "k_coarse.hip", "k_multi.hip",
-           "k_tree.hip", "amsp_tree.cpp",
+           "k_tree.hip", "k_batch.hip", "amsp_tree.cpp",
            "amsp_plan.cpp",
            "amsp_host.cpp"]
 

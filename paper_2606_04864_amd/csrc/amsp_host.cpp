@@ -2016,6 +2016,229 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
 // Methods for Sparse Linear Systems, Section 9.4.1): Arnoldi on A M^{-1}
 // with the preconditioned vectors kept, Gram-Schmidt twice per step on the
 // device, Givens rotations and the triangular solve on the host.
+// ------------------------------------------ independent problems at once --
+// One CG recurrence per (problem, column) on a block-diagonal matrix whose
+// blocks are the problems (rows [prob_ptr[s], prob_ptr[s+1])).  Every matrix
+// product and preconditioner application acts on all problems and columns
+// at once (the preconditioner of a block-diagonal matrix is block-diagonal:
+// its regions, local factors and coarse blocks never couple two problems);
+// the scalars of each recurrence come from its own problem's rows only.  The
+// stopping rule of amsp_pcg applies per recurrence, restarts included.
+extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int64_t *prob_ptr,
+                                        const double *f_dev, double *u_dev, int32_t nrhs,
+                                        double rtol, int32_t maxit, amsp_info *info,
+                                        int32_t *iterations, double *relres) {
+  if (!h || !prob_ptr || !f_dev || !u_dev || nprob < 1 || nrhs < 1 || nrhs > EIGP ||
+      !(rtol > 0.0) || maxit < 0)
+    return AMSP_ERR_ARG;
+  if (h->opt.cycle == 1) {
+    h->err = "amsp_pcg_batched: the multiplicative cycle is not available here";
+    return AMSP_ERR_ARG;
+  }
+  if (prob_ptr[0] != 0 || prob_ptr[nprob] != h->n) {
+    h->err = "amsp_pcg_batched: prob_ptr must run from 0 to n";
+    return AMSP_ERR_ARG;
+  }
+  for (int q = 0; q < nprob; ++q)
+    if (prob_ptr[q + 1] <= prob_ptr[q]) {
+      h->err = "amsp_pcg_batched: prob_ptr must be increasing";
+      return AMSP_ERR_ARG;
+    }
+  const double t0 = now_ms();
+  const int n = h->n, nseg = nprob, nr = nrhs, nrec = nseg * nr;
+  const size_t ld = (size_t)n, tot = ld * nr;
+  hipStream_t s = h->stream;
+  // row blocks of at most CH rows inside each problem
+  constexpr long long CH = 2048;
+  std::vector<long long> brow{0};
+  std::vector<int> bseg, sblk{0};
+  for (int q = 0; q < nseg; ++q) {
+    for (long long r = prob_ptr[q]; r < prob_ptr[q + 1]; r += CH) {
+      bseg.push_back(q);
+      brow.push_back(std::min<long long>(r + CH, prob_ptr[q + 1]));
+    }
+    sblk.push_back((int)bseg.size());
+  }
+  const int nblk = (int)bseg.size();
+  bool ok = true;
+  const long long *d_brow = upload(h, brow, ok);
+  const int *d_bseg = upload(h, bseg, ok);
+  const int *d_sblk = upload(h, sblk, ok);
+  std::vector<long long> sp(prob_ptr, prob_ptr + nprob + 1);
+  const long long *d_sptr = upload(h, sp, ok);
+  double *R = h->mem.alloc<double>(tot), *Z = h->mem.alloc<double>(tot),
+         *Pd = h->mem.alloc<double>(tot), *Q = h->mem.alloc<double>(tot);
+  double *part = h->mem.alloc<double>((size_t)nblk * nr);
+  double *sc = h->mem.alloc<double>((size_t)5 * nrec);  // alpha/beta, dots, rr, r2, a2
+  double *st_rz = h->mem.alloc<double>(nrec), *st_f2 = h->mem.alloc<double>(nrec),
+         *st_rr = h->mem.alloc<double>(nrec);
+  int *st_act = h->mem.alloc<int>(nrec), *st_its = h->mem.alloc<int>(nrec),
+      *flags = h->mem.alloc<int>(2);
+  auto release = [&]() {
+    for (const void *b : {(const void *)d_brow, (const void *)d_bseg, (const void *)d_sblk,
+                          (const void *)d_sptr, (const void *)R, (const void *)Z,
+                          (const void *)Pd, (const void *)Q, (const void *)part, (const void *)sc,
+                          (const void *)st_rz, (const void *)st_f2, (const void *)st_rr,
+                          (const void *)st_act, (const void *)st_its, (const void *)flags})
+      if (b) h->mem.free_one(const_cast<void *>(b));
+  };
+  if (!ok || !R || !Z || !Pd || !Q || !part || !sc || !st_rz || !st_f2 || !st_rr || !st_act ||
+      !st_its || !flags) {
+    release();
+    h->err = "amsp_pcg_batched: device allocation failed";
+    return AMSP_ERR_OOM;
+  }
+  double *alpha = sc, *dots = sc + nrec, *rrn = sc + 2 * nrec, *r2d = sc + 3 * nrec,
+         *a2d = sc + 4 * nrec;
+  // the problems must not be coupled
+  {
+    HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
+    launch_check_blocks(s, n, h->rowptr, h->col, nseg, d_sptr, flags);
+    int fl = 0;
+    HIP_TRY(hipMemcpyAsync(&fl, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (fl) {
+      release();
+      h->err = "amsp_pcg_batched: a stored entry couples two problems";
+      return AMSP_ERR_ARG;
+    }
+  }
+  auto rec_to_host = [&](const double *src, std::vector<double> &dst) -> hipError_t {
+    dst.resize(nrec);
+    hipError_t e = hipMemcpyAsync(dst.data(), src, nrec * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+  };
+  std::vector<double> f2, rr(nrec), rt(nrec, 0.0), fl(nrec, 0.0), rec(nrec, 0.0);
+  std::vector<int> active(nrec), its(nrec, 0);
+  launch_fill(s, tot, u_dev, 0.0);
+  HIP_TRY(hipMemcpyAsync(R, f_dev, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, f_dev, f_dev, part, dots);
+  HIP_TRY(rec_to_host(dots, f2));
+  for (int r = 0; r < nrec; ++r) {
+    if (!std::isfinite(f2[r])) {
+      release();
+      h->err = "right-hand side not finite";
+      return AMSP_ERR_BREAKDOWN;
+    }
+    rr[r] = f2[r];
+    active[r] = f2[r] > 0.0;
+  }
+  HIP_TRY(hipMemcpyAsync(st_f2, f2.data(), nrec * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(st_its, 0, nrec * sizeof(int), s));
+  HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
+  int *fl_host = nullptr;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&fl_host), 4 * sizeof(int), hipHostMallocDefault));
+  hipEvent_t fev[2] = {nullptr, nullptr};
+  struct Guard {
+    int *p;
+    hipEvent_t *e;
+    ~Guard() {
+      for (int k = 0; k < 2; ++k)
+        if (e[k]) (void)hipEventDestroy(e[k]);
+      if (p) (void)hipHostFree(p);
+    }
+  } guard{fl_host, fev};
+  for (hipEvent_t &e : fev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  const double rtol2 = rtol * rtol;
+  int it = 0;
+  bool breakdown = false;
+  amsp_status st = AMSP_OK;
+  for (int restarts = 0;; ++restarts) {
+    HIP_TRY(hipMemcpyAsync(st_act, active.data(), nrec * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(st_rr, rr.data(), nrec * sizeof(double), hipMemcpyHostToDevice, s));
+    if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) {
+      release();
+      return st;
+    }
+    launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, R, Z, part, st_rz);
+    HIP_TRY(hipMemcpyAsync(Pd, Z, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+    bool live = false;
+    for (int v : active) live = live || v;
+    int pend = -1;
+    while (live && it < maxit) {
+      launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, Pd, Q);
+      launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, Pd, Q, part, dots);
+      launch_seg_alpha(s, nrec, st_rz, st_f2, st_rr, st_act, st_its, flags, dots, alpha);
+      launch_seg_update(s, nblk, nseg, d_brow, d_bseg, d_sblk, ld, nr, alpha, Pd, Q, u_dev, R,
+                        part, rrn);
+      if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) {
+        release();
+        return st;
+      }
+      launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, R, Z, part, dots);
+      launch_seg_beta(s, nrec, st_rz, st_f2, st_rr, st_act, st_its, flags, rrn, dots, rtol2, alpha);
+      launch_seg_direction(s, nblk, nseg, d_brow, d_bseg, ld, nr, alpha, Z, Pd);
+      const int slot = pend == 0 ? 1 : 0;
+      HIP_TRY(hipMemcpyAsync(fl_host + 2 * slot, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(fev[slot], s));
+      HIP_TRY(hipGetLastError());
+      ++it;
+      if (pend >= 0) {  // the previous step's flags, read while this step runs
+        HIP_TRY(hipEventSynchronize(fev[pend]));
+        if (fl_host[2 * pend + 1] == 0) {
+          --it;  // this step found no active recurrence (its coefficients are zero)
+          pend = -1;
+          break;
+        }
+      }
+      pend = slot;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<double> rrv;
+    HIP_TRY(rec_to_host(st_rr, rrv));
+    HIP_TRY(hipMemcpy(its.data(), st_its, nrec * sizeof(int), hipMemcpyDeviceToHost));
+    int fb = 0;
+    HIP_TRY(hipMemcpy(&fb, flags, sizeof(int), hipMemcpyDeviceToHost));
+    breakdown = breakdown || fb != 0;
+    for (int r = 0; r < nrec; ++r) rec[r] = f2[r] > 0.0 ? std::sqrt(rrv[r] / f2[r]) : 0.0;
+    // true residuals R = F - A U and their attainable floors, per recurrence
+    launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, u_dev, Q);
+    launch_sub_columns(s, tot, f_dev, Q, R);
+    launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, R, R, part, r2d);
+    for (int k = 0; k < nr; ++k)
+      launch_abs_spmv_rows(s, n, h->rowptr, h->col, h->val, u_dev + k * ld, Q + k * ld);
+    launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, Q, Q, part, a2d);
+    std::vector<double> r2, a2;
+    HIP_TRY(rec_to_host(r2d, r2));
+    HIP_TRY(rec_to_host(a2d, a2));
+    bool again = false;
+    for (int r = 0; r < nrec; ++r) {
+      const double fk = std::sqrt(f2[r]);
+      rt[r] = fk > 0.0 ? std::sqrt(r2[r]) / fk : 0.0;
+      fl[r] = fk > 0.0 ? DBL_EPSILON * std::sqrt(a2[r]) / fk : 0.0;
+      rr[r] = r2[r];
+      const bool okr = !(fk > 0.0) || rt[r] <= std::max(rtol, fl[r]);
+      active[r] = !okr && std::isfinite(rt[r]) && restarts < 3 && it < maxit && !breakdown;
+      again = again || active[r];
+    }
+    if (!again) break;
+  }
+  amsp_info inf{};
+  inf.converged = 1;
+  for (int r = 0; r < nrec; ++r) {
+    const bool conv = (rt[r] <= std::max(rtol, fl[r]) || f2[r] == 0.0) && std::isfinite(rt[r]);
+    if (!conv) inf.converged = 0;
+    inf.iterations += its[r];
+    inf.first_segment += its[r];
+    inf.relres_true = std::max(inf.relres_true, rt[r]);
+    inf.relres_recursive = std::max(inf.relres_recursive, rec[r]);
+    inf.relres_floor = std::max(inf.relres_floor, fl[r]);
+    if (iterations) iterations[(size_t)(r % nseg) * nr + r / nseg] = its[r];
+    if (relres) relres[(size_t)(r % nseg) * nr + r / nseg] = rt[r];
+  }
+  inf.restarts = 0;
+  inf.solve_ms = now_ms() - t0;
+  inf.bytes_per_iter = 0;
+  if (info) *info = inf;
+  release();
+  if (breakdown) {
+    h->err = "CG breakdown in a recurrence (p.Ap <= 0 or a non-finite value)";
+    return AMSP_ERR_BREAKDOWN;
+  }
+  return inf.converged ? AMSP_OK : AMSP_ERR_PCG_NOCONV;
+}
+
 extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                                   int32_t restart, double rtol, int32_t maxit, amsp_info *info) {
   if (!h || !f_dev || !u_dev || nrhs < 1 || restart < 1 || restart > AMSP_GMRES_MAX_RESTART ||

@@ -293,4 +293,28 @@ template <typename T>
 void launch_trmv(hipStream_t s, const T *Wt, int T0, const double *x, double *part, double *y,
                  int transpose, const int *done);
 
+// ------------------------------------ independent problems (k_batch.hip) ---
+// Recurrence r = k * nseg + s (column k, problem s); row blocks never cross
+// a problem boundary (rows of block b: [brow[b], brow[b+1]), problem bseg[b];
+// problem s owns blocks [sblk[s], sblk[s+1])).
+void launch_seg_dots(hipStream_t s, int nblk, int nseg, const long long *brow, const int *sblk,
+                     size_t ld, int nr, const double *A, const double *B, double *part,
+                     double *out);
+void launch_seg_update(hipStream_t s, int nblk, int nseg, const long long *brow, const int *bseg,
+                       const int *sblk, size_t ld, int nr, const double *alpha, const double *P,
+                       const double *Q, double *X, double *R, double *part, double *rr);
+void launch_seg_direction(hipStream_t s, int nblk, int nseg, const long long *brow,
+                          const int *bseg, size_t ld, int nr, const double *beta, const double *Z,
+                          double *P);
+void launch_seg_alpha(hipStream_t s, int nrec, double *rz, double *f2, double *rr, int *active,
+                      int *its, int *flags, const double *pq, double *alpha);
+void launch_seg_beta(hipStream_t s, int nrec, double *rz, double *f2, double *rr, int *active,
+                     int *its, int *flags, const double *rrn, const double *rzn, double rtol2,
+                     double *beta);
+void launch_abs_spmv_rows(hipStream_t s, int n, const int *rp, const int *col, const double *val,
+                          const double *u, double *w);
+void launch_sub_columns(hipStream_t s, size_t tot, const double *F, const double *Q, double *R);
+void launch_check_blocks(hipStream_t s, int n, const int *rp, const int *col, int nseg,
+                         const long long *sptr, int *flag);
+
 }  // namespace amsp

@@ -139,6 +139,81 @@ def adjoint(nx: int = 256, nparts: int = 64, overlap: int = 2, nev: int = 6,
                            theta=theta, u_obs=u_obs)
 
 
+@dataclasses.dataclass
+class BatchWorkload:
+    """Independent problems concatenated into one block-diagonal system: A
+    (CSR), the concatenated partition (part ids offset per problem), the
+    right-hand sides B (n x nrhs, C order: column k is B[:, k]) and the
+    problems' row offsets seg_ptr (nprob + 1)."""
+    name: str
+    A: darcy.CSR
+    B: np.ndarray
+    part: np.ndarray
+    nparts: int
+    overlap: int
+    nev: int
+    seg_ptr: np.ndarray
+    sides: list
+    variances: list
+
+    @property
+    def n(self) -> int:
+        return self.A.n
+
+    @property
+    def nprob(self) -> int:
+        return len(self.sides)
+
+    def problem(self, p: int):
+        """(A_p as scipy CSR, its partition with ids from 0, its nparts, its rows)."""
+        a, b = int(self.seg_ptr[p]), int(self.seg_ptr[p + 1])
+        Ap = self.A.to_scipy()[a:b, a:b].tocsr()
+        pp = self.part[a:b]
+        return Ap, pp - pp.min(), int(pp.max() - pp.min() + 1), slice(a, b)
+
+
+def box_partition(nx: int, ny: int, px: int, py: int) -> np.ndarray:
+    """Cells (ix, iy), index ix + nx iy, in px x py rectangular boxes."""
+    ix = np.arange(nx) * px // nx
+    iy = np.arange(ny) * py // ny
+    return (ix[None, :] + px * iy[:, None]).ravel().astype(np.int32)
+
+
+def batch(nprob: int = 64, smin: int = 128, smax: int = 512, nrhs: int = 8, overlap: int = 1,
+          nev: int = 6, corr: float = 0.05, seed_key: int = 4) -> BatchWorkload:
+    """The batched configuration: nprob independent 2D two-point-flux Darcy
+    problems of side s ~ U{smin..smax}, log kappa = GRF(variance ~ U[2, 6],
+    correlation length 0.05), nrhs right-hand sides from N(0, 1) sources.
+    Each problem is cut into round(s/32)^2 rectangular boxes of ~1024 cells
+    (a graph partition of its grid), one overlap layer, 6 eigenvectors.
+    Seeds: sub-streams of SeedSequence(260604864 + 4): sizes and variances,
+    then one stream per problem for its field and sources."""
+    ss = np.random.SeedSequence(SEED_BASE + seed_key)
+    kids = ss.spawn(nprob + 1)
+    rng0 = np.random.default_rng(kids[0])
+    sides = [int(x) for x in rng0.integers(smin, smax + 1, size=nprob)]
+    variances = [float(x) for x in rng0.uniform(2.0, 6.0, size=nprob)]
+    mats, rhs, parts = [], [], []
+    poff = 0
+    for p, (s_, var) in enumerate(zip(sides, variances)):
+        rng = np.random.default_rng(kids[p + 1])
+        logk = darcy.gaussian_random_field((s_, s_), var, corr, rng)
+        Ap = darcy.tpfa_matrix(np.exp(logk)).to_scipy()
+        B = np.stack([darcy.rhs_from_source(rng.standard_normal((s_, s_))) for _ in range(nrhs)],
+                     axis=1)
+        nb = max(1, round(s_ / 32))
+        part = box_partition(s_, s_, nb, nb) + poff
+        poff += nb * nb
+        mats.append(Ap)
+        rhs.append(B)
+        parts.append(part)
+    import scipy.sparse as sp
+    A = darcy.CSR.from_scipy(sp.block_diag(mats, format="csr"))
+    seg = np.concatenate([[0], np.cumsum([m.shape[0] for m in mats])]).astype(np.int64)
+    return BatchWorkload(f"batch{nprob}", A, np.ascontiguousarray(np.concatenate(rhs, axis=0)),
+                         np.concatenate(parts), poff, overlap, nev, seg, sides, variances)
+
+
 @functools.lru_cache(maxsize=8)
 def get(name: str) -> Workload:
     """Workloads by name; cached per process."""
