@@ -21,7 +21,10 @@ reduction, and PCG to the same, outside the timed steps),
 setup + PCG to 1e-8, outside the timed steps), `multi_rhs` (16 columns per
 apply and 8 CG recurrences sharing each operator application, against one
 column at a time, outside the timed steps), `adjoint256` (forward and backward
-pass of dJ/dtheta on the adjoint configuration) and `cpu_baseline` (the oracle on
+pass of dJ/dtheta on the adjoint configuration), `batch64` (64 independent
+problems with 8 right-hand sides in one batched solve, default and autotuned
+schedules), `sweep_layered64` (subdomain size against eigenvectors per
+subdomain in 3D) and `cpu_baseline` (the oracle on
 a bounded sample, on the host cores) and `oracle_full_run` (the recorded run of
 the oracle on the whole workload against the GPU forms, from `--oracle-full`).
 """
@@ -46,13 +49,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(P, torch, w, f, prec, steps, warmup, timing):
+def run_form(P, torch, w, f, prec, steps, warmup, timing, coarse="auto"):
     rec = []
     for k in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec,
-                     timing=timing, timing_stride=TIMING_STRIDE)
+                     timing=timing, timing_stride=TIMING_STRIDE, coarse_solver=coarse)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         u, info = pc.pcg(f, 1e-8, 2000)
@@ -70,6 +73,7 @@ def run_form(P, torch, w, f, prec, steps, warmup, timing):
                             iterations=info["iterations"], relres_true=info["relres_true"],
                             relres_floor=info["relres_floor"], restarts=info["restarts"],
                             first_segment=info["first_segment"],
+                            coarse_solver=si["coarse_solver"],
                             kernel_ms=info["kernel_ms"], kernel_launches=info["kernel_launches"],
                             local_apply_bytes=info["local_apply_bytes"],
                             bytes_per_iter=info["bytes_per_iter"], u=u))
@@ -384,6 +388,76 @@ def adjoint_measure(P, torch, forms):
     return out
 
 
+def batch_measure(P, torch, forms):
+    """The batched configuration (batch64: 64 independent 2D problems of side
+    U{128..512}, lognormal kappa, 8 right-hand sides each; 512 CG recurrences
+    in one amsp_pcg_batched call on one block-diagonal setup).  The
+    autotuner first picks the subdomain size, nev and the columns per pass on
+    the batch's first 16 problems (mixed form); then the full
+    batch runs with the default schedule and with the tuned one.  One untimed
+    run, then one timed, host clock around synchronised calls; inputs
+    resident (the input transfer inside setup excluded)."""
+    from workloads import configs
+    from paper_2606_04864_amd import autotune
+
+    def make(box=32, nev=6):
+        s = configs.batch(box=box, nev=nev, first=16)
+        return dict(A=s.A, part=s.part, nparts=s.nparts, nev=s.nev, overlap=s.overlap, F=s.B,
+                    prob_ptr=s.seg_ptr)
+
+    cands = autotune.grid(box=[24, 32, 48], nev=[4, 6, 8], precision=["fp32"], columns=[8, 4])
+    best, table = autotune.autotune(make, cands, repeats=2, log=log)
+    out = {"autotune": {"sample": "the first 16 problems of the batch, mixed form, best of 2",
+                        "best": best, "candidates": table}}
+    for sched, box, nev, cols in (("default", 32, 6, 8),
+                                  ("tuned", best["box"], best["nev"], best["columns"])):
+        w = configs.batch(box=box, nev=nev)
+        prob = dict(A=w.A, part=w.part, nparts=w.nparts, nev=w.nev, overlap=w.overlap, F=w.B,
+                    prob_ptr=w.seg_ptr)
+        rec = {"box": box, "nev": nev, "columns": cols, "n": w.n, "problems": w.nprob,
+               "parts": w.nparts}
+        for prec in forms:
+            r = autotune.run_candidate(lambda **_: prob, {"precision": prec, "columns": cols})
+            rec[prec] = {k: r[k] for k in ("setup_ms", "pcg_ms", "total_ms", "steps_max",
+                                           "steps_mean", "converged", "worst_relres")}
+            log(f"[{prec}] batch64 {sched}: {rec[prec]}")
+        out[sched] = rec
+    return out
+
+
+def sweep_3d(P, torch):
+    """The subdomain-count / eigenvector-count trade-off (Section 5, parameter
+    test) on the 3D layered recipe at 64^3 (n = 262,144, one overlap layer,
+    mixed form): parts of ~2048, ~1024 and ~512 dofs (the 128^3 benchmark
+    configuration uses ~512) and nev 4, 8, 12; setup + PCG to 1e-8."""
+    from workloads import configs
+    out = []
+    for nparts in (128, 256, 512):
+        base = configs.layered(n=64, nparts=nparts, nev=8)
+        for nev in (4, 8, 12):
+            f = torch.tensor(base.b, device="cuda")
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pc = P.setup(base.A, base.part, nparts, nev, overlap=1, precision="fp32")
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, info = pc.pcg(f, 1e-8, 3000, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                upload = pc.info["phase_ms"][1]
+                nc = pc.info["nc"]
+                pc.close()
+            rec = {"parts": nparts, "dofs_per_part": base.n // nparts, "nev": nev, "nc": nc,
+                   "iterations": int(info["iterations"]),
+                   "setup_ms": round((t1 - t0) * 1e3 - upload, 2),
+                   "pcg_ms": round((t2 - t1) * 1e3, 2),
+                   "total_ms": round((t2 - t0) * 1e3 - upload, 2)}
+            out.append(rec)
+            log(f"sweep layered64: {rec}")
+    return out
+
+
 def gmres_measure(P, torch, w, f, forms, sums):
     """The paper's own solver configuration (Section 5): GMRES with the
     preconditioner, restarted every 30 steps, until the residual has dropped
@@ -420,6 +494,8 @@ def main():
     ap.add_argument("--workload", default="gauss1024")
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--coarse", default="auto", choices=["auto", "dense", "sparse"],
+                    help="coarse factorisation of the timed steps (default: the library's choice)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (no SpMV, GMRES, cycle, several-column, adjoint "
                          "or CPU-baseline sections)")
@@ -466,7 +542,7 @@ def main():
         # HIP events around every TIMING_STRIDE-th launch of the local-apply
         # kernel only: each timed launch adds two event records to the stream
         res[prec] = run_form(P, torch, w, f, prec, args.steps, args.warmup,
-                             timing=1 << P.KERNEL_CLASS["local"])
+                             timing=1 << P.KERNEL_CLASS["local"], coarse=args.coarse)
 
     def summary(rec):
         med = lambda k: float(np.median([r[k] for r in rec]))
@@ -478,6 +554,7 @@ def main():
                     iterations=int(rec[-1]["iterations"]), relres_true=float(rec[-1]["relres_true"]),
                     relres_floor=float(rec[-1]["relres_floor"]),
                     first_segment=int(rec[-1]["first_segment"]), restarts=int(rec[-1]["restarts"]),
+                    coarse_solver={1: "dense", 2: "sparse"}[int(rec[-1]["coarse_solver"])],
                     eig_sweeps=int(rec[-1]["eig_sweeps"]),
                     setup_phase_ms=[round(x, 3) for x in rec[-1]["phase_ms"]],
                     coupling_plan_ms=med("coupling_ms"), coupling_wait_ms=med("coupling_wait_ms"),
@@ -551,6 +628,10 @@ def main():
     line["multi_rhs"] = multi_rhs_measure(P, torch, w, f, forms)
     log("adjoint configuration ...")
     line["adjoint256"] = adjoint_measure(P, torch, forms)
+    log("batched configuration ...")
+    line["batch64"] = batch_measure(P, torch, forms)
+    log("3D subdomain / eigenvector sweep ...")
+    line["sweep_layered64"] = sweep_3d(P, torch)
     if not args.no_cpu:
         log("cpu baseline (oracle, bounded sample) ...")
         its64 = sums["fp64"]["iterations"] if "fp64" in sums else sums[head]["iterations"]

@@ -180,19 +180,23 @@ def box_partition(nx: int, ny: int, px: int, py: int) -> np.ndarray:
 
 
 def batch(nprob: int = 64, smin: int = 128, smax: int = 512, nrhs: int = 8, overlap: int = 1,
-          nev: int = 6, corr: float = 0.05, seed_key: int = 4) -> BatchWorkload:
+          nev: int = 6, corr: float = 0.05, seed_key: int = 4, box: int = 32,
+          first: int | None = None) -> BatchWorkload:
     """The batched configuration: nprob independent 2D two-point-flux Darcy
     problems of side s ~ U{smin..smax}, log kappa = GRF(variance ~ U[2, 6],
     correlation length 0.05), nrhs right-hand sides from N(0, 1) sources.
-    Each problem is cut into round(s/32)^2 rectangular boxes of ~1024 cells
-    (a graph partition of its grid), one overlap layer, 6 eigenvectors.
+    Each problem is cut into round(s/box)^2 rectangular boxes (box = 32: ~1024
+    cells; a graph partition of its grid), one overlap layer, 6 eigenvectors.
     Seeds: sub-streams of SeedSequence(260604864 + 4): sizes and variances,
-    then one stream per problem for its field and sources."""
+    then one stream per problem for its field and sources.  first: keep only
+    the first problems of the batch (a sample of the same problems)."""
     ss = np.random.SeedSequence(SEED_BASE + seed_key)
     kids = ss.spawn(nprob + 1)
     rng0 = np.random.default_rng(kids[0])
     sides = [int(x) for x in rng0.integers(smin, smax + 1, size=nprob)]
     variances = [float(x) for x in rng0.uniform(2.0, 6.0, size=nprob)]
+    if first is not None:
+        sides, variances = sides[:first], variances[:first]
     mats, rhs, parts = [], [], []
     poff = 0
     for p, (s_, var) in enumerate(zip(sides, variances)):
@@ -201,7 +205,7 @@ def batch(nprob: int = 64, smin: int = 128, smax: int = 512, nrhs: int = 8, over
         Ap = darcy.tpfa_matrix(np.exp(logk)).to_scipy()
         B = np.stack([darcy.rhs_from_source(rng.standard_normal((s_, s_))) for _ in range(nrhs)],
                      axis=1)
-        nb = max(1, round(s_ / 32))
+        nb = max(1, round(s_ / box))
         part = box_partition(s_, s_, nb, nb) + poff
         poff += nb * nb
         mats.append(Ap)
@@ -210,7 +214,7 @@ def batch(nprob: int = 64, smin: int = 128, smax: int = 512, nrhs: int = 8, over
     import scipy.sparse as sp
     A = darcy.CSR.from_scipy(sp.block_diag(mats, format="csr"))
     seg = np.concatenate([[0], np.cumsum([m.shape[0] for m in mats])]).astype(np.int64)
-    return BatchWorkload(f"batch{nprob}", A, np.ascontiguousarray(np.concatenate(rhs, axis=0)),
+    return BatchWorkload(f"batch{len(sides)}", A, np.ascontiguousarray(np.concatenate(rhs, axis=0)),
                          np.concatenate(parts), poff, overlap, nev, seg, sides, variances)
 
 
