@@ -250,7 +250,10 @@ amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t
  * every preconditioner application (the block path of amsp_apply).  The
  * workspace (4 n doubles per column) is allocated per call from the handle's
  * cache.  info sums the columns' iterations and reports the worst residuals;
- * a last single column takes the one-column path. */
+ * a last single column takes the one-column path.  A column that meets
+ * p.Ap <= 0 or a non-finite value stops there (keeping its last iterate);
+ * the others run to their own end, restarts included, and the call then
+ * returns AMSP_ERR_BREAKDOWN with u and info written for every column. */
 
 /* Independent problems solved together (the batched form): the handle's
  * matrix is block-diagonal, block s being problem s on rows
@@ -269,7 +272,11 @@ amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_dev, int32_t
  * info sums the steps and reports the worst residuals.  Errors: AMSP_ERR_ARG
  * for a bad prob_ptr, nrhs outside 1..16, cycle = 1, or a stored entry of A
  * that couples two problems (checked on the device); AMSP_ERR_PCG_NOCONV if
- * some recurrence did not converge (u holds the last iterates).  Workspace:
+ * some recurrence did not converge (u holds the last iterates);
+ * AMSP_ERR_BREAKDOWN if p.Ap <= 0 or a non-finite value stopped some
+ * recurrence: the others (every other problem's, and the same problem's
+ * other columns) run to their own end, and u, info, iterations and relres
+ * are written for all of them.  Workspace:
  * 4 n nrhs doubles and small tables from the handle's cache.  Blocks. */
 amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int64_t *prob_ptr,
                              const double *f_dev, double *u_dev, int32_t nrhs, double rtol,

@@ -39,11 +39,16 @@ ORDER = {"rcm": 0, "natural": 1}
 
 
 class AmspError(RuntimeError):
-    def __init__(self, code: int, msg: str):
+    """A non-OK status.  result holds what the call still wrote where the
+    library documents it (a CG breakdown in some columns or recurrences:
+    the same tuple the call returns on success), else None."""
+
+    def __init__(self, code: int, msg: str, result=None):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
         self.code = code
         self.name = STATUS.get(code, str(code))
         self.msg = msg
+        self.result = result
 
 
 class _CSR(ctypes.Structure):
@@ -341,7 +346,8 @@ class Preconditioner:
                 if name not in ("kernel_ms", "kernel_launches")}
         info["status"] = STATUS.get(st, st)
         if st != AMSP_OK and (raise_on_noconv or st != -9):
-            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
+            res = (u, info) if st == -10 and ft.shape[0] >= 2 else None
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode(), res)
         return u, info
 
     def spmv(self, x, out=None):
@@ -388,7 +394,8 @@ class Preconditioner:
         info["kernel_launches"] = list(inf.kernel_launches)
         info["status"] = STATUS.get(st, st)
         if st != AMSP_OK and (raise_on_noconv or st != -9):
-            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
+            res = (u, info) if st == -10 and f.dim() == 2 and f.shape[1] >= 2 else None
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode(), res)
         return u, info
 
     def pcg_batched(self, F, prob_ptr, rtol: float = 1e-8, maxit: int = 1000,
@@ -413,9 +420,10 @@ class Preconditioner:
         info = {name: getattr(inf, name) for name, _ in _Info._fields_
                 if name not in ("kernel_ms", "kernel_launches")}
         info["status"] = STATUS.get(st, st)
-        if st != AMSP_OK and (raise_on_noconv or st != -9):
-            raise AmspError(st, _lib.amsp_last_error(self._h).decode())
         U = Ut.t().reshape(F.shape) if F.dim() == 2 else Ut.reshape(-1)
+        if st != AMSP_OK and (raise_on_noconv or st != -9):
+            res = (U, info, its, rel) if st == -10 else None
+            raise AmspError(st, _lib.amsp_last_error(self._h).decode(), res)
         return U, info, its, rel
 
     def gmres(self, f, rtol: float = 1e-6, restart: int = 30, maxit: int = 1000, out=None,

@@ -1654,7 +1654,7 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
     active[k] = f2[k] > 0.0;
   }
   hist.push_back(f2[nr - 1]);
-  bool breakdown = false;
+  int broken = 0;  // bit k: column k broke down
   int it = 0;
   auto any_active = [&]() {
     for (int v : active)
@@ -1746,7 +1746,7 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
         its[k] = fin.its[k];
         active[k] = fin.active[k];
       }
-      breakdown = breakdown || fin.breakdown != 0;
+      broken |= fin.breakdown;
     }
     for (int k = 0; k < nr; ++k) rec[k] = f2[k] > 0.0 ? std::sqrt(rr[k] / f2[k]) : 0.0;
     // true residuals (left in R) and, where needed, the attainable floors
@@ -1772,7 +1772,8 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
       }
       rr[k] = r2;
       const bool ok = rt[k] <= std::max(rtol, fl[k]);
-      active[k] = !ok && std::isfinite(rt[k]) && restarts < 3 && it < maxit && !breakdown;
+      // a column that broke down stops; the others restart as usual
+      active[k] = !ok && std::isfinite(rt[k]) && restarts < 3 && it < maxit && !(broken >> k & 1);
       again = again || active[k];
     }
     if (!again) break;
@@ -1792,7 +1793,7 @@ static amsp_status pcg_columns(amsp_handle *h, const double *F, double *U, int n
   HIP_TRY(hipStreamSynchronize(s));
   release();
   h->mem.free_one(cs);
-  if (breakdown) {
+  if (broken) {
     h->err = "CG breakdown in a column (p.Ap <= 0 or a non-finite value)";
     return AMSP_ERR_BREAKDOWN;
   }
@@ -1815,6 +1816,7 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
     }
     const double t0 = now_ms();
     inf.converged = 1;
+    bool broke = false;  // a breakdown stops its column only: the others still run
     for (int k0 = 0; k0 < nrhs; k0 += EIGP) {
       const int nr = std::min(EIGP, nrhs - k0);
       amsp_status st = nr >= 2 ? pcg_columns(h, f_dev + (size_t)k0 * n, u_dev + (size_t)k0 * n, nr,
@@ -1823,19 +1825,28 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
       if (nr == 1) {  // a last single column: the one-column path
         amsp_info one{};
         st = amsp_pcg(h, f_dev + (size_t)k0 * n, u_dev + (size_t)k0 * n, 1, rtol, maxit, &one);
-        if (st != AMSP_OK && st != AMSP_ERR_PCG_NOCONV) return st;
+        if (st != AMSP_OK && st != AMSP_ERR_PCG_NOCONV && st != AMSP_ERR_BREAKDOWN) return st;
         inf.iterations += one.iterations;
         inf.first_segment += one.first_segment;
         inf.relres_true = std::max(inf.relres_true, one.relres_true);
         inf.relres_recursive = std::max(inf.relres_recursive, one.relres_recursive);
         inf.relres_floor = std::max(inf.relres_floor, one.relres_floor);
         if (!one.converged) inf.converged = 0;
+        if (st != AMSP_ERR_BREAKDOWN) st = AMSP_OK;
+      }
+      if (st == AMSP_ERR_BREAKDOWN) {
+        broke = true;
+        inf.converged = 0;
         st = AMSP_OK;
       }
       if (st != AMSP_OK) return st;
     }
     inf.solve_ms = now_ms() - t0;
     if (info) *info = inf;
+    if (broke) {
+      h->err = "CG breakdown in a column (p.Ap <= 0 or a non-finite value)";
+      return AMSP_ERR_BREAKDOWN;
+    }
     return inf.converged ? AMSP_OK : AMSP_ERR_PCG_NOCONV;
   }
   h->timing_active = h->opt.timing != 0;
@@ -2011,11 +2022,6 @@ extern "C" amsp_status amsp_pcg(amsp_handle *h, const double *f_dev, double *u_d
   return final_status;
 }
 
-// ---------------------------------------------------------------- GMRES ----
-// Restarted GMRES with flexible right preconditioning (Saad, Iterative
-// Methods for Sparse Linear Systems, Section 9.4.1): Arnoldi on A M^{-1}
-// with the preconditioned vectors kept, Gram-Schmidt twice per step on the
-// device, Givens rotations and the triangular solve on the host.
 // ------------------------------------------ independent problems at once --
 // One CG recurrence per (problem, column) on a block-diagonal matrix whose
 // blocks are the problems (rows [prob_ptr[s], prob_ptr[s+1])).  Every matrix
@@ -2072,7 +2078,7 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
   double *sc = h->mem.alloc<double>((size_t)5 * nrec);  // alpha/beta, dots, rr, r2, a2
   double *st_rz = h->mem.alloc<double>(nrec), *st_f2 = h->mem.alloc<double>(nrec),
          *st_rr = h->mem.alloc<double>(nrec);
-  int *st_act = h->mem.alloc<int>(nrec), *st_its = h->mem.alloc<int>(nrec),
+  int *st_act = h->mem.alloc<int>(nrec), *st_its = h->mem.alloc<int>((size_t)2 * nrec),
       *flags = h->mem.alloc<int>(2);
   auto release = [&]() {
     for (const void *b : {(const void *)d_brow, (const void *)d_bseg, (const void *)d_sblk,
@@ -2110,7 +2116,7 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
     return e;
   };
   std::vector<double> f2, rr(nrec), rt(nrec, 0.0), fl(nrec, 0.0), rec(nrec, 0.0);
-  std::vector<int> active(nrec), its(nrec, 0);
+  std::vector<int> active(nrec), its(nrec, 0), broken(nrec, 0);
   launch_fill(s, tot, u_dev, 0.0);
   HIP_TRY(hipMemcpyAsync(R, f_dev, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
   launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, f_dev, f_dev, part, dots);
@@ -2125,7 +2131,8 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
     active[r] = f2[r] > 0.0;
   }
   HIP_TRY(hipMemcpyAsync(st_f2, f2.data(), nrec * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(st_its, 0, nrec * sizeof(int), s));
+  int *st_brk = st_its + nrec;  // per recurrence: broke down
+  HIP_TRY(hipMemsetAsync(st_its, 0, 2 * nrec * sizeof(int), s));
   HIP_TRY(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
   int *fl_host = nullptr;
   HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&fl_host), 4 * sizeof(int), hipHostMallocDefault));
@@ -2159,7 +2166,7 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
     while (live && it < maxit) {
       launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, Pd, Q);
       launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, Pd, Q, part, dots);
-      launch_seg_alpha(s, nrec, st_rz, st_f2, st_rr, st_act, st_its, flags, dots, alpha);
+      launch_seg_alpha(s, nrec, st_rz, st_f2, st_rr, st_act, st_its, st_brk, flags, dots, alpha);
       launch_seg_update(s, nblk, nseg, d_brow, d_bseg, d_sblk, ld, nr, alpha, Pd, Q, u_dev, R,
                         part, rrn);
       if ((st = apply_block(h, R, Z, nr, 3)) != AMSP_OK) {
@@ -2167,7 +2174,8 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
         return st;
       }
       launch_seg_dots(s, nblk, nseg, d_brow, d_sblk, ld, nr, R, Z, part, dots);
-      launch_seg_beta(s, nrec, st_rz, st_f2, st_rr, st_act, st_its, flags, rrn, dots, rtol2, alpha);
+      launch_seg_beta(s, nrec, st_rz, st_f2, st_rr, st_act, st_its, st_brk, flags, rrn, dots, rtol2,
+                      alpha);
       launch_seg_direction(s, nblk, nseg, d_brow, d_bseg, ld, nr, alpha, Z, Pd);
       const int slot = pend == 0 ? 1 : 0;
       HIP_TRY(hipMemcpyAsync(fl_host + 2 * slot, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -2188,9 +2196,8 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
     std::vector<double> rrv;
     HIP_TRY(rec_to_host(st_rr, rrv));
     HIP_TRY(hipMemcpy(its.data(), st_its, nrec * sizeof(int), hipMemcpyDeviceToHost));
-    int fb = 0;
-    HIP_TRY(hipMemcpy(&fb, flags, sizeof(int), hipMemcpyDeviceToHost));
-    breakdown = breakdown || fb != 0;
+    HIP_TRY(hipMemcpy(broken.data(), st_brk, nrec * sizeof(int), hipMemcpyDeviceToHost));
+    for (int v : broken) breakdown = breakdown || v != 0;
     for (int r = 0; r < nrec; ++r) rec[r] = f2[r] > 0.0 ? std::sqrt(rrv[r] / f2[r]) : 0.0;
     // true residuals R = F - A U and their attainable floors, per recurrence
     launch_spmm_sell(s, n, h->sptr, h->scol, h->sval, ld, nr, u_dev, Q);
@@ -2209,7 +2216,8 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
       fl[r] = fk > 0.0 ? DBL_EPSILON * std::sqrt(a2[r]) / fk : 0.0;
       rr[r] = r2[r];
       const bool okr = !(fk > 0.0) || rt[r] <= std::max(rtol, fl[r]);
-      active[r] = !okr && std::isfinite(rt[r]) && restarts < 3 && it < maxit && !breakdown;
+      // a broken recurrence stops; the others restart as usual
+      active[r] = !okr && std::isfinite(rt[r]) && restarts < 3 && it < maxit && !broken[r];
       again = again || active[r];
     }
     if (!again) break;
@@ -2239,6 +2247,11 @@ extern "C" amsp_status amsp_pcg_batched(amsp_handle *h, int32_t nprob, const int
   return inf.converged ? AMSP_OK : AMSP_ERR_PCG_NOCONV;
 }
 
+// ---------------------------------------------------------------- GMRES ----
+// Restarted GMRES with flexible right preconditioning (Saad, Iterative
+// Methods for Sparse Linear Systems, Section 9.4.1): Arnoldi on A M^{-1}
+// with the preconditioned vectors kept, Gram-Schmidt twice per step on the
+// device, Givens rotations and the triangular solve on the host.
 extern "C" amsp_status amsp_gmres(amsp_handle *h, const double *f_dev, double *u_dev, int32_t nrhs,
                                   int32_t restart, double rtol, int32_t maxit, amsp_info *info) {
   if (!h || !f_dev || !u_dev || nrhs < 1 || restart < 1 || restart > AMSP_GMRES_MAX_RESTART ||

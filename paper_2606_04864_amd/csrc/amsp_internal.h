@@ -198,10 +198,10 @@ void launch_col_direction(hipStream_t s, int n, size_t ld, int nr, const double 
 struct ColCgState {
   double rz[EIGP], f2[EIGP], rr[EIGP];  // r.z, f.f and r.r (after the last update) per column
   int active[EIGP], its[EIGP];
-  int breakdown, nact;  // a column broke down; columns still active
+  int breakdown, nact;  // bit k: column k broke down; columns still active
 };
 // alpha_k = (r.z)_k / (p.Ap)_k for active columns (0 otherwise); a column with
-// p.Ap <= 0 or a non-finite ratio stops and sets breakdown.
+// p.Ap <= 0 or a non-finite ratio stops and sets its breakdown bit.
 void launch_col_alpha(hipStream_t s, int nr, ColCgState *cs, const double *pq, double *alpha);
 // After the update: an active column with r.r <= rtol2 f.f stops (a
 // non-finite r.r stops it with breakdown); the others take beta_k =
@@ -307,10 +307,10 @@ void launch_seg_direction(hipStream_t s, int nblk, int nseg, const long long *br
                           const int *bseg, size_t ld, int nr, const double *beta, const double *Z,
                           double *P);
 void launch_seg_alpha(hipStream_t s, int nrec, double *rz, double *f2, double *rr, int *active,
-                      int *its, int *flags, const double *pq, double *alpha);
+                      int *its, int *broken, int *flags, const double *pq, double *alpha);
 void launch_seg_beta(hipStream_t s, int nrec, double *rz, double *f2, double *rr, int *active,
-                     int *its, int *flags, const double *rrn, const double *rzn, double rtol2,
-                     double *beta);
+                     int *its, int *broken, int *flags, const double *rrn, const double *rzn,
+                     double rtol2, double *beta);
 void launch_abs_spmv_rows(hipStream_t s, int n, const int *rp, const int *col, const double *val,
                           const double *u, double *w);
 void launch_sub_columns(hipStream_t s, size_t tot, const double *F, const double *Q, double *R);

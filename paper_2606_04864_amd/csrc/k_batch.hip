@@ -16,7 +16,8 @@ namespace amsp {
 struct SegCgState {
   double *rz, *f2, *rr;  // nrec each
   int *active, *its;     // nrec each
-  int *flags;            // [0] breakdown, [1] active recurrences
+  int *broken;           // nrec: 1 once the recurrence broke down
+  int *flags;            // [1] active recurrences after the step
 };
 
 // part[k * nblk + b] = sum over the block's rows of A_k . B_k
@@ -82,7 +83,7 @@ __global__ void __launch_bounds__(WG) k_seg_direction(int nseg, const long long 
 }
 
 // alpha_r = (r.z)_r / (p.Ap)_r for active recurrences (0 otherwise); p.Ap <= 0
-// or a non-finite ratio stops the recurrence and sets the breakdown flag
+// or a non-finite ratio stops the recurrence and marks it broken
 __global__ void __launch_bounds__(WG) k_seg_alpha(int nrec, SegCgState st,
                                                   const double *__restrict__ pq,
                                                   double *__restrict__ alpha) {
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(WG) k_seg_alpha(int nrec, SegCgState st,
   if (st.active[r]) {
     const double q = st.rz[r] / pq[r];
     if (!(pq[r] > 0.0) || !isfinite(q)) {
-      atomicOr(st.flags, 1);
+      st.broken[r] = 1;
       st.active[r] = 0;
     } else {
       c = q;
@@ -115,7 +116,7 @@ __global__ void __launch_bounds__(WG) k_seg_beta(int nrec, SegCgState st,
     if (st.active[r]) {
       st.its[r] += 1;
       if (!isfinite(rr[r])) {
-        atomicOr(st.flags, 1);
+        st.broken[r] = 1;
         st.active[r] = 0;
       } else if (rr[r] <= rtol2 * st.f2[r]) {
         st.active[r] = 0;
@@ -198,15 +199,15 @@ void launch_seg_direction(hipStream_t s, int nblk, int nseg, const long long *br
 }
 
 void launch_seg_alpha(hipStream_t s, int nrec, double *rz, double *f2, double *rr, int *active,
-                      int *its, int *flags, const double *pq, double *alpha) {
-  const SegCgState st{rz, f2, rr, active, its, flags};
+                      int *its, int *broken, int *flags, const double *pq, double *alpha) {
+  const SegCgState st{rz, f2, rr, active, its, broken, flags};
   hipLaunchKernelGGL(k_seg_alpha, dim3((nrec + WG - 1) / WG), dim3(WG), 0, s, nrec, st, pq, alpha);
 }
 
 void launch_seg_beta(hipStream_t s, int nrec, double *rz, double *f2, double *rr, int *active,
-                     int *its, int *flags, const double *rrn, const double *rzn, double rtol2,
-                     double *beta) {
-  const SegCgState st{rz, f2, rr, active, its, flags};
+                     int *its, int *broken, int *flags, const double *rrn, const double *rzn,
+                     double rtol2, double *beta) {
+  const SegCgState st{rz, f2, rr, active, its, broken, flags};
   hipLaunchKernelGGL(k_seg_beta, dim3(1), dim3(WG), 0, s, nrec, st, rrn, rzn, rtol2, beta);
 }
 

@@ -408,16 +408,19 @@ __global__ void __launch_bounds__(64) k_col_alpha(int nr, ColCgState *cs,
   const int k = threadIdx.x;
   if (k >= nr) return;
   double c = 0.0;
+  bool brk = false;
   if (cs->active[k]) {
     const double q = cs->rz[k] / pq[k];
     if (!(pq[k] > 0.0) || !isfinite(q)) {
-      cs->breakdown = 1;
+      brk = true;
       cs->active[k] = 0;
     } else {
       c = q;
     }
   }
   alpha[k] = c;
+  const unsigned long long m = __ballot(brk);
+  if (k == 0 && m) cs->breakdown |= (int)m;
 }
 
 __global__ void __launch_bounds__(64) k_col_beta(int nr, ColCgState *cs,
@@ -426,13 +429,14 @@ __global__ void __launch_bounds__(64) k_col_beta(int nr, ColCgState *cs,
                                                  double *__restrict__ beta) {
   const int k = threadIdx.x;
   int act = 0;
+  bool brk = false;
   if (k < nr) {
     double c = 0.0;
     cs->rr[k] = rr[k];
     if (cs->active[k]) {
       cs->its[k] += 1;
       if (!isfinite(rr[k])) {
-        cs->breakdown = 1;
+        brk = true;
         cs->active[k] = 0;
       } else if (rr[k] <= rtol2 * cs->f2[k]) {
         cs->active[k] = 0;
@@ -444,8 +448,11 @@ __global__ void __launch_bounds__(64) k_col_beta(int nr, ColCgState *cs,
     beta[k] = c;
     act = cs->active[k];
   }
-  const unsigned long long m = __ballot(act != 0);
-  if (k == 0) cs->nact = __popcll(m);
+  const unsigned long long m = __ballot(act != 0), bm = __ballot(brk);
+  if (k == 0) {
+    cs->nact = __popcll(m);
+    if (bm) cs->breakdown |= (int)bm;
+  }
 }
 
 void launch_col_alpha(hipStream_t s, int nr, ColCgState *cs, const double *pq, double *alpha) {

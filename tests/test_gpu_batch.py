@@ -13,8 +13,10 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle as O
+from conftest import cg_breakdown_step, shifted_indefinite
 from workloads import configs
 
 pytestmark = pytest.mark.gpu
@@ -131,3 +133,49 @@ def test_full_batch_converges_and_matches_oracle_on_a_subset():
             for p in small:
                 check_problem(w, Uh, its, int(p), [0, 7], "full batch ")
         pc.close()
+
+
+def test_breakdown_stops_only_its_own_recurrences():
+    """Problem 0 SPD, problem 1 indefinite (A - sigma I, every local factor
+    SPD, nev = 0): problem 1's recurrences stop on the device at their first
+    p.Ap <= 0 with the oracle's iterate of the step before, while problem 0's
+    run to convergence and match the oracle; the call reports
+    AMSP_ERR_BREAKDOWN with every output written."""
+    ws, As, _, sigma = shifted_indefinite()
+    A0 = ws.A.to_scipy()
+    n = ws.n
+    M = sp.block_diag([A0, As], format="csr")
+    M.sort_indices()
+    part = np.concatenate([ws.part, ws.part + ws.nparts]).astype(np.int32)
+    pc = P.Preconditioner(M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data, part,
+                          2 * ws.nparts, 0, overlap=1)
+    F = np.random.default_rng(72).standard_normal((2 * n, 2))
+    with pytest.raises(P.AmspError) as e:
+        pc.pcg_batched(torch.tensor(F, device="cuda"), np.array([0, n, 2 * n]), 1e-8, 2000)
+    assert e.value.name == "AMSP_ERR_BREAKDOWN" and e.value.result is not None
+    U, info, its, rel = e.value.result
+    U = U.cpu().numpy()
+    st0 = O.setup(A0, ws.part, ws.nparts, 0, 1)
+    alt0 = O.setup(A0, ws.part, ws.nparts, 0, 1, local_order="descending")
+    st1 = O.setup(As, ws.part, ws.nparts, 0, 1)
+    alt1 = O.setup(As, ws.part, ws.nparts, 0, 1, local_order="descending")
+    for k in range(2):
+        f = F[:n, k]
+        ref = O.pcg(A0, f, st0.apply, 1e-8, 2000)
+        F0 = relerr(O.pcg(A0, f, alt0.apply, 1e-8, 2000).x, ref.x)
+        err = relerr(U[:n, k], ref.x)
+        h = np.array(ref.relres_history)
+        slack = 1 + int(np.sum((h > 1e-8) & (h < 3e-8)))
+        say(f"  SPD problem column {k}: its {its[0, k]} (oracle {ref.iterations}), true relres "
+            f"{rel[0, k]:.2e}, u err {err:.2e} bar {max(1e-10, 10 * F0):.2e}")
+        assert rel[0, k] <= 1e-8 * 1.0001
+        assert err <= max(1e-10, 10 * F0)
+        assert abs(int(its[0, k]) - ref.iterations) <= slack
+        t, xt = cg_breakdown_step(As, F[n:, k], st1.apply)
+        ta, xa = cg_breakdown_step(As, F[n:, k], alt1.apply)
+        e1, bar = relerr(U[n:, k], xt), max(1e-10, 10 * relerr(xa, xt))
+        say(f"  indefinite problem column {k} (sigma {sigma:.4f}): stops after {its[1, k]} "
+            f"steps (oracle {t}), iterate err {e1:.2e} bar {bar:.2e}")
+        assert t == ta and int(its[1, k]) == t
+        assert e1 <= bar
+    pc.close()

@@ -15,6 +15,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from conftest import cg_breakdown_step, shifted_indefinite
 
 pytestmark = pytest.mark.gpu
 
@@ -137,6 +138,42 @@ def test_block_pcg_mixed_and_edges():
     assert e.value.name == "AMSP_ERR_BREAKDOWN"
     u, info = pc.pcg(Ft[:, 0].contiguous(), 1e-8, 2000)  # the handle still solves
     assert info["converged"] == 1
+    pc.close()
+
+
+def test_block_pcg_breaks_down_mid_solve():
+    """An indefinite operator (A - sigma I, every local factor SPD, nev = 0):
+    each column stops on the device at its own first p.Ap <= 0 and keeps the
+    iterate of the step before, equal to the oracle's CG iterate of that
+    step; a zero column is untouched.  The call reports AMSP_ERR_BREAKDOWN
+    with u and info written for every column."""
+    w, As, val, sigma = shifted_indefinite()
+    st = O.setup(As, w.part, w.nparts, 0, 1)
+    alt = O.setup(As, w.part, w.nparts, 0, 1, local_order="descending")
+    pc = P.Preconditioner(w.A.row_ptr, w.A.col_idx, val, w.part, w.nparts, 0, overlap=1)
+    R = np.random.default_rng(71).standard_normal((w.n, 3))
+    F = np.column_stack([R[:, 1], np.zeros(w.n), R[:, 2]])
+    with pytest.raises(P.AmspError) as e:
+        pc.pcg(torch.tensor(F, device="cuda"), 1e-8, 500)
+    assert e.value.name == "AMSP_ERR_BREAKDOWN" and e.value.result is not None
+    U, info = e.value.result
+    U = host(U)
+    assert info["converged"] == 0 and np.all(U[:, 1] == 0)
+    steps = 0
+    for j in (0, 2):
+        t, xt = cg_breakdown_step(As, F[:, j], st.apply)
+        ta, xa = cg_breakdown_step(As, F[:, j], alt.apply)
+        assert t == ta and t >= 2
+        err, bar = relerr(U[:, j], xt), max(1e-10, 10 * relerr(xa, xt))
+        say(f"breakdown column {j}: oracle stops after {t} steps (sigma {sigma:.4f}), "
+            f"iterate err {err:.2e} bar {bar:.2e}")
+        assert err <= bar
+        steps += t
+    assert info["iterations"] == steps
+    # the one-column path stops on the same condition
+    with pytest.raises(P.AmspError) as e:
+        pc.pcg(torch.tensor(F[:, 0], device="cuda"), 1e-8, 500)
+    assert e.value.name == "AMSP_ERR_BREAKDOWN"
     pc.close()
 
 

@@ -80,3 +80,24 @@ def test_adjoint_workload():
     r = np.linalg.norm(A @ w.u_obs - w.b) / np.linalg.norm(w.b)
     assert r > 1e-3
     assert abs(w.theta.var() - 4.0) < 2.0
+
+
+def test_shifted_operator_breaks_cg_with_spd_local_factors():
+    """The breakdown cases' premise: A - sigma I is indefinite, every
+    overlapping region's Dirichlet matrix stays SPD (the oracle's local
+    Cholesky factors exist), and the oracle's CG meets p.Ap <= 0 within a
+    few steps on the right-hand sides those cases draw."""
+    import scipy.sparse as sp
+
+    import oracle as O
+    from conftest import cg_breakdown_step, shifted_indefinite
+    w, As, val, sigma = shifted_indefinite()
+    assert np.linalg.eigvalsh(As.toarray())[0] < 0
+    # the shifted values in the workload's CSR order are the shifted matrix
+    S = sp.csr_matrix((val, w.A.col_idx, w.A.row_ptr), shape=As.shape)
+    assert abs(S - As).max() == 0
+    st = O.setup(As, w.part, w.nparts, 0, 1)
+    R = np.random.default_rng(71).standard_normal((w.n, 3))
+    for j in (1, 2):
+        t, xt = cg_breakdown_step(As, R[:, j], st.apply)
+        assert 2 <= t <= 10
