@@ -334,7 +334,7 @@ __device__ __forceinline__ void stream_sweep(int nt, const int *es, const int *_
   // current block: index b in sweep order, its tile row I, stream start bs,
   // envelope size T and this thread's segment [bs + e0, bs + e0 + len)
   int b = 0, I = FWD ? 0 : nt - 1;
-  int bs = boff[I], T = es[I * TS + TS] - es[I * TS];
+  int bs = nt > 0 ? boff[I] : 0, T = es[I * TS + TS] - es[I * TS];
   int e0 = es[I * TS + rr] - es[I * TS], len = es[I * TS + rr + 1] - es[I * TS + rr];
   int cons = bs;  // stream position up to which this block's envelope has been used
   float acc = 0.f;
@@ -376,49 +376,63 @@ __device__ __forceinline__ void stream_sweep(int nt, const int *es, const int *_
         e0n = es[In * TS + rr] - sI;
         lenn = es[In * TS + rr + 1] - es[In * TS + rr];
       }
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
+      acc += dpp_quad_f<0xB1>(acc);  // the row's four partial sums (lanes 4rr .. 4rr+3)
+      acc += dpp_quad_f<0x4E>(acc);
       if (q == 0) tmp[rr] = v[I * TS + rr] + acc;
       __syncthreads();  // tmp complete
       const int dr = dI % RSZ;  // ring index of the diagonal tile
+      // Every LDS read of the diagonal step is issued before the first
+      // product, so that the step waits for LDS once.  Entries outside the
+      // triangle are read too (they lie inside the packed tile, which is
+      // whole in the ring) and dropped by a select.
       if (FWD) {
         // y[rr] = sum_c inv(L_II)[rr][c] tmp[c]: row rr, columns 16q .. 16q+15
         int ri = dr + dpos_row(rr) + 16 * q;
         ri = ri >= RSZ ? ri - RSZ : ri;
-        float y = 0.f;
+        f4 a[4], tt[4];
 #pragma unroll
         for (int c4 = 0; c4 < 4; ++c4) {
           const int rc = ri + 4 * c4 >= RSZ ? ri + 4 * c4 - RSZ : ri + 4 * c4;
-          if (16 * q + 4 * c4 <= rr) {
-            const f4 a = *reinterpret_cast<const f4 *>(ring + rc);
-            const float *tt = tmp + 16 * q + 4 * c4;
-            y = fmaf(a[0], tt[0], y);
-            y = fmaf(a[1], tt[1], y);
-            y = fmaf(a[2], tt[2], y);
-            y = fmaf(a[3], tt[3], y);
-          }
+          a[c4] = *reinterpret_cast<const f4 *>(ring + rc);
+          tt[c4] = *reinterpret_cast<const f4 *>(tmp + 16 * q + 4 * c4);
         }
-        y += __shfl_xor(y, 1, 64);
-        y += __shfl_xor(y, 2, 64);
+        float y = 0.f;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+          float s4 = a[c4][0] * tt[c4][0];
+          s4 = fmaf(a[c4][1], tt[c4][1], s4);
+          s4 = fmaf(a[c4][2], tt[c4][2], s4);
+          s4 = fmaf(a[c4][3], tt[c4][3], s4);
+          y += (16 * q + 4 * c4 <= rr) ? s4 : 0.f;
+        }
+        y += dpp_quad_f<0xB1>(y);
+        y += dpp_quad_f<0x4E>(y);
         if (q == 0) v[I * TS + rr] = y;
       } else {
-        // x[col] = sum_r inv(L_II)[r][col] tmp[r]: column 16w + (l & 15),
-        // rows 16 (l >> 4) .. +15
+        // x[col] = sum_r inv(L_II)[r][col] tmp[r]: lanes 4c .. 4c+3 of
+        // wavefront w hold column col = 16w + c; lane qq takes rows 4s + qq
         const int l = t & 63, w = t >> 6;
-        const int col = 16 * w + (l & 15), rw0 = 16 * (l >> 4);
-        int ri = dr + dpos_row(rw0) + col;  // entry (rw0, col); rows step by
-        ri = ri >= RSZ ? ri - RSZ : ri;     // their padded lengths
-        float x = 0.f;
+        const int col = 16 * w + (l >> 2), qq = l & 3;
+        const int base = dr + col + 4 * qq;  // entry (4s + qq, col) at base +
+        float rv[16], tv[16];                // dpos_row(4s + qq) - 4 qq
 #pragma unroll
-        for (int rq = 0; rq < 16; ++rq) {
-          const int row = rw0 + rq;
-          if (col <= row) x = fmaf(ring[ri], tmp[row], x);
-          ri += 4 * ((row >> 2) + 1);
+        for (int s4 = 0; s4 < 16; ++s4) {
+          int ri = base + 4 * qq * s4 + 8 * s4 * (s4 + 1);
           ri = ri >= RSZ ? ri - RSZ : ri;
+          rv[s4] = ring[ri];
+          tv[s4] = tmp[4 * s4 + qq];
         }
-        x += __shfl_xor(x, 16, 64);
-        x += __shfl_xor(x, 32, 64);
-        if ((l >> 4) == 0) v[I * TS + col] = x;
+        float x0 = 0.f, x1 = 0.f;  // two chains: rows 4s + qq for even and odd s
+#pragma unroll
+        for (int s4 = 0; s4 < 16; s4 += 2) {
+          const float p0 = rv[s4] * tv[s4], p1 = rv[s4 + 1] * tv[s4 + 1];
+          x0 += (col <= 4 * s4 + qq) ? p0 : 0.f;
+          x1 += (col <= 4 * s4 + 4 + qq) ? p1 : 0.f;
+        }
+        float x = x0 + x1;
+        x += dpp_quad_f<0xB1>(x);
+        x += dpp_quad_f<0x4E>(x);
+        if (qq == 0) v[I * TS + col] = x;
       }
       __syncthreads();  // block I final in v; tmp free
       acc = 0.f;

@@ -202,6 +202,12 @@ __device__ __forceinline__ double dpp_quad(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The same for a float.
+template <int CTRL>
+__device__ __forceinline__ float dpp_quad_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // Cholesky factor of a 64x64 SPD tile and the inverse of the factor, in LDS.
 //   a (stride LDT): lower triangle of the tile on entry, L on exit (upper 0)
 //   w (stride LDT): inv(L) on exit (upper 0)
