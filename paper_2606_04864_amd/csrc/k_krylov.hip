@@ -170,13 +170,63 @@ __global__ void __launch_bounds__(WG) k_cg_dir(int n, const long long *__restric
                                                const double *__restrict__ part_rzo, int nb, int t,
                                                int first, int flexible) {
   if (st->done) return;
-  __shared__ double sh[WG / 64];
+  __shared__ double sh[3][WG / 64];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // q = A p with p = z + beta p_old formed on the fly, on the sliced layout:
+  // U rows per thread (one 64-row slice per wavefront each), the first JU
+  // entries of every row loaded together.  The first rows' entries do not
+  // depend on beta: they are loaded before the partial sums are reduced, so
+  // that the two latencies overlap.
+  constexpr int U = 2, JU = 8;
+  const int stride = gridDim.x * WG;
+  long long base[U];
+  int wd[U];
+  int cj[U][JU];
+  double vj[U][JU];
+  auto load_rows = [&](int i0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * stride;
+      const int sl = i >> 6;
+      base[u] = i < n ? sptr[sl] : 0;
+      wd[u] = i < n ? (int)((sptr[sl + 1] - base[u]) >> 6) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < JU; ++j) {
+        const bool in = j < wd[u];
+        const long long e = base[u] + (long long)j * 64 + lane;
+        cj[u][j] = in ? scol[e] : 0;
+        vj[u][j] = in ? sval[e] : 0.0;
+      }
+  };
+  int i0 = blockIdx.x * WG + threadIdx.x;
+  if (i0 < n) load_rows(i0);
   double beta = 0.0;
   if (!first) {
-    const double rr = sum_partials(part_rr, nb, sh);
-    const double rz = sum_partials(part_rz, nb, sh);
-    const double rzo = flexible ? sum_partials(part_rzo, nb, sh) : 0.0;
+    // the three fixed-order sums of partials in one pass (the same order in
+    // every workgroup, so every workgroup takes the same beta)
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < nb; k += WG) {
+      a[0] += part_rr[k];
+      a[1] += part_rz[k];
+      if (flexible) a[2] += part_rzo[k];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) a[m] = wave_sum(a[m]);
+    if (lane == 0) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) sh[m][w] = a[m];
+    }
+    __syncthreads();
+    double rsum[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int v = 0; v < WG / 64; ++v) rsum[m] += sh[m][v];
+    const double rr = rsum[0], rz = rsum[1], rzo = flexible ? rsum[2] : 0.0;
     int stop = 0, brk = 0;
     if (!isfinite(rr)) {
       stop = brk = 1;
@@ -201,36 +251,11 @@ __global__ void __launch_bounds__(WG) k_cg_dir(int n, const long long *__restric
     }
     if (stop) return;
   }
-  // q = A p with p = z + beta p_old formed on the fly, on the sliced layout:
-  // U rows per thread (one 64-row slice per wavefront each), the first JU
-  // entries of every row loaded together.
-  constexpr int U = 2, JU = 8;
-  const int lane = threadIdx.x & 63;
-  const int stride = gridDim.x * WG;
   double acc = 0.0;
-  for (int i0 = blockIdx.x * WG + threadIdx.x; i0 < n; i0 += U * stride) {
-    long long base[U];
-    int wd[U];
+  for (; i0 < n; i0 += U * stride) {
     double sacc[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * stride;
-      const int sl = i >> 6;
-      base[u] = i < n ? sptr[sl] : 0;
-      wd[u] = i < n ? (int)((sptr[sl + 1] - base[u]) >> 6) : 0;
-      sacc[u] = 0.0;
-    }
-    int cj[U][JU];
-    double vj[U][JU];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int j = 0; j < JU; ++j) {
-        const bool in = j < wd[u];
-        const long long e = base[u] + (long long)j * 64 + lane;
-        cj[u][j] = in ? scol[e] : 0;
-        vj[u][j] = in ? sval[e] : 0.0;
-      }
+    for (int u = 0; u < U; ++u) sacc[u] = 0.0;
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -256,8 +281,9 @@ __global__ void __launch_bounds__(WG) k_cg_dir(int n, const long long *__restric
         acc = fma(pi, sacc[u], acc);
       }
     }
+    if (i0 + U * stride < n) load_rows(i0 + U * stride);
   }
-  double tot = block_sum(acc, sh);
+  double tot = block_sum(acc, sh[0]);
   if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
 }
 
@@ -294,6 +320,17 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, double *__restrict__ x,
                                                   double *__restrict__ part_rzo) {
   if (st->done) return;
   __shared__ double sh[WG / 64];
+  // this thread's first row is loaded before the partial sums are reduced
+  // (it does not depend on alpha), so that the two latencies overlap
+  int i = blockIdx.x * WG + threadIdx.x;
+  double xv = 0.0, pv = 0.0, qv = 0.0, rv = 0.0, zv = 0.0;
+  if (i < n) {
+    xv = x[i];
+    pv = p[i];
+    qv = q[i];
+    rv = r[i];
+    if (zold) zv = zold[i];
+  }
   const double pq = sum_partials(part_pq, nb, sh);
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(pq > 0.0) || !isfinite(pq)) {
@@ -311,12 +348,20 @@ __global__ void __launch_bounds__(WG) k_cg_update(int n, double *__restrict__ x,
     st->alpha = alpha;
   }
   double acc = 0.0, acc2 = 0.0;
-  for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-    x[i] = fma(alpha, p[i], x[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
+  for (; i < n; i += gridDim.x * WG) {
+    x[i] = fma(alpha, pv, xv);
+    const double ri = fma(-alpha, qv, rv);
     r[i] = ri;
     acc = fma(ri, ri, acc);
-    if (zold) acc2 = fma(ri, zold[i], acc2);
+    if (zold) acc2 = fma(ri, zv, acc2);
+    const int inext = i + gridDim.x * WG;
+    if (inext < n) {
+      xv = x[inext];
+      pv = p[inext];
+      qv = q[inext];
+      rv = r[inext];
+      if (zold) zv = zold[inext];
+    }
   }
   double tot = block_sum(acc, sh);
   if (threadIdx.x == 0) part_rr[blockIdx.x] = tot;
