@@ -201,7 +201,11 @@ void amsp_default_options(amsp_options *opt);
 amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, int32_t nparts,
                        int32_t nev, const amsp_options *opt, amsp_handle **out);
 
-/* z = M^{-1} r for nrhs columns (asynchronous on the handle's stream).
+/* z = M^{-1} r for nrhs columns (asynchronous on the handle's stream), with
+ * M^{-1} = sum_i R_i^T A_i^{-1} R_i + R0^T A0^{-1} R0: the coarse term of
+ * Section 3.1 (R0 from the eigenproblem of Section 3.2, A0 its Galerkin
+ * matrix) plus the local solves on the overlapping regions (the additive
+ * two-level reading of the method; with cycle = 1 the multiplicative cycle).
  * parts: 3 = both terms, 1 = local solves only, 2 = coarse correction only.
  * Columns are n apart (column-major).  Two or more columns are taken up to 16
  * at a time with one pass over the local factor: triangular solves with a
@@ -234,7 +238,10 @@ amsp_status amsp_apply_parts(amsp_handle *h, const double *r_dev, double *z_dev,
 amsp_status amsp_apply_noalloc(amsp_handle *h, const double *r_dev, double *z_dev, int32_t nrhs,
                                int32_t parts);
 
-/* Preconditioned CG from u = 0 until the recursive residual satisfies
+/* Preconditioned CG (Saad, Iterative Methods for Sparse Linear Systems,
+ * Algorithm 9.1) with the operator of amsp_apply, which is SPD; the paper's
+ * own Krylov method (Section 5) is GMRES, amsp_gmres below.  From u = 0
+ * until the recursive residual satisfies
  * ||r_k|| <= rtol ||f||; the true residual f - A u is then recomputed and
  * accepted if it is below max(rtol, floor) with floor = eps || |A||u| || / ||f||
  * (the rounding level of any float64 residual); otherwise CG restarts from the
@@ -333,8 +340,10 @@ amsp_status amsp_grad_values(amsp_handle *h, const double *lambda_dev, const dou
 
 /* Introspection (host copies; each blocks on the stream). */
 amsp_status amsp_get_setup_info(const amsp_handle *h, amsp_setup_info *info);
-/* lambda_host: N*(nev+1) values; row i holds lambda_1..lambda_{m_i+1} of
- * subdomain i (unused slots = NaN). */
+/* Eigenvalues of the local eigenproblems hat A_i psi = lambda S_i psi
+ * (Section 3.2, the algebraic eigenproblem), lowest first.  lambda_host:
+ * N*(nev+1) values; row i holds lambda_1..lambda_{m_i+1} of subdomain i
+ * (unused slots = NaN). */
 amsp_status amsp_get_eigenvalues(const amsp_handle *h, double *lambda_host);
 /* A0 as a dense row-major nc x nc float64 matrix (needs opt.keep_a0 = 1). */
 amsp_status amsp_get_coarse_matrix(const amsp_handle *h, double *a0_host);

@@ -21,6 +21,7 @@ import sys
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle as O
 import workloads as W
@@ -336,3 +337,29 @@ def test_device_error_codes():
     with pytest.raises(P.AmspError) as e:
         P.Preconditioner(w.A.row_ptr, w.A.col_idx, val, w.part, 4, 2, overlap=1)
     assert e.value.name in ("AMSP_ERR_NEUMANN_DIAG", "AMSP_ERR_LOCAL_NOT_SPD")
+
+
+def test_gap_flags_and_mu_c_match_the_oracle():
+    """The setup's gap flags (lambda_{m+1} - lambda_m below 1e-8 relative) and
+    mu_c = min_i lambda_{m_i+1} against the oracle's eigenvalues, on a grid of
+    3 x 3 square cores with a uniform coefficient: the centre region is
+    symmetric under the square's reflections, so a cut after its second mode
+    is degenerate (one flag) and a cut after the first is not (none)."""
+    from test_oracle_pins import blocks_problem
+    A, part = blocks_problem()
+    Ac = sp.csr_matrix(A)
+    Ac.sort_indices()
+    for nev, want in ((2, 1), (1, 0)):
+        st = O.setup(A, part, 9, nev, overlap=1)
+        flags = sum(1 for lam in st.lam if len(lam) > nev
+                    and lam[nev] - lam[nev - 1] < 1e-8 * max(lam[nev], 1e-12))
+        mu = min(lam[nev] for lam in st.lam)
+        assert flags == want
+        pc = P.Preconditioner(Ac.indptr.astype(np.int64), Ac.indices.astype(np.int32), Ac.data,
+                              part.astype(np.int32), 9, nev, overlap=1)
+        si = pc.info
+        say(f"nev {nev}: gap flags {si['n_gap_flags']} (oracle {flags}), mu_c {si['mu_c']:.12g} "
+            f"(oracle {mu:.12g})")
+        assert si["n_gap_flags"] == flags
+        assert abs(si["mu_c"] - mu) <= 1e-10 * mu
+        pc.close()

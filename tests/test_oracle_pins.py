@@ -600,3 +600,58 @@ def test_theta_gradient_single_cell_closed_form():
     uu = f / (8 * kappa)
     assert abs(u[0] - uu) <= 1e-15
     assert abs(g[0, 0] - (-(uu - uobs) * uu)) <= 1e-15
+
+
+def test_validate_rejects_bad_inputs():
+    """The oracle refuses what the method is not defined for: a non-square or
+    asymmetric matrix, a non-positive diagonal, a partition out of range or
+    with an empty subdomain."""
+    A = W.darcy.tpfa_matrix(np.ones((4, 4))).to_scipy()
+    part = np.repeat(np.arange(2), 8)
+    O.validate(A, part, 2)  # a valid input passes
+    with pytest.raises(O.OracleError, match="square"):
+        O.validate(sp.csr_matrix(np.ones((3, 4))), np.zeros(3, dtype=int), 1)
+    B = A.tolil()
+    B[0, 1] = B[0, 1] * 2.0
+    with pytest.raises(O.OracleError, match="symmetric"):
+        O.validate(B.tocsr(), part, 2)
+    C = A.tolil()
+    C[3, 3] = 0.0
+    with pytest.raises(O.OracleError, match="diagonal"):
+        O.validate(C.tocsr(), part, 2)
+    with pytest.raises(O.OracleError, match="range"):
+        O.validate(A, part, 1)
+    with pytest.raises(O.OracleError, match="range"):
+        O.validate(A, part[:-1], 2)
+    with pytest.raises(O.OracleError, match="empty"):
+        O.validate(A, part, 3)
+
+
+def blocks_problem(nb=3, side=8):
+    """Uniform coefficient on a grid of nb x nb square cores of side cells:
+    with one overlap layer the centre region is a plus shape (the core and a
+    strip of side cells on each of its four sides), symmetric under all
+    reflections of the square."""
+    nx = nb * side
+    A = W.darcy.tpfa_matrix(np.ones((nx, nx))).to_scipy()
+    ix, iy = np.meshgrid(np.arange(nx), np.arange(nx), indexing="ij")
+    part = ((ix // side) + nb * (iy // side)).ravel()
+    return A, part
+
+
+def test_symmetric_region_gives_a_degenerate_cut():
+    """The reading of the gap flags (lambda_{m+1} - lambda_m tiny): on a region
+    invariant under the square's reflections, with a uniform coefficient, the
+    Neumann pencil (hat A_i, S_i) has the same symmetry, so its second and
+    third eigenvalues coincide (a two-dimensional symmetry class) while the
+    first is zero (constants).  A cut after the second mode is then
+    degenerate there, a cut after the first is not."""
+    A, part = blocks_problem()
+    st = O.setup(A, part, 9, 2, overlap=1)
+    c = 4  # the centre core
+    assert len(st.regions[c]) == 64 + 4 * 8
+    lam = st.lam[c]
+    assert abs(lam[0]) < 1e-12
+    assert abs(lam[2] - lam[1]) <= 1e-10 * lam[2], lam
+    st1 = O.setup(A, part, 9, 1, overlap=1)
+    assert st1.lam[c][1] - st1.lam[c][0] > 1e-3
