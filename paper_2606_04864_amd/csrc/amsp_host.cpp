@@ -148,6 +148,8 @@ double now_ms() {
 
 }  // namespace
 
+constexpr size_t kStageBytes = size_t(4) << 20;
+
 struct amsp_handle {
   amsp_options opt{};
   hipStream_t stream = nullptr;
@@ -237,7 +239,13 @@ struct amsp_handle {
   std::vector<int> seg_cut;     // completed CG steps of each finished segment
   bool timing_active = false;
   int ev_count[5] = {0, 0, 0, 0, 0};  // launches per class seen by tstart (for the stride)
+  // page-locked staging area for the setup's small uploads (a block of the
+  // planner's cache): copies from pageable memory can stall the host for
+  // milliseconds in the runtime; staged ones are plain DMA
+  char *stage = nullptr;
+  size_t stage_off = 0;
   ~amsp_handle() {
+    if (stage) plan_free(stage, kStageBytes);
     for (hipEvent_t e : evs) hipEventDestroy(e);
     for (hipEvent_t e : st_ev)
       if (e) hipEventDestroy(e);
@@ -316,6 +324,25 @@ static void tstop(amsp_handle *h, int cls, int idx) {
     }                                                                     \
   } while (0)
 
+// Source of an upload of `bytes` from host memory `src` on the handle's
+// stream: a copy in the staging area when the data is small and fits (the
+// area is reused only after the stream has been synchronised:
+// stage_release), else src itself.
+static const void *stage_src(amsp_handle *h, hipStream_t stream, const void *src, size_t bytes) {
+  if (stream != h->stream || bytes == 0 || bytes > kStageBytes / 4) return src;
+  if (!h->stage) {
+    h->stage = static_cast<char *>(plan_alloc(kStageBytes));
+    if (!h->stage) return src;
+  }
+  const size_t at = (h->stage_off + 255) & ~size_t(255);
+  if (at + bytes > kStageBytes) return src;
+  std::memcpy(h->stage + at, src, bytes);
+  h->stage_off = at + bytes;
+  return h->stage + at;
+}
+// The stream has been synchronised: every staged copy has completed.
+static void stage_release(amsp_handle *h) { h->stage_off = 0; }
+
 template <typename V>
 static typename V::value_type *upload_on(amsp_handle *h, hipStream_t stream, const V &v, bool &ok) {
   using T = typename V::value_type;
@@ -324,8 +351,9 @@ static typename V::value_type *upload_on(amsp_handle *h, hipStream_t stream, con
     ok = false;
     return nullptr;
   }
-  if (!v.empty() &&
-      hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream) != hipSuccess) {
+  const size_t bytes = v.size() * sizeof(T);
+  if (!v.empty() && hipMemcpyAsync(d, stage_src(h, stream, v.data(), bytes), bytes,
+                                   hipMemcpyHostToDevice, stream) != hipSuccess) {
     ok = false;
     return nullptr;
   }
@@ -549,6 +577,7 @@ static amsp_status tree_coarse_setup(amsp_handle *h, const HostPlan &P) {
   int cs = 0;
   HIP_TRY(hipMemcpyAsync(&cs, cstat, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  stage_release(h);
   if (cs) {
     h->err = "coarse matrix A0 not SPD";
     return AMSP_ERR_COARSE_NOT_SPD;
@@ -748,6 +777,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   const int sum_ni = P.sd_ptr.back();
   const int sum_npad = P.vp_ptr.back();
   HIP_TRY(hipStreamSynchronize(h->stream));
+  stage_release(h);
   double t1 = now_ms();
   h->sinfo.phase_ms[1] = tb - ta;                   // input matrix transfer only
   h->sinfo.phase_ms[0] += (ta - t0) + (t1 - tb);  // planning includes its index uploads
@@ -774,6 +804,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   launch_extract_tiles(h->stream, p, h->ntilerows, h->val, h->sdiag, h->fac64, 0, 0.0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(h->stream));
+  stage_release(h);
   double t2 = now_ms();
   h->sinfo.phase_ms[2] = t2 - t1;
   launch_profile_cholesky(h->stream, p, h->fac64, status, 2);
@@ -1126,6 +1157,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   ALLOC(h->scal, double, 8);
   ALLOC(h->st, PcgState, 1);
   HIP_TRY(hipStreamSynchronize(h->stream));
+  stage_release(h);
   h->mem.free_one(status);
   for (void *b : deferred) h->mem.free_one(b);
   h->sinfo.phase_ms[7] = now_ms() - t0 + host_plan_ms;
