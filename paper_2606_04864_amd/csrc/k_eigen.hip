@@ -155,16 +155,20 @@ __global__ void __launch_bounds__(WG) k_eig_spmm(Plan p, const double *__restric
   const int i = blockIdx.y;
   if (conv[i]) return;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
-  const int l = blockIdx.x * (WG / EIGP) + (threadIdx.x >> 4), a = threadIdx.x & 15;
+  // four lanes per row, four columns each (32-byte row pieces): a row's
+  // entry indices and values are loaded by four lanes instead of sixteen
+  const int l = blockIdx.x * (WG / 4) + (threadIdx.x >> 2), a = 4 * (threadIdx.x & 3);
   if (l >= ni) return;
   const size_t base = (size_t)p.vp_ptr[i] * EIGP;
-  double acc = Y[base + (size_t)l * EIGP + a];
+  const d4 y0 = *reinterpret_cast<const d4 *>(Y + base + (size_t)l * EIGP + a);
+  double acc[4] = {y0[0], y0[1], y0[2], y0[3]};
   const int e0 = p.loc_rowptr[r0 + l], e1 = p.loc_rowptr[r0 + l + 1];
   // the first SU entries: all index and value loads, then all row loads,
   // then the products in entry order; longer rows continue one by one
   constexpr int SU = 8;
   int c[SU];
-  double b[SU], y[SU];
+  double b[SU];
+  d4 y[SU];
 #pragma unroll
   for (int u = 0; u < SU; ++u) {
     const bool in = e0 + u < e1;
@@ -172,13 +176,20 @@ __global__ void __launch_bounds__(WG) k_eig_spmm(Plan p, const double *__restric
     b[u] = in ? bval[e0 + u] : 0.0;
   }
 #pragma unroll
-  for (int u = 0; u < SU; ++u) y[u] = Y[base + (size_t)c[u] * EIGP + a];
+  for (int u = 0; u < SU; ++u) y[u] = *reinterpret_cast<const d4 *>(Y + base + (size_t)c[u] * EIGP + a);
 #pragma unroll
   for (int u = 0; u < SU; ++u)
-    if (e0 + u < e1) acc = fma(b[u], y[u], acc);
-  for (int e = e0 + SU; e < e1; ++e)
-    acc = fma(bval[e], Y[base + (size_t)p.loc_col[e] * EIGP + a], acc);
-  BY[base + (size_t)l * EIGP + a] = acc;
+    if (e0 + u < e1) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = fma(b[u], y[u][j], acc[j]);
+    }
+  for (int e = e0 + SU; e < e1; ++e) {
+    const double be = bval[e];
+    const d4 ye = *reinterpret_cast<const d4 *>(Y + base + (size_t)p.loc_col[e] * EIGP + a);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = fma(be, ye[j], acc[j]);
+  }
+  *reinterpret_cast<d4 *>(BY + base + (size_t)l * EIGP + a) = d4{acc[0], acc[1], acc[2], acc[3]};
 }
 
 // G = Y^T Y and K = Y^T (B Y) into GK[i][2*EIGP*EIGP].  One MFMA 16x16x4
@@ -645,58 +656,88 @@ k_env_solve_block(Plan p, const T *__restrict__ diag, const T *__restrict__ erow
       Xi[(size_t)row * EIGP + mi] = y[r];
     }
   };
+  // Each block's global loads (its diagonal tile row, first envelope chunk
+  // and right-hand side) are issued during the block before, each as soon
+  // as its registers are free, so that their latency overlaps that block's
+  // products; segment bounds are loaded two blocks ahead.
   // forward: Y_I = inv(L_II) (X_I - L[I rows, c < 64I] Y)
   {
-    Seg gn = seg_row(0);
+    T dA[16];
+    T ev0[4];
+    double xin[4];
+    Seg g = seg_row(0);
+    Seg gn = nt > 1 ? seg_row(TS) : g;
+    packed_row16(dA, dpool, 16 * w + mi, 16 * mq);
+    ev_load(erow_i, g, 0, ev0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xin[j] = Xin_i[(size_t)rr * EIGP + 4 * q + j];
     for (int I = 0; I < nt; ++I) {
       const int r0 = I * TS;
-      const Seg g = gn;
-      T dA[16];
-      packed_row16(dA, dpool + (size_t)I * DE, 16 * w + mi, 16 * mq);
-      T ev0[4];
-      ev_load(erow_i, g, 0, ev0);
-      double xin[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xin[j] = Xin_i[(size_t)(r0 + rr) * EIGP + 4 * q + j];
-      if (I + 1 < nt) gn = seg_row(r0 + TS);
+      const bool more = I + 1 < nt;
+      Seg gnn = gn;
+      if (I + 2 < nt) gnn = seg_row(r0 + 2 * TS);
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       env_part(erow_i, g, r0 - g.len, ev0, acc);
+      if (more) ev_load(erow_i, gn, 0, ev0);
 #pragma unroll
       for (int j = 0; j < 4; ++j) Acc[rr * LV + 4 * q + j] = xin[j] + acc[j];
+      if (more) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xin[j] = Xin_i[(size_t)(r0 + TS + rr) * EIGP + 4 * q + j];
+      }
       __syncthreads();  // Acc complete; all ring reads of this block done
       d4 y = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < 16; ++s) y = mfma16x16x4((double)dA[s], Acc[(16 * mq + s) * LV + mi], y);
+      if (more) packed_row16(dA, dpool + (size_t)(I + 1) * DE, 16 * w + mi, 16 * mq);
       store_block(r0, y);
       __syncthreads();  // Y_I visible in the ring and X; Acc free
+      g = gn;
+      gn = gnn;
     }
   }
   // backward: X_J = inv(L_JJ)^T (Y_J - L[r >= 64(J+1), J cols]^T X)
   {
-    Seg gn = seg_col((nt - 1) * TS);
-    for (int J = nt - 1; J >= 0; --J) {
-      const int r0 = J * TS, r1 = r0 + TS;
-      const Seg g = gn;
-      T dA[16];
+    T dA[16];
+    T ev0[4];
+    double yin[4];
+    auto load_dt = [&](int J) {
 #pragma unroll
       for (int s = 0; s < 16; ++s)
         dA[s] = packed_at(dpool + (size_t)J * DE, 16 * mq + s, 16 * w + mi);
-      T ev0[4];
-      ev_load(ecol_i, g, 0, ev0);
-      double yin[4];
+    };
+    const int J0 = nt - 1;
+    Seg g = seg_col(J0 * TS);
+    Seg gn = J0 > 0 ? seg_col((J0 - 1) * TS) : g;
+    load_dt(J0);
+    ev_load(ecol_i, g, 0, ev0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) yin[j] = Xi[(size_t)(r0 + rr) * EIGP + 4 * q + j];
-      if (J > 0) gn = seg_col(r0 - TS);
+    for (int j = 0; j < 4; ++j) yin[j] = Xi[(size_t)(J0 * TS + rr) * EIGP + 4 * q + j];
+    for (int J = J0; J >= 0; --J) {
+      const int r0 = J * TS, r1 = r0 + TS;
+      const bool more = J > 0;
+      Seg gnn = gn;
+      if (J > 1) gnn = seg_col(r0 - 2 * TS);
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       env_part(ecol_i, g, r1, ev0, acc);
+      if (more) ev_load(ecol_i, gn, 0, ev0);
 #pragma unroll
       for (int j = 0; j < 4; ++j) Acc[rr * LV + 4 * q + j] = yin[j] + acc[j];
+      if (more) {
+        // rows of block J - 1 of Y: final since the forward sweep, and not
+        // written by this sweep before block J - 1's own store
+#pragma unroll
+        for (int j = 0; j < 4; ++j) yin[j] = Xi[(size_t)(r0 - TS + rr) * EIGP + 4 * q + j];
+      }
       __syncthreads();
       d4 y = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < 16; ++s) y = mfma16x16x4((double)dA[s], Acc[(16 * mq + s) * LV + mi], y);
+      if (more) load_dt(J - 1);
       store_block(r0, y);
       __syncthreads();
+      g = gn;
+      gn = gnn;
     }
   }
 }
@@ -726,7 +767,7 @@ void launch_eig_bval(hipStream_t s, const Plan &p, const double *val, const doub
 void launch_eig_rr(hipStream_t s, const Plan &p, int max_ni, const double *val,
                    const double *sdiag, const double *bval, const double *Y, double *BY, double *X,
                    double *GK, double *CC, double tol, int *conv, double *lam, bool test_next) {
-  const int rows_per_wg = WG / EIGP;
+  const int rows_per_wg = WG / 4;
   hipLaunchKernelGGL(k_eig_spmm, dim3((max_ni + rows_per_wg - 1) / rows_per_wg, p.N), dim3(WG), 0,
                      s, p, bval, Y, BY, conv);
   hipLaunchKernelGGL(k_eig_gram, dim3(p.N), dim3(WG), 0, s, p, val, sdiag, Y, BY, GK, conv);
