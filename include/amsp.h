@@ -141,9 +141,10 @@ typedef struct {
   int64_t bytes_per_iter;   /* algorithmic HBM bytes of one CG iteration           */
   /* with opt.timing: summed device time and count of the timed launches per
    * kernel class (average duration = kernel_ms / kernel_launches):
-   * [0] SpMV (+ search-direction update), [1] local apply (gather, restriction,
-   * forward/backward solves), [2] coarse solve (both triangular products),
-   * [3] scatter-sum, [4] CG vector update and reductions */
+   * [0] SpMV (+ search-direction update), [1] local apply (gather,
+   * forward/backward solves, prolongation of the coarse correction), [2]
+   * coarse restriction and solve (both triangular products, or the sparse
+   * factor's solve), [3] scatter-sum, [4] CG vector update and reductions */
   double kernel_ms[5];
   int32_t kernel_launches[5];
   int64_t local_apply_bytes; /* algorithmic bytes of one local-apply launch          */

@@ -181,7 +181,7 @@ struct amsp_handle {
   long long nst_f = 0, nst_b = 0;            // stream lengths (entries)
   double *phi64 = nullptr;
   void *phi_lo = nullptr;  // float or bf16 copy used by the mixed apply
-  void *phi_nat = nullptr; // the apply's basis in ascending-index layout (scatter)
+  void *phi_nat = nullptr; // the apply's basis in ascending-index layout, by columns
   double *lam = nullptr;   // N*(nev+1)
   // coarse
   double *a0keep = nullptr;  // copy of A0 tiles before factorisation (introspection)
@@ -1098,6 +1098,17 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
       launch_basis_convert(h->stream, h->phi64, h->phi_lo, (size_t)sum_ni * h->nev, bf ? 1 : 0);
     }
   }
+  // each region's dofs in ascending order (rows of the ascending-index
+  // layout) and their local indices
+  {
+    int *asc = nullptr, *lop = nullptr;
+    ALLOC(asc, int, std::max<long long>(sum_ni, 1));
+    ALLOC(lop, int, std::max<long long>(sum_ni, 1));
+    launch_ascending_dofs(h->stream, p, asc, lop);
+    p.asc = asc;
+    p.lop = lop;
+    HIP_TRY(hipGetLastError());
+  }
   // direct operand indices of the inverse map for the scatter
   {
     const int ne = sum_ni;
@@ -1105,7 +1116,8 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     launch_inverse_direct(h->stream, ne, h->inv_sd, h->inv_loc, p, h->inv_x);
     HIP_TRY(hipGetLastError());
   }
-  // the scatter's copy of the apply basis, in ascending-global-index layout
+  // the single-vector apply's copy of the basis: ascending-global-index
+  // layout, one column after the other in each region
   if (h->nev > 0) {
     const size_t cnt = (size_t)sum_ni * h->nev;
     if (!mixed) {
@@ -1329,30 +1341,23 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
     HIP_TRY(hipGetLastError());
     return AMSP_OK;
   }
-  hipEvent_t e0, e1;
-  int tk = tpair(h, 1, &e0, &e1);
-  if (!mixed) {
-    launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->dg64,
-                                                 h->erow64, h->ecol64, h->phi64, h->xloc, h->cvec,
-                                                 do_local, do_coarse, done, e0, e1);
-  } else if (!bf) {
-    launch_local_apply_stream<float>(h->stream, p, h->hp.max_npad, r, h->fst32, h->bst32,
-                                     (const float *)h->phi_lo, h->xloc, h->cvec, do_local,
-                                     do_coarse, done, e0, e1);
-  } else {
-    launch_local_apply_stream<__hip_bfloat16>(h->stream, p, h->hp.max_npad, r, h->fst32,
-                                              h->bst32, (const __hip_bfloat16 *)h->phi_lo,
-                                              h->xloc, h->cvec, do_local, do_coarse, done, e0,
-                                              e1);
-  }
-  tpair_done(h, 1, tk);
-  if (do_coarse && h->tree) {
+  // Coarse part first (restriction, then the coarse solve), so that the
+  // local apply adds the prolongation Phi_i t_i to each region's output as
+  // it stores it; without the local part the prolongation runs before the
+  // scatter instead.
+  int tk;
+  if (do_coarse) {
     tk = tstart(h, 2);
-    coarse_solve_tree(h, h->stream, h->cvec, h->tvec, done);
-    tstop(h, 2, tk);
-  } else if (do_coarse) {
-    tk = tstart(h, 2);
-    if (!mixed) {
+    if (!mixed)
+      launch_restrict<double>(h->stream, p, r, (const double *)h->phi_nat, h->cvec, done);
+    else if (!bf)
+      launch_restrict<float>(h->stream, p, r, (const float *)h->phi_nat, h->cvec, done);
+    else
+      launch_restrict<__hip_bfloat16>(h->stream, p, r, (const __hip_bfloat16 *)h->phi_nat,
+                                      h->cvec, done);
+    if (h->tree) {
+      coarse_solve_tree(h, h->stream, h->cvec, h->tvec, done);
+    } else if (!mixed) {
       launch_trmv<double>(h->stream, h->W0, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
       launch_trmv<double>(h->stream, h->W0, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
     } else {
@@ -1361,20 +1366,39 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
     }
     tstop(h, 2, tk);
   }
+  if (do_local) {
+    const double *t = do_coarse ? h->tvec : nullptr;
+    hipEvent_t e0, e1;
+    tk = tpair(h, 1, &e0, &e1);
+    if (!mixed)
+      launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->dg64,
+                                                   h->erow64, h->ecol64,
+                                                   (const double *)h->phi_nat, t, h->xloc, done,
+                                                   e0, e1);
+    else if (!bf)
+      launch_local_apply_stream<float>(h->stream, p, h->hp.max_npad, r, h->fst32, h->bst32,
+                                       (const float *)h->phi_nat, t, h->xloc, done, e0, e1);
+    else
+      launch_local_apply_stream<__hip_bfloat16>(h->stream, p, h->hp.max_npad, r, h->fst32,
+                                                h->bst32, (const __hip_bfloat16 *)h->phi_nat, t,
+                                                h->xloc, done, e0, e1);
+    tpair_done(h, 1, tk);
+  }
   tk = tstart(h, 3);
   const int mni = h->hp.max_ni;
+  const int prolong = do_coarse && !do_local;
   if (!mixed || h->nev == 0)
     launch_scatter_sum_t<double>(h->stream, p, mni, h->n, h->inv_ptr, h->inv_x, h->xloc,
                                  (const double *)h->phi_nat, h->tvec, z,
-                                 partial_rz ? r : nullptr, partial_rz, do_local, do_coarse, done);
+                                 partial_rz ? r : nullptr, partial_rz, do_local, prolong, done);
   else if (!bf)
     launch_scatter_sum_t<float>(h->stream, p, mni, h->n, h->inv_ptr, h->inv_x, h->xloc,
                                 (const float *)h->phi_nat, h->tvec, z, partial_rz ? r : nullptr,
-                                partial_rz, do_local, do_coarse, done);
+                                partial_rz, do_local, prolong, done);
   else
     launch_scatter_sum_t<__hip_bfloat16>(h->stream, p, mni, h->n, h->inv_ptr, h->inv_x, h->xloc,
                                          (const __hip_bfloat16 *)h->phi_nat, h->tvec, z,
-                                         partial_rz ? r : nullptr, partial_rz, do_local, do_coarse,
+                                         partial_rz ? r : nullptr, partial_rz, do_local, prolong,
                                          done);
   tstop(h, 3, tk);
   HIP_TRY(hipGetLastError());
@@ -1605,8 +1629,8 @@ static int64_t apply_factor_elems(const HostPlan &P) {
 }
 
 // Algorithmic bytes of one local-apply launch: gather of r and the region
-// index, basis read for the restriction, envelope segment starts, both factor
-// sweeps, local output.
+// index, envelope segment starts, both factor sweeps, basis and coarse
+// solution read for the prolongation, local output.
 static int64_t local_apply_bytes(const amsp_handle *h) {
   const HostPlan &P = h->hp;
   const bool mixed = h->opt.precision != AMSP_FP64;

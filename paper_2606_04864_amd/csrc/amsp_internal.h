@@ -17,7 +17,10 @@ struct Plan {
   const int *sd_dofs;       // [sum n_i] global dof of each local index (local order)
   const int *nat;           // [sum n_i] rank of that dof among the region's dofs by global
                             // index: position in the ascending-index layout of the
-                            // local corrections and of the scatter's basis copy
+                            // local corrections and of the basis copy read by the apply
+  const int *asc;           // [sum n_i] the region's dofs in ascending order, and the local
+  const int *lop;           //   index of each: asc[r0 + nat[r0 + l]] = sd_dofs[r0 + l],
+                            //   lop[r0 + nat[r0 + l]] = l
   const int *vp_ptr;        // [N+1] padded offsets (multiples of 64) for tile-aligned vectors
   const int *trow_ptr;      // [N+1] offsets into the per-tile-row arrays
   const int *tfirst;        // [sum nt_i] first tile column of each tile row
@@ -131,25 +134,34 @@ constexpr int STREAM_TAIL = 4 * WG;
 void launch_stream_from_tiles(hipStream_t s, const Plan &p, int ntilerows, const double *tiles,
                               float *fst, float *bst);
 size_t local_apply_stream_lds_bytes(int max_npad);
+// Coarse restriction c = R0 r: c_i = Phi_i^T r_i for every region (TB basis
+// type; the copy made by launch_basis_to_natural).
+template <typename TB>
+void launch_restrict(hipStream_t s, const Plan &p, const double *r, const TB *phi, double *cvec,
+                     const int *done);
 // The mixed-form local apply on the streams (same operation as
 // launch_local_apply_t with float factors).
 template <typename TB>
 void launch_local_apply_stream(hipStream_t s, const Plan &p, int max_npad, const double *r,
-                               const float *fst, const float *bst, const TB *phi, double *xloc,
-                               double *cvec, int do_local, int do_coarse, const int *done,
-                               hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
-// Local apply: gather r, coarse restriction into c (do_coarse), envelope
-// forward/backward solve into xloc (do_local).  diag: the packed inverse
-// diagonal tiles (DE entries per tile row), erow/ecol: the envelope.
-// T factor, C compute, TB basis type.  ev_start / ev_stop (optional, created
-// with timing): bound to the dispatch itself (no extra packets in the stream).
+                               const float *fst, const float *bst, const TB *phi, const double *t,
+                               double *xloc, const int *done, hipEvent_t ev_start = nullptr,
+                               hipEvent_t ev_stop = nullptr);
+// Local apply: gather r, envelope forward/backward solve, store into xloc;
+// with the coarse solution t (else nullptr) the prolongation Phi_i t_i is
+// added to each region's output (phi: the copy made by
+// launch_basis_to_natural).  diag: the packed inverse diagonal tiles
+// (DE entries per tile row), erow/ecol: the envelope.  T factor, C compute,
+// TB basis type.  ev_start / ev_stop (optional, created with timing): bound
+// to the dispatch itself (no extra packets in the stream).
 template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
                           const T *diag, const T *erow, const T *ecol, const TB *phi,
-                          double *xloc, double *cvec, int do_local, int do_coarse,
-                          const int *done, hipEvent_t ev_start = nullptr,
-                          hipEvent_t ev_stop = nullptr);
+                          const double *t, double *xloc, const int *done,
+                          hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D);
+// The regions' dofs in ascending order and their local indices (Plan::asc,
+// Plan::lop).
+void launch_ascending_dofs(hipStream_t s, const Plan &p, int *asc, int *lop);
 // Direct operand indices of the inverse map (see k_inverse_direct).
 void launch_inverse_direct(hipStream_t s, int ne, const int *inv_sd, const int *inv_loc,
                            const Plan &p, int *ix);
@@ -229,8 +241,9 @@ void launch_local_csr(hipStream_t s, const Plan &p, int max_ni, const int *rowpt
 
 // ---------------------------------------------------------------- eigen ---
 void launch_eig_init(hipStream_t s, const Plan &p, const double *sdiag, double *X);
-// dst[(sd_ptr[i] + nat[k]) * nev + c] = src[(sd_ptr[i] + k) * nev + c]: the basis
-// in each region's ascending-global-index order (read by the scatter).
+// dst[sd_ptr[i] * nev + c * n_i + nat[k]] = src[(sd_ptr[i] + k) * nev + c]: the
+// basis in each region's ascending-global-index order, one column after the
+// other (read by the single-vector apply's restriction and prolongation).
 template <typename TB>
 void launch_basis_to_natural(hipStream_t s, const Plan &p, const TB *src, TB *dst);
 // Off-diagonal values of the scaled local operators B_i per local CSR entry.

@@ -1,8 +1,10 @@
 // The local solves of the additive Schwarz term (Section 3.2): one fused
 // kernel per application of the preconditioner gathers the residual on every
-// region, forms the coarse restriction Phi_i^T r_i, and runs the forward and
-// backward substitutions with the region's factor, stored as packed inverse
-// diagonal tiles plus the envelope below them (see k_local.hip).
+// region, runs the forward and backward substitutions with the region's
+// factor, stored as packed inverse diagonal tiles plus the envelope below
+// them (see k_local.hip), and adds the coarse prolongation Phi_i t_i to the
+// region's output.  The coarse restriction Phi_i^T r_i, which the coarse
+// solve needs first, is a kernel of its own (k_restrict).
 #include <hip/hip_ext.h>
 
 #include "k_common.h"
@@ -83,14 +85,158 @@ __device__ __forceinline__ C env_chunk_dot(const Frag<T> &f, const C *x, C acc) 
   return acc;
 }
 
+// Coefficients 0 .. KM-1 of row `row` of a region's basis stored column
+// after column (entry k at ph[k * ni]), with m >= 1 kept coefficients; those
+// for k >= m read as zero.  The loads are clamped into the m columns and
+// issued unconditionally, so that all of them are in flight together (a load
+// under "k < m" would be waited for one at a time).
+template <int KM, typename TB>
+__device__ __forceinline__ void basis_row_load(const TB *__restrict__ ph, int ni, int m,
+                                               TB (&raw)[KM]) {
+#pragma unroll
+  for (int k = 0; k < KM; ++k) raw[k] = ph[(size_t)min(k, m - 1) * ni];
+}
+template <int KM, typename TB>
+__device__ __forceinline__ double basis_coef(const TB (&raw)[KM], int k, int m) {
+  return k < m ? to_d(raw[k]) : 0.0;
+}
+
+// Restriction of one region with at most KM basis coefficients per row (see
+// k_restrict).
+template <int KM, typename TB>
+__device__ __forceinline__ void restrict_region(const Plan &p, int i, const double *__restrict__ r,
+                                                const TB *__restrict__ phi,
+                                                double *__restrict__ cvec, double (*red)[WG / 64]) {
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  const int m = p.mi[i];
+  if (m == 0) return;
+  const TB *phr = phi + (size_t)r0 * p.nev;
+  double cacc[KM];
+#pragma unroll
+  for (int k = 0; k < KM; ++k) cacc[k] = 0.0;
+  // rows per thread per pass (one pass covers regions up to GU * WG rows)
+  constexpr int GU = (sizeof(TB) == 8 ? 4 : 8) / (KM <= 8 ? 1 : 2);
+  for (int l0 = threadIdx.x; l0 < ni; l0 += GU * WG) {
+    int dof[GU];
+    double rv[GU];
+    TB raw[GU][KM];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int l = l0 + u * WG;
+      dof[u] = l < ni ? p.asc[r0 + l] : -1;
+      basis_row_load<KM>(phr + min(l, ni - 1), ni, m, raw[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) rv[u] = dof[u] >= 0 ? r[dof[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+#pragma unroll
+      for (int k = 0; k < KM; ++k) cacc[k] = fma(basis_coef<KM>(raw[u], k, m), rv[u], cacc[k]);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KM; ++k)
+    if (k < m) {
+      const double s = wave_sum(cacc[k]);
+      if (lane == 0) red[k][w] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < m) {
+    double s = 0.0;
+    for (int ww = 0; ww < WG / 64; ++ww) s += red[threadIdx.x][ww];
+    cvec[p.coff[i] + threadIdx.x] = s;
+  }
+}
+
+// Coarse restriction c_i = Phi_i^T r_i (the coarse term R0 r of the two-level
+// operator, Section 3.1), one region per workgroup, over the region's rows in
+// ascending global order (Plan::asc) with the basis stored column after
+// column in that order, so that neighbouring lanes read neighbouring entries
+// of r and of every basis column.  Each thread takes the rows t, t + WG, ...
+// in order (several rows' loads issued together), then the wavefronts' sums
+// are added in a fixed order (no atomics).
+template <typename TB>
+__global__ void __launch_bounds__(WG) k_restrict(Plan p, const double *__restrict__ r,
+                                                 const TB *__restrict__ phi,
+                                                 double *__restrict__ cvec,
+                                                 const int *__restrict__ done) {
+  if (done && *done) return;
+  __shared__ double red[MAXNEV][WG / 64];
+  static_assert(MAXNEV <= 16, "basis rows are read as at most 16 coefficients");
+  if (p.nev <= 4)
+    restrict_region<4>(p, blockIdx.x, r, phi, cvec, red);
+  else if (p.nev <= 8)
+    restrict_region<8>(p, blockIdx.x, r, phi, cvec, red);
+  else
+    restrict_region<16>(p, blockIdx.x, r, phi, cvec, red);
+}
+
+// Region i's output with the prolongation added (at most KM coefficients per
+// row), row by row in the ascending-index layout: dst[pos] = x_l +
+// sum_q Phi_i[pos][q] t_q for the local index l of position pos, the
+// coefficients taken in order (the same arithmetic as k_prolong_local).
+template <int KM, typename TB, typename V>
+__device__ __forceinline__ void store_local_prolong(const Plan &p, int i, int r0, int ni, int m,
+                                                    const V *v, const TB *__restrict__ phi,
+                                                    const double *__restrict__ t,
+                                                    double *__restrict__ dst) {
+  const TB *phr = phi + (size_t)r0 * p.nev;
+  const double *tt = t + p.coff[i];
+  double tk[KM];
+#pragma unroll
+  for (int q = 0; q < KM; ++q) tk[q] = q < m ? tt[min(q, m - 1)] : 0.0;
+  constexpr int GU = KM <= 8 ? 2 : 1;
+  for (int l0 = threadIdx.x; l0 < ni; l0 += GU * WG) {
+    TB raw[GU][KM];
+    int lo[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int pos = min(l0 + u * WG, ni - 1);
+      lo[u] = p.lop[r0 + pos];
+      basis_row_load<KM>(phr + pos, ni, m, raw[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int pos = l0 + u * WG;
+      if (pos < ni) {
+        double x = (double)v[lo[u]];
+#pragma unroll
+        for (int q = 0; q < KM; ++q) x = fma(basis_coef<KM>(raw[u], q, m), tk[q], x);
+        dst[pos] = x;
+      }
+    }
+  }
+}
+
+// Region i's output x_i (v, local order) into xloc in the region's
+// ascending-global-index layout (written in that order); with the coarse
+// solution t (else nullptr), the prolongation Phi_i t_i is added (phi: the
+// basis copy in that layout, column after column).
+template <typename TB, typename V>
+__device__ __forceinline__ void store_local(const Plan &p, int i, int r0, int ni, const V *v,
+                                            const TB *__restrict__ phi,
+                                            const double *__restrict__ t,
+                                            double *__restrict__ xloc) {
+  double *dst = xloc + p.vp_ptr[i];
+  const int m = t ? p.mi[i] : 0;
+  if (m == 0) {
+    for (int pos = threadIdx.x; pos < ni; pos += WG) dst[pos] = (double)v[p.lop[r0 + pos]];
+  } else if (p.nev <= 4) {
+    store_local_prolong<4>(p, i, r0, ni, m, v, phi, t, dst);
+  } else if (p.nev <= 8) {
+    store_local_prolong<8>(p, i, r0, ni, m, v, phi, t, dst);
+  } else {
+    store_local_prolong<16>(p, i, r0, ni, m, v, phi, t, dst);
+  }
+}
+
 size_t local_apply_lds_bytes(int max_npad, size_t csize) {
   return (size_t)(max_npad + TS) * csize + 2 * (size_t)(max_npad + 1) * sizeof(int);
 }
 
 // Fused additive-Schwarz local kernel for one region per workgroup:
-//   gather r on the region, coarse restriction c_i = Phi_i^T r_i (optional),
-//   forward/backward substitution with the factor (optional),
-//   store the local correction into the padded local vector xloc.
+//   gather r on the region, forward/backward substitution with the factor,
+//   store the local correction (plus Phi_i t_i when t is given) into xloc.
 // T: factor storage type, C: compute type, TB: basis storage type.
 template <typename T, typename C, typename TB>
 __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__restrict__ r,
@@ -98,9 +244,9 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
                                                     const T *__restrict__ erow,
                                                     const T *__restrict__ ecol,
                                                     const TB *__restrict__ phi,
+                                                    const double *__restrict__ t,
                                                     double *__restrict__ xloc,
-                                                    double *__restrict__ cvec, int do_local,
-                                                    int do_coarse, const int *__restrict__ done) {
+                                                    const int *__restrict__ done) {
   if (done && *done) return;
   extern __shared__ char smem_raw[];
   const int i = blockIdx.x;
@@ -111,47 +257,15 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
   C *tmp = v + npad;                         // 64
   int *er = reinterpret_cast<int *>(tmp + TS);  // npad + 1 row-form segment starts
   int *eu = er + npad + 1;                       // npad + 1 column-form segment starts
-  __shared__ double red[MAXNEV + 1][WG / 64];
-  const int nev = p.nev;
-  const int m = p.mi[i];
-  double cacc[MAXNEV];
-#pragma unroll
-  for (int k = 0; k < MAXNEV; ++k) cacc[k] = 0.0;
-  for (int l = threadIdx.x; l < npad; l += WG) {
-    double rv = 0.0;
-    if (l < ni) {
-      rv = r[p.sd_dofs[r0 + l]];
-      if (do_coarse) {
-        const TB *ph = phi + (size_t)(r0 + l) * nev;
-#pragma unroll
-        for (int k = 0; k < MAXNEV; ++k)
-          if (k < m) cacc[k] = fma(to_d(ph[k]), rv, cacc[k]);
-      }
-    }
-    v[l] = (C)rv;
-  }
-  if (do_local) {
+  for (int l = threadIdx.x; l < npad; l += WG) v[l] = l < ni ? (C)r[p.sd_dofs[r0 + l]] : C(0);
+  {
     const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
     for (int l = threadIdx.x; l <= npad; l += WG) {
       er[l] = ep[l];
       eu[l] = up[l];
     }
   }
-  if (do_coarse) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int k = 0; k < m; ++k) {
-      double s = wave_sum(cacc[k]);
-      if (lane == 0) red[k][w] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < m) {
-      double s = 0.0;
-      for (int ww = 0; ww < WG / 64; ++ww) s += red[threadIdx.x][ww];
-      cvec[p.coff[i] + threadIdx.x] = s;
-    }
-  }
   __syncthreads();
-  if (!do_local) return;
   const int rr = threadIdx.x >> 2, q = threadIdx.x & 3;
   const T *dpool = diag + (size_t)g0 * DE;
   const T *erow_i = erow + p.ebase[i];
@@ -268,10 +382,9 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
       if (I < 0) break;
     }
   }
-  // local correction in the region's ascending-global-index layout, so that
-  // the scatter reads contiguous runs
-  double *dst = xloc + p.vp_ptr[i];
-  for (int l = threadIdx.x; l < ni; l += WG) dst[p.nat[r0 + l]] = (double)v[l];
+  // local correction (+ prolongation) in the region's ascending-global-index
+  // layout, so that the scatter reads contiguous runs
+  store_local(p, i, r0, ni, v, phi, t, xloc);
 }
 
 // ------------------------------------ local solves on the f32 streams -----
@@ -455,9 +568,8 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
                                                            const float *__restrict__ fst,
                                                            const float *__restrict__ bst,
                                                            const TB *__restrict__ phi,
+                                                           const double *__restrict__ t,
                                                            double *__restrict__ xloc,
-                                                           double *__restrict__ cvec, int do_local,
-                                                           int do_coarse,
                                                            const int *__restrict__ done) {
   if (done && *done) return;
   extern __shared__ char smem_raw[];
@@ -469,15 +581,8 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
   float *tmp = v + npad;                             // 64
   float *ring = tmp + TS;                            // stream::RSZ
   int *es = reinterpret_cast<int *>(ring + stream::RSZ);  // npad + 1 segment starts
-  __shared__ double red[MAXNEV + 1][WG / 64];
-  const int nev = p.nev;
-  const int m = p.mi[i];
-  double cacc[MAXNEV];
-#pragma unroll
-  for (int k = 0; k < MAXNEV; ++k) cacc[k] = 0.0;
-  // gather and restriction, GU rows per thread per pass with all index
-  // loads, then all value loads, issued before use (rows l, l + WG, ... are
-  // accumulated in that order)
+  // gather, GU rows per thread per pass with all index loads, then all value
+  // loads, issued before use
   constexpr int GU = 4;
   for (int l0 = threadIdx.x; l0 < npad; l0 += GU * WG) {
     int dof[GU];
@@ -489,18 +594,6 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
     }
 #pragma unroll
     for (int u = 0; u < GU; ++u) rv[u] = dof[u] >= 0 ? r[dof[u]] : 0.0;
-    if (do_coarse) {
-#pragma unroll
-      for (int u = 0; u < GU; ++u) {
-        const int l = l0 + u * WG;
-        if (l < ni) {
-          const TB *ph = phi + (size_t)(r0 + l) * nev;
-#pragma unroll
-          for (int k = 0; k < MAXNEV; ++k)
-            if (k < m) cacc[k] = fma(to_d(ph[k]), rv[u], cacc[k]);
-        }
-      }
-    }
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
       const int l = l0 + u * WG;
@@ -512,30 +605,15 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
   // (regions up to UPR * WG - 1 padded rows), so that no global load sits
   // between the two sweeps
   constexpr int UPR = 8;
-  const bool up_regs = do_local && npad < UPR * WG;
+  const bool up_regs = npad < UPR * WG;
   int upv[UPR];
 #pragma unroll
   for (int u = 0; u < UPR; ++u) {
     const int l = threadIdx.x + u * WG;
     upv[u] = (up_regs && l <= npad) ? up[l] : 0;
   }
-  if (do_local)
-    for (int l = threadIdx.x; l <= npad; l += WG) es[l] = ep[l];
-  if (do_coarse) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int k = 0; k < m; ++k) {
-      double s = wave_sum(cacc[k]);
-      if (lane == 0) red[k][w] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < m) {
-      double s = 0.0;
-      for (int ww = 0; ww < WG / 64; ++ww) s += red[threadIdx.x][ww];
-      cvec[p.coff[i] + threadIdx.x] = s;
-    }
-  }
+  for (int l = threadIdx.x; l <= npad; l += WG) es[l] = ep[l];
   __syncthreads();
-  if (!do_local) return;
   const int Lf = (int)(p.sfr[i + 1] - p.sfr[i]), Lb = (int)(p.sbr[i + 1] - p.sbr[i]);
   stream_sweep<true>(nt, es, p.sfb + g0, fst + p.sfr[i], Lf, fst + p.sfr[p.N], v, tmp, ring);
   if (up_regs) {
@@ -549,57 +627,68 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
   }
   __syncthreads();
   stream_sweep<false>(nt, es, p.sbb + g0, bst + p.sbr[i], Lb, bst + p.sbr[p.N], v, tmp, ring);
-  // local correction in the region's ascending-global-index layout
-  double *dst = xloc + p.vp_ptr[i];
-  for (int l = threadIdx.x; l < ni; l += WG) dst[p.nat[r0 + l]] = (double)v[l];
+  // local correction (+ prolongation) in the region's ascending-global-index layout
+  store_local(p, i, r0, ni, v, phi, t, xloc);
 }
 
 // ------------------------------------------------------------- launchers ---
+template <typename TB>
+void launch_restrict(hipStream_t s, const Plan &p, const double *r, const TB *phi, double *cvec,
+                     const int *done) {
+  hipLaunchKernelGGL((k_restrict<TB>), dim3(p.N), dim3(WG), 0, s, p, r, phi, cvec, done);
+}
+template void launch_restrict<double>(hipStream_t, const Plan &, const double *, const double *,
+                                      double *, const int *);
+template void launch_restrict<float>(hipStream_t, const Plan &, const double *, const float *,
+                                     double *, const int *);
+template void launch_restrict<__hip_bfloat16>(hipStream_t, const Plan &, const double *,
+                                              const __hip_bfloat16 *, double *, const int *);
+
 template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
                           const T *diag, const T *erow, const T *ecol, const TB *phi,
-                          double *xloc, double *cvec, int do_local, int do_coarse,
-                          const int *done, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                          const double *t, double *xloc, const int *done, hipEvent_t ev_start,
+                          hipEvent_t ev_stop) {
   const size_t sm = local_apply_lds_bytes(max_npad, sizeof(C));
   allow_lds(k_local_apply<T, C, TB>, sm);
   if (ev_start || ev_stop)  // events bound to this dispatch: exact kernel duration
     hipExtLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, ev_start, ev_stop,
-                          0, p, r, diag, erow, ecol, phi, xloc, cvec, do_local, do_coarse, done);
+                          0, p, r, diag, erow, ecol, phi, t, xloc, done);
   else
     hipLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, p, r, diag, erow,
-                       ecol, phi, xloc, cvec, do_local, do_coarse, done);
+                       ecol, phi, t, xloc, done);
 }
 
 #define AMSP_LOCAL_APPLY_INST(T, C, TB)                                                        \
   template void launch_local_apply_t<T, C, TB>(hipStream_t, const Plan &, int, const double *, \
                                                const T *, const T *, const T *, const TB *,    \
-                                               double *, double *, int, int, const int *,      \
+                                               const double *, double *, const int *,          \
                                                hipEvent_t, hipEvent_t);
 AMSP_LOCAL_APPLY_INST(double, double, double)
 #undef AMSP_LOCAL_APPLY_INST
 
 template <typename TB>
 void launch_local_apply_stream(hipStream_t s, const Plan &p, int max_npad, const double *r,
-                               const float *fst, const float *bst, const TB *phi, double *xloc,
-                               double *cvec, int do_local, int do_coarse, const int *done,
-                               hipEvent_t ev_start, hipEvent_t ev_stop) {
+                               const float *fst, const float *bst, const TB *phi, const double *t,
+                               double *xloc, const int *done, hipEvent_t ev_start,
+                               hipEvent_t ev_stop) {
   const size_t sm = local_apply_stream_lds_bytes(max_npad);
   allow_lds(k_local_apply_stream<TB>, sm);
   if (ev_start || ev_stop)  // events bound to this dispatch: exact kernel duration
     hipExtLaunchKernelGGL((k_local_apply_stream<TB>), dim3(p.N), dim3(WG), sm, s, ev_start,
-                          ev_stop, 0, p, r, fst, bst, phi, xloc, cvec, do_local, do_coarse, done);
+                          ev_stop, 0, p, r, fst, bst, phi, t, xloc, done);
   else
     hipLaunchKernelGGL((k_local_apply_stream<TB>), dim3(p.N), dim3(WG), sm, s, p, r, fst, bst, phi,
-                       xloc, cvec, do_local, do_coarse, done);
+                       t, xloc, done);
 }
 template void launch_local_apply_stream<float>(hipStream_t, const Plan &, int, const double *,
                                                const float *, const float *, const float *,
-                                               double *, double *, int, int, const int *,
-                                               hipEvent_t, hipEvent_t);
+                                               const double *, double *, const int *, hipEvent_t,
+                                               hipEvent_t);
 template void launch_local_apply_stream<__hip_bfloat16>(hipStream_t, const Plan &, int,
                                                         const double *, const float *,
                                                         const float *, const __hip_bfloat16 *,
-                                                        double *, double *, int, int, const int *,
+                                                        const double *, double *, const int *,
                                                         hipEvent_t, hipEvent_t);
 
 }  // namespace amsp

@@ -479,7 +479,7 @@ __global__ void k_inverse_direct(int ne, const int *__restrict__ inv_sd,
 // Coarse prolongation per region, into the local output: w_i = x_i + Phi_i t_i
 // (or Phi_i t_i alone without the local part), in the region's
 // ascending-global-index layout, with Phi_i = D_i psi (the basis copy in that
-// layout).  Grid (row block, region); one row per thread.
+// layout, column after column).  Grid (row block, region); one row per thread.
 template <typename TB>
 __global__ void __launch_bounds__(WG) k_prolong_local(Plan p, const TB *__restrict__ phi,
                                                       const double *__restrict__ t,
@@ -492,12 +492,12 @@ __global__ void __launch_bounds__(WG) k_prolong_local(Plan p, const TB *__restri
   if (pos >= ni) return;
   const int m = p.mi[i], nev = p.nev;
   const double *tt = t + p.coff[i];
-  const TB *ph = phi + (size_t)(r0 + pos) * nev;
+  const TB *ph = phi + (size_t)r0 * nev + pos;
   double *dst = xloc + p.vp_ptr[i] + pos;
   double v = do_local ? *dst : 0.0;
 #pragma unroll
-  for (int q = 0; q < MAXNEV; ++q)  // predicated: all loads issue together
-    if (q < m) v = fma(to_d(ph[q]), tt[q], v);
+  for (int q = 0; q < MAXNEV; ++q)
+    if (q < m) v = fma(to_d(ph[(size_t)q * ni]), tt[q], v);
   *dst = v;
 }
 
@@ -556,11 +556,29 @@ __global__ void __launch_bounds__(WG) k_basis_to_natural(Plan p, const TB *__res
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, nev = p.nev;
   for (int e = threadIdx.x; e < ni * nev; e += WG) {
     const int l = e / nev, c = e % nev;
-    dst[(size_t)(r0 + p.nat[r0 + l]) * nev + c] = src[(size_t)(r0 + l) * nev + c];
+    dst[(size_t)r0 * nev + (size_t)c * ni + p.nat[r0 + l]] = src[(size_t)(r0 + l) * nev + c];
+  }
+}
+
+// asc[r0 + nat[r0 + l]] = sd_dofs[r0 + l], lop[r0 + nat[r0 + l]] = l: each
+// region's dofs in ascending order (the row order of the ascending-index
+// layout) and their local indices.
+__global__ void __launch_bounds__(WG) k_ascending_dofs(Plan p, int *__restrict__ asc,
+                                                       int *__restrict__ lop) {
+  const int i = blockIdx.x;
+  const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
+  for (int l = threadIdx.x; l < ni; l += WG) {
+    const int pos = r0 + p.nat[r0 + l];
+    asc[pos] = p.sd_dofs[r0 + l];
+    lop[pos] = l;
   }
 }
 
 // ------------------------------------------------------------- launchers ---
+void launch_ascending_dofs(hipStream_t s, const Plan &p, int *asc, int *lop) {
+  hipLaunchKernelGGL(k_ascending_dofs, dim3(p.N), dim3(WG), 0, s, p, asc, lop);
+}
+
 template <typename TB>
 void launch_basis_to_natural(hipStream_t s, const Plan &p, const TB *src, TB *dst) {
   hipLaunchKernelGGL((k_basis_to_natural<TB>), dim3(p.N), dim3(WG), 0, s, p, src, dst);
