@@ -85,22 +85,6 @@ __device__ __forceinline__ C env_chunk_dot(const Frag<T> &f, const C *x, C acc) 
   return acc;
 }
 
-// Coefficients 0 .. KM-1 of row `row` of a region's basis stored column
-// after column (entry k at ph[k * ni]), with m >= 1 kept coefficients; those
-// for k >= m read as zero.  The loads are clamped into the m columns and
-// issued unconditionally, so that all of them are in flight together (a load
-// under "k < m" would be waited for one at a time).
-template <int KM, typename TB>
-__device__ __forceinline__ void basis_row_load(const TB *__restrict__ ph, int ni, int m,
-                                               TB (&raw)[KM]) {
-#pragma unroll
-  for (int k = 0; k < KM; ++k) raw[k] = ph[(size_t)min(k, m - 1) * ni];
-}
-template <int KM, typename TB>
-__device__ __forceinline__ double basis_coef(const TB (&raw)[KM], int k, int m) {
-  return k < m ? to_d(raw[k]) : 0.0;
-}
-
 // Restriction of one region with at most KM basis coefficients per row (see
 // k_restrict).
 template <int KM, typename TB>
@@ -124,7 +108,7 @@ __device__ __forceinline__ void restrict_region(const Plan &p, int i, const doub
     for (int u = 0; u < GU; ++u) {
       const int l = l0 + u * WG;
       dof[u] = l < ni ? p.asc[r0 + l] : -1;
-      basis_row_load<KM>(phr + min(l, ni - 1), ni, m, raw[u]);
+      basis_row_load<KM>(phr + min(l, ni - 1), (size_t)ni, m, raw[u]);
     }
 #pragma unroll
     for (int u = 0; u < GU; ++u) rv[u] = dof[u] >= 0 ? r[dof[u]] : 0.0;
@@ -162,13 +146,9 @@ __global__ void __launch_bounds__(WG) k_restrict(Plan p, const double *__restric
                                                  const int *__restrict__ done) {
   if (done && *done) return;
   __shared__ double red[MAXNEV][WG / 64];
-  static_assert(MAXNEV <= 16, "basis rows are read as at most 16 coefficients");
-  if (p.nev <= 4)
-    restrict_region<4>(p, blockIdx.x, r, phi, cvec, red);
-  else if (p.nev <= 8)
-    restrict_region<8>(p, blockIdx.x, r, phi, cvec, red);
-  else
-    restrict_region<16>(p, blockIdx.x, r, phi, cvec, red);
+  with_km(p.nev, [&](auto km) __attribute__((always_inline)) {
+    restrict_region<decltype(km)::value>(p, blockIdx.x, r, phi, cvec, red);
+  });
 }
 
 // Region i's output with the prolongation added (at most KM coefficients per
@@ -193,7 +173,7 @@ __device__ __forceinline__ void store_local_prolong(const Plan &p, int i, int r0
     for (int u = 0; u < GU; ++u) {
       const int pos = min(l0 + u * WG, ni - 1);
       lo[u] = p.lop[r0 + pos];
-      basis_row_load<KM>(phr + pos, ni, m, raw[u]);
+      basis_row_load<KM>(phr + pos, (size_t)ni, m, raw[u]);
     }
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
@@ -221,12 +201,10 @@ __device__ __forceinline__ void store_local(const Plan &p, int i, int r0, int ni
   const int m = t ? p.mi[i] : 0;
   if (m == 0) {
     for (int pos = threadIdx.x; pos < ni; pos += WG) dst[pos] = (double)v[p.lop[r0 + pos]];
-  } else if (p.nev <= 4) {
-    store_local_prolong<4>(p, i, r0, ni, m, v, phi, t, dst);
-  } else if (p.nev <= 8) {
-    store_local_prolong<8>(p, i, r0, ni, m, v, phi, t, dst);
   } else {
-    store_local_prolong<16>(p, i, r0, ni, m, v, phi, t, dst);
+    with_km(p.nev, [&](auto km) __attribute__((always_inline)) {
+      store_local_prolong<decltype(km)::value>(p, i, r0, ni, m, v, phi, t, dst);
+    });
   }
 }
 

@@ -20,17 +20,26 @@ __global__ void __launch_bounds__(WG) k_apply_A_to_basis(Plan p, CoarsePlan c,
   const int e0 = c.ext_ptr[j], e1 = c.ext_ptr[j + 1];
   const int r0 = p.sd_ptr[j];
   for (int e = e0 + threadIdx.x; e < e1; e += WG) {
-    double acc[MAXNEV];
-#pragma unroll
-    for (int k = 0; k < MAXNEV; ++k) acc[k] = 0.0;
-    for (int q = c.ext_rowptr[e]; q < c.ext_rowptr[e + 1]; ++q) {
-      const double a = val[c.ext_src[q]];
-      const double *ph = phi + (size_t)(r0 + c.ext_loc[q]) * nev;
-#pragma unroll
-      for (int k = 0; k < MAXNEV; ++k)
-        if (k < m) acc[k] = fma(a, ph[k], acc[k]);
+    if (m == 0) {
+      for (int k = 0; k < nev; ++k) W[(size_t)e * nev + k] = 0.0;
+      continue;
     }
-    for (int k = 0; k < nev; ++k) W[(size_t)e * nev + k] = (k < m) ? acc[k] : 0.0;
+    with_km(nev, [&](auto km) __attribute__((always_inline)) {
+      constexpr int KM = decltype(km)::value;
+      double acc[KM];
+#pragma unroll
+      for (int k = 0; k < KM; ++k) acc[k] = 0.0;
+      for (int q = c.ext_rowptr[e]; q < c.ext_rowptr[e + 1]; ++q) {
+        const double a = val[c.ext_src[q]];
+        double raw[KM];
+        basis_row_load<KM>(phi + (size_t)(r0 + c.ext_loc[q]) * nev, 1, m, raw);
+#pragma unroll
+        for (int k = 0; k < KM; ++k) acc[k] = fma(a, basis_coef<KM>(raw, k, m), acc[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k)
+        if (k < nev) W[(size_t)e * nev + k] = (k < m) ? acc[k] : 0.0;
+    });
   }
 }
 

@@ -191,6 +191,36 @@ __device__ __forceinline__ void static_for(F &&f) {
   }
 }
 
+// Basis rows with m <= MAXNEV kept coefficients are read as KM = 4, 8 or 16
+// values (the smallest that holds nev): with_km(nev, f) calls f with
+// std::integral_constant<int, KM>.
+template <typename F>
+__device__ __forceinline__ void with_km(int nev, F &&f) {
+  static_assert(MAXNEV <= 16, "basis rows are read as at most 16 coefficients");
+  if (nev <= 4)
+    f(std::integral_constant<int, 4>{});
+  else if (nev <= 8)
+    f(std::integral_constant<int, 8>{});
+  else
+    f(std::integral_constant<int, 16>{});
+}
+
+// Coefficients 0 .. KM-1 of a basis row with m >= 1 kept coefficients, entry
+// k at ph[k * stride]; those for k >= m read as zero (basis_coef).  The loads
+// are clamped into the m kept entries and issued unconditionally, so that all
+// of them are in flight together: a load under "k < m" (a branch on a value
+// the compiler cannot see) would be waited for before the next is issued.
+template <int KM, typename TB>
+__device__ __forceinline__ void basis_row_load(const TB *__restrict__ ph, size_t stride, int m,
+                                               TB (&raw)[KM]) {
+#pragma unroll
+  for (int k = 0; k < KM; ++k) raw[k] = ph[(size_t)min(k, m - 1) * stride];
+}
+template <int KM, typename TB>
+__device__ __forceinline__ double basis_coef(const TB (&raw)[KM], int k, int m) {
+  return k < m ? to_d(raw[k]) : 0.0;
+}
+
 // Quad permutation of a double across lanes (DPP, no LDS traffic); CTRL is a
 // quad_perm control word: 0xB1 swaps neighbours (lane ^ 1), 0x4E swaps pairs
 // (lane ^ 2).

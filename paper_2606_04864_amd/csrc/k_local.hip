@@ -492,12 +492,22 @@ __global__ void __launch_bounds__(WG) k_prolong_local(Plan p, const TB *__restri
   if (pos >= ni) return;
   const int m = p.mi[i], nev = p.nev;
   const double *tt = t + p.coff[i];
-  const TB *ph = phi + (size_t)r0 * nev + pos;
   double *dst = xloc + p.vp_ptr[i] + pos;
   double v = do_local ? *dst : 0.0;
+  if (m == 0) {
+    *dst = v;
+    return;
+  }
+  with_km(nev, [&](auto km) __attribute__((always_inline)) {
+    constexpr int KM = decltype(km)::value;
+    TB raw[KM];
+    double tk[KM];
+    basis_row_load<KM>(phi + (size_t)r0 * nev + pos, (size_t)ni, m, raw);
 #pragma unroll
-  for (int q = 0; q < MAXNEV; ++q)
-    if (q < m) v = fma(to_d(ph[(size_t)q * ni]), tt[q], v);
+    for (int q = 0; q < KM; ++q) tk[q] = tt[min(q, m - 1)];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) v = fma(basis_coef<KM>(raw, q, m), tk[q], v);
+  });
   *dst = v;
 }
 

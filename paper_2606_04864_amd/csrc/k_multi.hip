@@ -34,9 +34,9 @@ __global__ void __launch_bounds__(WG) k_gather_multi(Plan p, int n, int nr,
 }
 
 // Restriction of every column: c_k[coff_i + q] = sum_l phi_i[l][q] X[l][k].
-// Thread (row group g, column k) adds rows g, g + 16, ... for all q; the 16
-// group sums are then added in group order.  The coarse vectors are ncp
-// apart (their padding stays zero).
+// Thread (row group g, column k) adds rows g, g + 16, ... for all q (GU rows'
+// loads issued together); the 16 group sums are then added in group order.
+// The coarse vectors are ncp apart (their padding stays zero).
 template <typename TB>
 __global__ void __launch_bounds__(WG) k_restrict_multi(Plan p, int nr, size_t ncp,
                                                        const TB *__restrict__ phi,
@@ -48,19 +48,30 @@ __global__ void __launch_bounds__(WG) k_restrict_multi(Plan p, int nr, size_t nc
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0, m = p.mi[i], nev = p.nev;
   const int k = threadIdx.x % EIGP, g = threadIdx.x / EIGP;
   const double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
-  double acc[MAXNEV];
+  if (m > 0)
+    with_km(nev, [&](auto km) __attribute__((always_inline)) {
+      constexpr int KM = decltype(km)::value, GU = 4;
+      double acc[KM];
 #pragma unroll
-  for (int q = 0; q < MAXNEV; ++q) acc[q] = 0.0;
-  for (int l = g; l < ni; l += RGS) {
-    const double x = Xi[(size_t)l * EIGP + k];
-    const TB *ph = phi + (size_t)(r0 + l) * nev;
+      for (int q = 0; q < KM; ++q) acc[q] = 0.0;
+      for (int l0 = g; l0 < ni; l0 += GU * RGS) {
+        double x[GU];
+        TB raw[GU][KM];
 #pragma unroll
-    for (int q = 0; q < MAXNEV; ++q)
-      if (q < m) acc[q] = fma(to_d(ph[q]), x, acc[q]);
-  }
+        for (int u = 0; u < GU; ++u) {
+          const int l = l0 + u * RGS, lc = min(l, ni - 1);
+          x[u] = l < ni ? Xi[(size_t)lc * EIGP + k] : 0.0;
+          basis_row_load<KM>(phi + (size_t)(r0 + lc) * nev, 1, m, raw[u]);
+        }
 #pragma unroll
-  for (int q = 0; q < MAXNEV; ++q)
-    if (q < m) sh[g][q][k] = acc[q];
+        for (int u = 0; u < GU; ++u)
+#pragma unroll
+          for (int q = 0; q < KM; ++q) acc[q] = fma(basis_coef<KM>(raw[u], q, m), x[u], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < KM; ++q)
+        if (q < m) sh[g][q][k] = acc[q];
+    });
   __syncthreads();
   if ((int)threadIdx.x < m * EIGP) {
     const int q = threadIdx.x / EIGP, kk = threadIdx.x % EIGP;
@@ -103,17 +114,19 @@ __global__ void __launch_bounds__(WG) k_prolong_multi(Plan p, int nr, size_t ncp
 #pragma unroll
       for (int k = 0; k < EIGP; ++k) v[k] = 0.0;
     }
-    if (t) {
-      const TB *ph = phi + (size_t)(r0 + l) * nev;
+    if (t && m > 0)
+      with_km(nev, [&](auto km) __attribute__((always_inline)) {
+        constexpr int KM = decltype(km)::value;
+        TB raw[KM];
+        basis_row_load<KM>(phi + (size_t)(r0 + l) * nev, 1, m, raw);
 #pragma unroll
-      for (int q = 0; q < MAXNEV; ++q) {
-        if (q < m) {
-          const double a = to_d(ph[q]);
+        for (int q = 0; q < KM; ++q)
+          if (q < m) {  // the loads above are already in flight
+            const double a = basis_coef<KM>(raw, q, m);
 #pragma unroll
-          for (int k = 0; k < EIGP; ++k) v[k] = fma(a, tl[q][k], v[k]);
-        }
-      }
-    }
+            for (int k = 0; k < EIGP; ++k) v[k] = fma(a, tl[q][k], v[k]);
+          }
+      });
 #pragma unroll
     for (int k = 0; k < EIGP; ++k)
       if (k >= nr) v[k] = 0.0;
