@@ -607,8 +607,8 @@ def main():
         "mixed_vs_fp64_speedup": (round(fp64_t / sums[head]["time_to_solution_ms"], 3)
                                   if fp64_t and head != "fp64" else None),
         "mixed_vs_fp64_u_relerr": agree,
-        "roofline": {"bound": "hbm", "kernel": "k_local_apply_stream (gather, restriction, "
-                                               "streamed forward/backward solves)",
+        "roofline": {"bound": "hbm", "kernel": "k_local_apply_stream (gather, streamed "
+                                               "forward/backward solves, prolongation)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic_from_profile(),
                      "avg_launch_ms": round(avg_ms, 5), "launches": kl,
