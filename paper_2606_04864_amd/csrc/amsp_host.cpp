@@ -1355,33 +1355,39 @@ static amsp_status apply_one(amsp_handle *h, const double *r, double *z, int par
     else
       launch_restrict<__hip_bfloat16>(h->stream, p, r, (const __hip_bfloat16 *)h->phi_nat,
                                       h->cvec, done);
+    // with the local part, the second dense product leaves its per-tile
+    // products, which the local apply sums for its own coarse values
+    double *t2 = do_local ? nullptr : h->tvec;
     if (h->tree) {
       coarse_solve_tree(h, h->stream, h->cvec, h->tvec, done);
     } else if (!mixed) {
       launch_trmv<double>(h->stream, h->W0, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
-      launch_trmv<double>(h->stream, h->W0, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
+      launch_trmv<double>(h->stream, h->W0, h->T0, h->t1, h->trmv_part, t2, 1, done);
     } else {
       launch_trmv<float>(h->stream, h->W0f, h->T0, h->cvec, h->trmv_part, h->t1, 0, done);
-      launch_trmv<float>(h->stream, h->W0f, h->T0, h->t1, h->trmv_part, h->tvec, 1, done);
+      launch_trmv<float>(h->stream, h->W0f, h->T0, h->t1, h->trmv_part, t2, 1, done);
     }
     tstop(h, 2, tk);
   }
   if (do_local) {
-    const double *t = do_coarse ? h->tvec : nullptr;
+    const bool parts = do_coarse && !h->tree;
+    const double *t = do_coarse && h->tree ? h->tvec : nullptr;
+    const double *tpart = parts ? h->trmv_part : nullptr;
     hipEvent_t e0, e1;
     tk = tpair(h, 1, &e0, &e1);
     if (!mixed)
       launch_local_apply_t<double, double, double>(h->stream, p, h->hp.max_npad, r, h->dg64,
                                                    h->erow64, h->ecol64,
-                                                   (const double *)h->phi_nat, t, h->xloc, done,
-                                                   e0, e1);
+                                                   (const double *)h->phi_nat, t, tpart, h->T0,
+                                                   h->xloc, done, e0, e1);
     else if (!bf)
       launch_local_apply_stream<float>(h->stream, p, h->hp.max_npad, r, h->fst32, h->bst32,
-                                       (const float *)h->phi_nat, t, h->xloc, done, e0, e1);
+                                       (const float *)h->phi_nat, t, tpart, h->T0, h->xloc, done,
+                                       e0, e1);
     else
       launch_local_apply_stream<__hip_bfloat16>(h->stream, p, h->hp.max_npad, r, h->fst32,
                                                 h->bst32, (const __hip_bfloat16 *)h->phi_nat, t,
-                                                h->xloc, done, e0, e1);
+                                                tpart, h->T0, h->xloc, done, e0, e1);
     tpair_done(h, 1, tk);
   }
   tk = tstart(h, 3);

@@ -144,20 +144,23 @@ void launch_restrict(hipStream_t s, const Plan &p, const double *r, const TB *ph
 template <typename TB>
 void launch_local_apply_stream(hipStream_t s, const Plan &p, int max_npad, const double *r,
                                const float *fst, const float *bst, const TB *phi, const double *t,
-                               double *xloc, const int *done, hipEvent_t ev_start = nullptr,
-                               hipEvent_t ev_stop = nullptr);
+                               const double *tpart, int T0, double *xloc, const int *done,
+                               hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // Local apply: gather r, envelope forward/backward solve, store into xloc;
 // with the coarse solution t (else nullptr) the prolongation Phi_i t_i is
 // added to each region's output (phi: the copy made by
-// launch_basis_to_natural).  diag: the packed inverse diagonal tiles
+// launch_basis_to_natural).  With tpart (else nullptr) the coarse solution
+// is instead summed from the per-tile products of W0^T (launch_trmv with
+// y == nullptr; T0 tiles), as the reduction would sum them.  diag: the packed inverse diagonal tiles
 // (DE entries per tile row), erow/ecol: the envelope.  T factor, C compute,
 // TB basis type.  ev_start / ev_stop (optional, created with timing): bound
 // to the dispatch itself (no extra packets in the stream).
 template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
                           const T *diag, const T *erow, const T *ecol, const TB *phi,
-                          const double *t, double *xloc, const int *done,
-                          hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                          const double *t, const double *tpart, int T0, double *xloc,
+                          const int *done, hipEvent_t ev_start = nullptr,
+                          hipEvent_t ev_stop = nullptr);
 void launch_selftest_mfma(hipStream_t s, const double *A, const double *B, double *D);
 // The regions' dofs in ascending order and their local indices (Plan::asc,
 // Plan::lop).
@@ -301,7 +304,12 @@ void launch_dense_inv_update(hipStream_t s, const double *Lt, double *Wt, int T0
 void launch_tiles_identity(hipStream_t s, double *Wt, int T0);
 void launch_dense_tiles_to_f32(hipStream_t s, const double *src, float *dst, int T0);
 // y = W x (transpose 0) or W^T x (transpose 1) over the lower tiles of W;
-// part: T0*T0*64 doubles of scratch.
+// part: T0*T0*64 doubles of scratch holding the per-tile products.  With
+// y == nullptr only the per-tile products are formed: entry O*64 + r of
+// W^T x is then the sum over K = O .. T0-1 of part[(O*T0 + K)*64 + r], split
+// into TRMV_RG consecutive pieces of K (piece g: K from O + len*g/TRMV_RG,
+// len = T0 - O), each summed in order and the pieces added in order from 0.
+constexpr int TRMV_RG = 16;
 template <typename T>
 void launch_trmv(hipStream_t s, const T *Wt, int T0, const double *x, double *part, double *y,
                  int transpose, const int *done);

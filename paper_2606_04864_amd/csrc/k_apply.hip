@@ -85,6 +85,27 @@ __device__ __forceinline__ C env_chunk_dot(const Frag<T> &f, const C *x, C acc) 
   return acc;
 }
 
+// dst[l] = src[l] for l < cnt (LDS from global), each thread's loads all in
+// flight together when cnt <= U * WG: they are clamped into range and
+// issued unconditionally, and the stores of rows past cnt go to
+// junk[threadIdx.x % 64] (scratch), so that no load waits inside a branch.
+template <int U>
+__device__ __forceinline__ void copy_ints_to_lds(int *dst, const int *__restrict__ src, int cnt,
+                                                 int *junk) {
+  if (cnt <= U * WG) {
+    int x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = src[min((int)threadIdx.x + u * WG, cnt - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = threadIdx.x + u * WG;
+      (l < cnt ? dst[l] : junk[threadIdx.x & (TS - 1)]) = x[u];
+    }
+  } else {
+    for (int l = threadIdx.x; l < cnt; l += WG) dst[l] = src[l];
+  }
+}
+
 // Restriction of one region with at most KM basis coefficients per row (see
 // k_restrict).
 template <int KM, typename TB>
@@ -106,12 +127,14 @@ __device__ __forceinline__ void restrict_region(const Plan &p, int i, const doub
     TB raw[GU][KM];
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
-      const int l = l0 + u * WG;
-      dof[u] = l < ni ? p.asc[r0 + l] : -1;
-      basis_row_load<KM>(phr + min(l, ni - 1), (size_t)ni, m, raw[u]);
+      const int lc = min(l0 + u * WG, ni - 1);  // clamped: every load is issued
+      dof[u] = p.asc[r0 + lc];
+      basis_row_load<KM>(phr + lc, (size_t)ni, m, raw[u]);
     }
 #pragma unroll
-    for (int u = 0; u < GU; ++u) rv[u] = dof[u] >= 0 ? r[dof[u]] : 0.0;
+    for (int u = 0; u < GU; ++u) rv[u] = r[dof[u]];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) rv[u] = l0 + u * WG < ni ? rv[u] : 0.0;
 #pragma unroll
     for (int u = 0; u < GU; ++u)
 #pragma unroll
@@ -156,12 +179,10 @@ __global__ void __launch_bounds__(WG) k_restrict(Plan p, const double *__restric
 // sum_q Phi_i[pos][q] t_q for the local index l of position pos, the
 // coefficients taken in order (the same arithmetic as k_prolong_local).
 template <int KM, typename TB, typename V>
-__device__ __forceinline__ void store_local_prolong(const Plan &p, int i, int r0, int ni, int m,
+__device__ __forceinline__ void store_local_prolong(const Plan &p, int r0, int ni, int m,
                                                     const V *v, const TB *__restrict__ phi,
-                                                    const double *__restrict__ t,
-                                                    double *__restrict__ dst) {
+                                                    const double *tt, double *__restrict__ dst) {
   const TB *phr = phi + (size_t)r0 * p.nev;
-  const double *tt = t + p.coff[i];
   double tk[KM];
 #pragma unroll
   for (int q = 0; q < KM; ++q) tk[q] = q < m ? tt[min(q, m - 1)] : 0.0;
@@ -189,23 +210,61 @@ __device__ __forceinline__ void store_local_prolong(const Plan &p, int i, int r0
 }
 
 // Region i's output x_i (v, local order) into xloc in the region's
-// ascending-global-index layout (written in that order); with the coarse
-// solution t (else nullptr), the prolongation Phi_i t_i is added (phi: the
-// basis copy in that layout, column after column).
+// ascending-global-index layout (written in that order); with the region's
+// coarse values tq (its m_i entries of the coarse solution; else nullptr),
+// the prolongation Phi_i t_i is added (phi: the basis copy in that layout,
+// column after column).
 template <typename TB, typename V>
 __device__ __forceinline__ void store_local(const Plan &p, int i, int r0, int ni, const V *v,
-                                            const TB *__restrict__ phi,
-                                            const double *__restrict__ t,
+                                            const TB *__restrict__ phi, const double *tq,
                                             double *__restrict__ xloc) {
   double *dst = xloc + p.vp_ptr[i];
-  const int m = t ? p.mi[i] : 0;
+  const int m = tq ? p.mi[i] : 0;
   if (m == 0) {
     for (int pos = threadIdx.x; pos < ni; pos += WG) dst[pos] = (double)v[p.lop[r0 + pos]];
   } else {
     with_km(p.nev, [&](auto km) __attribute__((always_inline)) {
-      store_local_prolong<decltype(km)::value>(p, i, r0, ni, m, v, phi, t, dst);
+      store_local_prolong<decltype(km)::value>(p, r0, ni, m, v, phi, tq, dst);
     });
   }
+}
+
+// The region's coarse values from the per-tile products of W0^T t1
+// (launch_trmv with y == nullptr), summed exactly as k_trmv_reduce sums
+// them.  Thread (q, g) = (t / TRMV_RG, t % TRMV_RG), q < m_i, adds piece g
+// of entry coff_i + q (coarse_partial_load, early: its loads then overlap the
+// gather); coarse_partial_finish adds the pieces in order inside each
+// 16-lane group and leaves the m_i values in tq (LDS; visible after the
+// next barrier).
+static_assert(MAXNEV * TRMV_RG <= WG, "one thread per (coarse value, piece)");
+__device__ __forceinline__ double coarse_partial_load(const Plan &p, int i,
+                                                      const double *__restrict__ part, int T0) {
+  const int q = threadIdx.x / TRMV_RG, g = threadIdx.x % TRMV_RG;
+  double s = 0.0;
+  if (q < p.mi[i]) {
+    const int gi = p.coff[i] + q, O = gi / TS, r = gi % TS;
+    const int len = T0 - O;
+    const int a = O + (len * g) / TRMV_RG, b = O + (len * (g + 1)) / TRMV_RG;
+    const double *src = part + (size_t)O * T0 * TS + r;
+    constexpr int U = 8;  // loads in flight together; added in order
+    for (int K0 = a; K0 < b; K0 += U) {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = K0 + u < b ? src[(size_t)(K0 + u) * TS] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (K0 + u < b) s += x[u];
+    }
+  }
+  return s;
+}
+__device__ __forceinline__ void coarse_partial_finish(const Plan &p, int i, double s, double *tq) {
+  const int lane = threadIdx.x & 63, base = lane & ~(TRMV_RG - 1);
+  double tot = 0.0;
+#pragma unroll
+  for (int g = 0; g < TRMV_RG; ++g) tot += __shfl(s, base + g, 64);
+  const int q = threadIdx.x / TRMV_RG;
+  if (threadIdx.x % TRMV_RG == 0 && q < p.mi[i]) tq[q] = tot;
 }
 
 size_t local_apply_lds_bytes(int max_npad, size_t csize) {
@@ -223,10 +282,12 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
                                                     const T *__restrict__ ecol,
                                                     const TB *__restrict__ phi,
                                                     const double *__restrict__ t,
+                                                    const double *__restrict__ tpart, int T0,
                                                     double *__restrict__ xloc,
                                                     const int *__restrict__ done) {
   if (done && *done) return;
   extern __shared__ char smem_raw[];
+  __shared__ double tq_s[16];  // the region's coarse values (a multiple of 16 bytes)
   const int i = blockIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
@@ -235,14 +296,32 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
   C *tmp = v + npad;                         // 64
   int *er = reinterpret_cast<int *>(tmp + TS);  // npad + 1 row-form segment starts
   int *eu = er + npad + 1;                       // npad + 1 column-form segment starts
-  for (int l = threadIdx.x; l < npad; l += WG) v[l] = l < ni ? (C)r[p.sd_dofs[r0 + l]] : C(0);
-  {
-    const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
-    for (int l = threadIdx.x; l <= npad; l += WG) {
-      er[l] = ep[l];
-      eu[l] = up[l];
+  const double cps = tpart ? coarse_partial_load(p, i, tpart, T0) : 0.0;
+  {  // gather, nothing conditional (as in the stream kernel; tmp takes the
+     // stores of rows past the padding)
+    constexpr int GU = 4;
+    for (int l0 = threadIdx.x; l0 < npad; l0 += GU * WG) {
+      int dof[GU];
+      double rv[GU];
+#pragma unroll
+      for (int u = 0; u < GU; ++u) dof[u] = p.sd_dofs[r0 + min(l0 + u * WG, ni - 1)];
+#pragma unroll
+      for (int u = 0; u < GU; ++u) rv[u] = r[dof[u]];
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const int l = l0 + u * WG;
+        v[l < npad ? l : npad + (threadIdx.x & (TS - 1))] = l < ni ? (C)rv[u] : C(0);
+      }
     }
   }
+  {
+    const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
+    int *junk = reinterpret_cast<int *>(tmp);  // scratch until the sweeps
+    copy_ints_to_lds<8>(er, ep, npad + 1, junk);
+    copy_ints_to_lds<8>(eu, up, npad + 1, junk);
+  }
+  if (tpart) coarse_partial_finish(p, i, cps, tq_s);
+  const double *tq = tpart ? tq_s : (t ? t + p.coff[i] : nullptr);
   __syncthreads();
   const int rr = threadIdx.x >> 2, q = threadIdx.x & 3;
   const T *dpool = diag + (size_t)g0 * DE;
@@ -362,7 +441,7 @@ __global__ void __launch_bounds__(WG) k_local_apply(Plan p, const double *__rest
   }
   // local correction (+ prolongation) in the region's ascending-global-index
   // layout, so that the scatter reads contiguous runs
-  store_local(p, i, r0, ni, v, phi, t, xloc);
+  store_local(p, i, r0, ni, v, phi, tq, xloc);
 }
 
 // ------------------------------------ local solves on the f32 streams -----
@@ -391,9 +470,15 @@ constexpr int RSZ = RU * UE;
 static_assert(NS >= 3, "a diagonal tile may start three units before the batch it ends in");
 }  // namespace stream
 
+// The region's coarse values (MAXNEV doubles, padded to 16 so that what
+// follows stays 16-byte aligned) head the stream kernel's LDS.
+constexpr size_t TQ_BYTES = 16 * sizeof(double);
+static_assert(MAXNEV <= 16, "coarse values of one region");
+
 size_t local_apply_stream_lds_bytes(int max_npad) {
-  // v (npad) + tmp (64) + ring + one form's segment starts (npad + 1)
-  return (size_t)(max_npad + TS + stream::RSZ) * sizeof(float) + (size_t)(max_npad + 1) * sizeof(int);
+  // coarse values + v (npad) + tmp (64) + ring + one form's segment starts (npad + 1)
+  return TQ_BYTES + (size_t)(max_npad + TS + stream::RSZ) * sizeof(float) +
+         (size_t)(max_npad + 1) * sizeof(int);
 }
 
 // One sweep.  FWD: blocks I = 0 .. nt-1, row form, y_I = inv(L_II)(b_I - env);
@@ -547,35 +632,39 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
                                                            const float *__restrict__ bst,
                                                            const TB *__restrict__ phi,
                                                            const double *__restrict__ t,
-                                                           double *__restrict__ xloc,
+                                                           const double *__restrict__ tpart,
+                                                           int T0, double *__restrict__ xloc,
                                                            const int *__restrict__ done) {
   if (done && *done) return;
-  extern __shared__ char smem_raw[];
+  extern __shared__ __align__(16) char smem_raw[];  // 16-byte ring accesses
   const int i = blockIdx.x;
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int g0 = p.trow_ptr[i], nt = p.trow_ptr[i + 1] - g0;
   const int npad = nt * TS;
-  float *v = reinterpret_cast<float *>(smem_raw);  // whole local vector (padded)
+  double *tq_s = reinterpret_cast<double *>(smem_raw);  // the region's coarse values
+  float *v = reinterpret_cast<float *>(smem_raw + TQ_BYTES);  // whole local vector (padded)
   float *tmp = v + npad;                             // 64
   float *ring = tmp + TS;                            // stream::RSZ
   int *es = reinterpret_cast<int *>(ring + stream::RSZ);  // npad + 1 segment starts
+  const double cps = tpart ? coarse_partial_load(p, i, tpart, T0) : 0.0;
   // gather, GU rows per thread per pass with all index loads, then all value
-  // loads, issued before use
+  // loads, issued before use.  Nothing here is conditional: the loads are
+  // clamped to the region's last row, padding rows are zeroed by a select,
+  // and rows past the padding are stored into tmp (scratch until the sweeps)
+  // (a load or store under a per-row condition would be waited for inside
+  // its branch, one row after the other)
   constexpr int GU = 4;
   for (int l0 = threadIdx.x; l0 < npad; l0 += GU * WG) {
     int dof[GU];
     double rv[GU];
 #pragma unroll
-    for (int u = 0; u < GU; ++u) {
-      const int l = l0 + u * WG;
-      dof[u] = l < ni ? p.sd_dofs[r0 + l] : -1;
-    }
+    for (int u = 0; u < GU; ++u) dof[u] = p.sd_dofs[r0 + min(l0 + u * WG, ni - 1)];
 #pragma unroll
-    for (int u = 0; u < GU; ++u) rv[u] = dof[u] >= 0 ? r[dof[u]] : 0.0;
+    for (int u = 0; u < GU; ++u) rv[u] = r[dof[u]];
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
       const int l = l0 + u * WG;
-      if (l < npad) v[l] = (float)rv[u];
+      v[l < npad ? l : npad + (threadIdx.x & (TS - 1))] = l < ni ? (float)rv[u] : 0.f;
     }
   }
   const int *ep = p.eptr + p.vp_ptr[i] + i, *up = p.uptr + p.vp_ptr[i] + i;
@@ -590,7 +679,9 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
     const int l = threadIdx.x + u * WG;
     upv[u] = (up_regs && l <= npad) ? up[l] : 0;
   }
-  for (int l = threadIdx.x; l <= npad; l += WG) es[l] = ep[l];
+  copy_ints_to_lds<UPR>(es, ep, npad + 1, reinterpret_cast<int *>(tmp));  // tmp: scratch here
+  if (tpart) coarse_partial_finish(p, i, cps, tq_s);
+  const double *tq = tpart ? tq_s : (t ? t + p.coff[i] : nullptr);
   __syncthreads();
   const int Lf = (int)(p.sfr[i + 1] - p.sfr[i]), Lb = (int)(p.sbr[i + 1] - p.sbr[i]);
   stream_sweep<true>(nt, es, p.sfb + g0, fst + p.sfr[i], Lf, fst + p.sfr[p.N], v, tmp, ring);
@@ -606,7 +697,7 @@ __global__ void __launch_bounds__(WG) k_local_apply_stream(Plan p, const double 
   __syncthreads();
   stream_sweep<false>(nt, es, p.sbb + g0, bst + p.sbr[i], Lb, bst + p.sbr[p.N], v, tmp, ring);
   // local correction (+ prolongation) in the region's ascending-global-index layout
-  store_local(p, i, r0, ni, v, phi, t, xloc);
+  store_local(p, i, r0, ni, v, phi, tq, xloc);
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -625,48 +716,49 @@ template void launch_restrict<__hip_bfloat16>(hipStream_t, const Plan &, const d
 template <typename T, typename C, typename TB>
 void launch_local_apply_t(hipStream_t s, const Plan &p, int max_npad, const double *r,
                           const T *diag, const T *erow, const T *ecol, const TB *phi,
-                          const double *t, double *xloc, const int *done, hipEvent_t ev_start,
-                          hipEvent_t ev_stop) {
+                          const double *t, const double *tpart, int T0, double *xloc,
+                          const int *done, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const size_t sm = local_apply_lds_bytes(max_npad, sizeof(C));
   allow_lds(k_local_apply<T, C, TB>, sm);
   if (ev_start || ev_stop)  // events bound to this dispatch: exact kernel duration
     hipExtLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, ev_start, ev_stop,
-                          0, p, r, diag, erow, ecol, phi, t, xloc, done);
+                          0, p, r, diag, erow, ecol, phi, t, tpart, T0, xloc, done);
   else
     hipLaunchKernelGGL((k_local_apply<T, C, TB>), dim3(p.N), dim3(WG), sm, s, p, r, diag, erow,
-                       ecol, phi, t, xloc, done);
+                       ecol, phi, t, tpart, T0, xloc, done);
 }
 
 #define AMSP_LOCAL_APPLY_INST(T, C, TB)                                                        \
   template void launch_local_apply_t<T, C, TB>(hipStream_t, const Plan &, int, const double *, \
                                                const T *, const T *, const T *, const TB *,    \
-                                               const double *, double *, const int *,          \
-                                               hipEvent_t, hipEvent_t);
+                                               const double *, const double *, int, double *,  \
+                                               const int *, hipEvent_t, hipEvent_t);
 AMSP_LOCAL_APPLY_INST(double, double, double)
 #undef AMSP_LOCAL_APPLY_INST
 
 template <typename TB>
 void launch_local_apply_stream(hipStream_t s, const Plan &p, int max_npad, const double *r,
                                const float *fst, const float *bst, const TB *phi, const double *t,
-                               double *xloc, const int *done, hipEvent_t ev_start,
-                               hipEvent_t ev_stop) {
+                               const double *tpart, int T0, double *xloc, const int *done,
+                               hipEvent_t ev_start, hipEvent_t ev_stop) {
   const size_t sm = local_apply_stream_lds_bytes(max_npad);
   allow_lds(k_local_apply_stream<TB>, sm);
   if (ev_start || ev_stop)  // events bound to this dispatch: exact kernel duration
     hipExtLaunchKernelGGL((k_local_apply_stream<TB>), dim3(p.N), dim3(WG), sm, s, ev_start,
-                          ev_stop, 0, p, r, fst, bst, phi, t, xloc, done);
+                          ev_stop, 0, p, r, fst, bst, phi, t, tpart, T0, xloc, done);
   else
     hipLaunchKernelGGL((k_local_apply_stream<TB>), dim3(p.N), dim3(WG), sm, s, p, r, fst, bst, phi,
-                       t, xloc, done);
+                       t, tpart, T0, xloc, done);
 }
 template void launch_local_apply_stream<float>(hipStream_t, const Plan &, int, const double *,
                                                const float *, const float *, const float *,
-                                               const double *, double *, const int *, hipEvent_t,
-                                               hipEvent_t);
+                                               const double *, const double *, int, double *,
+                                               const int *, hipEvent_t, hipEvent_t);
 template void launch_local_apply_stream<__hip_bfloat16>(hipStream_t, const Plan &, int,
                                                         const double *, const float *,
                                                         const float *, const __hip_bfloat16 *,
-                                                        const double *, double *, const int *,
-                                                        hipEvent_t, hipEvent_t);
+                                                        const double *, const double *, int,
+                                                        double *, const int *, hipEvent_t,
+                                                        hipEvent_t);
 
 }  // namespace amsp

@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(WG) k_trmv_tiles(const T *__restrict__ Wt, int
 // K ranging over J <= O (no transpose) or I >= O (transpose).  RG groups of
 // 64 threads per output tile split the K range into fixed consecutive
 // pieces (a few loads each, issued together), combined in group order.
-constexpr int RG = 16;
+constexpr int RG = TRMV_RG;
 __global__ void __launch_bounds__(RG * TS) k_trmv_reduce(int T0, const double *__restrict__ part,
                                                          double *__restrict__ y, int transpose,
                                                          const int *__restrict__ done) {
@@ -416,7 +416,8 @@ void launch_trmv(hipStream_t s, const T *Wt, int T0, const double *x, double *pa
                  int transpose, const int *done) {
   const int nb = T0 * (T0 + 1) / 2;
   hipLaunchKernelGGL((k_trmv_tiles<T>), dim3(nb), dim3(WG), 0, s, Wt, T0, x, part, transpose, done);
-  hipLaunchKernelGGL(k_trmv_reduce, dim3(T0), dim3(RG * TS), 0, s, T0, part, y, transpose, done);
+  if (y)
+    hipLaunchKernelGGL(k_trmv_reduce, dim3(T0), dim3(RG * TS), 0, s, T0, part, y, transpose, done);
 }
 template void launch_trmv<double>(hipStream_t, const double *, int, const double *, double *,
                                   double *, int, const int *);
