@@ -551,9 +551,13 @@ __global__ void __launch_bounds__(WG) k_gs_dots(int n, const double *__restrict_
   for (int c = 0; c < GSC; ++c) acc[c] = 0.0;
   for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += nb * WG) {
     const double wi = w[i];
+    // columns clamped to the last one and loaded unconditionally, so that
+    // the GSC loads are in flight together; the surplus ones are dropped
+    double vc[GSC];
 #pragma unroll
-    for (int c = 0; c < GSC; ++c)
-      if (c0 + c < k1) acc[c] = fma(V[(size_t)(c0 + c) * ldv + i], wi, acc[c]);
+    for (int c = 0; c < GSC; ++c) vc[c] = V[(size_t)min(c0 + c, k1 - 1) * ldv + i];
+#pragma unroll
+    for (int c = 0; c < GSC; ++c) acc[c] = c0 + c < k1 ? fma(vc[c], wi, acc[c]) : acc[c];
   }
 #pragma unroll
   for (int c = 0; c < GSC; ++c) {
@@ -580,7 +584,19 @@ __global__ void __launch_bounds__(WG) k_gs_update(int n, const double *__restric
   double acc = 0.0;
   for (int i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
     double wi = w[i];
-    for (int k = 0; k < k1; ++k) wi = fma(-V[(size_t)k * ldv + i], h[k], wi);
+    // GSC columns' loads at a time (clamped, all issued), used in order
+    for (int k0 = 0; k0 < k1; k0 += GSC) {
+      double vc[GSC], hc[GSC];
+#pragma unroll
+      for (int c = 0; c < GSC; ++c) {
+        const int k = min(k0 + c, k1 - 1);
+        vc[c] = V[(size_t)k * ldv + i];
+        hc[c] = h[k];
+      }
+#pragma unroll
+      for (int c = 0; c < GSC; ++c)
+        if (k0 + c < k1) wi = fma(-vc[c], hc[c], wi);
+    }
     w[i] = wi;
     acc = fma(wi, wi, acc);
   }

@@ -533,12 +533,20 @@ __global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict
     int e[SU + 1];
 #pragma unroll
     for (int u = 0; u <= SU; ++u) e[u] = inv_ptr[min(j0 + u, n)];
+    double rj[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) rj[u] = r ? r[min(j0 + u, n - 1)] : 0.0;
+    // the first SC copies' indices, then values, with the positions clamped
+    // into the run and every load issued (a load under a per-lane condition
+    // would be waited for inside its branch); copies past the run are
+    // dropped by the range test of the sums
+    const int klast = max(e[SU] - 1, 0);
+    int idx[SC];
+#pragma unroll
+    for (int c = 0; c < SC; ++c) idx[c] = ix[min(e[0] + c, klast)];
     double x[SC];
 #pragma unroll
-    for (int c = 0; c < SC; ++c) {
-      const int k = e[0] + c;
-      x[c] = k < e[SU] ? xloc[ix[k]] : 0.0;
-    }
+    for (int c = 0; c < SC; ++c) x[c] = xloc[idx[c]];
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
       double zj = 0.0;
@@ -551,7 +559,7 @@ __global__ void __launch_bounds__(WG) k_scatter_sum(int n, const int *__restrict
       const int j = j0 + u;
       if (j < n) {
         z[j] = zj;
-        if (r) acc = fma(r[j], zj, acc);
+        if (r) acc = fma(rj[u], zj, acc);
       }
     }
   }
