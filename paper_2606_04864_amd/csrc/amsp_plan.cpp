@@ -642,7 +642,9 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     for (int g : S.frontier)
       for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
         const int c = ci[e];
-        if (c != g && va[e] != 0.0 && S.stamp[c] != mark) {
+        // the stamp test first: most neighbours are already in the region,
+        // and it spares the read of the value
+        if (c != g && S.stamp[c] != mark && va[e] != 0.0) {
           S.stamp[c] = mark;
           S.next.push_back(c);
         }
@@ -791,7 +793,7 @@ static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, Su
     const int g = P.sd_dofs[r0 + k];
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
       const int c = ci[e];
-      if (c != g && va[e] != 0.0 && loc[c] < 0 && S.stamp[c] != mark) {
+      if (c != g && loc[c] < 0 && S.stamp[c] != mark && va[e] != 0.0) {
         S.stamp[c] = mark;
         out.ext.push_back(c);
       }

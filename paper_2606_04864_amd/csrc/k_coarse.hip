@@ -85,23 +85,37 @@ __global__ void __launch_bounds__(WG) k_pair_products(Plan p, CoarsePlan c,
   }
 }
 
-// Lower tiles <- (A0 + A0^T)/2, padding diagonal <- 1.  One thread per
-// lower-triangle element pair.
-__global__ void k_symmetrize(double *__restrict__ A0t, int T0, int nc) {
-  const size_t npad = (size_t)T0 * TS;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < npad * npad;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int R = (int)(e / npad), C = (int)(e % npad);
-    if (C > R) continue;
-    if (R >= nc || C >= nc) {
-      A0t[a0_index(R, C, T0)] = (R == C) ? 1.0 : 0.0;
-      if (R != C) A0t[a0_index(C, R, T0)] = 0.0;
-      continue;
-    }
-    const double v = 0.5 * (A0t[a0_index(R, C, T0)] + A0t[a0_index(C, R, T0)]);
-    A0t[a0_index(R, C, T0)] = v;
-    A0t[a0_index(C, R, T0)] = v;
+// Both triangles <- (A0 + A0^T)/2, padding diagonal <- 1.  One workgroup per
+// lower tile pair (I, J), J <= I: tiles (I, J) and (J, I) go through LDS, so
+// that every global access is a whole tile row.
+__global__ void __launch_bounds__(WG) k_symmetrize(double *__restrict__ A0t, int T0, int nc) {
+  __shared__ double X[TS * LDT], Y[TS * LDT];
+  const int b = blockIdx.x;
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;
+  double *xt = A0t + ((size_t)I * T0 + J) * TE, *yt = A0t + ((size_t)J * T0 + I) * TE;
+  for (int e = threadIdx.x; e < TE; e += WG) {
+    X[(e >> 6) * LDT + (e & 63)] = xt[e];
+    Y[(e >> 6) * LDT + (e & 63)] = yt[e];
   }
+  __syncthreads();
+  // element (r, c) of tile (I, J) is A0[R][C], R = 64I + r, C = 64J + c; its
+  // mirror A0[C][R] is element (c, r) of tile (J, I)
+  for (int e = threadIdx.x; e < TE; e += WG) {
+    const int r = e >> 6, c = e & 63, R = I * TS + r, C = J * TS + c;
+    double v;
+    if (R >= nc || C >= nc)
+      v = R == C ? 1.0 : 0.0;
+    else
+      v = 0.5 * (X[r * LDT + c] + Y[c * LDT + r]);
+    xt[e] = v;
+    Y[c * LDT + r] = v;  // read above by this thread only
+  }
+  if (I == J) return;
+  __syncthreads();
+  for (int e = threadIdx.x; e < TE; e += WG) yt[e] = Y[(e >> 6) * LDT + (e & 63)];
 }
 
 // ------------------------------------- singular problems: A0 + alpha u u^T ---
@@ -356,10 +370,8 @@ void launch_singular_regularize(hipStream_t s, const Plan &p, const double *phi,
 }
 
 void launch_symmetrize_tiles(hipStream_t s, double *A0t, int T0, int nc) {
-  size_t tot = (size_t)T0 * TS * T0 * TS;
-  size_t b = (tot + WG - 1) / WG;
-  if (b > 65535) b = 65535;
-  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)b), dim3(WG), 0, s, A0t, T0, nc);
+  const unsigned nb = (unsigned)((size_t)T0 * (T0 + 1) / 2);
+  if (nb > 0) hipLaunchKernelGGL(k_symmetrize, dim3(nb), dim3(WG), 0, s, A0t, T0, nc);
 }
 
 void launch_dense_potrf_diag(hipStream_t s, double *A0t, int T0, int k, double *dinv, int *status) {

@@ -268,10 +268,18 @@ __global__ void __launch_bounds__(WG) k_spmm_sell(int n, const long long *__rest
   }
   for (int k = 0; k < nr; ++k) {
     const double *x = X + (size_t)k * ld;
+    // every slot's x is loaded (c[j] is a valid row for the slots past the
+    // slice width), and those slots are dropped by a select, so that the
+    // loads are in flight together
+    double xv[JU];
+#pragma unroll
+    for (int j = 0; j < JU; ++j) xv[j] = x[c[j]];
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < JU; ++j)
-      if (j < wd) s = fma(v[j], x[c[j]], s);
+    for (int j = 0; j < JU; ++j) {
+      const double t = fma(v[j], xv[j], s);
+      s = j < wd ? t : s;
+    }
     for (int j = JU; j < wd; ++j) {
       const long long e = base + (long long)j * 64 + lane;
       s = fma(sval[e], x[scol[e]], s);
