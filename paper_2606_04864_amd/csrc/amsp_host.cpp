@@ -655,8 +655,26 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
   // --- upload matrix and plan
   double ta, tb;
   {
-    std::vector<int> rp32(h->n + 1);
-    for (int i = 0; i <= h->n; ++i) rp32[i] = (int)A->row_ptr[i];
+    // 32-bit row pointers and the sliced copy's slice starts, on the
+    // planner's threads (64 chunks of rows; 64-row slices)
+    const int n = h->n, ns = (n + 63) / 64;
+    ivec rp32;
+    rp32.resize(n + 1);
+    std::vector<long long> sp(ns + 1);
+    sp[0] = 0;
+    plan_parallel_for(64, [&](int c) {
+      const int s0 = (int)((long long)ns * c / 64), s1 = (int)((long long)ns * (c + 1) / 64);
+      for (int sl = s0; sl < s1; ++sl) {
+        int w = 0;
+        for (int i = 64 * sl; i < std::min(n, 64 * sl + 64); ++i) {
+          rp32[i] = (int)A->row_ptr[i];
+          w = std::max(w, (int)(A->row_ptr[i + 1] - A->row_ptr[i]));
+        }
+        sp[sl + 1] = 64LL * w;  // widths first, then the running sum
+      }
+    });
+    rp32[n] = (int)A->row_ptr[n];
+    for (int sl = 0; sl < ns; ++sl) sp[sl + 1] += sp[sl];
     ta = now_ms();
     h->rowptr = upload(h, rp32, ok);
     h->col = h->mem.alloc<int>(h->nnz);
@@ -670,15 +688,6 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     HIP_TRY(hipStreamSynchronize(h->stream));
     tb = now_ms();
     // sliced copy for the CG matrix product
-    const int ns = (h->n + 63) / 64;
-    std::vector<long long> sp(ns + 1);
-    sp[0] = 0;
-    for (int sl = 0; sl < ns; ++sl) {
-      int w = 0;
-      for (int i = 64 * sl; i < std::min(h->n, 64 * sl + 64); ++i)
-        w = std::max(w, (int)(A->row_ptr[i + 1] - A->row_ptr[i]));
-      sp[sl + 1] = sp[sl] + 64LL * w;
-    }
     h->sptr = upload(h, sp, ok);
     h->scol = h->mem.alloc<int>(std::max<long long>(1, sp[ns]));
     h->sval = h->mem.alloc<double>(std::max<long long>(1, sp[ns]));

@@ -266,6 +266,10 @@ static void parallel_for(int count, F fn) {
   for (auto &t : ts) t.join();
 }
 
+void plan_parallel_for(int count, const std::function<void(int)> &fn) {
+  parallel_for(count, [&](int c) { fn(c); });
+}
+
 // fn(i) for i in [0, count) in 64 contiguous chunks: neighbouring subdomains
 // stay on one worker, so the index arrays they share rarely bounce between
 // cores.

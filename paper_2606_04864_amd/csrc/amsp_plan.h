@@ -1,6 +1,7 @@
 // Host index planner (integer work) shared by the library's setup.
 #pragma once
 #include <array>
+#include <functional>
 #include <memory>
 #include <string>
 #include <utility>
@@ -16,6 +17,9 @@ namespace amsp {
 // their index arrays; smaller requests go to operator new.
 void *plan_alloc(size_t bytes);
 void plan_free(void *p, size_t bytes);
+// fn(c) for c in [0, count) on the planner's worker threads (at most 16,
+// dynamic schedule); returns when all have run.
+void plan_parallel_for(int count, const std::function<void(int)> &fn);
 // Joins the planner's worker threads and releases the free blocks of the
 // cache (blocks still in use stay valid and return to the cache later).
 // Also run by an exit handler.  Not to be called while a plan is being built.
