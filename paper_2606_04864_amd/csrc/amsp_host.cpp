@@ -1645,7 +1645,8 @@ static int64_t apply_factor_elems(const HostPlan &P) {
 
 // Algorithmic bytes of one local-apply launch: gather of r and the region
 // index, envelope segment starts, both factor sweeps, basis and coarse
-// solution read for the prolongation, local output.
+// solution (or the partials it is summed from) read for the prolongation,
+// local output.
 static int64_t local_apply_bytes(const amsp_handle *h) {
   const HostPlan &P = h->hp;
   const bool mixed = h->opt.precision != AMSP_FP64;
@@ -1656,7 +1657,14 @@ static int64_t local_apply_bytes(const amsp_handle *h) {
   // padding) once per sweep; the FP64 form reads diagonal tiles and envelope
   const int64_t fac = mixed ? (int64_t)(h->nst_f + h->nst_b) * fb : 2 * apply_factor_elems(P) * fb;
   int64_t b = sni * (8 + 4) + sni * 8 + 2 * (snp + h->N) * 4 + fac;
-  if (h->nc > 0) b += sni * h->nev * pb + (int64_t)h->nc * 8;
+  if (h->nc > 0) {
+    b += sni * h->nev * pb;  // basis rows for the prolongation
+    if (h->tree) {
+      b += (int64_t)h->nc * 8;  // the coarse solution
+    } else {  // the second coarse product's per-tile partials, summed here
+      for (int64_t g = 0; g < h->nc; ++g) b += (int64_t)(h->T0 - g / TS) * 8;
+    }
+  }
   return b;
 }
 
