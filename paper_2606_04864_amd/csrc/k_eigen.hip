@@ -466,53 +466,74 @@ __global__ void __launch_bounds__(WG) k_build_basis(Plan p, const double *__rest
   const int r0 = p.sd_ptr[i], ni = p.sd_ptr[i + 1] - r0;
   const int m = p.mi[i], nev = p.nev;
   const double *Xi = X + (size_t)p.vp_ptr[i] * EIGP;
-  __shared__ double bestv[WG / 64], bests[WG / 64];
-  __shared__ int bestg[WG / 64];
+  __shared__ double bestv[EIGP][WG / 64], bests[EIGP][WG / 64];
+  __shared__ int bestg[EIGP][WG / 64];
   __shared__ double sgn[EIGP];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int k = 0; k < m; ++k) {
-    double bv = -1.0;
-    int bg = 0x7fffffff;
-    double bs = 1.0;
-    for (int l = threadIdx.x; l < ni; l += WG) {
-      const double ps = Xi[(size_t)l * EIGP + k] / sqrt(sdiag[r0 + l]);
+  // one pass over the rows for all kept columns: each thread's largest
+  // |psi| per column (ties: lowest global dof) and its sign, then the
+  // wavefronts' and the workgroup's (the order of comparison does not
+  // matter: (|psi|, -dof) is a total order)
+  double bv[EIGP], bs[EIGP];
+  int bg[EIGP];
+#pragma unroll
+  for (int k = 0; k < EIGP; ++k) {
+    bv[k] = -1.0;
+    bg[k] = 0x7fffffff;
+    bs[k] = 1.0;
+  }
+  for (int l = threadIdx.x; l < ni; l += WG) {
+    const double sq = sqrt(sdiag[r0 + l]);
+    const int g = p.sd_dofs[r0 + l];
+    const double *xr = Xi + (size_t)l * EIGP;
+    double xv[EIGP];
+#pragma unroll
+    for (int k = 0; k < EIGP; ++k) xv[k] = xr[k];
+#pragma unroll
+    for (int k = 0; k < EIGP; ++k) {
+      const double ps = xv[k] / sq;
       const double a = fabs(ps);
-      const int g = p.sd_dofs[r0 + l];
-      if (a > bv || (a == bv && g < bg)) {
-        bv = a;
-        bg = g;
-        bs = ps < 0.0 ? -1.0 : 1.0;
+      if (a > bv[k] || (a == bv[k] && g < bg[k])) {
+        bv[k] = a;
+        bg[k] = g;
+        bs[k] = ps < 0.0 ? -1.0 : 1.0;
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int og = __shfl_xor(bg, o, 64);
-      const double os = __shfl_xor(bs, o, 64);
-      if (ov > bv || (ov == bv && og < bg)) {
-        bv = ov;
-        bg = og;
-        bs = os;
-      }
-    }
-    __syncthreads();
-    if (lane == 0) {
-      bestv[w] = bv;
-      bestg[w] = bg;
-      bests[w] = bs;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = bestv[0];
-      int g = bestg[0];
-      double s = bests[0];
-      for (int u = 1; u < WG / 64; ++u)
-        if (bestv[u] > v || (bestv[u] == v && bestg[u] < g)) {
-          v = bestv[u];
-          g = bestg[u];
-          s = bests[u];
+  }
+#pragma unroll
+  for (int k = 0; k < EIGP; ++k) {
+    if (k < m) {  // uniform
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv[k], o, 64);
+        const int og = __shfl_xor(bg[k], o, 64);
+        const double os = __shfl_xor(bs[k], o, 64);
+        if (ov > bv[k] || (ov == bv[k] && og < bg[k])) {
+          bv[k] = ov;
+          bg[k] = og;
+          bs[k] = os;
         }
-      sgn[k] = s;
+      }
+      if (lane == 0) {
+        bestv[k][w] = bv[k];
+        bestg[k][w] = bg[k];
+        bests[k][w] = bs[k];
+      }
     }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    const int k = threadIdx.x;
+    double v = bestv[k][0];
+    int g = bestg[k][0];
+    double sg = bests[k][0];
+    for (int u = 1; u < WG / 64; ++u)
+      if (bestv[k][u] > v || (bestv[k][u] == v && bestg[k][u] < g)) {
+        v = bestv[k][u];
+        g = bestg[k][u];
+        sg = bests[k][u];
+      }
+    sgn[k] = sg;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < ni * nev; e += WG) {

@@ -263,13 +263,53 @@ __global__ void __launch_bounds__(WG) k_extract_tiles(Plan p, int nrows_total,
   const bool real = l < ni;
   const int e0 = real ? p.loc_rowptr[r0 + l] : 0, e1 = real ? p.loc_rowptr[r0 + l + 1] : 0;
   const double sl = (real && mode == 1) ? sdiag[r0 + l] : 1.0;
+  // the row's first RE entries (local column and value, scaled in mode 1),
+  // loaded once for all its tiles with clamped indices, every load issued;
+  // longer rows take the rest one by one in each tile
+  constexpr int RE = 8;
+  int ec[RE];
+  double ea[RE];
+#pragma unroll
+  for (int k = 0; k < RE; ++k) {
+    ec[k] = -TS;
+    ea[k] = 0.0;
+  }
+  if (real) {  // a row of the region has at least its diagonal entry
+    const int el = e1 - 1;
+    int es[RE];
+#pragma unroll
+    for (int k = 0; k < RE; ++k) {
+      const int e = min(e0 + k, el);
+      ec[k] = p.loc_col[e];
+      es[k] = p.loc_src[e];
+    }
+#pragma unroll
+    for (int k = 0; k < RE; ++k) ea[k] = val[es[k]];
+    if (mode == 1) {
+      double sc[RE];
+#pragma unroll
+      for (int k = 0; k < RE; ++k) sc[k] = sdiag[r0 + ec[k]];
+#pragma unroll
+      for (int k = 0; k < RE; ++k) ea[k] = (ec[k] == l) ? 1.0 + sigma : ea[k] / sqrt(sl * sc[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < RE; ++k)
+      if (e0 + k >= e1) ec[k] = -TS;  // no entry: never inside a tile
+  }
   for (int J = fI; J <= I; ++J) {
     double v[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) v[c] = 0.0;
     const int cbase = J * TS + 16 * q;
     if (real) {
-      for (int e = e0; e < e1; ++e) {
+#pragma unroll
+      for (int k = 0; k < RE; ++k) {
+        const int off = ec[k] - cbase;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c == off) v[c] = ea[k];
+      }
+      for (int e = e0 + RE; e < e1; ++e) {
         const int lc = p.loc_col[e];
         const int off = lc - cbase;
         if (off >= 0 && off < 16) {
