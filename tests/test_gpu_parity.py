@@ -52,6 +52,8 @@ def case(name):
             w = configs.channels(nx=12, nparts=16, overlap=0, nev=3)
         elif name == "ragged":  # n not a multiple of 64, uneven parts
             w = configs.gauss_inclusions(nx=61, nparts=7, overlap=1, nev=5, ndisks=6)
+        elif name == "nev12":  # more than 8 kept vectors: basis rows read as 16 values
+            w = configs.channels(nx=64, nparts=16, overlap=1, nev=12)
         else:
             raise KeyError(name)
         A = w.A.to_scipy()
@@ -170,7 +172,7 @@ def test_setup_parity(name):
     pc.close()
 
 
-@pytest.mark.parametrize("name", ["channels64", "gauss128", "tiny16", "ragged"])
+@pytest.mark.parametrize("name", ["channels64", "gauss128", "tiny16", "ragged", "nev12"])
 def test_apply_parity(name):
     w, A, st = case(name)
     say("apply parity", name)
@@ -200,7 +202,7 @@ def test_preconditioner_symmetric_positive():
     pc.close()
 
 
-@pytest.mark.parametrize("name", ["channels64", "gauss128", "ragged"])
+@pytest.mark.parametrize("name", ["channels64", "gauss128", "ragged", "nev12"])
 def test_pcg_parity(name):
     w, A, st = case(name)
     say("pcg parity", name)
@@ -238,9 +240,10 @@ def test_pcg_parity(name):
     pc.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_mixed_forms_converge(prec):
-    w, A, st = case("gauss128")
+@pytest.mark.parametrize("prec,name", [("fp32", "gauss128"), ("bf16", "gauss128"),
+                                       ("fp32", "nev12")])
+def test_mixed_forms_converge(prec, name):
+    w, A, st = case(name)
     say("mixed", prec)
     pc = P.setup(w.A, w.part, w.nparts, w.nev, overlap=w.overlap, precision=prec)
     u, info = pc.pcg(dev(w.b), 1e-8, 2000)
