@@ -86,7 +86,7 @@ typedef struct {
   int32_t local_order;      /* amsp_local_order                                         */
   int32_t dense_tiles;      /* 1: store the full lower triangle of tiles (no profile)   */
   double eig_tol;           /* residual bound ||B x - theta x|| for the kept pairs;      */
-                            /* 0 (default): 1e-12, or 1e-5 for the mixed forms           */
+                            /* 0 (default): 1e-12, or 1e-4 for the mixed forms           */
   int32_t eig_maxit;        /* maximum subspace sweeps (default 80)                      */
   double eig_shift;         /* sigma in (B + sigma I)^{-1} (default 1e-4)                */
   int32_t chunk;            /* PCG iterations per host poll (default 8)                  */

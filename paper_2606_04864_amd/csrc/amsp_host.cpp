@@ -373,7 +373,7 @@ extern "C" void amsp_default_options(amsp_options *opt) {
   opt->pou = 0;
   opt->local_order = AMSP_ORDER_RCM;
   opt->dense_tiles = 0;
-  opt->eig_tol = 0.0;  // 0: 1e-12 (FP64) or 1e-5 (mixed forms)
+  opt->eig_tol = 0.0;  // 0: 1e-12 (FP64) or 1e-4 (mixed forms)
   opt->eig_maxit = 80;
   opt->eig_shift = 1e-4;
   opt->chunk = 8;
@@ -880,7 +880,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     facB = nullptr;
     launch_eig_init(h->stream, p, h->sdiag, X);
     launch_eig_bval(h->stream, p, h->val, h->sdiag, bval);
-    const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-5 : 1e-12);
+    const double tol = h->opt.eig_tol > 0 ? h->opt.eig_tol : (mixed ? 1e-4 : 1e-12);
     std::vector<int> hconv(h->N);
     int sweeps = 0, unconv = h->N;
     // Convergence is checked every second sweep from the fourth.  Each

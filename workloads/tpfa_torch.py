@@ -43,18 +43,30 @@ class TpfaAssembly:
             Q.append(np.take(cell, np.arange(1, shape[a]), axis=a).ravel())
             for end in (0, shape[a] - 1):
                 np.add.at(nb, np.take(cell, [end], axis=a).ravel(), 1.0)
+        nf = [len(x) for x in P]
         P, Q = np.concatenate(P), np.concatenate(Q)
+        # faces of every cell, 2 per axis (as P, as Q), the missing ones
+        # pointing at a zero appended to the face values: the diagonal is a
+        # row sum of this table, a fixed order (a scatter-add onto repeated
+        # indices would add in an order that changes from run to run)
+        faces = np.full((n, 2 * d), len(P), dtype=np.int64)
+        f0 = 0
+        for a in range(d):
+            fa = np.arange(f0, f0 + nf[a])
+            faces[P[fa], 2 * a] = fa
+            faces[Q[fa], 2 * a + 1] = fa
+            f0 += nf[a]
         diag = pos(np.arange(n), np.arange(n))
         t = lambda x: torch.as_tensor(x)
         self._P, self._Q = t(P), t(Q)
         self._pq, self._qp = t(pos(P, Q)), t(pos(Q, P))
-        self._dp, self._dq, self._diag = t(diag[P]), t(diag[Q]), t(diag)
+        self._diag, self._faces = t(diag), t(faces)
         self._nb = t(nb)
         self._dev = None
 
     def _to(self, device):
         if self._dev != device:
-            for name in ("_P", "_Q", "_pq", "_qp", "_dp", "_dq", "_diag", "_nb"):
+            for name in ("_P", "_Q", "_pq", "_qp", "_diag", "_faces", "_nb"):
                 setattr(self, name, getattr(self, name).to(device))
             self._dev = device
 
@@ -66,7 +78,9 @@ class TpfaAssembly:
         k = theta.permute(*reversed(range(theta.dim()))).reshape(-1).exp()  # cell order
         kP, kQ = k[self._P], k[self._Q]
         T = self.s * 2.0 * kP * kQ / (kP + kQ)
+        Tz = torch.cat([T, T.new_zeros(1)])
+        dg = Tz[self._faces].sum(dim=1) + self.s * 2.0 * k * self._nb
+        # every CSR position is written once: no accumulation, a fixed result
         vals = torch.zeros(self.nnz, dtype=theta.dtype, device=theta.device)
-        vals = vals.index_add(0, self._pq, -T).index_add(0, self._qp, -T)
-        vals = vals.index_add(0, self._dp, T).index_add(0, self._dq, T)
-        return vals.index_add(0, self._diag, self.s * 2.0 * k * self._nb)
+        vals = vals.index_put((self._pq,), -T).index_put((self._qp,), -T)
+        return vals.index_put((self._diag,), dg)
