@@ -1020,7 +1020,7 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     // the trailing update.  A third stream forms the inverse factor
     // W0 = inv(L0) by a right-looking solve of L0 X = I; its step k needs
     // only column k of L0, final once the panel of step k is done.
-    //   main:  potrf(k) trsm(k) [panel] ... wait [rest of k-1] next(k)
+    //   main:  trsm(k) [panel] ... wait [rest of k-1] next(k)+potrf(k+1)
     //   bulk:  wait [panel] rest(k) [rest]
     //   inv:   wait [panel] inv_row(k) inv_update(k)
     ALLOC(h->W0, double, (size_t)T0 * T0 * TE);
@@ -1033,15 +1033,17 @@ static amsp_status device_setup(amsp_handle *h, const amsp_csr *A) {
     HIP_TRY(hipStreamWaitEvent(bulk.s, ev_panel, 0));
     HIP_TRY(hipEventRecord(ev_rest, bulk.s));
     launch_tiles_identity(inv.s, h->W0, T0);
+    // the diagonal factor of step k + 1 runs in the same launch as step k's
+    // update of column k + 1 (launch_dense_next_potrf)
+    launch_dense_potrf_diag(h->stream, A0t, T0, 0, dinv, cstat);
     for (int k = 0; k < T0; ++k) {
-      launch_dense_potrf_diag(h->stream, A0t, T0, k, dinv, cstat);
       launch_dense_trsm_panel(h->stream, A0t, T0, k, dinv);
       HIP_TRY(hipEventRecord(ev_panel, h->stream));
       HIP_TRY(hipStreamWaitEvent(inv.s, ev_panel, 0));
       launch_dense_inv_row(inv.s, h->W0, T0, k, dinv);
       launch_dense_inv_update(inv.s, A0t, h->W0, T0, k);
       HIP_TRY(hipStreamWaitEvent(h->stream, ev_rest, 0));  // rest of step k-1
-      launch_dense_syrk_next(h->stream, A0t, T0, k);
+      launch_dense_next_potrf(h->stream, A0t, T0, k, dinv, cstat);
       HIP_TRY(hipStreamWaitEvent(bulk.s, ev_panel, 0));
       launch_dense_syrk_rest(bulk.s, A0t, T0, k);
       HIP_TRY(hipEventRecord(ev_rest, bulk.s));

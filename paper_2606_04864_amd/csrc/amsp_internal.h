@@ -296,8 +296,11 @@ void launch_singular_regularize(hipStream_t s, const Plan &p, const double *phi,
 void launch_dense_potrf_diag(hipStream_t s, double *A0t, int T0, int k, double *dinv, int *status);
 void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const double *dinv);
 // Trailing update of Cholesky step k split for lookahead: the next tile
-// column (j = k + 1) and the rest (j >= k + 2).
-void launch_dense_syrk_next(hipStream_t s, double *A0t, int T0, int k);
+// column (j = k + 1), in one launch with step k + 1's diagonal factor (the
+// next diagonal tile is factored by the workgroup that updates it), and the
+// rest (j >= k + 2).
+void launch_dense_next_potrf(hipStream_t s, double *A0t, int T0, int k, double *dinv,
+                             int *status);
 void launch_dense_syrk_rest(hipStream_t s, double *A0t, int T0, int k);
 void launch_dense_inv_row(hipStream_t s, double *Wt, int T0, int k, const double *dinv);
 void launch_dense_inv_update(hipStream_t s, const double *Lt, double *Wt, int T0, int k);

@@ -225,6 +225,40 @@ __global__ void __launch_bounds__(WG) k_dense_syrk_update(double *A0t, int T0, i
   acc_store(o, c);
 }
 
+// Step k's update of the next tile column, fused with step k+1's diagonal
+// factor: tile (k+1+b, k+1) -= L_{k+1+b,k} L_{k+1,k}^T for every b (as
+// k_dense_syrk_update over that column); workgroup 0 holds the next diagonal
+// tile, which it then factors in LDS as k_dense_potrf_diag does (L in place,
+// its inverse in dinv).  One launch and one launch gap less per step on the
+// critical path.
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_dense_next_potrf(double *A0t, int T0, int k, double *dinv, int *status) {
+  extern __shared__ double lds[];
+  double *Ly = lds, *Y = lds + TS * LDT;  // Ly then holds the tile to factor
+  __shared__ int fail;
+  const int b = blockIdx.x, j = k + 1, i = j + b;
+  __builtin_amdgcn_s_setprio(3);  // critical path
+  if (threadIdx.x == 0) fail = 0;
+  tile_to_lds(tile_ptr(A0t, T0, j, k), Ly);
+  double *c = tile_ptr(A0t, T0, i, j);
+  Acc4 o;
+  acc_load(o, c);
+  __syncthreads();
+  acc_mma_abt(o, tile_ptr(A0t, T0, i, k), TS, Ly, LDT, -1.0);
+  if (b != 0) {  // uniform over the workgroup
+    acc_store(o, c);
+    return;
+  }
+  __syncthreads();  // every wavefront has finished reading L_{k+1,k}
+  acc_to_lds(o, Ly);
+  __syncthreads();
+  lds_potrf_trtri<32>(Ly, Y, &fail);
+  lds_to_tile(Ly, c);
+  lds_to_tile(Y, dinv + (size_t)j * TE);
+  __syncthreads();
+  if (threadIdx.x == 0 && fail) *status |= 1;
+}
+
 // Inverse factor by a right-looking solve of L X = I, step k:
 //   row k:   X_kj <- inv(L_kk) B_kj  (j <= k)
 //   update:  B_ij -= L_ik X_kj        (i > k, j <= k)
@@ -386,10 +420,13 @@ void launch_dense_trsm_panel(hipStream_t s, double *A0t, int T0, int k, const do
   hipLaunchKernelGGL(k_dense_trsm_panel, dim3(nb), dim3(WG), 0, s, A0t, T0, k, dinv);
 }
 
-void launch_dense_syrk_next(hipStream_t s, double *A0t, int T0, int k) {
+void launch_dense_next_potrf(hipStream_t s, double *A0t, int T0, int k, double *dinv,
+                             int *status) {
   const int m = T0 - k - 1;
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_dense_syrk_update, dim3(m), dim3(WG), 0, s, A0t, T0, k, k + 1, 0);
+  allow_lds(k_dense_next_potrf, two_tiles_lds());
+  hipLaunchKernelGGL(k_dense_next_potrf, dim3(m), dim3(WG), two_tiles_lds(), s, A0t, T0, k, dinv,
+                     status);
 }
 
 void launch_dense_syrk_rest(hipStream_t s, double *A0t, int T0, int k) {
