@@ -1266,13 +1266,15 @@ extern "C" amsp_status amsp_setup(const amsp_csr *A, const int32_t *partition, i
     return AMSP_ERR_ARG;
   }
   std::string msg;
-  int s = validate_inputs(A, partition, nparts, nev, o.overlap, msg);
+  int64_t offdiag_zeros = -1;
+  int s = validate_inputs(A, partition, nparts, nev, o.overlap, msg, &offdiag_zeros);
   if (s != AMSP_OK) {
     g_setup_error = msg;
     return (amsp_status)s;
   }
   amsp_handle *h = new (std::nothrow) amsp_handle();
   if (!h) return AMSP_ERR_OOM;
+  h->hp.offdiag_zeros = offdiag_zeros != 0;
   h->opt = o;
   if (h->opt.flexible < 0) h->opt.flexible = (o.precision != AMSP_FP64) ? 1 : 0;
   h->stream = (hipStream_t)o.stream;
@@ -2611,12 +2613,14 @@ extern "C" amsp_status amsp_plan_regions(const amsp_csr *A, const int32_t *parti
   amsp_default_options(&o);
   if (opt) o = *opt;
   std::string msg;
-  int s = validate_inputs(A, partition, nparts, nev, o.overlap, msg);
+  int64_t offdiag_zeros = -1;
+  int s = validate_inputs(A, partition, nparts, nev, o.overlap, msg, &offdiag_zeros);
   if (s != AMSP_OK) {
     g_setup_error = msg;
     return (amsp_status)s;
   }
   HostPlan P;
+  P.offdiag_zeros = offdiag_zeros != 0;
   try {
     s = build_plan(A, partition, nparts, nev, o, P, msg);
   } catch (const std::bad_alloc &) {

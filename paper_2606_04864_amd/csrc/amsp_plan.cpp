@@ -336,7 +336,8 @@ static void sort_lists(const V &ptr, int n, V &key, V &pay) {
 static inline int atomic_inc(int *x) { return __atomic_fetch_add(x, 1, __ATOMIC_RELAXED); }
 
 int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
-                    int32_t overlap, std::string &msg) {
+                    int32_t overlap, std::string &msg, int64_t *offdiag_zeros) {
+  if (offdiag_zeros) *offdiag_zeros = -1;
   if (!A || !part || !A->row_ptr || !A->col_idx || !A->val) {
     msg = "null pointer argument";
     return AMSP_ERR_ARG;
@@ -369,7 +370,7 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
   // row overall is reported).
   const int nchunk = 64;
   std::vector<int> cerr(nchunk, 0);
-  std::vector<int64_t> crow(nchunk, -1), cup(nchunk, 0), clo(nchunk, 0);
+  std::vector<int64_t> crow(nchunk, -1), cup(nchunk, 0), clo(nchunk, 0), czero(nchunk, 0);
   std::vector<double> cmax(nchunk, 0.0);
   auto chunk_rows = [&](int c, int64_t &r0, int64_t &r1) {
     r0 = n * c / nchunk;
@@ -379,7 +380,7 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     int64_t r0, r1;
     chunk_rows(c, r0, r1);
     double amax = 0.0;
-    int64_t up = 0, lo = 0;
+    int64_t up = 0, lo = 0, zero = 0;
     for (int64_t i = r0; i < r1; ++i) {
       if (rp[i] < 0 || rp[i + 1] < rp[i] || rp[i + 1] > A->nnz) {
         cerr[c] = 4;
@@ -397,6 +398,7 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
         if (cc == i) diag = true;
         up += (cc > i);
         lo += (cc < i);
+        zero += (cc != i && A->val[e] == 0.0);
         amax = std::max(amax, std::fabs(A->val[e]));
       }
       if (!diag) {
@@ -408,6 +410,7 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     cmax[c] = amax;
     cup[c] = up;
     clo[c] = lo;
+    czero[c] = zero;
   });
   for (int c = 0; c < nchunk; ++c) {
     if (cerr[c] == 4) {
@@ -424,11 +427,12 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     }
   }
   double amax = 0.0;
-  int64_t nup = 0, nlo = 0;
+  int64_t nup = 0, nlo = 0, nzero = 0;
   for (int c = 0; c < nchunk; ++c) {
     amax = std::max(amax, cmax[c]);
     nup += cup[c];
     nlo += clo[c];
+    nzero += czero[c];
   }
   // Pass 2: every strictly upper entry (i, c) has its mirror (c, i) with the
   // same value up to 1e-14 max|a|; with as many lower as upper entries this
@@ -494,6 +498,7 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
       return AMSP_ERR_PARTITION;
     }
   }
+  if (offdiag_zeros) *offdiag_zeros = nzero;
   return AMSP_OK;
 }
 
@@ -587,6 +592,33 @@ static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &a
   std::reverse(order.begin(), order.end());
 }
 
+// Ascending order of distinct indices: a bitmap scan over their range when
+// it is compact (typical for mesh numberings), otherwise a comparison sort.
+static void sort_distinct(std::vector<int> &v, std::vector<unsigned long long> &bits) {
+  if (v.empty()) return;
+  int lo = v[0], hi = v[0];
+  for (int g : v) {
+    lo = std::min(lo, g);
+    hi = std::max(hi, g);
+  }
+  const long long range = (long long)hi - lo + 1;
+  if (range > 64LL * (long long)v.size()) {
+    std::sort(v.begin(), v.end());
+    return;
+  }
+  const size_t nw = (size_t)((range + 63) / 64);
+  bits.assign(nw, 0ULL);
+  for (int g : v) bits[(g - lo) >> 6] |= 1ULL << ((g - lo) & 63);
+  size_t k = 0;
+  for (size_t wi = 0; wi < nw; ++wi) {
+    unsigned long long b = bits[wi];
+    while (b) {
+      v[k++] = lo + (int)(wi * 64) + __builtin_ctzll(b);
+      b &= b - 1;
+    }
+  }
+}
+
 // Per-subdomain planning result (built independently, concatenated in order).
 struct SubPlan {
   std::vector<int> dofs;                 // local order -> global dof
@@ -625,6 +657,8 @@ static double g_sec[8];
 #define SEC(k) do { } while (0)
 #endif
 
+// ZV: A may store off-diagonal zeros (read each visited entry's value).
+template <bool ZV>
 static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_ptr,
                         const std::vector<int> &core, int nev, const amsp_options &opt,
                         Scratch &S, SubPlan &out) {
@@ -648,7 +682,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
         const int c = ci[e];
         // the stamp test first: most neighbours are already in the region,
         // and it spares the read of the value
-        if (c != g && S.stamp[c] != mark && va[e] != 0.0) {
+        if (c != g && S.stamp[c] != mark && (!ZV || va[e] != 0.0)) {
           S.stamp[c] = mark;
           S.next.push_back(c);
         }
@@ -658,32 +692,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
     S.frontier.swap(S.next);
   }
   region.resize(region_size);
-  // ascending order: bitmap scan over the index range when it is compact
-  // (typical for mesh numberings), otherwise a comparison sort
-  {
-    int lo = region[0], hi = region[0];
-    for (int g : region) {
-      lo = std::min(lo, g);
-      hi = std::max(hi, g);
-    }
-    const long long range = (long long)hi - lo + 1;
-    if (range <= 64LL * (long long)region.size()) {
-      const size_t nw = (size_t)((range + 63) / 64);
-      S.bits.assign(nw, 0ULL);
-      for (int g : region) S.bits[(g - lo) >> 6] |= 1ULL << ((g - lo) & 63);
-      size_t k = 0;
-      for (size_t wi = 0; wi < nw; ++wi) {
-        unsigned long long b = S.bits[wi];
-        while (b) {
-          const int bit = __builtin_ctzll(b);
-          region[k++] = lo + (int)(wi * 64) + bit;
-          b &= b - 1;
-        }
-      }
-    } else {
-      std::sort(region.begin(), region.end());
-    }
-  }
+  sort_distinct(region, S.bits);
   SEC(0);
   const int ni = (int)region.size();
   ivec &loc = S.loc;
@@ -702,7 +711,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
       const int lc = loc[c];
       if (lc < 0) continue;
       S.tcol.push_back(lc);
-      if (c != g && va[e] != 0.0) S.adj.push_back(lc);
+      if (c != g && (!ZV || va[e] != 0.0)) S.adj.push_back(lc);
     }
     S.adj_ptr[k + 1] = (int)S.adj.size();
     S.tptr[k + 1] = (int)S.tcol.size();
@@ -784,6 +793,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
 
 // Extended region of subdomain i (its region grown by one more layer) and
 // the entries of A coupling each extended row to the region (local indices).
+template <bool ZV>
 static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, SubPlan &out) {
   const int64_t *rp = A->row_ptr;
   const int32_t *ci = A->col_idx;
@@ -797,13 +807,13 @@ static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, Su
     const int g = P.sd_dofs[r0 + k];
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
       const int c = ci[e];
-      if (c != g && loc[c] < 0 && S.stamp[c] != mark && va[e] != 0.0) {
+      if (c != g && loc[c] < 0 && S.stamp[c] != mark && (!ZV || va[e] != 0.0)) {
         S.stamp[c] = mark;
         out.ext.push_back(c);
       }
     }
   }
-  std::sort(out.ext.begin(), out.ext.end());
+  sort_distinct(out.ext, S.bits);
   out.ext_rowlen.resize(out.ext.size());
   out.ext_src.clear();
   out.ext_loc.clear();
@@ -879,7 +889,10 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
     ScratchPool pool(n);
     parallel_for(N, [&](int i) {
       auto sc = pool.get();
-      plan_region(i, A, core_ptr, core, nev, opt, *sc, sub[i]);
+      if (P.offdiag_zeros)
+        plan_region<true>(i, A, core_ptr, core, nev, opt, *sc, sub[i]);
+      else
+        plan_region<false>(i, A, core_ptr, core, nev, opt, *sc, sub[i]);
       pool.put(std::move(sc));
     });
   }
@@ -890,7 +903,7 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
       return AMSP_ERR_ARG;
     }
 #ifdef AMSP_PLAN_PROFILE
-  fprintf(stderr, "   grow+sort %.1f adj %.1f rcm %.1f lcsr %.1f (thread-summed ms)\n", g_sec[0], g_sec[1], g_sec[2], g_sec[3]);
+  fprintf(stderr, "   grow+sort %.1f adj %.1f rcm %.1f lcsr %.1f env %.1f (thread-summed ms)\n", g_sec[0], g_sec[1], g_sec[2], g_sec[3], g_sec[4]);
   for (double &x : g_sec) x = 0;
 #endif
   P.sd_ptr.assign(N + 1, 0);
@@ -982,7 +995,10 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
     ScratchPool pool(n);
     parallel_for(N, [&](int i) {
       auto sc = pool.get();
-      plan_ext(i, A, P, *sc, sub[i]);
+      if (P.offdiag_zeros)
+        plan_ext<true>(i, A, P, *sc, sub[i]);
+      else
+        plan_ext<false>(i, A, P, *sc, sub[i]);
       pool.put(std::move(sc));
     });
   }

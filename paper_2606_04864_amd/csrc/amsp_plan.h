@@ -51,6 +51,11 @@ struct NoInitAlloc : std::allocator<T> {
 using ivec = std::vector<int, NoInitAlloc<int>>;
 
 struct HostPlan {
+  // Set by the caller before planning: whether A may store off-diagonal
+  // zeros.  The graph of A leaves such entries out, so the planner reads the
+  // value of every entry it visits; when validation counted none, it reads
+  // only the column indices.
+  bool offdiag_zeros = true;
   int n = 0, N = 0, nev = 0, nc = 0;
   int max_ni = 0, max_npad = 0;
   long long ntiles = 0;  // all profile tiles (off-diagonal + one diagonal per tile row)
@@ -77,8 +82,10 @@ struct HostPlan {
   ivec pair_l, pair_e;
 };
 
+// On success *offdiag_zeros (when given) receives the number of stored
+// off-diagonal entries whose value is zero (-1 on failure).
 int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
-                    int32_t overlap, std::string &msg);
+                    int32_t overlap, std::string &msg, int64_t *offdiag_zeros = nullptr);
 // Regions, local orders, local CSR and tile profiles (everything the local
 // factorisations and eigensolves need).
 int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,

@@ -96,12 +96,23 @@ void plan_case(const Grid &g, int nev, int overlap, int order, int dense, const 
   opt.dense_tiles = dense;
   const amsp_csr A = g.csr();
   std::string msg;
-  int s = validate_inputs(&A, g.part.data(), g.nparts, nev, overlap, msg);
-  expect(s == AMSP_OK, std::string(name) + ": validate " + msg);
+  int64_t zeros = -1;
+  int s = validate_inputs(&A, g.part.data(), g.nparts, nev, overlap, msg, &zeros);
+  expect(s == AMSP_OK && zeros == 0, std::string(name) + ": validate " + msg);
   HostPlan P;
+  P.offdiag_zeros = zeros != 0;  // the planner's column-only reads
   s = build_plan(&A, g.part.data(), g.nparts, nev, opt, P, msg);
   expect(s == AMSP_OK, std::string(name) + ": plan " + msg);
   if (s != AMSP_OK) return;
+  {  // the same plan when every visited value is read
+    HostPlan Q;
+    Q.offdiag_zeros = true;
+    s = build_plan(&A, g.part.data(), g.nparts, nev, opt, Q, msg);
+    expect(s == AMSP_OK && Q.sd_dofs == P.sd_dofs && Q.loc_rowptr == P.loc_rowptr &&
+               Q.tfirst == P.tfirst && Q.ext_ptr == P.ext_ptr && Q.ext_src == P.ext_src &&
+               Q.pair_j == P.pair_j && Q.pair_e == P.pair_e,
+           std::string(name) + ": plan with value reads differs");
+  }
   const int N = g.nparts;
   expect((int)P.sd_ptr.size() == N + 1, std::string(name) + ": sd_ptr size");
   bool mono = true, cores_in = true, sets = true;
