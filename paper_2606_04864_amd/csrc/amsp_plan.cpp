@@ -677,7 +677,11 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   size_t region_size = region.size();
   for (int d = 0; d < layers; ++d) {
     S.next.clear();
-    for (int g : S.frontier)
+    const int nf = (int)S.frontier.size();
+    for (int f = 0; f < nf; ++f) {
+      const int g = S.frontier[f];
+      // the rows ahead are mostly first touches of A: fetch them early
+      if (f + 16 < nf) __builtin_prefetch(ci + rp[S.frontier[f + 16]]);
       for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
         const int c = ci[e];
         // the stamp test first: most neighbours are already in the region,
@@ -687,6 +691,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
           S.next.push_back(c);
         }
       }
+    }
     region.insert(region.end(), S.next.begin(), S.next.end());
     if (d == delta - 1) region_size = region.size();
     S.frontier.swap(S.next);
