@@ -45,14 +45,22 @@ __global__ void __launch_bounds__(WG) k_eig_init(Plan p, const double *__restric
 }
 
 // Cyclic Jacobi on the symmetric EIGP x EIGP matrix H (LDS, stride HP) by
-// one workgroup of any size; V accumulates the rotations.  Round-robin
-// ordering: EIGP/2 disjoint pairs per round, EIGP-1 rounds per sweep.
-__device__ void jacobi16(double *H, double *V, double *cs, int *flag, double off_rel2) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int e = t; e < EIGP * EIGP; e += nt) V[(e / EIGP) * HP + e % EIGP] = (e / EIGP == e % EIGP) ? 1.0 : 0.0;
+// one wavefront; V accumulates the rotations.  Round-robin ordering: EIGP/2
+// disjoint pairs per round, EIGP-1 rounds per sweep.  Lane (i, j) = (t / 8,
+// t % 8) forms the rotations of pairs i and j itself (the same arithmetic in
+// every lane that needs them) and rotates the 2 x 2 block of H at the rows
+// of pair i and the columns of pair j, rows first (J^T H) then columns (H J),
+// and the same block of V by columns, into the other buffer of each pair
+// (Hs, Vs): one barrier per round.  H and V end up pointing at the result.
+__device__ void jacobi16(double *&H, double *&V, double *Hs, double *Vs, int *flag,
+                         double off_rel2) {
+  static_assert(EIGP == 16, "lane (i, j) of one wavefront per pair of pairs");
+  const int t = threadIdx.x;
+  for (int e = t; e < EIGP * EIGP; e += 64) V[(e / EIGP) * HP + e % EIGP] = (e / EIGP == e % EIGP) ? 1.0 : 0.0;
   __syncthreads();
+  const int i = t >> 3, j = t & 7;
   for (int sweep = 0; sweep < 30; ++sweep) {
-    if (t < 64) {  // first wavefront: off-diagonal and total Frobenius norms
+    {  // off-diagonal and total Frobenius norms
       double off = 0.0, tot = 0.0;
       for (int e = t; e < EIGP * EIGP; e += 64) {
         const int a = e / EIGP, b = e % EIGP;
@@ -69,55 +77,60 @@ __device__ void jacobi16(double *H, double *V, double *cs, int *flag, double off
     __syncthreads();
     if (*flag) break;
     for (int rnd = 0; rnd < EIGP - 1; ++rnd) {
-      if (t < EIGP / 2) {
-        int pp, qq;
-        if (t == 0) {
+      auto pair = [&](int k, int &pp, int &qq) {
+        if (k == 0) {
           pp = rnd;
           qq = EIGP - 1;
         } else {
-          pp = (rnd + t) % (EIGP - 1);
-          qq = (rnd - t + (EIGP - 1)) % (EIGP - 1);
+          pp = (rnd + k) % (EIGP - 1);
+          qq = (rnd - k + (EIGP - 1)) % (EIGP - 1);
         }
         if (pp > qq) {
-          int tmp = pp;
+          const int tmp = pp;
           pp = qq;
           qq = tmp;
         }
+      };
+      auto rotation = [&](int pp, int qq, double &c, double &s) {
         const double apq = H[pp * HP + qq];
-        double c = 1.0, s = 0.0;
+        c = 1.0;
+        s = 0.0;
         if (apq != 0.0) {
           const double tau = (H[qq * HP + qq] - H[pp * HP + pp]) / (2.0 * apq);
           const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + tt * tt);
           s = tt * c;
         }
-        cs[4 * t + 0] = c;
-        cs[4 * t + 1] = s;
-        cs[4 * t + 2] = (double)pp;
-        cs[4 * t + 3] = (double)qq;
-      }
+      };
+      int pi, qi, pj, qj;
+      pair(i, pi, qi);
+      pair(j, pj, qj);
+      double ci, si, cj, sj;
+      rotation(pi, qi, ci, si);
+      rotation(pj, qj, cj, sj);
+      const double hpp = H[pi * HP + pj], hpq = H[pi * HP + qj];
+      const double hqp = H[qi * HP + pj], hqq = H[qi * HP + qj];
+      const double vpp = V[pi * HP + pj], vpq = V[pi * HP + qj];
+      const double vqp = V[qi * HP + pj], vqq = V[qi * HP + qj];
+      // rows pi, qi (pair i's rotation), columns pj and qj
+      const double rpp = ci * hpp - si * hqp, rqp = si * hpp + ci * hqp;
+      const double rpq = ci * hpq - si * hqq, rqq = si * hpq + ci * hqq;
+      // then columns pj, qj (pair j's rotation)
+      Hs[pi * HP + pj] = cj * rpp - sj * rpq;
+      Hs[pi * HP + qj] = sj * rpp + cj * rpq;
+      Hs[qi * HP + pj] = cj * rqp - sj * rqq;
+      Hs[qi * HP + qj] = sj * rqp + cj * rqq;
+      Vs[pi * HP + pj] = cj * vpp - sj * vpq;
+      Vs[pi * HP + qj] = sj * vpp + cj * vpq;
+      Vs[qi * HP + pj] = cj * vqp - sj * vqq;
+      Vs[qi * HP + qj] = sj * vqp + cj * vqq;
       __syncthreads();
-      for (int u = t; u < (EIGP / 2) * EIGP; u += nt) {  // rows: H <- J^T H
-        const int pr = u / EIGP, k = u % EIGP;
-        const double c = cs[4 * pr], s = cs[4 * pr + 1];
-        const int pp = (int)cs[4 * pr + 2], qq = (int)cs[4 * pr + 3];
-        const double hp = H[pp * HP + k], hq = H[qq * HP + k];
-        H[pp * HP + k] = c * hp - s * hq;
-        H[qq * HP + k] = s * hp + c * hq;
-      }
-      __syncthreads();
-      for (int u = t; u < 2 * (EIGP / 2) * EIGP; u += nt) {
-        const int half = (EIGP / 2) * EIGP;
-        const int v = u < half ? u : u - half;
-        const int pr = v / EIGP, k = v % EIGP;
-        const double c = cs[4 * pr], s = cs[4 * pr + 1];
-        const int pp = (int)cs[4 * pr + 2], qq = (int)cs[4 * pr + 3];
-        double *M = u < half ? H : V;  // columns of H (H <- H J), then V <- V J
-        const double hp = M[k * HP + pp], hq = M[k * HP + qq];
-        M[k * HP + pp] = c * hp - s * hq;
-        M[k * HP + qq] = s * hp + c * hq;
-      }
-      __syncthreads();
+      double *x = H;
+      H = Hs;
+      Hs = x;
+      x = V;
+      V = Vs;
+      Vs = x;
     }
   }
 }
@@ -272,9 +285,9 @@ __global__ void __launch_bounds__(64) k_eig_ritz(double off_rel2, const double *
                                                  const int *__restrict__ conv) {
   const int i = blockIdx.x;
   if (conv[i]) return;
-  __shared__ double G[EIGP * HP], K[EIGP * HP], Li[EIGP * HP], H[EIGP * HP], V[EIGP * HP];
-  __shared__ double cs[4 * EIGP / 2];
+  __shared__ double G[EIGP * HP], K[EIGP * HP], Li[EIGP * HP], Hb[EIGP * HP], Vb[EIGP * HP];
   __shared__ int perm[EIGP];
+  double *H = Hb, *V = Vb;  // the Jacobi iteration's current buffers (G and K: the others)
   __shared__ double theta[EIGP];
   __shared__ int flag;
   __shared__ double floor_;
@@ -339,7 +352,7 @@ __global__ void __launch_bounds__(64) k_eig_ritz(double off_rel2, const double *
     }
   }
   __syncthreads();
-  jacobi16(H, V, cs, &flag, off_rel2);
+  jacobi16(H, V, G, K, &flag, off_rel2);  // G and K are free by now
   if (t == 0) {
     for (int a = 0; a < EIGP; ++a) {
       perm[a] = a;
