@@ -882,12 +882,39 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
   P.n = n;
   P.N = N;
   P.nev = nev;
+  // cores: the dofs of each part in ascending order (counting sort of the
+  // partition; in parallel over row chunks, each chunk's rows placed after
+  // those of the chunks before it)
   std::vector<int> core_ptr(N + 1, 0), core(n);
-  for (int j = 0; j < n; ++j) core_ptr[part[j] + 1]++;
-  for (int i = 0; i < N; ++i) core_ptr[i + 1] += core_ptr[i];
+  const int nch = N <= 16384 ? std::max(1, std::min(64, n / 16384)) : 1;
   {
-    std::vector<int> pos(core_ptr.begin(), core_ptr.end() - 1);
-    for (int j = 0; j < n; ++j) core[pos[part[j]]++] = j;
+    std::vector<int> cnt((size_t)nch * N, 0);
+    auto rows = [&](int c, int &a, int &b) {
+      a = (int)((long long)n * c / nch);
+      b = (int)((long long)n * (c + 1) / nch);
+    };
+    parallel_for(nch, [&](int c) {
+      int a, b;
+      rows(c, a, b);
+      int *h = cnt.data() + (size_t)c * N;
+      for (int j = a; j < b; ++j) h[part[j]]++;
+    });
+    int run = 0;
+    for (int i = 0; i < N; ++i) {
+      core_ptr[i] = run;
+      for (int c = 0; c < nch; ++c) {
+        const int x = cnt[(size_t)c * N + i];
+        cnt[(size_t)c * N + i] = run;
+        run += x;
+      }
+    }
+    core_ptr[N] = run;
+    parallel_for(nch, [&](int c) {
+      int a, b;
+      rows(c, a, b);
+      int *at = cnt.data() + (size_t)c * N;
+      for (int j = a; j < b; ++j) core[at[part[j]]++] = j;
+    });
   }
   std::vector<SubPlan> sub(N);
   {
