@@ -233,8 +233,11 @@ void register_exit_release() {
 }
 }  // namespace
 
+void scratch_release();
+
 void plan_release_caches() {
   PlanPool::shutdown();
+  scratch_release();
   BlockCache &c = block_cache();
   std::lock_guard<std::mutex> lk(c.mu);
   for (auto &kv : c.free_blocks) block_delete(kv.second.first, kv.second.second);
@@ -635,19 +638,73 @@ struct SubPlan {
 
 namespace {
 struct Scratch {
-  ivec stamp, loc;  // stamp: visit marks (fresh value per use); loc: -1 between uses
+  // stamp: visit marks (a fresh value per use); loc: -1 between uses.  Kept
+  // between planning calls (see scratch_get), indexable up to n_cap.
+  std::vector<int> stamp, loc;
+  int n_cap = 0;
   int gen = 0;
   RcmWork rcm;
   std::vector<unsigned long long> bits;  // bitmap for ordering a region's dofs
   std::vector<int> tptr, tcol, pos;  // local CSR columns in ascending order, relabelling
   std::vector<int> frontier, next, adj_ptr, adj, order, mincol, fenv;
   std::vector<std::pair<int, int>> row;
-  explicit Scratch(int n) {
+  explicit Scratch(int n) : n_cap(n) {
     stamp.assign(n, -1);
     loc.assign(n, -1);
   }
+  int next_mark() {  // a stamp value no entry holds yet
+    if (gen == INT_MAX) {
+      std::fill(stamp.begin(), stamp.end(), -1);
+      gen = 0;
+    }
+    return ++gen;
+  }
 };
+
+// Workers' scratch, kept between planning calls: a fresh Scratch costs two
+// n-sized fills (~1 ms per worker at n = 1M), which would otherwise delay
+// every worker's first region.  At most kScratchCap bytes are kept.
+constexpr size_t kScratchCap = size_t(1) << 30;
+struct ScratchCache {
+  std::mutex mu;
+  std::vector<std::unique_ptr<Scratch>> free;
+  size_t held = 0;
+};
+ScratchCache &scratch_cache() {
+  static ScratchCache *c = new ScratchCache();  // never destroyed (see block_cache)
+  return *c;
+}
+size_t scratch_bytes(const Scratch &s) { return 2 * (size_t)s.n_cap * sizeof(int); }
+std::unique_ptr<Scratch> scratch_get(int n) {
+  {
+    ScratchCache &c = scratch_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (size_t k = c.free.size(); k-- > 0;)
+      if (c.free[k]->n_cap >= n) {
+        std::unique_ptr<Scratch> s = std::move(c.free[k]);
+        c.free.erase(c.free.begin() + k);
+        c.held -= scratch_bytes(*s);
+        return s;
+      }
+  }
+  return std::unique_ptr<Scratch>(new Scratch(n));
+}
+// Returns a Scratch whose loc entries are all -1 again.
+void scratch_put(std::unique_ptr<Scratch> s) {
+  ScratchCache &c = scratch_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (c.held + scratch_bytes(*s) > kScratchCap) return;  // freed here
+  c.held += scratch_bytes(*s);
+  c.free.push_back(std::move(s));
+}
 }  // namespace
+
+void scratch_release() {
+  ScratchCache &c = scratch_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.free.clear();
+  c.held = 0;
+}
 
 #ifdef AMSP_PLAN_PROFILE
 #include <chrono>
@@ -670,7 +727,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   const double *va = A->val;
   const int delta = opt.overlap;
   std::vector<int> region(core.begin() + core_ptr[i], core.begin() + core_ptr[i + 1]);
-  const int mark = ++S.gen;
+  const int mark = S.next_mark();
   for (int g : region) S.stamp[g] = mark;
   S.frontier = region;
   const int layers = delta;
@@ -700,7 +757,7 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   sort_distinct(region, S.bits);
   SEC(0);
   const int ni = (int)region.size();
-  ivec &loc = S.loc;
+  std::vector<int> &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[region[k]] = k;
   // one pass over the region's rows of A (ascending order): the local CSR
   // columns in that order (tcol, diagonal included) and the adjacency for the
@@ -804,10 +861,10 @@ static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, Su
   const int32_t *ci = A->col_idx;
   const double *va = A->val;
   const int r0 = P.sd_ptr[i], ni = P.sd_ptr[i + 1] - r0;
-  ivec &loc = S.loc;
+  std::vector<int> &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[P.sd_dofs[r0 + k]] = k;
   out.ext.assign(P.sd_dofs.begin() + r0, P.sd_dofs.begin() + r0 + ni);
-  const int mark = ++S.gen;
+  const int mark = S.next_mark();
   for (int k = 0; k < ni; ++k) {
     const int g = P.sd_dofs[r0 + k];
     for (int64_t e = rp[g]; e < rp[g + 1]; ++e) {
@@ -849,30 +906,6 @@ static void plan_ext(int i, const amsp_csr *A, const HostPlan &P, Scratch &S, Su
 #define PSTART do { } while (0)
 #endif
 
-// Workers take scratch space (two n-sized index maps) from a shared pool.
-namespace {
-struct ScratchPool {
-  int n;
-  std::mutex mu;
-  std::vector<std::unique_ptr<Scratch>> pool;
-  explicit ScratchPool(int n_) : n(n_) {}
-  std::unique_ptr<Scratch> get() {
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      if (!pool.empty()) {
-        auto s = std::move(pool.back());
-        pool.pop_back();
-        return s;
-      }
-    }
-    return std::unique_ptr<Scratch>(new Scratch(n));
-  }
-  void put(std::unique_ptr<Scratch> s) {
-    std::lock_guard<std::mutex> lk(mu);
-    pool.push_back(std::move(s));
-  }
-};
-}  // namespace
 
 int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
                      const amsp_options &opt, HostPlan &P, std::string &msg) {
@@ -918,14 +951,13 @@ int build_plan_local(const amsp_csr *A, const int32_t *part, int32_t nparts, int
   }
   std::vector<SubPlan> sub(N);
   {
-    ScratchPool pool(n);
     parallel_for(N, [&](int i) {
-      auto sc = pool.get();
+      auto sc = scratch_get(n);
       if (P.offdiag_zeros)
         plan_region<true>(i, A, core_ptr, core, nev, opt, *sc, sub[i]);
       else
         plan_region<false>(i, A, core_ptr, core, nev, opt, *sc, sub[i]);
-      pool.put(std::move(sc));
+      scratch_put(std::move(sc));
     });
   }
   PTIME("regions");
@@ -1024,14 +1056,13 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
   if (nev == 0 || P.nc == 0) return AMSP_OK;
   std::vector<SubPlan> sub(N);
   {
-    ScratchPool pool(n);
     parallel_for(N, [&](int i) {
-      auto sc = pool.get();
+      auto sc = scratch_get(n);
       if (P.offdiag_zeros)
         plan_ext<true>(i, A, P, *sc, sub[i]);
       else
         plan_ext<false>(i, A, P, *sc, sub[i]);
-      pool.put(std::move(sc));
+      scratch_put(std::move(sc));
     });
   }
   std::vector<size_t> exs_off(N + 1, 0);
