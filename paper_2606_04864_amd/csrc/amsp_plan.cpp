@@ -367,25 +367,30 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
     msg = "row_ptr[0] must be 0, row_ptr[n] == nnz < 2^31";
     return AMSP_ERR_CSR;
   }
-  // Pass 1 over row chunks: row structure, column range and order, finite
+  // One pass over row chunks: row structure, column range and order, finite
   // values, diagonal present, max |a|, counts of strictly upper / lower
-  // entries; each chunk records its first failing row (the lowest failing
-  // row overall is reported).
+  // entries, and for every strictly upper entry (i, c) the largest
+  // |a_ci - a_ic| over its mirror (a missing mirror counts as infinite).
+  // Each chunk records its first failing row (the lowest failing row overall
+  // is reported).  A structure error is reported before any asymmetry: the
+  // mirror lookups read rows not yet checked (guarded so that they stay in
+  // bounds) and mean something only once every row is well formed.
   const int nchunk = 64;
   std::vector<int> cerr(nchunk, 0);
   std::vector<int64_t> crow(nchunk, -1), cup(nchunk, 0), clo(nchunk, 0), czero(nchunk, 0);
-  std::vector<double> cmax(nchunk, 0.0);
+  std::vector<double> cmax(nchunk, 0.0), cdiff(nchunk, 0.0);
   auto chunk_rows = [&](int c, int64_t &r0, int64_t &r1) {
     r0 = n * c / nchunk;
     r1 = n * (c + 1) / nchunk;
   };
+  const int64_t nnz = A->nnz;
   parallel_for(nchunk, [&](int c) {
     int64_t r0, r1;
     chunk_rows(c, r0, r1);
-    double amax = 0.0;
+    double amax = 0.0, dmax = 0.0;
     int64_t up = 0, lo = 0, zero = 0;
     for (int64_t i = r0; i < r1; ++i) {
-      if (rp[i] < 0 || rp[i + 1] < rp[i] || rp[i + 1] > A->nnz) {
+      if (rp[i] < 0 || rp[i + 1] < rp[i] || rp[i + 1] > nnz) {
         cerr[c] = 4;
         crow[c] = i;
         return;
@@ -403,6 +408,16 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
         lo += (cc < i);
         zero += (cc != i && A->val[e] == 0.0);
         amax = std::max(amax, std::fabs(A->val[e]));
+        if (cc > i) {
+          const int64_t b0 = rp[cc], b1 = rp[cc + 1];
+          double d = INFINITY;
+          if (b0 >= 0 && b0 <= b1 && b1 <= nnz) {
+            const int32_t *b = A->col_idx + b0, *en = A->col_idx + b1;
+            const int32_t *f = std::lower_bound(b, en, (int32_t)i);
+            if (f != en && *f == i) d = std::fabs(A->val[b0 + (f - b)] - A->val[e]);
+          }
+          dmax = std::max(dmax, d);
+        }
       }
       if (!diag) {
         cerr[c] = 2;
@@ -411,6 +426,7 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
       }
     }
     cmax[c] = amax;
+    cdiff[c] = dmax;
     cup[c] = up;
     clo[c] = lo;
     czero[c] = zero;
@@ -429,40 +445,44 @@ int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int3
       return AMSP_ERR_CSR;
     }
   }
-  double amax = 0.0;
+  double amax = 0.0, dmax = 0.0;
   int64_t nup = 0, nlo = 0, nzero = 0;
   for (int c = 0; c < nchunk; ++c) {
     amax = std::max(amax, cmax[c]);
+    dmax = std::max(dmax, cdiff[c]);
     nup += cup[c];
     nlo += clo[c];
     nzero += czero[c];
   }
-  // Pass 2: every strictly upper entry (i, c) has its mirror (c, i) with the
-  // same value up to 1e-14 max|a|; with as many lower as upper entries this
-  // pairs them all, so the pattern and the values are symmetric.
+  // Every strictly upper entry (i, c) has its mirror (c, i) with the same
+  // value up to 1e-14 max|a|; with as many lower as upper entries this pairs
+  // them all, so the pattern and the values are symmetric.  Only when that
+  // fails is the first failing row looked for, in a second pass.
   const double tol = 1e-14 * amax;
-  parallel_for(nchunk, [&](int c) {
-    int64_t r0, r1;
-    chunk_rows(c, r0, r1);
-    for (int64_t i = r0; i < r1; ++i) {
-      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-        const int32_t cc = A->col_idx[e];
-        if (cc <= i) continue;
-        const int32_t *b = A->col_idx + rp[cc], *en = A->col_idx + rp[cc + 1];
-        const int32_t *f = std::lower_bound(b, en, (int32_t)i);
-        if (f == en || *f != i || std::fabs(A->val[rp[cc] + (f - b)] - A->val[e]) > tol) {
-          cerr[c] = 3;
-          crow[c] = i;
-          return;
+  if (!(dmax <= tol)) {
+    parallel_for(nchunk, [&](int c) {
+      int64_t r0, r1;
+      chunk_rows(c, r0, r1);
+      for (int64_t i = r0; i < r1; ++i) {
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+          const int32_t cc = A->col_idx[e];
+          if (cc <= i) continue;
+          const int32_t *b = A->col_idx + rp[cc], *en = A->col_idx + rp[cc + 1];
+          const int32_t *f = std::lower_bound(b, en, (int32_t)i);
+          if (f == en || *f != i || std::fabs(A->val[rp[cc] + (f - b)] - A->val[e]) > tol) {
+            cerr[c] = 3;
+            crow[c] = i;
+            return;
+          }
         }
       }
-    }
-  });
-  for (int c = 0; c < nchunk; ++c)
-    if (cerr[c] == 3) {
-      msg = "matrix not symmetric in row " + std::to_string(crow[c]);
-      return AMSP_ERR_NONSYM;
-    }
+    });
+    for (int c = 0; c < nchunk; ++c)
+      if (cerr[c] == 3) {
+        msg = "matrix not symmetric in row " + std::to_string(crow[c]);
+        return AMSP_ERR_NONSYM;
+      }
+  }
   if (nup != nlo) {
     msg = "matrix pattern not symmetric (upper and lower entry counts differ)";
     return AMSP_ERR_NONSYM;

@@ -67,10 +67,26 @@ def test_error_codes_forced_from_host():
     va2 = va.copy()
     va2[0] = np.nan
     assert P.setup_error_code(rp, ci, va2, part, 4, 2)[0] == "AMSP_ERR_CSR"
-    # asymmetric values
+    # asymmetric values: the lowest row with a mismatched upper entry is named
     C = A.tolil()
     C[0, 1] = C[0, 1] * 1.5
     assert P.setup_error_code(*_csr_parts(C), part, 4, 2)[0] == "AMSP_ERR_NONSYM"
+    C = A.tolil()
+    C[50, 51] = C[50, 51] * 1.5
+    C[20, 21] = C[20, 21] * 1.5
+    code, msg = P.setup_error_code(*_csr_parts(C), part, 4, 2)
+    assert code == "AMSP_ERR_NONSYM" and msg.endswith("row 20"), msg
+    # a mismatch below 1e-14 max|a| is accepted
+    C = A.tolil()
+    C[20, 21] = C[20, 21] + 1e-16 * abs(A).max()
+    assert P.setup_error_code(*_csr_parts(sp.csr_matrix(C)), part, 4, 2)[0] == "AMSP_OK"
+    # asymmetric pattern with as many lower as upper entries: (3, 17) and
+    # (12, 5) without their mirrors
+    D = A.tolil()
+    D[3, 17] = -1e-3
+    D[12, 5] = -1e-3
+    code, msg = P.setup_error_code(*_csr_parts(sp.csr_matrix(D)), part, 4, 2)
+    assert code == "AMSP_ERR_NONSYM" and msg.endswith("row 3"), msg
     # partition value out of range, empty part, bad nparts
     p2 = part.copy()
     p2[0] = 7
