@@ -577,20 +577,15 @@ static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &a
     return best;
   };
   std::vector<int> &nb = W.nb;
-  for (int s0 = 0; s0 < n; ++s0) {
-    if (vis[s0]) continue;
-    int s = s0, ecc = -1;
-    for (int it = 0; it < 4; ++it) {
-      int e2;
-      const int cand = bfs_last_min(s, e2);
-      if (e2 <= ecc) break;
-      ecc = e2;
-      s = cand;
-    }
-    // Cuthill-McKee from s
-    size_t h = order.size();
+  // Cuthill-McKee from s (appended to order): a BFS whose levels are
+  // contiguous in the order, so it also yields s's eccentricity and the
+  // min-degree node of its last level, as bfs_last_min would
+  auto cm_from = [&](int s, int &ecc) {
+    const size_t h0 = order.size();
+    size_t h = h0;
     order.push_back(s);
     vis[s] = 1;
+    level[s] = 0;
     while (h < order.size()) {
       const int v = order[h++];
       nb.clear();
@@ -608,8 +603,38 @@ static void rcm_order(const std::vector<int> &adj_ptr, const std::vector<int> &a
       for (int w : nb)
         if (!vis[w]) {
           vis[w] = 1;
+          level[w] = level[v] + 1;
           order.push_back(w);
         }
+    }
+    const int last = level[order.back()];
+    int best = -1;
+    for (size_t k = order.size(); k-- > h0 && level[order[k]] == last;) {
+      const int v = order[k];
+      if (best < 0 || deg[v] < deg[best] || (deg[v] == deg[best] && v < best)) best = v;
+    }
+    for (size_t k = h0; k < order.size(); ++k) level[order[k]] = -1;
+    ecc = last;
+    return best;
+  };
+  for (int s0 = 0; s0 < n; ++s0) {
+    if (vis[s0]) continue;
+    // George-Liu: up to four BFS passes, each from the min-degree node of the
+    // previous pass's last level, while the eccentricity grows; the order
+    // starts from the last start that did not increase it.  A pass from a
+    // candidate start is the Cuthill-McKee traversal itself, kept when the
+    // search stops there.
+    int ecc;
+    int s = bfs_last_min(s0, ecc);
+    for (int it = 1;; ++it) {
+      const size_t h0 = order.size();
+      int e2;
+      const int cand = cm_from(s, e2);
+      if (e2 <= ecc || it == 4) break;  // the fourth pass's start is taken unchecked
+      for (size_t k = h0; k < order.size(); ++k) vis[order[k]] = 0;  // undo
+      order.resize(h0);
+      ecc = e2;
+      s = cand;
     }
   }
   std::reverse(order.begin(), order.end());
