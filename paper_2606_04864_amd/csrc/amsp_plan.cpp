@@ -273,18 +273,6 @@ void plan_parallel_for(int count, const std::function<void(int)> &fn) {
   parallel_for(count, [&](int c) { fn(c); });
 }
 
-// fn(i) for i in [0, count) in 64 contiguous chunks: neighbouring subdomains
-// stay on one worker, so the index arrays they share rarely bounce between
-// cores.
-template <typename F>
-static void parallel_chunks(int count, F fn) {
-  const int nch = std::max(1, std::min(count, 64));
-  parallel_for(nch, [&](int c) {
-    const int a = (int)((long long)count * c / nch), b = (int)((long long)count * (c + 1) / nch);
-    for (int i = a; i < b; ++i) fn(i);
-  });
-}
-
 // ptr[0] = 0, ptr[j + 1] = ptr[j] + cnt[j] for j < n (chunked, in parallel).
 template <typename V1, typename V2>
 static void exclusive_scan(const V1 &cnt, V2 &ptr, int n) {
@@ -313,30 +301,6 @@ static void exclusive_scan(const V1 &cnt, V2 &ptr, int n) {
     }
   });
 }
-
-// Sort each list [ptr[j], ptr[j+1]) of (key, payload) pairs by key; keys in
-// a list are distinct, lists are short.
-template <typename V>
-static void sort_lists(const V &ptr, int n, V &key, V &pay) {
-  const int nch = 64;
-  parallel_for(nch, [&](int c) {
-    const int a = (int)((long long)n * c / nch), b = (int)((long long)n * (c + 1) / nch);
-    for (int j = a; j < b; ++j)
-      for (int x = ptr[j] + 1; x < ptr[j + 1]; ++x) {
-        const int kk = key[x], pp = pay[x];
-        int y = x;
-        while (y > ptr[j] && key[y - 1] > kk) {
-          key[y] = key[y - 1];
-          pay[y] = pay[y - 1];
-          --y;
-        }
-        key[y] = kk;
-        pay[y] = pp;
-      }
-  });
-}
-
-static inline int atomic_inc(int *x) { return __atomic_fetch_add(x, 1, __ATOMIC_RELAXED); }
 
 int validate_inputs(const amsp_csr *A, const int32_t *part, int32_t nparts, int32_t nev,
                     int32_t overlap, std::string &msg, int64_t *offdiag_zeros) {
@@ -1138,25 +1102,55 @@ int build_plan_coupling(const amsp_csr *A, const amsp_options &opt, HostPlan &P,
   PTIME("ext regions");
   // coupled subdomain pairs for A0, grouped by partner subdomain (ascending)
   {
+    // every dof's list of (extended region j, index in it), j ascending: the
+    // dofs in 64 ranges, each range taking, region by region in ascending
+    // order, the part of the region's (ascending) extended set that falls in
+    // it; no atomics, and the lists come out sorted
     ivec xcnt, xptr, xj, xe;
-    xcnt.assign(n, 0);
-    parallel_chunks(N, [&](int j) {
-      for (int e = P.ext_ptr[j]; e < P.ext_ptr[j + 1]; ++e) atomic_inc(&xcnt[ext_dofs[e]]);
-    });
+    xcnt.resize(n);
     xptr.resize(n + 1);
+    const int nrg = 64;
+    auto range = [&](int c, int &g0, int &g1) {
+      g0 = (int)((long long)n * c / nrg);
+      g1 = (int)((long long)n * (c + 1) / nrg);
+    };
+    auto part_of = [&](int j, int g0, int g1, int &a, int &b) {
+      const int *x0 = ext_dofs.data() + P.ext_ptr[j], *x1 = ext_dofs.data() + P.ext_ptr[j + 1];
+      a = b = 0;
+      if (x0 == x1 || x1[-1] < g0 || x0[0] >= g1) return;
+      a = (int)(std::lower_bound(x0, x1, g0) - x0);
+      b = (int)(std::lower_bound(x0 + a, x1, g1) - x0);
+    };
+    parallel_for(nrg, [&](int c) {
+      int g0, g1;
+      range(c, g0, g1);
+      std::fill(xcnt.begin() + g0, xcnt.begin() + g1, 0);
+      for (int j = 0; j < N; ++j) {
+        int a, b;
+        part_of(j, g0, g1, a, b);
+        const int *x = ext_dofs.data() + P.ext_ptr[j];
+        for (int e = a; e < b; ++e) xcnt[x[e]]++;
+      }
+    });
     exclusive_scan(xcnt, xptr, n);
     xj.resize(ext_dofs.size());
     xe.resize(ext_dofs.size());
-    std::fill(xcnt.begin(), xcnt.end(), 0);
-    parallel_chunks(N, [&](int j) {
-      for (int e = P.ext_ptr[j]; e < P.ext_ptr[j + 1]; ++e) {
-        const int g = ext_dofs[e];
-        const int at = xptr[g] + atomic_inc(&xcnt[g]);
-        xj[at] = j;
-        xe[at] = e - P.ext_ptr[j];
+    parallel_for(nrg, [&](int c) {
+      int g0, g1;
+      range(c, g0, g1);
+      std::fill(xcnt.begin() + g0, xcnt.begin() + g1, 0);
+      for (int j = 0; j < N; ++j) {
+        int a, b;
+        part_of(j, g0, g1, a, b);
+        const int *x = ext_dofs.data() + P.ext_ptr[j];
+        for (int e = a; e < b; ++e) {
+          const int g = x[e];
+          const int at = xptr[g] + xcnt[g]++;
+          xj[at] = j;
+          xe[at] = e;
+        }
       }
     });
-    sort_lists(xptr, n, xj, xe);
     std::mutex mu;
     std::vector<std::unique_ptr<std::vector<int>>> slots;
     parallel_for(N, [&](int i) {
