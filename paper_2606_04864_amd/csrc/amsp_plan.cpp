@@ -769,10 +769,16 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
   std::vector<int> &loc = S.loc;
   for (int k = 0; k < ni; ++k) loc[region[k]] = k;
   // one pass over the region's rows of A (ascending order): the local CSR
-  // columns in that order (tcol, diagonal included) and the adjacency for the
-  // ordering (off-diagonal, nonzero values)
-  S.adj_ptr.assign(ni + 1, 0);
-  S.adj.clear();
+  // columns in that order (tcol, diagonal included) and, when A may store
+  // off-diagonal zeros, the adjacency for the ordering (off-diagonal, nonzero
+  // values).  Without such zeros the ordering takes tcol itself: every row
+  // lists itself once (the diagonal is present), which the searches skip as
+  // already visited and which adds one to every degree, so the order is the
+  // same.
+  if (ZV) {
+    S.adj_ptr.assign(ni + 1, 0);
+    S.adj.clear();
+  }
   S.tptr.assign(ni + 1, 0);
   S.tcol.clear();
   for (int k = 0; k < ni; ++k) {
@@ -782,14 +788,17 @@ static void plan_region(int i, const amsp_csr *A, const std::vector<int> &core_p
       const int lc = loc[c];
       if (lc < 0) continue;
       S.tcol.push_back(lc);
-      if (c != g && (!ZV || va[e] != 0.0)) S.adj.push_back(lc);
+      if (ZV && c != g && va[e] != 0.0) S.adj.push_back(lc);
     }
-    S.adj_ptr[k + 1] = (int)S.adj.size();
+    if (ZV) S.adj_ptr[k + 1] = (int)S.adj.size();
     S.tptr[k + 1] = (int)S.tcol.size();
   }
   SEC(1);
   if (opt.local_order == AMSP_ORDER_RCM) {
-    rcm_order(S.adj_ptr, S.adj, S.order, S.rcm);
+    if (ZV)
+      rcm_order(S.adj_ptr, S.adj, S.order, S.rcm);
+    else
+      rcm_order(S.tptr, S.tcol, S.order, S.rcm);
   } else {
     S.order.resize(ni);
     for (int k = 0; k < ni; ++k) S.order[k] = k;
