@@ -142,3 +142,24 @@ def test_planner_is_deterministic():
     b = P.plan_regions(w.A.row_ptr, w.A.col_idx, w.A.val, w.part, w.nparts, w.nev, overlap=2)
     assert a[1:] == b[1:]
     assert all(np.array_equal(x, y) for x, y in zip(a[0], b[0]))
+
+
+def test_planner_repeatable_across_problem_sizes():
+    """The planner keeps its workers' scratch between calls (index maps sized
+    for the largest problem seen); plans must not depend on what ran before:
+    a large problem, a smaller one, then the large one again give the same
+    regions in the same local (RCM) order, tile count and pair count."""
+    big = W.get("gauss128")
+    small = configs.channels(nx=24, nparts=9, overlap=1, nev=3)
+
+    def plan(w):
+        return P.plan_regions(w.A.row_ptr, w.A.col_idx, w.A.val, w.part, w.nparts, w.nev,
+                              overlap=2)
+
+    r1, nt1, np1 = plan(big)
+    rs, nts, nps = plan(small)
+    r2, nt2, np2 = plan(big)
+    rs2, nts2, nps2 = plan(small)
+    assert (nt1, np1) == (nt2, np2) and (nts, nps) == (nts2, nps2)
+    assert all(np.array_equal(a, b) for a, b in zip(r1, r2))
+    assert all(np.array_equal(a, b) for a, b in zip(rs, rs2))
