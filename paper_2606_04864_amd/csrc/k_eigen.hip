@@ -320,13 +320,18 @@ __global__ void __launch_bounds__(64) k_eig_ritz(double off_rel2, const double *
     __syncthreads();
   }
   if (t < EIGP) {  // Li = L^{-1}: lane j computes column j by forward substitution
-    const int j = t;
-    for (int r = 0; r < EIGP; ++r) Li[r * HP + j] = 0.0;
-    for (int r = j; r < EIGP; ++r) {
+    const int j = t;  // (the column in registers; terms m = j .. r-1 in that order)
+    double lc[EIGP];
+#pragma unroll
+    for (int r = 0; r < EIGP; ++r) {
       double s = (r == j) ? 1.0 : 0.0;
-      for (int m = j; m < r; ++m) s = fma(-G[r * HP + m], Li[m * HP + j], s);
-      Li[r * HP + j] = s / G[r * HP + r];
+#pragma unroll
+      for (int m = 0; m < r; ++m)
+        if (m >= j) s = fma(-G[r * HP + m], lc[m], s);
+      lc[r] = r >= j ? s / G[r * HP + r] : 0.0;
     }
+#pragma unroll
+    for (int r = 0; r < EIGP; ++r) Li[r * HP + j] = lc[r];
   }
   __syncthreads();
   for (int e = t; e < EIGP * EIGP; e += 64) {  // V <- Li K (temporary)
@@ -353,23 +358,20 @@ __global__ void __launch_bounds__(64) k_eig_ritz(double off_rel2, const double *
   }
   __syncthreads();
   jacobi16(H, V, G, K, &flag, off_rel2);  // G and K are free by now
-  if (t == 0) {
-    for (int a = 0; a < EIGP; ++a) {
-      perm[a] = a;
-      theta[a] = H[a * HP + a];
+  if (t < EIGP) {  // ascending order, ties by index (a stable sort): lane a places value a
+    auto key = [&](int a) {
+      const double x = H[a * HP + a];
+      return x == x ? x : INFINITY;  // a NaN sorts last (the result is then unused)
+    };
+    const double th = key(t);
+    int rank = 0;
+#pragma unroll
+    for (int b = 0; b < EIGP; ++b) {
+      const double x = key(b);
+      rank += (x < th || (x == th && b < t)) ? 1 : 0;
     }
-    for (int a = 1; a < EIGP; ++a) {  // insertion sort, ascending
-      int pa = perm[a];
-      double th = theta[a];
-      int b = a - 1;
-      while (b >= 0 && theta[b] > th) {
-        theta[b + 1] = theta[b];
-        perm[b + 1] = perm[b];
-        --b;
-      }
-      theta[b + 1] = th;
-      perm[b + 1] = pa;
-    }
+    perm[rank] = t;
+    theta[rank] = H[t * HP + t];
   }
   __syncthreads();
   double *out = CC + (size_t)i * (EIGP * EIGP + EIGP);
