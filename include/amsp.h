@@ -374,8 +374,9 @@ amsp_status amsp_selftest_mfma(const double *a_host, const double *b_host, doubl
 
 void amsp_destroy(amsp_handle *h);
 /* Returns the process-wide caches to the system: device blocks kept for
- * later setups (freed with hipFree on their own device) and page-locked
- * planner blocks; stops and joins the planner's worker threads.  Blocks
+ * later setups (freed with hipFree on their own device), page-locked
+ * planner blocks and the planner workers' index maps (at most 1 GiB, kept
+ * between setups); stops and joins the planner's worker threads.  Blocks
  * still owned by live handles are untouched.  Later calls re-create the
  * caches on demand.  Must not run concurrently with any other call.  The
  * library also does this from an exit handler that runs before the HIP
